@@ -63,11 +63,17 @@ class Oracle:
         Y = np.repeat(x2, len(x1))
         return X, Y, np.outer(w2, w1).reshape(-1)
 
-    def local_matrix(self, e1, e2, cvals=None):
-        """E[l, m] = sum_g w_g c_g B_l B_m over local functions l = a2 (p+1) + a1."""
+    def local_matrix(self, e1, e2, cvals=None, absolute=False):
+        """E[l, m] = sum_g w_g c_g B_l B_m over local functions l = a2 (p+1) + a1.
+
+        ``absolute`` sums |w_g c_g| B_l B_m instead: the scale of the entry's
+        rounding error (B-splines are non-negative).
+        """
         x, y, w = self.element_points(e1, e2)
         if cvals is None:
             cvals = self.coef(x, y, e1, e2)
+        if absolute:
+            w, cvals = np.abs(w), np.abs(cvals)
         B1 = bspline.local_basis(self.k1, self.p, e1, x)
         B2 = bspline.local_basis(self.k2, self.p, e2, y)
         phi = np.einsum("ga,gb->gba", B1, B2).reshape(len(x), -1)
@@ -78,7 +84,7 @@ class Oracle:
         return np.array([(e2 + a2) * n1 + (e1 + a1) for a2 in range(p + 1) for a1 in range(p + 1)])
 
     # ------------------------------------------------------- reference
-    def gauss_reference(self, rows_flat=None, elements=None):
+    def gauss_reference(self, rows_flat=None, elements=None, absolute=False):
         """Element-wise Gauss matrix over the visible domain (rows restricted to ``rows_flat``)."""
         ts = self.ts
         act = ts.act_of
@@ -96,7 +102,7 @@ class Oracle:
             rmask = ok if keep_row is None else (ok & keep_row[gl])
             if not rmask.any():
                 continue
-            E = self.local_matrix(e1, e2)
+            E = self.local_matrix(e1, e2, absolute=absolute)
             ri = np.nonzero(rmask)[0]
             ci = np.nonzero(ok)[0]
             rr, cc = np.meshgrid(ri, ci, indexing="ij")
@@ -138,15 +144,18 @@ class Oracle:
                         c[a, b] = 0.0
         return c
 
-    def wq_row(self, i1, i2, mask_outside=False):
+    def wq_row(self, i1, i2, mask_outside=False, absolute=False):
         """Entries of row (i1, i2) by the weighted-quadrature double sum; dict flat col -> value."""
         p, n1, n2 = self.p, self.ts.n1, self.ts.n2
         q1 = np.nonzero(self.W1[i1])[0]
         q2 = np.nonzero(self.W2[i2])[0]
         cg = self.wq_point_coef(q1, q2, mask_outside)
+        w1, w2 = self.W1[i1, q1], self.W2[i2, q2]
+        if absolute:
+            w1, w2, cg = np.abs(w1), np.abs(w2), np.abs(cg)
         J1 = np.arange(max(0, i1 - p), min(n1 - 1, i1 + p) + 1)
         J2 = np.arange(max(0, i2 - p), min(n2 - 1, i2 + p) + 1)
-        vals = np.einsum("k,l,ka,lb,kl->ab", self.W1[i1, q1], self.W2[i2, q2],
+        vals = np.einsum("k,l,ka,lb,kl->ab", w1, w2,
                          self.T1[np.ix_(q1, J1)], self.T2[np.ix_(q2, J2)], cg)
         out = {}
         for a, j1 in enumerate(J1):
@@ -154,13 +163,13 @@ class Oracle:
                 out[int(j2 * n1 + j1)] = vals[a, b]
         return out
 
-    def wq_rows(self, rows_flat, mask_outside=False):
+    def wq_rows(self, rows_flat, mask_outside=False, absolute=False):
         ts = self.ts
         R, C, V = [], [], []
         for f in rows_flat:
             i2, i1 = divmod(int(f), ts.n1)
             r = ts.act_of[f]
-            for col, v in self.wq_row(i1, i2, mask_outside).items():
+            for col, v in self.wq_row(i1, i2, mask_outside, absolute).items():
                 cc = ts.act_of[col]
                 if cc >= 0:
                     R.append(r)
@@ -183,13 +192,13 @@ class Oracle:
         e2, e1 = np.nonzero(m)
         return list(zip(e1.tolist(), e2.tolist()))
 
-    def hybrid(self):
-        Mi = self.wq_rows(self.interior_rows_flat())
-        Mc = self.gauss_reference(self.cut_rows_flat(), self.cut_band_elements())
+    def hybrid(self, absolute=False):
+        Mi = self.wq_rows(self.interior_rows_flat(), absolute=absolute)
+        Mc = self.gauss_reference(self.cut_rows_flat(), self.cut_band_elements(), absolute=absolute)
         return (Mi + Mc).tocsr()
 
-    def naive(self):
-        return self.wq_rows(self.ts.active, mask_outside=True)
+    def naive(self, absolute=False):
+        return self.wq_rows(self.ts.active, mask_outside=True, absolute=absolute)
 
 
 def to_ell(M, ts):

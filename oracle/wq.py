@@ -92,3 +92,19 @@ def wq_weights(knots, p, xs=None, el=None, M1=None, return_residual=False):
     if return_residual:
         return W, worst
     return W
+
+
+def wq_condition(knots, p, xs=None, el=None):
+    """2-norm condition number of each system (5) (NumPy's routine), per test function."""
+    if xs is None:
+        xs, el = wq_points(knots, p)
+    n_el = len(bspline.breakpoints(knots, p)) - 1
+    n = bspline.n_functions(knots, p)
+    T = basis_at_points(knots, p, xs, el)
+    out = np.zeros(n)
+    for i in range(n):
+        sup = list(bspline.support_elements(p, n_el, i))
+        Qi = np.nonzero((el >= sup[0]) & (el <= sup[-1]))[0]
+        Ji = np.arange(max(0, i - p), min(n - 1, i + p) + 1)
+        out[i] = np.linalg.cond(T[np.ix_(Qi, Ji)].T)
+    return out
