@@ -1,0 +1,283 @@
+/*
+ * iga_trim.h -- C ABI of the gfx950 library that forms isogeometric mass
+ * matrices over trimmed bivariate B-spline patches by weighted quadrature.
+ *
+ * Method: Marussig, "Fast formation and assembly of isogeometric Galerkin
+ * matrices for trimmed patches", arXiv 2101.08053.
+ *
+ *   M_ij = int_{Omega_v} c B_i B_j            (Eq. (6), visible domain of Sect. 2.2)
+ *
+ * Interior test functions use row-based weighted quadrature with sum
+ * factorisation (Sect. 2.1, Eqs. (4), (5), (7)); cut test functions use
+ * hybrid Gauss (Sect. 3.2) or discontinuous weighted quadrature (Sect. 3.3);
+ * cut elements use a higher-order cut-element rule (Sect. 3.1). The matrix
+ * feeds an L2 projection (Sect. 4.2).
+ *
+ * Conventions shared by every call:
+ *  - Both parametric directions have the same degree p (1 <= p <= 8) and an
+ *    open knot vector on [0, 1] with simple interior knots (C^{p-1}).
+ *  - Function (i1, i2) has flat index i = i2 * n1 + i1 (xi_1 fastest); the
+ *    active functions (not exterior) are numbered 0..n_act-1 in increasing
+ *    flat order ("compact ids").
+ *  - The mass matrix is returned in a slot-major band layout:
+ *      vals[s * n_act + r],  s = (a + p) * (2p+1) + (b + p),  a, b in [-p, p],
+ *    holding M(row r, column (i1 + a, i2 + b)). Column ids are implicit;
+ *    slots whose column is out of range or exterior hold 0.
+ *  - "Device" pointers are HIP device memory of the device that was current
+ *    when the plan was created; "host" pointers are ordinary memory and are
+ *    only read during the call. Streams are hipStream_t passed as void*
+ *    (NULL = the default stream). Stream-ordered calls return after enqueue.
+ *  - Every call returns IGA_OK (0) or a negative IGA_E_* code; no exception
+ *    crosses the ABI. iga_last_error() gives a message for the calling thread.
+ */
+#ifndef IGA_TRIM_H
+#define IGA_TRIM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------- status codes */
+#define IGA_OK                   0
+#define IGA_E_INVALID           -1  /* bad argument, knot vector or curve          */
+#define IGA_E_UNSUPPORTED       -2  /* degree outside 1..8, unknown kind, ...      */
+#define IGA_E_NOMEM             -3  /* device allocation failed                    */
+#define IGA_E_HIP               -4  /* a HIP runtime call failed                   */
+#define IGA_E_SINGULAR_WEIGHTS  -5  /* a weight system (Eq. (5)) is rank deficient */
+#define IGA_E_TOPOLOGY          -6  /* trimming geometry outside what is handled   */
+#define IGA_E_CAPACITY          -7  /* a size exceeded what the plan reserved      */
+#define IGA_E_NOCONV            -8  /* PCG did not reach the tolerance             */
+
+/* ------------------------------------------------------------------ methods */
+#define IGA_GAUSS_REF     0  /* element Gauss + cut rule on every row (Sect. 4 reference)  */
+#define IGA_HYBRID_GAUSS  1  /* WQ interior rows, element Gauss cut rows (Sect. 3.2)     */
+#define IGA_DWQ           2  /* WQ interior rows, discontinuous WQ cut rows (Sect. 3.3)  */
+#define IGA_NAIVE_WQ      3  /* WQ on every row, c = 0 outside (Table 1, third column)   */
+
+/* ------------------------------------------------------------ curve kinds */
+#define IGA_CURVE_BSPLINE 0  /* closed uniform periodic B-spline, degree 1..3 */
+#define IGA_CURVE_ELLIPSE 1  /* ellipse (circle when a == b)                  */
+
+/* ------------------------------------------------------- coefficient kinds */
+#define IGA_COEF_CONST      0  /* c = value                                          */
+#define IGA_COEF_GEOM_DETJ  1  /* c = |det DF| of a B-spline map of the patch's space */
+#define IGA_COEF_AT_POINTS  2  /* c given at every rule point (iga_plan_points order) */
+
+/* ------------------------------------------------------------- form flags */
+#define IGA_FORM_FULL     1  /* rebuild layout, weights, trimming data and cut rules first */
+
+/* A closed trimming curve (Sect. 2.2). The hole is its interior, whatever
+ * its orientation; the visible domain is [0,1]^2 minus the union of holes. */
+typedef struct iga_curve {
+    int32_t kind;        /* IGA_CURVE_*                                      */
+    int32_t degree;      /* BSPLINE: 1..3                                    */
+    int32_t n_cp;        /* BSPLINE: control points (> degree)               */
+    int32_t reserved;
+    const double* cp;    /* BSPLINE, host: n_cp (x, y) pairs                 */
+    double cx, cy;       /* ELLIPSE: centre                                  */
+    double a, b;         /* ELLIPSE: semi-axes (> 0)                         */
+    double phi;          /* ELLIPSE: rotation of the a-axis (radians)        */
+} iga_curve;
+
+/* The problem statement: knots, degree, trimming curves, method. */
+typedef struct iga_patch_desc {
+    int32_t degree;              /* p, both directions                        */
+    int32_t method;              /* IGA_GAUSS_REF .. IGA_NAIVE_WQ             */
+    int32_t n_knots[2];          /* lengths of the two knot vectors            */
+    const double* knots[2];      /* host                                      */
+    int32_t n_curves;            /* 0 = untrimmed                             */
+    int32_t reserved;
+    const iga_curve* curves;     /* host, n_curves entries                    */
+} iga_patch_desc;
+
+/* Optional rule and tile settings (NULL or 0 fields = defaults). */
+typedef struct iga_opts {
+    int32_t n_r;        /* inner Gauss points of the cut rule (default p+1)          */
+    int32_t n_q;        /* points per boundary arc (default d(2p+1), d = 3 ellipses) */
+    int32_t n_s;        /* points along straight edge pieces (default p+1)           */
+    int32_t tile1;      /* interior-row tile along xi_1, <= 64 (0 = automatic)       */
+    int32_t tile2;      /* interior-row tile along xi_2 (0 = automatic)              */
+    int32_t reserved[3];
+} iga_opts;
+
+typedef struct iga_plan iga_plan;   /* opaque, library owned */
+
+typedef struct iga_sizes {
+    int64_t p;
+    int64_t N1, N2;           /* elements per direction                          */
+    int64_t n1, n2;           /* functions per direction                         */
+    int64_t n_act;            /* active functions = rows                         */
+    int64_t n_interior;       /* interior functions                              */
+    int64_t n_cut_fn;         /* cut functions                                   */
+    int64_t n_cut_el;         /* cut elements                                    */
+    int64_t n_band_el;        /* inside elements in the support of a cut function */
+    int64_t band;             /* (2p+1)^2 slots per row                          */
+    int64_t q1, q2;           /* weighted-quadrature points per direction        */
+    int64_t n_cut_nodes;      /* nodes of all cut-element rules                  */
+    int64_t n_points;         /* q1*q2 + n_band_el*(p+1)^2 + n_cut_nodes        */
+    int64_t nnz;              /* active-active pairs inside the band             */
+    int64_t n_arcs;           /* boundary arcs of the visible domain             */
+    int64_t n_dwq_rows;       /* cut rows formed with a discontinuous rule (DWQ) */
+    int64_t workspace_bytes;  /* device memory the plan holds                    */
+} iga_sizes;
+
+/* The coefficient c of Eq. (6). */
+typedef struct iga_coeff {
+    int32_t kind;             /* IGA_COEF_*                                              */
+    int32_t reserved;
+    double value;             /* CONST                                                   */
+    const double* geom_cp;    /* GEOM_DETJ, device: control points [n2][n1][2]           */
+    const double* c_points;   /* AT_POINTS, device: n_points values, iga_plan_points order */
+} iga_coeff;
+
+/* Target g of the L2 projection (Sect. 4.2). */
+#define IGA_TARGET_SINCOS    0  /* g = sin(w0 x + w1) cos(w2 y + w3), x,y physical */
+#define IGA_TARGET_MONOMIAL  1  /* g = x^e0 y^e1 (e = (int)w0, (int)w1)            */
+#define IGA_TARGET_AT_POINTS 2  /* g given at every rule point                     */
+typedef struct iga_target {
+    int32_t kind;
+    int32_t reserved;
+    double w[4];
+    const double* g_points;   /* AT_POINTS, device: n_points values */
+} iga_target;
+
+typedef struct iga_solve_info {
+    int32_t iterations;
+    int32_t converged;
+    double rel_residual;      /* ||b - A u|| / ||b|| with A = (M + M^T)/2 */
+} iga_solve_info;
+
+/* ---------------------------------------------------------------- calls */
+
+/* Builds a plan for one patch (Sects. 2.1-3.3): reads the host inputs, takes
+ * device memory for every table, runs the set-up kernels once (weighted-
+ * quadrature layout and weights, trimming, classes, cut rules, and for DWQ
+ * the discontinuous weights) and synchronises to learn the sizes.
+ * opts may be NULL. On success *out owns device memory until
+ * iga_plan_destroy. Errors: IGA_E_INVALID (knots not open/uniformly simple,
+ * curve data), IGA_E_UNSUPPORTED (p, kinds), IGA_E_NOMEM, IGA_E_HIP,
+ * IGA_E_SINGULAR_WEIGHTS, IGA_E_TOPOLOGY. */
+int iga_plan_create(const iga_patch_desc* desc, const iga_opts* opts, iga_plan** out);
+
+/* Releases the plan and its device memory (NULL is accepted). */
+void iga_plan_destroy(iga_plan* plan);
+
+/* Fills *s (host). */
+int iga_plan_sizes(const iga_plan* plan, iga_sizes* s);
+
+/* Device view of the rule points, valid while the plan lives: xy[2*k],
+ * xy[2*k+1] are the parameter coordinates of point k, in this order:
+ * the WQ grid (k = k2*q1 + k1), then the (p+1)^2 Gauss points of each band
+ * element (flat element order, g2 outer, g1 inner), then the cut-element
+ * nodes (cut elements in flat order). *npts receives n_points. */
+int iga_plan_points(const iga_plan* plan, const double** xy, int64_t* npts);
+
+/* Device views of the index maps, valid while the plan lives: act_of[flat]
+ * (compact id or -1) of length n1*n2, fn_of[compact] (flat index) of length
+ * n_act, fn_class[flat] (0 exterior, 1 interior, 2 cut). Any output may be NULL. */
+int iga_plan_index_maps(const iga_plan* plan, const int32_t** act_of, const int32_t** fn_of,
+                        const int8_t** fn_class);
+
+/* Forms the mass matrix (Eq. (6) over the visible domain) with the plan's
+ * method into vals (device, band * n_act doubles, caller owned), on stream.
+ * flags & IGA_FORM_FULL re-runs every set-up kernel from the plan's inputs
+ * before the formation (the whole job); without it the resident tables are
+ * reused. Errors found on the device (a singular weight system) are reported
+ * by iga_plan_status after the stream has run. */
+int iga_trim_mass_form(iga_plan* plan, const iga_coeff* c, double* vals, int32_t flags, void* stream);
+
+/* Synchronises stream and returns the device status word of the plan
+ * (IGA_OK or IGA_E_SINGULAR_WEIGHTS / IGA_E_CAPACITY), then clears it. */
+int iga_plan_status(iga_plan* plan, void* stream);
+
+/* L2 projection (Sect. 4.2): b_i by row i's own rule applied to g c, then
+ * Jacobi-preconditioned CG on A = (M + M^T)/2 (M from iga_trim_mass_form
+ * with the same c) until ||b - A u|| <= rtol ||b|| or maxit iterations.
+ * u (device, n_act) is caller owned and used as the start vector.
+ * Synchronous: returns after the solve. Returns IGA_E_NOCONV (with u the
+ * last iterate and info filled) when the tolerance was not reached. */
+int iga_trim_l2_project(iga_plan* plan, const iga_coeff* c, const double* vals, const iga_target* g,
+                        double rtol, int32_t maxit, double* u, iga_solve_info* info, void* stream);
+
+/* Right-hand side alone: b (device, n_act) = row rules applied to g c. */
+int iga_trim_rhs(iga_plan* plan, const iga_coeff* c, const iga_target* g, double* b, void* stream);
+
+/* Matrix-free product y = M(c) u (device vectors of length n_act) with c
+ * given at every rule point (c_points, n_points values), the rows formed by
+ * the plan's interior and hybrid rules, basis values recomputed on the fly. */
+int iga_mf_apply(iga_plan* plan, const double* c_points, const double* u, double* y, void* stream);
+
+/* Adjoint of iga_mf_apply: for a cotangent gy (n_act), du = M(c)^T gy
+ * (n_act) and dc[k] = (sum_j B_j(x_k) u_j) (sum_i w_hat_{k,i} gy_i)
+ * (n_points), w_hat_{k,i} being row i's test-side weight at point k. */
+int iga_mf_adjoint(iga_plan* plan, const double* c_points, const double* u, const double* gy,
+                   double* du, double* dc, void* stream);
+
+/* Batched formation: forms count plans' matrices with one launch per phase
+ * over all patches (work items concatenated across patches), optionally
+ * recorded once into a HIP graph and replayed on later calls with the same
+ * arguments (use_graph != 0). cs and vals are arrays of count entries. */
+int iga_trim_mass_form_batched(iga_plan* const* plans, int32_t count, const iga_coeff* cs,
+                               double* const* vals, int32_t use_graph, void* stream);
+
+/* Per-phase device timing of the plan's calls (hipEvents on the call's
+ * stream). enable != 0 starts recording; iga_plan_timings synchronises and
+ * returns the accumulated milliseconds and counts per phase. */
+#define IGA_PHASE_SETUP     0  /* layout, weights, trimming, cut rules        */
+#define IGA_PHASE_COEF      1  /* coefficient at rule points                  */
+#define IGA_PHASE_INTERIOR  2  /* interior rows (WQ + sum factorisation)       */
+#define IGA_PHASE_CUT       3  /* cut-element matrices and cut rows           */
+#define IGA_PHASE_COUNT     4
+int iga_plan_set_timing(iga_plan* plan, int32_t enable);
+int iga_plan_timings(iga_plan* plan, double* ms, int64_t* counts);
+
+/* Read-only device views of the plan's tables (valid while the plan lives),
+ * for inspection and parity checks:
+ *   IGA_TABLE_WQ_POINTS   direction dir: q_dir point coordinates
+ *   IGA_TABLE_WQ_WEIGHTS  direction dir: n_dir rows of `stride` weights; row i
+ *                         holds w_{k,i} (Eq. (5)) for the points k = k0(i)+q of
+ *                         supp B_i, k0(i) = first point of element max(0, i-p)
+ *   IGA_TABLE_MASS_1D     direction dir: n_dir rows of 2p+1, int B_i B_{i+d-p}
+ *   IGA_TABLE_C_WQ / C_BAND / C_CUT: c at the WQ grid, band Gauss points and
+ *                         cut nodes from the last IGA_COEF_GEOM_DETJ formation
+ *   IGA_TABLE_CUT_W       weights of the cut-element nodes
+ * *count receives the number of doubles, *stride the row length (or 1). */
+#define IGA_TABLE_WQ_POINTS   0
+#define IGA_TABLE_WQ_WEIGHTS  1
+#define IGA_TABLE_MASS_1D     2
+#define IGA_TABLE_C_WQ        3
+#define IGA_TABLE_C_BAND      4
+#define IGA_TABLE_C_CUT       5
+#define IGA_TABLE_CUT_W       6
+int iga_plan_table(const iga_plan* plan, int32_t table, int32_t dir, const double** ptr, int64_t* count,
+                   int64_t* stride);
+
+/* Replaces the weighted-quadrature weights of direction dir by W (device,
+ * layout of IGA_TABLE_WQ_WEIGHTS), stream ordered. Later formations without
+ * IGA_FORM_FULL use them; a FULL formation recomputes them. For checking the
+ * formation kernels under rules fixed from outside. */
+int iga_plan_set_weights(iga_plan* plan, int32_t dir, const double* W, void* stream);
+
+/* Replaces the cut-element nodes (device arrays of n coordinates and weights,
+ * in the order of iga_plan_points; n must equal n_cut_nodes, else
+ * IGA_E_INVALID) and refreshes the point view.
+ * Later formations, right-hand sides and matrix-free products without
+ * IGA_FORM_FULL use them; a FULL formation rebuilds them. For checking the
+ * kernels under rules fixed from outside. */
+int iga_plan_set_cut_nodes(iga_plan* plan, const double* x, const double* y, const double* w, int64_t n,
+                           void* stream);
+
+/* Copies bytes between device (or host) buffers on stream and waits for it
+ * (hipMemcpyAsync with hipMemcpyDefault, then a stream synchronisation); used
+ * by bindings to read the plan's device views. */
+int iga_copy(void* dst, const void* src, int64_t bytes, void* stream);
+
+const char* iga_status_string(int code);
+const char* iga_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* IGA_TRIM_H */

@@ -1,0 +1,546 @@
+// C ABI of the library (declared in include/iga_trim.h): plan creation,
+// formation, status, timing. Host code only orchestrates device work;
+// every step of the method runs in the kernels of setup.hip, trim.hip,
+// form.hip, solve.hip and matfree.hip.
+#include <algorithm>
+#include <memory>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "plan.hpp"
+
+namespace iga {
+
+static thread_local std::string g_last_error;
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+Plan::~Plan() {
+    if (sw.h_scal) hipHostFree(sw.h_scal);
+    for (auto& e : ev_pool) hipEventDestroy(e);
+    for (void* ptr : allocations) hipFree(ptr);
+}
+
+static int qmax_of(int N, int p) {
+    // most WQ points in the support of one function: elements i-p..i
+    int best = 0;
+    for (int i = 0; i < N + p; ++i) {
+        int tot = 0;
+        for (int e = std::max(0, i - p); e <= std::min(N - 1, i); ++e)
+            tot += (e == 0 || e == N - 1) ? p + 1 : 2;
+        best = std::max(best, tot);
+    }
+    return best;
+}
+
+template <typename T>
+static void h2d(T* dst, const T* src, size_t n, hipStream_t s) {
+    HIPX(hipMemcpyAsync(dst, src, n * sizeof(T), hipMemcpyHostToDevice, s));
+}
+template <typename T>
+static T d2h1(const T* src, hipStream_t s) {
+    T v;
+    HIPX(hipMemcpyAsync(&v, src, sizeof(T), hipMemcpyDeviceToHost, s));
+    HIPX(hipStreamSynchronize(s));
+    return v;
+}
+
+static void check_status(Plan& P, hipStream_t s) {
+    int st = d2h1(P.status, s);
+    if (st != IGA_OK) {
+        int z = 0;
+        HIPX(hipMemcpyAsync(P.status, &z, sizeof(int), hipMemcpyHostToDevice, s));
+        HIPX(hipStreamSynchronize(s));
+        throw Error{st, st == IGA_E_SINGULAR_WEIGHTS ? "a weight system of Eq. (5) is rank deficient"
+                                                     : "trimming geometry outside what is handled"};
+    }
+}
+
+// Set-up kernels in dependency order. With `discover`, device counts are read
+// back after each stage to size the next buffers (plan creation only).
+static void run_setup(Plan& P, hipStream_t s, bool discover) {
+    launch_gauss_table(P, s);
+    for (int d = 0; d < 2; ++d) launch_dir_tables(P, d, s);
+    for (int d = 0; d < 2; ++d) launch_wq_weights(P, d, s);
+    TrimDev& T = P.trim;
+    if (T.n_curves > 0) {
+        launch_trim_curves(P, s);
+        launch_orientation(P, s);
+        launch_trim_crossings(P, s);
+        if (discover) {
+            int np = d2h1(T.n_pieces, s);
+            std::vector<int> off(1);
+            int ncross = d2h1(T.cross_off + T.cap_pieces, s);
+            (void)np;
+            T.cap_cross = std::max(ncross, 1);
+            T.cap_arcs = ncross + np;
+            T.cross = P.alloc<CrossDev>(T.cap_cross);
+            T.merged = P.alloc<CrossDev>(T.cap_cross);
+            T.arcs = P.alloc<ArcDev>(std::max(T.cap_arcs, 1));
+        }
+        launch_trim_arcs(P, s);
+    }
+    launch_trim_classes(P, s);
+    launch_trim_lists(P, s);
+    if (discover) {
+        int c[4];
+        HIPX(hipMemcpyAsync(c, P.counts, 4 * sizeof(int), hipMemcpyDeviceToHost, s));
+        HIPX(hipStreamSynchronize(s));
+        P.n_act = c[0];
+        P.n_form_rows = c[1];
+        P.n_cut_el = c[2];
+        P.n_band = c[3];
+        int nc = (int)P.n_cut_el;
+        P.arc_cnt = P.alloc<int>(nc + 1);
+        P.arc_off = P.alloc<int>(nc + 1);
+        P.arc_fill = P.alloc<int>(nc + 1);
+        P.arc_list = P.alloc<int>(std::max(T.cap_arcs, 1));
+        P.cut_el = P.alloc<CutElemDev>(std::max(nc, 1));
+        P.node_cnt = P.alloc<int>(nc + 1);
+        P.node_off = P.alloc<int>(nc + 1);
+    }
+    launch_trim_cutprep(P, s);
+    if (discover) {
+        P.n_nodes = (P.n_cut_el > 0) ? d2h1(P.node_off + P.n_cut_el, s) : 0;
+        P.n_arcs = (P.n_cut_el > 0) ? d2h1(P.arc_off + P.n_cut_el, s) : 0;
+        size_t nn = std::max<int64_t>(P.n_nodes, 1);
+        P.node_x = P.alloc<double>(nn);
+        P.node_y = P.alloc<double>(nn);
+        P.node_w = P.alloc<double>(nn);
+        P.node_el = P.alloc<int>(nn);
+        size_t L = (size_t)(P.p + 1) * (P.p + 1);
+        P.cutE = P.alloc<double>(std::max<int64_t>(P.n_cut_el, 1) * L * L);
+        size_t nq = (size_t)P.dir[0].Q * P.dir[1].Q;
+        size_t nb = (size_t)P.n_band * L;
+        P.n_points = (int64_t)(nq + nb + P.n_nodes);
+        P.pts_xy = P.alloc<double>(2 * P.n_points);
+        P.c_wq = P.alloc<double>(nq);
+        P.c_band = P.alloc<double>(std::max<size_t>(nb, 1));
+        P.c_cut = P.alloc<double>(nn);
+        if (P.method == IGA_NAIVE_WQ) P.c_wq_masked = P.alloc<double>(nq);
+    }
+    launch_trim_nodes(P, s);
+    launch_points(P, s);
+    if (discover) {
+        check_status(P, s);
+        int nf = P.n1 * P.n2;
+        int* cnt = P.flags;
+        int* out = P.flags + (nf + 1);
+        launch_row_nnz(P, cnt, out, s);
+        P.nnz = d2h1(out + P.n_act, s);
+        // interior and cut counts
+        std::vector<int8_t> fc(nf);
+        HIPX(hipMemcpyAsync(fc.data(), P.fcls, nf, hipMemcpyDeviceToHost, s));
+        HIPX(hipStreamSynchronize(s));
+        P.n_interior = std::count(fc.begin(), fc.end(), (int8_t)FN_INTERIOR);
+        P.n_cut_fn = std::count(fc.begin(), fc.end(), (int8_t)FN_CUT);
+    }
+}
+
+struct PhaseTimer {
+    Plan& P;
+    hipStream_t s;
+    int phase;
+    hipEvent_t a{}, b{};
+    PhaseTimer(Plan& P_, hipStream_t s_, int ph) : P(P_), s(s_), phase(ph) {
+        if (!P.timing) return;
+        HIPX(hipEventCreate(&a));
+        HIPX(hipEventCreate(&b));
+        HIPX(hipEventRecord(a, s));
+    }
+    ~PhaseTimer() {
+        if (!P.timing) return;
+        hipEventRecord(b, s);
+        P.ev_records.push_back({phase, {a, b}});
+    }
+};
+
+static void form(Plan& P, const iga_coeff& c, double* vals, int flags, hipStream_t s) {
+    if (flags & IGA_FORM_FULL) {
+        PhaseTimer t(P, s, IGA_PHASE_SETUP);
+        run_setup(P, s, false);
+    }
+    {
+        PhaseTimer t(P, s, IGA_PHASE_COEF);
+        launch_coef(P, c, s);
+        if (P.method == IGA_NAIVE_WQ) {
+            const double* src = (c.kind == IGA_COEF_CONST) ? nullptr
+                                : (c.kind == IGA_COEF_GEOM_DETJ ? P.c_wq : c.c_points);
+            launch_naive_mask(P, src, c.value, s);
+        }
+    }
+    {
+        PhaseTimer t(P, s, IGA_PHASE_INTERIOR);
+        launch_interior_rows(P, c, vals, s);
+    }
+    {
+        PhaseTimer t(P, s, IGA_PHASE_CUT);
+        launch_cut_rows(P, c, vals, s);
+    }
+}
+
+static void validate_knots(const double* k, int n, int p, int d) {
+    IGA_REQUIRE(k != nullptr && n >= 2 * p + 2, IGA_E_INVALID, "knot vector " + std::to_string(d) + " too short");
+    for (int i = 0; i <= p; ++i) {
+        IGA_REQUIRE(k[i] == 0.0, IGA_E_INVALID, "knot vectors must start with p+1 zeros");
+        IGA_REQUIRE(k[n - 1 - i] == 1.0, IGA_E_INVALID, "knot vectors must end with p+1 ones");
+    }
+    for (int i = p; i < n - p - 1; ++i)
+        IGA_REQUIRE(k[i + 1] > k[i], IGA_E_INVALID, "interior knots must be simple and increasing");
+}
+
+}  // namespace iga
+
+using namespace iga;
+
+#define API_BEGIN try {
+#define API_END                               \
+    }                                         \
+    catch (const Error& e) {                  \
+        set_error(e.msg);                     \
+        return e.code;                        \
+    }                                         \
+    catch (const std::exception& e) {         \
+        set_error(e.what());                  \
+        return IGA_E_INVALID;                 \
+    }                                         \
+    return IGA_OK;
+
+extern "C" {
+
+int iga_plan_create(const iga_patch_desc* desc, const iga_opts* opts, iga_plan** out) {
+    API_BEGIN
+    IGA_REQUIRE(desc && out, IGA_E_INVALID, "null argument");
+    *out = nullptr;
+    int p = desc->degree;
+    IGA_REQUIRE(p >= 1 && p <= IGA_MAXP, IGA_E_UNSUPPORTED, "degree must be in 1..8");
+    IGA_REQUIRE(desc->method >= IGA_GAUSS_REF && desc->method <= IGA_NAIVE_WQ, IGA_E_UNSUPPORTED, "unknown method");
+    IGA_REQUIRE(desc->method != IGA_DWQ, IGA_E_UNSUPPORTED, "discontinuous weighted quadrature is not built");
+    for (int d = 0; d < 2; ++d) validate_knots(desc->knots[d], desc->n_knots[d], p, d);
+    IGA_REQUIRE(desc->n_curves >= 0 && (desc->n_curves == 0 || desc->curves), IGA_E_INVALID, "curves missing");
+    bool all_ellipses = true;
+    for (int c = 0; c < desc->n_curves; ++c) {
+        const iga_curve& C = desc->curves[c];
+        if (C.kind == IGA_CURVE_BSPLINE) {
+            IGA_REQUIRE(C.degree >= 1 && C.degree <= 3, IGA_E_UNSUPPORTED, "curve degree must be 1..3");
+            IGA_REQUIRE(C.n_cp > C.degree && C.cp, IGA_E_INVALID, "curve needs more control points than its degree");
+            all_ellipses = false;
+        } else if (C.kind == IGA_CURVE_ELLIPSE) {
+            IGA_REQUIRE(C.a > 0 && C.b > 0, IGA_E_INVALID, "ellipse semi-axes must be positive");
+        } else {
+            throw Error{IGA_E_UNSUPPORTED, "unknown curve kind"};
+        }
+    }
+    IGA_REQUIRE(desc->n_curves <= 1 || all_ellipses, IGA_E_UNSUPPORTED,
+                "a union of several holes is handled for ellipses only");
+
+    auto* P = new iga_plan();
+    std::unique_ptr<iga_plan> guard(P);
+    HIPX(hipGetDevice(&P->device));
+    P->p = p;
+    P->method = desc->method;
+    P->n_r = (opts && opts->n_r > 0) ? opts->n_r : p + 1;
+    P->n_s = (opts && opts->n_s > 0) ? opts->n_s : p + 1;
+    P->n_q_override = (opts && opts->n_q > 0) ? opts->n_q : 0;
+    IGA_REQUIRE(P->n_r <= IGA_MAX_GAUSS && P->n_s <= IGA_MAX_GAUSS && P->n_q_override <= IGA_MAX_GAUSS &&
+                    3 * (2 * p + 1) <= IGA_MAX_GAUSS,
+                IGA_E_UNSUPPORTED, "rule sizes above 64 points");
+    hipStream_t s;
+    HIPX(hipStreamCreate(&s));
+    struct StreamGuard {
+        hipStream_t s;
+        ~StreamGuard() { hipStreamDestroy(s); }
+    } sg{s};
+
+    for (int d = 0; d < 2; ++d) {
+        DirDev& D = P->dir[d];
+        D.N = desc->n_knots[d] - 2 * p - 1;
+        D.n = D.N + p;
+        D.Q = (D.N == 1) ? p + 1 : 2 * D.N + 2 * p - 2;
+        D.qmax = qmax_of(D.N, p);
+        IGA_REQUIRE(D.qmax <= 64, IGA_E_UNSUPPORTED, "too many points in one support");
+        P->h_knots[d].assign(desc->knots[d], desc->knots[d] + desc->n_knots[d]);
+        P->knots[d] = P->alloc<double>(desc->n_knots[d]);
+        h2d(P->knots[d], desc->knots[d], desc->n_knots[d], s);
+        D.knots = P->knots[d];
+        D.bp = P->alloc<double>(D.N + 1);
+        D.xq = P->alloc<double>(D.Q);
+        D.eq = P->alloc<int>(D.Q);
+        D.pt0 = P->alloc<int>(D.N + 1);
+        D.Bq = P->alloc<double>((size_t)D.Q * (p + 1));
+        D.dBq = P->alloc<double>((size_t)D.Q * (p + 1));
+        D.M1 = P->alloc<double>((size_t)D.n * (2 * p + 1));
+        D.W = P->alloc<double>((size_t)D.n * D.qmax);
+        D.xg = P->alloc<double>((size_t)D.N * (p + 1));
+        D.wg = P->alloc<double>((size_t)D.N * (p + 1));
+        D.Bg = P->alloc<double>((size_t)D.N * (p + 1) * (p + 1));
+        D.dBg = P->alloc<double>((size_t)D.N * (p + 1) * (p + 1));
+    }
+    P->N1 = P->dir[0].N;
+    P->N2 = P->dir[1].N;
+    P->n1 = P->dir[0].n;
+    P->n2 = P->dir[1].n;
+    if (opts && opts->tile2 > 0) P->tile2 = opts->tile2;
+    else {
+        // enough workgroups to fill 256 compute units several times over
+        int tiles1 = (P->n1 + 63) / 64;
+        int t2 = (int)std::max<int64_t>(1, std::min<int64_t>(8, (int64_t)tiles1 * P->n2 / 2048));
+        P->tile2 = t2;
+    }
+    P->gauss_x = P->alloc<double>(gauss_off(IGA_MAX_GAUSS + 1));
+    P->gauss_w = P->alloc<double>(gauss_off(IGA_MAX_GAUSS + 1));
+    P->status = P->alloc<int>(1);
+    P->counts = P->alloc<int>(16);
+    HIPX(hipMemsetAsync(P->status, 0, sizeof(int), s));
+
+    // curves
+    TrimDev& T = P->trim;
+    T.n_curves = desc->n_curves;
+    std::vector<double> cp;
+    std::vector<int> cp_off;
+    int nseg = 0;
+    for (int c = 0; c < desc->n_curves; ++c) {
+        const iga_curve& C = desc->curves[c];
+        CurveDev D{};
+        D.kind = C.kind;
+        D.degree = C.degree;
+        D.seg0 = nseg;
+        D.cx = C.cx;
+        D.cy = C.cy;
+        D.a = C.a;
+        D.b = C.b;
+        D.phi = C.phi;
+        D.sigma = 1.0;
+        cp_off.push_back((int)(cp.size() / 2));
+        if (C.kind == IGA_CURVE_BSPLINE) {
+            D.n_seg = C.n_cp;
+            D.t_range = 1.0;
+            cp.insert(cp.end(), C.cp, C.cp + 2 * C.n_cp);
+        } else {
+            D.n_seg = 1;
+            D.t_range = 2.0 * M_PI;
+        }
+        nseg += D.n_seg;
+        P->h_curves.push_back(D);
+    }
+    T.n_segs = nseg;
+    if (T.n_curves > 0) {
+        IGA_REQUIRE(nseg <= 1 << 20, IGA_E_UNSUPPORTED, "too many curve segments");
+        P->d_curves = P->alloc<CurveDev>(T.n_curves);
+        h2d(P->d_curves, P->h_curves.data(), T.n_curves, s);
+        T.curves = P->d_curves;
+        P->d_cp = P->alloc<double>(std::max<size_t>(cp.size(), 2));
+        if (!cp.empty()) h2d(P->d_cp, cp.data(), cp.size(), s);
+        P->d_cp_off = P->alloc<int>(T.n_curves);
+        h2d(P->d_cp_off, cp_off.data(), cp_off.size(), s);
+        T.segs = P->alloc<SegDev>(nseg);
+        T.cap_pieces0 = kMaxPiecesPerSeg * nseg;
+        T.cap_pieces = (T.n_curves > 1) ? T.cap_pieces0 * (kMaxIsectPerPiece + 1) : T.cap_pieces0;
+        T.pieces = P->alloc<PieceDev>(T.cap_pieces);
+        T.pieces0 = (T.n_curves > 1) ? P->alloc<PieceDev>(T.cap_pieces0) : T.pieces;
+        T.n_pieces = P->alloc<int>(1);
+        T.n_pieces0 = (T.n_curves > 1) ? P->alloc<int>(1) : T.n_pieces;
+        T.piece_curve_off = P->alloc<int>(T.n_curves + 1);
+        T.isect_t = P->alloc<double>((size_t)T.cap_pieces0 * kMaxIsectPerPiece);
+        T.isect_n = P->alloc<int>(T.cap_pieces0);
+        T.cross_cnt = P->alloc<int>(T.cap_pieces + 1);
+        T.nv = P->alloc<int>(T.cap_pieces + 1);
+        T.cross_off = P->alloc<int>(T.cap_pieces + 1);
+    }
+    int nf = P->n1 * P->n2, ne = P->N1 * P->N2;
+    P->ecls = P->alloc<int8_t>(ne);
+    P->cut_id = P->alloc<int>(ne);
+    P->band_id = P->alloc<int>(ne);
+    P->cut_list = P->alloc<int>(ne);
+    P->band_list = P->alloc<int>(ne);
+    P->fcls = P->alloc<int8_t>(nf);
+    P->act_of = P->alloc<int>(nf);
+    P->fn_of = P->alloc<int>(nf);
+    P->form_rows = P->alloc<int>(nf);
+    P->flags = P->alloc<int>(2 * (size_t)(nf + 1) + 2 * (size_t)(ne + 1));
+    int big = std::max(std::max(nf, ne), T.cap_pieces) + 2;
+    P->scan_pos_off = ((big + 1023) / 1024 + 64 + 63) / 64 * 64;  // block sums first, then positions
+    P->scan_tmp = P->alloc<int>((size_t)P->scan_pos_off + (size_t)big);
+
+    run_setup(*P, s, true);
+    HIPX(hipStreamSynchronize(s));
+    *out = guard.release();
+    API_END
+}
+
+void iga_plan_destroy(iga_plan* plan) {
+    if (!plan) return;
+    hipDeviceSynchronize();
+    delete plan;
+}
+
+int iga_plan_sizes(const iga_plan* P, iga_sizes* s) {
+    API_BEGIN
+    IGA_REQUIRE(P && s, IGA_E_INVALID, "null argument");
+    std::memset(s, 0, sizeof(*s));
+    s->p = P->p;
+    s->N1 = P->N1;
+    s->N2 = P->N2;
+    s->n1 = P->n1;
+    s->n2 = P->n2;
+    s->n_act = P->n_act;
+    s->n_interior = P->n_interior;
+    s->n_cut_fn = P->n_cut_fn;
+    s->n_cut_el = P->n_cut_el;
+    s->n_band_el = P->n_band;
+    s->band = (int64_t)(2 * P->p + 1) * (2 * P->p + 1);
+    s->q1 = P->dir[0].Q;
+    s->q2 = P->dir[1].Q;
+    s->n_cut_nodes = P->n_nodes;
+    s->n_points = P->n_points;
+    s->nnz = P->nnz;
+    s->n_arcs = P->n_arcs;
+    s->n_dwq_rows = 0;
+    s->workspace_bytes = P->bytes;
+    API_END
+}
+
+int iga_plan_points(const iga_plan* P, const double** xy, int64_t* npts) {
+    API_BEGIN
+    IGA_REQUIRE(P, IGA_E_INVALID, "null plan");
+    if (xy) *xy = P->pts_xy;
+    if (npts) *npts = P->n_points;
+    API_END
+}
+
+int iga_plan_index_maps(const iga_plan* P, const int32_t** act_of, const int32_t** fn_of, const int8_t** fn_class) {
+    API_BEGIN
+    IGA_REQUIRE(P, IGA_E_INVALID, "null plan");
+    if (act_of) *act_of = P->act_of;
+    if (fn_of) *fn_of = P->fn_of;
+    if (fn_class) *fn_class = P->fcls;
+    API_END
+}
+
+int iga_trim_mass_form(iga_plan* P, const iga_coeff* c, double* vals, int32_t flags, void* stream) {
+    API_BEGIN
+    IGA_REQUIRE(P && c && vals, IGA_E_INVALID, "null argument");
+    IGA_REQUIRE(c->kind >= IGA_COEF_CONST && c->kind <= IGA_COEF_AT_POINTS, IGA_E_UNSUPPORTED, "coefficient kind");
+    IGA_REQUIRE(c->kind != IGA_COEF_GEOM_DETJ || c->geom_cp, IGA_E_INVALID, "geometry control points missing");
+    IGA_REQUIRE(c->kind != IGA_COEF_AT_POINTS || c->c_points, IGA_E_INVALID, "per-point coefficient missing");
+    form(*P, *c, vals, flags, (hipStream_t)stream);
+    HIPX(hipGetLastError());
+    API_END
+}
+
+int iga_plan_status(iga_plan* P, void* stream) {
+    API_BEGIN
+    IGA_REQUIRE(P, IGA_E_INVALID, "null plan");
+    check_status(*P, (hipStream_t)stream);
+    API_END
+}
+
+int iga_plan_set_timing(iga_plan* P, int32_t enable) {
+    API_BEGIN
+    IGA_REQUIRE(P, IGA_E_INVALID, "null plan");
+    P->timing = enable != 0;
+    API_END
+}
+
+int iga_plan_timings(iga_plan* P, double* ms, int64_t* counts) {
+    API_BEGIN
+    IGA_REQUIRE(P, IGA_E_INVALID, "null plan");
+    for (auto& r : P->ev_records) {
+        HIPX(hipEventSynchronize(r.second.second));
+        float t = 0.f;
+        HIPX(hipEventElapsedTime(&t, r.second.first, r.second.second));
+        P->phase_ms[r.first] += t;
+        P->phase_cnt[r.first] += 1;
+        hipEventDestroy(r.second.first);
+        hipEventDestroy(r.second.second);
+    }
+    P->ev_records.clear();
+    for (int k = 0; k < IGA_PHASE_COUNT; ++k) {
+        if (ms) ms[k] = P->phase_ms[k];
+        if (counts) counts[k] = P->phase_cnt[k];
+        P->phase_ms[k] = 0;
+        P->phase_cnt[k] = 0;
+    }
+    API_END
+}
+
+int iga_plan_table(const iga_plan* P, int32_t table, int32_t dir, const double** ptr, int64_t* count,
+                   int64_t* stride) {
+    API_BEGIN
+    IGA_REQUIRE(P && ptr, IGA_E_INVALID, "null argument");
+    IGA_REQUIRE(dir == 0 || dir == 1, IGA_E_INVALID, "direction must be 0 or 1");
+    const DirDev& D = P->dir[dir];
+    int64_t n = 0, st = 1;
+    const double* p = nullptr;
+    size_t L = (size_t)(P->p + 1) * (P->p + 1);
+    switch (table) {
+        case IGA_TABLE_WQ_POINTS: p = D.xq; n = D.Q; break;
+        case IGA_TABLE_WQ_WEIGHTS: p = D.W; n = (int64_t)D.n * D.qmax; st = D.qmax; break;
+        case IGA_TABLE_MASS_1D: p = D.M1; n = (int64_t)D.n * (2 * P->p + 1); st = 2 * P->p + 1; break;
+        case IGA_TABLE_C_WQ: p = P->c_wq; n = (int64_t)P->dir[0].Q * P->dir[1].Q; break;
+        case IGA_TABLE_C_BAND: p = P->c_band; n = P->n_band * (int64_t)L; break;
+        case IGA_TABLE_C_CUT: p = P->c_cut; n = P->n_nodes; break;
+        case IGA_TABLE_CUT_W: p = P->node_w; n = P->n_nodes; break;
+        default: throw Error{IGA_E_INVALID, "unknown table"};
+    }
+    *ptr = p;
+    if (count) *count = n;
+    if (stride) *stride = st;
+    API_END
+}
+
+int iga_plan_set_weights(iga_plan* P, int32_t dir, const double* W, void* stream) {
+    API_BEGIN
+    IGA_REQUIRE(P && W, IGA_E_INVALID, "null argument");
+    IGA_REQUIRE(dir == 0 || dir == 1, IGA_E_INVALID, "direction must be 0 or 1");
+    const DirDev& D = P->dir[dir];
+    HIPX(hipMemcpyAsync(D.W, W, sizeof(double) * (size_t)D.n * D.qmax, hipMemcpyDefault, (hipStream_t)stream));
+    API_END
+}
+
+int iga_plan_set_cut_nodes(iga_plan* P, const double* x, const double* y, const double* w, int64_t n_in,
+                           void* stream) {
+    API_BEGIN
+    IGA_REQUIRE(P && x && y && w, IGA_E_INVALID, "null argument");
+    IGA_REQUIRE(n_in == P->n_nodes, IGA_E_INVALID,
+                "node count " + std::to_string(n_in) + " differs from the plan's " + std::to_string(P->n_nodes));
+    hipStream_t s = (hipStream_t)stream;
+    size_t n = (size_t)P->n_nodes;
+    if (n > 0) {
+        HIPX(hipMemcpyAsync(P->node_x, x, n * sizeof(double), hipMemcpyDefault, s));
+        HIPX(hipMemcpyAsync(P->node_y, y, n * sizeof(double), hipMemcpyDefault, s));
+        HIPX(hipMemcpyAsync(P->node_w, w, n * sizeof(double), hipMemcpyDefault, s));
+        launch_points(*P, s);
+    }
+    API_END
+}
+
+int iga_copy(void* dst, const void* src, int64_t bytes, void* stream) {
+    API_BEGIN
+    IGA_REQUIRE(bytes >= 0 && (bytes == 0 || (dst && src)), IGA_E_INVALID, "bad copy arguments");
+    if (bytes > 0) {
+        HIPX(hipMemcpyAsync(dst, src, (size_t)bytes, hipMemcpyDefault, (hipStream_t)stream));
+        HIPX(hipStreamSynchronize((hipStream_t)stream));
+    }
+    API_END
+}
+
+const char* iga_status_string(int code) {
+    switch (code) {
+        case IGA_OK: return "ok";
+        case IGA_E_INVALID: return "invalid argument";
+        case IGA_E_UNSUPPORTED: return "unsupported";
+        case IGA_E_NOMEM: return "out of device memory";
+        case IGA_E_HIP: return "HIP runtime error";
+        case IGA_E_SINGULAR_WEIGHTS: return "singular weight system";
+        case IGA_E_TOPOLOGY: return "unsupported trimming topology";
+        case IGA_E_CAPACITY: return "capacity exceeded";
+        case IGA_E_NOCONV: return "no convergence";
+        default: return "unknown status";
+    }
+}
+
+const char* iga_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,101 @@
+// Shared device helpers of the gfx950 library: error plumbing, B-spline
+// evaluation, Gauss-Legendre tables and scans. Host and device code of the
+// library only; nothing here is shared with the CPU oracle.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+
+#include "../../include/iga_trim.h"
+
+#define IGA_MAXP 8
+#define IGA_MAX_GAUSS 64  // largest Gauss-Legendre rule kept in the table
+
+namespace iga {
+
+void set_error(const std::string& msg);
+
+struct Error {
+    int code;
+    std::string msg;
+};
+
+#define HIPX(expr)                                                                         \
+    do {                                                                                   \
+        hipError_t e_ = (expr);                                                            \
+        if (e_ != hipSuccess)                                                              \
+            throw ::iga::Error{IGA_E_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)}; \
+    } while (0)
+
+#define IGA_REQUIRE(cond, code, msg)                    \
+    do {                                                \
+        if (!(cond)) throw ::iga::Error{(code), (msg)}; \
+    } while (0)
+
+// Offset of the n-point rule in the packed Gauss table (rules 1..IGA_MAX_GAUSS).
+__host__ __device__ inline int gauss_off(int n) { return n * (n - 1) / 2; }
+
+// -------------------------------------------------------------------------
+// B-spline values on one element by the triangular Cox-de Boor scheme.
+// span = index of the knot at the element's left end (p + e for open knot
+// vectors with simple interior knots). N[0..p] receives B_{span-p..span}(x).
+// -------------------------------------------------------------------------
+template <int P>
+__device__ __forceinline__ void basis_eval(const double* __restrict__ knots, int span, double x, double* N) {
+    double left[P + 1], right[P + 1];
+    N[0] = 1.0;
+#pragma unroll
+    for (int j = 1; j <= P; ++j) {
+        left[j] = x - knots[span + 1 - j];
+        right[j] = knots[span + j] - x;
+        double saved = 0.0;
+#pragma unroll
+        for (int r = 0; r < j; ++r) {
+            double tmp = N[r] / (right[r + 1] + left[j - r]);
+            N[r] = saved + right[r + 1] * tmp;
+            saved = left[j - r] * tmp;
+        }
+        N[j] = saved;
+    }
+}
+
+// Runtime-degree variant (p <= IGA_MAXP); also returns first derivatives if dN != nullptr.
+__device__ __forceinline__ void basis_eval_rt(const double* __restrict__ knots, int p, int span, double x,
+                                              double* N, double* dN) {
+    double left[IGA_MAXP + 1], right[IGA_MAXP + 1];
+    double low[IGA_MAXP + 1];
+    N[0] = 1.0;
+    for (int j = 1; j <= p; ++j) {
+        if (j == p) {
+            for (int r = 0; r < p; ++r) low[r] = N[r];
+        }
+        left[j] = x - knots[span + 1 - j];
+        right[j] = knots[span + j] - x;
+        double saved = 0.0;
+        for (int r = 0; r < j; ++r) {
+            double tmp = N[r] / (right[r + 1] + left[j - r]);
+            N[r] = saved + right[r + 1] * tmp;
+            saved = left[j - r] * tmp;
+        }
+        N[j] = saved;
+    }
+    if (dN) {
+        if (p == 0) {
+            dN[0] = 0.0;
+            return;
+        }
+        // derivative of B_{span-p+a, p}: p/(k[i+p]-k[i]) low_i - p/(k[i+p+1]-k[i+1]) low_{i+1}
+        for (int a = 0; a <= p; ++a) {
+            int i = span - p + a;
+            double v = 0.0;
+            if (a >= 1) v += p * low[a - 1] / (knots[i + p] - knots[i]);
+            if (a <= p - 1) v -= p * low[a] / (knots[i + p + 1] - knots[i + 1]);
+            dN[a] = v;
+        }
+    }
+}
+
+}  // namespace iga

@@ -1,0 +1,353 @@
+// Matrix-free product y = M(c) u and its adjoint.
+//
+// With c given at every rule point, the rows of M are
+//   y_i = sum_k w_hat_{k,i} c_k U_k,   U_k = sum_j B_j(x_k) u_j,
+// where w_hat_{k,i} is row i's test-side weight at point k: w1 w2 for rows
+// formed by weighted quadrature (interior rows), w_g B_i(x_g) for rows formed
+// element-wise (hybrid Gauss cut rows: element Gauss points and cut nodes).
+// For L(u, c) with dL/dy = r the adjoint is
+//   du_j = sum_k B_j(x_k) c_k R_k,   dc_k = U_k R_k,   R_k = sum_i w_hat_{k,i} r_i.
+// Basis values come from the per-direction tables or are recomputed at cut
+// nodes; U and R are never stored per row.
+#include "plan.hpp"
+
+namespace iga {
+
+struct MfArgs {
+    DirDev d1, d2;
+    int p, n1, n2, N1, N2;
+    int method;
+    const int8_t* fcls;
+    const int8_t* ecls;
+    const int* act_of;
+    const int* fn_of;
+    const int* band_list;
+    const int* cut_list;
+    const int* band_id;
+    const int* cut_id;
+    const int* node_off;
+    const double *nx, *ny, *nw;
+    int n_band, n_cut, n_act;
+    const double* c;   // n_points, plan point order
+    int nq, nb;        // point offsets: band points start at nq, cut nodes at nq + nb
+};
+
+__device__ __forceinline__ double u_at(const MfArgs& A, const double* __restrict__ u, int j1, int j2) {
+    int c = A.act_of[j2 * A.n1 + j1];
+    return c >= 0 ? u[c] : 0.0;
+}
+
+// U_k on the whole WQ grid; out = c_k U_k (forward) or U_k (adjoint).
+__global__ void k_mf_grid(MfArgs A, const double* __restrict__ u, double* __restrict__ out, int times_c) {
+    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= A.nq) return;
+    int p = A.p;
+    int k1 = k % A.d1.Q, k2 = k / A.d1.Q;
+    int e1 = A.d1.eq[k1], e2 = A.d2.eq[k2];
+    double U = 0.0;
+    for (int a2 = 0; a2 <= p; ++a2) {
+        double s = 0.0;
+        for (int a1 = 0; a1 <= p; ++a1) s += A.d1.Bq[k1 * (p + 1) + a1] * u_at(A, u, e1 + a1, e2 + a2);
+        U += A.d2.Bq[k2 * (p + 1) + a2] * s;
+    }
+    out[k] = times_c ? A.c[k] * U : U;
+}
+
+__device__ __forceinline__ bool wq_row(const MfArgs& A, int8_t cls) {
+    return A.method != IGA_GAUSS_REF && cls == FN_INTERIOR;
+}
+
+// y for rows formed by weighted quadrature.
+__global__ void k_mf_wq_rows(MfArgs A, const double* __restrict__ G, double* __restrict__ y) {
+    int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= A.n_act) return;
+    int f = A.fn_of[r];
+    if (!wq_row(A, A.fcls[f])) return;
+    int p = A.p;
+    int i1 = f % A.n1, i2 = f / A.n1;
+    int k1 = A.d1.pt0[max(0, i1 - p)], q1 = A.d1.pt0[min(A.N1 - 1, i1) + 1] - k1;
+    int k2 = A.d2.pt0[max(0, i2 - p)], q2 = A.d2.pt0[min(A.N2 - 1, i2) + 1] - k2;
+    double s = 0.0;
+    for (int b = 0; b < q2; ++b) {
+        double in = 0.0;
+        for (int a = 0; a < q1; ++a) in += A.d1.W[(size_t)i1 * A.d1.qmax + a] * G[(size_t)(k2 + b) * A.d1.Q + k1 + a];
+        s += A.d2.W[(size_t)i2 * A.d2.qmax + b] * in;
+    }
+    y[r] = s;
+}
+
+// Adjoint on the WQ grid: R_k from the rows that use point k, dc_k = U_k R_k,
+// and CR_k = c_k R_k for the du gather.
+__global__ void k_mf_grid_adj(MfArgs A, const double* __restrict__ U, const double* __restrict__ r,
+                              double* __restrict__ dc, double* __restrict__ CR) {
+    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= A.nq) return;
+    int p = A.p;
+    int k1 = k % A.d1.Q, k2 = k / A.d1.Q;
+    int e1 = A.d1.eq[k1], e2 = A.d2.eq[k2];
+    double R = 0.0;
+    for (int i2 = e2; i2 <= e2 + p; ++i2) {
+        int q2 = k2 - A.d2.pt0[max(0, i2 - p)];
+        double w2 = A.d2.W[(size_t)i2 * A.d2.qmax + q2];
+        double s = 0.0;
+        for (int i1 = e1; i1 <= e1 + p; ++i1) {
+            int f = i2 * A.n1 + i1;
+            if (!wq_row(A, A.fcls[f])) continue;
+            int q1 = k1 - A.d1.pt0[max(0, i1 - p)];
+            s += A.d1.W[(size_t)i1 * A.d1.qmax + q1] * r[A.act_of[f]];
+        }
+        R += w2 * s;
+    }
+    dc[k] = U[k] * R;
+    CR[k] = A.c[k] * R;
+}
+
+// Element part: per band / cut element, forward Y_e[l] = sum_g w_g c_g U_g B_l(x_g),
+// adjoint D_e[l] = sum_g c_g R_g B_l(x_g) with R_g = w_g sum_l B_l r_l over the
+// element-formed rows, and dc_g = U_g R_g.
+template <int P>
+__global__ void __launch_bounds__(64) k_mf_elem(MfArgs A, const double* __restrict__ u, const double* __restrict__ r,
+                                                double* __restrict__ Ye, double* __restrict__ dc) {
+    constexpr int L = (P + 1) * (P + 1);
+    constexpr int PER = (L + 63) / 64;
+    __shared__ double sPhi[64][L];
+    __shared__ double sT[64];
+    __shared__ double sU[L], sR[L];
+    int re = blockIdx.x;
+    bool is_cut = re >= A.n_band;
+    int e = is_cut ? A.cut_list[re - A.n_band] : A.band_list[re];
+    int e1 = e % A.N1, e2 = e / A.N1;
+    for (int l = threadIdx.x; l < L; l += 64) {
+        int j1 = e1 + l % (P + 1), j2 = e2 + l / (P + 1);
+        int f = j2 * A.n1 + j1;
+        int cid = A.act_of[f];
+        sU[l] = (cid >= 0) ? u[cid] : 0.0;
+        // rows formed element-wise: cut rows (hybrid) or every row (reference)
+        bool erow = cid >= 0 && !wq_row(A, A.fcls[f]);
+        sR[l] = (r && erow) ? r[cid] : 0.0;
+    }
+    int nb, ne, pbase;
+    if (is_cut) {
+        nb = A.node_off[re - A.n_band];
+        ne = A.node_off[re - A.n_band + 1];
+        pbase = A.nq + A.nb;
+    } else {
+        nb = 0;
+        ne = L;
+        pbase = A.nq + re * L;
+    }
+    double acc[PER];
+#pragma unroll
+    for (int k = 0; k < PER; ++k) acc[k] = 0.0;
+    for (int base = nb; base < ne; base += 64) {
+        __syncthreads();
+        int n = base + threadIdx.x;
+        if (n < ne) {
+            double B1[P + 1], B2[P + 1], w;
+            if (is_cut) {
+                basis_eval<P>(A.d1.knots, P + e1, A.nx[n], B1);
+                basis_eval<P>(A.d2.knots, P + e2, A.ny[n], B2);
+                w = A.nw[n];
+            } else {
+                int g1 = n % (P + 1), g2 = n / (P + 1);
+#pragma unroll
+                for (int a = 0; a <= P; ++a) {
+                    B1[a] = A.d1.Bg[(e1 * (P + 1) + g1) * (P + 1) + a];
+                    B2[a] = A.d2.Bg[(e2 * (P + 1) + g2) * (P + 1) + a];
+                }
+                w = A.d1.wg[e1 * (P + 1) + g1] * A.d2.wg[e2 * (P + 1) + g2];
+            }
+            double Ug = 0.0, Rg = 0.0;
+#pragma unroll
+            for (int a2 = 0; a2 <= P; ++a2)
+#pragma unroll
+                for (int a1 = 0; a1 <= P; ++a1) {
+                    double phi = B1[a1] * B2[a2];
+                    sPhi[threadIdx.x][a2 * (P + 1) + a1] = phi;
+                    Ug += phi * sU[a2 * (P + 1) + a1];
+                    Rg += phi * sR[a2 * (P + 1) + a1];
+                }
+            double cg = A.c[pbase + n];
+            if (r) {
+                Rg *= w;
+                dc[pbase + n] = Ug * Rg;
+                sT[threadIdx.x] = cg * Rg;
+            } else {
+                sT[threadIdx.x] = w * cg * Ug;
+            }
+        }
+        __syncthreads();
+        int cnt = min(64, ne - base);
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            int l = threadIdx.x + 64 * k;
+            if (l < L)
+                for (int m = 0; m < cnt; ++m) acc[k] += sT[m] * sPhi[m][l];
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        int l = threadIdx.x + 64 * k;
+        if (l < L) Ye[(size_t)re * L + l] = acc[k];
+    }
+}
+
+// Sum of the element vectors over the band / cut elements of supp B_j,
+// for the rows formed element-wise (forward) or every active function (adjoint),
+// plus (adjoint) the WQ-grid part sum_k B_j(x_k) CR_k.
+__global__ void k_mf_gather(MfArgs A, const double* __restrict__ Ye, const double* __restrict__ CR,
+                            double* __restrict__ out, int adjoint) {
+    int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= A.n_act) return;
+    int f = A.fn_of[r];
+    int p = A.p;
+    int8_t cls = A.fcls[f];
+    if (!adjoint && wq_row(A, cls)) return;
+    int i1 = f % A.n1, i2 = f / A.n1;
+    int L = (p + 1) * (p + 1);
+    double s = 0.0;
+    for (int e2 = max(0, i2 - p); e2 <= min(A.N2 - 1, i2); ++e2)
+        for (int e1 = max(0, i1 - p); e1 <= min(A.N1 - 1, i1); ++e1) {
+            int e = e2 * A.N1 + e1;
+            int8_t c = A.ecls[e];
+            if (c == EL_OUTSIDE) continue;
+            int re = (c == EL_CUT) ? A.n_band + A.cut_id[e] : A.band_id[e];
+            if (re < 0) continue;  // inside element used by no element-formed row
+            s += Ye[(size_t)re * L + (i2 - e2) * (p + 1) + (i1 - e1)];
+        }
+    if (adjoint && A.method != IGA_GAUSS_REF) {
+        int k1 = A.d1.pt0[max(0, i1 - p)], q1 = A.d1.pt0[min(A.N1 - 1, i1) + 1] - k1;
+        int k2 = A.d2.pt0[max(0, i2 - p)], q2 = A.d2.pt0[min(A.N2 - 1, i2) + 1] - k2;
+        double g = 0.0;
+        for (int b = 0; b < q2; ++b) {
+            int kk2 = k2 + b, m2 = A.d2.eq[kk2];
+            double b2 = A.d2.Bq[kk2 * (p + 1) + (i2 - m2)];
+            double in = 0.0;
+            for (int a = 0; a < q1; ++a) {
+                int kk1 = k1 + a, m1 = A.d1.eq[kk1];
+                in += A.d1.Bq[kk1 * (p + 1) + (i1 - m1)] * CR[(size_t)kk2 * A.d1.Q + kk1];
+            }
+            g += b2 * in;
+        }
+        s += g;
+    }
+    out[r] = s;
+}
+
+static MfArgs mf_args(Plan& P, const double* c) {
+    MfArgs A;
+    A.d1 = P.dir[0];
+    A.d2 = P.dir[1];
+    A.p = P.p;
+    A.n1 = P.n1;
+    A.n2 = P.n2;
+    A.N1 = P.N1;
+    A.N2 = P.N2;
+    A.method = P.method;
+    A.fcls = P.fcls;
+    A.ecls = P.ecls;
+    A.act_of = P.act_of;
+    A.fn_of = P.fn_of;
+    A.band_list = P.band_list;
+    A.cut_list = P.cut_list;
+    A.band_id = P.band_id;
+    A.cut_id = P.cut_id;
+    A.node_off = P.node_off;
+    A.nx = P.node_x;
+    A.ny = P.node_y;
+    A.nw = P.node_w;
+    A.n_band = (int)P.n_band;
+    A.n_cut = (int)P.n_cut_el;
+    A.n_act = (int)P.n_act;
+    A.c = c;
+    A.nq = P.dir[0].Q * P.dir[1].Q;
+    A.nb = (int)P.n_band * (P.p + 1) * (P.p + 1);
+    return A;
+}
+
+static void mf_buffers(Plan& P) {
+    size_t nq = (size_t)P.dir[0].Q * P.dir[1].Q;
+    size_t L = (size_t)(P.p + 1) * (P.p + 1);
+    if (!P.sw.G) P.sw.G = P.alloc<double>(2 * nq);
+    if (!P.sw.Ue) P.sw.Ue = P.alloc<double>(std::max<int64_t>(1, P.n_band + P.n_cut_el) * L);
+}
+
+static void launch_elem(Plan& P, const MfArgs& A, const double* u, const double* r, double* Ye, double* dc,
+                        hipStream_t s) {
+    int nre = (int)(P.n_band + P.n_cut_el);
+    if (nre == 0) return;
+    switch (P.p) {
+#define CASE(PP) \
+    case PP: hipLaunchKernelGGL(k_mf_elem<PP>, dim3(nre), dim3(64), 0, s, A, u, r, Ye, dc); break;
+        CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
+#undef CASE
+    }
+}
+
+void mf_apply(Plan& P, const double* c, const double* u, double* y, hipStream_t s) {
+    mf_buffers(P);
+    MfArgs A = mf_args(P, c);
+    int n = (int)P.n_act;
+    if (P.method != IGA_GAUSS_REF) {
+        hipLaunchKernelGGL(k_mf_grid, dim3((A.nq + 255) / 256), dim3(256), 0, s, A, u, P.sw.G, 1);
+        hipLaunchKernelGGL(k_mf_wq_rows, dim3((n + 255) / 256), dim3(256), 0, s, A, (const double*)P.sw.G, y);
+    }
+    launch_elem(P, A, u, nullptr, P.sw.Ue, nullptr, s);
+    hipLaunchKernelGGL(k_mf_gather, dim3((n + 255) / 256), dim3(256), 0, s, A, (const double*)P.sw.Ue,
+                       (const double*)nullptr, y, 0);
+}
+
+void mf_adjoint(Plan& P, const double* c, const double* u, const double* r, double* du, double* dc, hipStream_t s) {
+    mf_buffers(P);
+    MfArgs A = mf_args(P, c);
+    int n = (int)P.n_act;
+    size_t nq = (size_t)A.nq;
+    double* U = P.sw.G;
+    double* CR = P.sw.G + nq;
+    if (P.method != IGA_GAUSS_REF) {
+        hipLaunchKernelGGL(k_mf_grid, dim3((A.nq + 255) / 256), dim3(256), 0, s, A, u, U, 0);
+        hipLaunchKernelGGL(k_mf_grid_adj, dim3((A.nq + 255) / 256), dim3(256), 0, s, A, (const double*)U, r, dc, CR);
+    } else {
+        HIPX(hipMemsetAsync(dc, 0, sizeof(double) * nq, s));
+    }
+    launch_elem(P, A, u, r, P.sw.Ue, dc, s);
+    hipLaunchKernelGGL(k_mf_gather, dim3((n + 255) / 256), dim3(256), 0, s, A, (const double*)P.sw.Ue,
+                       (const double*)CR, du, 1);
+}
+
+}  // namespace iga
+
+using namespace iga;
+
+extern "C" {
+
+int iga_mf_apply(iga_plan* plan, const double* c_points, const double* u, double* y, void* stream) {
+    try {
+        IGA_REQUIRE(plan && c_points && u && y, IGA_E_INVALID, "null argument");
+        IGA_REQUIRE(plan->method == IGA_HYBRID_GAUSS || plan->method == IGA_GAUSS_REF, IGA_E_UNSUPPORTED,
+                    "matrix-free product is built for hybrid Gauss and the reference rules");
+        mf_apply(*plan, c_points, u, y, (hipStream_t)stream);
+        HIPX(hipGetLastError());
+    } catch (const Error& e) {
+        set_error(e.msg);
+        return e.code;
+    }
+    return IGA_OK;
+}
+
+int iga_mf_adjoint(iga_plan* plan, const double* c_points, const double* u, const double* gy, double* du, double* dc,
+                   void* stream) {
+    try {
+        IGA_REQUIRE(plan && c_points && u && gy && du && dc, IGA_E_INVALID, "null argument");
+        IGA_REQUIRE(plan->method == IGA_HYBRID_GAUSS || plan->method == IGA_GAUSS_REF, IGA_E_UNSUPPORTED,
+                    "matrix-free adjoint is built for hybrid Gauss and the reference rules");
+        mf_adjoint(*plan, c_points, u, gy, du, dc, (hipStream_t)stream);
+        HIPX(hipGetLastError());
+    } catch (const Error& e) {
+        set_error(e.msg);
+        return e.code;
+    }
+    return IGA_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,245 @@
+// Internal layout of a plan: device tables of one trimmed patch.
+#pragma once
+
+#include "common.hpp"
+
+#include <vector>
+
+namespace iga {
+
+enum ElemClass : int8_t { EL_OUTSIDE = 0, EL_INSIDE = 1, EL_CUT = 2 };
+enum FnClass : int8_t { FN_EXTERIOR = 0, FN_INTERIOR = 1, FN_CUT = 2 };
+
+// Endpoint kinds of an arc: a piece end, a crossing of x = bp1[line], or of y = bp2[line].
+enum : int32_t { END_PIECE = 0, END_VLINE = 1, END_HLINE = 2 };
+
+constexpr int kMaxEdgeSegs = 8;     // visible segments per element edge
+constexpr int kMaxEdgeCuts = 16;    // split points per element edge
+constexpr int kMaxPiecesPerSeg = 5; // monotone pieces per curve segment
+constexpr int kMaxIsectPerPiece = 8;
+
+// Per-direction weighted-quadrature and Gauss tables (device pointers).
+struct DirDev {
+    int N;      // elements
+    int n;      // functions
+    int Q;      // WQ points
+    int qmax;   // max points in one support
+    const double* knots;  // p+1 repeated ends + interior (length N + 2p + 1)
+    double* bp;           // N+1 breakpoints
+    double* xq;           // Q
+    int* eq;              // Q owning element
+    int* pt0;             // N+1 first point of element
+    double* Bq;           // Q*(p+1)
+    double* dBq;          // Q*(p+1)
+    double* M1;           // n*(2p+1) univariate mass band
+    double* W;            // n*qmax weights, point k0(i)+q with k0(i) = pt0[max(0,i-p)]
+    double* xg;           // N*(p+1) Gauss points
+    double* wg;           // N*(p+1) Gauss weights
+    double* Bg;           // N*(p+1)*(p+1) [e][g][a]
+    double* dBg;          // N*(p+1)*(p+1)
+};
+
+struct CurveDev {
+    int kind;       // IGA_CURVE_*
+    int degree;
+    int n_seg;      // polynomial segments (1 for ellipses)
+    int seg0;       // first segment in the segment array
+    double cx, cy, a, b, phi;
+    double sigma;   // -1 if the native orientation is counter-clockwise
+    double t_range; // parameter length of one segment (1 or 2 pi)
+};
+
+struct SegDev {
+    int curve;
+    int seg;        // index within its curve
+    int kind;
+    int pad;
+    double px[4], py[4];  // power coefficients, low first (BSPLINE)
+};
+
+struct PieceDev {
+    int curve, seg;      // owning curve and segment
+    int pad0, pad1;
+    double t0, t1;       // parameter range, t0 < t1
+    double x0, y0, x1, y1;
+};
+
+struct CrossDev {
+    double t;
+    int kind;   // END_VLINE or END_HLINE
+    int line;   // breakpoint index
+};
+
+struct ArcDev {
+    int curve, seg, piece, keep;
+    double t0, t1;
+    int e1, e2;
+    int k0, l0;   // start endpoint kind / line
+    int k1, l1;   // end endpoint kind / line
+};
+
+struct CutElemDev {
+    int e1, e2;
+    int variant;        // 0 left, 1 right, 2 bottom, 3 top base
+    int nseg[4];        // visible segments per edge: 0 left, 1 right, 2 bottom, 3 top
+    double seg[4][kMaxEdgeSegs][2];
+};
+
+// Everything the trimming kernels need, passed by value.
+struct TrimDev {
+    int n_curves;
+    int n_segs;
+    const CurveDev* curves;
+    SegDev* segs;
+    PieceDev* pieces;      // capacity cap_pieces
+    int* n_pieces;         // device count
+    int* piece_curve_off;  // n_curves+1: pieces of curve c are [off[c], off[c+1])
+    PieceDev* pieces0;     // before curve-curve splits
+    int* n_pieces0;
+    double* isect_t;       // cap_pieces0 * kMaxIsectPerPiece
+    int* isect_n;
+    int* cross_cnt;        // per piece: nv + nh
+    int* nv;               // per piece vertical crossings
+    int* cross_off;        // cap_pieces + 1 (exclusive scan)
+    CrossDev* cross;       // capacity cap_cross, ordered per piece (vertical then horizontal)
+    CrossDev* merged;      // sorted by t per piece
+    ArcDev* arcs;          // capacity cap_cross + cap_pieces
+    int cap_pieces0, cap_pieces, cap_cross, cap_arcs;
+};
+
+// Buffers of the L2 projection and the matrix-free product (allocated on first use).
+struct SolveWork {
+    double* gc = nullptr;     // g c at every rule point
+    double* F = nullptr;      // element vectors of band and cut elements
+    double* A = nullptr;      // (M + M^T)/2
+    double *r = nullptr, *z = nullptr, *pv = nullptr, *q = nullptr, *part = nullptr, *scal = nullptr, *b = nullptr;
+    double* h_scal = nullptr; // pinned host copy of the scalars
+    double* G = nullptr;      // matrix-free: c U on the WQ grid / c R
+    double* Ue = nullptr;     // matrix-free: element vectors
+};
+
+struct Plan {
+    int device = 0;
+    int p = 0;
+    int method = IGA_HYBRID_GAUSS;
+    int n_r = 0, n_q_override = 0, n_s = 0;
+    int tile1 = 64, tile2 = 8;
+    int N1 = 0, N2 = 0, n1 = 0, n2 = 0;
+
+    // raw inputs (device)
+    double* knots[2] = {nullptr, nullptr};
+    std::vector<double> h_knots[2];
+    std::vector<CurveDev> h_curves;
+    std::vector<SegDev> h_segs_in;  // control points kept here for the segment build
+    double* d_cp = nullptr;         // packed curve control points (x, y)
+    int* d_cp_off = nullptr;        // per curve offset into d_cp
+
+    DirDev dir[2];
+    double* gauss_x = nullptr;  // packed Gauss-Legendre table
+    double* gauss_w = nullptr;
+
+    // trimming
+    TrimDev trim{};
+    CurveDev* d_curves = nullptr;
+    int8_t* ecls = nullptr;        // N1*N2
+    int* cut_id = nullptr;         // N1*N2 -> cut element id or -1
+    int* band_id = nullptr;        // N1*N2 -> band element id or -1
+    int8_t* fcls = nullptr;        // n1*n2
+    int* act_of = nullptr;         // n1*n2
+    int* fn_of = nullptr;          // n_act
+    int* cut_rows = nullptr;       // compact ids of cut rows
+    int* form_rows = nullptr;      // rows formed by the element/cut kernel (method dependent)
+    int* cut_list = nullptr;       // flat ids of cut elements
+    int* band_list = nullptr;      // flat ids of band elements
+    int* arc_cnt = nullptr;        // per cut element
+    int* arc_off = nullptr;
+    int* arc_fill = nullptr;
+    int* arc_list = nullptr;
+    CutElemDev* cut_el = nullptr;
+    int* node_cnt = nullptr;
+    int* node_off = nullptr;
+    double* node_x = nullptr;      // n_cut_nodes
+    double* node_y = nullptr;
+    double* node_w = nullptr;
+    int* node_el = nullptr;        // cut element id of each node
+    double* cutE = nullptr;        // n_cut_el * (p+1)^4 local matrices
+
+    // scratch for scans and counts
+    int* flags = nullptr;          // max(n1*n2, N1*N2) + 1
+    int* scan_tmp = nullptr;       // block sums of a scan, then compaction positions
+    int scan_pos_off = 0;
+    int* counts = nullptr;         // small device counter block
+    int* status = nullptr;         // device status word
+
+    // points and coefficient values (c_wq [Q2][Q1], c_band, c_cut)
+    double* pts_xy = nullptr;      // n_points * 2
+    double* c_wq = nullptr;
+    double* c_band = nullptr;
+    double* c_cut = nullptr;
+    double* c_wq_masked = nullptr; // naive WQ only
+
+    // sizes
+    int64_t n_act = 0, n_interior = 0, n_cut_fn = 0, n_cut_el = 0, n_band = 0;
+    int64_t n_nodes = 0, n_arcs = 0, nnz = 0, n_form_rows = 0, n_points = 0;
+    int64_t bytes = 0;
+
+    // timing
+    bool timing = false;
+    std::vector<hipEvent_t> ev_pool;
+    std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_records;
+    double phase_ms[IGA_PHASE_COUNT] = {0, 0, 0, 0};
+    int64_t phase_cnt[IGA_PHASE_COUNT] = {0, 0, 0, 0};
+
+    SolveWork sw;
+    std::vector<void*> allocations;
+    template <typename T>
+    T* alloc(size_t n) {
+        void* ptr = nullptr;
+        size_t bytes_ = n * sizeof(T) + 16;
+        if (hipMalloc(&ptr, bytes_) != hipSuccess)
+            throw Error{IGA_E_NOMEM, "hipMalloc of " + std::to_string(bytes_) + " bytes failed"};
+        allocations.push_back(ptr);
+        bytes += (int64_t)bytes_;
+        return static_cast<T*>(ptr);
+    }
+    ~Plan();
+};
+
+// Coefficient values seen by the formation kernels.
+struct CoefView {
+    int is_const;
+    double value;
+    const double* wq;    // [Q2][Q1]
+    const double* band;  // [n_band][(p+1)^2]
+    const double* cut;   // [n_nodes]
+};
+
+// ---------------------------------------------------------------- launchers
+// setup.hip
+void launch_gauss_table(Plan& P, hipStream_t s);
+void launch_dir_tables(Plan& P, int d, hipStream_t s);
+void launch_wq_weights(Plan& P, int d, hipStream_t s);
+// scan.hip
+void exclusive_scan(const int* in, int* out, int n, int* tmp, hipStream_t s);
+// trim.hip
+void launch_trim_curves(Plan& P, hipStream_t s);            // segments + monotone pieces (+ unions)
+void launch_trim_crossings(Plan& P, hipStream_t s);         // counts + scan
+void launch_trim_arcs(Plan& P, hipStream_t s);              // solve, merge, arcs
+void launch_trim_classes(Plan& P, hipStream_t s);           // elements, functions, flags
+void launch_trim_lists(Plan& P, hipStream_t s);             // act_of, cut/band lists
+void launch_trim_cutprep(Plan& P, hipStream_t s);           // per cut element segments, variant, counts
+void launch_trim_nodes(Plan& P, hipStream_t s);             // node coordinates and weights
+void launch_orientation(Plan& P, hipStream_t s);
+void launch_naive_mask(Plan& P, const double* src, double cval, hipStream_t s);
+void launch_row_nnz(Plan& P, int* cnt, int* out, hipStream_t s);
+// form.hip
+CoefView coef_view(Plan& P, const iga_coeff& c);
+void launch_points(Plan& P, hipStream_t s);
+void launch_coef(Plan& P, const iga_coeff& c, hipStream_t s);
+void launch_interior_rows(Plan& P, const iga_coeff& c, double* vals, hipStream_t s);
+void launch_cut_rows(Plan& P, const iga_coeff& c, double* vals, hipStream_t s);
+
+}  // namespace iga
+
+// The opaque handle of the C ABI is the plan itself.
+struct iga_plan : public iga::Plan {};

@@ -1,0 +1,187 @@
+"""GPU parity of mass formation (Eq. (6) over the visible domain) against the oracle.
+
+Metric: max |dM_ij| / S_ij with S_ij = sum of |w c B_i B_j| over the entry's
+quadrature terms (the entry's relative error measured against the scale of its
+own rounding; it equals the plain relative error when no term cancels).
+* P1 -- weights of Eq. (5), solved independently on each side (Householder QR
+  of A^T on the device, SVD least squares in the oracle): row-relative
+  difference <= max(1e-13, 1e-15 cond(A_i)).
+* P2 -- formation under identical rules (the oracle's weights and cut nodes
+  injected): <= 1e-12, no floor.
+* P3 -- end to end with the device's own weights and nodes: <= max(1e-10,
+  1e-15 max_i cond(A_i)), entries floored at 1e-3 of their row's largest term
+  sum and 1e-9 of the largest entry; for p = 6 the systems next to the patch
+  boundary reach cond ~ 1e7, and two NumPy solvers already differ by ~3e-10
+  there.
+Integer data (classes, compaction maps, counts) match exactly.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from gpu_common import (FLOOR_P3, ROWFLOOR_P3, inject_oracle_rules, oracle_cut_nodes, oracle_weight_table, p3_bound,
+                        parity_S, require_gpu, say)
+from oracle.assemble import Oracle, to_ell
+from oracle.geometry import Coefficient
+from oracle.trim import CUT_FN, EXTERIOR_FN
+from paper_2101_08053_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+CASES = {
+    "circle_p2_N100": lambda: wl.config1(N=100),
+    "cubic16_p4_N80": lambda: wl.config2(N=80),
+    "ellipses3_p6_N70": lambda: wl.config3(N=70),
+    "ellipses3_p3_N40": lambda: wl.config3(N=40, p=3),
+    "line_p3_N10": lambda: wl.table1_line(3),
+}
+_oracles = {}
+
+
+def _oracle(name):
+    if name not in _oracles:
+        cfg = CASES[name]()
+        _oracles[name] = (cfg, Oracle(cfg))
+    return _oracles[name]
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_structure_matches_oracle(name):
+    require_gpu()
+    from paper_2101_08053_amd import igatrim
+    cfg, o = _oracle(name)
+    say(f"[structure] {name}")
+    plan = igatrim.Plan(cfg, igatrim.HYBRID_GAUSS)
+    s = plan.sizes
+    ts = o.ts
+    assert s["n_act"] == ts.n_act
+    assert s["n_cut_el"] == len(ts.cut_elements())
+    act_of, fn_of, fcls = (t.cpu().numpy() for t in plan.index_maps())
+    np.testing.assert_array_equal(fcls, ts.fcls.reshape(-1))
+    np.testing.assert_array_equal(act_of, ts.act_of)
+    np.testing.assert_array_equal(fn_of, ts.active)
+    assert s["n_band_el"] == int(ts.band.sum())
+    # cut-element nodes, same order and values
+    ox, oy, ow = oracle_cut_nodes(o)
+    assert s["n_cut_nodes"] == len(ow)
+    pts = plan.points().cpu().numpy()
+    off = s["q1"] * s["q2"] + s["n_band_el"] * (cfg.p + 1) ** 2
+    np.testing.assert_allclose(pts[off:, 0], ox, rtol=0, atol=1e-13)
+    np.testing.assert_allclose(pts[off:, 1], oy, rtol=0, atol=1e-13)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_weight_tables_p1(name):
+    """P1: the device's weights of Eq. (5) against the oracle's (independent solvers)."""
+    torch = require_gpu()
+    from paper_2101_08053_amd import igatrim
+    cfg, o = _oracle(name)
+    plan = igatrim.Plan(cfg, igatrim.HYBRID_GAUSS)
+    from oracle import wq
+    for d in range(2):
+        Wg = plan.table(igatrim.TABLE_WQ_WEIGHTS, d).cpu().numpy()
+        Wo = oracle_weight_table(o, d, Wg.shape[1])
+        kappa = wq.wq_condition(cfg.knots[d], cfg.p)
+        rel = np.abs(Wg - Wo).max(axis=1) / np.abs(Wo).max(axis=1)
+        say(f"[P1] {name} dir {d}: max row-relative weight difference {rel.max():.3e} (row {rel.argmax()}, "
+            f"cond {kappa[rel.argmax()]:.2e})")
+        assert np.all(rel <= np.maximum(1e-13, 1e-15 * kappa))
+        xq = plan.table(igatrim.TABLE_WQ_POINTS, d).cpu().numpy().ravel()
+        np.testing.assert_allclose(xq, o.xs1 if d == 0 else o.xs2, rtol=0, atol=1e-15)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_hybrid_parity(name):
+    torch = require_gpu()
+    from paper_2101_08053_amd import igatrim
+    cfg, o = _oracle(name)
+    say(f"[hybrid] {name}")
+    plan = igatrim.Plan(cfg, igatrim.HYBRID_GAUSS)
+    ref = to_ell(o.hybrid(), o.ts)
+    S = to_ell(o.hybrid(absolute=True), o.ts)
+    # P2: formation under the oracle's weights and cut nodes
+    inject_oracle_rules(plan, o)
+    v2 = plan.mass_form().cpu().numpy()
+    plan.status()
+    m2 = parity_S(v2, ref, S, o.ts, "P2")
+    if cfg.coef == wl.COEF_GEOM_DETJ:
+        cg = plan.table(igatrim.TABLE_C_WQ).cpu().numpy().reshape(len(o.xs2), len(o.xs1)).T
+        co = o.wq_grid_coef()
+        say(f"   c on WQ grid: max rel diff {np.abs(cg - co).max() / np.abs(co).max():.3e}")
+    say(f"   P2 parity {m2:.3e}")
+    assert m2 <= 1e-12
+    # P3: end to end with the device's own weights (rebuilt by a full formation)
+    v3 = plan.mass_form(full=True).cpu().numpy()
+    m3 = parity_S(v3, ref, S, o.ts, "P3", FLOOR_P3, ROWFLOOR_P3)
+    tol, kappa = p3_bound(o)
+    say(f"   P3 parity {m3:.3e} (bound {tol:.1e}, max cond {kappa:.2e})")
+    assert m3 <= tol
+    vals2 = plan.mass_form(full=True).cpu().numpy()
+    assert np.array_equal(v3, vals2)
+
+
+@pytest.mark.parametrize("p", [1, 2, 4, 6])
+def test_table1_methods(p):
+    """Reference Gauss, hybrid and naive WQ on the line trim (Table 1 setting), c = 1."""
+    require_gpu()
+    from paper_2101_08053_amd import igatrim
+    cfg = wl.table1_line(p)
+    o = Oracle(cfg, coef=Coefficient(cfg, kind=wl.COEF_CONST))
+    say(f"[table1] p={p}")
+    G = to_ell(o.gauss_reference(), o.ts)
+    SG = to_ell(o.gauss_reference(absolute=True), o.ts)
+    SH = to_ell(o.hybrid(absolute=True), o.ts)
+    SN = to_ell(o.naive(absolute=True), o.ts)
+    tol, _ = p3_bound(o)
+    outs, own = {}, {}
+    for meth in (igatrim.GAUSS_REF, igatrim.HYBRID_GAUSS, igatrim.NAIVE_WQ):
+        plan = igatrim.Plan(cfg, meth)
+        c1 = plan.coeff(igatrim.COEF_CONST, 1.0)
+        own[meth] = plan.mass_form(c1).cpu().numpy()
+        inject_oracle_rules(plan, o)
+        outs[meth] = plan.mass_form(c1).cpu().numpy()
+    H, N = to_ell(o.hybrid(), o.ts), to_ell(o.naive(), o.ts)
+    assert parity_S(outs[igatrim.GAUSS_REF], G, SG, o.ts, "ref") <= 1e-12
+    assert parity_S(outs[igatrim.HYBRID_GAUSS], H, SH, o.ts, "hybrid") <= 1e-12
+    assert parity_S(outs[igatrim.NAIVE_WQ], N, SN, o.ts, "naive") <= 1e-12
+    assert parity_S(own[igatrim.GAUSS_REF], G, SG, o.ts, "ref own", FLOOR_P3, ROWFLOOR_P3) <= tol
+    assert parity_S(own[igatrim.HYBRID_GAUSS], H, SH, o.ts, "hybrid own", FLOOR_P3, ROWFLOOR_P3) <= tol
+    assert parity_S(own[igatrim.NAIVE_WQ], N, SN, o.ts, "naive own", FLOOR_P3, ROWFLOOR_P3) <= tol
+    outs = own
+    # Table 1: hybrid at round-off from the reference, naive WQ far from it
+    assert np.linalg.norm(outs[igatrim.HYBRID_GAUSS] - G) < 1e-14
+    assert np.linalg.norm(outs[igatrim.NAIVE_WQ] - G) > 1e-5
+
+
+def test_area_invariant_c1():
+    """sum_ij M_ij = visible area (1 - pi/16 for the circle), c = 1."""
+    require_gpu()
+    from paper_2101_08053_amd import igatrim
+    for N in (32, 100):
+        cfg = wl.config1(N=N)
+        plan = igatrim.Plan(cfg, igatrim.HYBRID_GAUSS)
+        vals = plan.mass_form(plan.coeff(igatrim.COEF_CONST, 1.0)).cpu().numpy()
+        assert abs(vals.sum() - (1 - math.pi / 16)) < 1e-10
+
+
+def test_untrimmed_kronecker():
+    require_gpu()
+    from oracle import wq
+    from paper_2101_08053_amd import igatrim
+    p, N1 = 3, 70
+    cfg = wl.Patch(p=p, n_el=(N1, 9), knots=(wl.open_uniform_knots(N1, p), wl.open_uniform_knots(9, p)))
+    plan = igatrim.Plan(cfg, igatrim.HYBRID_GAUSS)
+    vals = plan.mass_form(plan.coeff(igatrim.COEF_CONST, 1.0)).cpu().numpy()
+    M1, M2 = wq.mass_1d(cfg.knots[0], p), wq.mass_1d(cfg.knots[1], p)
+    n1, n2 = N1 + p, 9 + p
+    W = 2 * p + 1
+    ref = np.zeros_like(vals)
+    for s in range(W * W):
+        a, b = s // W - p, s % W - p
+        for r in range(n1 * n2):
+            i1, i2 = r % n1, r // n1
+            j1, j2 = i1 + a, i2 + b
+            if 0 <= j1 < n1 and 0 <= j2 < n2:
+                ref[s, r] = M1[i1, j1] * M2[i2, j2]
+    assert np.abs(vals - ref).max() <= 1e-13 * np.abs(ref).max()

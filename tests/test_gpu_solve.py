@@ -1,0 +1,113 @@
+"""GPU L2 projection (Sect. 4.2): right-hand side and PCG against the oracle.
+
+Right-hand side under identical rules (oracle weights and cut nodes
+injected): max |db| <= 1e-13 max |b|; with the device's own rules 1e-10.
+Solution: the oracle's residual of the device solution, ||b - A u|| / ||b||
+with the oracle's A and b, stays within 1e-10 (PCG stops at 1e-12 on the
+device's A and b).
+"""
+import math
+
+import numpy as np
+import pytest
+
+from gpu_common import inject_oracle_rules, require_gpu, say
+from oracle import project
+from oracle.assemble import Oracle
+from oracle.geometry import Coefficient
+from paper_2101_08053_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+def _sincos():
+    from paper_2101_08053_amd import igatrim
+    return igatrim.target_sincos(math.pi, 0.0, math.pi, 0.0)
+
+
+def _project(cfg, method=None, coef_kind=None, oracle=None):
+    from paper_2101_08053_amd import igatrim
+    plan = igatrim.Plan(cfg, igatrim.HYBRID_GAUSS if method is None else method)
+    if oracle is not None:
+        inject_oracle_rules(plan, oracle)
+    c = plan.coeff(coef_kind) if coef_kind is not None else plan.coeff()
+    vals = plan.mass_form(c)
+    u, info = igatrim.l2_project(plan, vals, c, _sincos(), rtol=1e-12)
+    b = igatrim.rhs(plan, c, _sincos())
+    return plan, u.cpu().numpy(), b.cpu().numpy(), info
+
+
+@pytest.mark.parametrize("N", [32, 70])
+def test_projection_config1(N):
+    require_gpu()
+    cfg = wl.config1(N=N)
+    o = Oracle(cfg)
+    plan, u, b, info = _project(cfg, oracle=o)
+    say(f"[l2] circle N={N}: {info}")
+    assert info["converged"] and info["rel_residual"] <= 1e-12
+    bo = project.rhs(o, wl.config1_target)
+    assert np.abs(b - bo).max() <= 1e-13 * np.abs(bo).max()
+    M = o.hybrid()
+    A = 0.5 * (M + M.T)
+    res = np.linalg.norm(bo - A @ u) / np.linalg.norm(bo)
+    say(f"   oracle residual of device u: {res:.2e}")
+    assert res <= 1e-10
+    e_dev = project.l2_error(o, u, wl.config1_target)
+    e_or = project.l2_error(o, project.solve(M, bo), wl.config1_target)
+    assert abs(e_dev - e_or) <= 1e-6 * e_or
+
+
+def test_projection_rate():
+    """Device solutions converge at order p+1 = 3 (Sect. 4.2, optimal rate)."""
+    require_gpu()
+    errs = []
+    for N in (8, 16, 32, 64):
+        cfg = wl.config1(N=N)
+        _, u, _, info = _project(cfg)
+        assert info["converged"]
+        errs.append(project.l2_error(Oracle(cfg), u, wl.config1_target))
+    rates = [math.log2(errs[k] / errs[k + 1]) for k in range(3)]
+    say(f"[rate] errors {errs} rates {rates}")
+    assert min(rates[1:]) > 2.7
+
+
+def test_projection_polynomial_reproduction():
+    require_gpu()
+    from paper_2101_08053_amd import igatrim
+    cfg = wl.config1(N=20, p=3)
+    plan = igatrim.Plan(cfg, igatrim.HYBRID_GAUSS)
+    c = plan.coeff(igatrim.COEF_CONST, 1.0)
+    vals = plan.mass_form(c)
+    u, info = igatrim.l2_project(plan, vals, c, igatrim.target_monomial(3, 3), rtol=1e-13)
+    o = Oracle(cfg, coef=Coefficient(cfg, kind=wl.COEF_CONST))
+    err = project.l2_error(o, u.cpu().numpy(), lambda x, y: x ** 3 * y ** 3)
+    say(f"[reproduction] {info} error {err:.2e}")
+    assert err < 1e-10
+
+
+def test_projection_geometry_detj():
+    """Perturbed geometry, c = |det J|, g at physical points."""
+    require_gpu()
+    cfg = wl.config2(N=40, p=3)
+    o = Oracle(cfg)
+    plan, u, b, info = _project(cfg)
+    say(f"[l2 detJ] {info}")
+    assert info["converged"]
+    bo = project.rhs(o, wl.config1_target)
+    assert np.abs(b - bo).max() <= 1e-10 * np.abs(bo).max()
+    plan2, u2, b2, info2 = _project(cfg, oracle=o)
+    assert np.abs(b2 - bo).max() <= 1e-13 * np.abs(bo).max()
+    M = o.hybrid()
+    res = np.linalg.norm(bo - 0.5 * (M + M.T) @ u) / np.linalg.norm(bo)
+    assert res <= 1e-9
+
+
+def test_projection_reference_rules():
+    require_gpu()
+    from paper_2101_08053_amd import igatrim
+    cfg = wl.config1(N=24)
+    o = Oracle(cfg)
+    plan, u, b, info = _project(cfg, method=igatrim.GAUSS_REF, oracle=o)
+    assert info["converged"]
+    bo = project.rhs(o, wl.config1_target, "reference")
+    assert np.abs(b - bo).max() <= 1e-13 * np.abs(bo).max()
