@@ -272,6 +272,7 @@ int iga_plan_create(const iga_patch_desc* desc, const iga_opts* opts, iga_plan**
         D.dBq = P->alloc<double>((size_t)D.Q * (p + 1));
         D.M1 = P->alloc<double>((size_t)D.n * (2 * p + 1));
         D.W = P->alloc<double>((size_t)D.n * D.qmax);
+        D.WB = P->alloc<double>((size_t)D.n * D.qmax * (2 * p + 1));
         D.xg = P->alloc<double>((size_t)D.N * (p + 1));
         D.wg = P->alloc<double>((size_t)D.N * (p + 1));
         D.Bg = P->alloc<double>((size_t)D.N * (p + 1) * (p + 1));
@@ -496,6 +497,7 @@ int iga_plan_set_weights(iga_plan* P, int32_t dir, const double* W, void* stream
     IGA_REQUIRE(dir == 0 || dir == 1, IGA_E_INVALID, "direction must be 0 or 1");
     const DirDev& D = P->dir[dir];
     HIPX(hipMemcpyAsync(D.W, W, sizeof(double) * (size_t)D.n * D.qmax, hipMemcpyDefault, (hipStream_t)stream));
+    launch_wb_table(*P, dir, (hipStream_t)stream);
     API_END
 }
 

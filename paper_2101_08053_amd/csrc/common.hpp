@@ -38,6 +38,15 @@ struct Error {
 // Offset of the n-point rule in the packed Gauss table (rules 1..IGA_MAX_GAUSS).
 __host__ __device__ inline int gauss_off(int n) { return n * (n - 1) / 2; }
 
+// First weighted-quadrature point of element e in one direction (layout of
+// the WQ points: p+1 points in the first and the last element, 2 in every
+// other one); wq_pt0(N, N, p) is the number of points Q.
+__host__ __device__ inline int wq_pt0(int e, int N, int p) {
+    if (e <= 0) return 0;
+    if (e >= N) return (N == 1) ? p + 1 : 2 * (p + 1) + 2 * (N - 2);
+    return (p + 1) + 2 * (e - 1);
+}
+
 // -------------------------------------------------------------------------
 // B-spline values on one element by the triangular Cox-de Boor scheme.
 // span = index of the knot at the element's left end (p + e for open knot
@@ -59,6 +68,39 @@ __device__ __forceinline__ void basis_eval(const double* __restrict__ knots, int
             saved = left[j - r] * tmp;
         }
         N[j] = saved;
+    }
+}
+
+// Values and first derivatives, compile-time degree.
+template <int P>
+__device__ __forceinline__ void basis_eval_d(const double* __restrict__ knots, int span, double x, double* N,
+                                             double* dN) {
+    double left[P + 1], right[P + 1], low[P + 1];
+    N[0] = 1.0;
+#pragma unroll
+    for (int j = 1; j <= P; ++j) {
+        if (j == P) {
+#pragma unroll
+            for (int r = 0; r < P; ++r) low[r] = N[r];
+        }
+        left[j] = x - knots[span + 1 - j];
+        right[j] = knots[span + j] - x;
+        double saved = 0.0;
+#pragma unroll
+        for (int r = 0; r < j; ++r) {
+            double tmp = N[r] / (right[r + 1] + left[j - r]);
+            N[r] = saved + right[r + 1] * tmp;
+            saved = left[j - r] * tmp;
+        }
+        N[j] = saved;
+    }
+#pragma unroll
+    for (int a = 0; a <= P; ++a) {
+        int i = span - P + a;
+        double v = 0.0;
+        if (a >= 1) v += P * low[a - 1] / (knots[i + P] - knots[i]);
+        if (a <= P - 1) v -= P * low[a] / (knots[i + P + 1] - knots[i + 1]);
+        dN[a] = v;
     }
 }
 

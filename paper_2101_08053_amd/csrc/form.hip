@@ -104,17 +104,18 @@ __global__ void k_coef_band(DirDev D1, DirDev D2, int p, const double* __restric
     c[t] = detj_local(cp, n1, p, e1, e2, D1.Bg + r1, D1.dBg + r1, D2.Bg + r2, D2.dBg + r2);
 }
 
-__global__ void k_coef_cut(DirDev D1, DirDev D2, int p, const double* __restrict__ cp, int n1,
+template <int P>
+__global__ void k_coef_cut(DirDev D1, DirDev D2, const double* __restrict__ cp, int n1,
                            const int* __restrict__ cut_list, const int* __restrict__ node_el,
                            const double* __restrict__ nx, const double* __restrict__ ny, int n,
                            double* __restrict__ c) {
     int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= n) return;
     int e = cut_list[node_el[t]], e1 = e % D1.N, e2 = e / D1.N;
-    double B1[IGA_MAXP + 1], dB1[IGA_MAXP + 1], B2[IGA_MAXP + 1], dB2[IGA_MAXP + 1];
-    basis_eval_rt(D1.knots, p, p + e1, nx[t], B1, dB1);
-    basis_eval_rt(D2.knots, p, p + e2, ny[t], B2, dB2);
-    c[t] = detj_local(cp, n1, p, e1, e2, B1, dB1, B2, dB2);
+    double B1[P + 1], dB1[P + 1], B2[P + 1], dB2[P + 1];
+    basis_eval_d<P>(D1.knots, P + e1, nx[t], B1, dB1);
+    basis_eval_d<P>(D2.knots, P + e2, ny[t], B2, dB2);
+    c[t] = detj_local(cp, n1, P, e1, e2, B1, dB1, B2, dB2);
 }
 
 CoefView coef_view(Plan& P, const iga_coeff& c) {
@@ -146,9 +147,18 @@ void launch_coef(Plan& P, const iga_coeff& c, hipStream_t s) {
     if (nb > 0)
         hipLaunchKernelGGL(k_coef_band, dim3((nb + 255) / 256), dim3(256), 0, s, D1, D2, p, c.geom_cp, P.n1,
                            P.band_list, (int)P.n_band, P.c_band);
-    if (P.n_nodes > 0)
-        hipLaunchKernelGGL(k_coef_cut, dim3((P.n_nodes + 255) / 256), dim3(256), 0, s, D1, D2, p, c.geom_cp, P.n1,
-                           P.cut_list, P.node_el, P.node_x, P.node_y, (int)P.n_nodes, P.c_cut);
+    if (P.n_nodes > 0) {
+        dim3 g((unsigned)((P.n_nodes + 255) / 256)), b(256);
+        switch (p) {
+#define CASE(PP)                                                                                              \
+    case PP:                                                                                                  \
+        hipLaunchKernelGGL(k_coef_cut<PP>, g, b, 0, s, D1, D2, c.geom_cp, P.n1, P.cut_list, P.node_el, P.node_x, \
+                           P.node_y, (int)P.n_nodes, P.c_cut);                                                \
+        break;
+            CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
+#undef CASE
+        }
+    }
 }
 
 // ------------------------------------------------------- interior rows
@@ -162,109 +172,245 @@ struct IntArgs {
     double* vals;
     int64_t n_act;
     int tile2;
+    int ntx;                 // tiles along xi_1
 };
 
 template <int P>
-struct IntShape {
-    static constexpr int W = 2 * P + 1;          // band width
-    static constexpr int QM = 4 * P + 2;         // max WQ points in one support
-    static constexpr int KS = 2 * (64 + P) + 2 * P + 2;  // max xi_1 points of a tile
+struct IntCfg {
+    static constexpr int W = 2 * P + 1;                  // band width
+    static constexpr int QM = 4 * P + 2;                 // max WQ points in one support
+    static constexpr int NR = 2 * P + 2;                 // support points of a regular function
+    static constexpr int KS = 2 * (64 + P) + 2 * P + 2;  // max xi_1 points of a tile window
+    static constexpr int KG = 4 * P + 2;                 // max xi_1 points of a boundary tile
+    static constexpr bool WBREG = (P <= 5);              // w1 * B1 of each lane held in registers
 };
 
+// Tiles along xi_1: for N1 >= p+3, tile 0 holds the p+1 functions whose
+// support touches the first element, the last tile those touching the last
+// element (their elements carry p+1 points), and the tiles in between hold
+// 64 "regular" functions each (2 points in every support element). Smaller
+// patches use one generic tile.
+__device__ __forceinline__ void tile_of(int tx, int ntx, int N1, int n1, int p, int& I1, int& nlive, bool& generic) {
+    if (N1 < p + 3) {
+        I1 = 0;
+        nlive = n1;
+        generic = true;
+    } else if (tx == 0) {
+        I1 = 0;
+        nlive = p + 1;
+        generic = true;
+    } else if (tx == ntx - 1) {
+        I1 = N1 - 1;
+        nlive = p + 1;
+        generic = true;
+    } else {
+        I1 = p + 1 + 64 * (tx - 1);
+        nlive = min(64, (N1 - 2) - I1 + 1);
+        generic = false;
+    }
+}
+
+// Workgroups are handed to the XCDs round-robin; renumber them so that each
+// XCD works on a contiguous range of rows (neighbouring rows share most of
+// their coefficient points, which then stay in that XCD's L2).
+__device__ __forceinline__ int xcd_block(int bid, int nb) {
+    const int q = nb >> 3, r = nb & 7, x = bid & 7;
+    return x * q + min(x, r) + (bid >> 3);
+}
+
+// One workgroup = one test-function row i2 and a tile of (up to) 64 rows i1.
+// Stage 1 contracts xi_2 for every xi_1 point k of the tile's window,
+//   T[b][k] = sum_q (w2 B2)[i2][q][b] c(k, k2lo + q),
+// one point per thread; stage 2 contracts xi_1, one row i1 per lane,
+//   M[a][b] = sum_k (w1 B1)[i1][k][a] T[b][k],
+// the four wavefronts sharing the 2p+1 columns b. Every global load of a
+// stage is issued before the first one is used.
 template <int P>
 __global__ void __launch_bounds__(256) k_interior(IntArgs A) {
-    using S = IntShape<P>;
-    constexpr int W = S::W, QM = S::QM, KS = S::KS;
-    __shared__ double sT[W][KS];          // T[b][k1 - k1lo]
-    __shared__ double sB1[KS][P + 1];     // B values at the tile's xi_1 points
-    __shared__ double sW1[64][QM + 1];    // weights of each lane's test function
-    __shared__ double sWB2[QM][W];        // w2 * B for the current i2
-    __shared__ int sPt0[64 + P + 2];
+    using C = IntCfg<P>;
+    constexpr int W = C::W, QM = C::QM, NR = C::NR, KS = C::KS, KG = C::KG;
+    __shared__ __align__(16) double sT[W][KS];   // T[b][k - k1lo]
+    __shared__ double sWB2[QM][W];                 // w2 * B2 of the row
+    __shared__ double sB1[C::WBREG ? KG : KS][P + 1];  // B1 at the window's points
+    __shared__ double sW1[64][QM + 1];             // boundary tiles: w1 per lane
 
     const DirDev& D1 = A.d1;
     const DirDev& D2 = A.d2;
-    int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    int I1 = blockIdx.x * 64;
-    int I2 = blockIdx.y * A.tile2;
-    int elo = max(0, I1 - P), ehi = min(D1.N - 1, I1 + 63);
-    int k1lo = D1.pt0[elo], k1hi = D1.pt0[ehi + 1];
-    int ks = k1hi - k1lo;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int ntx = A.ntx;
+    const int blk = xcd_block(blockIdx.x, gridDim.x);
+    const int i2 = blk / ntx;
+    int I1, nlive;
+    bool generic;
+    tile_of(blk - i2 * ntx, ntx, D1.N, D1.n, P, I1, nlive, generic);
+    const int elo = max(0, I1 - P), ehi = min(D1.N - 1, I1 + nlive - 1);
+    const int k1lo = wq_pt0(elo, D1.N, P);
+    const int ks = wq_pt0(ehi + 1, D1.N, P) - k1lo;
+    const int k2lo = wq_pt0(max(0, i2 - P), D2.N, P);
+    const int q2 = wq_pt0(min(D2.N - 1, i2) + 1, D2.N, P) - k2lo;
+    const bool reg_row = (i2 >= P + 1) && (i2 <= D2.N - 2);  // q2 == NR, two points per element
 
-    for (int t = tid; t < ehi - elo + 2; t += 256) sPt0[t] = D1.pt0[elo + t] - k1lo;
-    for (int t = tid; t < ks * (P + 1); t += 256) sB1[t / (P + 1)][t % (P + 1)] = D1.Bq[(size_t)k1lo * (P + 1) + t];
-    for (int t = tid; t < 64 * QM; t += 256) {
-        int l = t / QM, q = t % QM;
-        int i1 = I1 + l;
-        sW1[l][q] = (i1 < D1.n && q < D1.qmax) ? D1.W[(size_t)i1 * D1.qmax + q] : 0.0;
+    // ---- loads: row identity, xi_2 factors, window tables, coefficient column
+    const int i1 = I1 + lane;
+    bool live = false;
+    int64_t cid = 0;
+    if (lane < nlive) {
+        const int f = i2 * D1.n + i1;
+        const int8_t cls = A.fcls[f];
+        const int id = A.act_of[f];
+        live = A.all_active ? (cls != FN_EXTERIOR) : (cls == FN_INTERIOR);
+        cid = id;
     }
-    int i1 = I1 + lane;
-    int k0_1 = (i1 < D1.n) ? D1.pt0[max(0, i1 - P)] - k1lo : 0;
+    double wb2 = 0.0;
+    if (tid < QM * W) {
+        const int q = tid / W;
+        if (q < q2) wb2 = D2.WB[((size_t)i2 * D2.qmax) * W + tid];
+    }
+    constexpr int NGB = (KG * (P + 1) + 255) / 256;
+    double gb[NGB];
+    if (generic) {
+#pragma unroll
+        for (int u = 0; u < NGB; ++u) {
+            const int t = tid + 256 * u;
+            gb[u] = (t < ks * (P + 1)) ? D1.Bq[(size_t)k1lo * (P + 1) + t] : 0.0;
+        }
+    }
+    const int kk = min(tid, ks - 1);
+    double cv[QM];
+    if (reg_row) {
+        if (A.cwq) {
+            const double* cc = A.cwq + (size_t)k2lo * D1.Q + k1lo + kk;
+#pragma unroll
+            for (int q = 0; q < NR; ++q) cv[q] = cc[(size_t)q * D1.Q];
+        } else {
+#pragma unroll
+            for (int q = 0; q < NR; ++q) cv[q] = A.c.value;
+        }
+    } else {
+        if (A.cwq) {
+            const double* cc = A.cwq + (size_t)k2lo * D1.Q + k1lo + kk;
+#pragma unroll
+            for (int q = 0; q < QM; ++q) cv[q] = (q < q2) ? cc[(size_t)q * D1.Q] : 0.0;
+        } else {
+#pragma unroll
+            for (int q = 0; q < QM; ++q) cv[q] = (q < q2) ? A.c.value : 0.0;
+        }
+    }
+    if (!generic && !C::WBREG) {
+        for (int t = tid; t < ks * (P + 1); t += 256) sB1[t / (P + 1)][t % (P + 1)] = D1.Bq[(size_t)k1lo * (P + 1) + t];
+    }
+    if (generic) {
+        for (int t = tid; t < 64 * QM; t += 256) {
+            const int l = t / QM, q = t % QM;
+            sW1[l][q] = (l < nlive && q < D1.qmax) ? D1.W[(size_t)(I1 + l) * D1.qmax + q] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < NGB; ++u) {
+            const int t = tid + 256 * u;
+            if (t < ks * (P + 1)) sB1[t / (P + 1)][t % (P + 1)] = gb[u];
+        }
+    }
+    if (tid < QM * W) sWB2[tid / W][tid % W] = wb2;
+    if (!__syncthreads_or(live)) return;   // no row of the tile is formed here
 
-    for (int r = 0; r < A.tile2; ++r) {
-        int i2 = I2 + r;
-        if (i2 >= D2.n) break;
-        int e2lo = max(0, i2 - P), e2hi = min(D2.N - 1, i2);
-        int k2lo = D2.pt0[e2lo], q2 = D2.pt0[e2hi + 1] - k2lo;
-        __syncthreads();
-        // w2_{k2,i2} B_{i2+b}(x_k2) for the current i2
-        for (int t = tid; t < QM * W; t += 256) {
-            int q = t / W, b = t % W;
-            double v = 0.0;
-            if (q < q2) {
-                int k2 = k2lo + q, e = D2.eq[k2];
-                int loc = i2 + b - P - e;
-                if (loc >= 0 && loc <= P) v = D2.W[(size_t)i2 * D2.qmax + q] * D2.Bq[(size_t)k2 * (P + 1) + loc];
-            }
-            sWB2[q][b] = v;
-        }
-        __syncthreads();
-        // stage 1: contract xi_2
-        for (int t = tid; t < ks; t += 256) {
-            double cv[QM];
+    // ---- stage 1: contract xi_2 for every xi_1 point of the window
+    if (tid < ks) {
+        if (reg_row) {
+            double T[W];
 #pragma unroll
-            for (int q = 0; q < QM; ++q) {
-                cv[q] = 0.0;
-                if (q < q2) cv[q] = A.cwq ? A.cwq[(size_t)(k2lo + q) * D1.Q + k1lo + t] : A.c.value;
+            for (int b = 0; b < W; ++b) T[b] = 0.0;
+#pragma unroll
+            for (int q = 0; q < NR; ++q) {
+                const int m2 = q >> 1;
+#pragma unroll
+                for (int bl = 0; bl <= P; ++bl) T[m2 + bl] += sWB2[q][m2 + bl] * cv[q];
             }
 #pragma unroll
+            for (int b = 0; b < W; ++b) sT[b][tid] = T[b];
+        } else {
+#pragma unroll 1
             for (int b = 0; b < W; ++b) {
-                double acc = 0.0;
+                double Tb = 0.0;
 #pragma unroll
-                for (int q = 0; q < QM; ++q) acc += sWB2[q][b] * cv[q];
-                sT[b][t] = acc;
+                for (int q = 0; q < QM; ++q) Tb += sWB2[q][b] * cv[q];
+                sT[b][tid] = Tb;
             }
         }
-        __syncthreads();
-        // stage 2: contract xi_1, one row per lane
-        bool live = false;
-        int64_t cid = -1;
-        if (i1 < D1.n) {
-            int f = i2 * D1.n + i1;
-            int8_t cls = A.fcls[f];
-            live = A.all_active ? (cls != FN_EXTERIOR) : (cls == FN_INTERIOR);
-            if (live) cid = A.act_of[f];
+    }
+
+    // regular lanes: w1 * B1 (or w1) at the 2p+2 support points, loaded while stage 1 finishes
+    double wb[C::WBREG ? NR : 1][C::WBREG ? P + 1 : 1];
+    double w1[C::WBREG ? 1 : NR];
+    if (!generic) {
+        const int i1c = min(i1, D1.n - 1);
+        if constexpr (C::WBREG) {
+            const double* row = D1.WB + (size_t)i1c * D1.qmax * W;
+#pragma unroll
+            for (int q = 0; q < NR; ++q)
+#pragma unroll
+                for (int al = 0; al <= P; ++al) wb[q][al] = row[q * W + (q >> 1) + al];
+        } else {
+#pragma unroll
+            for (int q = 0; q < NR; ++q) w1[q] = D1.W[(size_t)i1c * D1.qmax + q];
         }
+    }
+    __syncthreads();
+
+    // ---- stage 2: contract xi_1, one row per lane, columns b shared by the wavefronts
+    if (!generic) {
+        // regular lane: support points 2*lane .. 2*lane + 2p+1 of the window, two per element
+#pragma unroll 1
         for (int b = wave; b < W; b += 4) {
             double acc[W];
 #pragma unroll
             for (int a = 0; a < W; ++a) acc[a] = 0.0;
-            if (live) {
 #pragma unroll
-                for (int m = 0; m <= P; ++m) {
-                    int e = i1 - P + m;
-                    if (e < 0 || e >= D1.N) continue;
-                    int kb = sPt0[e - elo], ke = sPt0[e - elo + 1];
-                    for (int k = kb; k < ke; ++k) {
-                        double wt = sW1[lane][k - k0_1] * sT[b][k];
+            for (int m = 0; m <= P; ++m) {
+                const int k = 2 * lane + 2 * m;
+                const double2 t2 = *reinterpret_cast<const double2*>(&sT[b][k]);
+                if constexpr (C::WBREG) {
 #pragma unroll
-                        for (int al = 0; al <= P; ++al) acc[m + al] += wt * sB1[k][al];
-                    }
+                    for (int al = 0; al <= P; ++al) acc[m + al] += wb[2 * m][al] * t2.x + wb[2 * m + 1][al] * t2.y;
+                } else {
+                    const double wa = w1[2 * m] * t2.x, wc = w1[2 * m + 1] * t2.y;
+#pragma unroll
+                    for (int al = 0; al <= P; ++al) acc[m + al] += wa * sB1[k][al] + wc * sB1[k + 1][al];
                 }
+            }
+            if (live)
 #pragma unroll
                 for (int a = 0; a < W; ++a) A.vals[(size_t)(a * W + b) * A.n_act + cid] = acc[a];
+        }
+    } else if (live) {
+        const int k0_1 = wq_pt0(max(0, i1 - P), D1.N, P) - k1lo;
+#pragma unroll 1
+        for (int b = wave; b < W; b += 4) {
+            double acc[W];
+#pragma unroll
+            for (int a = 0; a < W; ++a) acc[a] = 0.0;
+#pragma unroll
+            for (int m = 0; m <= P; ++m) {
+                const int e = i1 - P + m;
+                if (e < 0 || e >= D1.N) continue;
+                const int kb = wq_pt0(e, D1.N, P) - k1lo, ke = wq_pt0(e + 1, D1.N, P) - k1lo;
+                for (int k = kb; k < ke; ++k) {
+                    const double wt = sW1[lane][k - k0_1] * sT[b][k];
+#pragma unroll
+                    for (int al = 0; al <= P; ++al) acc[m + al] += wt * sB1[k][al];
+                }
             }
+#pragma unroll
+            for (int a = 0; a < W; ++a) A.vals[(size_t)(a * W + b) * A.n_act + cid] = acc[a];
         }
     }
+}
+
+template <int P>
+static void launch_interior_p(Plan& Pl, IntArgs A, hipStream_t s) {
+    const int N1 = Pl.N1;
+    A.ntx = (N1 < P + 3) ? 1 : 2 + ((N1 - 2) - (P + 1) + 1 + 63) / 64;
+    const int nb = A.ntx * Pl.n2;
+    hipLaunchKernelGGL(k_interior<P>, dim3(nb), dim3(256), 0, s, A);
 }
 
 void launch_interior_rows(Plan& P, const iga_coeff& c, double* vals, hipStream_t s) {
@@ -281,12 +427,15 @@ void launch_interior_rows(Plan& P, const iga_coeff& c, double* vals, hipStream_t
     A.vals = vals;
     A.n_act = P.n_act;
     A.tile2 = P.tile2;
-    dim3 g((P.n1 + 63) / 64, (P.n2 + P.tile2 - 1) / P.tile2), b(256);
     switch (P.p) {
-#define CASE(PP) \
-    case PP: hipLaunchKernelGGL(k_interior<PP>, g, b, 0, s, A); break;
-        CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
-#undef CASE
+        case 1: launch_interior_p<1>(P, A, s); break;
+        case 2: launch_interior_p<2>(P, A, s); break;
+        case 3: launch_interior_p<3>(P, A, s); break;
+        case 4: launch_interior_p<4>(P, A, s); break;
+        case 5: launch_interior_p<5>(P, A, s); break;
+        case 6: launch_interior_p<6>(P, A, s); break;
+        case 7: launch_interior_p<7>(P, A, s); break;
+        case 8: launch_interior_p<8>(P, A, s); break;
         default: throw Error{IGA_E_UNSUPPORTED, "degree outside 1..8"};
     }
 }
@@ -379,50 +528,93 @@ struct CutRowArgs {
     int64_t n_act;
 };
 
+// One workgroup per row; the row's per-direction Gauss factors
+// F1[m1][g1][a] = w_g1 B_i1 B_{i1+a-p} (element e1 = i1-p+m1), F2 likewise,
+// the element classes and c at the Gauss points of its support elements are
+// staged in LDS; thread (a, b) then sums over the elements shared with its
+// column: Gauss on inside elements (sum-factorised), the cut element matrix
+// on cut elements.
 template <int P>
-__global__ void k_cut_rows(CutRowArgs A) {
-    constexpr int W = 2 * P + 1, L = (P + 1) * (P + 1);
-    int r = blockIdx.x;
+__global__ void __launch_bounds__((((2 * P + 1) * (2 * P + 1) + 63) / 64) * 64) k_cut_rows(CutRowArgs A) {
+    constexpr int W = 2 * P + 1, L = (P + 1) * (P + 1), NP = P + 1;
+    __shared__ double sF1[NP][NP][W];
+    __shared__ double sF2[NP][NP][W];
+    __shared__ double sC[NP][NP][L];
+    __shared__ int sCls[NP][NP];
+    __shared__ int sId[NP][NP];
+    const int r = blockIdx.x;
     if (r >= A.n_rows) return;
-    int s = threadIdx.x;
-    if (s >= W * W) return;
-    int row = A.rows[r];
-    int f = A.fn_of[row];
     const DirDev& D1 = A.d1;
     const DirDev& D2 = A.d2;
-    int i1 = f % D1.n, i2 = f / D1.n;
-    int a = s / W - P, b = s % W - P;
-    int j1 = i1 + a, j2 = i2 + b;
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const int row = A.rows[r];
+    const int f = A.fn_of[row];
+    const int i1 = f % D1.n, i2 = f / D1.n;
+    for (int t = tid; t < NP * NP * W; t += nt) {
+        int m = t / (NP * W), g = (t / W) % NP, a = t % W;
+        // direction 1
+        int e1 = i1 - P + m, j1 = i1 + a - P;
+        double v = 0.0;
+        if (e1 >= 0 && e1 < D1.N && j1 - e1 >= 0 && j1 - e1 <= P) {
+            int rr = (e1 * NP + g) * NP;
+            v = D1.wg[e1 * NP + g] * D1.Bg[rr + i1 - e1] * D1.Bg[rr + j1 - e1];
+        }
+        sF1[m][g][a] = v;
+        int e2 = i2 - P + m, j2 = i2 + a - P;
+        v = 0.0;
+        if (e2 >= 0 && e2 < D2.N && j2 - e2 >= 0 && j2 - e2 <= P) {
+            int rr = (e2 * NP + g) * NP;
+            v = D2.wg[e2 * NP + g] * D2.Bg[rr + i2 - e2] * D2.Bg[rr + j2 - e2];
+        }
+        sF2[m][g][a] = v;
+    }
+    for (int t = tid; t < NP * NP; t += nt) {
+        int m2 = t / NP, m1 = t % NP;
+        int e1 = i1 - P + m1, e2 = i2 - P + m2;
+        int cls = -1, id = -1;
+        if (e1 >= 0 && e1 < D1.N && e2 >= 0 && e2 < D2.N) {
+            int e = e2 * D1.N + e1;
+            cls = A.ecls[e];
+            id = (cls == EL_CUT) ? A.cut_id[e] : (cls == EL_INSIDE ? A.band_id[e] : -1);
+        }
+        sCls[m2][m1] = cls;
+        sId[m2][m1] = id;
+    }
+    __syncthreads();
+    if (!A.c.is_const) {
+        for (int t = tid; t < NP * NP * L; t += nt) {
+            int m2 = t / (NP * L), m1 = (t / L) % NP, g = t % L;
+            sC[m2][m1][g] = (sCls[m2][m1] == EL_INSIDE) ? A.c.band[(size_t)sId[m2][m1] * L + g] : 0.0;
+        }
+        __syncthreads();
+    }
+    const int s = tid;
+    if (s >= W * W) return;
+    const int a = s / W, b = s % W;          // column offsets a-p, b-p
+    const int j1 = i1 + a - P, j2 = i2 + b - P;
     double val = 0.0;
     if (j1 >= 0 && j1 < D1.n && j2 >= 0 && j2 < D2.n && A.act_of[j2 * D1.n + j1] >= 0) {
-        int e1lo = max(max(i1, j1) - P, 0), e1hi = min(min(i1, j1), D1.N - 1);
-        int e2lo = max(max(i2, j2) - P, 0), e2hi = min(min(i2, j2), D2.N - 1);
-        for (int e2 = e2lo; e2 <= e2hi; ++e2)
-            for (int e1 = e1lo; e1 <= e1hi; ++e1) {
-                int e = e2 * D1.N + e1;
-                int8_t cls = A.ecls[e];
-                if (cls == EL_OUTSIDE) continue;
-                if (cls == EL_CUT) {
-                    int li = (i2 - e2) * (P + 1) + (i1 - e1), lj = (j2 - e2) * (P + 1) + (j1 - e1);
-                    val += A.E[(size_t)A.cut_id[e] * L * L + li * L + lj];
-                    continue;
-                }
-                const double* cb = A.c.is_const ? nullptr : A.c.band + (size_t)A.band_id[e] * (P + 1) * (P + 1);
-                double sum = 0.0;
+        const int m1lo = max(0, a - P), m1hi = P + min(0, a - P);
+        const int m2lo = max(0, b - P), m2hi = P + min(0, b - P);
+        for (int m2 = m2lo; m2 <= m2hi; ++m2)
+            for (int m1 = m1lo; m1 <= m1hi; ++m1) {
+                const int cls = sCls[m2][m1];
+                if (cls == EL_INSIDE) {
+                    double sum = 0.0;
 #pragma unroll
-                for (int g2 = 0; g2 <= P; ++g2) {
-                    int r2 = (e2 * (P + 1) + g2) * (P + 1);
-                    double f2 = D2.wg[e2 * (P + 1) + g2] * D2.Bg[r2 + i2 - e2] * D2.Bg[r2 + j2 - e2];
-                    double in = 0.0;
+                    for (int g2 = 0; g2 < NP; ++g2) {
+                        double in = 0.0;
 #pragma unroll
-                    for (int g1 = 0; g1 <= P; ++g1) {
-                        int r1 = (e1 * (P + 1) + g1) * (P + 1);
-                        double cv = cb ? cb[g2 * (P + 1) + g1] : A.c.value;
-                        in += D1.wg[e1 * (P + 1) + g1] * D1.Bg[r1 + i1 - e1] * D1.Bg[r1 + j1 - e1] * cv;
+                        for (int g1 = 0; g1 < NP; ++g1)
+                            in += sF1[m1][g1][a] * (A.c.is_const ? A.c.value : sC[m2][m1][g2 * NP + g1]);
+                        sum += sF2[m2][g2][b] * in;
                     }
-                    sum += f2 * in;
+                    val += sum;
+                } else if (cls == EL_CUT) {
+                    const int li = (P - m2) * NP + (P - m1);
+                    const int lj = (j2 - (i2 - P + m2)) * NP + (j1 - (i1 - P + m1));
+                    val += A.E[(size_t)sId[m2][m1] * L * L + li * L + lj];
                 }
-                val += sum;
             }
     }
     A.vals[(size_t)s * A.n_act + row] = val;

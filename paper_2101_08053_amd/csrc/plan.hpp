@@ -33,6 +33,7 @@ struct DirDev {
     double* dBq;          // Q*(p+1)
     double* M1;           // n*(2p+1) univariate mass band
     double* W;            // n*qmax weights, point k0(i)+q with k0(i) = pt0[max(0,i-p)]
+    double* WB;           // n*qmax*(2p+1): W[i][q] * B_{i+b-p}(x_{k0(i)+q}) (0 off the element)
     double* xg;           // N*(p+1) Gauss points
     double* wg;           // N*(p+1) Gauss weights
     double* Bg;           // N*(p+1)*(p+1) [e][g][a]
@@ -219,6 +220,7 @@ struct CoefView {
 void launch_gauss_table(Plan& P, hipStream_t s);
 void launch_dir_tables(Plan& P, int d, hipStream_t s);
 void launch_wq_weights(Plan& P, int d, hipStream_t s);
+void launch_wb_table(Plan& P, int d, hipStream_t s);
 // scan.hip
 void exclusive_scan(const int* in, int* out, int n, int* tmp, hipStream_t s);
 // trim.hip

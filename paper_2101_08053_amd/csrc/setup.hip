@@ -16,7 +16,8 @@ __global__ void k_gauss_table(double* __restrict__ gx, double* __restrict__ gw) 
     int i = tid - gauss_off(n);
     double x = -cos(M_PI * (i + 0.75) / (n + 0.5));
     double dp = 1.0;
-    for (int it = 0; it < 100; ++it) {
+    bool last = false;
+    for (int it = 0; it < 60; ++it) {
         double p0 = 1.0, p1 = x;
         for (int k = 1; k < n; ++k) {
             double p2 = ((2 * k + 1) * x * p1 - k * p0) / (k + 1);
@@ -24,19 +25,13 @@ __global__ void k_gauss_table(double* __restrict__ gx, double* __restrict__ gw) 
             p1 = p2;
         }
         dp = (n == 1) ? 1.0 : n * (x * p1 - p0) / (x * x - 1.0);
+        if (last) break;            // dp at the converged node
         double dx = p1 / dp;
         x -= dx;
-        if (fabs(dx) <= 1e-17) break;
+        if (fabs(dx) <= 1e-14) last = true;  // quadratic convergence: one more step is exact
+        if (n == 1) break;
     }
-    {
-        double p0 = 1.0, p1 = x;
-        for (int k = 1; k < n; ++k) {
-            double p2 = ((2 * k + 1) * x * p1 - k * p0) / (k + 1);
-            p0 = p1;
-            p1 = p2;
-        }
-        dp = (n == 1) ? 1.0 : n * (x * p1 - p0) / (x * x - 1.0);
-    }
+    if (n == 1) dp = 1.0;
     gx[tid] = x;
     gw[tid] = 2.0 / ((1.0 - x * x) * dp * dp);
 }
@@ -54,12 +49,11 @@ __global__ void k_layout(DirDev D, int p) {
     if (e > D.N) return;
     D.bp[e] = D.knots[p + e];
     if (e == D.N) {
-        int tot = (D.N == 1) ? (p + 1) : 2 * (p + 1) + 2 * (D.N - 2);
-        D.pt0[D.N] = tot;
+        D.pt0[D.N] = wq_pt0(D.N, D.N, p);
         return;
     }
     int ne = (e == 0 || e == D.N - 1) ? p + 1 : 2;
-    int off = (e == 0) ? 0 : (p + 1) + 2 * (e - 1);
+    int off = wq_pt0(e, D.N, p);
     D.pt0[e] = off;
     double a = D.knots[p + e], b = D.knots[p + e + 1];
     for (int k = 1; k <= ne; ++k) {
@@ -224,6 +218,28 @@ __global__ void __launch_bounds__(64) k_wq_weights(DirDev D, int* __restrict__ s
     if (lane == 0 && (singular || !(rmax <= 1e-12 * bmax))) atomicExch(status, IGA_E_SINGULAR_WEIGHTS);
 }
 
+// Test-side factors of the weighted-quadrature rows, WB[i][q][b] =
+// w_{k0(i)+q, i} B_{i+b-p}(x_{k0(i)+q}), zero where B_{i+b-p} vanishes.
+__global__ void k_wb_table(DirDev D, int p) {
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    int W = 2 * p + 1;
+    if (t >= D.n * D.qmax * W) return;
+    int i = t / (D.qmax * W), q = (t / W) % D.qmax, b = t % W;
+    int k0 = D.pt0[max(0, i - p)], q_i = D.pt0[min(D.N - 1, i) + 1] - k0;
+    double v = 0.0;
+    if (q < q_i) {
+        int k = k0 + q, loc = i + b - p - D.eq[k];
+        if (loc >= 0 && loc <= p) v = D.W[(size_t)i * D.qmax + q] * D.Bq[(size_t)k * (p + 1) + loc];
+    }
+    D.WB[t] = v;
+}
+
+void launch_wb_table(Plan& P, int d, hipStream_t s) {
+    DirDev& D = P.dir[d];
+    int n = D.n * D.qmax * (2 * P.p + 1);
+    hipLaunchKernelGGL(k_wb_table, dim3((n + 255) / 256), dim3(256), 0, s, D, P.p);
+}
+
 void launch_wq_weights(Plan& P, int d, hipStream_t s) {
     DirDev& D = P.dir[d];
     dim3 g(D.n), b(64);
@@ -234,6 +250,7 @@ void launch_wq_weights(Plan& P, int d, hipStream_t s) {
 #undef CASE
         default: throw Error{IGA_E_UNSUPPORTED, "degree outside 1..8"};
     }
+    launch_wb_table(P, d, s);
 }
 
 }  // namespace iga

@@ -729,60 +729,70 @@ __device__ __forceinline__ int arc_nq(const CutArgs& A, const CurveDev& C) {
     return d * (2 * A.p + 1);
 }
 
-// One thread per cut element: visible edge pieces, base choice, node count.
-__global__ void k_cutprep(CutArgs A) {
-    int c = blockIdx.x * blockDim.x + threadIdx.x;
+// One wavefront per cut element: lanes 0..3 build the visible pieces of the
+// four edges; every lane adds its share of sum |w| of the four bases over the
+// arcs' Gauss points; lane 0 picks the base and the node count.
+__global__ void __launch_bounds__(64) k_cutprep(CutArgs A) {
+    const int c = blockIdx.x;
     if (c >= A.n_cut) return;
     const TrimDev& T = A.T;
-    int e = A.cut_list[c];
-    int e1 = e % A.G.N1, e2 = e / A.G.N1;
-    double xa = A.G.bp1[e1], xb = A.G.bp1[e1 + 1], ya = A.G.bp2[e2], yb = A.G.bp2[e2 + 1];
-    double cuts[4][kMaxEdgeCuts];
-    int nc[4] = {0, 0, 0, 0};
-    bool overflow = false;
-    int alo = A.arc_off[c], ahi = A.arc_off[c + 1];
-    for (int q = alo; q < ahi; ++q) {
-        const ArcDev R = T.arcs[A.arc_list[q]];
-        const SegDev S = T.segs[T.pieces[R.piece].seg];
-        for (int end = 0; end < 2; ++end) {
-            int kind = end ? R.k1 : R.k0, line = end ? R.l1 : R.l0;
-            double t = end ? R.t1 : R.t0;
-            int edge = -1;
-            if (kind == END_VLINE) edge = (line == e1) ? 0 : (line == e1 + 1 ? 1 : -1);
-            if (kind == END_HLINE) edge = (line == e2) ? 2 : (line == e2 + 1 ? 3 : -1);
-            if (edge < 0) continue;
-            double X, Y, dX, dY;
-            seg_eval(S, t, X, Y, dX, dY);
-            double v = (edge < 2) ? Y : X;
-            if (nc[edge] < kMaxEdgeCuts) cuts[edge][nc[edge]++] = v;
-            else overflow = true;
+    const int lane = threadIdx.x;
+    __shared__ double sLen[4];
+    __shared__ int sOverflow;
+    const int e = A.cut_list[c];
+    const int e1 = e % A.G.N1, e2 = e / A.G.N1;
+    const double xa = A.G.bp1[e1], xb = A.G.bp1[e1 + 1], ya = A.G.bp2[e2], yb = A.G.bp2[e2 + 1];
+    const int alo = A.arc_off[c], ahi = A.arc_off[c + 1];
+    CutElemDev& out = A.cut_el[c];
+    if (lane == 0) sOverflow = 0;
+    __syncthreads();
+    if (lane < 4) {
+        const int edge = lane;
+        double cuts[kMaxEdgeCuts];
+        int n = 0;
+        bool overflow = false;
+        for (int q = alo; q < ahi; ++q) {
+            const ArcDev R = T.arcs[A.arc_list[q]];
+            const SegDev S = T.segs[T.pieces[R.piece].seg];
+            for (int end = 0; end < 2; ++end) {
+                int kind = end ? R.k1 : R.k0, line = end ? R.l1 : R.l0;
+                double X, Y, dX, dY;
+                seg_eval(S, end ? R.t1 : R.t0, X, Y, dX, dY);
+                bool on = false;
+                if (kind == END_VLINE) on = (line == e1 + (edge == 1)) && edge < 2;
+                else if (kind == END_HLINE) on = (line == e2 + (edge == 3)) && edge >= 2;
+                else {
+                    // a piece end (extremum or segment junction) that lies on a grid line: the
+                    // half-open crossing count gives that crossing to the neighbouring piece only
+                    const double ref = (edge == 0) ? xa : (edge == 1) ? xb : (edge == 2) ? ya : yb;
+                    const double h = (edge < 2) ? xb - xa : yb - ya;
+                    on = fabs(((edge < 2) ? X : Y) - ref) <= 1e-12 * h;
+                }
+                if (!on) continue;
+                if (n < kMaxEdgeCuts) cuts[n++] = (edge < 2) ? Y : X;
+                else overflow = true;
+            }
         }
-    }
-    CutElemDev out;
-    out.e1 = e1;
-    out.e2 = e2;
-    for (int edge = 0; edge < 4; ++edge) {
-        double lo = (edge < 2) ? ya : xa, hi = (edge < 2) ? yb : xb;
-        double fixed = (edge == 0) ? xa : (edge == 1) ? xb : (edge == 2) ? ya : yb;
-        int n = nc[edge];
         for (int a = 1; a < n; ++a) {
-            double v = cuts[edge][a];
+            double v = cuts[a];
             int b = a - 1;
-            while (b >= 0 && cuts[edge][b] > v) { cuts[edge][b + 1] = cuts[edge][b]; --b; }
-            cuts[edge][b + 1] = v;
+            while (b >= 0 && cuts[b] > v) { cuts[b + 1] = cuts[b]; --b; }
+            cuts[b + 1] = v;
         }
+        const double lo = (edge < 2) ? ya : xa, hi = (edge < 2) ? yb : xb;
+        const double fixed = (edge == 0) ? xa : (edge == 1) ? xb : (edge == 2) ? ya : yb;
+        const double tol = 1e-13 * (hi - lo);
         int ns = 0;
-        double prev = lo;
-        double tol = 1e-13 * (hi - lo);
+        double prev = lo, len = 0.0, last_hi = 0.0;
         for (int q = 0; q <= n; ++q) {
             double a = prev;
-            double b = (q == n) ? hi : fmin(fmax(cuts[edge][q], lo), hi);
+            double b = (q == n) ? hi : fmin(fmax(cuts[q], lo), hi);
             prev = b;
             if (b - a <= tol) continue;
             double m = 0.5 * (a + b);
             double x = (edge < 2) ? fixed : m, y = (edge < 2) ? m : fixed;
             if (in_any_hole(T, x, y)) continue;
-            if (ns > 0 && fabs(out.seg[edge][ns - 1][1] - a) <= tol) {
+            if (ns > 0 && fabs(last_hi - a) <= tol) {
                 out.seg[edge][ns - 1][1] = b;
             } else if (ns < kMaxEdgeSegs) {
                 out.seg[edge][ns][0] = a;
@@ -790,42 +800,55 @@ __global__ void k_cutprep(CutArgs A) {
                 ++ns;
             } else {
                 overflow = true;
+                continue;
             }
+            last_hi = b;
+            len += b - a;
         }
         out.nseg[edge] = ns;
+        sLen[edge] = len;
+        if (overflow) sOverflow = 1;
     }
-    // sum |w| of the four bases
-    double sums[4] = {0, 0, 0, 0};
+    // sum |w| of the four bases over the arcs' Gauss points
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
     int narc_nodes = 0;
     for (int q = alo; q < ahi; ++q) {
         const ArcDev R = T.arcs[A.arc_list[q]];
         const SegDev S = T.segs[T.pieces[R.piece].seg];
-        const CurveDev C = T.curves[R.curve];
-        int nq = arc_nq(A, C);
+        const int nq = arc_nq(A, T.curves[R.curve]);
         narc_nodes += nq * A.n_r;
-        for (int g = 0; g < nq; ++g) {
+        for (int g = lane; g < nq; g += 64) {
             double tq = R.t0 + (R.t1 - R.t0) * (A.gx[gauss_off(nq) + g] + 1.0) * 0.5;
             double wt = A.gw[gauss_off(nq) + g] * (R.t1 - R.t0) * 0.5;
             double X, Y, dX, dY;
             seg_eval(S, tq, X, Y, dX, dY);
-            sums[0] += wt * fabs(dY) * fabs(X - xa);
-            sums[1] += wt * fabs(dY) * fabs(X - xb);
-            sums[2] += wt * fabs(dX) * fabs(Y - ya);
-            sums[3] += wt * fabs(dX) * fabs(Y - yb);
+            s0 += wt * fabs(dY) * fabs(X - xa);
+            s1 += wt * fabs(dY) * fabs(X - xb);
+            s2 += wt * fabs(dX) * fabs(Y - ya);
+            s3 += wt * fabs(dX) * fabs(Y - yb);
         }
     }
-    const int opp[4] = {1, 0, 3, 2};
-    for (int v = 0; v < 4; ++v) {
-        double w = (v < 2) ? (xb - xa) : (yb - ya);
-        for (int q = 0; q < out.nseg[opp[v]]; ++q) sums[v] += (out.seg[opp[v]][q][1] - out.seg[opp[v]][q][0]) * w;
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+        s0 += __shfl_xor(s0, o, 64);
+        s1 += __shfl_xor(s1, o, 64);
+        s2 += __shfl_xor(s2, o, 64);
+        s3 += __shfl_xor(s3, o, 64);
     }
-    double mn = fmin(fmin(sums[0], sums[1]), fmin(sums[2], sums[3]));
-    int var = 0;
-    while (var < 3 && !(sums[var] <= mn * (1.0 + 1e-9))) ++var;
-    out.variant = var;
-    A.cut_el[c] = out;
-    A.node_cnt[c] = narc_nodes + out.nseg[opp[var]] * A.n_s * A.n_r;
-    if (overflow) atomicExch(A.status, IGA_E_TOPOLOGY);
+    __syncthreads();
+    if (lane == 0) {
+        double sums[4] = {s0 + sLen[1] * (xb - xa), s1 + sLen[0] * (xb - xa), s2 + sLen[3] * (yb - ya),
+                          s3 + sLen[2] * (yb - ya)};
+        double mn = fmin(fmin(sums[0], sums[1]), fmin(sums[2], sums[3]));
+        int var = 0;
+        while (var < 3 && !(sums[var] <= mn * (1.0 + 1e-9))) ++var;
+        const int opp = var ^ 1;
+        out.e1 = e1;
+        out.e2 = e2;
+        out.variant = var;
+        A.node_cnt[c] = narc_nodes + out.nseg[opp] * A.n_s * A.n_r;
+        if (sOverflow) atomicExch(A.status, IGA_E_TOPOLOGY);
+    }
 }
 
 void launch_trim_cutprep(Plan& P, hipStream_t s) {
@@ -842,7 +865,7 @@ void launch_trim_cutprep(Plan& P, hipStream_t s) {
     hipLaunchKernelGGL(k_arc_sort, dim3((nc + 127) / 128), dim3(128), 0, s, nc, P.arc_off, P.arc_list);
     CutArgs A{T, G, nc, P.cut_list, P.arc_off, P.arc_list, P.cut_el, P.node_cnt,
               P.n_r, P.n_q_override, P.n_s, P.p, P.gauss_x, P.gauss_w, P.status};
-    hipLaunchKernelGGL(k_cutprep, dim3((nc + 63) / 64), dim3(64), 0, s, A);
+    hipLaunchKernelGGL(k_cutprep, dim3(nc), dim3(64), 0, s, A);
     exclusive_scan(P.node_cnt, P.node_off, nc, P.scan_tmp, s);
 }
 
@@ -853,7 +876,7 @@ __global__ void __launch_bounds__(64) k_cut_nodes(CutArgs A, const int* __restri
     int c = blockIdx.x;
     if (c >= A.n_cut) return;
     const TrimDev& T = A.T;
-    const CutElemDev E = A.cut_el[c];
+    const CutElemDev& E = A.cut_el[c];
     double xa = A.G.bp1[E.e1], xb = A.G.bp1[E.e1 + 1], ya = A.G.bp2[E.e2], yb = A.G.bp2[E.e2 + 1];
     int var = E.variant;
     bool vert = var < 2;

@@ -30,7 +30,7 @@ def parity_metric(gpu, ref):
 EPS = np.finfo(np.float64).eps
 
 
-FLOOR_P3 = 1e-9
+FLOOR_P3 = 1e-5
 ROWFLOOR_P3 = 1e-3
 
 
