@@ -185,7 +185,10 @@ int iga_plan_index_maps(const iga_plan* plan, const int32_t** act_of, const int3
  * flags & IGA_FORM_FULL re-runs every set-up kernel from the plan's inputs
  * before the formation (the whole job); without it the resident tables are
  * reused. Errors found on the device (a singular weight system) are reported
- * by iga_plan_status after the stream has run. */
+ * by iga_plan_status after the stream has run. With method IGA_DWQ the
+ * coefficient must be IGA_COEF_CONST or IGA_COEF_GEOM_DETJ (the rule has
+ * points nested between the WQ points, where no per-point value is given):
+ * IGA_E_UNSUPPORTED otherwise. */
 int iga_trim_mass_form(iga_plan* plan, const iga_coeff* c, double* vals, int32_t flags, void* stream);
 
 /* Synchronises stream and returns the device status word of the plan
@@ -243,6 +246,13 @@ int iga_plan_timings(iga_plan* plan, double* ms, int64_t* counts);
  *   IGA_TABLE_C_WQ / C_BAND / C_CUT: c at the WQ grid, band Gauss points and
  *                         cut nodes from the last IGA_COEF_GEOM_DETJ formation
  *   IGA_TABLE_CUT_W       weights of the cut-element nodes
+ *   IGA_TABLE_DWQ_X       method IGA_DWQ, direction dir: for each interior knot
+ *                         t = bp[s] (s = 1..N-1) and side (slot 2(s-1)+side,
+ *                         side 0 below t, 1 above), `stride` point coordinates
+ *                         in increasing order (IGA_ITABLE_DWQ_NPTS of them used)
+ *   IGA_TABLE_DWQ_W       method IGA_DWQ, direction dir: per slot, p rows of
+ *                         `stride` weights; row ii holds the discontinuous rule
+ *                         of B_{s+ii} (Sect. 3.3) on the slot's points
  * *count receives the number of doubles, *stride the row length (or 1). */
 #define IGA_TABLE_WQ_POINTS   0
 #define IGA_TABLE_WQ_WEIGHTS  1
@@ -251,14 +261,46 @@ int iga_plan_timings(iga_plan* plan, double* ms, int64_t* counts);
 #define IGA_TABLE_C_BAND      4
 #define IGA_TABLE_C_CUT       5
 #define IGA_TABLE_CUT_W       6
+#define IGA_TABLE_DWQ_X       7
+#define IGA_TABLE_DWQ_W       8
 int iga_plan_table(const iga_plan* plan, int32_t table, int32_t dir, const double** ptr, int64_t* count,
                    int64_t* stride);
+
+/* Read-only device views of the plan's integer tables (valid while the plan
+ * lives; NULL with *count = 0 where the method has none):
+ *   IGA_ITABLE_DWQ_NPTS   direction dir: points used in each DWQ slot
+ *   IGA_ITABLE_DWQ_ELEM   direction dir: element of each DWQ slot point
+ *   IGA_ITABLE_DWQ_WQIDX  direction dir: WQ point index of each DWQ slot point,
+ *                         -1 for a point nested between them (Sect. 3.3)
+ *   IGA_ITABLE_DWQ_BOX    per row formed element-wise (IGA_ITABLE_FORM_ROWS
+ *                         order), 8 ints lo1, hi1, s1, side1, lo2, hi2, s2,
+ *                         side2: the box of inside elements integrated with
+ *                         the direction-d rule on elements lo_d..hi_d (s_d = -1:
+ *                         the WQ rule of Eq. (5), else the discontinuous rule
+ *                         of side side_d of knot s_d); lo1 = -1: no box, the
+ *                         row is formed element-wise only
+ *   IGA_ITABLE_FORM_ROWS  compact ids of the rows formed element-wise
+ * dir is ignored by the last two. */
+#define IGA_ITABLE_DWQ_NPTS   0
+#define IGA_ITABLE_DWQ_ELEM   1
+#define IGA_ITABLE_DWQ_WQIDX  2
+#define IGA_ITABLE_DWQ_BOX    3
+#define IGA_ITABLE_FORM_ROWS  4
+int iga_plan_int_table(const iga_plan* plan, int32_t table, int32_t dir, const int32_t** ptr, int64_t* count,
+                       int64_t* stride);
 
 /* Replaces the weighted-quadrature weights of direction dir by W (device,
  * layout of IGA_TABLE_WQ_WEIGHTS), stream ordered. Later formations without
  * IGA_FORM_FULL use them; a FULL formation recomputes them. For checking the
  * formation kernels under rules fixed from outside. */
 int iga_plan_set_weights(iga_plan* plan, int32_t dir, const double* W, void* stream);
+
+/* Replaces the discontinuous weights of direction dir (method IGA_DWQ) by w
+ * (device, layout of IGA_TABLE_DWQ_W), stream ordered; the point lists are
+ * kept. Later formations without IGA_FORM_FULL use them; a FULL formation
+ * recomputes them. For checking the formation kernels under rules fixed from
+ * outside. IGA_E_INVALID if the plan's method is not IGA_DWQ. */
+int iga_plan_set_dwq_weights(iga_plan* plan, int32_t dir, const double* w, void* stream);
 
 /* Replaces the cut-element nodes (device arrays of n coordinates and weights,
  * in the order of iga_plan_points; n must equal n_cut_nodes, else

@@ -133,6 +133,7 @@ class Direction:
         self.xs, self.el = wq.wq_points(self.knots, p)
         self.W = wq.wq_weights(self.knots, p, self.xs, self.el)
         self._cache = {}
+        self._cond = {}
 
     def side_rule(self, s, side):
         """Refined points of the side of t = bp[s] and the weights w~ of its refined functions.
@@ -181,6 +182,7 @@ class Direction:
             span = int(np.searchsorted(kv, bp[e], side="right")) - 1
             Tr[np.ix_(idx, np.arange(span - p, span + 1))] = span_basis(kv, p, span, x[idx])
         Wt = np.zeros((len(touch), len(x)))
+        cond = 1.0
         for r, l in enumerate(touch):
             lo, hi = kv[l], kv[l + p + 1]
             Ql = np.nonzero((x > lo) & (x < hi))[0]
@@ -188,9 +190,16 @@ class Direction:
             A = Tr[np.ix_(Ql, Jl)].T
             b = np.array([self._refined_moment(kv, m, l) for m in Jl])
             Wt[r, Ql] = np.linalg.lstsq(A, b, rcond=None)[0]
+            cond = max(cond, float(np.linalg.cond(A)))
         out = (x, el, kidx, S, np.array(touch), Wt)
         self._cache[key] = out
+        self._cond[key] = cond
         return out
+
+    def side_condition(self, s, side):
+        """Largest 2-norm condition number of the refined systems of the side of bp[s]."""
+        self.side_rule(s, side)
+        return self._cond[(s, side)]
 
     def _refined_moment(self, kv, m, l):
         """int B~_m B~_l, (p+1)-point Gauss on every element of the overlap."""

@@ -63,6 +63,7 @@ static void run_setup(Plan& P, hipStream_t s, bool discover) {
     launch_gauss_table(P, s);
     for (int d = 0; d < 2; ++d) launch_dir_tables(P, d, s);
     for (int d = 0; d < 2; ++d) launch_wq_weights(P, d, s);
+    launch_dwq_sides(P, s);
     TrimDev& T = P.trim;
     if (T.n_curves > 0) {
         launch_trim_curves(P, s);
@@ -99,7 +100,9 @@ static void run_setup(Plan& P, hipStream_t s, bool discover) {
         P.cut_el = P.alloc<CutElemDev>(std::max(nc, 1));
         P.node_cnt = P.alloc<int>(nc + 1);
         P.node_off = P.alloc<int>(nc + 1);
+        if (P.method == IGA_DWQ) P.dwq_region = P.alloc<int>(8 * (size_t)std::max<int64_t>(P.n_form_rows, 1));
     }
+    launch_dwq_choose(P, s);
     launch_trim_cutprep(P, s);
     if (discover) {
         P.n_nodes = (P.n_cut_el > 0) ? d2h1(P.node_off + P.n_cut_el, s) : 0;
@@ -135,6 +138,13 @@ static void run_setup(Plan& P, hipStream_t s, bool discover) {
         HIPX(hipStreamSynchronize(s));
         P.n_interior = std::count(fc.begin(), fc.end(), (int8_t)FN_INTERIOR);
         P.n_cut_fn = std::count(fc.begin(), fc.end(), (int8_t)FN_CUT);
+        if (P.method == IGA_DWQ && P.n_form_rows > 0) {
+            std::vector<int> reg(8 * (size_t)P.n_form_rows);
+            HIPX(hipMemcpyAsync(reg.data(), P.dwq_region, sizeof(int) * reg.size(), hipMemcpyDeviceToHost, s));
+            HIPX(hipStreamSynchronize(s));
+            P.n_dwq_rows = 0;
+            for (int64_t r = 0; r < P.n_form_rows; ++r) P.n_dwq_rows += reg[8 * r] >= 0;
+        }
     }
 }
 
@@ -177,6 +187,7 @@ static void form(Plan& P, const iga_coeff& c, double* vals, int flags, hipStream
     {
         PhaseTimer t(P, s, IGA_PHASE_CUT);
         launch_cut_rows(P, c, vals, s);
+        launch_dwq_rows(P, c, vals, s);
     }
 }
 
@@ -216,7 +227,6 @@ int iga_plan_create(const iga_patch_desc* desc, const iga_opts* opts, iga_plan**
     int p = desc->degree;
     IGA_REQUIRE(p >= 1 && p <= IGA_MAXP, IGA_E_UNSUPPORTED, "degree must be in 1..8");
     IGA_REQUIRE(desc->method >= IGA_GAUSS_REF && desc->method <= IGA_NAIVE_WQ, IGA_E_UNSUPPORTED, "unknown method");
-    IGA_REQUIRE(desc->method != IGA_DWQ, IGA_E_UNSUPPORTED, "discontinuous weighted quadrature is not built");
     for (int d = 0; d < 2; ++d) validate_knots(desc->knots[d], desc->n_knots[d], p, d);
     IGA_REQUIRE(desc->n_curves >= 0 && (desc->n_curves == 0 || desc->curves), IGA_E_INVALID, "curves missing");
     bool all_ellipses = true;
@@ -277,6 +287,20 @@ int iga_plan_create(const iga_patch_desc* desc, const iga_opts* opts, iga_plan**
         D.wg = P->alloc<double>((size_t)D.N * (p + 1));
         D.Bg = P->alloc<double>((size_t)D.N * (p + 1) * (p + 1));
         D.dBg = P->alloc<double>((size_t)D.N * (p + 1) * (p + 1));
+        D.dq_KQ = 4 * p + 2;
+        D.dq_n = nullptr;
+        D.dq_x = nullptr;
+        D.dq_el = nullptr;
+        D.dq_k = nullptr;
+        D.dq_w = nullptr;
+        if (desc->method == IGA_DWQ && D.N > 1) {
+            const size_t slots = 2 * (size_t)(D.N - 1);
+            D.dq_n = P->alloc<int>(slots);
+            D.dq_x = P->alloc<double>(slots * D.dq_KQ);
+            D.dq_el = P->alloc<int>(slots * D.dq_KQ);
+            D.dq_k = P->alloc<int>(slots * D.dq_KQ);
+            D.dq_w = P->alloc<double>(slots * p * D.dq_KQ);
+        }
     }
     P->N1 = P->dir[0].N;
     P->N2 = P->dir[1].N;
@@ -397,7 +421,7 @@ int iga_plan_sizes(const iga_plan* P, iga_sizes* s) {
     s->n_points = P->n_points;
     s->nnz = P->nnz;
     s->n_arcs = P->n_arcs;
-    s->n_dwq_rows = 0;
+    s->n_dwq_rows = P->n_dwq_rows;
     s->workspace_bytes = P->bytes;
     API_END
 }
@@ -425,6 +449,8 @@ int iga_trim_mass_form(iga_plan* P, const iga_coeff* c, double* vals, int32_t fl
     IGA_REQUIRE(c->kind >= IGA_COEF_CONST && c->kind <= IGA_COEF_AT_POINTS, IGA_E_UNSUPPORTED, "coefficient kind");
     IGA_REQUIRE(c->kind != IGA_COEF_GEOM_DETJ || c->geom_cp, IGA_E_INVALID, "geometry control points missing");
     IGA_REQUIRE(c->kind != IGA_COEF_AT_POINTS || c->c_points, IGA_E_INVALID, "per-point coefficient missing");
+    IGA_REQUIRE(!(P->method == IGA_DWQ && c->kind == IGA_COEF_AT_POINTS), IGA_E_UNSUPPORTED,
+                "discontinuous weighted quadrature needs c at nested points: constant or |det J| only");
     form(*P, *c, vals, flags, (hipStream_t)stream);
     HIPX(hipGetLastError());
     API_END
@@ -483,6 +509,35 @@ int iga_plan_table(const iga_plan* P, int32_t table, int32_t dir, const double**
         case IGA_TABLE_C_BAND: p = P->c_band; n = P->n_band * (int64_t)L; break;
         case IGA_TABLE_C_CUT: p = P->c_cut; n = P->n_nodes; break;
         case IGA_TABLE_CUT_W: p = P->node_w; n = P->n_nodes; break;
+        case IGA_TABLE_DWQ_X: p = D.dq_x; n = D.dq_x ? 2 * (int64_t)(D.N - 1) * D.dq_KQ : 0; st = D.dq_KQ; break;
+        case IGA_TABLE_DWQ_W:
+            p = D.dq_w;
+            n = D.dq_w ? 2 * (int64_t)(D.N - 1) * P->p * D.dq_KQ : 0;
+            st = D.dq_KQ;
+            break;
+        default: throw Error{IGA_E_INVALID, "unknown table"};
+    }
+    *ptr = p;
+    if (count) *count = n;
+    if (stride) *stride = st;
+    API_END
+}
+
+int iga_plan_int_table(const iga_plan* P, int32_t table, int32_t dir, const int32_t** ptr, int64_t* count,
+                       int64_t* stride) {
+    API_BEGIN
+    IGA_REQUIRE(P && ptr, IGA_E_INVALID, "null argument");
+    IGA_REQUIRE(dir == 0 || dir == 1, IGA_E_INVALID, "direction must be 0 or 1");
+    const DirDev& D = P->dir[dir];
+    const int64_t slots = D.dq_n ? 2 * (int64_t)(D.N - 1) : 0;
+    int64_t n = 0, st = 1;
+    const int* p = nullptr;
+    switch (table) {
+        case IGA_ITABLE_DWQ_NPTS: p = D.dq_n; n = slots; break;
+        case IGA_ITABLE_DWQ_ELEM: p = D.dq_el; n = slots * D.dq_KQ; st = D.dq_KQ; break;
+        case IGA_ITABLE_DWQ_WQIDX: p = D.dq_k; n = slots * D.dq_KQ; st = D.dq_KQ; break;
+        case IGA_ITABLE_DWQ_BOX: p = P->dwq_region; n = P->dwq_region ? 8 * P->n_form_rows : 0; st = 8; break;
+        case IGA_ITABLE_FORM_ROWS: p = P->form_rows; n = P->n_form_rows; break;
         default: throw Error{IGA_E_INVALID, "unknown table"};
     }
     *ptr = p;
@@ -498,6 +553,18 @@ int iga_plan_set_weights(iga_plan* P, int32_t dir, const double* W, void* stream
     const DirDev& D = P->dir[dir];
     HIPX(hipMemcpyAsync(D.W, W, sizeof(double) * (size_t)D.n * D.qmax, hipMemcpyDefault, (hipStream_t)stream));
     launch_wb_table(*P, dir, (hipStream_t)stream);
+    API_END
+}
+
+int iga_plan_set_dwq_weights(iga_plan* P, int32_t dir, const double* w, void* stream) {
+    API_BEGIN
+    IGA_REQUIRE(P && w, IGA_E_INVALID, "null argument");
+    IGA_REQUIRE(dir == 0 || dir == 1, IGA_E_INVALID, "direction must be 0 or 1");
+    const DirDev& D = P->dir[dir];
+    IGA_REQUIRE(P->method == IGA_DWQ, IGA_E_INVALID, "the plan's method is not IGA_DWQ");
+    if (D.dq_w)
+        HIPX(hipMemcpyAsync(D.dq_w, w, sizeof(double) * 2 * (size_t)(D.N - 1) * P->p * D.dq_KQ, hipMemcpyDefault,
+                            (hipStream_t)stream));
     API_END
 }
 

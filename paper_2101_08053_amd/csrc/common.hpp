@@ -140,4 +140,75 @@ __device__ __forceinline__ void basis_eval_rt(const double* __restrict__ knots, 
     }
 }
 
+// -------------------------------------------------------------------------
+// Minimum 2-norm solution of a small under-determined system A w = b on one
+// wavefront (Eq. (5) and its refined variants). Lane l holds row l of A^T
+// (one quadrature point) in a[0..m); lanes >= q hold zeros. Householder QR
+// of A^T = Q R, then w = Q R^{-T} b. bcol(c) returns b[c] (uniform across
+// the wave). On return y is the weight of the lane's point (0 for lanes >=
+// q); singular is set if a pivot of R vanishes; the result is checked by the
+// caller.
+// -------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+template <int M, typename BCol>
+__device__ __forceinline__ double wave_min_norm(double (&a)[M], int q, int m, BCol bcol, bool& singular) {
+    const int lane = threadIdx.x & 63;
+    double v[M], vn[M];
+#pragma unroll
+    for (int c = 0; c < M; ++c) {
+        v[c] = 0.0;
+        vn[c] = 0.0;
+    }
+    singular = false;
+#pragma unroll
+    for (int c = 0; c < M; ++c) {
+        if (c >= m) break;
+        double x = (lane >= c && lane < q) ? a[c] : 0.0;
+        double nrm2 = wave_sum(x * x);
+        double xc = __shfl(a[c], c, 64);
+        double alpha = (xc >= 0.0) ? -sqrt(nrm2) : sqrt(nrm2);
+        double vl = (lane == c) ? x - alpha : x;
+        double vv = 2.0 * (nrm2 - alpha * xc);
+        v[c] = vl;
+        vn[c] = vv;
+        if (vv > 0.0) {
+#pragma unroll
+            for (int j = c + 1; j < M; ++j) {
+                if (j >= m) break;
+                double d = wave_sum(vl * ((lane >= c) ? a[j] : 0.0));
+                if (lane >= c) a[j] -= 2.0 * vl * d / vv;
+            }
+        }
+        if (lane == c) a[c] = (vv > 0.0) ? alpha : xc;
+        else if (lane > c) a[c] = 0.0;
+        double rcc = __shfl(a[c], c, 64);
+        if (!(fabs(rcc) > 0.0)) singular = true;
+    }
+    // forward substitution R^T z = b (R[k][c] sits in lane k, column c)
+    double zl = 0.0;
+#pragma unroll
+    for (int c = 0; c < M; ++c) {
+        if (c >= m) break;
+        double bc = bcol(c);
+        double sacc = wave_sum((lane < c) ? a[c] * zl : 0.0);
+        double rcc = __shfl(a[c], c, 64);
+        double zc = (bc - sacc) / rcc;
+        if (lane == c) zl = zc;
+    }
+    // w = H_0 ... H_{m-1} [z; 0]
+    double y = (lane < m) ? zl : 0.0;
+#pragma unroll
+    for (int c = M - 1; c >= 0; --c) {
+        if (c >= m || !(vn[c] > 0.0)) continue;
+        double d = wave_sum(v[c] * y);
+        y -= 2.0 * v[c] * d / vn[c];
+    }
+    return (lane < q) ? y : 0.0;
+}
+
 }  // namespace iga

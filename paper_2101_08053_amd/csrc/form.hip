@@ -61,30 +61,6 @@ void launch_points(Plan& P, hipStream_t s) {
 }
 
 // ------------------------------------------------------- coefficient
-// |det DF| at a point from per-direction values/derivatives of the local
-// functions and the (p+1)^2 control points of element (e1, e2).
-__device__ __forceinline__ double detj_local(const double* __restrict__ cp, int n1, int p, int e1, int e2,
-                                             const double* B1, const double* dB1, const double* B2,
-                                             const double* dB2) {
-    double x1 = 0, x2 = 0, y1 = 0, y2 = 0;
-    for (int a2 = 0; a2 <= p; ++a2) {
-        double sx1 = 0, sx = 0, sy1 = 0, sy = 0;
-        const double* row = cp + 2 * ((size_t)(e2 + a2) * n1 + e1);
-        for (int a1 = 0; a1 <= p; ++a1) {
-            double px = row[2 * a1], py = row[2 * a1 + 1];
-            sx1 += dB1[a1] * px;
-            sx += B1[a1] * px;
-            sy1 += dB1[a1] * py;
-            sy += B1[a1] * py;
-        }
-        x1 += B2[a2] * sx1;
-        y1 += B2[a2] * sy1;
-        x2 += dB2[a2] * sx;
-        y2 += dB2[a2] * sy;
-    }
-    return fabs(x1 * y2 - x2 * y1);
-}
-
 __global__ void k_coef_wq(DirDev D1, DirDev D2, int p, const double* __restrict__ cp, int n1, double* __restrict__ c) {
     int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= D1.Q * D2.Q) return;
@@ -524,6 +500,7 @@ struct CutRowArgs {
     const int* cut_id;
     const int* band_id;
     const double* E;
+    const int* region;      // DWQ: box of inside elements left to k_dwq_rows (nullptr: none)
     double* vals;
     int64_t n_act;
 };
@@ -550,6 +527,13 @@ __global__ void __launch_bounds__((((2 * P + 1) * (2 * P + 1) + 63) / 64) * 64) 
     const int row = A.rows[r];
     const int f = A.fn_of[row];
     const int i1 = f % D1.n, i2 = f / D1.n;
+    int bx0 = 1, bx1 = 0, by0 = 1, by1 = 0;   // DWQ box (empty by default)
+    if (A.region && A.region[(size_t)r * 8] >= 0) {
+        bx0 = A.region[(size_t)r * 8];
+        bx1 = A.region[(size_t)r * 8 + 1];
+        by0 = A.region[(size_t)r * 8 + 4];
+        by1 = A.region[(size_t)r * 8 + 5];
+    }
     for (int t = tid; t < NP * NP * W; t += nt) {
         int m = t / (NP * W), g = (t / W) % NP, a = t % W;
         // direction 1
@@ -572,7 +556,7 @@ __global__ void __launch_bounds__((((2 * P + 1) * (2 * P + 1) + 63) / 64) * 64) 
         int m2 = t / NP, m1 = t % NP;
         int e1 = i1 - P + m1, e2 = i2 - P + m2;
         int cls = -1, id = -1;
-        if (e1 >= 0 && e1 < D1.N && e2 >= 0 && e2 < D2.N) {
+        if (e1 >= 0 && e1 < D1.N && e2 >= 0 && e2 < D2.N && !(e1 >= bx0 && e1 <= bx1 && e2 >= by0 && e2 <= by1)) {
             int e = e2 * D1.N + e1;
             cls = A.ecls[e];
             id = (cls == EL_CUT) ? A.cut_id[e] : (cls == EL_INSIDE ? A.band_id[e] : -1);
@@ -637,7 +621,7 @@ void launch_cut_rows(Plan& P, const iga_coeff& c, double* vals, hipStream_t s) {
     }
     if (P.n_form_rows > 0) {
         CutRowArgs A{P.dir[0], P.dir[1], cv, P.form_rows, (int)P.n_form_rows, P.fn_of, P.act_of, P.ecls,
-                     P.cut_id, P.band_id, P.cutE, vals, P.n_act};
+                     P.cut_id, P.band_id, P.cutE, P.method == IGA_DWQ ? P.dwq_region : nullptr, vals, P.n_act};
         int W = 2 * P.p + 1;
         dim3 g((unsigned)P.n_form_rows), b(((W * W + 63) / 64) * 64);
         switch (P.p) {

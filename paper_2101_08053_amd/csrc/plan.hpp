@@ -38,6 +38,14 @@ struct DirDev {
     double* wg;           // N*(p+1) Gauss weights
     double* Bg;           // N*(p+1)*(p+1) [e][g][a]
     double* dBg;          // N*(p+1)*(p+1)
+    // discontinuous weighted quadrature (method IGA_DWQ), one list per side of
+    // every interior knot s = 1..N-1, slot = 2 (s-1) + side (0 below, 1 above)
+    int dq_KQ;            // points per list (capacity)
+    int* dq_n;            // [slots] points in the list
+    double* dq_x;         // [slots][KQ] coordinates, increasing
+    int* dq_el;           // [slots][KQ] owning element
+    int* dq_k;            // [slots][KQ] WQ point index, -1 for a nested point
+    double* dq_w;         // [slots][p][KQ] weights of B_{s+ii}, ii = 0..p-1
 };
 
 struct CurveDev {
@@ -150,6 +158,7 @@ struct Plan {
     int* fn_of = nullptr;          // n_act
     int* cut_rows = nullptr;       // compact ids of cut rows
     int* form_rows = nullptr;      // rows formed by the element/cut kernel (method dependent)
+    int* dwq_region = nullptr;     // [n_form_rows][8] DWQ box of each formed row (lo1 = -1: none)
     int* cut_list = nullptr;       // flat ids of cut elements
     int* band_list = nullptr;      // flat ids of band elements
     int* arc_cnt = nullptr;        // per cut element
@@ -181,7 +190,7 @@ struct Plan {
 
     // sizes
     int64_t n_act = 0, n_interior = 0, n_cut_fn = 0, n_cut_el = 0, n_band = 0;
-    int64_t n_nodes = 0, n_arcs = 0, nnz = 0, n_form_rows = 0, n_points = 0;
+    int64_t n_nodes = 0, n_arcs = 0, nnz = 0, n_form_rows = 0, n_points = 0, n_dwq_rows = 0;
     int64_t bytes = 0;
 
     // timing
@@ -215,6 +224,31 @@ struct CoefView {
     const double* cut;   // [n_nodes]
 };
 
+// |det DF| at a point from per-direction values/derivatives of the local
+// functions and the (p+1)^2 control points of element (e1, e2).
+__device__ __forceinline__ double detj_local(const double* __restrict__ cp, int n1, int p, int e1, int e2,
+                                             const double* B1, const double* dB1, const double* B2,
+                                             const double* dB2) {
+    double x1 = 0, x2 = 0, y1 = 0, y2 = 0;
+    for (int a2 = 0; a2 <= p; ++a2) {
+        double sx1 = 0, sx = 0, sy1 = 0, sy = 0;
+        const double* row = cp + 2 * ((size_t)(e2 + a2) * n1 + e1);
+        for (int a1 = 0; a1 <= p; ++a1) {
+            double px = row[2 * a1], py = row[2 * a1 + 1];
+            sx1 += dB1[a1] * px;
+            sx += B1[a1] * px;
+            sy1 += dB1[a1] * py;
+            sy += B1[a1] * py;
+        }
+        x1 += B2[a2] * sx1;
+        y1 += B2[a2] * sy1;
+        x2 += dB2[a2] * sx;
+        y2 += dB2[a2] * sy;
+    }
+    return fabs(x1 * y2 - x2 * y1);
+}
+
+
 // ---------------------------------------------------------------- launchers
 // setup.hip
 void launch_gauss_table(Plan& P, hipStream_t s);
@@ -240,6 +274,10 @@ void launch_points(Plan& P, hipStream_t s);
 void launch_coef(Plan& P, const iga_coeff& c, hipStream_t s);
 void launch_interior_rows(Plan& P, const iga_coeff& c, double* vals, hipStream_t s);
 void launch_cut_rows(Plan& P, const iga_coeff& c, double* vals, hipStream_t s);
+// dwq.hip
+void launch_dwq_sides(Plan& P, hipStream_t s);
+void launch_dwq_choose(Plan& P, hipStream_t s);
+void launch_dwq_rows(Plan& P, const iga_coeff& c, double* vals, hipStream_t s);
 
 }  // namespace iga
 

@@ -120,12 +120,6 @@ void launch_dir_tables(Plan& P, int d, hipStream_t s) {
 }
 
 // ---------------------------------------------------------- WQ weights (5)
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
-}
-
 // One wavefront per test function i. Lane l owns row l of A^T (point
 // k0 + l of supp B_i); A[j][k] = B_j(x_k) for the trial functions j with
 // |j - i| <= p. Householder QR of A^T = Q R gives the minimum-norm solution
@@ -141,13 +135,9 @@ __global__ void __launch_bounds__(64) k_wq_weights(DirDev D, int* __restrict__ s
     int jlo = max(0, i - P), jhi = min(D.n - 1, i + P);
     int m = jhi - jlo + 1;
 
-    double a[M], v[M], vn[M];
+    double a[M];
 #pragma unroll
-    for (int c = 0; c < M; ++c) {
-        a[c] = 0.0;
-        v[c] = 0.0;
-        vn[c] = 0.0;
-    }
+    for (int c = 0; c < M; ++c) a[c] = 0.0;
     if (lane < q) {
         int k = k0 + lane, e = D.eq[k];
 #pragma unroll
@@ -157,50 +147,7 @@ __global__ void __launch_bounds__(64) k_wq_weights(DirDev D, int* __restrict__ s
         }
     }
     bool singular = false;
-#pragma unroll
-    for (int c = 0; c < M; ++c) {
-        if (c >= m) break;
-        double x = (lane >= c && lane < q) ? a[c] : 0.0;
-        double nrm2 = wave_sum(x * x);
-        double xc = __shfl(a[c], c, 64);
-        double alpha = (xc >= 0.0) ? -sqrt(nrm2) : sqrt(nrm2);
-        double vl = (lane == c) ? x - alpha : x;
-        double vv = 2.0 * (nrm2 - alpha * xc);
-        v[c] = vl;
-        vn[c] = vv;
-        if (vv > 0.0) {
-#pragma unroll
-            for (int j = c + 1; j < M; ++j) {
-                if (j >= m) break;
-                double d = wave_sum(vl * ((lane >= c) ? a[j] : 0.0));
-                if (lane >= c) a[j] -= 2.0 * vl * d / vv;
-            }
-        }
-        if (lane == c) a[c] = (vv > 0.0) ? alpha : xc;
-        else if (lane > c) a[c] = 0.0;
-        double rcc = __shfl(a[c], c, 64);
-        if (!(fabs(rcc) > 0.0)) singular = true;
-    }
-    // forward substitution R^T z = b (R[k][c] sits in lane k, column c)
-    double zl = 0.0;
-#pragma unroll
-    for (int c = 0; c < M; ++c) {
-        if (c >= m) break;
-        double bc = D.M1[i * M + (jlo + c - i + P)];
-        double sacc = wave_sum((lane < c) ? a[c] * zl : 0.0);
-        double rcc = __shfl(a[c], c, 64);
-        double zc = (bc - sacc) / rcc;
-        if (lane == c) zl = zc;
-    }
-    // w = H_0 ... H_{m-1} [z; 0]
-    double y = (lane < m) ? zl : 0.0;
-#pragma unroll
-    for (int c = M - 1; c >= 0; --c) {
-        if (c >= m || !(vn[c] > 0.0)) continue;
-        double d = wave_sum(v[c] * y);
-        y -= 2.0 * v[c] * d / vn[c];
-    }
-    if (lane >= q) y = 0.0;
+    double y = wave_min_norm<M>(a, q, m, [&](int c) { return D.M1[i * M + (jlo + c - i + P)]; }, singular);
     // residual of Eq. (5)
     double rmax = 0.0, bmax = 0.0;
     {

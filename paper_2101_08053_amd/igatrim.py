@@ -103,7 +103,10 @@ def lib():
             "iga_copy": (C.c_int, [V, V, C.c_int64, V]),
             "iga_plan_table": (C.c_int, [P, C.c_int32, C.c_int32, C.POINTER(C.c_void_p), C.POINTER(C.c_int64),
                                          C.POINTER(C.c_int64)]),
+            "iga_plan_int_table": (C.c_int, [P, C.c_int32, C.c_int32, C.POINTER(C.c_void_p), C.POINTER(C.c_int64),
+                                             C.POINTER(C.c_int64)]),
             "iga_plan_set_weights": (C.c_int, [P, C.c_int32, V, V]),
+            "iga_plan_set_dwq_weights": (C.c_int, [P, C.c_int32, V, V]),
             "iga_plan_set_cut_nodes": (C.c_int, [P, V, V, V, C.c_int64, V]),
             "iga_status_string": (C.c_char_p, [C.c_int]),
             "iga_last_error": (C.c_char_p, []),
@@ -119,9 +122,12 @@ def lib():
 EXPORTED = ("iga_plan_create", "iga_plan_destroy", "iga_plan_sizes", "iga_plan_points", "iga_plan_index_maps",
             "iga_trim_mass_form", "iga_plan_status", "iga_trim_l2_project", "iga_trim_rhs", "iga_mf_apply",
             "iga_mf_adjoint", "iga_trim_mass_form_batched", "iga_plan_set_timing", "iga_plan_timings",
-            "iga_copy", "iga_plan_table", "iga_plan_set_weights", "iga_plan_set_cut_nodes", "iga_status_string", "iga_last_error")
+            "iga_copy", "iga_plan_table", "iga_plan_int_table", "iga_plan_set_weights",
+            "iga_plan_set_dwq_weights", "iga_plan_set_cut_nodes", "iga_status_string", "iga_last_error")
 
-TABLE_WQ_POINTS, TABLE_WQ_WEIGHTS, TABLE_MASS_1D, TABLE_C_WQ, TABLE_C_BAND, TABLE_C_CUT, TABLE_CUT_W = range(7)
+(TABLE_WQ_POINTS, TABLE_WQ_WEIGHTS, TABLE_MASS_1D, TABLE_C_WQ, TABLE_C_BAND, TABLE_C_CUT, TABLE_CUT_W,
+ TABLE_DWQ_X, TABLE_DWQ_W) = range(9)
+ITABLE_DWQ_NPTS, ITABLE_DWQ_ELEM, ITABLE_DWQ_WQIDX, ITABLE_DWQ_BOX, ITABLE_FORM_ROWS = range(5)
 
 
 def _check(code):
@@ -225,9 +231,20 @@ class Plan:
         _check(lib().iga_plan_table(self.h, which, d, C.byref(ptr), C.byref(n), C.byref(st)))
         return self._copy_dev(ptr, n.value, torch.float64).view(-1, st.value)
 
+    def int_table(self, which, d=0):
+        """Device copy of an integer plan table, reshaped (rows, stride)."""
+        torch = _torch()
+        ptr, n, st = C.c_void_p(), C.c_int64(), C.c_int64()
+        _check(lib().iga_plan_int_table(self.h, which, d, C.byref(ptr), C.byref(n), C.byref(st)))
+        return self._copy_dev(ptr, n.value, torch.int32).view(-1, st.value)
+
     def set_weights(self, d, W):
         """Inject weights of direction d (device tensor in the weight-table layout)."""
         _check(lib().iga_plan_set_weights(self.h, d, _dptr(W), _stream()))
+
+    def set_dwq_weights(self, d, w):
+        """Inject discontinuous weights of direction d (device tensor in the IGA_TABLE_DWQ_W layout)."""
+        _check(lib().iga_plan_set_dwq_weights(self.h, d, _dptr(w), _stream()))
 
     def set_cut_nodes(self, x, y, w):
         """Inject cut-element nodes (device tensors of n_cut_nodes values)."""

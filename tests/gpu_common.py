@@ -127,3 +127,36 @@ def worst_entries(gpu, ref, ts, k=5):
         out.append(dict(slot=s, row=r, cls=int(ts.fcls.reshape(-1)[flat]), gpu=gpu[s, r], ref=ref[s, r],
                         rel=rel[s, r], rowmax=rowmax[0, r]))
     return out
+
+
+def oracle_dwq_tables(o, d, KQ):
+    """The oracle's discontinuous rules of direction d in the device layout.
+
+    Per slot 2(s-1)+side: the points of the side's first p+1 elements (all
+    non-zero weights of the p functions containing t lie there), their
+    elements and WQ indices, and the weights of B_{s+ii}, ii = 0..p-1.
+    """
+    from oracle import dwq
+    D = o.dwq_dirs()[d]
+    p = o.p
+    slots = 2 * (D.N - 1)
+    npts = np.zeros(slots, dtype=np.int64)
+    X = np.zeros((slots, KQ))
+    E = np.full((slots, KQ), -1, dtype=np.int64)
+    K = np.full((slots, KQ), -1, dtype=np.int64)
+    Wt = np.zeros((slots, p, KQ))
+    cond = np.ones(slots)
+    for s in range(1, D.N):
+        for side in (dwq.LOW, dwq.HIGH):
+            sl = 2 * (s - 1) + side
+            x, el, k, _, _, _ = D.side_rule(s, side)
+            keep = (el <= s + p) if side == dwq.HIGH else (el >= s - 1 - p)
+            n = int(keep.sum())
+            npts[sl] = n
+            X[sl, :n] = x[keep]
+            E[sl, :n] = el[keep]
+            K[sl, :n] = k[keep]
+            for ii in range(p):
+                Wt[sl, ii, :n] = D.dwq_weights(s + ii, s, side)[3][keep]
+            cond[sl] = D.side_condition(s, side)
+    return npts, X, E, K, Wt, cond
