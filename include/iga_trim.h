@@ -218,10 +218,46 @@ int iga_mf_apply(iga_plan* plan, const double* c_points, const double* u, double
 int iga_mf_adjoint(iga_plan* plan, const double* c_points, const double* u, const double* gy,
                    double* du, double* dc, void* stream);
 
-/* Batched formation: forms count plans' matrices with one launch per phase
- * over all patches (work items concatenated across patches), optionally
- * recorded once into a HIP graph and replayed on later calls with the same
- * arguments (use_graph != 0). cs and vals are arrays of count entries. */
+/* Batched formation of many patches (the batched use named in the north
+ * star; each patch's rules as in Sects. 2-3): the resident tables of count
+ * plans (set up, each plan with its own degree <= 6, method hybrid Gauss or
+ * element Gauss) are formed into vals[k] (device, band_k * n_act_k doubles)
+ * with coefficient cs[k], in ONE persistent launch (plus a counter reset):
+ * a cost-sorted work queue of coefficient chunks, cut-element matrices,
+ * interior work items and element-formed rows of all patches, taken by a
+ * fixed grid of workgroups; items that need another kind's results of their
+ * patch wait on that patch's completion counter (bounded wait).
+ *
+ * A batch object keeps the descriptors, the queue and, with use_graph != 0,
+ * a HIP graph recorded on the first such call and replayed afterwards. The
+ * plans, coefficient data and output buffers are borrowed: they must stay
+ * valid and keep their addresses while the batch lives. Calls on one batch
+ * must not overlap (they share its counters). */
+typedef struct iga_batch iga_batch;
+typedef struct iga_batch_stats {
+    int64_t n_plans;
+    int64_t n_items;      /* work items in the queue                    */
+    int64_t nnz;          /* sum of the plans' structural non-zeros     */
+    int32_t grid;         /* persistent workgroups                      */
+    int32_t wg_per_cu;    /* workgroups per compute unit (autotuned)    */
+    int32_t order;        /* 0: cost-sorted queue, 1: patch by patch    */
+    int32_t graph_ready;  /* a recorded graph is cached                 */
+} iga_batch_stats;
+int iga_batch_create(iga_plan* const* plans, int32_t count, const iga_coeff* cs, double* const* vals,
+                     iga_batch** out);
+void iga_batch_destroy(iga_batch* batch);
+/* Enqueues the batched formation on stream (graph replay with use_graph). */
+int iga_batch_form(iga_batch* batch, int32_t use_graph, void* stream);
+/* Autotuner: times the persistent grid (1..4 workgroups per compute unit)
+ * and the two queue orders on the device (3 timed runs each, stream
+ * synchronised), keeps the fastest and drops a cached graph; *best_ms
+ * (may be NULL) receives its time. */
+int iga_batch_autotune(iga_batch* batch, void* stream, float* best_ms);
+int iga_batch_info(const iga_batch* batch, iga_batch_stats* st);
+/* Synchronises stream; IGA_E_INVALID if a dependency wait hit its bound
+ * (the bound is sticky for the batch), else the first plan's device status. */
+int iga_batch_status(iga_batch* batch, void* stream);
+/* One-shot form: create a batch, form (graph if use_graph), synchronise, destroy. */
 int iga_trim_mass_form_batched(iga_plan* const* plans, int32_t count, const iga_coeff* cs,
                                double* const* vals, int32_t use_graph, void* stream);
 

@@ -1,0 +1,478 @@
+// Batched formation of many patches in one persistent launch.
+//
+// The work of every patch is cut into items of four kinds: chunks of
+// coefficient points (|det J| of each patch's geometry), cut-element local
+// matrices, interior work items (one test-function row i2 x one tile of 64
+// rows i1) and element-formed rows. Items are queued kind by kind --
+// coefficients first, then cut elements, then interior and element-formed
+// rows together -- and by decreasing cost inside a kind, one queue per
+// degree. A fixed grid of workgroups, split over the degrees in proportion
+// to their work, takes items from its degree's queue head (one atomic add
+// each; the degree is fixed per workgroup, so each body is compiled for its
+// degree and the kernel's registers are those of the largest body); an item
+// that needs another kind's results of its own patch waits on that patch's
+// completion counter, which only ever refers to items taken earlier, so the
+// waits always end. Each wait is bounded all the same: past the bound the
+// item proceeds and the batch status records the timeout.
+//
+// A batch object keeps the descriptors, the item list, the counters and,
+// once asked, a HIP graph of the two launches (counter reset, persistent
+// kernel); the autotuner times the grid size and the item order on the
+// device and keeps the fastest.
+#include <algorithm>
+#include <memory>
+#include <vector>
+
+#include "form_body.hpp"
+
+namespace iga {
+
+enum : int { BK_COEF = 0, BK_CUTE = 1, BK_INT = 2, BK_CUTR = 3, BK_NKIND = 4 };
+constexpr int kBatchMaxP = 6;
+constexpr int kCoefChunk = 1024;  // coefficient points per item
+
+struct BatchPlan {
+    int p;
+    int method;
+    int need[BK_NKIND];  // items of each kind
+    IntArgs ia;
+    CutEArgs ce;
+    CutRowArgs cr;
+    CoefArgs co;
+};
+
+struct BatchItem {
+    int plan, kind, unit, pad;
+};
+
+constexpr int kBatchGroups = kBatchMaxP;  // one queue per degree 1..6
+
+struct BatchDev {
+    const BatchPlan* plans;
+    const BatchItem* items;  // queue g holds items[off[g] .. off[g] + n[g])
+    int* heads;              // [kBatchGroups] queue heads
+    int* done;               // [n_plans][BK_NKIND] finished items
+    int* status;             // 1: a dependency wait hit its bound
+    int spin_limit;
+    int first_block[kBatchGroups + 1];  // workgroups [first_block[g], first_block[g+1]) serve degree g+1
+    int off[kBatchGroups], n[kBatchGroups];
+};
+
+template <int P>
+struct BatchSmemSize {
+    static constexpr size_t a = sizeof(IntSmem<P>), b = sizeof(CutESmem<P>), c = sizeof(CutRSmem<P>);
+    static constexpr size_t v = a > b ? (a > c ? a : c) : (b > c ? b : c);
+};
+template <int P>
+constexpr size_t batch_smem_max() {
+    return (BatchSmemSize<P>::v > batch_smem_max<P - 1>()) ? BatchSmemSize<P>::v : batch_smem_max<P - 1>();
+}
+template <>
+constexpr size_t batch_smem_max<0>() {
+    return 0;
+}
+
+__device__ __forceinline__ bool wait_count(int* ctr, int need, int limit) {
+    int spins = 0;
+    while (__hip_atomic_load(ctr, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < need) {
+        if (++spins > limit) return false;
+        __builtin_amdgcn_s_sleep(4);
+    }
+    return true;
+}
+
+template <int P>
+__device__ __forceinline__ void run_item(const BatchPlan& Bp, const BatchItem& it, unsigned char* smem) {
+    switch (it.kind) {
+        case BK_COEF: {
+            const int64_t n = Bp.co.nq + Bp.co.nb + Bp.co.n_nodes;
+            const int64_t t0 = (int64_t)it.unit * kCoefChunk;
+            for (int64_t t = t0 + threadIdx.x; t < min(n, t0 + kCoefChunk); t += 256) coef_point<P>(Bp.co, t);
+            break;
+        }
+        case BK_CUTE:
+            cut_elem_body<P>(Bp.ce, it.unit, *reinterpret_cast<CutESmem<P>*>(smem));
+            break;
+        case BK_INT:
+            interior_block<P>(Bp.ia, it.unit % Bp.ia.ntx, it.unit / Bp.ia.ntx, *reinterpret_cast<IntSmem<P>*>(smem));
+            break;
+        default:
+            cut_row_body<P>(Bp.cr, it.unit, *reinterpret_cast<CutRSmem<P>*>(smem));
+            break;
+    }
+}
+
+__global__ void k_batch_reset(int* heads, int n_heads, int* done, int n_done) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n_heads) heads[t] = 0;
+    if (t < n_done) done[t] = 0;
+}
+
+template <int P>
+__device__ __forceinline__ void batch_loop(const BatchDev& B, int g, unsigned char* smem, int* s_idx) {
+    const BatchItem* items = B.items + B.off[g];
+    const int n = B.n[g];
+    for (;;) {
+        __syncthreads();  // the previous item is done with LDS and s_idx
+        if (threadIdx.x == 0) *s_idx = atomicAdd(B.heads + g, 1);
+        __syncthreads();
+        const int idx = __builtin_amdgcn_readfirstlane(*s_idx);
+        if (idx >= n) break;
+        BatchItem it = items[idx];
+        it.plan = __builtin_amdgcn_readfirstlane(it.plan);  // uniform: the descriptor is read once per wave
+        it.kind = __builtin_amdgcn_readfirstlane(it.kind);
+        it.unit = __builtin_amdgcn_readfirstlane(it.unit);
+        const BatchPlan& Bp = B.plans[it.plan];
+        // after a timed-out wait (status set) no item waits any more, so the launch always ends quickly
+        if (threadIdx.x == 0 && it.kind != BK_COEF &&
+            __hip_atomic_load(B.status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
+            int* d = B.done + (size_t)it.plan * BK_NKIND;
+            bool ok = wait_count(d + BK_COEF, Bp.need[BK_COEF], B.spin_limit);
+            if (it.kind == BK_CUTR) ok = wait_count(d + BK_CUTE, Bp.need[BK_CUTE], B.spin_limit) && ok;
+            if (!ok) atomicExch(B.status, 1);
+        }
+        __syncthreads();
+        run_item<P>(Bp, it, smem);
+        __syncthreads();  // every store of the item has reached L2
+        if (threadIdx.x == 0)
+            __hip_atomic_fetch_add(B.done + (size_t)it.plan * BK_NKIND + it.kind, 1, __ATOMIC_RELEASE,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+__global__ void __launch_bounds__(256) k_batch(BatchDev B) {
+    __shared__ __align__(16) unsigned char smem[batch_smem_max<kBatchMaxP>()];
+    __shared__ int s_idx;
+    int g = 0;
+    while (g < kBatchGroups - 1 && (int)blockIdx.x >= B.first_block[g + 1]) ++g;
+    switch (g + 1) {
+        case 1: batch_loop<1>(B, g, smem, &s_idx); break;
+        case 2: batch_loop<2>(B, g, smem, &s_idx); break;
+        case 3: batch_loop<3>(B, g, smem, &s_idx); break;
+        case 4: batch_loop<4>(B, g, smem, &s_idx); break;
+        case 5: batch_loop<5>(B, g, smem, &s_idx); break;
+        case 6: batch_loop<6>(B, g, smem, &s_idx); break;
+        default: break;
+    }
+}
+
+// ------------------------------------------------------------------ host
+struct Batch {
+    std::vector<Plan*> plans;
+    std::vector<iga_coeff> coeffs;
+    std::vector<double*> outs;
+    std::vector<BatchItem> items_lpt, items_plan;  // two queue orders, grouped by degree
+    int g_off[kBatchGroups] = {}, g_n[kBatchGroups] = {};
+    double g_work[kBatchGroups] = {};
+    BatchPlan* d_plans = nullptr;
+    BatchItem* d_items = nullptr;
+    int* d_counters = nullptr;  // status, heads[kBatchGroups], done[]
+    int n_items = 0;
+    int n_cu = 256;
+    int wg_per_cu = 2;
+    int order = 0;  // 0 cost-sorted, 1 patch by patch
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipStream_t cap_stream = nullptr;
+    int64_t nnz = 0;
+
+    ~Batch() {
+        if (exec) hipGraphExecDestroy(exec);
+        if (graph) hipGraphDestroy(graph);
+        if (cap_stream) hipStreamDestroy(cap_stream);
+        if (d_plans) hipFree(d_plans);
+        if (d_items) hipFree(d_items);
+        if (d_counters) hipFree(d_counters);
+    }
+    void drop_graph() {
+        if (exec) hipGraphExecDestroy(exec);
+        if (graph) hipGraphDestroy(graph);
+        exec = nullptr;
+        graph = nullptr;
+    }
+    void upload_items(hipStream_t s) {
+        const auto& v = order == 0 ? items_lpt : items_plan;
+        HIPX(hipMemcpyAsync(d_items, v.data(), sizeof(BatchItem) * v.size(), hipMemcpyHostToDevice, s));
+        HIPX(hipStreamSynchronize(s));
+    }
+    // workgroups per degree: proportional to the degree's work, at least one, at most its items
+    void split(int* first, int& total) const {
+        double wsum = 0.0;
+        for (int g = 0; g < kBatchGroups; ++g) wsum += g_work[g];
+        const int budget = n_cu * wg_per_cu;
+        total = 0;
+        for (int g = 0; g < kBatchGroups; ++g) {
+            first[g] = total;
+            if (g_n[g] == 0) continue;
+            int w = (int)(budget * (g_work[g] / std::max(wsum, 1e-300)));
+            total += std::max(1, std::min(w, g_n[g]));
+        }
+        first[kBatchGroups] = total;
+    }
+    int grid() const {
+        int first[kBatchGroups + 1], total = 0;
+        split(first, total);
+        return std::max(1, total);
+    }
+    void launch(hipStream_t s) {
+        const int nd = (int)plans.size() * BK_NKIND;
+        int* heads = d_counters + 1;
+        int* done = d_counters + 1 + kBatchGroups;
+        hipLaunchKernelGGL(k_batch_reset, dim3((std::max(nd, kBatchGroups) + 255) / 256), dim3(256), 0, s, heads,
+                           kBatchGroups, done, nd);
+        BatchDev B{};
+        B.plans = d_plans;
+        B.items = d_items;
+        B.heads = heads;
+        B.done = done;
+        B.status = d_counters;
+        B.spin_limit = 1 << 20;
+        int total = 0;
+        split(B.first_block, total);
+        for (int g = 0; g < kBatchGroups; ++g) {
+            B.off[g] = g_off[g];
+            B.n[g] = g_n[g];
+        }
+        if (total > 0) hipLaunchKernelGGL(k_batch, dim3(total), dim3(256), 0, s, B);
+    }
+};
+
+static double item_cost(const Plan& P, int kind, int unit, const std::vector<int>& node_off) {
+    const double p1 = P.p + 1.0;
+    switch (kind) {
+        case BK_COEF: return kCoefChunk * p1 * p1;
+        case BK_CUTE: return (node_off[unit + 1] - node_off[unit]) * p1 * p1 * p1 * p1 * 0.5;
+        case BK_INT: return 64.0 * p1 * p1 * p1 * 4.0;
+        default: return p1 * p1 * p1 * p1 * p1;
+    }
+}
+
+}  // namespace iga
+
+struct iga_batch : public iga::Batch {};
+
+namespace iga {
+
+static iga_batch* batch_create(iga_plan* const* plans, int count, const iga_coeff* cs, double* const* outs) {
+    IGA_REQUIRE(count > 0 && plans && cs && outs, IGA_E_INVALID, "empty batch");
+    auto B = std::make_unique<iga_batch>();
+    int dev = 0;
+    HIPX(hipGetDevice(&dev));
+    HIPX(hipDeviceGetAttribute(&B->n_cu, hipDeviceAttributeMultiprocessorCount, dev));
+    HIPX(hipStreamCreate(&B->cap_stream));
+    std::vector<BatchPlan> hp(count);
+    struct Cand {
+        BatchItem it;
+        double cost;
+    };
+    std::vector<Cand> all;
+    for (int k = 0; k < count; ++k) {
+        IGA_REQUIRE(plans[k], IGA_E_INVALID, "null plan in batch");
+        Plan& P = *static_cast<Plan*>(plans[k]);
+        const iga_coeff& c = cs[k];
+        IGA_REQUIRE(outs[k], IGA_E_INVALID, "output buffer missing");
+        IGA_REQUIRE(P.p <= kBatchMaxP, IGA_E_UNSUPPORTED, "batched formation handles degrees up to 6");
+        IGA_REQUIRE(P.method == IGA_HYBRID_GAUSS || P.method == IGA_GAUSS_REF, IGA_E_UNSUPPORTED,
+                    "batched formation handles hybrid Gauss and element Gauss plans");
+        IGA_REQUIRE(c.kind >= IGA_COEF_CONST && c.kind <= IGA_COEF_AT_POINTS, IGA_E_UNSUPPORTED, "coefficient kind");
+        IGA_REQUIRE(c.kind != IGA_COEF_GEOM_DETJ || c.geom_cp, IGA_E_INVALID, "geometry control points missing");
+        IGA_REQUIRE(c.kind != IGA_COEF_AT_POINTS || c.c_points, IGA_E_INVALID, "per-point coefficient missing");
+        B->plans.push_back(&P);
+        B->coeffs.push_back(c);
+        B->outs.push_back(outs[k]);
+        B->nnz += P.nnz;
+        BatchPlan& bp = hp[k];
+        bp.p = P.p;
+        bp.method = P.method;
+        bp.ia = int_args(P, c, outs[k]);
+        bp.ce = cute_args(P, c);
+        bp.cr = cutr_args(P, c, outs[k]);
+        bp.co = coef_args(P, c);
+        std::vector<int> node_off(P.n_cut_el + 1, 0);
+        if (P.n_cut_el > 0)
+            HIPX(hipMemcpy(node_off.data(), P.node_off, sizeof(int) * (P.n_cut_el + 1), hipMemcpyDeviceToHost));
+        const int64_t npts = bp.co.nq + bp.co.nb + bp.co.n_nodes;
+        const int n_coef = (c.kind == IGA_COEF_GEOM_DETJ) ? (int)((npts + kCoefChunk - 1) / kCoefChunk) : 0;
+        const int n_int = (P.method == IGA_GAUSS_REF) ? 0 : bp.ia.ntx * P.n2;
+        const int n_cute = (int)P.n_cut_el, n_cutr = (int)P.n_form_rows;
+        const int counts[BK_NKIND] = {n_coef, n_cute, n_int, n_cutr};
+        for (int kind = 0; kind < BK_NKIND; ++kind) {
+            bp.need[kind] = counts[kind];
+            for (int u = 0; u < counts[kind]; ++u)
+                all.push_back({BatchItem{k, kind, u, 0}, item_cost(P, kind, u, node_off)});
+        }
+    }
+    // queues by degree; inside, kinds in dependency order (interior and element-formed rows share a
+    // stage), then by decreasing cost (or patch by patch)
+    auto stage = [](int kind) { return kind == BK_COEF ? 0 : (kind == BK_CUTE ? 1 : 2); };
+    auto deg = [&](const Cand& a) { return hp[a.it.plan].p; };
+    std::vector<Cand> lpt = all;
+    std::stable_sort(lpt.begin(), lpt.end(), [&](const Cand& a, const Cand& b) {
+        if (deg(a) != deg(b)) return deg(a) < deg(b);
+        if (stage(a.it.kind) != stage(b.it.kind)) return stage(a.it.kind) < stage(b.it.kind);
+        return a.cost > b.cost;
+    });
+    std::vector<Cand> pm = all;
+    std::stable_sort(pm.begin(), pm.end(), [&](const Cand& a, const Cand& b) {
+        if (deg(a) != deg(b)) return deg(a) < deg(b);
+        if (stage(a.it.kind) != stage(b.it.kind)) return stage(a.it.kind) < stage(b.it.kind);
+        return a.it.plan < b.it.plan;
+    });
+    for (int g = 0; g < kBatchGroups; ++g) B->g_off[g] = B->g_n[g] = 0;
+    for (size_t k = 0; k < lpt.size(); ++k) {
+        const int g = deg(lpt[k]) - 1;
+        if (B->g_n[g] == 0) B->g_off[g] = (int)k;
+        B->g_n[g]++;
+        B->g_work[g] += lpt[k].cost;
+    }
+    for (auto& c : lpt) B->items_lpt.push_back(c.it);
+    for (auto& c : pm) B->items_plan.push_back(c.it);
+    B->n_items = (int)all.size();
+    HIPX(hipMalloc(&B->d_plans, sizeof(BatchPlan) * count));
+    HIPX(hipMemcpy(B->d_plans, hp.data(), sizeof(BatchPlan) * count, hipMemcpyHostToDevice));
+    HIPX(hipMalloc(&B->d_items, sizeof(BatchItem) * std::max(1, B->n_items)));
+    HIPX(hipMalloc(&B->d_counters, sizeof(int) * (1 + kBatchGroups + (size_t)count * BK_NKIND)));
+    HIPX(hipMemset(B->d_counters, 0, sizeof(int) * (1 + kBatchGroups + (size_t)count * BK_NKIND)));
+    B->upload_items(B->cap_stream);
+    return B.release();
+}
+
+static void batch_form(Batch& B, int use_graph, hipStream_t s) {
+    if (!use_graph) {
+        B.launch(s);
+        return;
+    }
+    if (!B.exec) {
+        HIPX(hipStreamBeginCapture(B.cap_stream, hipStreamCaptureModeRelaxed));
+        B.launch(B.cap_stream);
+        HIPX(hipStreamEndCapture(B.cap_stream, &B.graph));
+        HIPX(hipGraphInstantiate(&B.exec, B.graph, nullptr, nullptr, 0));
+    }
+    HIPX(hipGraphLaunch(B.exec, s));
+}
+
+// Times every (workgroups per CU, item order) pair on the device, keeps the fastest.
+static void batch_autotune(Batch& B, hipStream_t s, float* best_ms) {
+    hipEvent_t a, b;
+    HIPX(hipEventCreate(&a));
+    HIPX(hipEventCreate(&b));
+    float best = 1e30f;
+    int bw = B.wg_per_cu, bo = B.order;
+    for (int order = 0; order < 2; ++order) {
+        B.order = order;
+        B.upload_items(s);
+        for (int w = 1; w <= 4; ++w) {
+            B.wg_per_cu = w;
+            B.launch(s);  // warm-up
+            float t = 1e30f;
+            for (int rep = 0; rep < 3; ++rep) {
+                HIPX(hipEventRecord(a, s));
+                B.launch(s);
+                HIPX(hipEventRecord(b, s));
+                HIPX(hipEventSynchronize(b));
+                float ms = 0.f;
+                HIPX(hipEventElapsedTime(&ms, a, b));
+                t = std::min(t, ms);
+            }
+            if (t < best) {
+                best = t;
+                bw = w;
+                bo = order;
+            }
+        }
+    }
+    hipEventDestroy(a);
+    hipEventDestroy(b);
+    B.wg_per_cu = bw;
+    B.order = bo;
+    B.upload_items(s);
+    B.drop_graph();
+    if (best_ms) *best_ms = best;
+}
+
+}  // namespace iga
+
+using namespace iga;
+
+extern "C" {
+
+#define API_TRY try {
+#define API_CATCH                             \
+    }                                         \
+    catch (const Error& e) {                  \
+        set_error(e.msg);                     \
+        return e.code;                        \
+    }                                         \
+    catch (const std::exception& e) {         \
+        set_error(e.what());                  \
+        return IGA_E_INVALID;                 \
+    }                                         \
+    return IGA_OK;
+
+int iga_batch_create(iga_plan* const* plans, int32_t count, const iga_coeff* cs, double* const* vals,
+                     iga_batch** out) {
+    API_TRY
+    IGA_REQUIRE(out, IGA_E_INVALID, "null argument");
+    *out = batch_create(plans, count, cs, vals);
+    API_CATCH
+}
+
+void iga_batch_destroy(iga_batch* b) {
+    if (!b) return;
+    hipDeviceSynchronize();
+    delete b;
+}
+
+int iga_batch_form(iga_batch* b, int32_t use_graph, void* stream) {
+    API_TRY
+    IGA_REQUIRE(b, IGA_E_INVALID, "null batch");
+    batch_form(*b, use_graph, (hipStream_t)stream);
+    HIPX(hipGetLastError());
+    API_CATCH
+}
+
+int iga_batch_autotune(iga_batch* b, void* stream, float* best_ms) {
+    API_TRY
+    IGA_REQUIRE(b, IGA_E_INVALID, "null batch");
+    batch_autotune(*b, (hipStream_t)stream, best_ms);
+    API_CATCH
+}
+
+int iga_batch_info(const iga_batch* b, iga_batch_stats* st) {
+    API_TRY
+    IGA_REQUIRE(b && st, IGA_E_INVALID, "null argument");
+    st->n_plans = (int64_t)b->plans.size();
+    st->n_items = b->n_items;
+    st->nnz = b->nnz;
+    st->grid = b->grid();
+    st->wg_per_cu = b->wg_per_cu;
+    st->order = b->order;
+    st->graph_ready = b->exec != nullptr;
+    API_CATCH
+}
+
+int iga_batch_status(iga_batch* b, void* stream) {
+    API_TRY
+    IGA_REQUIRE(b, IGA_E_INVALID, "null batch");
+    int h = 0;
+    HIPX(hipMemcpyAsync(&h, b->d_counters, sizeof(int), hipMemcpyDeviceToHost, (hipStream_t)stream));
+    HIPX(hipStreamSynchronize((hipStream_t)stream));
+    IGA_REQUIRE(h == 0, IGA_E_INVALID, "a dependency wait of the batched kernel hit its bound");
+    for (Plan* P : b->plans) {
+        int st = 0;
+        HIPX(hipMemcpy(&st, P->status, sizeof(int), hipMemcpyDeviceToHost));
+        IGA_REQUIRE(st == 0, st, "device status of a batched plan");
+    }
+    API_CATCH
+}
+
+int iga_trim_mass_form_batched(iga_plan* const* plans, int32_t count, const iga_coeff* cs, double* const* vals,
+                               int32_t use_graph, void* stream) {
+    API_TRY
+    std::unique_ptr<iga_batch> B(batch_create(plans, count, cs, vals));
+    batch_form(*B, use_graph, (hipStream_t)stream);
+    HIPX(hipStreamSynchronize((hipStream_t)stream));
+    API_CATCH
+}
+
+}  // extern "C"

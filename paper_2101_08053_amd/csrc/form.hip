@@ -15,7 +15,7 @@
 //    rows; the reference: every row): element Gauss on inside elements of
 //    the support, the cut element matrices on cut elements. One workgroup per
 //    row, one thread per band slot.
-#include "plan.hpp"
+#include "form_body.hpp"
 
 namespace iga {
 
@@ -61,37 +61,9 @@ void launch_points(Plan& P, hipStream_t s) {
 }
 
 // ------------------------------------------------------- coefficient
-__global__ void k_coef_wq(DirDev D1, DirDev D2, int p, const double* __restrict__ cp, int n1, double* __restrict__ c) {
-    int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= D1.Q * D2.Q) return;
-    int k1 = k % D1.Q, k2 = k / D1.Q;
-    c[k] = detj_local(cp, n1, p, D1.eq[k1], D2.eq[k2], D1.Bq + k1 * (p + 1), D1.dBq + k1 * (p + 1),
-                      D2.Bq + k2 * (p + 1), D2.dBq + k2 * (p + 1));
-}
-
-__global__ void k_coef_band(DirDev D1, DirDev D2, int p, const double* __restrict__ cp, int n1,
-                            const int* __restrict__ band_list, int n_band, double* __restrict__ c) {
-    int t = blockIdx.x * blockDim.x + threadIdx.x;
-    int ng = (p + 1) * (p + 1);
-    if (t >= n_band * ng) return;
-    int b = t / ng, g = t % ng, g1 = g % (p + 1), g2 = g / (p + 1);
-    int e = band_list[b], e1 = e % D1.N, e2 = e / D1.N;
-    int r1 = (e1 * (p + 1) + g1) * (p + 1), r2 = (e2 * (p + 1) + g2) * (p + 1);
-    c[t] = detj_local(cp, n1, p, e1, e2, D1.Bg + r1, D1.dBg + r1, D2.Bg + r2, D2.dBg + r2);
-}
-
 template <int P>
-__global__ void k_coef_cut(DirDev D1, DirDev D2, const double* __restrict__ cp, int n1,
-                           const int* __restrict__ cut_list, const int* __restrict__ node_el,
-                           const double* __restrict__ nx, const double* __restrict__ ny, int n,
-                           double* __restrict__ c) {
-    int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= n) return;
-    int e = cut_list[node_el[t]], e1 = e % D1.N, e2 = e / D1.N;
-    double B1[P + 1], dB1[P + 1], B2[P + 1], dB2[P + 1];
-    basis_eval_d<P>(D1.knots, P + e1, nx[t], B1, dB1);
-    basis_eval_d<P>(D2.knots, P + e2, ny[t], B2, dB2);
-    c[t] = detj_local(cp, n1, P, e1, e2, B1, dB1, B2, dB2);
+__global__ void __launch_bounds__(256) k_coef(CoefArgs A) {
+    coef_point<P>(A, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
 }
 
 CoefView coef_view(Plan& P, const iga_coeff& c) {
@@ -113,284 +85,42 @@ CoefView coef_view(Plan& P, const iga_coeff& c) {
     return v;
 }
 
+CoefArgs coef_args(Plan& P, const iga_coeff& c) {
+    return CoefArgs{P.dir[0], P.dir[1], c.geom_cp, P.n1, P.band_list, (int)P.n_band, P.cut_list, P.node_el,
+                    P.node_x, P.node_y, (int)P.n_nodes, P.c_wq, P.c_band, P.c_cut,
+                    (int64_t)P.dir[0].Q * P.dir[1].Q, (int64_t)P.n_band * (P.p + 1) * (P.p + 1)};
+}
+
 void launch_coef(Plan& P, const iga_coeff& c, hipStream_t s) {
     if (c.kind != IGA_COEF_GEOM_DETJ) return;
-    DirDev &D1 = P.dir[0], &D2 = P.dir[1];
-    int p = P.p;
-    int nq = D1.Q * D2.Q;
-    hipLaunchKernelGGL(k_coef_wq, dim3((nq + 255) / 256), dim3(256), 0, s, D1, D2, p, c.geom_cp, P.n1, P.c_wq);
-    int nb = (int)P.n_band * (p + 1) * (p + 1);
-    if (nb > 0)
-        hipLaunchKernelGGL(k_coef_band, dim3((nb + 255) / 256), dim3(256), 0, s, D1, D2, p, c.geom_cp, P.n1,
-                           P.band_list, (int)P.n_band, P.c_band);
-    if (P.n_nodes > 0) {
-        dim3 g((unsigned)((P.n_nodes + 255) / 256)), b(256);
-        switch (p) {
-#define CASE(PP)                                                                                              \
-    case PP:                                                                                                  \
-        hipLaunchKernelGGL(k_coef_cut<PP>, g, b, 0, s, D1, D2, c.geom_cp, P.n1, P.cut_list, P.node_el, P.node_x, \
-                           P.node_y, (int)P.n_nodes, P.c_cut);                                                \
-        break;
-            CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
+    CoefArgs A = coef_args(P, c);
+    const int64_t n = A.nq + A.nb + A.n_nodes;
+    dim3 g((unsigned)((n + 255) / 256)), b(256);
+    switch (P.p) {
+#define CASE(PP) \
+    case PP: hipLaunchKernelGGL(k_coef<PP>, g, b, 0, s, A); break;
+        CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
 #undef CASE
-        }
+        default: throw Error{IGA_E_UNSUPPORTED, "degree outside 1..8"};
     }
 }
 
 // ------------------------------------------------------- interior rows
-struct IntArgs {
-    DirDev d1, d2;
-    CoefView c;
-    const double* cwq;       // coefficient on the WQ grid (nullptr -> constant c.value)
-    const int8_t* fcls;
-    const int* act_of;
-    int all_active;          // 1: every active row (naive WQ), 0: interior rows only
-    double* vals;
-    int64_t n_act;
-    int tile2;
-    int ntx;                 // tiles along xi_1
-};
-
-template <int P>
-struct IntCfg {
-    static constexpr int W = 2 * P + 1;                  // band width
-    static constexpr int QM = 4 * P + 2;                 // max WQ points in one support
-    static constexpr int NR = 2 * P + 2;                 // support points of a regular function
-    static constexpr int KS = 2 * (64 + P) + 2 * P + 2;  // max xi_1 points of a tile window
-    static constexpr int KG = 4 * P + 2;                 // max xi_1 points of a boundary tile
-    static constexpr bool WBREG = (P <= 5);              // w1 * B1 of each lane held in registers
-};
-
-// Tiles along xi_1: for N1 >= p+3, tile 0 holds the p+1 functions whose
-// support touches the first element, the last tile those touching the last
-// element (their elements carry p+1 points), and the tiles in between hold
-// 64 "regular" functions each (2 points in every support element). Smaller
-// patches use one generic tile.
-__device__ __forceinline__ void tile_of(int tx, int ntx, int N1, int n1, int p, int& I1, int& nlive, bool& generic) {
-    if (N1 < p + 3) {
-        I1 = 0;
-        nlive = n1;
-        generic = true;
-    } else if (tx == 0) {
-        I1 = 0;
-        nlive = p + 1;
-        generic = true;
-    } else if (tx == ntx - 1) {
-        I1 = N1 - 1;
-        nlive = p + 1;
-        generic = true;
-    } else {
-        I1 = p + 1 + 64 * (tx - 1);
-        nlive = min(64, (N1 - 2) - I1 + 1);
-        generic = false;
-    }
-}
-
-// Workgroups are handed to the XCDs round-robin; renumber them so that each
-// XCD works on a contiguous range of rows (neighbouring rows share most of
-// their coefficient points, which then stay in that XCD's L2).
-__device__ __forceinline__ int xcd_block(int bid, int nb) {
-    const int q = nb >> 3, r = nb & 7, x = bid & 7;
-    return x * q + min(x, r) + (bid >> 3);
-}
-
-// One workgroup = one test-function row i2 and a tile of (up to) 64 rows i1.
-// Stage 1 contracts xi_2 for every xi_1 point k of the tile's window,
-//   T[b][k] = sum_q (w2 B2)[i2][q][b] c(k, k2lo + q),
-// one point per thread; stage 2 contracts xi_1, one row i1 per lane,
-//   M[a][b] = sum_k (w1 B1)[i1][k][a] T[b][k],
-// the four wavefronts sharing the 2p+1 columns b. Every global load of a
-// stage is issued before the first one is used.
 template <int P>
 __global__ void __launch_bounds__(256) k_interior(IntArgs A) {
-    using C = IntCfg<P>;
-    constexpr int W = C::W, QM = C::QM, NR = C::NR, KS = C::KS, KG = C::KG;
-    __shared__ __align__(16) double sT[W][KS];   // T[b][k - k1lo]
-    __shared__ double sWB2[QM][W];                 // w2 * B2 of the row
-    __shared__ double sB1[C::WBREG ? KG : KS][P + 1];  // B1 at the window's points
-    __shared__ double sW1[64][QM + 1];             // boundary tiles: w1 per lane
-
-    const DirDev& D1 = A.d1;
-    const DirDev& D2 = A.d2;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int ntx = A.ntx;
+    __shared__ __align__(16) IntSmem<P> S;
     const int blk = xcd_block(blockIdx.x, gridDim.x);
-    const int i2 = blk / ntx;
-    int I1, nlive;
-    bool generic;
-    tile_of(blk - i2 * ntx, ntx, D1.N, D1.n, P, I1, nlive, generic);
-    const int elo = max(0, I1 - P), ehi = min(D1.N - 1, I1 + nlive - 1);
-    const int k1lo = wq_pt0(elo, D1.N, P);
-    const int ks = wq_pt0(ehi + 1, D1.N, P) - k1lo;
-    const int k2lo = wq_pt0(max(0, i2 - P), D2.N, P);
-    const int q2 = wq_pt0(min(D2.N - 1, i2) + 1, D2.N, P) - k2lo;
-    const bool reg_row = (i2 >= P + 1) && (i2 <= D2.N - 2);  // q2 == NR, two points per element
-
-    // ---- loads: row identity, xi_2 factors, window tables, coefficient column
-    const int i1 = I1 + lane;
-    bool live = false;
-    int64_t cid = 0;
-    if (lane < nlive) {
-        const int f = i2 * D1.n + i1;
-        const int8_t cls = A.fcls[f];
-        const int id = A.act_of[f];
-        live = A.all_active ? (cls != FN_EXTERIOR) : (cls == FN_INTERIOR);
-        cid = id;
-    }
-    double wb2 = 0.0;
-    if (tid < QM * W) {
-        const int q = tid / W;
-        if (q < q2) wb2 = D2.WB[((size_t)i2 * D2.qmax) * W + tid];
-    }
-    constexpr int NGB = (KG * (P + 1) + 255) / 256;
-    double gb[NGB];
-    if (generic) {
-#pragma unroll
-        for (int u = 0; u < NGB; ++u) {
-            const int t = tid + 256 * u;
-            gb[u] = (t < ks * (P + 1)) ? D1.Bq[(size_t)k1lo * (P + 1) + t] : 0.0;
-        }
-    }
-    const int kk = min(tid, ks - 1);
-    double cv[QM];
-    if (reg_row) {
-        if (A.cwq) {
-            const double* cc = A.cwq + (size_t)k2lo * D1.Q + k1lo + kk;
-#pragma unroll
-            for (int q = 0; q < NR; ++q) cv[q] = cc[(size_t)q * D1.Q];
-        } else {
-#pragma unroll
-            for (int q = 0; q < NR; ++q) cv[q] = A.c.value;
-        }
-    } else {
-        if (A.cwq) {
-            const double* cc = A.cwq + (size_t)k2lo * D1.Q + k1lo + kk;
-#pragma unroll
-            for (int q = 0; q < QM; ++q) cv[q] = (q < q2) ? cc[(size_t)q * D1.Q] : 0.0;
-        } else {
-#pragma unroll
-            for (int q = 0; q < QM; ++q) cv[q] = (q < q2) ? A.c.value : 0.0;
-        }
-    }
-    if (!generic && !C::WBREG) {
-        for (int t = tid; t < ks * (P + 1); t += 256) sB1[t / (P + 1)][t % (P + 1)] = D1.Bq[(size_t)k1lo * (P + 1) + t];
-    }
-    if (generic) {
-        for (int t = tid; t < 64 * QM; t += 256) {
-            const int l = t / QM, q = t % QM;
-            sW1[l][q] = (l < nlive && q < D1.qmax) ? D1.W[(size_t)(I1 + l) * D1.qmax + q] : 0.0;
-        }
-#pragma unroll
-        for (int u = 0; u < NGB; ++u) {
-            const int t = tid + 256 * u;
-            if (t < ks * (P + 1)) sB1[t / (P + 1)][t % (P + 1)] = gb[u];
-        }
-    }
-    if (tid < QM * W) sWB2[tid / W][tid % W] = wb2;
-    if (!__syncthreads_or(live)) return;   // no row of the tile is formed here
-
-    // ---- stage 1: contract xi_2 for every xi_1 point of the window
-    if (tid < ks) {
-        if (reg_row) {
-            double T[W];
-#pragma unroll
-            for (int b = 0; b < W; ++b) T[b] = 0.0;
-#pragma unroll
-            for (int q = 0; q < NR; ++q) {
-                const int m2 = q >> 1;
-#pragma unroll
-                for (int bl = 0; bl <= P; ++bl) T[m2 + bl] += sWB2[q][m2 + bl] * cv[q];
-            }
-#pragma unroll
-            for (int b = 0; b < W; ++b) sT[b][tid] = T[b];
-        } else {
-#pragma unroll 1
-            for (int b = 0; b < W; ++b) {
-                double Tb = 0.0;
-#pragma unroll
-                for (int q = 0; q < QM; ++q) Tb += sWB2[q][b] * cv[q];
-                sT[b][tid] = Tb;
-            }
-        }
-    }
-
-    // regular lanes: w1 * B1 (or w1) at the 2p+2 support points, loaded while stage 1 finishes
-    double wb[C::WBREG ? NR : 1][C::WBREG ? P + 1 : 1];
-    double w1[C::WBREG ? 1 : NR];
-    if (!generic) {
-        const int i1c = min(i1, D1.n - 1);
-        if constexpr (C::WBREG) {
-            const double* row = D1.WB + (size_t)i1c * D1.qmax * W;
-#pragma unroll
-            for (int q = 0; q < NR; ++q)
-#pragma unroll
-                for (int al = 0; al <= P; ++al) wb[q][al] = row[q * W + (q >> 1) + al];
-        } else {
-#pragma unroll
-            for (int q = 0; q < NR; ++q) w1[q] = D1.W[(size_t)i1c * D1.qmax + q];
-        }
-    }
-    __syncthreads();
-
-    // ---- stage 2: contract xi_1, one row per lane, columns b shared by the wavefronts
-    if (!generic) {
-        // regular lane: support points 2*lane .. 2*lane + 2p+1 of the window, two per element
-#pragma unroll 1
-        for (int b = wave; b < W; b += 4) {
-            double acc[W];
-#pragma unroll
-            for (int a = 0; a < W; ++a) acc[a] = 0.0;
-#pragma unroll
-            for (int m = 0; m <= P; ++m) {
-                const int k = 2 * lane + 2 * m;
-                const double2 t2 = *reinterpret_cast<const double2*>(&sT[b][k]);
-                if constexpr (C::WBREG) {
-#pragma unroll
-                    for (int al = 0; al <= P; ++al) acc[m + al] += wb[2 * m][al] * t2.x + wb[2 * m + 1][al] * t2.y;
-                } else {
-                    const double wa = w1[2 * m] * t2.x, wc = w1[2 * m + 1] * t2.y;
-#pragma unroll
-                    for (int al = 0; al <= P; ++al) acc[m + al] += wa * sB1[k][al] + wc * sB1[k + 1][al];
-                }
-            }
-            if (live)
-#pragma unroll
-                for (int a = 0; a < W; ++a) A.vals[(size_t)(a * W + b) * A.n_act + cid] = acc[a];
-        }
-    } else if (live) {
-        const int k0_1 = wq_pt0(max(0, i1 - P), D1.N, P) - k1lo;
-#pragma unroll 1
-        for (int b = wave; b < W; b += 4) {
-            double acc[W];
-#pragma unroll
-            for (int a = 0; a < W; ++a) acc[a] = 0.0;
-#pragma unroll
-            for (int m = 0; m <= P; ++m) {
-                const int e = i1 - P + m;
-                if (e < 0 || e >= D1.N) continue;
-                const int kb = wq_pt0(e, D1.N, P) - k1lo, ke = wq_pt0(e + 1, D1.N, P) - k1lo;
-                for (int k = kb; k < ke; ++k) {
-                    const double wt = sW1[lane][k - k0_1] * sT[b][k];
-#pragma unroll
-                    for (int al = 0; al <= P; ++al) acc[m + al] += wt * sB1[k][al];
-                }
-            }
-#pragma unroll
-            for (int a = 0; a < W; ++a) A.vals[(size_t)(a * W + b) * A.n_act + cid] = acc[a];
-        }
-    }
+    const int i2 = blk / A.ntx;
+    interior_block<P>(A, blk - i2 * A.ntx, i2, S);
 }
 
 template <int P>
 static void launch_interior_p(Plan& Pl, IntArgs A, hipStream_t s) {
-    const int N1 = Pl.N1;
-    A.ntx = (N1 < P + 3) ? 1 : 2 + ((N1 - 2) - (P + 1) + 1 + 63) / 64;
     const int nb = A.ntx * Pl.n2;
     hipLaunchKernelGGL(k_interior<P>, dim3(nb), dim3(256), 0, s, A);
 }
 
-void launch_interior_rows(Plan& P, const iga_coeff& c, double* vals, hipStream_t s) {
-    if (P.method == IGA_GAUSS_REF) return;
+IntArgs int_args(Plan& P, const iga_coeff& c, double* vals) {
     IntArgs A;
     A.d1 = P.dir[0];
     A.d2 = P.dir[1];
@@ -403,6 +133,24 @@ void launch_interior_rows(Plan& P, const iga_coeff& c, double* vals, hipStream_t
     A.vals = vals;
     A.n_act = P.n_act;
     A.tile2 = P.tile2;
+    A.ntx = interior_ntx(P.N1, P.p);
+    return A;
+}
+
+CutEArgs cute_args(Plan& P, const iga_coeff& c) {
+    return CutEArgs{P.dir[0], P.dir[1], coef_view(P, c), P.cut_list, P.node_off, P.node_x, P.node_y, P.node_w,
+                    P.cutE, (int)P.n_cut_el};
+}
+
+CutRowArgs cutr_args(Plan& P, const iga_coeff& c, double* vals) {
+    return CutRowArgs{P.dir[0], P.dir[1], coef_view(P, c), P.form_rows, (int)P.n_form_rows, P.fn_of, P.act_of,
+                      P.ecls, P.cut_id, P.band_id, P.cutE, P.method == IGA_DWQ ? P.dwq_region : nullptr, vals,
+                      P.n_act};
+}
+
+void launch_interior_rows(Plan& P, const iga_coeff& c, double* vals, hipStream_t s) {
+    if (P.method == IGA_GAUSS_REF) return;
+    IntArgs A = int_args(P, c, vals);
     switch (P.p) {
         case 1: launch_interior_p<1>(P, A, s); break;
         case 2: launch_interior_p<2>(P, A, s); break;
@@ -416,200 +164,23 @@ void launch_interior_rows(Plan& P, const iga_coeff& c, double* vals, hipStream_t
     }
 }
 
-// -------------------------------------------------- cut element matrices
-struct CutEArgs {
-    DirDev d1, d2;
-    CoefView c;
-    const int* cut_list;
-    const int* node_off;
-    const double *nx, *ny, *nw;
-    double* E;
-    int n_cut;
-};
-
+// -------------------------------------------------- cut element matrices / rows
 template <int P>
 __global__ void __launch_bounds__(256) k_cut_elem(CutEArgs A) {
-    constexpr int L = (P + 1) * (P + 1);
-    constexpr int NE = L * (L + 1) / 2;
-    constexpr int PER = (NE + 255) / 256;
-    constexpr int CH = 64;
-    __shared__ double sPhi[CH][L];
-    __shared__ double sWc[CH];
-    int c = blockIdx.x;
-    if (c >= A.n_cut) return;
-    int e = A.cut_list[c], e1 = e % A.d1.N, e2 = e / A.d1.N;
-    int nb = A.node_off[c], ne = A.node_off[c + 1];
-    double acc[PER];
-    int el[PER], em[PER];
-#pragma unroll
-    for (int k = 0; k < PER; ++k) {
-        acc[k] = 0.0;
-        int t = threadIdx.x + 256 * k;
-        int l = 0, rem = t;
-        while (l < L && rem >= L - l) { rem -= L - l; ++l; }   // upper-triangle enumeration
-        el[k] = (t < NE) ? l : -1;
-        em[k] = (t < NE) ? l + rem : -1;
-    }
-    for (int base = nb; base < ne; base += CH) {
-        __syncthreads();
-        if (threadIdx.x < CH) {
-            int n = base + threadIdx.x;
-            if (n < ne) {
-                double B1[P + 1], B2[P + 1];
-                basis_eval<P>(A.d1.knots, P + e1, A.nx[n], B1);
-                basis_eval<P>(A.d2.knots, P + e2, A.ny[n], B2);
-#pragma unroll
-                for (int a2 = 0; a2 <= P; ++a2)
-#pragma unroll
-                    for (int a1 = 0; a1 <= P; ++a1) sPhi[threadIdx.x][a2 * (P + 1) + a1] = B1[a1] * B2[a2];
-                sWc[threadIdx.x] = A.nw[n] * (A.c.is_const ? A.c.value : A.c.cut[n]);
-            } else {
-                sWc[threadIdx.x] = 0.0;
-#pragma unroll
-                for (int l = 0; l < L; ++l) sPhi[threadIdx.x][l] = 0.0;
-            }
-        }
-        __syncthreads();
-        int cnt = min(CH, ne - base);
-#pragma unroll
-        for (int k = 0; k < PER; ++k) {
-            if (el[k] < 0) continue;
-            double s = 0.0;
-            for (int n = 0; n < cnt; ++n) s += sWc[n] * sPhi[n][el[k]] * sPhi[n][em[k]];
-            acc[k] += s;
-        }
-    }
-    double* E = A.E + (size_t)c * L * L;
-#pragma unroll
-    for (int k = 0; k < PER; ++k) {
-        if (el[k] < 0) continue;
-        E[el[k] * L + em[k]] = acc[k];
-        E[em[k] * L + el[k]] = acc[k];
-    }
+    __shared__ CutESmem<P> S;
+    cut_elem_body<P>(A, blockIdx.x, S);
 }
 
-// ------------------------------------------------------------ cut rows
-struct CutRowArgs {
-    DirDev d1, d2;
-    CoefView c;
-    const int* rows;        // compact ids of the rows formed here
-    int n_rows;
-    const int* fn_of;
-    const int* act_of;
-    const int8_t* ecls;
-    const int* cut_id;
-    const int* band_id;
-    const double* E;
-    const int* region;      // DWQ: box of inside elements left to k_dwq_rows (nullptr: none)
-    double* vals;
-    int64_t n_act;
-};
-
-// One workgroup per row; the row's per-direction Gauss factors
-// F1[m1][g1][a] = w_g1 B_i1 B_{i1+a-p} (element e1 = i1-p+m1), F2 likewise,
-// the element classes and c at the Gauss points of its support elements are
-// staged in LDS; thread (a, b) then sums over the elements shared with its
-// column: Gauss on inside elements (sum-factorised), the cut element matrix
-// on cut elements.
 template <int P>
 __global__ void __launch_bounds__((((2 * P + 1) * (2 * P + 1) + 63) / 64) * 64) k_cut_rows(CutRowArgs A) {
-    constexpr int W = 2 * P + 1, L = (P + 1) * (P + 1), NP = P + 1;
-    __shared__ double sF1[NP][NP][W];
-    __shared__ double sF2[NP][NP][W];
-    __shared__ double sC[NP][NP][L];
-    __shared__ int sCls[NP][NP];
-    __shared__ int sId[NP][NP];
-    const int r = blockIdx.x;
-    if (r >= A.n_rows) return;
-    const DirDev& D1 = A.d1;
-    const DirDev& D2 = A.d2;
-    const int tid = threadIdx.x, nt = blockDim.x;
-    const int row = A.rows[r];
-    const int f = A.fn_of[row];
-    const int i1 = f % D1.n, i2 = f / D1.n;
-    int bx0 = 1, bx1 = 0, by0 = 1, by1 = 0;   // DWQ box (empty by default)
-    if (A.region && A.region[(size_t)r * 8] >= 0) {
-        bx0 = A.region[(size_t)r * 8];
-        bx1 = A.region[(size_t)r * 8 + 1];
-        by0 = A.region[(size_t)r * 8 + 4];
-        by1 = A.region[(size_t)r * 8 + 5];
-    }
-    for (int t = tid; t < NP * NP * W; t += nt) {
-        int m = t / (NP * W), g = (t / W) % NP, a = t % W;
-        // direction 1
-        int e1 = i1 - P + m, j1 = i1 + a - P;
-        double v = 0.0;
-        if (e1 >= 0 && e1 < D1.N && j1 - e1 >= 0 && j1 - e1 <= P) {
-            int rr = (e1 * NP + g) * NP;
-            v = D1.wg[e1 * NP + g] * D1.Bg[rr + i1 - e1] * D1.Bg[rr + j1 - e1];
-        }
-        sF1[m][g][a] = v;
-        int e2 = i2 - P + m, j2 = i2 + a - P;
-        v = 0.0;
-        if (e2 >= 0 && e2 < D2.N && j2 - e2 >= 0 && j2 - e2 <= P) {
-            int rr = (e2 * NP + g) * NP;
-            v = D2.wg[e2 * NP + g] * D2.Bg[rr + i2 - e2] * D2.Bg[rr + j2 - e2];
-        }
-        sF2[m][g][a] = v;
-    }
-    for (int t = tid; t < NP * NP; t += nt) {
-        int m2 = t / NP, m1 = t % NP;
-        int e1 = i1 - P + m1, e2 = i2 - P + m2;
-        int cls = -1, id = -1;
-        if (e1 >= 0 && e1 < D1.N && e2 >= 0 && e2 < D2.N && !(e1 >= bx0 && e1 <= bx1 && e2 >= by0 && e2 <= by1)) {
-            int e = e2 * D1.N + e1;
-            cls = A.ecls[e];
-            id = (cls == EL_CUT) ? A.cut_id[e] : (cls == EL_INSIDE ? A.band_id[e] : -1);
-        }
-        sCls[m2][m1] = cls;
-        sId[m2][m1] = id;
-    }
-    __syncthreads();
-    if (!A.c.is_const) {
-        for (int t = tid; t < NP * NP * L; t += nt) {
-            int m2 = t / (NP * L), m1 = (t / L) % NP, g = t % L;
-            sC[m2][m1][g] = (sCls[m2][m1] == EL_INSIDE) ? A.c.band[(size_t)sId[m2][m1] * L + g] : 0.0;
-        }
-        __syncthreads();
-    }
-    const int s = tid;
-    if (s >= W * W) return;
-    const int a = s / W, b = s % W;          // column offsets a-p, b-p
-    const int j1 = i1 + a - P, j2 = i2 + b - P;
-    double val = 0.0;
-    if (j1 >= 0 && j1 < D1.n && j2 >= 0 && j2 < D2.n && A.act_of[j2 * D1.n + j1] >= 0) {
-        const int m1lo = max(0, a - P), m1hi = P + min(0, a - P);
-        const int m2lo = max(0, b - P), m2hi = P + min(0, b - P);
-        for (int m2 = m2lo; m2 <= m2hi; ++m2)
-            for (int m1 = m1lo; m1 <= m1hi; ++m1) {
-                const int cls = sCls[m2][m1];
-                if (cls == EL_INSIDE) {
-                    double sum = 0.0;
-#pragma unroll
-                    for (int g2 = 0; g2 < NP; ++g2) {
-                        double in = 0.0;
-#pragma unroll
-                        for (int g1 = 0; g1 < NP; ++g1)
-                            in += sF1[m1][g1][a] * (A.c.is_const ? A.c.value : sC[m2][m1][g2 * NP + g1]);
-                        sum += sF2[m2][g2][b] * in;
-                    }
-                    val += sum;
-                } else if (cls == EL_CUT) {
-                    const int li = (P - m2) * NP + (P - m1);
-                    const int lj = (j2 - (i2 - P + m2)) * NP + (j1 - (i1 - P + m1));
-                    val += A.E[(size_t)sId[m2][m1] * L * L + li * L + lj];
-                }
-            }
-    }
-    A.vals[(size_t)s * A.n_act + row] = val;
+    __shared__ CutRSmem<P> S;
+    cut_row_body<P>(A, blockIdx.x, S);
 }
 
 void launch_cut_rows(Plan& P, const iga_coeff& c, double* vals, hipStream_t s) {
     if (P.method == IGA_NAIVE_WQ) return;
-    CoefView cv = coef_view(P, c);
     if (P.n_cut_el > 0) {
-        CutEArgs A{P.dir[0], P.dir[1], cv, P.cut_list, P.node_off, P.node_x, P.node_y, P.node_w, P.cutE,
-                   (int)P.n_cut_el};
+        CutEArgs A = cute_args(P, c);
         dim3 g((unsigned)P.n_cut_el), b(256);
         switch (P.p) {
 #define CASE(PP) \
@@ -620,8 +191,7 @@ void launch_cut_rows(Plan& P, const iga_coeff& c, double* vals, hipStream_t s) {
         }
     }
     if (P.n_form_rows > 0) {
-        CutRowArgs A{P.dir[0], P.dir[1], cv, P.form_rows, (int)P.n_form_rows, P.fn_of, P.act_of, P.ecls,
-                     P.cut_id, P.band_id, P.cutE, P.method == IGA_DWQ ? P.dwq_region : nullptr, vals, P.n_act};
+        CutRowArgs A = cutr_args(P, c, vals);
         int W = 2 * P.p + 1;
         dim3 g((unsigned)P.n_form_rows), b(((W * W + 63) / 64) * 64);
         switch (P.p) {

@@ -66,6 +66,11 @@ class iga_target(C.Structure):
     _fields_ = [("kind", C.c_int32), ("reserved", C.c_int32), ("w", C.c_double * 4), ("g_points", C.c_void_p)]
 
 
+class iga_batch_stats(C.Structure):
+    _fields_ = [("n_plans", C.c_int64), ("n_items", C.c_int64), ("nnz", C.c_int64), ("grid", C.c_int32),
+                ("wg_per_cu", C.c_int32), ("order", C.c_int32), ("graph_ready", C.c_int32)]
+
+
 class iga_solve_info(C.Structure):
     _fields_ = [("iterations", C.c_int32), ("converged", C.c_int32), ("rel_residual", C.c_double)]
 
@@ -98,6 +103,13 @@ def lib():
             "iga_mf_adjoint": (C.c_int, [P, V, V, V, V, V, V]),
             "iga_trim_mass_form_batched": (C.c_int, [C.POINTER(P), C.c_int32, C.POINTER(iga_coeff),
                                                      C.POINTER(C.c_void_p), C.c_int32, V]),
+            "iga_batch_create": (C.c_int, [C.POINTER(P), C.c_int32, C.POINTER(iga_coeff), C.POINTER(C.c_void_p),
+                                           C.POINTER(P)]),
+            "iga_batch_destroy": (None, [P]),
+            "iga_batch_form": (C.c_int, [P, C.c_int32, V]),
+            "iga_batch_autotune": (C.c_int, [P, V, C.POINTER(C.c_float)]),
+            "iga_batch_info": (C.c_int, [P, C.POINTER(iga_batch_stats)]),
+            "iga_batch_status": (C.c_int, [P, V]),
             "iga_plan_set_timing": (C.c_int, [P, C.c_int32]),
             "iga_plan_timings": (C.c_int, [P, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
             "iga_copy": (C.c_int, [V, V, C.c_int64, V]),
@@ -121,7 +133,9 @@ def lib():
 
 EXPORTED = ("iga_plan_create", "iga_plan_destroy", "iga_plan_sizes", "iga_plan_points", "iga_plan_index_maps",
             "iga_trim_mass_form", "iga_plan_status", "iga_trim_l2_project", "iga_trim_rhs", "iga_mf_apply",
-            "iga_mf_adjoint", "iga_trim_mass_form_batched", "iga_plan_set_timing", "iga_plan_timings",
+            "iga_mf_adjoint", "iga_trim_mass_form_batched", "iga_batch_create", "iga_batch_destroy",
+            "iga_batch_form", "iga_batch_autotune", "iga_batch_info", "iga_batch_status",
+            "iga_plan_set_timing", "iga_plan_timings",
             "iga_copy", "iga_plan_table", "iga_plan_int_table", "iga_plan_set_weights",
             "iga_plan_set_dwq_weights", "iga_plan_set_cut_nodes", "iga_status_string", "iga_last_error")
 
@@ -403,3 +417,66 @@ def mass_apply(u, c_points, plan):
     if _MassApply is None:
         _MassApply = _make_mass_apply()
     return _MassApply.apply(u, c_points, plan)
+
+
+class Batch:
+    """Batched formation of several set-up plans (one persistent launch, optional HIP graph).
+
+    The plans, coefficients and output tensors are kept referenced: the
+    library borrows them for the batch's life.
+    """
+
+    def __init__(self, plans, coeffs=None, outs=None):
+        torch = _torch()
+        self.plans = list(plans)
+        self.coeffs = [p.coeff() for p in self.plans] if coeffs is None else list(coeffs)
+        self.outs = outs if outs is not None else [
+            torch.empty((p.sizes["band"], p.sizes["n_act"]), dtype=torch.float64, device="cuda") for p in self.plans]
+        n = len(self.plans)
+        hs = (C.c_void_p * n)(*[p.h for p in self.plans])
+        cs = (iga_coeff * n)(*self.coeffs)
+        vs = (C.c_void_p * n)(*[_dptr(o) for o in self.outs])
+        self.h = C.c_void_p()
+        _check(lib().iga_batch_create(hs, n, cs, vs, C.byref(self.h)))
+
+    def form(self, use_graph=False, stream=None):
+        _check(lib().iga_batch_form(self.h, 1 if use_graph else 0, _stream(stream)))
+        return self.outs
+
+    def autotune(self, stream=None):
+        ms = C.c_float()
+        _check(lib().iga_batch_autotune(self.h, _stream(stream), C.byref(ms)))
+        return ms.value
+
+    def info(self):
+        st = iga_batch_stats()
+        _check(lib().iga_batch_info(self.h, C.byref(st)))
+        return {k: getattr(st, k) for k, _ in st._fields_}
+
+    def status(self, stream=None):
+        _check(lib().iga_batch_status(self.h, _stream(stream)))
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().iga_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def mass_form_batched(plans, coeffs=None, outs=None, use_graph=False, stream=None):
+    """One-shot batched formation (the C call builds, runs and frees a batch)."""
+    torch = _torch()
+    coeffs = [p.coeff() for p in plans] if coeffs is None else list(coeffs)
+    outs = outs if outs is not None else [
+        torch.empty((p.sizes["band"], p.sizes["n_act"]), dtype=torch.float64, device="cuda") for p in plans]
+    n = len(plans)
+    hs = (C.c_void_p * n)(*[p.h for p in plans])
+    cs = (iga_coeff * n)(*coeffs)
+    vs = (C.c_void_p * n)(*[_dptr(o) for o in outs])
+    _check(lib().iga_trim_mass_form_batched(hs, n, cs, vs, 1 if use_graph else 0, _stream(stream)))
+    return outs

@@ -1,0 +1,99 @@
+"""Batched formation (one persistent launch over many patches, HIP graph, autotuner).
+
+The batched kernel runs the same per-item bodies as the one-patch kernels,
+with the same summation order per entry, so its output must equal the
+one-patch formation bit for bit; the one-patch formation itself is checked
+against the oracle in test_gpu_form. The patch set follows the batched
+workload's generator (degrees 2..5, element counts log-uniform per
+direction, one ellipse each) at sizes small enough for a test.
+"""
+import numpy as np
+import pytest
+
+from gpu_common import require_gpu, say
+from paper_2101_08053_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+def _plans(n=10, n_range=(6, 40), seed=None):
+    from paper_2101_08053_amd import igatrim
+    kw = {} if seed is None else {"seed": seed}
+    cfgs = wl.config4(n_patch=n, n_range=n_range, **kw)
+    return cfgs, [igatrim.Plan(c, igatrim.HYBRID_GAUSS) for c in cfgs]
+
+
+def _plain(plans, coeffs):
+    return [p.mass_form(c).cpu().numpy() for p, c in zip(plans, coeffs)]
+
+
+def test_batch_equals_plain():
+    torch = require_gpu()
+    from paper_2101_08053_amd import igatrim
+    cfgs, plans = _plans()
+    say("[batch] degrees", [c.p for c in cfgs], "sizes", [c.n_el for c in cfgs])
+    coeffs = [p.coeff() for p in plans]
+    ref = _plain(plans, coeffs)
+    b = igatrim.Batch(plans, coeffs)
+    for o in b.outs:
+        o.fill_(np.nan)
+    outs = [o.cpu().numpy() for o in b.form()]
+    b.status()
+    for k, (g, r) in enumerate(zip(outs, ref)):
+        assert np.array_equal(g, r), f"patch {k}: max diff {np.nanmax(np.abs(g - r))}"
+    info = b.info()
+    say("[batch] info", info)
+    assert info["n_plans"] == len(plans) and info["grid"] >= 1
+
+
+def test_batch_graph_replays():
+    """Graph replays, with eager work and synchronisation between them, equal the eager batch."""
+    torch = require_gpu()
+    from paper_2101_08053_amd import igatrim
+    cfgs, plans = _plans(n=8, seed=wl.SEED_BASE + 40)
+    coeffs = [p.coeff() for p in plans]
+    ref = _plain(plans, coeffs)
+    b = igatrim.Batch(plans, coeffs)
+    for rep in range(4):
+        for o in b.outs:
+            o.zero_()
+        x = torch.randn(1 << 16, device="cuda", dtype=torch.float64)
+        _ = (x * x).sum().item()           # eager work between replays
+        torch.cuda.synchronize()
+        b.form(use_graph=True)
+        torch.cuda.synchronize()
+        b.status()
+        for k, (o, r) in enumerate(zip(b.outs, ref)):
+            assert np.array_equal(o.cpu().numpy(), r), f"replay {rep} patch {k}"
+    assert b.info()["graph_ready"] == 1
+
+
+def test_batch_autotune_keeps_results():
+    torch = require_gpu()
+    from paper_2101_08053_amd import igatrim
+    cfgs, plans = _plans(n=12, seed=wl.SEED_BASE + 41)
+    coeffs = [p.coeff() for p in plans]
+    ref = _plain(plans, coeffs)
+    b = igatrim.Batch(plans, coeffs)
+    ms = b.autotune()
+    info = b.info()
+    say(f"[batch autotune] best {ms:.3f} ms, {info}")
+    assert 1 <= info["wg_per_cu"] <= 4 and info["order"] in (0, 1)
+    outs = [o.cpu().numpy() for o in b.form(use_graph=True)]
+    b.status()
+    for g, r in zip(outs, ref):
+        assert np.array_equal(g, r)
+
+
+def test_batch_constant_coefficient_and_one_shot():
+    """c = 1 (no coefficient items) through the one-shot call; area invariant per patch."""
+    torch = require_gpu()
+    from paper_2101_08053_amd import igatrim
+    from oracle.trim import TrimmedSpace
+    cfgs, plans = _plans(n=6, seed=wl.SEED_BASE + 42)
+    coeffs = [p.coeff(igatrim.COEF_CONST, 1.0) for p in plans]
+    ref = _plain(plans, coeffs)
+    outs = [o.cpu().numpy() for o in igatrim.mass_form_batched(plans, coeffs)]
+    for g, r, c in zip(outs, ref, cfgs):
+        assert np.array_equal(g, r)
+        assert abs(g.sum() - TrimmedSpace(c).visible_area()) < 1e-10
