@@ -9,6 +9,12 @@ cut rows (hybrid Gauss). Workload: degree 4, 256 x 256 elements, perturbed
 geometry, hole bounded by a 16-point closed cubic B-spline (seeded).
 
 Prints one JSON line. `value` = structural nonzeros formed per second.
+Beside the headline the line carries: the same workload with discontinuous
+weighted quadrature; 256 patches formed by the batched persistent kernel
+(HIP graph, autotuned) against the same patches formed one by one; the
+matrix-free product and its adjoint on 1024 x 1024 elements against plain
+formation at that size; the dominant kernel's roofline; the oracle's rate on
+a bounded sample.
 """
 import argparse
 import json
@@ -33,7 +39,51 @@ def parse():
     ap.add_argument("--p", type=int, default=4)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle timing")
     ap.add_argument("--cpu-rows", type=int, default=8000, help="oracle sample: interior rows")
+    ap.add_argument("--no-extra", action="store_true", help="headline only (no DWQ / batched / adjoint lines)")
+    ap.add_argument("--batch", type=int, default=256, help="patches of the batched workload")
+    ap.add_argument("--mf-N", type=int, default=1024, help="elements per direction of the matrix-free workload")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only copy MIB MiB device to device 5 times (scale of the HBM byte counters) and exit")
     return ap.parse_args()
+
+
+def _timed(fn, steps, warmup, sync):
+    """Mean milliseconds of fn() over `steps` calls after `warmup`, synchronised on both sides."""
+    for _ in range(warmup):
+        fn()
+    sync()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    sync()
+    return 1e3 * (time.perf_counter() - t0) / steps
+
+
+def _source_digest(paths):
+    import hashlib
+    h = hashlib.sha256()
+    for p in paths:
+        with open(os.path.join(ROOT, p), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def _traffic(kernel_file, sources):
+    """HBM bytes per launch from a committed counter summary, or None if the kernel changed since."""
+    path = os.path.join(ROOT, "profiles", kernel_file)
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        if ":" in line and line.strip().startswith("- "):
+            k, v = line.strip()[2:].split(":", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("source digest") != _source_digest(sources):
+        return None
+    try:
+        return int(float(vals["HBM bytes per launch"]))
+    except (KeyError, ValueError):
+        return None
 
 
 def cpu_baseline(cfg, nnz_total, n_act, sample_rows):
@@ -46,8 +96,15 @@ def cpu_baseline(cfg, nnz_total, n_act, sample_rows):
     rows sampled.
     """
     import numpy as np
+    from threadpoolctl import threadpool_limits
+
     from oracle.assemble import Oracle
 
+    with threadpool_limits(limits=1):
+        return _cpu_baseline(Oracle, np, cfg, nnz_total, n_act, sample_rows)
+
+
+def _cpu_baseline(Oracle, np, cfg, nnz_total, n_act, sample_rows):
     t0 = time.perf_counter()
     o = Oracle(cfg)
     t_setup = time.perf_counter() - t0
@@ -80,6 +137,9 @@ def cpu_baseline(cfg, nnz_total, n_act, sample_rows):
                       f"+ {k_cut} cut rows of the same workload ({nnz_sample} nnz in {t_rows:.1f} s)"}
 
 
+INTERIOR_SOURCES = ["paper_2101_08053_amd/csrc/form_body.hpp", "paper_2101_08053_amd/csrc/form.hip"]
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -96,57 +156,50 @@ def main():
         from paper_2101_08053_amd import build
         build.build()
     torch.cuda.set_device(0)
+    sync = torch.cuda.synchronize
+    if args.copy_calibration:
+        n = args.copy_calibration * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        sync()
+        print(json.dumps({"copy_calibration_bytes_each_way": n * 8, "copies": 5}), flush=True)
+        return
+    stream = torch.cuda.current_stream()
     cfg = wl.config2(N=args.N, p=args.p)
     plan = igatrim.Plan(cfg, igatrim.HYBRID_GAUSS)
     sz = plan.sizes
     coef = plan.coeff()
     vals = torch.empty((sz["band"], sz["n_act"]), dtype=torch.float64, device="cuda")
-    stream = torch.cuda.current_stream()
 
     def step(full=True):
         plan.mass_form(coef, out=vals, full=full, stream=stream)
 
     for _ in range(args.warmup):
         step()
-    torch.cuda.synchronize()
+    sync()
     plan.status()
 
-    # timed region: whole formation path, per-phase HIP events recorded by the library
+    # timed region: the whole formation path; the library records per-phase HIP events on the stream
     plan.set_timing(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    t_wall = time.perf_counter() - t0
+    ms_step = _timed(step, args.steps, 0, sync)
     phases = plan.timings()
     plan.set_timing(False)
-    ms_step = 1e3 * t_wall / args.steps
     nnz = sz["nnz"]
     value = nnz / (ms_step * 1e-3)
+    ms_form = _timed(lambda: step(full=False), args.steps, 2, sync)
 
-    # formation only (tables resident): coefficient + interior + cut rows
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step(full=False)
-    torch.cuda.synchronize()
-    ms_form = 1e3 * (time.perf_counter() - t0) / args.steps
-
-    # dominant kernel of the step: interior rows (k_interior), one launch per step
+    # dominant kernel of the formation: interior rows (one k_interior launch per step), HBM bound
     int_ms, int_cnt = phases["interior"]
     k_ms = int_ms / max(1, int_cnt)
-    band = sz["band"]
-    alg_bytes = 8 * band * sz["n_interior"] + 8 * sz["q1"] * sz["q2"]
+    alg_bytes = 8 * sz["band"] * sz["n_interior"] + 8 * sz["q1"] * sz["q2"]
     achieved = alg_bytes / (k_ms * 1e-3) / 1e9
-    roof = {"kernel": "k_interior<4> (interior rows, WQ + sum factorisation)", "bound": "hbm",
+    traffic = _traffic(f"k_interior_p{args.p}_N{args.N}_traffic.md", INTERIOR_SOURCES)
+    roof = {"kernel": f"k_interior<{args.p}> (interior rows: WQ + sum factorisation)", "bound": "hbm",
             "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
             "avg_launch_ms": round(k_ms, 5), "algorithmic_bytes": int(alg_bytes)}
-
-    cpu = None
-    if not args.no_cpu:
-        cpu = cpu_baseline(cfg, nnz, sz["n_act"], args.cpu_rows)
 
     out = {
         "metric": "mass-matrix nnz formed/s (FP64, p=4 trimmed 256^2)",
@@ -159,12 +212,93 @@ def main():
                    "n_interior": sz["n_interior"], "n_cut_fn": sz["n_cut_fn"], "n_cut_el": sz["n_cut_el"],
                    "parallelism": "single GPU"},
         "roofline": roof,
-        "cpu_baseline": cpu,
+        "cpu_baseline": None,
         "phases_ms_per_step": {k: round(v[0] / max(1, v[1]), 5) for k, v in phases.items()},
         "formation_only": {"ms_per_step": ms_form, "value": nnz / (ms_form * 1e-3), "unit": "nnz/s",
                            "note": "tables resident; coefficient + interior rows + cut rows"},
     }
+    del vals
+    if not args.no_extra:
+        out["dwq"] = bench_dwq(igatrim, wl, cfg, args, sync, stream)
+        out["batched"] = bench_batched(igatrim, wl, args, sync)
+        out["adjoint"] = bench_adjoint(igatrim, wl, args, sync)
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(cfg, nnz, sz["n_act"], args.cpu_rows)
     print(json.dumps(out), flush=True)
+
+
+def bench_dwq(igatrim, wl, cfg, args, sync, stream):
+    """The headline workload with discontinuous weighted quadrature for the cut rows."""
+    import torch
+    plan = igatrim.Plan(cfg, igatrim.DWQ)
+    sz = plan.sizes
+    coef = plan.coeff()
+    vals = torch.empty((sz["band"], sz["n_act"]), dtype=torch.float64, device="cuda")
+    ms_full = _timed(lambda: plan.mass_form(coef, out=vals, full=True, stream=stream), args.steps, args.warmup, sync)
+    ms_form = _timed(lambda: plan.mass_form(coef, out=vals, stream=stream), args.steps, 2, sync)
+    plan.status()
+    return {"value": sz["nnz"] / (ms_full * 1e-3), "unit": "nnz/s", "ms_per_step": ms_full,
+            "formation_only_ms": ms_form, "formation_only_value": sz["nnz"] / (ms_form * 1e-3),
+            "n_dwq_rows": sz["n_dwq_rows"], "n_cut_fn": sz["n_cut_fn"],
+            "note": "same workload and step as the headline, cut rows by DWQ boxes + element rules"}
+
+
+def bench_batched(igatrim, wl, args, sync):
+    """256 patches (p 2..5, 16..256 elements per direction, one ellipse each): batched vs one by one."""
+    import torch
+    cfgs = wl.config4(n_patch=args.batch)
+    t0 = time.perf_counter()
+    plans = [igatrim.Plan(c, igatrim.HYBRID_GAUSS) for c in cfgs]
+    t_plan = time.perf_counter() - t0
+    coeffs = [p.coeff() for p in plans]
+    nnz = sum(p.sizes["nnz"] for p in plans)
+    b = igatrim.Batch(plans, coeffs)
+    tune_ms = b.autotune()
+    steps = max(5, args.steps // 2)
+    ms_graph = _timed(lambda: b.form(use_graph=True), steps, 2, sync)
+    ms_eager = _timed(lambda: b.form(use_graph=False), steps, 2, sync)
+    b.status()
+    outs = b.outs
+
+    def plain():
+        for p, c, o in zip(plans, coeffs, outs):
+            p.mass_form(c, out=o)
+
+    ms_plain = _timed(plain, max(3, steps // 2), 1, sync)
+    info = b.info()
+    return {"value": nnz / (ms_graph * 1e-3), "unit": "nnz/s", "ms": ms_graph, "eager_ms": ms_eager,
+            "plain_ms": ms_plain, "plain_value": nnz / (ms_plain * 1e-3), "speedup_vs_plain": ms_plain / ms_graph,
+            "patches": len(plans), "nnz": nnz, "items": info["n_items"], "grid": info["grid"],
+            "wg_per_cu": info["wg_per_cu"], "chunk": info["chunk"],
+            "order": ["cost-sorted", "patch by patch"][info["order"]],
+            "autotune_best_ms": tune_ms, "plan_setup_s": round(t_plan, 2),
+            "note": "formation over resident tables, one persistent launch per call (graph replay) vs one "
+                    "formation call per patch"}
+
+
+def bench_adjoint(igatrim, wl, args, sync):
+    """Matrix-free y = M(c) u and its adjoint on the 1024^2 workload, against plain formation there."""
+    import torch
+    cfg = wl.config5(N=args.mf_N)
+    plan = igatrim.Plan(cfg, igatrim.HYBRID_GAUSS)
+    sz = plan.sizes
+    pts = plan.points()
+    c = wl.config5_coef(pts[:, 0], pts[:, 1], torch).contiguous()
+    u_np, f_np = wl.config5_vectors(sz["n_act"])
+    u = torch.as_tensor(u_np, device="cuda")
+    gy = torch.as_tensor(f_np, device="cuda")
+    steps = max(5, args.steps // 2)
+    ms_fwd = _timed(lambda: igatrim.mf_apply(plan, c, u), steps, 2, sync)
+    ms_bwd = _timed(lambda: igatrim.mf_adjoint(plan, c, u, gy), steps, 2, sync)
+    coef = plan.coeff(igatrim.COEF_AT_POINTS, c_points=c)
+    vals = torch.empty((sz["band"], sz["n_act"]), dtype=torch.float64, device="cuda")
+    ms_form = _timed(lambda: plan.mass_form(coef, out=vals), steps, 2, sync)
+    nnz = sz["nnz"]
+    return {"forward_ms": ms_fwd, "backward_ms": ms_bwd, "plain_formation_ms": ms_form,
+            "forward_value": nnz / (ms_fwd * 1e-3), "backward_value": nnz / (ms_bwd * 1e-3),
+            "plain_value": nnz / (ms_form * 1e-3), "unit": "nnz-equivalent/s", "nnz": nnz,
+            "n_act": sz["n_act"], "n_points": sz["n_points"],
+            "note": f"p=4, {args.mf_N}^2 elements, c at every rule point; y = M(c)u and (dL/du, dL/dc)"}
 
 
 if __name__ == "__main__":

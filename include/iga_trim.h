@@ -242,14 +242,16 @@ typedef struct iga_batch_stats {
     int32_t wg_per_cu;    /* workgroups per compute unit (autotuned)    */
     int32_t order;        /* 0: cost-sorted queue, 1: patch by patch    */
     int32_t graph_ready;  /* a recorded graph is cached                 */
+    int32_t chunk;        /* queue items reserved per atomic (autotuned) */
+    int32_t reserved;
 } iga_batch_stats;
 int iga_batch_create(iga_plan* const* plans, int32_t count, const iga_coeff* cs, double* const* vals,
                      iga_batch** out);
 void iga_batch_destroy(iga_batch* batch);
 /* Enqueues the batched formation on stream (graph replay with use_graph). */
 int iga_batch_form(iga_batch* batch, int32_t use_graph, void* stream);
-/* Autotuner: times the persistent grid (1..4 workgroups per compute unit)
- * and the two queue orders on the device (3 timed runs each, stream
+/* Autotuner: times the persistent grid (1..4 workgroups per compute unit),
+ * the queue chunk (4, 16, 64 items per atomic) and the two queue orders on the device (3 timed runs each, stream
  * synchronised), keeps the fastest and drops a cached graph; *best_ms
  * (may be NULL) receives its time. */
 int iga_batch_autotune(iga_batch* batch, void* stream, float* best_ms);

@@ -9,10 +9,15 @@
 // degree. A fixed grid of workgroups, split over the degrees in proportion
 // to their work, takes items from its degree's queue head (one atomic add
 // each; the degree is fixed per workgroup, so each body is compiled for its
-// degree and the kernel's registers are those of the largest body); an item
-// that needs another kind's results of its own patch waits on that patch's
-// completion counter, which only ever refers to items taken earlier, so the
-// waits always end. Each wait is bounded all the same: past the bound the
+// degree and the kernel's registers are those of the largest body).
+// Dependencies go by level (0: coefficients, 1: cut elements, 2: rows): a
+// workgroup counts the items it finished at each level and publishes the
+// counts (one agent-scope release, i.e. one L2 write-back) only when it takes
+// its first item of a later level or runs out of items; before running an
+// item of level l it waits (agent-scope acquire) until its degree's items of
+// all lower levels are published. Every item of a lower level sits earlier in
+// the queue and is held by a workgroup that publishes before it waits, so the
+// waits always end; each is bounded all the same, and past the bound the
 // item proceeds and the batch status records the timeout.
 //
 // A batch object keeps the descriptors, the item list, the counters and,
@@ -51,12 +56,16 @@ struct BatchDev {
     const BatchPlan* plans;
     const BatchItem* items;  // queue g holds items[off[g] .. off[g] + n[g])
     int* heads;              // [kBatchGroups] queue heads
-    int* done;               // [n_plans][BK_NKIND] finished items
+    int* level_done;         // [kBatchGroups][2] published items of levels 0 and 1
     int* status;             // 1: a dependency wait hit its bound
     int spin_limit;
+    int chunk;                          // consecutive items reserved per queue-head atomic
     int first_block[kBatchGroups + 1];  // workgroups [first_block[g], first_block[g+1]) serve degree g+1
     int off[kBatchGroups], n[kBatchGroups];
+    int n_level[kBatchGroups][2];       // items of levels 0 and 1 per queue
 };
+
+__device__ __forceinline__ int item_level(int kind) { return kind == BK_COEF ? 0 : (kind == BK_CUTE ? 1 : 2); }
 
 template <int P>
 struct BatchSmemSize {
@@ -102,56 +111,79 @@ __device__ __forceinline__ void run_item(const BatchPlan& Bp, const BatchItem& i
     }
 }
 
-__global__ void k_batch_reset(int* heads, int n_heads, int* done, int n_done) {
+__global__ void k_batch_reset(int* counters, int n) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t < n_heads) heads[t] = 0;
-    if (t < n_done) done[t] = 0;
+    if (t < n) counters[t] = 0;
+}
+
+// Thread 0 of the workgroup: publish the finished lower-level items (release; every wave of
+// the workgroup has fenced its own stores before), then, unless the workgroup is leaving
+// (level 3), wait for the queue's lower levels to be complete (acquire).
+__device__ __forceinline__ void publish_and_wait(const BatchDev& B, int g, int level, int* pend) {
+    int* ld = B.level_done + 2 * g;
+    for (int l = 0; l < 2; ++l)
+        if (pend[l]) {
+            __hip_atomic_fetch_add(ld + l, pend[l], __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            pend[l] = 0;
+        }
+    if (level > 2 || __hip_atomic_load(B.status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return;
+    bool ok = true;
+    for (int l = 0; l < level && ok; ++l) ok = wait_count(ld + l, B.n_level[g][l], B.spin_limit);
+    if (!ok) atomicExch(B.status, 1);
 }
 
 template <int P>
-__device__ __forceinline__ void batch_loop(const BatchDev& B, int g, unsigned char* smem, int* s_idx) {
+__device__ __forceinline__ void batch_loop(const BatchDev& B, int g, unsigned char* smem, int* s_sh) {
     const BatchItem* items = B.items + B.off[g];
     const int n = B.n[g];
+    int cur = 0;             // level of the items run so far (uniform)
+    int pend[2] = {0, 0};    // finished, unpublished items of levels 0 and 1 (thread 0)
+    int next = 0, stop = 0;  // reserved range of the queue (thread 0)
     for (;;) {
-        __syncthreads();  // the previous item is done with LDS and s_idx
-        if (threadIdx.x == 0) *s_idx = atomicAdd(B.heads + g, 1);
+        __syncthreads();  // the previous item is done with LDS and the shared slots
+        if (threadIdx.x == 0) {
+            if (next >= stop) {  // reserve the next chunk: queue order is kept, one atomic per chunk
+                next = atomicAdd(B.heads + g, B.chunk);
+                stop = next + B.chunk;
+            }
+            const int idx = next < n ? next++ : n;
+            const int lvl = (idx < n) ? item_level(items[idx].kind) : 3;
+            s_sh[0] = idx;
+            s_sh[1] = lvl;
+            s_sh[2] = (lvl > cur) && (pend[0] + pend[1] > 0);
+        }
         __syncthreads();
-        const int idx = __builtin_amdgcn_readfirstlane(*s_idx);
+        const int idx = __builtin_amdgcn_readfirstlane(s_sh[0]);
+        const int lvl = __builtin_amdgcn_readfirstlane(s_sh[1]);
+        if (lvl > cur) {
+            if (s_sh[2]) __threadfence();   // this wave's stores of the finished items, at agent scope
+            __syncthreads();
+            if (threadIdx.x == 0) publish_and_wait(B, g, lvl, pend);
+            __syncthreads();
+            cur = lvl;
+        }
         if (idx >= n) break;
         BatchItem it = items[idx];
         it.plan = __builtin_amdgcn_readfirstlane(it.plan);  // uniform: the descriptor is read once per wave
         it.kind = __builtin_amdgcn_readfirstlane(it.kind);
         it.unit = __builtin_amdgcn_readfirstlane(it.unit);
-        const BatchPlan& Bp = B.plans[it.plan];
-        // after a timed-out wait (status set) no item waits any more, so the launch always ends quickly
-        if (threadIdx.x == 0 && it.kind != BK_COEF &&
-            __hip_atomic_load(B.status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
-            int* d = B.done + (size_t)it.plan * BK_NKIND;
-            bool ok = wait_count(d + BK_COEF, Bp.need[BK_COEF], B.spin_limit);
-            if (it.kind == BK_CUTR) ok = wait_count(d + BK_CUTE, Bp.need[BK_CUTE], B.spin_limit) && ok;
-            if (!ok) atomicExch(B.status, 1);
-        }
-        __syncthreads();
-        run_item<P>(Bp, it, smem);
-        __syncthreads();  // every store of the item has reached L2
-        if (threadIdx.x == 0)
-            __hip_atomic_fetch_add(B.done + (size_t)it.plan * BK_NKIND + it.kind, 1, __ATOMIC_RELEASE,
-                                   __HIP_MEMORY_SCOPE_AGENT);
+        run_item<P>(B.plans[it.plan], it, smem);
+        if (threadIdx.x == 0 && lvl < 2) pend[lvl]++;
     }
 }
 
 __global__ void __launch_bounds__(256) k_batch(BatchDev B) {
     __shared__ __align__(16) unsigned char smem[batch_smem_max<kBatchMaxP>()];
-    __shared__ int s_idx;
+    __shared__ int s_sh[3];
     int g = 0;
     while (g < kBatchGroups - 1 && (int)blockIdx.x >= B.first_block[g + 1]) ++g;
     switch (g + 1) {
-        case 1: batch_loop<1>(B, g, smem, &s_idx); break;
-        case 2: batch_loop<2>(B, g, smem, &s_idx); break;
-        case 3: batch_loop<3>(B, g, smem, &s_idx); break;
-        case 4: batch_loop<4>(B, g, smem, &s_idx); break;
-        case 5: batch_loop<5>(B, g, smem, &s_idx); break;
-        case 6: batch_loop<6>(B, g, smem, &s_idx); break;
+        case 1: batch_loop<1>(B, g, smem, s_sh); break;
+        case 2: batch_loop<2>(B, g, smem, s_sh); break;
+        case 3: batch_loop<3>(B, g, smem, s_sh); break;
+        case 4: batch_loop<4>(B, g, smem, s_sh); break;
+        case 5: batch_loop<5>(B, g, smem, s_sh); break;
+        case 6: batch_loop<6>(B, g, smem, s_sh); break;
         default: break;
     }
 }
@@ -162,15 +194,16 @@ struct Batch {
     std::vector<iga_coeff> coeffs;
     std::vector<double*> outs;
     std::vector<BatchItem> items_lpt, items_plan;  // two queue orders, grouped by degree
-    int g_off[kBatchGroups] = {}, g_n[kBatchGroups] = {};
+    int g_off[kBatchGroups] = {}, g_n[kBatchGroups] = {}, g_lvl[kBatchGroups][2] = {};
     double g_work[kBatchGroups] = {};
     BatchPlan* d_plans = nullptr;
     BatchItem* d_items = nullptr;
-    int* d_counters = nullptr;  // status, heads[kBatchGroups], done[]
+    int* d_counters = nullptr;  // status, heads[kBatchGroups], level counters[kBatchGroups][2]
     int n_items = 0;
     int n_cu = 256;
     int wg_per_cu = 2;
     int order = 0;  // 0 cost-sorted, 1 patch by patch
+    int chunk = 16; // queue items reserved per atomic
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     hipStream_t cap_stream = nullptr;
@@ -215,23 +248,23 @@ struct Batch {
         return std::max(1, total);
     }
     void launch(hipStream_t s) {
-        const int nd = (int)plans.size() * BK_NKIND;
-        int* heads = d_counters + 1;
-        int* done = d_counters + 1 + kBatchGroups;
-        hipLaunchKernelGGL(k_batch_reset, dim3((std::max(nd, kBatchGroups) + 255) / 256), dim3(256), 0, s, heads,
-                           kBatchGroups, done, nd);
+        const int nc = 1 + 3 * kBatchGroups;  // status, heads, level counters
+        hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(64), 0, s, d_counters, nc);
         BatchDev B{};
         B.plans = d_plans;
         B.items = d_items;
-        B.heads = heads;
-        B.done = done;
         B.status = d_counters;
+        B.heads = d_counters + 1;
+        B.level_done = d_counters + 1 + kBatchGroups;
         B.spin_limit = 1 << 20;
+        B.chunk = chunk;
         int total = 0;
         split(B.first_block, total);
         for (int g = 0; g < kBatchGroups; ++g) {
             B.off[g] = g_off[g];
             B.n[g] = g_n[g];
+            B.n_level[g][0] = g_lvl[g][0];
+            B.n_level[g][1] = g_lvl[g][1];
         }
         if (total > 0) hipLaunchKernelGGL(k_batch, dim3(total), dim3(256), 0, s, B);
     }
@@ -323,6 +356,7 @@ static iga_batch* batch_create(iga_plan* const* plans, int count, const iga_coef
         const int g = deg(lpt[k]) - 1;
         if (B->g_n[g] == 0) B->g_off[g] = (int)k;
         B->g_n[g]++;
+        if (stage(lpt[k].it.kind) < 2) B->g_lvl[g][stage(lpt[k].it.kind)]++;
         B->g_work[g] += lpt[k].cost;
     }
     for (auto& c : lpt) B->items_lpt.push_back(c.it);
@@ -331,8 +365,8 @@ static iga_batch* batch_create(iga_plan* const* plans, int count, const iga_coef
     HIPX(hipMalloc(&B->d_plans, sizeof(BatchPlan) * count));
     HIPX(hipMemcpy(B->d_plans, hp.data(), sizeof(BatchPlan) * count, hipMemcpyHostToDevice));
     HIPX(hipMalloc(&B->d_items, sizeof(BatchItem) * std::max(1, B->n_items)));
-    HIPX(hipMalloc(&B->d_counters, sizeof(int) * (1 + kBatchGroups + (size_t)count * BK_NKIND)));
-    HIPX(hipMemset(B->d_counters, 0, sizeof(int) * (1 + kBatchGroups + (size_t)count * BK_NKIND)));
+    HIPX(hipMalloc(&B->d_counters, sizeof(int) * (1 + 3 * kBatchGroups)));
+    HIPX(hipMemset(B->d_counters, 0, sizeof(int) * (1 + 3 * kBatchGroups)));
     B->upload_items(B->cap_stream);
     return B.release();
 }
@@ -351,17 +385,20 @@ static void batch_form(Batch& B, int use_graph, hipStream_t s) {
     HIPX(hipGraphLaunch(B.exec, s));
 }
 
-// Times every (workgroups per CU, item order) pair on the device, keeps the fastest.
+// Times every (workgroups per CU, queue chunk, item order) choice on the device, keeps the fastest.
 static void batch_autotune(Batch& B, hipStream_t s, float* best_ms) {
     hipEvent_t a, b;
     HIPX(hipEventCreate(&a));
     HIPX(hipEventCreate(&b));
     float best = 1e30f;
     int bw = B.wg_per_cu, bo = B.order;
+    int bc = B.chunk;
     for (int order = 0; order < 2; ++order) {
         B.order = order;
         B.upload_items(s);
+        for (int cidx = 0; cidx < 3; ++cidx)
         for (int w = 1; w <= 4; ++w) {
+            B.chunk = (cidx == 0) ? 4 : (cidx == 1 ? 16 : 64);
             B.wg_per_cu = w;
             B.launch(s);  // warm-up
             float t = 1e30f;
@@ -378,6 +415,7 @@ static void batch_autotune(Batch& B, hipStream_t s, float* best_ms) {
                 best = t;
                 bw = w;
                 bo = order;
+                bc = B.chunk;
             }
         }
     }
@@ -385,6 +423,7 @@ static void batch_autotune(Batch& B, hipStream_t s, float* best_ms) {
     hipEventDestroy(b);
     B.wg_per_cu = bw;
     B.order = bo;
+    B.chunk = bc;
     B.upload_items(s);
     B.drop_graph();
     if (best_ms) *best_ms = best;
@@ -447,6 +486,7 @@ int iga_batch_info(const iga_batch* b, iga_batch_stats* st) {
     st->grid = b->grid();
     st->wg_per_cu = b->wg_per_cu;
     st->order = b->order;
+    st->chunk = b->chunk;
     st->graph_ready = b->exec != nullptr;
     API_CATCH
 }
