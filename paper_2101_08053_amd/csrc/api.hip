@@ -60,9 +60,9 @@ static void check_status(Plan& P, hipStream_t s) {
 // Set-up kernels in dependency order. With `discover`, device counts are read
 // back after each stage to size the next buffers (plan creation only).
 static void run_setup(Plan& P, hipStream_t s, bool discover) {
-    launch_gauss_table(P, s);
-    for (int d = 0; d < 2; ++d) launch_dir_tables(P, d, s);
-    for (int d = 0; d < 2; ++d) launch_wq_weights(P, d, s);
+    if (discover) launch_gauss_table(P, s);  // a constant table: once per plan
+    launch_dir_tables(P, s);
+    launch_wq_weights(P, s);
     launch_dwq_sides(P, s);
     TrimDev& T = P.trim;
     if (T.n_curves > 0) {

@@ -140,6 +140,36 @@ __device__ __forceinline__ void basis_eval_rt(const double* __restrict__ knots, 
     }
 }
 
+// ------------------------------------------------------------------ scans
+__device__ __forceinline__ int wave_incl_scan(int v, int lane) {
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        int u = __shfl_up(v, o, 64);
+        if (lane >= o) v += u;
+    }
+    return v;
+}
+
+// Exclusive scan of one value per thread over the block; returns the block total.
+__device__ __forceinline__ int block_excl_scan(int v, int* sh, int& total) {
+    int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    int nw = blockDim.x >> 6;
+    int inc = wave_incl_scan(v, lane);
+    if (lane == 63) sh[wid] = inc;
+    __syncthreads();
+    if (wid == 0) {
+        int t = (lane < nw) ? sh[lane] : 0;
+        int ti = wave_incl_scan(t, lane);
+        if (lane < nw) sh[lane] = ti - t;
+        if (lane == nw - 1) sh[nw] = ti;
+    }
+    __syncthreads();
+    int res = inc - v + sh[wid];
+    total = sh[nw];
+    __syncthreads();
+    return res;
+}
+
 // -------------------------------------------------------------------------
 // Minimum 2-norm solution of a small under-determined system A w = b on one
 // wavefront (Eq. (5) and its refined variants). Lane l holds row l of A^T

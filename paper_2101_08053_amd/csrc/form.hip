@@ -20,44 +20,40 @@
 namespace iga {
 
 // ------------------------------------------------------------ points
-__global__ void k_points_wq(DirDev D1, DirDev D2, double* __restrict__ xy) {
-    int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= D1.Q * D2.Q) return;
-    int k1 = k % D1.Q, k2 = k / D1.Q;
-    xy[2 * k] = D1.xq[k1];
-    xy[2 * k + 1] = D2.xq[k2];
-}
-
-__global__ void k_points_band(DirDev D1, DirDev D2, int p, const int* __restrict__ band_list, int n_band,
-                              double* __restrict__ xy) {
-    int t = blockIdx.x * blockDim.x + threadIdx.x;
-    int ng = (p + 1) * (p + 1);
-    if (t >= n_band * ng) return;
-    int b = t / ng, g = t % ng, g1 = g % (p + 1), g2 = g / (p + 1);
-    int e = band_list[b], e1 = e % D1.N, e2 = e / D1.N;
-    xy[2 * t] = D1.xg[e1 * (p + 1) + g1];
-    xy[2 * t + 1] = D2.xg[e2 * (p + 1) + g2];
-}
-
-__global__ void k_points_cut(const double* __restrict__ nx, const double* __restrict__ ny, int n,
-                             double* __restrict__ xy) {
-    int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= n) return;
-    xy[2 * t] = nx[t];
-    xy[2 * t + 1] = ny[t];
+// Coordinates of every rule point: the WQ grid, the band Gauss points, the cut nodes.
+__global__ void k_points(DirDev D1, DirDev D2, int p, const int* __restrict__ band_list, int nb,
+                         const double* __restrict__ nx, const double* __restrict__ ny, int nn,
+                         double* __restrict__ xy) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t nq = (int64_t)D1.Q * D2.Q;
+    double x, y;
+    if (t < nq) {
+        x = D1.xq[t % D1.Q];
+        y = D2.xq[t / D1.Q];
+    } else if (t < nq + nb) {
+        const int ng = (p + 1) * (p + 1);
+        const int u = (int)(t - nq), b = u / ng, g = u % ng, g1 = g % (p + 1), g2 = g / (p + 1);
+        const int e = band_list[b], e1 = e % D1.N, e2 = e / D1.N;
+        x = D1.xg[e1 * (p + 1) + g1];
+        y = D2.xg[e2 * (p + 1) + g2];
+    } else if (t < nq + nb + nn) {
+        const int u = (int)(t - nq - nb);
+        x = nx[u];
+        y = ny[u];
+    } else {
+        return;
+    }
+    xy[2 * t] = x;
+    xy[2 * t + 1] = y;
 }
 
 void launch_points(Plan& P, hipStream_t s) {
     DirDev &D1 = P.dir[0], &D2 = P.dir[1];
-    int nq = D1.Q * D2.Q;
-    hipLaunchKernelGGL(k_points_wq, dim3((nq + 255) / 256), dim3(256), 0, s, D1, D2, P.pts_xy);
-    int nb = (int)P.n_band * (P.p + 1) * (P.p + 1);
-    if (nb > 0)
-        hipLaunchKernelGGL(k_points_band, dim3((nb + 255) / 256), dim3(256), 0, s, D1, D2, P.p, P.band_list,
-                           (int)P.n_band, P.pts_xy + 2 * (size_t)nq);
-    if (P.n_nodes > 0)
-        hipLaunchKernelGGL(k_points_cut, dim3((P.n_nodes + 255) / 256), dim3(256), 0, s, P.node_x, P.node_y,
-                           (int)P.n_nodes, P.pts_xy + 2 * ((size_t)nq + nb));
+    const int64_t nq = (int64_t)D1.Q * D2.Q;
+    const int nb = (int)P.n_band * (P.p + 1) * (P.p + 1);
+    const int64_t n = nq + nb + P.n_nodes;
+    hipLaunchKernelGGL(k_points, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, D1, D2, P.p, P.band_list, nb,
+                       P.node_x, P.node_y, (int)P.n_nodes, P.pts_xy);
 }
 
 // ------------------------------------------------------- coefficient

@@ -252,8 +252,8 @@ __device__ __forceinline__ double detj_local(const double* __restrict__ cp, int 
 // ---------------------------------------------------------------- launchers
 // setup.hip
 void launch_gauss_table(Plan& P, hipStream_t s);
-void launch_dir_tables(Plan& P, int d, hipStream_t s);
-void launch_wq_weights(Plan& P, int d, hipStream_t s);
+void launch_dir_tables(Plan& P, hipStream_t s);
+void launch_wq_weights(Plan& P, hipStream_t s);
 void launch_wb_table(Plan& P, int d, hipStream_t s);
 // scan.hip
 void exclusive_scan(const int* in, int* out, int n, int* tmp, hipStream_t s);

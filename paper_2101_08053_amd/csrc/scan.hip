@@ -10,35 +10,6 @@ constexpr int kScanThreads = 256;
 constexpr int kScanItems = 4;
 constexpr int kScanTile = kScanThreads * kScanItems;
 
-__device__ __forceinline__ int wave_incl_scan(int v, int lane) {
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        int u = __shfl_up(v, o, 64);
-        if (lane >= o) v += u;
-    }
-    return v;
-}
-
-// Exclusive scan of one value per thread over the block; returns the block total.
-__device__ int block_excl_scan(int v, int* sh, int& total) {
-    int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    int nw = blockDim.x >> 6;
-    int inc = wave_incl_scan(v, lane);
-    if (lane == 63) sh[wid] = inc;
-    __syncthreads();
-    if (wid == 0) {
-        int t = (lane < nw) ? sh[lane] : 0;
-        int ti = wave_incl_scan(t, lane);
-        if (lane < nw) sh[lane] = ti - t;
-        if (lane == nw - 1) sh[nw] = ti;
-    }
-    __syncthreads();
-    int res = inc - v + sh[wid];
-    total = sh[nw];
-    __syncthreads();
-    return res;
-}
-
 __global__ void __launch_bounds__(kScanThreads) k_scan_tiles(const int* __restrict__ in, int* __restrict__ out,
                                                              int n, int* __restrict__ bsum) {
     __shared__ int sh[kScanThreads / 64 + 1];
@@ -82,8 +53,36 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_add(int* __restrict__ out
         if (base + j < n) out[base + j] += add;
 }
 
+// One workgroup for short arrays: chunks of 4096 with a running carry.
+__global__ void __launch_bounds__(1024) k_scan_single(const int* __restrict__ in, int* __restrict__ out, int n) {
+    __shared__ int sh[1024 / 64 + 1];
+    int carry = 0;
+    for (int base = 0; base < n; base += 4096) {
+        const int i0 = base + threadIdx.x * 4;
+        int v[4], s = 0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            v[j] = (i0 + j < n) ? in[i0 + j] : 0;
+            s += v[j];
+        }
+        int total;
+        int ex = block_excl_scan(s, sh, total) + carry;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            if (i0 + j < n) out[i0 + j] = ex;
+            ex += v[j];
+        }
+        carry += total;
+    }
+    if (threadIdx.x == 0) out[n] = carry;
+}
+
 // tmp must hold ceil(n / 1024) + 1 ints.
 void exclusive_scan(const int* in, int* out, int n, int* tmp, hipStream_t s) {
+    if (n <= 16384) {
+        hipLaunchKernelGGL(k_scan_single, dim3(1), dim3(1024), 0, s, in, out, n);
+        return;
+    }
     int nb = (n + kScanTile - 1) / kScanTile;
     if (nb == 0) nb = 1;
     hipLaunchKernelGGL(k_scan_tiles, dim3(nb), dim3(kScanThreads), 0, s, in, out, n, tmp);

@@ -41,127 +41,188 @@ void launch_gauss_table(Plan& P, hipStream_t s) {
     hipLaunchKernelGGL(k_gauss_table, dim3((tot + 255) / 256), dim3(256), 0, s, P.gauss_x, P.gauss_w);
 }
 
-// ------------------------------------------------------- WQ point layout
-// p+1 points in the first and last element, 2 elsewhere, uniformly inside
-// each element (never on a knot).
-__global__ void k_layout(DirDev D, int p) {
-    int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e > D.N) return;
-    D.bp[e] = D.knots[p + e];
-    if (e == D.N) {
-        D.pt0[D.N] = wq_pt0(D.N, D.N, p);
+// ------------------------------------------------------- direction tables
+// Both directions in one launch. Per direction the thread range covers the
+// breakpoints and first-point offsets (N+1), the WQ points with their basis
+// values and derivatives (Q; p+1 points in the first and last element, 2
+// elsewhere, uniformly inside each element, never on a knot) and the (p+1)
+// Gauss points of every element with theirs.
+template <int P>
+__device__ __forceinline__ void dir_table_entry(const DirDev& D, int t, const double* __restrict__ gx,
+                                                const double* __restrict__ gw) {
+    const int N = D.N;
+    if (t <= N) {
+        D.bp[t] = D.knots[P + t];
+        D.pt0[t] = wq_pt0(t, N, P);
         return;
     }
-    int ne = (e == 0 || e == D.N - 1) ? p + 1 : 2;
-    int off = wq_pt0(e, D.N, p);
-    D.pt0[e] = off;
-    double a = D.knots[p + e], b = D.knots[p + e + 1];
-    for (int k = 1; k <= ne; ++k) {
-        D.xq[off + k - 1] = a + (b - a) * k / (ne + 1);
-        D.eq[off + k - 1] = e;
+    t -= N + 1;
+    if (t < D.Q) {
+        // element of point t: inverse of wq_pt0
+        int e;
+        if (N == 1 || t < P + 1) e = 0;
+        else if (t >= D.Q - (P + 1)) e = N - 1;
+        else e = 1 + (t - (P + 1)) / 2;
+        const int ne = (e == 0 || e == N - 1) ? P + 1 : 2;
+        const int k = t - wq_pt0(e, N, P) + 1;
+        const double a = D.knots[P + e], b = D.knots[P + e + 1];
+        const double x = a + (b - a) * k / (ne + 1);
+        D.xq[t] = x;
+        D.eq[t] = e;
+        double Nv[P + 1], dN[P + 1];
+        basis_eval_d<P>(D.knots, P + e, x, Nv, dN);
+#pragma unroll
+        for (int c = 0; c <= P; ++c) {
+            D.Bq[(size_t)t * (P + 1) + c] = Nv[c];
+            D.dBq[(size_t)t * (P + 1) + c] = dN[c];
+        }
+        return;
+    }
+    t -= D.Q;
+    if (t < N * (P + 1)) {
+        const int e = t / (P + 1), g = t % (P + 1);
+        const double a = D.knots[P + e], b = D.knots[P + e + 1];
+        const double x = a + (b - a) * (gx[gauss_off(P + 1) + g] + 1.0) * 0.5;
+        D.xg[t] = x;
+        D.wg[t] = gw[gauss_off(P + 1) + g] * (b - a) * 0.5;
+        double Nv[P + 1], dN[P + 1];
+        basis_eval_d<P>(D.knots, P + e, x, Nv, dN);
+#pragma unroll
+        for (int c = 0; c <= P; ++c) {
+            D.Bg[(size_t)t * (P + 1) + c] = Nv[c];
+            D.dBg[(size_t)t * (P + 1) + c] = dN[c];
+        }
     }
 }
 
-__global__ void k_basis_points(DirDev D, int p) {
-    int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= D.Q) return;
-    int e = D.eq[k];
-    double N[IGA_MAXP + 1], dN[IGA_MAXP + 1];
-    basis_eval_rt(D.knots, p, p + e, D.xq[k], N, dN);
-    for (int a = 0; a <= p; ++a) {
-        D.Bq[k * (p + 1) + a] = N[a];
-        D.dBq[k * (p + 1) + a] = dN[a];
-    }
+__host__ __device__ inline int dir_table_count(const DirDev& D, int p) { return D.N + 1 + D.Q + D.N * (p + 1); }
+
+template <int P>
+__global__ void __launch_bounds__(256) k_dir_tables(DirDev D1, DirDev D2, const double* __restrict__ gx,
+                                                    const double* __restrict__ gw) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    const int n1 = dir_table_count(D1, P);
+    if (t < n1) dir_table_entry<P>(D1, t, gx, gw);
+    else if (t < n1 + dir_table_count(D2, P)) dir_table_entry<P>(D2, t - n1, gx, gw);
 }
 
-__global__ void k_gauss_dir(DirDev D, int p, const double* __restrict__ gx, const double* __restrict__ gw) {
-    int t = blockIdx.x * blockDim.x + threadIdx.x;
-    int ng = p + 1;
-    if (t >= D.N * ng) return;
-    int e = t / ng, g = t % ng;
-    double a = D.knots[p + e], b = D.knots[p + e + 1];
-    double x = a + (b - a) * (gx[gauss_off(ng) + g] + 1.0) * 0.5;
-    D.xg[t] = x;
-    D.wg[t] = gw[gauss_off(ng) + g] * (b - a) * 0.5;
-    double N[IGA_MAXP + 1], dN[IGA_MAXP + 1];
-    basis_eval_rt(D.knots, p, p + e, x, N, dN);
-    for (int c = 0; c <= p; ++c) {
-        D.Bg[t * ng + c] = N[c];
-        D.dBg[t * ng + c] = dN[c];
+void launch_dir_tables(Plan& P, hipStream_t s) {
+    const int n = dir_table_count(P.dir[0], P.p) + dir_table_count(P.dir[1], P.p);
+    dim3 g((n + 255) / 256), b(256);
+    switch (P.p) {
+#define CASE(PP) \
+    case PP: hipLaunchKernelGGL(k_dir_tables<PP>, g, b, 0, s, P.dir[0], P.dir[1], P.gauss_x, P.gauss_w); break;
+        CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
+#undef CASE
+        default: throw Error{IGA_E_UNSUPPORTED, "degree outside 1..8"};
     }
-}
-
-// Univariate mass band M1[i][j-i+p] = int B_i B_j, exact with p+1 Gauss points per element.
-__global__ void k_mass1d(DirDev D, int p) {
-    int t = blockIdx.x * blockDim.x + threadIdx.x;
-    int w = 2 * p + 1;
-    if (t >= D.n * w) return;
-    int i = t / w, j = i + t % w - p;
-    double s = 0.0;
-    if (j >= 0 && j < D.n) {
-        int elo = max(max(i, j) - p, 0), ehi = min(min(i, j), D.N - 1);
-        for (int e = elo; e <= ehi; ++e)
-            for (int g = 0; g <= p; ++g) {
-                int r = (e * (p + 1) + g) * (p + 1);
-                s += D.wg[e * (p + 1) + g] * D.Bg[r + i - e] * D.Bg[r + j - e];
-            }
-    }
-    D.M1[t] = s;
-}
-
-void launch_dir_tables(Plan& P, int d, hipStream_t s) {
-    DirDev& D = P.dir[d];
-    int p = P.p;
-    hipLaunchKernelGGL(k_layout, dim3((D.N + 1 + 127) / 128), dim3(128), 0, s, D, p);
-    hipLaunchKernelGGL(k_basis_points, dim3((D.Q + 127) / 128), dim3(128), 0, s, D, p);
-    hipLaunchKernelGGL(k_gauss_dir, dim3((D.N * (p + 1) + 127) / 128), dim3(128), 0, s, D, p, P.gauss_x,
-                       P.gauss_w);
-    hipLaunchKernelGGL(k_mass1d, dim3((D.n * (2 * p + 1) + 127) / 128), dim3(128), 0, s, D, p);
 }
 
 // ---------------------------------------------------------- WQ weights (5)
-// One wavefront per test function i. Lane l owns row l of A^T (point
-// k0 + l of supp B_i); A[j][k] = B_j(x_k) for the trial functions j with
-// |j - i| <= p. Householder QR of A^T = Q R gives the minimum-norm solution
-// w = Q R^{-T} b of A w = b, b_j = int B_j B_i.
+// One wavefront per test function i (both directions in one launch: blocks
+// [0, n1) direction 1, then direction 2). The band of the univariate mass
+// matrix, b_j = int B_j B_i (exact with p+1 Gauss points per element), is
+// summed over the wavefront's (element, Gauss point) pairs. Lane l owns
+// row l of A^T (point k0 + l of supp B_i), A[j][k] = B_j(x_k) for |j - i| <= p;
+// the minimum-norm solution of A w = b (Householder QR of A^T) is checked
+// by its residual, then written with the row's test-side factors
+// WB[i][q][b] = w_q B_{i+b-p}(x_q).
 template <int P>
-__global__ void __launch_bounds__(64) k_wq_weights(DirDev D, int* __restrict__ status) {
+__global__ void __launch_bounds__(64) k_wq_weights(DirDev D1, DirDev D2, const double* __restrict__ gx,
+                                                   const double* __restrict__ gw, int* __restrict__ status) {
     constexpr int M = 2 * P + 1;
     int i = blockIdx.x;
+    const bool second = i >= D1.n;
+    const DirDev& D = second ? D2 : D1;
+    if (second) i -= D1.n;
     if (i >= D.n) return;
-    int lane = threadIdx.x;
-    int elo = max(0, i - P), ehi = min(D.N - 1, i);
-    int k0 = D.pt0[elo], q = D.pt0[ehi + 1] - k0;
-    int jlo = max(0, i - P), jhi = min(D.n - 1, i + P);
-    int m = jhi - jlo + 1;
+    const int lane = threadIdx.x;
+    const int elo = max(0, i - P), ehi = min(D.N - 1, i);
+    const int k0 = wq_pt0(elo, D.N, P), q = wq_pt0(ehi + 1, D.N, P) - k0;
+    const int jlo = max(0, i - P), jhi = min(D.n - 1, i + P);
+    const int m = jhi - jlo + 1;
 
-    double a[M];
+    // univariate mass band of row i
+    double mom[M];
 #pragma unroll
-    for (int c = 0; c < M; ++c) a[c] = 0.0;
-    if (lane < q) {
-        int k = k0 + lane, e = D.eq[k];
+    for (int c = 0; c < M; ++c) mom[c] = 0.0;
+    for (int pg = lane; pg < (ehi - elo + 1) * (P + 1); pg += 64) {
+        const int e = elo + pg / (P + 1), g = pg % (P + 1);
+        const double a = D.knots[P + e], b = D.knots[P + e + 1];
+        const double x = a + (b - a) * (gx[gauss_off(P + 1) + g] + 1.0) * 0.5;
+        const double w = gw[gauss_off(P + 1) + g] * (b - a) * 0.5;
+        double Nv[P + 1];
+        basis_eval<P>(D.knots, P + e, x, Nv);
+        const double bi = w * Nv[i - e];
 #pragma unroll
         for (int c = 0; c < M; ++c) {
-            int j = jlo + c;
-            if (c < m && j >= e && j <= e + P) a[c] = D.Bq[k * (P + 1) + (j - e)];
+            const int j = i + c - P;
+            if (j >= e && j <= e + P) mom[c] += bi * Nv[j - e];
         }
     }
+#pragma unroll
+    for (int c = 0; c < M; ++c) mom[c] = wave_sum(mom[c]);
+    if (lane < M) {
+        double v = 0.0;
+#pragma unroll
+        for (int c = 0; c < M; ++c)
+            if (c == lane) v = mom[c];
+        D.M1[(size_t)i * M + lane] = v;
+    }
+
+    double a[M], a0[M];
+#pragma unroll
+    for (int c = 0; c < M; ++c) a[c] = 0.0;
+    int e_l = 0;
+    if (lane < q) {
+        const int k = k0 + lane;
+        e_l = D.eq[k];
+#pragma unroll
+        for (int c = 0; c < M; ++c) {
+            const int j = jlo + c;
+            if (c < m && j >= e_l && j <= e_l + P) a[c] = D.Bq[(size_t)k * (P + 1) + (j - e_l)];
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < M; ++c) a0[c] = a[c];
     bool singular = false;
-    double y = wave_min_norm<M>(a, q, m, [&](int c) { return D.M1[i * M + (jlo + c - i + P)]; }, singular);
+    const int off = jlo - i + P;  // band column of trial function jlo
+    const double y = wave_min_norm<M>(a, q, m, [&](int c) {
+        double v = 0.0;
+#pragma unroll
+        for (int cc = 0; cc < M; ++cc)
+            if (cc == c + off) v = mom[cc];
+        return v;
+    }, singular);
     // residual of Eq. (5)
     double rmax = 0.0, bmax = 0.0;
-    {
-        int k = k0 + lane, e = (lane < q) ? D.eq[k] : 0;
-        for (int c = 0; c < m; ++c) {
-            int j = jlo + c;
-            double ajk = (lane < q && j >= e && j <= e + P) ? D.Bq[k * (P + 1) + (j - e)] : 0.0;
-            double r = wave_sum(ajk * y);
-            double bc = D.M1[i * M + (j - i + P)];
-            rmax = fmax(rmax, fabs(r - bc));
-            bmax = fmax(bmax, fabs(bc));
+#pragma unroll
+    for (int c = 0; c < M; ++c) {
+        if (c >= m) break;
+        const double r = wave_sum(a0[c] * y);
+        double bc = 0.0;
+#pragma unroll
+        for (int cc = 0; cc < M; ++cc)
+            if (cc == c + off) bc = mom[cc];
+        rmax = fmax(rmax, fabs(r - bc));
+        bmax = fmax(bmax, fabs(bc));
+    }
+    if (lane < D.qmax) {
+        D.W[(size_t)i * D.qmax + lane] = y;
+        // WB row q = lane: w_q B_{i+b-p}(x_q), zero where B_{i+b-p} vanishes on the point's element
+        double* wb = D.WB + ((size_t)i * D.qmax + lane) * M;
+#pragma unroll
+        for (int bb = 0; bb < M; ++bb) {
+            const int j = i + bb - P;
+            double v = 0.0;
+            if (lane < q && j >= e_l && j <= e_l + P && j >= jlo && j <= jhi) {
+#pragma unroll
+                for (int c = 0; c < M; ++c)
+                    if (c == j - jlo) v = y * a0[c];
+            }
+            wb[bb] = v;
         }
     }
-    if (lane < D.qmax) D.W[(size_t)i * D.qmax + lane] = y;
     if (lane == 0 && (singular || !(rmax <= 1e-12 * bmax))) atomicExch(status, IGA_E_SINGULAR_WEIGHTS);
 }
 
@@ -187,17 +248,17 @@ void launch_wb_table(Plan& P, int d, hipStream_t s) {
     hipLaunchKernelGGL(k_wb_table, dim3((n + 255) / 256), dim3(256), 0, s, D, P.p);
 }
 
-void launch_wq_weights(Plan& P, int d, hipStream_t s) {
-    DirDev& D = P.dir[d];
-    dim3 g(D.n), b(64);
+void launch_wq_weights(Plan& P, hipStream_t s) {
+    dim3 g(P.dir[0].n + P.dir[1].n), b(64);
     switch (P.p) {
-#define CASE(PP) \
-    case PP: hipLaunchKernelGGL(k_wq_weights<PP>, g, b, 0, s, D, P.status); break;
+#define CASE(PP)                                                                                                 \
+    case PP:                                                                                                     \
+        hipLaunchKernelGGL(k_wq_weights<PP>, g, b, 0, s, P.dir[0], P.dir[1], P.gauss_x, P.gauss_w, P.status); \
+        break;
         CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
 #undef CASE
         default: throw Error{IGA_E_UNSUPPORTED, "degree outside 1..8"};
     }
-    launch_wb_table(P, d, s);
 }
 
 }  // namespace iga

@@ -631,45 +631,110 @@ void launch_trim_classes(Plan& P, hipStream_t s) {
 }
 
 // --------------------------------------------------------------- lists
-__global__ void k_compact(const int* __restrict__ flag, const int* __restrict__ pos, int n, int* __restrict__ map,
-                          int* __restrict__ list, const int* __restrict__ value_map) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    if (flag[i]) {
-        if (map) map[i] = pos[i];
-        if (list) list[pos[i]] = value_map ? value_map[i] : i;
-    } else if (map) {
-        map[i] = -1;
+// The four compactions of the classes -- active functions (act_of, fn_of),
+// rows formed element-wise (their compact ids), cut elements and band
+// elements (id map and list) -- in one pass of three launches: per-tile
+// counts of all four flag arrays, one scan of the tile counts, and per-tile
+// positions with the writes. Lists come out in increasing flat order.
+constexpr int kListTile = 1024;  // 256 threads x 4 items
+
+struct ListArgs {
+    const int* flag[4];  // f_active, f_cut (functions), e_cut, e_band (elements)
+    int n[4];
+    int* map[4];         // act_of, -, cut_id, band_id
+    int* list[4];        // fn_of, form_rows (compact ids), cut_list, band_list
+    int* bsum;           // [4][ntiles] tile counts, then tile offsets
+    int ntiles;
+    int* counts;         // [4] totals
+};
+
+__device__ __forceinline__ int block_sum256(int v, int* sh) {
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    if (lane == 0) sh[wid] = v;
+    __syncthreads();
+    const int tot = sh[0] + sh[1] + sh[2] + sh[3];
+    __syncthreads();
+    return tot;
+}
+
+__global__ void __launch_bounds__(256) k_list_count(ListArgs A) {
+    __shared__ int sh[4];
+    const int b = blockIdx.x, base = b * kListTile + threadIdx.x * 4;
+    int c[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+        c[a] = 0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) c[a] += (base + j < A.n[a]) ? (A.flag[a][base + j] != 0) : 0;
+    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+        const int tot = block_sum256(c[a], sh);
+        if (threadIdx.x == 0) A.bsum[a * A.ntiles + b] = tot;
+    }
+}
+
+__global__ void __launch_bounds__(1024) k_list_scan(ListArgs A) {
+    __shared__ int sh[1024 / 64 + 1];
+    for (int a = 0; a < 4; ++a) {
+        int carry = 0;
+        for (int base = 0; base < A.ntiles; base += 1024) {
+            const int idx = base + threadIdx.x;
+            const int v = (idx < A.ntiles) ? A.bsum[a * A.ntiles + idx] : 0;
+            int total;
+            const int ex = block_excl_scan(v, sh, total);
+            if (idx < A.ntiles) A.bsum[a * A.ntiles + idx] = ex + carry;
+            carry += total;
+        }
+        if (threadIdx.x == 0) A.counts[a] = carry;
+    }
+}
+
+__global__ void __launch_bounds__(256) k_list_write(ListArgs A) {
+    __shared__ int sh[256 / 64 + 1];
+    const int b = blockIdx.x, base = b * kListTile + threadIdx.x * 4;
+    int fl[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) fl[a][j] = (base + j < A.n[a]) ? (A.flag[a][base + j] != 0) : 0;
+    int actpos[4] = {0, 0, 0, 0};
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+        const int v = fl[a][0] + fl[a][1] + fl[a][2] + fl[a][3];
+        int total;
+        int pos = block_excl_scan(v, sh, total) + A.bsum[a * A.ntiles + b];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int i = base + j;
+            if (i >= A.n[a]) continue;
+            if (a == 0) actpos[j] = pos;
+            if (A.map[a]) A.map[a][i] = fl[a][j] ? pos : -1;
+            if (fl[a][j]) A.list[a][pos] = (a == 1) ? actpos[j] : i;
+            pos += fl[a][j];
+        }
     }
 }
 
 void launch_trim_lists(Plan& P, hipStream_t s) {
-    int nf = P.n1 * P.n2, ne = P.N1 * P.N2;
+    const int nf = P.n1 * P.n2, ne = P.N1 * P.N2;
     int* f_active = P.flags;
     int* f_cut = P.flags + (nf + 1);
     int* e_cut = P.flags + 2 * (nf + 1);
     int* e_band = e_cut + (ne + 1);
-    int* pos = P.scan_tmp + P.scan_pos_off;  // scratch region after the block sums
-    // active functions
-    exclusive_scan(f_active, pos, nf, P.scan_tmp, s);
-    hipLaunchKernelGGL(k_compact, dim3((nf + 127) / 128), dim3(128), 0, s, f_active, pos, nf, P.act_of, P.fn_of,
-                       (const int*)nullptr);
-    hipMemcpyAsync(P.counts + 0, pos + nf, sizeof(int), hipMemcpyDeviceToDevice, s);
-    // rows formed element-wise (compact ids)
-    exclusive_scan(f_cut, pos, nf, P.scan_tmp, s);
-    hipLaunchKernelGGL(k_compact, dim3((nf + 127) / 128), dim3(128), 0, s, f_cut, pos, nf, (int*)nullptr, P.form_rows,
-                       (const int*)P.act_of);
-    hipMemcpyAsync(P.counts + 1, pos + nf, sizeof(int), hipMemcpyDeviceToDevice, s);
-    // cut elements
-    exclusive_scan(e_cut, pos, ne, P.scan_tmp, s);
-    hipLaunchKernelGGL(k_compact, dim3((ne + 127) / 128), dim3(128), 0, s, e_cut, pos, ne, P.cut_id, P.cut_list,
-                       (const int*)nullptr);
-    hipMemcpyAsync(P.counts + 2, pos + ne, sizeof(int), hipMemcpyDeviceToDevice, s);
-    // band elements
-    exclusive_scan(e_band, pos, ne, P.scan_tmp, s);
-    hipLaunchKernelGGL(k_compact, dim3((ne + 127) / 128), dim3(128), 0, s, e_band, pos, ne, P.band_id, P.band_list,
-                       (const int*)nullptr);
-    hipMemcpyAsync(P.counts + 3, pos + ne, sizeof(int), hipMemcpyDeviceToDevice, s);
+    ListArgs A;
+    A.flag[0] = f_active; A.flag[1] = f_cut; A.flag[2] = e_cut; A.flag[3] = e_band;
+    A.n[0] = nf; A.n[1] = nf; A.n[2] = ne; A.n[3] = ne;
+    A.map[0] = P.act_of; A.map[1] = nullptr; A.map[2] = P.cut_id; A.map[3] = P.band_id;
+    A.list[0] = P.fn_of; A.list[1] = P.form_rows; A.list[2] = P.cut_list; A.list[3] = P.band_list;
+    A.ntiles = (std::max(nf, ne) + kListTile - 1) / kListTile;
+    A.bsum = P.scan_tmp + P.scan_pos_off;  // 4 * ntiles <= the position region
+    A.counts = P.counts;
+    hipLaunchKernelGGL(k_list_count, dim3(A.ntiles), dim3(256), 0, s, A);
+    hipLaunchKernelGGL(k_list_scan, dim3(1), dim3(1024), 0, s, A);
+    hipLaunchKernelGGL(k_list_write, dim3(A.ntiles), dim3(256), 0, s, A);
 }
 
 // ------------------------------------------------------ arcs per element
@@ -706,6 +771,14 @@ __global__ void k_arc_sort(int n_cut, const int* __restrict__ off, int* __restri
 __global__ void k_zero_int(int* p, int n) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = 0;
+}
+
+__global__ void k_zero_int2(int* a, int* b, int n) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) {
+        a[i] = 0;
+        b[i] = 0;
+    }
 }
 
 struct CutArgs {
@@ -856,8 +929,7 @@ void launch_trim_cutprep(Plan& P, hipStream_t s) {
     int nc = (int)P.n_cut_el;
     if (T.n_curves == 0 || nc == 0) return;
     GridDev G{P.dir[0].bp, P.dir[1].bp, P.N1, P.N2};
-    hipLaunchKernelGGL(k_zero_int, dim3((nc + 1 + 127) / 128), dim3(128), 0, s, P.arc_cnt, nc + 1);
-    hipLaunchKernelGGL(k_zero_int, dim3((nc + 1 + 127) / 128), dim3(128), 0, s, P.arc_fill, nc + 1);
+    hipLaunchKernelGGL(k_zero_int2, dim3((nc + 1 + 127) / 128), dim3(128), 0, s, P.arc_cnt, P.arc_fill, nc + 1);
     hipLaunchKernelGGL(k_arc_count, dim3((T.cap_arcs + 127) / 128), dim3(128), 0, s, T, P.N1, P.cut_id, P.arc_cnt);
     exclusive_scan(P.arc_cnt, P.arc_off, nc, P.scan_tmp, s);
     hipLaunchKernelGGL(k_arc_fill, dim3((T.cap_arcs + 127) / 128), dim3(128), 0, s, T, P.N1, P.cut_id, P.arc_off,
