@@ -18,6 +18,9 @@ void set_error(const std::string& msg) { g_last_error = msg; }
 
 Plan::~Plan() {
     if (sw.h_scal) hipHostFree(sw.h_scal);
+    for (hipEvent_t e : {ev_fork, ev_tables, ev_lists, ev_interior})
+        if (e) hipEventDestroy(e);
+    if (aux) hipStreamDestroy(aux);
     for (auto& e : ev_pool) hipEventDestroy(e);
     for (void* ptr : allocations) hipFree(ptr);
 }
@@ -59,16 +62,30 @@ static void check_status(Plan& P, hipStream_t s) {
 
 // Set-up kernels in dependency order. With `discover`, device counts are read
 // back after each stage to size the next buffers (plan creation only).
-static void run_setup(Plan& P, hipStream_t s, bool discover) {
-    if (discover) launch_gauss_table(P, s);  // a constant table: once per plan
+// Univariate tables, weighted-quadrature weights (and DWQ side rules): they
+// depend on the knots only.
+static void setup_tables(Plan& P, hipStream_t s) {
     launch_dir_tables(P, s);
     launch_wq_weights(P, s);
     launch_dwq_sides(P, s);
+}
+
+// Trimming, classes, lists, cut rules and rule points. `tables_ready`, if
+// given, is waited for before the first kernel that reads the univariate
+// tables (the rule points); the trimming reads the knots directly.
+static void setup_trim(Plan& P, hipStream_t s, bool discover, hipEvent_t tables_ready);
+
+static void run_setup(Plan& P, hipStream_t s, bool discover) {
+    if (discover) launch_gauss_table(P, s);  // a constant table: once per plan
+    setup_tables(P, s);
+    setup_trim(P, s, discover, nullptr);
+}
+
+static void setup_trim(Plan& P, hipStream_t s, bool discover, hipEvent_t tables_ready) {
+    ++P.epoch;
     TrimDev& T = P.trim;
     if (T.n_curves > 0) {
         launch_trim_curves(P, s);
-        launch_orientation(P, s);
-        launch_trim_crossings(P, s);
         if (discover) {
             int np = d2h1(T.n_pieces, s);
             std::vector<int> off(1);
@@ -84,6 +101,7 @@ static void run_setup(Plan& P, hipStream_t s, bool discover) {
     }
     launch_trim_classes(P, s);
     launch_trim_lists(P, s);
+    HIPX(hipEventRecord(P.ev_lists, s));  // classes and compact maps are ready
     if (discover) {
         int c[4];
         HIPX(hipMemcpyAsync(c, P.counts, 4 * sizeof(int), hipMemcpyDeviceToHost, s));
@@ -124,6 +142,7 @@ static void run_setup(Plan& P, hipStream_t s, bool discover) {
         if (P.method == IGA_NAIVE_WQ) P.c_wq_masked = P.alloc<double>(nq);
     }
     launch_trim_nodes(P, s);
+    if (tables_ready) HIPX(hipStreamWaitEvent(s, tables_ready, 0));
     launch_points(P, s);
     if (discover) {
         check_status(P, s);
@@ -166,7 +185,8 @@ struct PhaseTimer {
     }
 };
 
-static void form(Plan& P, const iga_coeff& c, double* vals, int flags, hipStream_t s) {
+// Naive weighted quadrature masks c with the trimming: formed on one stream.
+static void form_serial(Plan& P, const iga_coeff& c, double* vals, int flags, hipStream_t s) {
     if (flags & IGA_FORM_FULL) {
         PhaseTimer t(P, s, IGA_PHASE_SETUP);
         run_setup(P, s, false);
@@ -189,6 +209,48 @@ static void form(Plan& P, const iga_coeff& c, double* vals, int flags, hipStream
         launch_cut_rows(P, c, vals, s);
         launch_dwq_rows(P, c, vals, s);
     }
+}
+
+// Two streams: the caller's stream s carries the trimming chain, the cut
+// rules, the band/cut coefficients and the cut rows; the plan's second
+// stream carries the univariate tables and weights, the WQ-grid coefficient
+// and the interior rows (after the compact maps exist). Both start after the
+// work already queued on s and are joined back into s. Phase timers: SETUP
+// and CUT on s, COEF (WQ grid) and INTERIOR on the second stream (they overlap).
+static void form(Plan& P, const iga_coeff& c, double* vals, int flags, hipStream_t s) {
+    if (P.method == IGA_NAIVE_WQ) {
+        form_serial(P, c, vals, flags, s);
+        return;
+    }
+    const bool full = (flags & IGA_FORM_FULL) != 0;
+    hipStream_t a = P.aux;
+    HIPX(hipEventRecord(P.ev_fork, s));
+    HIPX(hipStreamWaitEvent(a, P.ev_fork, 0));
+    if (full) setup_tables(P, a);
+    {
+        PhaseTimer t(P, a, IGA_PHASE_COEF);
+        launch_coef(P, c, a, 1);
+    }
+    HIPX(hipEventRecord(P.ev_tables, a));
+    if (full) {
+        PhaseTimer t(P, s, IGA_PHASE_SETUP);
+        setup_trim(P, s, false, P.ev_tables);
+    } else {
+        HIPX(hipEventRecord(P.ev_lists, s));
+    }
+    HIPX(hipStreamWaitEvent(a, P.ev_lists, 0));
+    {
+        PhaseTimer t(P, a, IGA_PHASE_INTERIOR);
+        launch_interior_rows(P, c, vals, a);
+    }
+    HIPX(hipEventRecord(P.ev_interior, a));
+    {
+        PhaseTimer t(P, s, IGA_PHASE_CUT);
+        launch_coef(P, c, s, 2);
+        launch_cut_rows(P, c, vals, s);
+        launch_dwq_rows(P, c, vals, s);
+    }
+    HIPX(hipStreamWaitEvent(s, P.ev_interior, 0));
 }
 
 static void validate_knots(const double* k, int n, int p, int d) {
@@ -248,6 +310,9 @@ int iga_plan_create(const iga_patch_desc* desc, const iga_opts* opts, iga_plan**
     auto* P = new iga_plan();
     std::unique_ptr<iga_plan> guard(P);
     HIPX(hipGetDevice(&P->device));
+    HIPX(hipStreamCreateWithFlags(&P->aux, hipStreamNonBlocking));
+    for (hipEvent_t* e : {&P->ev_fork, &P->ev_tables, &P->ev_lists, &P->ev_interior})
+        HIPX(hipEventCreateWithFlags(e, hipEventDisableTiming));
     P->p = p;
     P->method = desc->method;
     P->n_r = (opts && opts->n_r > 0) ? opts->n_r : p + 1;
@@ -375,6 +440,8 @@ int iga_plan_create(const iga_patch_desc* desc, const iga_opts* opts, iga_plan**
     }
     int nf = P->n1 * P->n2, ne = P->N1 * P->N2;
     P->ecls = P->alloc<int8_t>(ne);
+    P->emark = P->alloc<int>(ne);
+    HIPX(hipMemsetAsync(P->emark, 0, sizeof(int) * (size_t)ne, s));
     P->cut_id = P->alloc<int>(ne);
     P->band_id = P->alloc<int>(ne);
     P->cut_list = P->alloc<int>(ne);

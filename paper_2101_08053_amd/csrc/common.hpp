@@ -71,6 +71,38 @@ __device__ __forceinline__ void basis_eval(const double* __restrict__ knots, int
     }
 }
 
+// The triangular scheme's denominators right[r+1] + left[j-r] do not depend
+// on x: knots[span+r+1] - knots[span+1-j+r]. basis_rec<P> tabulates their
+// reciprocals for one span (index j(j-1)/2 + r, j = 1..P, r < j) so that many
+// points of one element are evaluated without divisions.
+template <int P>
+__device__ __forceinline__ double basis_rec(const double* __restrict__ knots, int span, int idx) {
+    int j = 1;
+    while (j * (j + 1) / 2 <= idx) ++j;
+    const int r = idx - j * (j - 1) / 2;
+    return 1.0 / (knots[span + r + 1] - knots[span + 1 - j + r]);
+}
+
+template <int P>
+__device__ __forceinline__ void basis_eval_rec(const double* __restrict__ knots, int span,
+                                               const double* __restrict__ rinv, double x, double* N) {
+    double left[P + 1], right[P + 1];
+    N[0] = 1.0;
+#pragma unroll
+    for (int j = 1; j <= P; ++j) {
+        left[j] = x - knots[span + 1 - j];
+        right[j] = knots[span + j] - x;
+        double saved = 0.0;
+#pragma unroll
+        for (int r = 0; r < j; ++r) {
+            const double tmp = N[r] * rinv[j * (j - 1) / 2 + r];
+            N[r] = saved + right[r + 1] * tmp;
+            saved = left[j - r] * tmp;
+        }
+        N[j] = saved;
+    }
+}
+
 // Values and first derivatives, compile-time degree.
 template <int P>
 __device__ __forceinline__ void basis_eval_d(const double* __restrict__ knots, int span, double x, double* N,

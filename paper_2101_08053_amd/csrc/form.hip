@@ -58,8 +58,9 @@ void launch_points(Plan& P, hipStream_t s) {
 
 // ------------------------------------------------------- coefficient
 template <int P>
-__global__ void __launch_bounds__(256) k_coef(CoefArgs A) {
-    coef_point<P>(A, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+__global__ void __launch_bounds__(256) k_coef(CoefArgs A, int64_t t0, int64_t t1) {
+    const int64_t t = t0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < t1) coef_point<P>(A, t);
 }
 
 CoefView coef_view(Plan& P, const iga_coeff& c) {
@@ -87,14 +88,17 @@ CoefArgs coef_args(Plan& P, const iga_coeff& c) {
                     (int64_t)P.dir[0].Q * P.dir[1].Q, (int64_t)P.n_band * (P.p + 1) * (P.p + 1)};
 }
 
-void launch_coef(Plan& P, const iga_coeff& c, hipStream_t s) {
+// part: 0 every rule point, 1 the WQ grid only, 2 band Gauss points and cut nodes only
+void launch_coef(Plan& P, const iga_coeff& c, hipStream_t s, int part) {
     if (c.kind != IGA_COEF_GEOM_DETJ) return;
     CoefArgs A = coef_args(P, c);
-    const int64_t n = A.nq + A.nb + A.n_nodes;
-    dim3 g((unsigned)((n + 255) / 256)), b(256);
+    const int64_t t0 = (part == 2) ? A.nq : 0;
+    const int64_t t1 = (part == 1) ? A.nq : A.nq + A.nb + A.n_nodes;
+    if (t1 <= t0) return;
+    dim3 g((unsigned)((t1 - t0 + 255) / 256)), b(256);
     switch (P.p) {
 #define CASE(PP) \
-    case PP: hipLaunchKernelGGL(k_coef<PP>, g, b, 0, s, A); break;
+    case PP: hipLaunchKernelGGL(k_coef<PP>, g, b, 0, s, A, t0, t1); break;
         CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
 #undef CASE
         default: throw Error{IGA_E_UNSUPPORTED, "degree outside 1..8"};

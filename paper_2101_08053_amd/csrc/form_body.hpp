@@ -322,25 +322,34 @@ struct CutEArgs {
 };
 
 template <int P>
+struct CutECfg {
+    static constexpr int L = (P + 1) * (P + 1);
+    static constexpr int CH = (P <= 4) ? 256 : ((P <= 6) ? 128 : 64);  // nodes staged at a time
+    static constexpr int NR = P * (P + 1) / 2;                          // reciprocal denominators per direction
+};
+
+template <int P>
 struct CutESmem {
-    double sPhi[64][(P + 1) * (P + 1)];
-    double sWc[64];
+    double sPhi[CutECfg<P>::CH][CutECfg<P>::L];
+    double sWc[CutECfg<P>::CH];
+    double sRec[2][CutECfg<P>::NR + 1];
 };
 
 // Local matrix of cut element c (256 threads): the element's nodes are
-// staged 64 at a time with their basis products; thread t owns entries of
-// the upper triangle and mirrors them.
+// staged CH at a time with their basis products (one node per thread, the
+// element's reciprocal knot differences shared, so no divisions per node);
+// thread t owns entries of the upper triangle and mirrors them.
 template <int P>
 __device__ __forceinline__ void cut_elem_body(const CutEArgs& A, int c, CutESmem<P>& S) {
-    constexpr int L = (P + 1) * (P + 1);
+    using C = CutECfg<P>;
+    constexpr int L = C::L, CH = C::CH, NR = C::NR;
     constexpr int NE = L * (L + 1) / 2;
     constexpr int PER = (NE + 255) / 256;
-    constexpr int CH = 64;
     auto& sPhi = S.sPhi;
     auto& sWc = S.sWc;
     if (c >= A.n_cut) return;
-    int e = A.cut_list[c], e1 = e % A.d1.N, e2 = e / A.d1.N;
-    int nb = A.node_off[c], ne = A.node_off[c + 1];
+    const int e = A.cut_list[c], e1 = e % A.d1.N, e2 = e / A.d1.N;
+    const int nb = A.node_off[c], ne = A.node_off[c + 1];
     double acc[PER];
     int el[PER], em[PER];
 #pragma unroll
@@ -352,19 +361,32 @@ __device__ __forceinline__ void cut_elem_body(const CutEArgs& A, int c, CutESmem
         el[k] = (t < NE) ? l : -1;
         em[k] = (t < NE) ? l + rem : -1;
     }
+    int elc[PER], emc[PER];  // clamped: threads past the triangle accumulate a discarded entry
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        elc[k] = max(el[k], 0);
+        emc[k] = max(em[k], 0);
+    }
+    __syncthreads();  // LDS of the previous work item is free
+    if (threadIdx.x < 2 * NR) {
+        const int d = threadIdx.x / NR, idx = threadIdx.x % NR;
+        S.sRec[d][idx] = basis_rec<P>(d ? A.d2.knots : A.d1.knots, P + (d ? e2 : e1), idx);
+    }
     for (int base = nb; base < ne; base += CH) {
         __syncthreads();
         if (threadIdx.x < CH) {
-            int n = base + threadIdx.x;
+            const int n = base + threadIdx.x;
             if (n < ne) {
+                const double x = A.nx[n], y = A.ny[n], w = A.nw[n];
+                const double cv = A.c.is_const ? A.c.value : A.c.cut[n];
                 double B1[P + 1], B2[P + 1];
-                basis_eval<P>(A.d1.knots, P + e1, A.nx[n], B1);
-                basis_eval<P>(A.d2.knots, P + e2, A.ny[n], B2);
+                basis_eval_rec<P>(A.d1.knots, P + e1, S.sRec[0], x, B1);
+                basis_eval_rec<P>(A.d2.knots, P + e2, S.sRec[1], y, B2);
 #pragma unroll
                 for (int a2 = 0; a2 <= P; ++a2)
 #pragma unroll
                     for (int a1 = 0; a1 <= P; ++a1) sPhi[threadIdx.x][a2 * (P + 1) + a1] = B1[a1] * B2[a2];
-                sWc[threadIdx.x] = A.nw[n] * (A.c.is_const ? A.c.value : A.c.cut[n]);
+                sWc[threadIdx.x] = w * cv;
             } else {
                 sWc[threadIdx.x] = 0.0;
 #pragma unroll
@@ -372,13 +394,13 @@ __device__ __forceinline__ void cut_elem_body(const CutEArgs& A, int c, CutESmem
             }
         }
         __syncthreads();
-        int cnt = min(CH, ne - base);
+        const int cnt = min(CH, ne - base);
+        // no branch in the loop body, so the LDS reads of several nodes are issued ahead
+#pragma unroll 8
+        for (int n = 0; n < cnt; ++n) {
+            const double wc = sWc[n];
 #pragma unroll
-        for (int k = 0; k < PER; ++k) {
-            if (el[k] < 0) continue;
-            double s = 0.0;
-            for (int n = 0; n < cnt; ++n) s += sWc[n] * sPhi[n][el[k]] * sPhi[n][em[k]];
-            acc[k] += s;
+            for (int k = 0; k < PER; ++k) acc[k] += wc * sPhi[n][elc[k]] * sPhi[n][emc[k]];
         }
     }
     double* E = A.E + (size_t)c * L * L;
@@ -417,7 +439,8 @@ template <int P>
 struct CutRSmem {
     double sF1[P + 1][P + 1][2 * P + 1];
     double sF2[P + 1][P + 1][2 * P + 1];
-    double sC[P + 1][P + 1][(P + 1) * (P + 1)];
+    double sX[P + 1][P + 1][(P + 1) * (P + 1)];  // inside element: c at its Gauss points (else 0)
+    double sE[P + 1][P + 1][(P + 1) * (P + 1)];  // cut element: row i of its local matrix (else 0)
     int sCls[P + 1][P + 1];
     int sId[P + 1][P + 1];
 };
@@ -427,7 +450,8 @@ __device__ __forceinline__ void cut_row_body(const CutRowArgs& A, int r, CutRSme
     constexpr int W = 2 * P + 1, L = (P + 1) * (P + 1), NP = P + 1;
     auto& sF1 = S.sF1;
     auto& sF2 = S.sF2;
-    auto& sC = S.sC;
+    auto& sX = S.sX;
+    auto& sE = S.sE;
     auto& sCls = S.sCls;
     auto& sId = S.sId;
     if (r >= A.n_rows) return;
@@ -467,49 +491,54 @@ __device__ __forceinline__ void cut_row_body(const CutRowArgs& A, int r, CutRSme
         int e1 = i1 - P + m1, e2 = i2 - P + m2;
         int cls = -1, id = -1;
         if (e1 >= 0 && e1 < D1.N && e2 >= 0 && e2 < D2.N && !(e1 >= bx0 && e1 <= bx1 && e2 >= by0 && e2 <= by1)) {
-            int e = e2 * D1.N + e1;
-            cls = A.ecls[e];
-            id = (cls == EL_CUT) ? A.cut_id[e] : (cls == EL_INSIDE ? A.band_id[e] : -1);
+            // every inside element of a formed row's support is a band element
+            const int e = e2 * D1.N + e1;
+            const int ci = A.cut_id[e], bi = A.band_id[e];
+            cls = (ci >= 0) ? EL_CUT : (bi >= 0 ? EL_INSIDE : -1);
+            id = (ci >= 0) ? ci : bi;
         }
         sCls[m2][m1] = cls;
         sId[m2][m1] = id;
     }
     __syncthreads();
-    if (!A.c.is_const) {
-        for (int t = tid; t < NP * NP * L; t += nt) {
-            int m2 = t / (NP * L), m1 = (t / L) % NP, g = t % L;
-            sC[m2][m1][g] = (sCls[m2][m1] == EL_INSIDE) ? A.c.band[(size_t)sId[m2][m1] * L + g] : 0.0;
-        }
-        __syncthreads();
+    // per support element: c at its Gauss points (inside) or row i of its local matrix (cut)
+    for (int t = tid; t < NP * NP * L; t += nt) {
+        const int m2 = t / (NP * L), m1 = (t / L) % NP, g = t % L;
+        const int cls = sCls[m2][m1];
+        double v = 0.0, w = 0.0;
+        if (cls == EL_INSIDE) v = A.c.is_const ? A.c.value : A.c.band[(size_t)sId[m2][m1] * L + g];
+        else if (cls == EL_CUT) w = A.E[((size_t)sId[m2][m1] * L + (P - m2) * NP + (P - m1)) * L + g];
+        sX[m2][m1][g] = v;
+        sE[m2][m1][g] = w;
     }
+    __syncthreads();
     const int s = tid;
     if (s >= W * W) return;
     const int a = s / W, b = s % W;          // column offsets a-p, b-p
     const int j1 = i1 + a - P, j2 = i2 + b - P;
     double val = 0.0;
     if (j1 >= 0 && j1 < D1.n && j2 >= 0 && j2 < D2.n && A.act_of[j2 * D1.n + j1] >= 0) {
-        const int m1lo = max(0, a - P), m1hi = P + min(0, a - P);
-        const int m2lo = max(0, b - P), m2hi = P + min(0, b - P);
-        for (int m2 = m2lo; m2 <= m2hi; ++m2)
-            for (int m1 = m1lo; m1 <= m1hi; ++m1) {
-                const int cls = sCls[m2][m1];
-                if (cls == EL_INSIDE) {
-                    double sum = 0.0;
+        // every support element, without branches: the Gauss factors F vanish off the column's
+        // overlap and sX / sE hold zeros where the element is not inside / cut
 #pragma unroll
-                    for (int g2 = 0; g2 < NP; ++g2) {
-                        double in = 0.0;
+        for (int m2 = 0; m2 <= P; ++m2) {
+            const int l2 = j2 - (i2 - P + m2);  // column's local index in the element, direction 2
 #pragma unroll
-                        for (int g1 = 0; g1 < NP; ++g1)
-                            in += sF1[m1][g1][a] * (A.c.is_const ? A.c.value : sC[m2][m1][g2 * NP + g1]);
-                        sum += sF2[m2][g2][b] * in;
-                    }
-                    val += sum;
-                } else if (cls == EL_CUT) {
-                    const int li = (P - m2) * NP + (P - m1);
-                    const int lj = (j2 - (i2 - P + m2)) * NP + (j1 - (i1 - P + m1));
-                    val += A.E[(size_t)sId[m2][m1] * L * L + li * L + lj];
+            for (int m1 = 0; m1 <= P; ++m1) {
+                const int l1 = j1 - (i1 - P + m1);
+                double sum = 0.0;
+#pragma unroll
+                for (int g2 = 0; g2 < NP; ++g2) {
+                    double in = 0.0;
+#pragma unroll
+                    for (int g1 = 0; g1 < NP; ++g1) in += sF1[m1][g1][a] * sX[m2][m1][g2 * NP + g1];
+                    sum += sF2[m2][g2][b] * in;
                 }
+                const bool ov = (l1 >= 0 && l1 <= P && l2 >= 0 && l2 <= P);
+                const double ev = sE[m2][m1][ov ? l2 * NP + l1 : 0];
+                val += sum + (ov ? ev : 0.0);
             }
+        }
     }
     A.vals[(size_t)s * A.n_act + row] = val;
 }

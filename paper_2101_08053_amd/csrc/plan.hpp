@@ -159,6 +159,8 @@ struct Plan {
     int* cut_rows = nullptr;       // compact ids of cut rows
     int* form_rows = nullptr;      // rows formed by the element/cut kernel (method dependent)
     int* dwq_region = nullptr;     // [n_form_rows][8] DWQ box of each formed row (lo1 = -1: none)
+    int* emark = nullptr;          // [N1*N2] element owns a visible arc iff emark == epoch
+    int epoch = 0;                 // set-up counter (marks need no clearing)
     int* cut_list = nullptr;       // flat ids of cut elements
     int* band_list = nullptr;      // flat ids of band elements
     int* arc_cnt = nullptr;        // per cut element
@@ -192,6 +194,11 @@ struct Plan {
     int64_t n_act = 0, n_interior = 0, n_cut_fn = 0, n_cut_el = 0, n_band = 0;
     int64_t n_nodes = 0, n_arcs = 0, nnz = 0, n_form_rows = 0, n_points = 0, n_dwq_rows = 0;
     int64_t bytes = 0;
+
+    // second stream of the formation: univariate tables, weights, WQ-grid coefficient and interior
+    // rows run there, beside the trimming chain (default priority; joined by events)
+    hipStream_t aux = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_tables = nullptr, ev_lists = nullptr, ev_interior = nullptr;
 
     // timing
     bool timing = false;
@@ -259,19 +266,17 @@ void launch_wb_table(Plan& P, int d, hipStream_t s);
 void exclusive_scan(const int* in, int* out, int n, int* tmp, hipStream_t s);
 // trim.hip
 void launch_trim_curves(Plan& P, hipStream_t s);            // segments + monotone pieces (+ unions)
-void launch_trim_crossings(Plan& P, hipStream_t s);         // counts + scan
 void launch_trim_arcs(Plan& P, hipStream_t s);              // solve, merge, arcs
 void launch_trim_classes(Plan& P, hipStream_t s);           // elements, functions, flags
 void launch_trim_lists(Plan& P, hipStream_t s);             // act_of, cut/band lists
 void launch_trim_cutprep(Plan& P, hipStream_t s);           // per cut element segments, variant, counts
 void launch_trim_nodes(Plan& P, hipStream_t s);             // node coordinates and weights
-void launch_orientation(Plan& P, hipStream_t s);
 void launch_naive_mask(Plan& P, const double* src, double cval, hipStream_t s);
 void launch_row_nnz(Plan& P, int* cnt, int* out, hipStream_t s);
 // form.hip
 CoefView coef_view(Plan& P, const iga_coeff& c);
 void launch_points(Plan& P, hipStream_t s);
-void launch_coef(Plan& P, const iga_coeff& c, hipStream_t s);
+void launch_coef(Plan& P, const iga_coeff& c, hipStream_t s, int part = 0);
 void launch_interior_rows(Plan& P, const iga_coeff& c, double* vals, hipStream_t s);
 void launch_cut_rows(Plan& P, const iga_coeff& c, double* vals, hipStream_t s);
 // dwq.hip

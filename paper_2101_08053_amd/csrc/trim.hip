@@ -140,9 +140,7 @@ __device__ __forceinline__ double blend(int d, int l, int pw) {
     return b3[l][pw];
 }
 
-__global__ void k_segments(TrimDev T, const double* __restrict__ cp, const int* __restrict__ cp_off) {
-    int s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= T.n_segs) return;
+__device__ void segment_make(const TrimDev& T, const double* __restrict__ cp, const int* __restrict__ cp_off, int s) {
     int c = 0;
     while (c + 1 < T.n_curves && T.curves[c + 1].seg0 <= s) ++c;
     const CurveDev C = T.curves[c];
@@ -243,8 +241,8 @@ __device__ __forceinline__ PieceDev make_piece(const TrimDev& T, int s, double t
 __device__ int block_scan_carry(int v, int* sh, int& total);
 
 // Single block: monotone pieces of every segment, compacted in segment order.
-__global__ void __launch_bounds__(1024) k_pieces(TrimDev T, PieceDev* __restrict__ out, int* __restrict__ count,
-                                                 int* __restrict__ curve_off) {
+__device__ void pieces_build(const TrimDev& T, PieceDev* __restrict__ out, int* __restrict__ count,
+                             int* __restrict__ curve_off) {
     __shared__ int sh[1024 / 64 + 1];
     int carry = 0;
     for (int base = 0; base < T.n_segs; base += blockDim.x) {
@@ -364,7 +362,7 @@ __global__ void __launch_bounds__(64) k_piece_isect(TrimDev T, int* __restrict__
     }
 }
 
-__global__ void __launch_bounds__(1024) k_split_pieces(TrimDev T) {
+__device__ void pieces_split(const TrimDev& T) {
     __shared__ int sh[1024 / 64 + 1];
     int carry = 0;
     int n0 = *T.n_pieces0;
@@ -391,19 +389,6 @@ __global__ void __launch_bounds__(1024) k_split_pieces(TrimDev T) {
     }
 }
 
-void launch_trim_curves(Plan& P, hipStream_t s) {
-    TrimDev& T = P.trim;
-    if (T.n_curves == 0) return;
-    hipLaunchKernelGGL(k_segments, dim3((T.n_segs + 63) / 64), dim3(64), 0, s, T, P.d_cp, P.d_cp_off);
-    if (T.n_curves == 1) {
-        hipLaunchKernelGGL(k_pieces, dim3(1), dim3(1024), 0, s, T, T.pieces, T.n_pieces, T.piece_curve_off);
-    } else {
-        hipLaunchKernelGGL(k_pieces, dim3(1), dim3(1024), 0, s, T, T.pieces0, T.n_pieces0, T.piece_curve_off);
-        hipLaunchKernelGGL(k_piece_isect, dim3(T.cap_pieces0), dim3(64), 0, s, T, P.status);
-        hipLaunchKernelGGL(k_split_pieces, dim3(1), dim3(1024), 0, s, T);
-    }
-}
-
 // ------------------------------------------------------------ crossings
 struct GridDev {
     const double* bp1;
@@ -411,10 +396,9 @@ struct GridDev {
     int N1, N2;
 };
 
-__global__ void k_cross_count(TrimDev T, GridDev G) {
-    int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= T.cap_pieces) return;
-    int np = *T.n_pieces;
+// Crossings of piece k with the vertical (then horizontal) grid lines in its
+// box, counted half-open so that a crossing at a shared end belongs to one piece.
+__device__ __forceinline__ void cross_count_one(const TrimDev& T, const GridDev& G, int k, int np) {
     if (k >= np) {
         T.cross_cnt[k] = 0;
         T.nv[k] = 0;
@@ -429,141 +413,195 @@ __global__ void k_cross_count(TrimDev T, GridDev G) {
     T.cross_cnt[k] = nv + nh;
 }
 
-void launch_trim_crossings(Plan& P, hipStream_t s) {
+// One workgroup of 1024: orientation of every curve (sign of its enclosed area
+// by Gauss on each segment; a hole traversed with the visible domain on its
+// left is clockwise), crossing counts of every piece and their offsets.
+__device__ void curves_orient_count(const TrimDev& T, CurveDev* __restrict__ curves, const GridDev& G,
+                                    const double* __restrict__ gx, const double* __restrict__ gw) {
+    __shared__ double sh_area[1024 / 64];
+    __shared__ int sh[1024 / 64 + 1];
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    constexpr int ng = 8;
+    for (int c = 0; c < T.n_curves; ++c) {
+        const CurveDev C = curves[c];
+        double area = 0.0;
+        for (int u = tid; u < C.n_seg * ng; u += 1024) {
+            const SegDev S = T.segs[C.seg0 + u / ng];
+            const int g = u % ng;
+            const double tt = C.t_range * (gx[gauss_off(ng) + g] + 1.0) * 0.5;
+            const double w = gw[gauss_off(ng) + g] * C.t_range * 0.5;
+            double X, Y, dX, dY;
+            seg_eval(S, tt, X, Y, dX, dY);
+            area += 0.5 * w * (X * dY - Y * dX);
+        }
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) area += __shfl_xor(area, o, 64);
+        if (lane == 0) sh_area[wid] = area;
+        __syncthreads();
+        if (tid == 0) {
+            double a = 0.0;
+            for (int w = 0; w < 1024 / 64; ++w) a += sh_area[w];
+            curves[c].sigma = (a > 0.0) ? -1.0 : 1.0;
+        }
+        __syncthreads();
+    }
+    const int np = *T.n_pieces;
+    for (int k = tid; k < T.cap_pieces; k += 1024) cross_count_one(T, G, k, np);
+    __syncthreads();
+    int carry = 0;
+    for (int base = 0; base < T.cap_pieces; base += 1024) {
+        const int k = base + tid;
+        const int v = (k < T.cap_pieces) ? T.cross_cnt[k] : 0;
+        int total;
+        const int ex = block_excl_scan(v, sh, total);
+        if (k < T.cap_pieces) T.cross_off[k] = ex + carry;
+        carry += total;
+    }
+    if (tid == 0) T.cross_off[T.cap_pieces] = carry;
+}
+
+// Front of the trimming set-up in one workgroup: segments, monotone pieces,
+// then (single hole) orientation, crossing counts and offsets. For a union
+// of holes only the unsplit pieces are built here.
+__global__ void __launch_bounds__(1024) k_trim_front(TrimDev T, const double* __restrict__ cp,
+                                                     const int* __restrict__ cp_off, CurveDev* __restrict__ curves,
+                                                     GridDev G, const double* __restrict__ gx,
+                                                     const double* __restrict__ gw) {
+    for (int s = threadIdx.x; s < T.n_segs; s += 1024) segment_make(T, cp, cp_off, s);
+    __syncthreads();
+    if (T.n_curves == 1) {
+        pieces_build(T, T.pieces, T.n_pieces, T.piece_curve_off);
+        __syncthreads();
+        curves_orient_count(T, curves, G, gx, gw);
+    } else {
+        pieces_build(T, T.pieces0, T.n_pieces0, T.piece_curve_off);
+    }
+}
+
+// Union of holes: split the pieces where they meet another curve, then orientation and counts.
+__global__ void __launch_bounds__(1024) k_trim_split(TrimDev T, CurveDev* __restrict__ curves, GridDev G,
+                                                     const double* __restrict__ gx, const double* __restrict__ gw) {
+    pieces_split(T);
+    __syncthreads();
+    curves_orient_count(T, curves, G, gx, gw);
+}
+
+void launch_trim_curves(Plan& P, hipStream_t s) {
     TrimDev& T = P.trim;
     if (T.n_curves == 0) return;
-    GridDev G{P.dir[0].bp, P.dir[1].bp, P.N1, P.N2};
-    hipLaunchKernelGGL(k_cross_count, dim3((T.cap_pieces + 127) / 128), dim3(128), 0, s, T, G);
-    exclusive_scan(T.cross_cnt, T.cross_off, T.cap_pieces, P.scan_tmp, s);
+    GridDev G{P.dir[0].knots + P.p, P.dir[1].knots + P.p, P.N1, P.N2};  // breakpoints
+    hipLaunchKernelGGL(k_trim_front, dim3(1), dim3(1024), 0, s, T, P.d_cp, P.d_cp_off, P.d_curves, G, P.gauss_x,
+                       P.gauss_w);
+    if (T.n_curves > 1) {
+        hipLaunchKernelGGL(k_piece_isect, dim3(T.cap_pieces0), dim3(64), 0, s, T, P.status);
+        hipLaunchKernelGGL(k_trim_split, dim3(1), dim3(1024), 0, s, T, P.d_curves, G, P.gauss_x, P.gauss_w);
+    }
 }
 
-__global__ void k_cross_solve(TrimDev T, GridDev G) {
-    int c = blockIdx.x * blockDim.x + threadIdx.x;
-    int np = *T.n_pieces;
-    if (c >= T.cross_off[np]) return;
-    int k = upper_bound_i(T.cross_off, np + 1, c) - 1;
-    int j = c - T.cross_off[k];
-    const PieceDev Pc = T.pieces[k];
-    const SegDev S = T.segs[Pc.seg];
-    CrossDev X;
-    int nv = T.nv[k];
-    if (j < nv) {
-        int line = lower_bound_d(G.bp1, G.N1 + 1, fmin(Pc.x0, Pc.x1)) + j;
-        X.kind = END_VLINE;
-        X.line = line;
-        X.t = solve_monotone(S, 0, G.bp1[line], Pc.t0, Pc.t1);
-    } else {
-        int line = lower_bound_d(G.bp2, G.N2 + 1, fmin(Pc.y0, Pc.y1)) + (j - nv);
-        X.kind = END_HLINE;
-        X.line = line;
-        X.t = solve_monotone(S, 1, G.bp2[line], Pc.t0, Pc.t1);
+// One workgroup per piece: solve its crossings, order them along the piece
+// (own rank plus the crossings of the other family before it, vertical first
+// on ties), cut the piece into arcs, keep the visible ones and mark their
+// elements cut (mark = this set-up's epoch).
+__global__ void __launch_bounds__(256) k_piece_arcs(TrimDev T, GridDev G, int* __restrict__ emark, int epoch) {
+    const int k = blockIdx.x;
+    const int np = *T.n_pieces;
+    const int tid = threadIdx.x;
+    if (k == 0) {  // arcs past the last piece's (capacity left from the plan's first set-up)
+        const int n_arcs = T.cross_off[np] + np;
+        for (int a = n_arcs + tid; a < T.cap_arcs; a += 256) T.arcs[a].keep = 0;
     }
-    T.cross[c] = X;
-}
-
-// Rank of each crossing in its piece's t order: own rank plus the number of
-// crossings of the other family before it (vertical first on ties).
-__global__ void k_cross_merge(TrimDev T) {
-    int c = blockIdx.x * blockDim.x + threadIdx.x;
-    int np = *T.n_pieces;
-    if (c >= T.cross_off[np]) return;
-    int k = upper_bound_i(T.cross_off, np + 1, c) - 1;
-    int base = T.cross_off[k];
-    int j = c - base;
-    int nv = T.nv[k], nh = T.cross_cnt[k] - nv;
-    const PieceDev Pc = T.pieces[k];
-    bool incx = Pc.x1 > Pc.x0, incy = Pc.y1 > Pc.y0;
-    double t = T.cross[c].t;
-    int own, other = 0;
-    if (j < nv) {
-        own = incx ? j : nv - 1 - j;
-        // horizontal crossings with t' < t
-        int lo = 0, hi = nh;
-        while (lo < hi) {
-            int mid = (lo + hi) >> 1;
-            int idx = incy ? mid : nh - 1 - mid;
-            if (T.cross[base + nv + idx].t < t) lo = mid + 1; else hi = mid;
-        }
-        other = lo;
-    } else {
-        int jh = j - nv;
-        own = incy ? jh : nh - 1 - jh;
-        int lo = 0, hi = nv;
-        while (lo < hi) {
-            int mid = (lo + hi) >> 1;
-            int idx = incx ? mid : nv - 1 - mid;
-            if (T.cross[base + idx].t <= t) lo = mid + 1; else hi = mid;
-        }
-        other = lo;
-    }
-    T.merged[base + own + other] = T.cross[c];
-}
-
-__global__ void k_arcs(TrimDev T, GridDev G) {
-    int a = blockIdx.x * blockDim.x + threadIdx.x;
-    int np = *T.n_pieces;
-    int n_arcs = T.cross_off[np] + np;
-    if (a >= T.cap_arcs) return;
-    if (a >= n_arcs) {
-        T.arcs[a].keep = 0;
-        return;
-    }
-    // arcs of piece k start at cross_off[k] + k
-    int lo = 0, hi = np;
-    while (lo < hi) {
-        int mid = (lo + hi) >> 1;
-        if (T.cross_off[mid] + mid <= a) lo = mid + 1; else hi = mid;
-    }
-    int k = lo - 1;
-    int base = T.cross_off[k];
-    int j = a - base - k;
-    int n = T.cross_cnt[k];
+    if (k >= np) return;
+    const int base = T.cross_off[k], n = T.cross_cnt[k], nv = T.nv[k];
     const PieceDev Pc = T.pieces[k];
     const SegDev S = T.segs[Pc.seg];
     const CurveDev C = T.curves[Pc.curve];
-    ArcDev A;
-    A.curve = Pc.curve;
-    A.seg = S.seg;
-    A.piece = k;
-    if (j == 0) { A.t0 = Pc.t0; A.k0 = END_PIECE; A.l0 = -1; }
-    else { CrossDev X = T.merged[base + j - 1]; A.t0 = X.t; A.k0 = X.kind; A.l0 = X.line; }
-    if (j == n) { A.t1 = Pc.t1; A.k1 = END_PIECE; A.l1 = -1; }
-    else { CrossDev X = T.merged[base + j]; A.t1 = X.t; A.k1 = X.kind; A.l1 = X.line; }
-    double X, Y, dX, dY;
-    seg_eval(S, 0.5 * (A.t0 + A.t1), X, Y, dX, dY);
-    int keep = (A.t1 - A.t0 > 1e-13 * C.t_range);
-    keep = keep && X > G.bp1[0] && X < G.bp1[G.N1] && Y > G.bp2[0] && Y < G.bp2[G.N2];
-    if (keep && T.n_curves > 1) keep = !in_any_hole(T, X, Y, Pc.curve);
-    A.keep = keep;
-    A.e1 = min(max(upper_bound_d(G.bp1, G.N1 + 1, X) - 1, 0), G.N1 - 1);
-    A.e2 = min(max(upper_bound_d(G.bp2, G.N2 + 1, Y) - 1, 0), G.N2 - 1);
-    T.arcs[a] = A;
+    const int lv0 = lower_bound_d(G.bp1, G.N1 + 1, fmin(Pc.x0, Pc.x1));
+    const int lh0 = lower_bound_d(G.bp2, G.N2 + 1, fmin(Pc.y0, Pc.y1));
+    for (int j = tid; j < n; j += 256) {
+        CrossDev X;
+        if (j < nv) {
+            X.kind = END_VLINE;
+            X.line = lv0 + j;
+            X.t = solve_monotone(S, 0, G.bp1[X.line], Pc.t0, Pc.t1);
+        } else {
+            X.kind = END_HLINE;
+            X.line = lh0 + (j - nv);
+            X.t = solve_monotone(S, 1, G.bp2[X.line], Pc.t0, Pc.t1);
+        }
+        T.cross[base + j] = X;
+    }
+    __syncthreads();
+    const int nh = n - nv;
+    const bool incx = Pc.x1 > Pc.x0, incy = Pc.y1 > Pc.y0;
+    for (int j = tid; j < n; j += 256) {
+        const CrossDev X = T.cross[base + j];
+        int own, other;
+        if (j < nv) {
+            own = incx ? j : nv - 1 - j;
+            int lo = 0, hi = nh;
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                const int idx = incy ? mid : nh - 1 - mid;
+                if (T.cross[base + nv + idx].t < X.t) lo = mid + 1; else hi = mid;
+            }
+            other = lo;
+        } else {
+            const int jh = j - nv;
+            own = incy ? jh : nh - 1 - jh;
+            int lo = 0, hi = nv;
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                const int idx = incx ? mid : nv - 1 - mid;
+                if (T.cross[base + idx].t <= X.t) lo = mid + 1; else hi = mid;
+            }
+            other = lo;
+        }
+        T.merged[base + own + other] = X;
+    }
+    __syncthreads();
+    for (int j = tid; j <= n; j += 256) {
+        ArcDev A;
+        A.curve = Pc.curve;
+        A.seg = S.seg;
+        A.piece = k;
+        if (j == 0) { A.t0 = Pc.t0; A.k0 = END_PIECE; A.l0 = -1; }
+        else { const CrossDev X = T.merged[base + j - 1]; A.t0 = X.t; A.k0 = X.kind; A.l0 = X.line; }
+        if (j == n) { A.t1 = Pc.t1; A.k1 = END_PIECE; A.l1 = -1; }
+        else { const CrossDev X = T.merged[base + j]; A.t1 = X.t; A.k1 = X.kind; A.l1 = X.line; }
+        double X, Y, dX, dY;
+        seg_eval(S, 0.5 * (A.t0 + A.t1), X, Y, dX, dY);
+        int keep = (A.t1 - A.t0 > 1e-13 * C.t_range);
+        keep = keep && X > G.bp1[0] && X < G.bp1[G.N1] && Y > G.bp2[0] && Y < G.bp2[G.N2];
+        if (keep && T.n_curves > 1) keep = !in_any_hole(T, X, Y, Pc.curve);
+        A.keep = keep;
+        A.e1 = min(max(upper_bound_d(G.bp1, G.N1 + 1, X) - 1, 0), G.N1 - 1);
+        A.e2 = min(max(upper_bound_d(G.bp2, G.N2 + 1, Y) - 1, 0), G.N2 - 1);
+        T.arcs[base + k + j] = A;
+        if (keep) emark[A.e2 * G.N1 + A.e1] = epoch;
+    }
 }
 
 void launch_trim_arcs(Plan& P, hipStream_t s) {
     TrimDev& T = P.trim;
     if (T.n_curves == 0) return;
-    GridDev G{P.dir[0].bp, P.dir[1].bp, P.N1, P.N2};
-    int nc = T.cap_cross > 0 ? T.cap_cross : 1;
-    hipLaunchKernelGGL(k_cross_solve, dim3((nc + 127) / 128), dim3(128), 0, s, T, G);
-    hipLaunchKernelGGL(k_cross_merge, dim3((nc + 127) / 128), dim3(128), 0, s, T);
-    hipLaunchKernelGGL(k_arcs, dim3((T.cap_arcs + 127) / 128), dim3(128), 0, s, T, G);
+    GridDev G{P.dir[0].knots + P.p, P.dir[1].knots + P.p, P.N1, P.N2};  // breakpoints
+    hipLaunchKernelGGL(k_piece_arcs, dim3(std::max(T.cap_pieces, 1)), dim3(256), 0, s, T, G, P.emark, P.epoch);
 }
 
 // -------------------------------------------------------------- classes
-__global__ void k_elem_centre(TrimDev T, GridDev G, int8_t* __restrict__ ecls) {
+// Element classes: cut if it owns a visible arc (marked with this set-up's
+// epoch), otherwise inside / outside by the test at its centre.
+__global__ void k_elem_centre(TrimDev T, GridDev G, const int* __restrict__ emark, int epoch,
+                              int8_t* __restrict__ ecls) {
     int e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= G.N1 * G.N2) return;
+    if (emark[e] == epoch) {
+        ecls[e] = EL_CUT;
+        return;
+    }
     int e1 = e % G.N1, e2 = e / G.N1;
     double x = 0.5 * (G.bp1[e1] + G.bp1[e1 + 1]), y = 0.5 * (G.bp2[e2] + G.bp2[e2 + 1]);
     ecls[e] = in_any_hole(T, x, y) ? EL_OUTSIDE : EL_INSIDE;
-}
-
-__global__ void k_mark_cut(TrimDev T, int N1, int8_t* __restrict__ ecls) {
-    int a = blockIdx.x * blockDim.x + threadIdx.x;
-    if (a >= T.cap_arcs) return;
-    const ArcDev A = T.arcs[a];
-    if (A.keep) ecls[A.e2 * N1 + A.e1] = EL_CUT;
 }
 
 struct ClassArgs {
@@ -615,11 +653,9 @@ __global__ void k_elem_flags(ClassArgs A) {
 
 void launch_trim_classes(Plan& P, hipStream_t s) {
     TrimDev& T = P.trim;
-    GridDev G{P.dir[0].bp, P.dir[1].bp, P.N1, P.N2};
+    GridDev G{P.dir[0].knots + P.p, P.dir[1].knots + P.p, P.N1, P.N2};  // breakpoints
     int ne = P.N1 * P.N2;
-    hipLaunchKernelGGL(k_elem_centre, dim3((ne + 127) / 128), dim3(128), 0, s, T, G, P.ecls);
-    if (T.n_curves > 0)
-        hipLaunchKernelGGL(k_mark_cut, dim3((T.cap_arcs + 127) / 128), dim3(128), 0, s, T, P.N1, P.ecls);
+    hipLaunchKernelGGL(k_elem_centre, dim3((ne + 127) / 128), dim3(128), 0, s, T, G, P.emark, P.epoch, P.ecls);
     int nf = P.n1 * P.n2;
     int* f_active = P.flags;
     int* f_cut = P.flags + (nf + 1);
@@ -802,69 +838,125 @@ __device__ __forceinline__ int arc_nq(const CutArgs& A, const CurveDev& C) {
     return d * (2 * A.p + 1);
 }
 
-// One wavefront per cut element: lanes 0..3 build the visible pieces of the
-// four edges; every lane adds its share of sum |w| of the four bases over the
-// arcs' Gauss points; lane 0 picks the base and the node count.
+constexpr int kMaxArcsPerElem = 64;
+
+// One wavefront per cut element. (1) one lane per arc of the element loads the
+// arc, its piece and segment and evaluates its ends; (2) lanes 0..3, one per
+// edge (0 left, 1 right, 2 bottom, 3 top), collect the arc ends lying on the
+// edge -- crossings of that grid line, and piece ends (extrema or segment
+// junctions) that lie on it -- sort them and list the sub-intervals between;
+// (3) all lanes test the sub-intervals' midpoints against the holes; (4) lanes
+// 0..3 merge the visible sub-intervals; (5) every lane adds its share of
+// sum |w| of the four bases over the arcs' Gauss points; lane 0 picks the base
+// and the node count.
 __global__ void __launch_bounds__(64) k_cutprep(CutArgs A) {
     const int c = blockIdx.x;
     if (c >= A.n_cut) return;
     const TrimDev& T = A.T;
     const int lane = threadIdx.x;
+    __shared__ double sEnd[kMaxArcsPerElem][2][2];   // (X, Y) at t0, t1
+    __shared__ int sKind[kMaxArcsPerElem][2][2];     // (kind, line) at t0, t1
+    __shared__ double sT[kMaxArcsPerElem][2];        // t0, t1
+    __shared__ int sSeg[kMaxArcsPerElem], sCurve[kMaxArcsPerElem];
+    __shared__ double sIv[4][kMaxEdgeCuts + 1][2];   // sub-intervals per edge
+    __shared__ int sIvOk[4][kMaxEdgeCuts + 1];        // -1 too short, 0 in a hole, 1 visible
+    __shared__ int sNiv[4];
     __shared__ double sLen[4];
     __shared__ int sOverflow;
     const int e = A.cut_list[c];
     const int e1 = e % A.G.N1, e2 = e / A.G.N1;
     const double xa = A.G.bp1[e1], xb = A.G.bp1[e1 + 1], ya = A.G.bp2[e2], yb = A.G.bp2[e2 + 1];
     const int alo = A.arc_off[c], ahi = A.arc_off[c + 1];
+    const int na = min(ahi - alo, kMaxArcsPerElem);
     CutElemDev& out = A.cut_el[c];
-    if (lane == 0) sOverflow = 0;
+    if (lane == 0) sOverflow = (ahi - alo > kMaxArcsPerElem);
+    // (1) arcs, one lane each
+    for (int q = lane; q < na; q += 64) {
+        const ArcDev R = T.arcs[A.arc_list[alo + q]];
+        const int sidx = T.pieces[R.piece].seg;
+        const SegDev S = T.segs[sidx];
+        double X, Y, dX, dY;
+        seg_eval(S, R.t0, X, Y, dX, dY);
+        sEnd[q][0][0] = X;
+        sEnd[q][0][1] = Y;
+        seg_eval(S, R.t1, X, Y, dX, dY);
+        sEnd[q][1][0] = X;
+        sEnd[q][1][1] = Y;
+        sKind[q][0][0] = R.k0;
+        sKind[q][0][1] = R.l0;
+        sKind[q][1][0] = R.k1;
+        sKind[q][1][1] = R.l1;
+        sT[q][0] = R.t0;
+        sT[q][1] = R.t1;
+        sSeg[q] = sidx;
+        sCurve[q] = R.curve;
+    }
     __syncthreads();
+    // (2) edge cut points and sub-intervals
     if (lane < 4) {
         const int edge = lane;
         double cuts[kMaxEdgeCuts];
         int n = 0;
         bool overflow = false;
-        for (int q = alo; q < ahi; ++q) {
-            const ArcDev R = T.arcs[A.arc_list[q]];
-            const SegDev S = T.segs[T.pieces[R.piece].seg];
+        const double ref = (edge == 0) ? xa : (edge == 1) ? xb : (edge == 2) ? ya : yb;
+        const double h = (edge < 2) ? xb - xa : yb - ya;
+        for (int q = 0; q < na; ++q) {
             for (int end = 0; end < 2; ++end) {
-                int kind = end ? R.k1 : R.k0, line = end ? R.l1 : R.l0;
-                double X, Y, dX, dY;
-                seg_eval(S, end ? R.t1 : R.t0, X, Y, dX, dY);
+                const int kind = sKind[q][end][0], line = sKind[q][end][1];
+                const double X = sEnd[q][end][0], Y = sEnd[q][end][1];
                 bool on = false;
                 if (kind == END_VLINE) on = (line == e1 + (edge == 1)) && edge < 2;
                 else if (kind == END_HLINE) on = (line == e2 + (edge == 3)) && edge >= 2;
-                else {
-                    // a piece end (extremum or segment junction) that lies on a grid line: the
-                    // half-open crossing count gives that crossing to the neighbouring piece only
-                    const double ref = (edge == 0) ? xa : (edge == 1) ? xb : (edge == 2) ? ya : yb;
-                    const double h = (edge < 2) ? xb - xa : yb - ya;
-                    on = fabs(((edge < 2) ? X : Y) - ref) <= 1e-12 * h;
-                }
+                // a piece end (extremum or segment junction) on a grid line: the half-open
+                // crossing count gives that crossing to the neighbouring piece only
+                else on = fabs(((edge < 2) ? X : Y) - ref) <= 1e-12 * h;
                 if (!on) continue;
                 if (n < kMaxEdgeCuts) cuts[n++] = (edge < 2) ? Y : X;
                 else overflow = true;
             }
         }
         for (int a = 1; a < n; ++a) {
-            double v = cuts[a];
+            const double v = cuts[a];
             int b = a - 1;
             while (b >= 0 && cuts[b] > v) { cuts[b + 1] = cuts[b]; --b; }
             cuts[b + 1] = v;
         }
         const double lo = (edge < 2) ? ya : xa, hi = (edge < 2) ? yb : xb;
+        const double tol = 1e-13 * (hi - lo);
+        double prev = lo;
+        for (int q = 0; q <= n; ++q) {
+            const double a = prev;
+            const double b = (q == n) ? hi : fmin(fmax(cuts[q], lo), hi);
+            prev = b;
+            sIv[edge][q][0] = a;
+            sIv[edge][q][1] = b;
+            sIvOk[edge][q] = (b - a <= tol) ? -1 : 0;
+        }
+        sNiv[edge] = n + 1;
+        if (overflow) sOverflow = 1;
+    }
+    __syncthreads();
+    // (3) hole tests of the sub-intervals' midpoints, all lanes
+    for (int u = lane; u < 4 * (kMaxEdgeCuts + 1); u += 64) {
+        const int edge = u / (kMaxEdgeCuts + 1), q = u % (kMaxEdgeCuts + 1);
+        if (q >= sNiv[edge] || sIvOk[edge][q] < 0) continue;
         const double fixed = (edge == 0) ? xa : (edge == 1) ? xb : (edge == 2) ? ya : yb;
+        const double m = 0.5 * (sIv[edge][q][0] + sIv[edge][q][1]);
+        const double x = (edge < 2) ? fixed : m, y = (edge < 2) ? m : fixed;
+        sIvOk[edge][q] = in_any_hole(T, x, y) ? 0 : 1;
+    }
+    __syncthreads();
+    // (4) merge the visible sub-intervals
+    if (lane < 4) {
+        const int edge = lane;
+        const double lo = (edge < 2) ? ya : xa, hi = (edge < 2) ? yb : xb;
         const double tol = 1e-13 * (hi - lo);
         int ns = 0;
-        double prev = lo, len = 0.0, last_hi = 0.0;
-        for (int q = 0; q <= n; ++q) {
-            double a = prev;
-            double b = (q == n) ? hi : fmin(fmax(cuts[q], lo), hi);
-            prev = b;
-            if (b - a <= tol) continue;
-            double m = 0.5 * (a + b);
-            double x = (edge < 2) ? fixed : m, y = (edge < 2) ? m : fixed;
-            if (in_any_hole(T, x, y)) continue;
+        bool overflow = false;
+        double len = 0.0, last_hi = 0.0;
+        for (int q = 0; q < sNiv[edge]; ++q) {
+            if (sIvOk[edge][q] != 1) continue;
+            const double a = sIv[edge][q][0], b = sIv[edge][q][1];
             if (ns > 0 && fabs(last_hi - a) <= tol) {
                 out.seg[edge][ns - 1][1] = b;
             } else if (ns < kMaxEdgeSegs) {
@@ -882,17 +974,17 @@ __global__ void __launch_bounds__(64) k_cutprep(CutArgs A) {
         sLen[edge] = len;
         if (overflow) sOverflow = 1;
     }
-    // sum |w| of the four bases over the arcs' Gauss points
+    // (5) sum |w| of the four bases over the arcs' Gauss points
     double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
     int narc_nodes = 0;
-    for (int q = alo; q < ahi; ++q) {
-        const ArcDev R = T.arcs[A.arc_list[q]];
-        const SegDev S = T.segs[T.pieces[R.piece].seg];
-        const int nq = arc_nq(A, T.curves[R.curve]);
+    for (int q = 0; q < na; ++q) {
+        const SegDev S = T.segs[sSeg[q]];
+        const int nq = arc_nq(A, T.curves[sCurve[q]]);
         narc_nodes += nq * A.n_r;
+        const double t0 = sT[q][0], t1 = sT[q][1];
         for (int g = lane; g < nq; g += 64) {
-            double tq = R.t0 + (R.t1 - R.t0) * (A.gx[gauss_off(nq) + g] + 1.0) * 0.5;
-            double wt = A.gw[gauss_off(nq) + g] * (R.t1 - R.t0) * 0.5;
+            const double tq = t0 + (t1 - t0) * (A.gx[gauss_off(nq) + g] + 1.0) * 0.5;
+            const double wt = A.gw[gauss_off(nq) + g] * (t1 - t0) * 0.5;
             double X, Y, dX, dY;
             seg_eval(S, tq, X, Y, dX, dY);
             s0 += wt * fabs(dY) * fabs(X - xa);
@@ -928,7 +1020,7 @@ void launch_trim_cutprep(Plan& P, hipStream_t s) {
     TrimDev& T = P.trim;
     int nc = (int)P.n_cut_el;
     if (T.n_curves == 0 || nc == 0) return;
-    GridDev G{P.dir[0].bp, P.dir[1].bp, P.N1, P.N2};
+    GridDev G{P.dir[0].knots + P.p, P.dir[1].knots + P.p, P.N1, P.N2};  // breakpoints
     hipLaunchKernelGGL(k_zero_int2, dim3((nc + 1 + 127) / 128), dim3(128), 0, s, P.arc_cnt, P.arc_fill, nc + 1);
     hipLaunchKernelGGL(k_arc_count, dim3((T.cap_arcs + 127) / 128), dim3(128), 0, s, T, P.N1, P.cut_id, P.arc_cnt);
     exclusive_scan(P.arc_cnt, P.arc_off, nc, P.scan_tmp, s);
@@ -1011,7 +1103,7 @@ void launch_trim_nodes(Plan& P, hipStream_t s) {
     TrimDev& T = P.trim;
     int nc = (int)P.n_cut_el;
     if (T.n_curves == 0 || nc == 0) return;
-    GridDev G{P.dir[0].bp, P.dir[1].bp, P.N1, P.N2};
+    GridDev G{P.dir[0].knots + P.p, P.dir[1].knots + P.p, P.N1, P.N2};  // breakpoints
     CutArgs A{T, G, nc, P.cut_list, P.arc_off, P.arc_list, P.cut_el, P.node_cnt,
               P.n_r, P.n_q_override, P.n_s, P.p, P.gauss_x, P.gauss_w, P.status};
     hipLaunchKernelGGL(k_cut_nodes, dim3(nc), dim3(64), 0, s, A, P.node_off, P.node_x, P.node_y, P.node_w, P.node_el);
@@ -1020,38 +1112,6 @@ void launch_trim_nodes(Plan& P, hipStream_t s) {
 }  // namespace iga
 
 namespace iga {
-
-// Orientation of each curve: sign of (1/2) closed integral of (x dy - y dx),
-// exact by Gauss on each polynomial segment; a hole traversed with the
-// visible domain on its left is clockwise, so sigma = -1 for a
-// counter-clockwise native orientation.
-__global__ void __launch_bounds__(64) k_orientation(TrimDev T, CurveDev* __restrict__ curves,
-                                                    const double* __restrict__ gx, const double* __restrict__ gw) {
-    int c = blockIdx.x;
-    if (c >= T.n_curves) return;
-    CurveDev C = curves[c];
-    double area = 0.0;
-    const int ng = 8;
-    for (int s = threadIdx.x; s < C.n_seg; s += 64) {
-        const SegDev S = T.segs[C.seg0 + s];
-        for (int g = 0; g < ng; ++g) {
-            double t = C.t_range * (gx[gauss_off(ng) + g] + 1.0) * 0.5;
-            double w = gw[gauss_off(ng) + g] * C.t_range * 0.5;
-            double X, Y, dX, dY;
-            seg_eval(S, t, X, Y, dX, dY);
-            area += 0.5 * w * (X * dY - Y * dX);
-        }
-    }
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) area += __shfl_xor(area, o, 64);
-    if (threadIdx.x == 0) curves[c].sigma = (area > 0.0) ? -1.0 : 1.0;
-}
-
-void launch_orientation(Plan& P, hipStream_t s) {
-    if (P.trim.n_curves == 0) return;
-    hipLaunchKernelGGL(k_orientation, dim3(P.trim.n_curves), dim3(64), 0, s, P.trim, P.d_curves, P.gauss_x,
-                       P.gauss_w);
-}
 
 // Naive weighted quadrature (Table 1): c set to zero at WQ points in a hole.
 __global__ void k_naive_mask(TrimDev T, DirDev D1, DirDev D2, const double* __restrict__ src, double cval,
