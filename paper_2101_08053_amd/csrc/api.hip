@@ -18,7 +18,7 @@ void set_error(const std::string& msg) { g_last_error = msg; }
 
 Plan::~Plan() {
     if (sw.h_scal) hipHostFree(sw.h_scal);
-    for (hipEvent_t e : {ev_fork, ev_tables, ev_lists, ev_interior})
+    for (hipEvent_t e : {ev_fork, ev_tables, ev_lists, ev_interior, ev_band})
         if (e) hipEventDestroy(e);
     if (aux) hipStreamDestroy(aux);
     for (auto& e : ev_pool) hipEventDestroy(e);
@@ -70,18 +70,18 @@ static void setup_tables(Plan& P, hipStream_t s) {
     launch_dwq_sides(P, s);
 }
 
-// Trimming, classes, lists, cut rules and rule points. `tables_ready`, if
-// given, is waited for before the first kernel that reads the univariate
-// tables (the rule points); the trimming reads the knots directly.
-static void setup_trim(Plan& P, hipStream_t s, bool discover, hipEvent_t tables_ready);
+// Trimming, classes, lists, cut rules and (with `points`) the grid and band
+// entries of the rule-point table. The trimming reads the knots directly;
+// only the rule points read the univariate tables.
+static void setup_trim(Plan& P, hipStream_t s, bool discover, bool points);
 
 static void run_setup(Plan& P, hipStream_t s, bool discover) {
     if (discover) launch_gauss_table(P, s);  // a constant table: once per plan
     setup_tables(P, s);
-    setup_trim(P, s, discover, nullptr);
+    setup_trim(P, s, discover, true);
 }
 
-static void setup_trim(Plan& P, hipStream_t s, bool discover, hipEvent_t tables_ready) {
+static void setup_trim(Plan& P, hipStream_t s, bool discover, bool points) {
     ++P.epoch;
     TrimDev& T = P.trim;
     if (T.n_curves > 0) {
@@ -96,6 +96,7 @@ static void setup_trim(Plan& P, hipStream_t s, bool discover, hipEvent_t tables_
             T.cross = P.alloc<CrossDev>(T.cap_cross);
             T.merged = P.alloc<CrossDev>(T.cap_cross);
             T.arcs = P.alloc<ArcDev>(std::max(T.cap_arcs, 1));
+            P.arc_next = P.alloc<int>(std::max(T.cap_arcs, 1));
         }
         launch_trim_arcs(P, s);
     }
@@ -111,10 +112,6 @@ static void setup_trim(Plan& P, hipStream_t s, bool discover, hipEvent_t tables_
         P.n_cut_el = c[2];
         P.n_band = c[3];
         int nc = (int)P.n_cut_el;
-        P.arc_cnt = P.alloc<int>(nc + 1);
-        P.arc_off = P.alloc<int>(nc + 1);
-        P.arc_fill = P.alloc<int>(nc + 1);
-        P.arc_list = P.alloc<int>(std::max(T.cap_arcs, 1));
         P.cut_el = P.alloc<CutElemDev>(std::max(nc, 1));
         P.node_cnt = P.alloc<int>(nc + 1);
         P.node_off = P.alloc<int>(nc + 1);
@@ -124,7 +121,13 @@ static void setup_trim(Plan& P, hipStream_t s, bool discover, hipEvent_t tables_
     launch_trim_cutprep(P, s);
     if (discover) {
         P.n_nodes = (P.n_cut_el > 0) ? d2h1(P.node_off + P.n_cut_el, s) : 0;
-        P.n_arcs = (P.n_cut_el > 0) ? d2h1(P.arc_off + P.n_cut_el, s) : 0;
+        P.n_arcs = 0;
+        if (P.n_cut_el > 0) {
+            std::vector<CutElemDev> ce((size_t)P.n_cut_el);
+            HIPX(hipMemcpyAsync(ce.data(), P.cut_el, ce.size() * sizeof(CutElemDev), hipMemcpyDeviceToHost, s));
+            HIPX(hipStreamSynchronize(s));
+            for (const CutElemDev& E : ce) P.n_arcs += E.narc;
+        }
         size_t nn = std::max<int64_t>(P.n_nodes, 1);
         P.node_x = P.alloc<double>(nn);
         P.node_y = P.alloc<double>(nn);
@@ -142,8 +145,7 @@ static void setup_trim(Plan& P, hipStream_t s, bool discover, hipEvent_t tables_
         if (P.method == IGA_NAIVE_WQ) P.c_wq_masked = P.alloc<double>(nq);
     }
     launch_trim_nodes(P, s);
-    if (tables_ready) HIPX(hipStreamWaitEvent(s, tables_ready, 0));
-    launch_points(P, s);
+    if (points) launch_points(P, s);
     if (discover) {
         check_status(P, s);
         int nf = P.n1 * P.n2;
@@ -224,6 +226,10 @@ static void form(Plan& P, const iga_coeff& c, double* vals, int flags, hipStream
     }
     const bool full = (flags & IGA_FORM_FULL) != 0;
     hipStream_t a = P.aux;
+    // aux stream: univariate tables and weights, c on the WQ grid and the band
+    // Gauss points, interior rows, rule points; the caller's stream: trimming,
+    // classes, lists, cut rules, c at the cut nodes, cut element matrices, the
+    // rows formed element-wise.
     HIPX(hipEventRecord(P.ev_fork, s));
     HIPX(hipStreamWaitEvent(a, P.ev_fork, 0));
     if (full) setup_tables(P, a);
@@ -234,20 +240,24 @@ static void form(Plan& P, const iga_coeff& c, double* vals, int flags, hipStream
     HIPX(hipEventRecord(P.ev_tables, a));
     if (full) {
         PhaseTimer t(P, s, IGA_PHASE_SETUP);
-        setup_trim(P, s, false, P.ev_tables);
+        setup_trim(P, s, false, false);
     } else {
         HIPX(hipEventRecord(P.ev_lists, s));
     }
     HIPX(hipStreamWaitEvent(a, P.ev_lists, 0));
+    launch_coef(P, c, a, 3);
+    HIPX(hipEventRecord(P.ev_band, a));
     {
         PhaseTimer t(P, a, IGA_PHASE_INTERIOR);
         launch_interior_rows(P, c, vals, a);
     }
+    if (full) launch_points(P, a);
     HIPX(hipEventRecord(P.ev_interior, a));
     {
         PhaseTimer t(P, s, IGA_PHASE_CUT);
-        launch_coef(P, c, s, 2);
-        launch_cut_rows(P, c, vals, s);
+        if (full) HIPX(hipStreamWaitEvent(s, P.ev_tables, 0));
+        launch_coef(P, c, s, 4);
+        launch_cut_rows(P, c, vals, s, P.ev_band);
         launch_dwq_rows(P, c, vals, s);
     }
     HIPX(hipStreamWaitEvent(s, P.ev_interior, 0));
@@ -311,7 +321,7 @@ int iga_plan_create(const iga_patch_desc* desc, const iga_opts* opts, iga_plan**
     std::unique_ptr<iga_plan> guard(P);
     HIPX(hipGetDevice(&P->device));
     HIPX(hipStreamCreateWithFlags(&P->aux, hipStreamNonBlocking));
-    for (hipEvent_t* e : {&P->ev_fork, &P->ev_tables, &P->ev_lists, &P->ev_interior})
+    for (hipEvent_t* e : {&P->ev_fork, &P->ev_tables, &P->ev_lists, &P->ev_interior, &P->ev_band})
         HIPX(hipEventCreateWithFlags(e, hipEventDisableTiming));
     P->p = p;
     P->method = desc->method;
@@ -382,6 +392,8 @@ int iga_plan_create(const iga_patch_desc* desc, const iga_opts* opts, iga_plan**
     P->gauss_w = P->alloc<double>(gauss_off(IGA_MAX_GAUSS + 1));
     P->status = P->alloc<int>(1);
     P->counts = P->alloc<int>(16);
+    P->tickets = P->alloc<int>(8);
+    HIPX(hipMemsetAsync(P->tickets, 0, 8 * sizeof(int), s));
     HIPX(hipMemsetAsync(P->status, 0, sizeof(int), s));
 
     // curves
@@ -437,11 +449,16 @@ int iga_plan_create(const iga_patch_desc* desc, const iga_opts* opts, iga_plan**
         T.cross_cnt = P->alloc<int>(T.cap_pieces + 1);
         T.nv = P->alloc<int>(T.cap_pieces + 1);
         T.cross_off = P->alloc<int>(T.cap_pieces + 1);
+        T.row_cnt = P->alloc<int>(P->N2);
+        T.row_key = P->alloc<double>((size_t)P->N2 * kRowCross);
+        T.row_curve = P->alloc<int>((size_t)P->N2 * kRowCross);
     }
     int nf = P->n1 * P->n2, ne = P->N1 * P->N2;
     P->ecls = P->alloc<int8_t>(ne);
     P->emark = P->alloc<int>(ne);
     HIPX(hipMemsetAsync(P->emark, 0, sizeof(int) * (size_t)ne, s));
+    P->ehead = P->alloc<unsigned long long>(ne);
+    HIPX(hipMemsetAsync(P->ehead, 0, sizeof(unsigned long long) * (size_t)ne, s));
     P->cut_id = P->alloc<int>(ne);
     P->band_id = P->alloc<int>(ne);
     P->cut_list = P->alloc<int>(ne);
@@ -647,7 +664,7 @@ int iga_plan_set_cut_nodes(iga_plan* P, const double* x, const double* y, const 
         HIPX(hipMemcpyAsync(P->node_x, x, n * sizeof(double), hipMemcpyDefault, s));
         HIPX(hipMemcpyAsync(P->node_y, y, n * sizeof(double), hipMemcpyDefault, s));
         HIPX(hipMemcpyAsync(P->node_w, w, n * sizeof(double), hipMemcpyDefault, s));
-        launch_points(*P, s);
+        launch_points(*P, s, true);
     }
     API_END
 }

@@ -20,7 +20,8 @@
 namespace iga {
 
 // ------------------------------------------------------------ points
-// Coordinates of every rule point: the WQ grid, the band Gauss points, the cut nodes.
+// Coordinates of the WQ grid and band Gauss points in the rule-point table,
+// and of the cut nodes if given (the set-up's node kernel writes those itself).
 __global__ void k_points(DirDev D1, DirDev D2, int p, const int* __restrict__ band_list, int nb,
                          const double* __restrict__ nx, const double* __restrict__ ny, int nn,
                          double* __restrict__ xy) {
@@ -47,13 +48,14 @@ __global__ void k_points(DirDev D1, DirDev D2, int p, const int* __restrict__ ba
     xy[2 * t + 1] = y;
 }
 
-void launch_points(Plan& P, hipStream_t s) {
+void launch_points(Plan& P, hipStream_t s, bool with_nodes) {
     DirDev &D1 = P.dir[0], &D2 = P.dir[1];
     const int64_t nq = (int64_t)D1.Q * D2.Q;
     const int nb = (int)P.n_band * (P.p + 1) * (P.p + 1);
-    const int64_t n = nq + nb + P.n_nodes;
+    const int nn = with_nodes ? (int)P.n_nodes : 0;
+    const int64_t n = nq + nb + nn;
     hipLaunchKernelGGL(k_points, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, D1, D2, P.p, P.band_list, nb,
-                       P.node_x, P.node_y, (int)P.n_nodes, P.pts_xy);
+                       P.node_x, P.node_y, nn, P.pts_xy);
 }
 
 // ------------------------------------------------------- coefficient
@@ -88,12 +90,12 @@ CoefArgs coef_args(Plan& P, const iga_coeff& c) {
                     (int64_t)P.dir[0].Q * P.dir[1].Q, (int64_t)P.n_band * (P.p + 1) * (P.p + 1)};
 }
 
-// part: 0 every rule point, 1 the WQ grid only, 2 band Gauss points and cut nodes only
 void launch_coef(Plan& P, const iga_coeff& c, hipStream_t s, int part) {
     if (c.kind != IGA_COEF_GEOM_DETJ) return;
     CoefArgs A = coef_args(P, c);
-    const int64_t t0 = (part == 2) ? A.nq : 0;
-    const int64_t t1 = (part == 1) ? A.nq : A.nq + A.nb + A.n_nodes;
+    // part 0: every rule point; 1: the WQ grid; 2: band Gauss points and cut nodes; 3: band; 4: cut nodes
+    const int64_t t0 = (part == 2 || part == 3) ? A.nq : (part == 4 ? A.nq + A.nb : 0);
+    const int64_t t1 = (part == 1) ? A.nq : (part == 3 ? A.nq + A.nb : A.nq + A.nb + A.n_nodes);
     if (t1 <= t0) return;
     dim3 g((unsigned)((t1 - t0 + 255) / 256)), b(256);
     switch (P.p) {
@@ -177,7 +179,7 @@ __global__ void __launch_bounds__((((2 * P + 1) * (2 * P + 1) + 63) / 64) * 64) 
     cut_row_body<P>(A, blockIdx.x, S);
 }
 
-void launch_cut_rows(Plan& P, const iga_coeff& c, double* vals, hipStream_t s) {
+void launch_cut_rows(Plan& P, const iga_coeff& c, double* vals, hipStream_t s, hipEvent_t before_rows) {
     if (P.method == IGA_NAIVE_WQ) return;
     if (P.n_cut_el > 0) {
         CutEArgs A = cute_args(P, c);
@@ -190,6 +192,7 @@ void launch_cut_rows(Plan& P, const iga_coeff& c, double* vals, hipStream_t s) {
             default: throw Error{IGA_E_UNSUPPORTED, "degree outside 1..8"};
         }
     }
+    if (before_rows) HIPX(hipStreamWaitEvent(s, before_rows, 0));
     if (P.n_form_rows > 0) {
         CutRowArgs A = cutr_args(P, c, vals);
         int W = 2 * P.p + 1;

@@ -326,6 +326,10 @@ struct CutECfg {
     static constexpr int L = (P + 1) * (P + 1);
     static constexpr int CH = (P <= 4) ? 256 : ((P <= 6) ? 128 : 64);  // nodes staged at a time
     static constexpr int NR = P * (P + 1) / 2;                          // reciprocal denominators per direction
+    static constexpr int T = (L + 15) / 16;                             // 16-wide blocks of the local basis
+    static constexpr int NT = T * (T + 1) / 2;                          // 16 x 16 tiles of the upper triangle
+    static constexpr int KS = (NT == 1) ? 4 : 1;                        // wavefronts sharing one tile's nodes
+    static constexpr int TPW = (NT + 3) / 4;                            // tiles per wavefront (KS == 1)
 };
 
 template <int P>
@@ -335,38 +339,54 @@ struct CutESmem {
     double sRec[2][CutECfg<P>::NR + 1];
 };
 
-// Local matrix of cut element c (256 threads): the element's nodes are
-// staged CH at a time with their basis products (one node per thread, the
-// element's reciprocal knot differences shared, so no divisions per node);
-// thread t owns entries of the upper triangle and mirrors them.
+typedef double mfma_f64x4 __attribute__((ext_vector_type(4)));
+
+// Upper-triangle tile t -> block row I <= block column J (row-major).
+__device__ __forceinline__ void tile_ij(int t, int T, int& I, int& J) {
+    I = 0;
+    while (t >= T - I) {
+        t -= T - I;
+        ++I;
+    }
+    J = I + t;
+}
+
+// Local matrix of cut element c (256 threads): E = sum_n w_n c_n phi_n phi_n^T
+// over the element's nodes, a Gram product contracted on the matrix cores.
+// Nodes are staged CH at a time with their basis products (one node per
+// thread, the element's reciprocal knot differences shared, so no divisions
+// per node). The L x L result is cut into 16 x 16 tiles of its upper
+// triangle; each MFMA step (v_mfma_f64_16x16x4) takes four nodes, lane l
+// holding phi at node l / 16 for basis 16 I + l % 16 (times w c for the row
+// operand) and basis 16 J + l % 16 for the column operand. With one tile
+// (p <= 3) the four wavefronts split the nodes and add their partial tiles
+// in a fixed order; otherwise the wavefronts split the tiles. The lower
+// triangle is the mirror of the upper one.
 template <int P>
 __device__ __forceinline__ void cut_elem_body(const CutEArgs& A, int c, CutESmem<P>& S) {
     using C = CutECfg<P>;
-    constexpr int L = C::L, CH = C::CH, NR = C::NR;
-    constexpr int NE = L * (L + 1) / 2;
-    constexpr int PER = (NE + 255) / 256;
+    constexpr int L = C::L, CH = C::CH, NR = C::NR, T = C::T, NT = C::NT, KS = C::KS, TPW = C::TPW;
+    static_assert(CH % 4 == 0, "nodes are contracted four at a time");
+    static_assert(KS == 1 || sizeof(S.sPhi) >= 4 * 256 * sizeof(double), "partial tiles reuse the node stage");
     auto& sPhi = S.sPhi;
     auto& sWc = S.sWc;
     if (c >= A.n_cut) return;
     const int e = A.cut_list[c], e1 = e % A.d1.N, e2 = e / A.d1.N;
     const int nb = A.node_off[c], ne = A.node_off[c + 1];
-    double acc[PER];
-    int el[PER], em[PER];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int kq = lane >> 4, col = lane & 15;      // node within a step, basis within a block
+    int tI[TPW], tJ[TPW];
+    bool tOn[TPW];
 #pragma unroll
-    for (int k = 0; k < PER; ++k) {
-        acc[k] = 0.0;
-        int t = threadIdx.x + 256 * k;
-        int l = 0, rem = t;
-        while (l < L && rem >= L - l) { rem -= L - l; ++l; }   // upper-triangle enumeration
-        el[k] = (t < NE) ? l : -1;
-        em[k] = (t < NE) ? l + rem : -1;
+    for (int u = 0; u < TPW; ++u) {
+        const int t = (KS == 1) ? wave + 4 * u : 0;
+        tOn[u] = t < NT;
+        tile_ij(tOn[u] ? t : 0, T, tI[u], tJ[u]);
     }
-    int elc[PER], emc[PER];  // clamped: threads past the triangle accumulate a discarded entry
+    mfma_f64x4 acc[TPW];
 #pragma unroll
-    for (int k = 0; k < PER; ++k) {
-        elc[k] = max(el[k], 0);
-        emc[k] = max(em[k], 0);
-    }
+    for (int u = 0; u < TPW; ++u) acc[u] = mfma_f64x4{0.0, 0.0, 0.0, 0.0};
+
     __syncthreads();  // LDS of the previous work item is free
     if (threadIdx.x < 2 * NR) {
         const int d = threadIdx.x / NR, idx = threadIdx.x % NR;
@@ -387,28 +407,58 @@ __device__ __forceinline__ void cut_elem_body(const CutEArgs& A, int c, CutESmem
 #pragma unroll
                     for (int a1 = 0; a1 <= P; ++a1) sPhi[threadIdx.x][a2 * (P + 1) + a1] = B1[a1] * B2[a2];
                 sWc[threadIdx.x] = w * cv;
-            } else {
+            } else {  // rows past the last node contribute zero
                 sWc[threadIdx.x] = 0.0;
 #pragma unroll
                 for (int l = 0; l < L; ++l) sPhi[threadIdx.x][l] = 0.0;
             }
         }
         __syncthreads();
-        const int cnt = min(CH, ne - base);
-        // no branch in the loop body, so the LDS reads of several nodes are issued ahead
-#pragma unroll 8
-        for (int n = 0; n < cnt; ++n) {
+        if (KS == 1 && wave >= NT) continue;
+        const int nsteps = (min(CH, ne - base) + 3) >> 2;
+        for (int k = (KS == 1) ? 0 : wave; k < nsteps; k += KS) {
+            const int n = 4 * k + kq;
             const double wc = sWc[n];
+            double ph[T];
 #pragma unroll
-            for (int k = 0; k < PER; ++k) acc[k] += wc * sPhi[n][elc[k]] * sPhi[n][emc[k]];
+            for (int J = 0; J < T; ++J) {
+                const int l = 16 * J + col;
+                const double v = sPhi[n][l < L ? l : 0];
+                ph[J] = (l < L) ? v : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < TPW; ++u)
+                if (tOn[u]) acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(wc * ph[tI[u]], ph[tJ[u]], acc[u], 0, 0, 0);
         }
     }
     double* E = A.E + (size_t)c * L * L;
+    if constexpr (KS == 1) {
+        // accumulator element v of lane l is row l / 16 + 4 v, column l % 16 of the tile
 #pragma unroll
-    for (int k = 0; k < PER; ++k) {
-        if (el[k] < 0) continue;
-        E[el[k] * L + em[k]] = acc[k];
-        E[em[k] * L + el[k]] = acc[k];
+        for (int u = 0; u < TPW; ++u) {
+            if (!tOn[u]) continue;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int r = 16 * tI[u] + kq + 4 * v, q = 16 * tJ[u] + col;
+                if (r < L && q < L && r <= q) {
+                    E[r * L + q] = acc[u][v];
+                    E[q * L + r] = acc[u][v];
+                }
+            }
+        }
+    } else {
+        double (*sRed)[256] = reinterpret_cast<double (*)[256]>(&sPhi[0][0]);
+        __syncthreads();  // every wavefront is done with the node stage
+#pragma unroll
+        for (int v = 0; v < 4; ++v) sRed[wave][lane * 4 + v] = acc[0][v];
+        __syncthreads();
+        const int ln = threadIdx.x >> 2, v = threadIdx.x & 3;
+        const int r = (ln >> 4) + 4 * v, q = ln & 15;
+        if (r < L && q < L && r <= q) {
+            const double sum = ((sRed[0][threadIdx.x] + sRed[1][threadIdx.x]) + sRed[2][threadIdx.x]) + sRed[3][threadIdx.x];
+            E[r * L + q] = sum;
+            E[q * L + r] = sum;
+        }
     }
 }
 
@@ -432,15 +482,17 @@ struct CutRowArgs {
 // One workgroup per row; the row's per-direction Gauss factors
 // F1[m1][g1][a] = w_g1 B_i1 B_{i1+a-p} (element e1 = i1-p+m1), F2 likewise,
 // the element classes and c at the Gauss points of its support elements are
-// staged in LDS; thread (a, b) then sums over the elements shared with its
-// column: Gauss on inside elements (sum-factorised), the cut element matrix
-// on cut elements.
+// staged in LDS. Inside elements are summed in two contractions: the
+// workgroup first forms U[m2][g2][a] (direction 1, summed over the element
+// columns m1), then thread (a, b) contracts U with F2 and adds its column's
+// entries of the cut element matrices.
 template <int P>
 struct CutRSmem {
     double sF1[P + 1][P + 1][2 * P + 1];
     double sF2[P + 1][P + 1][2 * P + 1];
     double sX[P + 1][P + 1][(P + 1) * (P + 1)];  // inside element: c at its Gauss points (else 0)
     double sE[P + 1][P + 1][(P + 1) * (P + 1)];  // cut element: row i of its local matrix (else 0)
+    double sU[P + 1][P + 1][2 * P + 1];          // direction-1 contraction, summed over m1
     int sCls[P + 1][P + 1];
     int sId[P + 1][P + 1];
 };
@@ -512,31 +564,39 @@ __device__ __forceinline__ void cut_row_body(const CutRowArgs& A, int r, CutRSme
         sE[m2][m1][g] = w;
     }
     __syncthreads();
+    // inside elements, sum-factorised: F2 does not depend on m1, so the direction-1 contraction
+    // is summed over the element columns first, U[m2][g2][a] = sum_m1 sum_g1 F1[m1][g1][a] X[m2][m1][g2][g1]
+    for (int t = tid; t < NP * NP * W; t += nt) {
+        const int m2 = t / (NP * W), g2 = (t / W) % NP, a = t % W;
+        double u = 0.0;
+#pragma unroll
+        for (int m1 = 0; m1 <= P; ++m1)
+#pragma unroll
+            for (int g1 = 0; g1 < NP; ++g1) u += sF1[m1][g1][a] * sX[m2][m1][g2 * NP + g1];
+        S.sU[m2][g2][a] = u;
+    }
+    __syncthreads();
     const int s = tid;
     if (s >= W * W) return;
     const int a = s / W, b = s % W;          // column offsets a-p, b-p
     const int j1 = i1 + a - P, j2 = i2 + b - P;
     double val = 0.0;
     if (j1 >= 0 && j1 < D1.n && j2 >= 0 && j2 < D2.n && A.act_of[j2 * D1.n + j1] >= 0) {
-        // every support element, without branches: the Gauss factors F vanish off the column's
-        // overlap and sX / sE hold zeros where the element is not inside / cut
+#pragma unroll
+        for (int m2 = 0; m2 <= P; ++m2)
+#pragma unroll
+            for (int g2 = 0; g2 < NP; ++g2) val += sF2[m2][g2][b] * S.sU[m2][g2][a];
+        // cut elements: the column's entry of the staged row, zero where the element is not cut
+        // or does not overlap the column's support
 #pragma unroll
         for (int m2 = 0; m2 <= P; ++m2) {
-            const int l2 = j2 - (i2 - P + m2);  // column's local index in the element, direction 2
+            const int l2 = j2 - (i2 - P + m2);
 #pragma unroll
             for (int m1 = 0; m1 <= P; ++m1) {
                 const int l1 = j1 - (i1 - P + m1);
-                double sum = 0.0;
-#pragma unroll
-                for (int g2 = 0; g2 < NP; ++g2) {
-                    double in = 0.0;
-#pragma unroll
-                    for (int g1 = 0; g1 < NP; ++g1) in += sF1[m1][g1][a] * sX[m2][m1][g2 * NP + g1];
-                    sum += sF2[m2][g2][b] * in;
-                }
                 const bool ov = (l1 >= 0 && l1 <= P && l2 >= 0 && l2 <= P);
                 const double ev = sE[m2][m1][ov ? l2 * NP + l1 : 0];
-                val += sum + (ov ? ev : 0.0);
+                val += ov ? ev : 0.0;
             }
         }
     }

@@ -17,6 +17,8 @@ constexpr int kMaxEdgeSegs = 8;     // visible segments per element edge
 constexpr int kMaxEdgeCuts = 16;    // split points per element edge
 constexpr int kMaxPiecesPerSeg = 5; // monotone pieces per curve segment
 constexpr int kMaxIsectPerPiece = 8;
+constexpr int kRowCross = 16;       // centre-line crossings kept per row of elements
+constexpr int kMaxArcsPerElem = 64; // kept arcs per cut element
 
 // Per-direction weighted-quadrature and Gauss tables (device pointers).
 struct DirDev {
@@ -91,7 +93,9 @@ struct CutElemDev {
     int e1, e2;
     int variant;        // 0 left, 1 right, 2 bottom, 3 top base
     int nseg[4];        // visible segments per edge: 0 left, 1 right, 2 bottom, 3 top
+    int narc;           // kept arcs in the element, ascending arc index
     double seg[4][kMaxEdgeSegs][2];
+    int arc[kMaxArcsPerElem];
 };
 
 // Everything the trimming kernels need, passed by value.
@@ -114,6 +118,11 @@ struct TrimDev {
     CrossDev* merged;      // sorted by t per piece
     ArcDev* arcs;          // capacity cap_cross + cap_pieces
     int cap_pieces0, cap_pieces, cap_cross, cap_arcs;
+    // Per row of elements: crossings of spline pieces with the horizontal line
+    // through the row's element centres (key = min(X, piece's largest x)).
+    int* row_cnt;          // N2
+    double* row_key;       // N2 * kRowCross
+    int* row_curve;        // N2 * kRowCross
 };
 
 // Buffers of the L2 projection and the matrix-free product (allocated on first use).
@@ -160,13 +169,13 @@ struct Plan {
     int* form_rows = nullptr;      // rows formed by the element/cut kernel (method dependent)
     int* dwq_region = nullptr;     // [n_form_rows][8] DWQ box of each formed row (lo1 = -1: none)
     int* emark = nullptr;          // [N1*N2] element owns a visible arc iff emark == epoch
+    // [N1*N2] head of the element's list of kept arcs: (epoch << 32) | (arc + 1),
+    // stale when the epoch differs; arc_next[a] is the next arc of a's element or -1
+    unsigned long long* ehead = nullptr;
+    int* arc_next = nullptr;
     int epoch = 0;                 // set-up counter (marks need no clearing)
     int* cut_list = nullptr;       // flat ids of cut elements
     int* band_list = nullptr;      // flat ids of band elements
-    int* arc_cnt = nullptr;        // per cut element
-    int* arc_off = nullptr;
-    int* arc_fill = nullptr;
-    int* arc_list = nullptr;
     CutElemDev* cut_el = nullptr;
     int* node_cnt = nullptr;
     int* node_off = nullptr;
@@ -181,6 +190,7 @@ struct Plan {
     int* scan_tmp = nullptr;       // block sums of a scan, then compaction positions
     int scan_pos_off = 0;
     int* counts = nullptr;         // small device counter block
+    int* tickets = nullptr;        // last-workgroup tickets (zero between launches)
     int* status = nullptr;         // device status word
 
     // points and coefficient values (c_wq [Q2][Q1], c_band, c_cut)
@@ -198,7 +208,7 @@ struct Plan {
     // second stream of the formation: univariate tables, weights, WQ-grid coefficient and interior
     // rows run there, beside the trimming chain (default priority; joined by events)
     hipStream_t aux = nullptr;
-    hipEvent_t ev_fork = nullptr, ev_tables = nullptr, ev_lists = nullptr, ev_interior = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_tables = nullptr, ev_lists = nullptr, ev_interior = nullptr, ev_band = nullptr;
 
     // timing
     bool timing = false;
@@ -275,10 +285,12 @@ void launch_naive_mask(Plan& P, const double* src, double cval, hipStream_t s);
 void launch_row_nnz(Plan& P, int* cnt, int* out, hipStream_t s);
 // form.hip
 CoefView coef_view(Plan& P, const iga_coeff& c);
-void launch_points(Plan& P, hipStream_t s);
+// rule-point coordinates: WQ grid and band Gauss points (and the cut nodes with with_nodes)
+void launch_points(Plan& P, hipStream_t s, bool with_nodes = false);
 void launch_coef(Plan& P, const iga_coeff& c, hipStream_t s, int part = 0);
 void launch_interior_rows(Plan& P, const iga_coeff& c, double* vals, hipStream_t s);
-void launch_cut_rows(Plan& P, const iga_coeff& c, double* vals, hipStream_t s);
+// before_rows: an event the rows wait for after the cut element matrices are launched (or null)
+void launch_cut_rows(Plan& P, const iga_coeff& c, double* vals, hipStream_t s, hipEvent_t before_rows = nullptr);
 // dwq.hip
 void launch_dwq_sides(Plan& P, hipStream_t s);
 void launch_dwq_choose(Plan& P, hipStream_t s);

@@ -126,24 +126,23 @@ __device__ __forceinline__ int upper_bound_i(const int* a, int n, int v) {
 }
 
 // ---------------------------------------------------------- segments
-// Uniform B-spline blending polynomials (power basis, low first) of degree 1..3.
+// Uniform B-spline blending polynomials (power basis, low first) of degree 1..3:
+// rows are the functions, columns the powers.
+__constant__ double kBlend1[2][2] = {{1, -1}, {0, 1}};
+__constant__ double kBlend2[3][3] = {{0.5, -1, 0.5}, {0.5, 1, -1}, {0, 0, 0.5}};
+__constant__ double kBlend3[4][4] = {{1.0 / 6, -0.5, 0.5, -1.0 / 6},
+                                     {4.0 / 6, 0, -1, 0.5},
+                                     {1.0 / 6, 0.5, 0.5, -0.5},
+                                     {0, 0, 0, 1.0 / 6}};
 __device__ __forceinline__ double blend(int d, int l, int pw) {
-    // rows: function l, columns: power
-    const double b1[2][2] = {{1, -1}, {0, 1}};
-    const double b2[3][3] = {{0.5, -1, 0.5}, {0.5, 1, -1}, {0, 0, 0.5}};
-    const double b3[4][4] = {{1.0 / 6, -0.5, 0.5, -1.0 / 6},
-                             {4.0 / 6, 0, -1, 0.5},
-                             {1.0 / 6, 0.5, 0.5, -0.5},
-                             {0, 0, 0, 1.0 / 6}};
-    if (d == 1) return b1[l][pw];
-    if (d == 2) return b2[l][pw];
-    return b3[l][pw];
+    if (d == 1) return kBlend1[l][pw];
+    if (d == 2) return kBlend2[l][pw];
+    return kBlend3[l][pw];
 }
 
-__device__ void segment_make(const TrimDev& T, const double* __restrict__ cp, const int* __restrict__ cp_off, int s) {
-    int c = 0;
-    while (c + 1 < T.n_curves && T.curves[c + 1].seg0 <= s) ++c;
-    const CurveDev C = T.curves[c];
+// Segment s (of curve c) in power form.
+__device__ SegDev segment_form(const CurveDev& C, int c, const double* __restrict__ cp, const int* __restrict__ cp_off,
+                               int s) {
     SegDev S;
     S.curve = c;
     S.seg = s - C.seg0;
@@ -155,77 +154,113 @@ __device__ void segment_make(const TrimDev& T, const double* __restrict__ cp, co
         S.px[0] = C.cx; S.px[1] = C.a * cph; S.px[2] = -C.b * sph;
         S.py[0] = C.cy; S.py[1] = C.a * sph; S.py[2] = C.b * cph;
     } else {
-        int d = C.degree, m = C.n_seg;
-        for (int l = 0; l <= d; ++l) {
-            int idx = (S.seg + l) % m;
-            double x = cp[2 * (cp_off[c] + idx)], y = cp[2 * (cp_off[c] + idx) + 1];
-            for (int pw = 0; pw <= d; ++pw) {
+        // fixed trip counts (degree <= 3), so the coefficients stay in registers
+        const int d = C.degree, m = C.n_seg, o = cp_off[c];
+#pragma unroll
+        for (int l = 0; l <= 3; ++l) {
+            if (l > d) continue;
+            const int idx = (S.seg + l) % m;
+            const double x = cp[2 * (o + idx)], y = cp[2 * (o + idx) + 1];
+#pragma unroll
+            for (int pw = 0; pw <= 3; ++pw) {
+                if (pw > d) continue;
                 S.px[pw] += blend(d, l, pw) * x;
                 S.py[pw] += blend(d, l, pw) * y;
             }
         }
     }
-    T.segs[s] = S;
+    return S;
 }
 
-// Zeros of a + b t + c t^2 in (lo, hi), ascending.
-__device__ int quad_roots(double a, double b, double c, double lo, double hi, double* r) {
-    int n = 0;
+__device__ void segment_make(const TrimDev& T, const double* __restrict__ cp, const int* __restrict__ cp_off, int s) {
+    int c = 0;
+    while (c + 1 < T.n_curves && T.curves[c + 1].seg0 <= s) ++c;
+    T.segs[s] = segment_form(T.curves[c], c, cp, cp_off, s);
+}
+
+// Zeros of a + b t + c t^2 in (lo, hi), ascending, +inf where absent.
+__device__ __forceinline__ void quad_roots(double a, double b, double c, double lo, double hi, double& r0, double& r1) {
+    const double inf = __builtin_inf();
+    r0 = r1 = inf;
     double scale = fabs(a) + fabs(b) + fabs(c);
-    if (scale == 0.0) return 0;
+    if (scale == 0.0) return;
     if (fabs(c) <= 1e-14 * scale) {
         if (fabs(b) > 1e-14 * scale) {
             double t = -a / b;
-            if (t > lo && t < hi) r[n++] = t;
+            if (t > lo && t < hi) r0 = t;
         }
-        return n;
+        return;
     }
     double disc = b * b - 4.0 * a * c;
-    if (disc < 0.0) return 0;
+    if (disc < 0.0) return;
     double q = -0.5 * (b + copysign(sqrt(disc), b));
     double t1 = q / c, t2 = (q != 0.0) ? a / q : t1;
     if (t1 > t2) { double t = t1; t1 = t2; t2 = t; }
-    if (t1 > lo && t1 < hi) r[n++] = t1;
-    if (t2 > lo && t2 < hi && t2 != t1) r[n++] = t2;
-    return n;
+    if (t1 > lo && t1 < hi) r0 = t1;
+    if (t2 > lo && t2 < hi && t2 != t1) r1 = t2;
 }
 
-// Split parameters of segment s (x- and y-extrema), sorted, plus the ends.
-__device__ int segment_splits(const TrimDev& T, int s, double* ts) {
-    const SegDev S = T.segs[s];
-    const CurveDev C = T.curves[S.curve];
-    int n = 0;
-    double lo = 0.0, hi = C.t_range;
-    ts[n++] = lo;
-    double r[8];
-    int nr = 0;
+__device__ __forceinline__ void sort2(double& a, double& b) {
+    const double lo = fmin(a, b), hi = fmax(a, b);
+    a = lo;
+    b = hi;
+}
+
+// Interior split parameters of a segment (the zeros of X' and Y' in (0, hi)),
+// ascending, +inf where absent. The monotone pieces run between 0, every
+// split above the last one used, and hi.
+__device__ __forceinline__ void segment_splits(const SegDev& S, double hi, double r[4]) {
+    const double lo = 0.0, inf = __builtin_inf();
     if (S.kind == IGA_CURVE_ELLIPSE) {
         const double tp = 2.0 * M_PI;
-        double c[4] = {atan2(S.px[2], S.px[1]), atan2(S.px[2], S.px[1]) + M_PI, atan2(S.py[2], S.py[1]),
-                       atan2(S.py[2], S.py[1]) + M_PI};
+        const double c[4] = {atan2(S.px[2], S.px[1]), atan2(S.px[2], S.px[1]) + M_PI, atan2(S.py[2], S.py[1]),
+                             atan2(S.py[2], S.py[1]) + M_PI};
+#pragma unroll
         for (int k = 0; k < 4; ++k) {
             double t = fmod(c[k], tp);
             if (t < 0.0) t += tp;
-            if (t > lo && t < hi) r[nr++] = t;
+            r[k] = (t > lo && t < hi) ? t : inf;
         }
     } else {
-        nr += quad_roots(S.px[1], 2.0 * S.px[2], 3.0 * S.px[3], lo, hi, r + nr);
-        nr += quad_roots(S.py[1], 2.0 * S.py[2], 3.0 * S.py[3], lo, hi, r + nr);
+        quad_roots(S.px[1], 2.0 * S.px[2], 3.0 * S.px[3], lo, hi, r[0], r[1]);
+        quad_roots(S.py[1], 2.0 * S.py[2], 3.0 * S.py[3], lo, hi, r[2], r[3]);
     }
-    for (int a = 1; a < nr; ++a) {  // insertion sort
-        double v = r[a];
-        int b = a - 1;
-        while (b >= 0 && r[b] > v) { r[b + 1] = r[b]; --b; }
-        r[b + 1] = v;
-    }
-    for (int k = 0; k < nr; ++k)
-        if (r[k] > ts[n - 1]) ts[n++] = r[k];
-    ts[n++] = hi;
-    return n;
+    sort2(r[0], r[1]);
+    sort2(r[2], r[3]);
+    sort2(r[0], r[2]);
+    sort2(r[1], r[3]);
+    sort2(r[1], r[2]);
 }
 
-__device__ __forceinline__ PieceDev make_piece(const TrimDev& T, int s, double t0, double t1) {
-    const SegDev S = T.segs[s];
+// Monotone pieces of a segment: candidate k of {r[0..3], hi} closes a piece
+// if it is below hi (or is hi itself) and above the last bound used. Fixed
+// slots, so the arrays stay in registers.
+struct SegPieces {
+    double t0[5], t1[5];
+    bool use[5];
+    int n;
+};
+
+__device__ __forceinline__ SegPieces segment_pieces(double hi, const double r[4]) {
+    SegPieces P;
+    double last = 0.0;
+    P.n = 0;
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+        const double nxt = (k < 4) ? r[k] : hi;
+        const bool use = (k < 4) ? (nxt < hi && nxt > last) : true;
+        P.use[k] = use;
+        P.t0[k] = last;
+        P.t1[k] = nxt;
+        if (use) {
+            last = nxt;
+            ++P.n;
+        }
+    }
+    return P;
+}
+
+__device__ __forceinline__ PieceDev make_piece(const SegDev& S, int s, double t0, double t1) {
     PieceDev Pc;
     Pc.curve = S.curve;
     Pc.seg = s;
@@ -240,22 +275,31 @@ __device__ __forceinline__ PieceDev make_piece(const TrimDev& T, int s, double t
 
 __device__ int block_scan_carry(int v, int* sh, int& total);
 
-// Single block: monotone pieces of every segment, compacted in segment order.
+// Single block: monotone pieces of every segment (already in T.segs),
+// compacted in segment order.
 __device__ void pieces_build(const TrimDev& T, PieceDev* __restrict__ out, int* __restrict__ count,
                              int* __restrict__ curve_off) {
     __shared__ int sh[1024 / 64 + 1];
     int carry = 0;
     for (int base = 0; base < T.n_segs; base += blockDim.x) {
-        int s = base + threadIdx.x;
-        double ts[12];
-        int nt = 0;
-        if (s < T.n_segs) nt = segment_splits(T, s, ts);
-        int np = (nt > 1) ? nt - 1 : 0;
-        int total;
-        int off = block_scan_carry(np, sh, total) + carry;
+        const int s = base + threadIdx.x;
+        SegDev S;
+        SegPieces sp;
+        sp.n = 0;
         if (s < T.n_segs) {
-            for (int k = 0; k < np; ++k) out[off + k] = make_piece(T, s, ts[k], ts[k + 1]);
-            const SegDev S = T.segs[s];
+            S = T.segs[s];
+            double r[4];
+            const double hi = T.curves[S.curve].t_range;
+            segment_splits(S, hi, r);
+            sp = segment_pieces(hi, r);
+        }
+        int total;
+        const int off = block_scan_carry(sp.n, sh, total) + carry;
+        if (s < T.n_segs) {
+            int q = 0;
+#pragma unroll
+            for (int k = 0; k < 5; ++k)
+                if (sp.use[k]) out[off + q++] = make_piece(S, s, sp.t0[k], sp.t1[k]);
             if (S.seg == 0) curve_off[S.curve] = off;
         }
         carry += total;
@@ -373,10 +417,11 @@ __device__ void pieces_split(const TrimDev& T) {
         int off = block_scan_carry(ns, sh, total) + carry;
         if (k < n0) {
             const PieceDev Pc = T.pieces0[k];
+            const SegDev S = T.segs[Pc.seg];
             double a = Pc.t0;
             for (int q = 0; q < ns; ++q) {
                 double b = (q == ns - 1) ? Pc.t1 : T.isect_t[k * kMaxIsectPerPiece + q];
-                T.pieces[off + q] = make_piece(T, Pc.seg, a, b);
+                T.pieces[off + q] = make_piece(S, Pc.seg, a, b);
                 a = b;
             }
             if (k == 0 || T.pieces0[k - 1].curve != Pc.curve) T.piece_curve_off[Pc.curve] = off;
@@ -396,28 +441,37 @@ struct GridDev {
     int N1, N2;
 };
 
-// Crossings of piece k with the vertical (then horizontal) grid lines in its
-// box, counted half-open so that a crossing at a shared end belongs to one piece.
-__device__ __forceinline__ void cross_count_one(const TrimDev& T, const GridDev& G, int k, int np) {
-    if (k >= np) {
-        T.cross_cnt[k] = 0;
-        T.nv[k] = 0;
-        return;
-    }
-    const PieceDev Pc = T.pieces[k];
-    double xmin = fmin(Pc.x0, Pc.x1), xmax = fmax(Pc.x0, Pc.x1);
-    double ymin = fmin(Pc.y0, Pc.y1), ymax = fmax(Pc.y0, Pc.y1);
-    int nv = lower_bound_d(G.bp1, G.N1 + 1, xmax) - lower_bound_d(G.bp1, G.N1 + 1, xmin);
-    int nh = lower_bound_d(G.bp2, G.N2 + 1, ymax) - lower_bound_d(G.bp2, G.N2 + 1, ymin);
-    T.nv[k] = nv;
-    T.cross_cnt[k] = nv + nh;
+// Breakpoints of both directions, staged in LDS by the single-workgroup and
+// per-piece kernels when they fit (the global arrays otherwise).
+constexpr int kLdsBp = 4096;
+struct BpView {
+    const double* b1;
+    const double* b2;
+};
+
+__device__ __forceinline__ BpView stage_bp(const GridDev& G, double* sbp) {
+    const int n1 = G.N1 + 1, n2 = G.N2 + 1;
+    if (n1 + n2 > kLdsBp) return {G.bp1, G.bp2};
+    for (int i = threadIdx.x; i < n1 + n2; i += blockDim.x) sbp[i] = (i < n1) ? G.bp1[i] : G.bp2[i - n1];
+    return {sbp, sbp + n1};  // the caller synchronises before use
 }
 
-// One workgroup of 1024: orientation of every curve (sign of its enclosed area
-// by Gauss on each segment; a hole traversed with the visible domain on its
-// left is clockwise), crossing counts of every piece and their offsets.
+// Crossings of a piece with the vertical (then horizontal) grid lines in its
+// box, counted half-open so that a crossing at a shared end belongs to one piece.
+__device__ __forceinline__ void piece_cross_count(const PieceDev& Pc, const BpView& bp, const GridDev& G, int& nv,
+                                                  int& nh) {
+    const double xmin = fmin(Pc.x0, Pc.x1), xmax = fmax(Pc.x0, Pc.x1);
+    const double ymin = fmin(Pc.y0, Pc.y1), ymax = fmax(Pc.y0, Pc.y1);
+    nv = lower_bound_d(bp.b1, G.N1 + 1, xmax) - lower_bound_d(bp.b1, G.N1 + 1, xmin);
+    nh = lower_bound_d(bp.b2, G.N2 + 1, ymax) - lower_bound_d(bp.b2, G.N2 + 1, ymin);
+}
+
+// Union of holes (one workgroup of 1024, after the curve-curve splits):
+// orientation of every curve (sign of its enclosed area by Gauss on each
+// segment; a hole traversed with the visible domain on its left is
+// clockwise), crossing counts of every piece and their offsets.
 __device__ void curves_orient_count(const TrimDev& T, CurveDev* __restrict__ curves, const GridDev& G,
-                                    const double* __restrict__ gx, const double* __restrict__ gw) {
+                                    const BpView& bp, const double* __restrict__ gx, const double* __restrict__ gw) {
     __shared__ double sh_area[1024 / 64];
     __shared__ int sh[1024 / 64 + 1];
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
@@ -446,7 +500,12 @@ __device__ void curves_orient_count(const TrimDev& T, CurveDev* __restrict__ cur
         __syncthreads();
     }
     const int np = *T.n_pieces;
-    for (int k = tid; k < T.cap_pieces; k += 1024) cross_count_one(T, G, k, np);
+    for (int k = tid; k < T.cap_pieces; k += 1024) {
+        int nv = 0, nh = 0;
+        if (k < np) piece_cross_count(T.pieces[k], bp, G, nv, nh);
+        T.nv[k] = nv;
+        T.cross_cnt[k] = nv + nh;
+    }
     __syncthreads();
     int carry = 0;
     for (int base = 0; base < T.cap_pieces; base += 1024) {
@@ -460,20 +519,114 @@ __device__ void curves_orient_count(const TrimDev& T, CurveDev* __restrict__ cur
     if (tid == 0) T.cross_off[T.cap_pieces] = carry;
 }
 
-// Front of the trimming set-up in one workgroup: segments, monotone pieces,
-// then (single hole) orientation, crossing counts and offsets. For a union
-// of holes only the unsplit pieces are built here.
-__global__ void __launch_bounds__(1024) k_trim_front(TrimDev T, const double* __restrict__ cp,
+// One curve, one workgroup: each thread forms its segment, splits it
+// into monotone pieces and counts their grid-line crossings, all in
+// registers; two block scans place the pieces and their crossings. The
+// segment's 8-point Gauss share of the enclosed area gives the orientation.
+__device__ void front_one_curve(const TrimDev& T, const double* __restrict__ cp, const int* __restrict__ cp_off,
+                                CurveDev* __restrict__ curves, const GridDev& G, const BpView& bp,
+                                const double* __restrict__ gx, const double* __restrict__ gw) {
+    __shared__ int sh[1024 / 64 + 1];
+    __shared__ double sh_area[1024 / 64];
+    constexpr int ng = 8;
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6, nt = blockDim.x;
+    const CurveDev C = curves[0];
+    double gxv[ng], gwv[ng];
+#pragma unroll
+    for (int g = 0; g < ng; ++g) {
+        gxv[g] = gx[gauss_off(ng) + g];
+        gwv[g] = gw[gauss_off(ng) + g];
+    }
+    int carry_p = 0, carry_c = 0;
+    double area = 0.0;
+    for (int base = 0; base < T.n_segs; base += nt) {
+        const int s = base + tid;
+        const bool valid = s < T.n_segs;
+        SegDev S;
+        SegPieces sp;
+        sp.n = 0;
+        if (valid) {
+            S = segment_form(C, 0, cp, cp_off, s);
+            T.segs[s] = S;
+            double r[4];
+            segment_splits(S, C.t_range, r);
+            sp = segment_pieces(C.t_range, r);
+#pragma unroll
+            for (int g = 0; g < ng; ++g) {
+                const double tt = C.t_range * (gxv[g] + 1.0) * 0.5;
+                const double w = gwv[g] * C.t_range * 0.5;
+                double X, Y, dX, dY;
+                seg_eval(S, tt, X, Y, dX, dY);
+                area += 0.5 * w * (X * dY - Y * dX);
+            }
+        }
+        int tot_p, tot_c;
+        const int offp = block_scan_carry(sp.n, sh, tot_p) + carry_p;
+        int cnt[5], nvk[5], csum = 0;
+#pragma unroll
+        for (int k = 0; k < 5; ++k) {
+            cnt[k] = nvk[k] = 0;
+            if (valid && sp.use[k]) {
+                int nh;
+                piece_cross_count(make_piece(S, s, sp.t0[k], sp.t1[k]), bp, G, nvk[k], nh);
+                cnt[k] = nvk[k] + nh;
+                csum += cnt[k];
+            }
+        }
+        const int offc = block_scan_carry(csum, sh, tot_c) + carry_c;
+        if (valid) {
+            int q = offp, run = offc;
+#pragma unroll
+            for (int k = 0; k < 5; ++k) {
+                if (!sp.use[k]) continue;
+                T.pieces[q] = make_piece(S, s, sp.t0[k], sp.t1[k]);
+                T.nv[q] = nvk[k];
+                T.cross_cnt[q] = cnt[k];
+                T.cross_off[q] = run;
+                run += cnt[k];
+                ++q;
+            }
+            if (S.seg == 0) T.piece_curve_off[0] = offp;
+        }
+        carry_p += tot_p;
+        carry_c += tot_c;
+    }
+    for (int k = carry_p + tid; k < T.cap_pieces; k += nt) {
+        T.nv[k] = 0;
+        T.cross_cnt[k] = 0;
+        T.cross_off[k] = carry_c;
+    }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) area += __shfl_xor(area, o, 64);
+    if (lane == 0) sh_area[wid] = area;
+    __syncthreads();
+    if (tid == 0) {
+        *T.n_pieces = carry_p;
+        T.piece_curve_off[1] = carry_p;
+        T.cross_off[T.cap_pieces] = carry_c;
+        double a = 0.0;
+        for (int w = 0; w < nt / 64; ++w) a += sh_area[w];
+        curves[0].sigma = (a > 0.0) ? -1.0 : 1.0;
+    }
+}
+
+// Front of the trimming set-up in one workgroup (256 threads). One curve: segments, pieces,
+// crossing counts and offsets, orientation (front_one_curve). A union of
+// holes: segments and the unsplit pieces only. Both clear the per-row
+// centre-line crossing counts that the arc kernel fills.
+__global__ void __launch_bounds__(256) k_trim_front(TrimDev T, const double* __restrict__ cp,
                                                      const int* __restrict__ cp_off, CurveDev* __restrict__ curves,
                                                      GridDev G, const double* __restrict__ gx,
                                                      const double* __restrict__ gw) {
-    for (int s = threadIdx.x; s < T.n_segs; s += 1024) segment_make(T, cp, cp_off, s);
-    __syncthreads();
+    __shared__ double sbp[kLdsBp];
+    for (int r = threadIdx.x; r < G.N2; r += blockDim.x) T.row_cnt[r] = 0;
     if (T.n_curves == 1) {
-        pieces_build(T, T.pieces, T.n_pieces, T.piece_curve_off);
+        const BpView bp = stage_bp(G, sbp);
         __syncthreads();
-        curves_orient_count(T, curves, G, gx, gw);
+        front_one_curve(T, cp, cp_off, curves, G, bp, gx, gw);
     } else {
+        for (int s = threadIdx.x; s < T.n_segs; s += blockDim.x) segment_make(T, cp, cp_off, s);
+        __syncthreads();
         pieces_build(T, T.pieces0, T.n_pieces0, T.piece_curve_off);
     }
 }
@@ -481,16 +634,18 @@ __global__ void __launch_bounds__(1024) k_trim_front(TrimDev T, const double* __
 // Union of holes: split the pieces where they meet another curve, then orientation and counts.
 __global__ void __launch_bounds__(1024) k_trim_split(TrimDev T, CurveDev* __restrict__ curves, GridDev G,
                                                      const double* __restrict__ gx, const double* __restrict__ gw) {
+    __shared__ double sbp[kLdsBp];
+    const BpView bp = stage_bp(G, sbp);
     pieces_split(T);
     __syncthreads();
-    curves_orient_count(T, curves, G, gx, gw);
+    curves_orient_count(T, curves, G, bp, gx, gw);
 }
 
 void launch_trim_curves(Plan& P, hipStream_t s) {
     TrimDev& T = P.trim;
     if (T.n_curves == 0) return;
     GridDev G{P.dir[0].knots + P.p, P.dir[1].knots + P.p, P.N1, P.N2};  // breakpoints
-    hipLaunchKernelGGL(k_trim_front, dim3(1), dim3(1024), 0, s, T, P.d_cp, P.d_cp_off, P.d_curves, G, P.gauss_x,
+    hipLaunchKernelGGL(k_trim_front, dim3(1), dim3(256), 0, s, T, P.d_cp, P.d_cp_off, P.d_curves, G, P.gauss_x,
                        P.gauss_w);
     if (T.n_curves > 1) {
         hipLaunchKernelGGL(k_piece_isect, dim3(T.cap_pieces0), dim3(64), 0, s, T, P.status);
@@ -501,8 +656,17 @@ void launch_trim_curves(Plan& P, hipStream_t s) {
 // One workgroup per piece: solve its crossings, order them along the piece
 // (own rank plus the crossings of the other family before it, vertical first
 // on ties), cut the piece into arcs, keep the visible ones and mark their
-// elements cut (mark = this set-up's epoch).
-__global__ void __launch_bounds__(256) k_piece_arcs(TrimDev T, GridDev G, int* __restrict__ emark, int epoch) {
+// elements cut (mark = this set-up's epoch) and push each kept arc onto its
+// element's list (a head per element tagged with the epoch, so nothing is
+// cleared between set-ups). Spline pieces also record where they cross the
+// horizontal line through each row's element centres, for the centre test of
+// the other elements. Breakpoints and (short pieces') crossings live in LDS.
+constexpr int kArcLds = 512;
+
+__global__ void __launch_bounds__(256) k_piece_arcs(TrimDev T, GridDev G, int* __restrict__ emark, int epoch,
+                                                    unsigned long long* __restrict__ ehead, int* __restrict__ arc_next) {
+    __shared__ double sbp[kLdsBp];
+    __shared__ CrossDev sCross[kArcLds], sMerged[kArcLds];
     const int k = blockIdx.x;
     const int np = *T.n_pieces;
     const int tid = threadIdx.x;
@@ -511,30 +675,66 @@ __global__ void __launch_bounds__(256) k_piece_arcs(TrimDev T, GridDev G, int* _
         for (int a = n_arcs + tid; a < T.cap_arcs; a += 256) T.arcs[a].keep = 0;
     }
     if (k >= np) return;
+    const BpView bp = stage_bp(G, sbp);
     const int base = T.cross_off[k], n = T.cross_cnt[k], nv = T.nv[k];
     const PieceDev Pc = T.pieces[k];
     const SegDev S = T.segs[Pc.seg];
     const CurveDev C = T.curves[Pc.curve];
-    const int lv0 = lower_bound_d(G.bp1, G.N1 + 1, fmin(Pc.x0, Pc.x1));
-    const int lh0 = lower_bound_d(G.bp2, G.N2 + 1, fmin(Pc.y0, Pc.y1));
-    for (int j = tid; j < n; j += 256) {
-        CrossDev X;
-        if (j < nv) {
-            X.kind = END_VLINE;
-            X.line = lv0 + j;
-            X.t = solve_monotone(S, 0, G.bp1[X.line], Pc.t0, Pc.t1);
-        } else {
-            X.kind = END_HLINE;
-            X.line = lh0 + (j - nv);
-            X.t = solve_monotone(S, 1, G.bp2[X.line], Pc.t0, Pc.t1);
+    CrossDev* cross = (n <= kArcLds) ? sCross : T.cross + base;
+    CrossDev* merged = (n <= kArcLds) ? sMerged : T.merged + base;
+    __syncthreads();
+    const double xmin = fmin(Pc.x0, Pc.x1), xmax = fmax(Pc.x0, Pc.x1);
+    const double ymin = fmin(Pc.y0, Pc.y1), ymax = fmax(Pc.y0, Pc.y1);
+    const int lv0 = lower_bound_d(bp.b1, G.N1 + 1, xmin);
+    const int lh0 = lower_bound_d(bp.b2, G.N2 + 1, ymin);
+    // spline pieces: rows whose centre y lies in [ymin, ymax) (centres are non-decreasing in the row)
+    int r0 = 0, r1 = 0;
+    if (C.kind != IGA_CURVE_ELLIPSE) {
+        int lo = 0, hi = G.N2;
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (0.5 * (bp.b2[mid] + bp.b2[mid + 1]) < ymin) lo = mid + 1; else hi = mid;
         }
-        T.cross[base + j] = X;
+        r0 = lo;
+        hi = G.N2;
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (0.5 * (bp.b2[mid] + bp.b2[mid + 1]) < ymax) lo = mid + 1; else hi = mid;
+        }
+        r1 = lo;
+    }
+    // grid-line crossings (j < n) and centre-line crossings (j >= n) in one pass
+    for (int j = tid; j < n + (r1 - r0); j += 256) {
+        if (j < n) {
+            CrossDev X;
+            if (j < nv) {
+                X.kind = END_VLINE;
+                X.line = lv0 + j;
+                X.t = solve_monotone(S, 0, bp.b1[X.line], Pc.t0, Pc.t1);
+            } else {
+                X.kind = END_HLINE;
+                X.line = lh0 + (j - nv);
+                X.t = solve_monotone(S, 1, bp.b2[X.line], Pc.t0, Pc.t1);
+            }
+            cross[j] = X;
+        } else {
+            const int r = r0 + (j - n);
+            const double y = 0.5 * (bp.b2[r] + bp.b2[r + 1]);
+            const double t = solve_monotone(S, 1, y, Pc.t0, Pc.t1);
+            double X, Y, dX, dY;
+            seg_eval(S, t, X, Y, dX, dY);
+            const int slot = atomicAdd(&T.row_cnt[r], 1);
+            if (slot < kRowCross) {
+                T.row_key[(size_t)r * kRowCross + slot] = fmin(X, xmax);
+                T.row_curve[(size_t)r * kRowCross + slot] = Pc.curve;
+            }
+        }
     }
     __syncthreads();
     const int nh = n - nv;
     const bool incx = Pc.x1 > Pc.x0, incy = Pc.y1 > Pc.y0;
     for (int j = tid; j < n; j += 256) {
-        const CrossDev X = T.cross[base + j];
+        const CrossDev X = cross[j];
         int own, other;
         if (j < nv) {
             own = incx ? j : nv - 1 - j;
@@ -542,7 +742,7 @@ __global__ void __launch_bounds__(256) k_piece_arcs(TrimDev T, GridDev G, int* _
             while (lo < hi) {
                 const int mid = (lo + hi) >> 1;
                 const int idx = incy ? mid : nh - 1 - mid;
-                if (T.cross[base + nv + idx].t < X.t) lo = mid + 1; else hi = mid;
+                if (cross[nv + idx].t < X.t) lo = mid + 1; else hi = mid;
             }
             other = lo;
         } else {
@@ -552,11 +752,11 @@ __global__ void __launch_bounds__(256) k_piece_arcs(TrimDev T, GridDev G, int* _
             while (lo < hi) {
                 const int mid = (lo + hi) >> 1;
                 const int idx = incx ? mid : nv - 1 - mid;
-                if (T.cross[base + idx].t <= X.t) lo = mid + 1; else hi = mid;
+                if (cross[idx].t <= X.t) lo = mid + 1; else hi = mid;
             }
             other = lo;
         }
-        T.merged[base + own + other] = X;
+        merged[own + other] = X;
     }
     __syncthreads();
     for (int j = tid; j <= n; j += 256) {
@@ -565,19 +765,26 @@ __global__ void __launch_bounds__(256) k_piece_arcs(TrimDev T, GridDev G, int* _
         A.seg = S.seg;
         A.piece = k;
         if (j == 0) { A.t0 = Pc.t0; A.k0 = END_PIECE; A.l0 = -1; }
-        else { const CrossDev X = T.merged[base + j - 1]; A.t0 = X.t; A.k0 = X.kind; A.l0 = X.line; }
+        else { const CrossDev X = merged[j - 1]; A.t0 = X.t; A.k0 = X.kind; A.l0 = X.line; }
         if (j == n) { A.t1 = Pc.t1; A.k1 = END_PIECE; A.l1 = -1; }
-        else { const CrossDev X = T.merged[base + j]; A.t1 = X.t; A.k1 = X.kind; A.l1 = X.line; }
+        else { const CrossDev X = merged[j]; A.t1 = X.t; A.k1 = X.kind; A.l1 = X.line; }
         double X, Y, dX, dY;
         seg_eval(S, 0.5 * (A.t0 + A.t1), X, Y, dX, dY);
         int keep = (A.t1 - A.t0 > 1e-13 * C.t_range);
-        keep = keep && X > G.bp1[0] && X < G.bp1[G.N1] && Y > G.bp2[0] && Y < G.bp2[G.N2];
+        keep = keep && X > bp.b1[0] && X < bp.b1[G.N1] && Y > bp.b2[0] && Y < bp.b2[G.N2];
         if (keep && T.n_curves > 1) keep = !in_any_hole(T, X, Y, Pc.curve);
         A.keep = keep;
-        A.e1 = min(max(upper_bound_d(G.bp1, G.N1 + 1, X) - 1, 0), G.N1 - 1);
-        A.e2 = min(max(upper_bound_d(G.bp2, G.N2 + 1, Y) - 1, 0), G.N2 - 1);
-        T.arcs[base + k + j] = A;
-        if (keep) emark[A.e2 * G.N1 + A.e1] = epoch;
+        A.e1 = min(max(upper_bound_d(bp.b1, G.N1 + 1, X) - 1, 0), G.N1 - 1);
+        A.e2 = min(max(upper_bound_d(bp.b2, G.N2 + 1, Y) - 1, 0), G.N2 - 1);
+        const int idx = base + k + j;
+        T.arcs[idx] = A;
+        if (keep) {  // push onto the element's list (order fixed later by arc index)
+            const int e = A.e2 * G.N1 + A.e1;
+            emark[e] = epoch;
+            const unsigned long long old =
+                atomicExch(&ehead[e], ((unsigned long long)(unsigned)epoch << 32) | (unsigned)(idx + 1));
+            arc_next[idx] = ((int)(old >> 32) == epoch) ? (int)(old & 0xffffffffull) - 1 : -1;
+        }
     }
 }
 
@@ -585,12 +792,18 @@ void launch_trim_arcs(Plan& P, hipStream_t s) {
     TrimDev& T = P.trim;
     if (T.n_curves == 0) return;
     GridDev G{P.dir[0].knots + P.p, P.dir[1].knots + P.p, P.N1, P.N2};  // breakpoints
-    hipLaunchKernelGGL(k_piece_arcs, dim3(std::max(T.cap_pieces, 1)), dim3(256), 0, s, T, G, P.emark, P.epoch);
+    hipLaunchKernelGGL(k_piece_arcs, dim3(std::max(T.cap_pieces, 1)), dim3(256), 0, s, T, G, P.emark, P.epoch,
+                       P.ehead, P.arc_next);
 }
 
 // -------------------------------------------------------------- classes
 // Element classes: cut if it owns a visible arc (marked with this set-up's
-// epoch), otherwise inside / outside by the test at its centre.
+// epoch), otherwise inside / outside by the even-odd test at its centre. For
+// spline curves the test counts the crossings the arc kernel recorded on the
+// row's centre line right of the centre (a crossing counts when both it and
+// its piece's largest x lie right of the point, as in inside_curve); ellipses
+// use their implicit function. Rows with more crossings than recorded fall
+// back to the direct test.
 __global__ void k_elem_centre(TrimDev T, GridDev G, const int* __restrict__ emark, int epoch,
                               int8_t* __restrict__ ecls) {
     int e = blockIdx.x * blockDim.x + threadIdx.x;
@@ -601,7 +814,23 @@ __global__ void k_elem_centre(TrimDev T, GridDev G, const int* __restrict__ emar
     }
     int e1 = e % G.N1, e2 = e / G.N1;
     double x = 0.5 * (G.bp1[e1] + G.bp1[e1 + 1]), y = 0.5 * (G.bp2[e2] + G.bp2[e2 + 1]);
-    ecls[e] = in_any_hole(T, x, y) ? EL_OUTSIDE : EL_INSIDE;
+    bool out = false;
+    if (T.n_curves > 0) {
+        const int nc = T.row_cnt[e2];
+        if (nc > kRowCross || T.n_curves > 32) {
+            out = in_any_hole(T, x, y);
+        } else {
+            unsigned par = 0u;
+            for (int j = 0; j < nc; ++j)
+                if (T.row_key[(size_t)e2 * kRowCross + j] > x) par ^= 1u << T.row_curve[(size_t)e2 * kRowCross + j];
+            out = par != 0u;
+            for (int c = 0; c < T.n_curves && !out; ++c) {
+                const CurveDev C = T.curves[c];
+                if (C.kind == IGA_CURVE_ELLIPSE) out = ellipse_implicit(C, x, y) < 0.0;
+            }
+        }
+    }
+    ecls[e] = out ? EL_OUTSIDE : EL_INSIDE;
 }
 
 struct ClassArgs {
@@ -614,40 +843,68 @@ struct ClassArgs {
     int* e_band;     // N1*N2 flags
 };
 
-__global__ void k_fn_class(ClassArgs A) {
-    int f = blockIdx.x * blockDim.x + threadIdx.x;
-    if (f >= A.n1 * A.n2) return;
-    int i1 = f % A.n1, i2 = f / A.n1;
-    int nin = 0, nout = 0, ntot = 0;
-    for (int e2 = max(0, i2 - A.p); e2 <= min(A.N2 - 1, i2); ++e2)
-        for (int e1 = max(0, i1 - A.p); e1 <= min(A.N1 - 1, i1); ++e1) {
-            int8_t c = A.ecls[e2 * A.N1 + e1];
-            nin += (c == EL_INSIDE);
-            nout += (c == EL_OUTSIDE);
-            ++ntot;
-        }
-    int8_t cls = (nout == ntot) ? FN_EXTERIOR : (nin == ntot ? FN_INTERIOR : FN_CUT);
-    A.fcls[f] = cls;
-    A.f_active[f] = cls != FN_EXTERIOR;
-    A.f_cut[f] = (A.method == IGA_GAUSS_REF) ? (cls != FN_EXTERIOR) : (cls == FN_CUT);
-}
+// Function classes and element flags on 16 x 16 tiles of elements. The
+// tile's element classes with a halo of p on each side are staged in LDS;
+// from them the classes of the functions [x0, x0 + 16 + p) x [y0, ...)
+// (Sect. 2.2: exterior if every support element is outside, interior if
+// every one is inside, cut otherwise), and from those the tile's element
+// flags: cut, and "band" -- an inside element in the support of a cut
+// function, whose Gauss points some row formed element-wise uses. The last
+// tile of each direction also owns the p functions past the last element.
+constexpr int kClsTile = 16;
 
-// Element flags: cut elements, and "band" elements -- inside elements whose
-// Gauss points are used by some row formed element-wise.
-__global__ void k_elem_flags(ClassArgs A) {
-    int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= A.N1 * A.N2) return;
-    int e1 = e % A.N1, e2 = e / A.N1;
-    int8_t c = A.ecls[e];
-    A.e_cut[e] = (c == EL_CUT);
+__global__ void __launch_bounds__(256) k_classes(ClassArgs A) {
+    constexpr int WE = kClsTile + 2 * IGA_MAXP, WF = kClsTile + IGA_MAXP;
+    __shared__ int8_t sE[WE][WE];
+    __shared__ int8_t sF[WF][WF];
+    const int p = A.p, tid = threadIdx.x;
+    const int x0 = blockIdx.x * kClsTile, y0 = blockIdx.y * kClsTile;
+    const int we = kClsTile + 2 * p, wf = kClsTile + p;
+    for (int t = tid; t < we * we; t += 256) {
+        const int u = t % we, v = t / we;
+        const int ex = x0 - p + u, ey = y0 - p + v;
+        sE[v][u] = (ex >= 0 && ex < A.N1 && ey >= 0 && ey < A.N2) ? A.ecls[ey * A.N1 + ex] : (int8_t)-1;
+    }
+    __syncthreads();
+    const bool lastx = blockIdx.x == gridDim.x - 1, lasty = blockIdx.y == gridDim.y - 1;
+    for (int t = tid; t < wf * wf; t += 256) {
+        const int u = t % wf, v = t / wf;
+        const int j1 = x0 + u, j2 = y0 + v;
+        int8_t cls = FN_EXTERIOR;
+        if (j1 < A.n1 && j2 < A.n2) {
+            int nin = 0, nout = 0, ntot = 0;
+            for (int e2 = max(0, j2 - p); e2 <= min(A.N2 - 1, j2); ++e2)
+                for (int e1 = max(0, j1 - p); e1 <= min(A.N1 - 1, j1); ++e1) {
+                    const int8_t c = sE[e2 - y0 + p][e1 - x0 + p];
+                    nin += (c == EL_INSIDE);
+                    nout += (c == EL_OUTSIDE);
+                    ++ntot;
+                }
+            cls = (nout == ntot) ? FN_EXTERIOR : (nin == ntot ? FN_INTERIOR : FN_CUT);
+            const bool own = (u < kClsTile || lastx) && (v < kClsTile || lasty);
+            if (own) {
+                const int f = j2 * A.n1 + j1;
+                A.fcls[f] = cls;
+                A.f_active[f] = cls != FN_EXTERIOR;
+                A.f_cut[f] = (A.method == IGA_GAUSS_REF) ? (cls != FN_EXTERIOR) : (cls == FN_CUT);
+            }
+        }
+        sF[v][u] = cls;
+    }
+    __syncthreads();
+    const int tx = tid % kClsTile, ty = tid / kClsTile;
+    const int e1 = x0 + tx, e2 = y0 + ty;
+    if (e1 >= A.N1 || e2 >= A.N2) return;
+    const int8_t c = sE[ty + p][tx + p];
     int band = 0;
     if (c == EL_INSIDE && A.method != IGA_NAIVE_WQ) {
         if (A.method == IGA_GAUSS_REF) band = 1;
         else
-            for (int j2 = e2; j2 <= e2 + A.p && !band; ++j2)
-                for (int j1 = e1; j1 <= e1 + A.p; ++j1)
-                    if (A.fcls[j2 * A.n1 + j1] == FN_CUT) { band = 1; break; }
+            for (int d2 = 0; d2 <= p; ++d2)
+                for (int d1 = 0; d1 <= p; ++d1) band |= (sF[ty + d2][tx + d1] == FN_CUT);
     }
+    const int e = e2 * A.N1 + e1;
+    A.e_cut[e] = (c == EL_CUT);
     A.e_band[e] = band;
 }
 
@@ -662,8 +919,8 @@ void launch_trim_classes(Plan& P, hipStream_t s) {
     int* e_cut = P.flags + 2 * (nf + 1);
     int* e_band = e_cut + (ne + 1);
     ClassArgs A{P.p, P.N1, P.N2, P.n1, P.n2, P.method, P.ecls, P.fcls, f_active, f_cut, e_cut, e_band};
-    hipLaunchKernelGGL(k_fn_class, dim3((nf + 127) / 128), dim3(128), 0, s, A);
-    hipLaunchKernelGGL(k_elem_flags, dim3((ne + 127) / 128), dim3(128), 0, s, A);
+    dim3 g((P.N1 + kClsTile - 1) / kClsTile, (P.N2 + kClsTile - 1) / kClsTile);
+    hipLaunchKernelGGL(k_classes, g, dim3(256), 0, s, A);
 }
 
 // --------------------------------------------------------------- lists
@@ -682,6 +939,7 @@ struct ListArgs {
     int* bsum;           // [4][ntiles] tile counts, then tile offsets
     int ntiles;
     int* counts;         // [4] totals
+    int* ticket;         // workgroups done counting (the last one scans, then resets it)
 };
 
 __device__ __forceinline__ int block_sum256(int v, int* sh) {
@@ -695,8 +953,11 @@ __device__ __forceinline__ int block_sum256(int v, int* sh) {
     return tot;
 }
 
+// Tile counts of the four flag arrays; the workgroup that finishes last
+// (ticket) turns them into tile offsets and totals.
 __global__ void __launch_bounds__(256) k_list_count(ListArgs A) {
-    __shared__ int sh[4];
+    __shared__ int sh[256 / 64 + 1];
+    __shared__ int s_last;
     const int b = blockIdx.x, base = b * kListTile + threadIdx.x * 4;
     int c[4];
 #pragma unroll
@@ -710,21 +971,34 @@ __global__ void __launch_bounds__(256) k_list_count(ListArgs A) {
         const int tot = block_sum256(c[a], sh);
         if (threadIdx.x == 0) A.bsum[a * A.ntiles + b] = tot;
     }
-}
-
-__global__ void __launch_bounds__(1024) k_list_scan(ListArgs A) {
-    __shared__ int sh[1024 / 64 + 1];
-    for (int a = 0; a < 4; ++a) {
-        int carry = 0;
-        for (int base = 0; base < A.ntiles; base += 1024) {
-            const int idx = base + threadIdx.x;
-            const int v = (idx < A.ntiles) ? A.bsum[a * A.ntiles + idx] : 0;
+    if (threadIdx.x == 0) {
+        __threadfence();  // this tile's counts are visible before its ticket
+        s_last = atomicAdd(A.ticket, 1) == A.ntiles - 1;
+    }
+    __syncthreads();
+    if (!s_last) return;
+    __threadfence();      // every tile's counts are visible to the last workgroup
+    int carry[4] = {0, 0, 0, 0};
+    for (int t0 = 0; t0 < A.ntiles; t0 += 256) {
+        const int idx = t0 + threadIdx.x;
+        int v[4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+            v[a] = (idx < A.ntiles)
+                       ? __hip_atomic_load(&A.bsum[a * A.ntiles + idx], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                       : 0;
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
             int total;
-            const int ex = block_excl_scan(v, sh, total);
-            if (idx < A.ntiles) A.bsum[a * A.ntiles + idx] = ex + carry;
-            carry += total;
+            const int ex = block_excl_scan(v[a], sh, total);
+            if (idx < A.ntiles) A.bsum[a * A.ntiles + idx] = ex + carry[a];
+            carry[a] += total;
         }
-        if (threadIdx.x == 0) A.counts[a] = carry;
+    }
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int a = 0; a < 4; ++a) A.counts[a] = carry[a];
+        *A.ticket = 0;
     }
 }
 
@@ -768,68 +1042,28 @@ void launch_trim_lists(Plan& P, hipStream_t s) {
     A.ntiles = (std::max(nf, ne) + kListTile - 1) / kListTile;
     A.bsum = P.scan_tmp + P.scan_pos_off;  // 4 * ntiles <= the position region
     A.counts = P.counts;
+    A.ticket = P.tickets + 0;
     hipLaunchKernelGGL(k_list_count, dim3(A.ntiles), dim3(256), 0, s, A);
-    hipLaunchKernelGGL(k_list_scan, dim3(1), dim3(1024), 0, s, A);
     hipLaunchKernelGGL(k_list_write, dim3(A.ntiles), dim3(256), 0, s, A);
 }
 
-// ------------------------------------------------------ arcs per element
-__global__ void k_arc_count(TrimDev T, int N1, const int* __restrict__ cut_id, int* __restrict__ cnt) {
-    int a = blockIdx.x * blockDim.x + threadIdx.x;
-    if (a >= T.cap_arcs) return;
-    const ArcDev A = T.arcs[a];
-    if (A.keep) atomicAdd(&cnt[cut_id[A.e2 * N1 + A.e1]], 1);
-}
-
-__global__ void k_arc_fill(TrimDev T, int N1, const int* __restrict__ cut_id, const int* __restrict__ off,
-                           int* __restrict__ fill, int* __restrict__ list) {
-    int a = blockIdx.x * blockDim.x + threadIdx.x;
-    if (a >= T.cap_arcs) return;
-    const ArcDev A = T.arcs[a];
-    if (!A.keep) return;
-    int c = cut_id[A.e2 * N1 + A.e1];
-    int slot = atomicAdd(&fill[c], 1);
-    list[off[c] + slot] = a;
-}
-
-// Arc indices are already in (curve, segment, t) order; sort each element's list by index.
-__global__ void k_arc_sort(int n_cut, const int* __restrict__ off, int* __restrict__ list) {
-    int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= n_cut) return;
-    int lo = off[c], hi = off[c + 1];
-    for (int a = lo + 1; a < hi; ++a) {
-        int v = list[a], b = a - 1;
-        while (b >= lo && list[b] > v) { list[b + 1] = list[b]; --b; }
-        list[b + 1] = v;
-    }
-}
-
-__global__ void k_zero_int(int* p, int n) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) p[i] = 0;
-}
-
-__global__ void k_zero_int2(int* a, int* b, int n) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) {
-        a[i] = 0;
-        b[i] = 0;
-    }
-}
-
+// ------------------------------------------------------ cut-element rules
 struct CutArgs {
     TrimDev T;
     GridDev G;
     int n_cut;
     const int* cut_list;
-    const int* arc_off;
-    const int* arc_list;
+    const unsigned long long* ehead;  // element lists of kept arcs (k_piece_arcs)
+    const int* arc_next;
+    int epoch;
     CutElemDev* cut_el;
     int* node_cnt;
     int n_r, n_q_override, n_s, p;
     const double* gx;
     const double* gw;
     int* status;
+    int* node_off;      // exclusive scan of node_cnt, written by the last workgroup of k_cutprep
+    int* ticket;
 };
 
 __device__ __forceinline__ int arc_nq(const CutArgs& A, const CurveDev& C) {
@@ -838,9 +1072,40 @@ __device__ __forceinline__ int arc_nq(const CutArgs& A, const CurveDev& C) {
     return d * (2 * A.p + 1);
 }
 
-constexpr int kMaxArcsPerElem = 64;
+// Pieces as the even-odd test reads them, staged in LDS by k_cutprep.
+constexpr int kPrepPieces = 256;
+struct PieceBox {
+    double ymin, ymax, xmax, t0, t1;
+    int seg, curve;
+};
 
-// One wavefront per cut element. (1) one lane per arc of the element loads the
+// in_any_hole with the pieces' boxes read from LDS (same tests, same order).
+__device__ bool in_any_hole_lds(const TrimDev& T, const PieceBox* sp, const int* scoff, double x, double y) {
+    for (int c = 0; c < T.n_curves; ++c) {
+        const CurveDev C = T.curves[c];
+        if (C.kind == IGA_CURVE_ELLIPSE) {
+            if (ellipse_implicit(C, x, y) < 0.0) return true;
+            continue;
+        }
+        bool in = false;
+        for (int k = scoff[c]; k < scoff[c + 1]; ++k) {
+            const PieceBox& B = sp[k];
+            if (!(y >= B.ymin && y < B.ymax)) continue;
+            if (B.xmax <= x) continue;
+            const SegDev S = T.segs[B.seg];
+            const double t = solve_monotone(S, 1, y, B.t0, B.t1);
+            double X, Y, dX, dY;
+            seg_eval(S, t, X, Y, dX, dY);
+            if (X > x) in = !in;
+        }
+        if (in) return true;
+    }
+    return false;
+}
+
+// One wavefront per cut element. (0) lane 0 walks the element's list of kept
+// arcs and sorts it by arc index, while the lanes stage the pieces for the
+// hole tests in LDS; (1) one lane per arc of the element loads the
 // arc, its piece and segment and evaluates its ends; (2) lanes 0..3, one per
 // edge (0 left, 1 right, 2 bottom, 3 top), collect the arc ends lying on the
 // edge -- crossings of that grid line, and piece ends (extrema or segment
@@ -848,7 +1113,7 @@ constexpr int kMaxArcsPerElem = 64;
 // (3) all lanes test the sub-intervals' midpoints against the holes; (4) lanes
 // 0..3 merge the visible sub-intervals; (5) every lane adds its share of
 // sum |w| of the four bases over the arcs' Gauss points; lane 0 picks the base
-// and the node count.
+// and the node count. The workgroup that finishes last scans the node counts.
 __global__ void __launch_bounds__(64) k_cutprep(CutArgs A) {
     const int c = blockIdx.x;
     if (c >= A.n_cut) return;
@@ -863,16 +1128,49 @@ __global__ void __launch_bounds__(64) k_cutprep(CutArgs A) {
     __shared__ int sNiv[4];
     __shared__ double sLen[4];
     __shared__ int sOverflow;
+    __shared__ int sLast;
+    __shared__ int sArc[kMaxArcsPerElem];
+    __shared__ int sNa;
+    __shared__ PieceBox sP[kPrepPieces];
+    __shared__ int sCoff[33];
     const int e = A.cut_list[c];
     const int e1 = e % A.G.N1, e2 = e / A.G.N1;
     const double xa = A.G.bp1[e1], xb = A.G.bp1[e1 + 1], ya = A.G.bp2[e2], yb = A.G.bp2[e2 + 1];
-    const int alo = A.arc_off[c], ahi = A.arc_off[c + 1];
-    const int na = min(ahi - alo, kMaxArcsPerElem);
     CutElemDev& out = A.cut_el[c];
-    if (lane == 0) sOverflow = (ahi - alo > kMaxArcsPerElem);
+    // (0) the pieces for the hole tests, and the element's kept arcs in ascending order
+    const int npc = *T.n_pieces;
+    const bool staged = npc <= kPrepPieces && T.n_curves <= 32;
+    if (staged) {
+        for (int k = lane; k < npc; k += 64) {
+            const PieceDev Pc = T.pieces[k];
+            sP[k] = PieceBox{fmin(Pc.y0, Pc.y1), fmax(Pc.y0, Pc.y1), fmax(Pc.x0, Pc.x1), Pc.t0, Pc.t1, Pc.seg, Pc.curve};
+        }
+        for (int k = lane; k <= T.n_curves; k += 64) sCoff[k] = T.piece_curve_off[k];
+    }
+    if (lane == 0) {
+        const unsigned long long h = A.ehead[e];
+        int a = ((int)(h >> 32) == A.epoch) ? (int)(h & 0xffffffffull) - 1 : -1;
+        int n = 0;
+        for (int it = 0; a >= 0 && it <= kMaxArcsPerElem; ++it) {
+            if (n < kMaxArcsPerElem) sArc[n++] = a;
+            a = A.arc_next[a];
+        }
+        sOverflow = a >= 0;
+        for (int i = 1; i < n; ++i) {
+            const int v = sArc[i];
+            int j = i - 1;
+            while (j >= 0 && sArc[j] > v) { sArc[j + 1] = sArc[j]; --j; }
+            sArc[j + 1] = v;
+        }
+        sNa = n;
+        out.narc = n;
+    }
+    __syncthreads();
+    const int na = sNa;
     // (1) arcs, one lane each
     for (int q = lane; q < na; q += 64) {
-        const ArcDev R = T.arcs[A.arc_list[alo + q]];
+        out.arc[q] = sArc[q];
+        const ArcDev R = T.arcs[sArc[q]];
         const int sidx = T.pieces[R.piece].seg;
         const SegDev S = T.segs[sidx];
         double X, Y, dX, dY;
@@ -943,7 +1241,7 @@ __global__ void __launch_bounds__(64) k_cutprep(CutArgs A) {
         const double fixed = (edge == 0) ? xa : (edge == 1) ? xb : (edge == 2) ? ya : yb;
         const double m = 0.5 * (sIv[edge][q][0] + sIv[edge][q][1]);
         const double x = (edge < 2) ? fixed : m, y = (edge < 2) ? m : fixed;
-        sIvOk[edge][q] = in_any_hole(T, x, y) ? 0 : 1;
+        sIvOk[edge][q] = (staged ? in_any_hole_lds(T, sP, sCoff, x, y) : in_any_hole(T, x, y)) ? 0 : 1;
     }
     __syncthreads();
     // (4) merge the visible sub-intervals
@@ -1013,6 +1311,42 @@ __global__ void __launch_bounds__(64) k_cutprep(CutArgs A) {
         out.variant = var;
         A.node_cnt[c] = narc_nodes + out.nseg[opp] * A.n_s * A.n_r;
         if (sOverflow) atomicExch(A.status, IGA_E_TOPOLOGY);
+        __threadfence();  // this element's count is visible before its ticket
+        sLast = atomicAdd(A.ticket, 1) == A.n_cut - 1;
+    }
+    __syncthreads();
+    if (!sLast) return;
+    // the last workgroup: node offsets, exclusive scan of every element's count;
+    // 2048 counts at a time, each lane loading a contiguous run of up to 32 at once
+    __threadfence();
+    int carry = 0;
+    for (int b0 = 0; b0 < A.n_cut; b0 += 64 * 32) {
+        const int K = min(32, (A.n_cut - b0 + 63) / 64);
+        int v[32];
+#pragma unroll
+        for (int j = 0; j < 32; ++j) {
+            const int i = b0 + lane * K + j;
+            v[j] = (j < K && i < A.n_cut) ? __hip_atomic_load(&A.node_cnt[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                                          : 0;
+        }
+        int lsum = 0;
+#pragma unroll
+        for (int j = 0; j < 32; ++j) lsum += v[j];
+        const int inc = wave_incl_scan(lsum, lane);
+        int run = carry + inc - lsum;
+#pragma unroll
+        for (int j = 0; j < 32; ++j) {
+            const int i = b0 + lane * K + j;
+            if (j < K && i < A.n_cut) {
+                A.node_off[i] = run;
+                run += v[j];
+            }
+        }
+        carry += __shfl(inc, 63, 64);
+    }
+    if (lane == 0) {
+        A.node_off[A.n_cut] = carry;
+        *A.ticket = 0;
     }
 }
 
@@ -1021,22 +1355,15 @@ void launch_trim_cutprep(Plan& P, hipStream_t s) {
     int nc = (int)P.n_cut_el;
     if (T.n_curves == 0 || nc == 0) return;
     GridDev G{P.dir[0].knots + P.p, P.dir[1].knots + P.p, P.N1, P.N2};  // breakpoints
-    hipLaunchKernelGGL(k_zero_int2, dim3((nc + 1 + 127) / 128), dim3(128), 0, s, P.arc_cnt, P.arc_fill, nc + 1);
-    hipLaunchKernelGGL(k_arc_count, dim3((T.cap_arcs + 127) / 128), dim3(128), 0, s, T, P.N1, P.cut_id, P.arc_cnt);
-    exclusive_scan(P.arc_cnt, P.arc_off, nc, P.scan_tmp, s);
-    hipLaunchKernelGGL(k_arc_fill, dim3((T.cap_arcs + 127) / 128), dim3(128), 0, s, T, P.N1, P.cut_id, P.arc_off,
-                       P.arc_fill, P.arc_list);
-    hipLaunchKernelGGL(k_arc_sort, dim3((nc + 127) / 128), dim3(128), 0, s, nc, P.arc_off, P.arc_list);
-    CutArgs A{T, G, nc, P.cut_list, P.arc_off, P.arc_list, P.cut_el, P.node_cnt,
-              P.n_r, P.n_q_override, P.n_s, P.p, P.gauss_x, P.gauss_w, P.status};
+    CutArgs A{T, G, nc, P.cut_list, P.ehead, P.arc_next, P.epoch, P.cut_el, P.node_cnt,
+              P.n_r, P.n_q_override, P.n_s, P.p, P.gauss_x, P.gauss_w, P.status, P.node_off, P.tickets + 1};
     hipLaunchKernelGGL(k_cutprep, dim3(nc), dim3(64), 0, s, A);
-    exclusive_scan(P.node_cnt, P.node_off, nc, P.scan_tmp, s);
 }
 
-// One wavefront per cut element writes its nodes.
+// One wavefront per cut element writes its nodes (and their entries of the rule-point table).
 __global__ void __launch_bounds__(64) k_cut_nodes(CutArgs A, const int* __restrict__ node_off, double* __restrict__ nx,
                                                   double* __restrict__ ny, double* __restrict__ nw,
-                                                  int* __restrict__ nel) {
+                                                  int* __restrict__ nel, double* __restrict__ xy) {
     int c = blockIdx.x;
     if (c >= A.n_cut) return;
     const TrimDev& T = A.T;
@@ -1050,8 +1377,8 @@ __global__ void __launch_bounds__(64) k_cut_nodes(CutArgs A, const int* __restri
     const double* rx = A.gx + gauss_off(nr);
     const double* rw = A.gw + gauss_off(nr);
     int pos = node_off[c];
-    for (int q = A.arc_off[c]; q < A.arc_off[c + 1]; ++q) {
-        const ArcDev R = T.arcs[A.arc_list[q]];
+    for (int q = 0; q < E.narc; ++q) {
+        const ArcDev R = T.arcs[E.arc[q]];
         const SegDev S = T.segs[T.pieces[R.piece].seg];
         const CurveDev C = T.curves[R.curve];
         int nq = arc_nq(A, C);
@@ -1063,16 +1390,13 @@ __global__ void __launch_bounds__(64) k_cut_nodes(CutArgs A, const int* __restri
             for (int r = 0; r < nr; ++r) {
                 int o = pos + g * nr + r;
                 double f = (rx[r] + 1.0) * 0.5;
-                if (vert) {
-                    nx[o] = b0 + (X - b0) * f;
-                    ny[o] = Y;
-                    nw[o] = C.sigma * wt * dY * rw[r] * (X - b0) * 0.5;
-                } else {
-                    nx[o] = X;
-                    ny[o] = b0 + (Y - b0) * f;
-                    nw[o] = -C.sigma * wt * dX * rw[r] * (Y - b0) * 0.5;
-                }
+                const double x = vert ? b0 + (X - b0) * f : X, y = vert ? Y : b0 + (Y - b0) * f;
+                nx[o] = x;
+                ny[o] = y;
+                nw[o] = vert ? C.sigma * wt * dY * rw[r] * (X - b0) * 0.5 : -C.sigma * wt * dX * rw[r] * (Y - b0) * 0.5;
                 nel[o] = c;
+                xy[2 * o] = x;
+                xy[2 * o + 1] = y;
             }
         }
         pos += nq * nr;
@@ -1094,6 +1418,8 @@ __global__ void __launch_bounds__(64) k_cut_nodes(CutArgs A, const int* __restri
             ny[o] = vert ? u : inner;
             nw[o] = wu * rw[r] * fabs(b1 - b0) * 0.5;
             nel[o] = c;
+            xy[2 * o] = vert ? inner : u;
+            xy[2 * o + 1] = vert ? u : inner;
         }
         pos += ns * nr;
     }
@@ -1104,9 +1430,11 @@ void launch_trim_nodes(Plan& P, hipStream_t s) {
     int nc = (int)P.n_cut_el;
     if (T.n_curves == 0 || nc == 0) return;
     GridDev G{P.dir[0].knots + P.p, P.dir[1].knots + P.p, P.N1, P.N2};  // breakpoints
-    CutArgs A{T, G, nc, P.cut_list, P.arc_off, P.arc_list, P.cut_el, P.node_cnt,
-              P.n_r, P.n_q_override, P.n_s, P.p, P.gauss_x, P.gauss_w, P.status};
-    hipLaunchKernelGGL(k_cut_nodes, dim3(nc), dim3(64), 0, s, A, P.node_off, P.node_x, P.node_y, P.node_w, P.node_el);
+    CutArgs A{T, G, nc, P.cut_list, P.ehead, P.arc_next, P.epoch, P.cut_el, P.node_cnt,
+              P.n_r, P.n_q_override, P.n_s, P.p, P.gauss_x, P.gauss_w, P.status, P.node_off, P.tickets + 1};
+    const size_t cut0 = (size_t)P.dir[0].Q * P.dir[1].Q + (size_t)P.n_band * (P.p + 1) * (P.p + 1);
+    hipLaunchKernelGGL(k_cut_nodes, dim3(nc), dim3(64), 0, s, A, P.node_off, P.node_x, P.node_y, P.node_w, P.node_el,
+                       P.pts_xy + 2 * cut0);
 }
 
 }  // namespace iga
