@@ -120,12 +120,16 @@ static void setup_trim(Plan& P, hipStream_t s, bool discover, bool points) {
     launch_dwq_choose(P, s);
     launch_trim_cutprep(P, s);
     if (discover) {
-        P.n_nodes = (P.n_cut_el > 0) ? d2h1(P.node_off + P.n_cut_el, s) : 0;
+        // node offsets are formed with the nodes; their total is needed to size the buffers first
+        P.n_nodes = 0;
         P.n_arcs = 0;
         if (P.n_cut_el > 0) {
+            std::vector<int> cnt((size_t)P.n_cut_el);
             std::vector<CutElemDev> ce((size_t)P.n_cut_el);
+            HIPX(hipMemcpyAsync(cnt.data(), P.node_cnt, cnt.size() * sizeof(int), hipMemcpyDeviceToHost, s));
             HIPX(hipMemcpyAsync(ce.data(), P.cut_el, ce.size() * sizeof(CutElemDev), hipMemcpyDeviceToHost, s));
             HIPX(hipStreamSynchronize(s));
+            for (int v : cnt) P.n_nodes += v;
             for (const CutElemDev& E : ce) P.n_arcs += E.narc;
         }
         size_t nn = std::max<int64_t>(P.n_nodes, 1);
@@ -392,8 +396,6 @@ int iga_plan_create(const iga_patch_desc* desc, const iga_opts* opts, iga_plan**
     P->gauss_w = P->alloc<double>(gauss_off(IGA_MAX_GAUSS + 1));
     P->status = P->alloc<int>(1);
     P->counts = P->alloc<int>(16);
-    P->tickets = P->alloc<int>(8);
-    HIPX(hipMemsetAsync(P->tickets, 0, 8 * sizeof(int), s));
     HIPX(hipMemsetAsync(P->status, 0, sizeof(int), s));
 
     // curves

@@ -82,8 +82,9 @@ struct CrossDev {
 };
 
 struct ArcDev {
-    int curve, seg, piece, keep;
+    int curve, gseg, piece, keep;   // gseg: index into the segment array
     double t0, t1;
+    double x0, y0, x1, y1;          // curve points at t0 and t1
     int e1, e2;
     int k0, l0;   // start endpoint kind / line
     int k1, l1;   // end endpoint kind / line
@@ -190,7 +191,6 @@ struct Plan {
     int* scan_tmp = nullptr;       // block sums of a scan, then compaction positions
     int scan_pos_off = 0;
     int* counts = nullptr;         // small device counter block
-    int* tickets = nullptr;        // last-workgroup tickets (zero between launches)
     int* status = nullptr;         // device status word
 
     // points and coefficient values (c_wq [Q2][Q1], c_band, c_cut)

@@ -20,13 +20,28 @@
 namespace iga {
 
 // ------------------------------------------------------------ evaluation
+// A point and tangent of a curve.
+struct CurvePt {
+    double X, Y, dX, dY;
+};
+
+// Ellipse branch out of line: its sine and cosine are large, and the trimming
+// kernels run few waves each, so instruction fetch rather than arithmetic
+// bounds them. Arguments and result travel in registers.
+__device__ __attribute__((noinline)) CurvePt ellipse_eval(double x0, double x1, double x2, double y0, double y1,
+                                                          double y2, double t) {
+    double s, c;
+    sincos(t, &s, &c);
+    return CurvePt{x0 + x1 * c + x2 * s, y0 + y1 * c + y2 * s, -x1 * s + x2 * c, -y1 * s + y2 * c};
+}
+
 __device__ __forceinline__ void seg_eval(const SegDev& S, double t, double& X, double& Y, double& dX, double& dY) {
     if (S.kind == IGA_CURVE_ELLIPSE) {
-        double c = cos(t), s = sin(t);
-        X = S.px[0] + S.px[1] * c + S.px[2] * s;
-        Y = S.py[0] + S.py[1] * c + S.py[2] * s;
-        dX = -S.px[1] * s + S.px[2] * c;
-        dY = -S.py[1] * s + S.py[2] * c;
+        const CurvePt q = ellipse_eval(S.px[0], S.px[1], S.px[2], S.py[0], S.py[1], S.py[2], t);
+        X = q.X;
+        Y = q.Y;
+        dX = q.dX;
+        dY = q.dY;
     } else {
         X = ((S.px[3] * t + S.px[2]) * t + S.px[1]) * t + S.px[0];
         Y = ((S.py[3] * t + S.py[2]) * t + S.py[1]) * t + S.py[0];
@@ -125,6 +140,39 @@ __device__ __forceinline__ int upper_bound_i(const int* a, int n, int v) {
     return lo;
 }
 
+// Branch-free lower / upper bound of K values at once (first index with
+// a[i] >= v, resp. a[i] > v; n >= 1): the trip count depends on n only, so
+// the K searches' loads overlap.
+template <int K>
+__device__ __forceinline__ void lower_bound_k(const double* a, int n, const double* v, int* r) {
+    int base[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) base[k] = 0;
+    for (int len = n; len > 1;) {
+        const int half = len >> 1;
+#pragma unroll
+        for (int k = 0; k < K; ++k) base[k] = (a[base[k] + half] < v[k]) ? base[k] + half : base[k];
+        len -= half;
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) r[k] = base[k] + (a[base[k]] < v[k]);
+}
+
+template <int K>
+__device__ __forceinline__ void upper_bound_k(const double* a, int n, const double* v, int* r) {
+    int base[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) base[k] = 0;
+    for (int len = n; len > 1;) {
+        const int half = len >> 1;
+#pragma unroll
+        for (int k = 0; k < K; ++k) base[k] = (a[base[k] + half] <= v[k]) ? base[k] + half : base[k];
+        len -= half;
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) r[k] = base[k] + (a[base[k]] <= v[k]);
+}
+
 // ---------------------------------------------------------- segments
 // Uniform B-spline blending polynomials (power basis, low first) of degree 1..3:
 // rows are the functions, columns the powers.
@@ -150,7 +198,8 @@ __device__ SegDev segment_form(const CurveDev& C, int c, const double* __restric
     S.pad = 0;
     for (int k = 0; k < 4; ++k) S.px[k] = S.py[k] = 0.0;
     if (C.kind == IGA_CURVE_ELLIPSE) {
-        double cph = cos(C.phi), sph = sin(C.phi);
+        const CurvePt q = ellipse_eval(0.0, 1.0, 0.0, 0.0, 0.0, 1.0, C.phi);  // (cos phi, sin phi)
+        const double cph = q.X, sph = q.Y;
         S.px[0] = C.cx; S.px[1] = C.a * cph; S.px[2] = -C.b * sph;
         S.py[0] = C.cy; S.py[1] = C.a * sph; S.py[2] = C.b * cph;
     } else {
@@ -200,6 +249,20 @@ __device__ __forceinline__ void quad_roots(double a, double b, double c, double 
     if (t2 > lo && t2 < hi && t2 != t1) r1 = t2;
 }
 
+// Zeros of X' and Y' of an ellipse segment in (0, hi) (+inf where outside), out of line.
+__device__ __attribute__((noinline)) CurvePt ellipse_splits(double x1, double x2, double y1, double y2, double hi) {
+    const double tp = 2.0 * M_PI, lo = 0.0, inf = __builtin_inf();
+    const double c[4] = {atan2(x2, x1), atan2(x2, x1) + M_PI, atan2(y2, y1), atan2(y2, y1) + M_PI};
+    double r[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        double t = fmod(c[k], tp);
+        if (t < 0.0) t += tp;
+        r[k] = (t > lo && t < hi) ? t : inf;
+    }
+    return CurvePt{r[0], r[1], r[2], r[3]};
+}
+
 __device__ __forceinline__ void sort2(double& a, double& b) {
     const double lo = fmin(a, b), hi = fmax(a, b);
     a = lo;
@@ -212,15 +275,11 @@ __device__ __forceinline__ void sort2(double& a, double& b) {
 __device__ __forceinline__ void segment_splits(const SegDev& S, double hi, double r[4]) {
     const double lo = 0.0, inf = __builtin_inf();
     if (S.kind == IGA_CURVE_ELLIPSE) {
-        const double tp = 2.0 * M_PI;
-        const double c[4] = {atan2(S.px[2], S.px[1]), atan2(S.px[2], S.px[1]) + M_PI, atan2(S.py[2], S.py[1]),
-                             atan2(S.py[2], S.py[1]) + M_PI};
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            double t = fmod(c[k], tp);
-            if (t < 0.0) t += tp;
-            r[k] = (t > lo && t < hi) ? t : inf;
-        }
+        const CurvePt q = ellipse_splits(S.px[1], S.px[2], S.py[1], S.py[2], hi);
+        r[0] = q.X;
+        r[1] = q.Y;
+        r[2] = q.dX;
+        r[3] = q.dY;
     } else {
         quad_roots(S.px[1], 2.0 * S.px[2], 3.0 * S.px[3], lo, hi, r[0], r[1]);
         quad_roots(S.py[1], 2.0 * S.py[2], 3.0 * S.py[3], lo, hi, r[2], r[3]);
@@ -460,10 +519,13 @@ __device__ __forceinline__ BpView stage_bp(const GridDev& G, double* sbp) {
 // box, counted half-open so that a crossing at a shared end belongs to one piece.
 __device__ __forceinline__ void piece_cross_count(const PieceDev& Pc, const BpView& bp, const GridDev& G, int& nv,
                                                   int& nh) {
-    const double xmin = fmin(Pc.x0, Pc.x1), xmax = fmax(Pc.x0, Pc.x1);
-    const double ymin = fmin(Pc.y0, Pc.y1), ymax = fmax(Pc.y0, Pc.y1);
-    nv = lower_bound_d(bp.b1, G.N1 + 1, xmax) - lower_bound_d(bp.b1, G.N1 + 1, xmin);
-    nh = lower_bound_d(bp.b2, G.N2 + 1, ymax) - lower_bound_d(bp.b2, G.N2 + 1, ymin);
+    const double vx[2] = {fmin(Pc.x0, Pc.x1), fmax(Pc.x0, Pc.x1)};
+    const double vy[2] = {fmin(Pc.y0, Pc.y1), fmax(Pc.y0, Pc.y1)};
+    int rx[2], ry[2];
+    lower_bound_k<2>(bp.b1, G.N1 + 1, vx, rx);
+    lower_bound_k<2>(bp.b2, G.N2 + 1, vy, ry);
+    nv = rx[1] - rx[0];
+    nh = ry[1] - ry[0];
 }
 
 // Union of holes (one workgroup of 1024, after the curve-curve splits):
@@ -562,16 +624,27 @@ __device__ void front_one_curve(const TrimDev& T, const double* __restrict__ cp,
         }
         int tot_p, tot_c;
         const int offp = block_scan_carry(sp.n, sh, tot_p) + carry_p;
+        // crossing counts of all five piece slots, the twenty searches in lockstep
+        PieceDev pcs[5];
+        double vx[10], vy[10];
+#pragma unroll
+        for (int k = 0; k < 5; ++k) {
+            pcs[k] = (valid && sp.use[k]) ? make_piece(S, s, sp.t0[k], sp.t1[k]) : PieceDev{};
+            vx[2 * k] = fmin(pcs[k].x0, pcs[k].x1);
+            vx[2 * k + 1] = fmax(pcs[k].x0, pcs[k].x1);
+            vy[2 * k] = fmin(pcs[k].y0, pcs[k].y1);
+            vy[2 * k + 1] = fmax(pcs[k].y0, pcs[k].y1);
+        }
+        int rx[10], ry[10];
+        lower_bound_k<10>(bp.b1, G.N1 + 1, vx, rx);
+        lower_bound_k<10>(bp.b2, G.N2 + 1, vy, ry);
         int cnt[5], nvk[5], csum = 0;
 #pragma unroll
         for (int k = 0; k < 5; ++k) {
-            cnt[k] = nvk[k] = 0;
-            if (valid && sp.use[k]) {
-                int nh;
-                piece_cross_count(make_piece(S, s, sp.t0[k], sp.t1[k]), bp, G, nvk[k], nh);
-                cnt[k] = nvk[k] + nh;
-                csum += cnt[k];
-            }
+            const bool on = valid && sp.use[k];
+            nvk[k] = on ? rx[2 * k + 1] - rx[2 * k] : 0;
+            cnt[k] = on ? nvk[k] + (ry[2 * k + 1] - ry[2 * k]) : 0;
+            csum += cnt[k];
         }
         const int offc = block_scan_carry(csum, sh, tot_c) + carry_c;
         if (valid) {
@@ -579,7 +652,7 @@ __device__ void front_one_curve(const TrimDev& T, const double* __restrict__ cp,
 #pragma unroll
             for (int k = 0; k < 5; ++k) {
                 if (!sp.use[k]) continue;
-                T.pieces[q] = make_piece(S, s, sp.t0[k], sp.t1[k]);
+                T.pieces[q] = pcs[k];
                 T.nv[q] = nvk[k];
                 T.cross_cnt[q] = cnt[k];
                 T.cross_off[q] = run;
@@ -685,23 +758,22 @@ __global__ void __launch_bounds__(256) k_piece_arcs(TrimDev T, GridDev G, int* _
     __syncthreads();
     const double xmin = fmin(Pc.x0, Pc.x1), xmax = fmax(Pc.x0, Pc.x1);
     const double ymin = fmin(Pc.y0, Pc.y1), ymax = fmax(Pc.y0, Pc.y1);
-    const int lv0 = lower_bound_d(bp.b1, G.N1 + 1, xmin);
-    const int lh0 = lower_bound_d(bp.b2, G.N2 + 1, ymin);
-    // spline pieces: rows whose centre y lies in [ymin, ymax) (centres are non-decreasing in the row)
+    int lv0, lh0;
+    lower_bound_k<1>(bp.b1, G.N1 + 1, &xmin, &lv0);
+    lower_bound_k<1>(bp.b2, G.N2 + 1, &ymin, &lh0);
+    // spline pieces: rows whose centre y lies in [ymin, ymax) (centres are non-decreasing in
+    // the row): branch-free lower bounds of ymin and ymax over the row centres, in lockstep
     int r0 = 0, r1 = 0;
     if (C.kind != IGA_CURVE_ELLIPSE) {
-        int lo = 0, hi = G.N2;
-        while (lo < hi) {
-            const int mid = (lo + hi) >> 1;
-            if (0.5 * (bp.b2[mid] + bp.b2[mid + 1]) < ymin) lo = mid + 1; else hi = mid;
+        int b0 = 0, b1 = 0;
+        for (int len = G.N2; len > 1;) {
+            const int half = len >> 1;
+            b0 = (0.5 * (bp.b2[b0 + half] + bp.b2[b0 + half + 1]) < ymin) ? b0 + half : b0;
+            b1 = (0.5 * (bp.b2[b1 + half] + bp.b2[b1 + half + 1]) < ymax) ? b1 + half : b1;
+            len -= half;
         }
-        r0 = lo;
-        hi = G.N2;
-        while (lo < hi) {
-            const int mid = (lo + hi) >> 1;
-            if (0.5 * (bp.b2[mid] + bp.b2[mid + 1]) < ymax) lo = mid + 1; else hi = mid;
-        }
-        r1 = lo;
+        r0 = b0 + (0.5 * (bp.b2[b0] + bp.b2[b0 + 1]) < ymin);
+        r1 = b1 + (0.5 * (bp.b2[b1] + bp.b2[b1 + 1]) < ymax);
     }
     // grid-line crossings (j < n) and centre-line crossings (j >= n) in one pass
     for (int j = tid; j < n + (r1 - r0); j += 256) {
@@ -762,20 +834,25 @@ __global__ void __launch_bounds__(256) k_piece_arcs(TrimDev T, GridDev G, int* _
     for (int j = tid; j <= n; j += 256) {
         ArcDev A;
         A.curve = Pc.curve;
-        A.seg = S.seg;
+        A.gseg = Pc.seg;
         A.piece = k;
         if (j == 0) { A.t0 = Pc.t0; A.k0 = END_PIECE; A.l0 = -1; }
         else { const CrossDev X = merged[j - 1]; A.t0 = X.t; A.k0 = X.kind; A.l0 = X.line; }
         if (j == n) { A.t1 = Pc.t1; A.k1 = END_PIECE; A.l1 = -1; }
         else { const CrossDev X = merged[j]; A.t1 = X.t; A.k1 = X.kind; A.l1 = X.line; }
         double X, Y, dX, dY;
+        seg_eval(S, A.t0, A.x0, A.y0, dX, dY);
+        seg_eval(S, A.t1, A.x1, A.y1, dX, dY);
         seg_eval(S, 0.5 * (A.t0 + A.t1), X, Y, dX, dY);
         int keep = (A.t1 - A.t0 > 1e-13 * C.t_range);
         keep = keep && X > bp.b1[0] && X < bp.b1[G.N1] && Y > bp.b2[0] && Y < bp.b2[G.N2];
         if (keep && T.n_curves > 1) keep = !in_any_hole(T, X, Y, Pc.curve);
         A.keep = keep;
-        A.e1 = min(max(upper_bound_d(bp.b1, G.N1 + 1, X) - 1, 0), G.N1 - 1);
-        A.e2 = min(max(upper_bound_d(bp.b2, G.N2 + 1, Y) - 1, 0), G.N2 - 1);
+        int u1, u2;
+        upper_bound_k<1>(bp.b1, G.N1 + 1, &X, &u1);
+        upper_bound_k<1>(bp.b2, G.N2 + 1, &Y, &u2);
+        A.e1 = min(max(u1 - 1, 0), G.N1 - 1);
+        A.e2 = min(max(u2 - 1, 0), G.N2 - 1);
         const int idx = base + k + j;
         T.arcs[idx] = A;
         if (keep) {  // push onto the element's list (order fixed later by arc index)
@@ -939,7 +1016,7 @@ struct ListArgs {
     int* bsum;           // [4][ntiles] tile counts, then tile offsets
     int ntiles;
     int* counts;         // [4] totals
-    int* ticket;         // workgroups done counting (the last one scans, then resets it)
+    int prefix_here;     // 1: each writing workgroup sums the tile counts before it; 0: bsum holds offsets
 };
 
 __device__ __forceinline__ int block_sum256(int v, int* sh) {
@@ -953,11 +1030,9 @@ __device__ __forceinline__ int block_sum256(int v, int* sh) {
     return tot;
 }
 
-// Tile counts of the four flag arrays; the workgroup that finishes last
-// (ticket) turns them into tile offsets and totals.
+// Tile counts of the four flag arrays.
 __global__ void __launch_bounds__(256) k_list_count(ListArgs A) {
-    __shared__ int sh[256 / 64 + 1];
-    __shared__ int s_last;
+    __shared__ int sh[4];
     const int b = blockIdx.x, base = b * kListTile + threadIdx.x * 4;
     int c[4];
 #pragma unroll
@@ -971,40 +1046,43 @@ __global__ void __launch_bounds__(256) k_list_count(ListArgs A) {
         const int tot = block_sum256(c[a], sh);
         if (threadIdx.x == 0) A.bsum[a * A.ntiles + b] = tot;
     }
-    if (threadIdx.x == 0) {
-        __threadfence();  // this tile's counts are visible before its ticket
-        s_last = atomicAdd(A.ticket, 1) == A.ntiles - 1;
-    }
-    __syncthreads();
-    if (!s_last) return;
-    __threadfence();      // every tile's counts are visible to the last workgroup
-    int carry[4] = {0, 0, 0, 0};
-    for (int t0 = 0; t0 < A.ntiles; t0 += 256) {
-        const int idx = t0 + threadIdx.x;
-        int v[4];
-#pragma unroll
-        for (int a = 0; a < 4; ++a)
-            v[a] = (idx < A.ntiles)
-                       ? __hip_atomic_load(&A.bsum[a * A.ntiles + idx], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
-                       : 0;
-#pragma unroll
-        for (int a = 0; a < 4; ++a) {
+}
+
+// Many tiles: exclusive scan of the tile counts (one workgroup).
+__global__ void __launch_bounds__(1024) k_list_scan(ListArgs A) {
+    __shared__ int sh[1024 / 64 + 1];
+    for (int a = 0; a < 4; ++a) {
+        int carry = 0;
+        for (int t0 = 0; t0 < A.ntiles; t0 += 1024) {
+            const int idx = t0 + threadIdx.x;
+            const int v = (idx < A.ntiles) ? A.bsum[a * A.ntiles + idx] : 0;
             int total;
-            const int ex = block_excl_scan(v[a], sh, total);
-            if (idx < A.ntiles) A.bsum[a * A.ntiles + idx] = ex + carry[a];
-            carry[a] += total;
+            const int ex = block_excl_scan(v, sh, total);
+            if (idx < A.ntiles) A.bsum[a * A.ntiles + idx] = ex + carry;
+            carry += total;
         }
-    }
-    if (threadIdx.x == 0) {
-#pragma unroll
-        for (int a = 0; a < 4; ++a) A.counts[a] = carry[a];
-        *A.ticket = 0;
+        if (threadIdx.x == 0) A.counts[a] = carry;
     }
 }
 
 __global__ void __launch_bounds__(256) k_list_write(ListArgs A) {
     __shared__ int sh[256 / 64 + 1];
+    __shared__ int s_off[4];
     const int b = blockIdx.x, base = b * kListTile + threadIdx.x * 4;
+    if (A.prefix_here) {  // this tile's offsets: the counts of the tiles before it
+        int v[4] = {0, 0, 0, 0};
+        for (int t = threadIdx.x; t < b; t += 256)
+#pragma unroll
+            for (int a = 0; a < 4; ++a) v[a] += A.bsum[a * A.ntiles + t];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+            const int tot = block_sum256(v[a], sh);
+            if (threadIdx.x == 0) s_off[a] = tot;
+        }
+    } else if (threadIdx.x < 4) {
+        s_off[threadIdx.x] = A.bsum[threadIdx.x * A.ntiles + b];
+    }
+    __syncthreads();
     int fl[4][4];
 #pragma unroll
     for (int a = 0; a < 4; ++a)
@@ -1015,7 +1093,8 @@ __global__ void __launch_bounds__(256) k_list_write(ListArgs A) {
     for (int a = 0; a < 4; ++a) {
         const int v = fl[a][0] + fl[a][1] + fl[a][2] + fl[a][3];
         int total;
-        int pos = block_excl_scan(v, sh, total) + A.bsum[a * A.ntiles + b];
+        int pos = block_excl_scan(v, sh, total) + s_off[a];
+        if (A.prefix_here && b == A.ntiles - 1 && threadIdx.x == 0) A.counts[a] = s_off[a] + total;
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const int i = base + j;
@@ -1042,8 +1121,9 @@ void launch_trim_lists(Plan& P, hipStream_t s) {
     A.ntiles = (std::max(nf, ne) + kListTile - 1) / kListTile;
     A.bsum = P.scan_tmp + P.scan_pos_off;  // 4 * ntiles <= the position region
     A.counts = P.counts;
-    A.ticket = P.tickets + 0;
+    A.prefix_here = A.ntiles <= 1024;
     hipLaunchKernelGGL(k_list_count, dim3(A.ntiles), dim3(256), 0, s, A);
+    if (!A.prefix_here) hipLaunchKernelGGL(k_list_scan, dim3(1), dim3(1024), 0, s, A);
     hipLaunchKernelGGL(k_list_write, dim3(A.ntiles), dim3(256), 0, s, A);
 }
 
@@ -1062,8 +1142,7 @@ struct CutArgs {
     const double* gx;
     const double* gw;
     int* status;
-    int* node_off;      // exclusive scan of node_cnt, written by the last workgroup of k_cutprep
-    int* ticket;
+    int* node_off;      // exclusive scan of node_cnt (written by k_cut_nodes)
 };
 
 __device__ __forceinline__ int arc_nq(const CutArgs& A, const CurveDev& C) {
@@ -1079,24 +1158,39 @@ struct PieceBox {
     int seg, curve;
 };
 
-// in_any_hole with the pieces' boxes read from LDS (same tests, same order).
-__device__ bool in_any_hole_lds(const TrimDev& T, const PieceBox* sp, const int* scoff, double x, double y) {
+// in_any_hole with the pieces' boxes (and, if staged, the segments) read
+// from LDS: same tests, same order.
+constexpr int kPrepSegs = 128;
+__device__ bool in_any_hole_lds(const TrimDev& T, const PieceBox* sp, const int* scoff, const SegDev* sseg, double x,
+                                double y) {
     for (int c = 0; c < T.n_curves; ++c) {
         const CurveDev C = T.curves[c];
         if (C.kind == IGA_CURVE_ELLIPSE) {
             if (ellipse_implicit(C, x, y) < 0.0) return true;
             continue;
         }
+        // eight boxes per step, so their LDS reads overlap; the (few) hits are solved after
         bool in = false;
-        for (int k = scoff[c]; k < scoff[c + 1]; ++k) {
-            const PieceBox& B = sp[k];
-            if (!(y >= B.ymin && y < B.ymax)) continue;
-            if (B.xmax <= x) continue;
-            const SegDev S = T.segs[B.seg];
-            const double t = solve_monotone(S, 1, y, B.t0, B.t1);
-            double X, Y, dX, dY;
-            seg_eval(S, t, X, Y, dX, dY);
-            if (X > x) in = !in;
+        const int k1 = scoff[c + 1];
+        for (int kb = scoff[c]; kb < k1; kb += 8) {
+            unsigned hit = 0u;
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int k = min(kb + u, k1 - 1);
+                const PieceBox& B = sp[k];
+                const bool h = (kb + u < k1) && (y >= B.ymin && y < B.ymax) && !(B.xmax <= x);
+                hit |= (h ? 1u : 0u) << u;
+            }
+            while (hit) {
+                const int u = __builtin_ctz(hit);
+                hit &= hit - 1u;
+                const PieceBox& B = sp[kb + u];
+                const SegDev S = sseg ? sseg[B.seg] : T.segs[B.seg];
+                const double t = solve_monotone(S, 1, y, B.t0, B.t1);
+                double X, Y, dX, dY;
+                seg_eval(S, t, X, Y, dX, dY);
+                if (X > x) in = !in;
+            }
         }
         if (in) return true;
     }
@@ -1113,7 +1207,7 @@ __device__ bool in_any_hole_lds(const TrimDev& T, const PieceBox* sp, const int*
 // (3) all lanes test the sub-intervals' midpoints against the holes; (4) lanes
 // 0..3 merge the visible sub-intervals; (5) every lane adds its share of
 // sum |w| of the four bases over the arcs' Gauss points; lane 0 picks the base
-// and the node count. The workgroup that finishes last scans the node counts.
+// and the node count.
 __global__ void __launch_bounds__(64) k_cutprep(CutArgs A) {
     const int c = blockIdx.x;
     if (c >= A.n_cut) return;
@@ -1122,17 +1216,18 @@ __global__ void __launch_bounds__(64) k_cutprep(CutArgs A) {
     __shared__ double sEnd[kMaxArcsPerElem][2][2];   // (X, Y) at t0, t1
     __shared__ int sKind[kMaxArcsPerElem][2][2];     // (kind, line) at t0, t1
     __shared__ double sT[kMaxArcsPerElem][2];        // t0, t1
-    __shared__ int sSeg[kMaxArcsPerElem], sCurve[kMaxArcsPerElem];
     __shared__ double sIv[4][kMaxEdgeCuts + 1][2];   // sub-intervals per edge
     __shared__ int sIvOk[4][kMaxEdgeCuts + 1];        // -1 too short, 0 in a hole, 1 visible
     __shared__ int sNiv[4];
     __shared__ double sLen[4];
     __shared__ int sOverflow;
-    __shared__ int sLast;
     __shared__ int sArc[kMaxArcsPerElem];
     __shared__ int sNa;
     __shared__ PieceBox sP[kPrepPieces];
     __shared__ int sCoff[33];
+    __shared__ SegDev sSegAll[kPrepSegs];
+    __shared__ SegDev sArcSeg[kMaxArcsPerElem];
+    __shared__ int sNq[kMaxArcsPerElem], sNqOff[kMaxArcsPerElem + 1];
     const int e = A.cut_list[c];
     const int e1 = e % A.G.N1, e2 = e / A.G.N1;
     const double xa = A.G.bp1[e1], xb = A.G.bp1[e1 + 1], ya = A.G.bp2[e2], yb = A.G.bp2[e2 + 1];
@@ -1147,6 +1242,9 @@ __global__ void __launch_bounds__(64) k_cutprep(CutArgs A) {
         }
         for (int k = lane; k <= T.n_curves; k += 64) sCoff[k] = T.piece_curve_off[k];
     }
+    const bool segs_staged = staged && T.n_segs <= kPrepSegs;
+    if (segs_staged)
+        for (int k = lane; k < T.n_segs; k += 64) sSegAll[k] = T.segs[k];
     if (lane == 0) {
         const unsigned long long h = A.ehead[e];
         int a = ((int)(h >> 32) == A.epoch) ? (int)(h & 0xffffffffull) - 1 : -1;
@@ -1171,23 +1269,18 @@ __global__ void __launch_bounds__(64) k_cutprep(CutArgs A) {
     for (int q = lane; q < na; q += 64) {
         out.arc[q] = sArc[q];
         const ArcDev R = T.arcs[sArc[q]];
-        const int sidx = T.pieces[R.piece].seg;
-        const SegDev S = T.segs[sidx];
-        double X, Y, dX, dY;
-        seg_eval(S, R.t0, X, Y, dX, dY);
-        sEnd[q][0][0] = X;
-        sEnd[q][0][1] = Y;
-        seg_eval(S, R.t1, X, Y, dX, dY);
-        sEnd[q][1][0] = X;
-        sEnd[q][1][1] = Y;
+        sArcSeg[q] = T.segs[R.gseg];
+        sNq[q] = arc_nq(A, T.curves[R.curve]);
+        sEnd[q][0][0] = R.x0;
+        sEnd[q][0][1] = R.y0;
+        sEnd[q][1][0] = R.x1;
+        sEnd[q][1][1] = R.y1;
         sKind[q][0][0] = R.k0;
         sKind[q][0][1] = R.l0;
         sKind[q][1][0] = R.k1;
         sKind[q][1][1] = R.l1;
         sT[q][0] = R.t0;
         sT[q][1] = R.t1;
-        sSeg[q] = sidx;
-        sCurve[q] = R.curve;
     }
     __syncthreads();
     // (2) edge cut points and sub-intervals
@@ -1232,6 +1325,13 @@ __global__ void __launch_bounds__(64) k_cutprep(CutArgs A) {
         }
         sNiv[edge] = n + 1;
         if (overflow) sOverflow = 1;
+    } else if (lane == 4) {  // offsets of the arcs' Gauss points
+        int off = 0;
+        for (int q = 0; q < na; ++q) {
+            sNqOff[q] = off;
+            off += sNq[q];
+        }
+        sNqOff[na] = off;
     }
     __syncthreads();
     // (3) hole tests of the sub-intervals' midpoints, all lanes
@@ -1241,7 +1341,10 @@ __global__ void __launch_bounds__(64) k_cutprep(CutArgs A) {
         const double fixed = (edge == 0) ? xa : (edge == 1) ? xb : (edge == 2) ? ya : yb;
         const double m = 0.5 * (sIv[edge][q][0] + sIv[edge][q][1]);
         const double x = (edge < 2) ? fixed : m, y = (edge < 2) ? m : fixed;
-        sIvOk[edge][q] = (staged ? in_any_hole_lds(T, sP, sCoff, x, y) : in_any_hole(T, x, y)) ? 0 : 1;
+        sIvOk[edge][q] = (staged ? in_any_hole_lds(T, sP, sCoff, segs_staged ? sSegAll : nullptr, x, y)
+                                 : in_any_hole(T, x, y))
+                             ? 0
+                             : 1;
     }
     __syncthreads();
     // (4) merge the visible sub-intervals
@@ -1272,24 +1375,23 @@ __global__ void __launch_bounds__(64) k_cutprep(CutArgs A) {
         sLen[edge] = len;
         if (overflow) sOverflow = 1;
     }
-    // (5) sum |w| of the four bases over the arcs' Gauss points
+    // (5) sum |w| of the four bases over the arcs' Gauss points, one (arc, point) pair per lane
     double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-    int narc_nodes = 0;
-    for (int q = 0; q < na; ++q) {
-        const SegDev S = T.segs[sSeg[q]];
-        const int nq = arc_nq(A, T.curves[sCurve[q]]);
-        narc_nodes += nq * A.n_r;
+    const int npts = sNqOff[na];
+    const int narc_nodes = npts * A.n_r;
+    for (int u = lane; u < npts; u += 64) {
+        int q = 0;
+        while (q + 1 < na && sNqOff[q + 1] <= u) ++q;
+        const int nq = sNq[q], g = u - sNqOff[q];
         const double t0 = sT[q][0], t1 = sT[q][1];
-        for (int g = lane; g < nq; g += 64) {
-            const double tq = t0 + (t1 - t0) * (A.gx[gauss_off(nq) + g] + 1.0) * 0.5;
-            const double wt = A.gw[gauss_off(nq) + g] * (t1 - t0) * 0.5;
-            double X, Y, dX, dY;
-            seg_eval(S, tq, X, Y, dX, dY);
-            s0 += wt * fabs(dY) * fabs(X - xa);
-            s1 += wt * fabs(dY) * fabs(X - xb);
-            s2 += wt * fabs(dX) * fabs(Y - ya);
-            s3 += wt * fabs(dX) * fabs(Y - yb);
-        }
+        const double tq = t0 + (t1 - t0) * (A.gx[gauss_off(nq) + g] + 1.0) * 0.5;
+        const double wt = A.gw[gauss_off(nq) + g] * (t1 - t0) * 0.5;
+        double X, Y, dX, dY;
+        seg_eval(sArcSeg[q], tq, X, Y, dX, dY);
+        s0 += wt * fabs(dY) * fabs(X - xa);
+        s1 += wt * fabs(dY) * fabs(X - xb);
+        s2 += wt * fabs(dX) * fabs(Y - ya);
+        s3 += wt * fabs(dX) * fabs(Y - yb);
     }
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) {
@@ -1311,42 +1413,6 @@ __global__ void __launch_bounds__(64) k_cutprep(CutArgs A) {
         out.variant = var;
         A.node_cnt[c] = narc_nodes + out.nseg[opp] * A.n_s * A.n_r;
         if (sOverflow) atomicExch(A.status, IGA_E_TOPOLOGY);
-        __threadfence();  // this element's count is visible before its ticket
-        sLast = atomicAdd(A.ticket, 1) == A.n_cut - 1;
-    }
-    __syncthreads();
-    if (!sLast) return;
-    // the last workgroup: node offsets, exclusive scan of every element's count;
-    // 2048 counts at a time, each lane loading a contiguous run of up to 32 at once
-    __threadfence();
-    int carry = 0;
-    for (int b0 = 0; b0 < A.n_cut; b0 += 64 * 32) {
-        const int K = min(32, (A.n_cut - b0 + 63) / 64);
-        int v[32];
-#pragma unroll
-        for (int j = 0; j < 32; ++j) {
-            const int i = b0 + lane * K + j;
-            v[j] = (j < K && i < A.n_cut) ? __hip_atomic_load(&A.node_cnt[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
-                                          : 0;
-        }
-        int lsum = 0;
-#pragma unroll
-        for (int j = 0; j < 32; ++j) lsum += v[j];
-        const int inc = wave_incl_scan(lsum, lane);
-        int run = carry + inc - lsum;
-#pragma unroll
-        for (int j = 0; j < 32; ++j) {
-            const int i = b0 + lane * K + j;
-            if (j < K && i < A.n_cut) {
-                A.node_off[i] = run;
-                run += v[j];
-            }
-        }
-        carry += __shfl(inc, 63, 64);
-    }
-    if (lane == 0) {
-        A.node_off[A.n_cut] = carry;
-        *A.ticket = 0;
     }
 }
 
@@ -1356,12 +1422,15 @@ void launch_trim_cutprep(Plan& P, hipStream_t s) {
     if (T.n_curves == 0 || nc == 0) return;
     GridDev G{P.dir[0].knots + P.p, P.dir[1].knots + P.p, P.N1, P.N2};  // breakpoints
     CutArgs A{T, G, nc, P.cut_list, P.ehead, P.arc_next, P.epoch, P.cut_el, P.node_cnt,
-              P.n_r, P.n_q_override, P.n_s, P.p, P.gauss_x, P.gauss_w, P.status, P.node_off, P.tickets + 1};
+              P.n_r, P.n_q_override, P.n_s, P.p, P.gauss_x, P.gauss_w, P.status, P.node_off};
     hipLaunchKernelGGL(k_cutprep, dim3(nc), dim3(64), 0, s, A);
 }
 
-// One wavefront per cut element writes its nodes (and their entries of the rule-point table).
-__global__ void __launch_bounds__(64) k_cut_nodes(CutArgs A, const int* __restrict__ node_off, double* __restrict__ nx,
+// One wavefront per cut element writes its nodes (and their entries of the
+// rule-point table), at the offset the counts before it add up to.
+constexpr int kNodePrefixMax = 8192;  // up to this many cut elements each workgroup sums the counts before it
+
+__global__ void __launch_bounds__(64) k_cut_nodes(CutArgs A, int prefix_here, double* __restrict__ nx,
                                                   double* __restrict__ ny, double* __restrict__ nw,
                                                   int* __restrict__ nel, double* __restrict__ xy) {
     int c = blockIdx.x;
@@ -1376,10 +1445,33 @@ __global__ void __launch_bounds__(64) k_cut_nodes(CutArgs A, const int* __restri
     int nr = A.n_r;
     const double* rx = A.gx + gauss_off(nr);
     const double* rw = A.gw + gauss_off(nr);
-    int pos = node_off[c];
+    // this element's first node: the sum of the counts before it (or the scanned offsets)
+    int pos;
+    if (prefix_here) {
+        int sum = 0;
+        for (int i0 = 0; i0 < c; i0 += 64 * 8) {
+            int v[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int i = i0 + threadIdx.x + 64 * j;
+                v[j] = (i < c) ? A.node_cnt[i] : 0;
+            }
+#pragma unroll
+            for (int j = 0; j < 8; ++j) sum += v[j];
+        }
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) sum += __shfl_xor(sum, o, 64);
+        pos = sum;
+        if (threadIdx.x == 0) {
+            A.node_off[c] = pos;
+            if (c == A.n_cut - 1) A.node_off[A.n_cut] = pos + A.node_cnt[c];
+        }
+    } else {
+        pos = A.node_off[c];
+    }
     for (int q = 0; q < E.narc; ++q) {
         const ArcDev R = T.arcs[E.arc[q]];
-        const SegDev S = T.segs[T.pieces[R.piece].seg];
+        const SegDev S = T.segs[R.gseg];
         const CurveDev C = T.curves[R.curve];
         int nq = arc_nq(A, C);
         for (int g = threadIdx.x; g < nq; g += 64) {
@@ -1431,10 +1523,12 @@ void launch_trim_nodes(Plan& P, hipStream_t s) {
     if (T.n_curves == 0 || nc == 0) return;
     GridDev G{P.dir[0].knots + P.p, P.dir[1].knots + P.p, P.N1, P.N2};  // breakpoints
     CutArgs A{T, G, nc, P.cut_list, P.ehead, P.arc_next, P.epoch, P.cut_el, P.node_cnt,
-              P.n_r, P.n_q_override, P.n_s, P.p, P.gauss_x, P.gauss_w, P.status, P.node_off, P.tickets + 1};
+              P.n_r, P.n_q_override, P.n_s, P.p, P.gauss_x, P.gauss_w, P.status, P.node_off};
     const size_t cut0 = (size_t)P.dir[0].Q * P.dir[1].Q + (size_t)P.n_band * (P.p + 1) * (P.p + 1);
-    hipLaunchKernelGGL(k_cut_nodes, dim3(nc), dim3(64), 0, s, A, P.node_off, P.node_x, P.node_y, P.node_w, P.node_el,
-                       P.pts_xy + 2 * cut0);
+    const int prefix_here = nc <= kNodePrefixMax;
+    if (!prefix_here) exclusive_scan(P.node_cnt, P.node_off, nc, P.scan_tmp, s);
+    hipLaunchKernelGGL(k_cut_nodes, dim3(nc), dim3(64), 0, s, A, prefix_here, P.node_x, P.node_y, P.node_w,
+                       P.node_el, P.pts_xy + 2 * cut0);
 }
 
 }  // namespace iga
