@@ -102,7 +102,6 @@ static void setup_trim(Plan& P, hipStream_t s, bool discover, bool points) {
     }
     launch_trim_classes(P, s);
     launch_trim_lists(P, s);
-    HIPX(hipEventRecord(P.ev_lists, s));  // classes and compact maps are ready
     if (discover) {
         int c[4];
         HIPX(hipMemcpyAsync(c, P.counts, 4 * sizeof(int), hipMemcpyDeviceToHost, s));
@@ -118,6 +117,7 @@ static void setup_trim(Plan& P, hipStream_t s, bool discover, bool points) {
         if (P.method == IGA_DWQ) P.dwq_region = P.alloc<int>(8 * (size_t)std::max<int64_t>(P.n_form_rows, 1));
     }
     launch_dwq_choose(P, s);
+    HIPX(hipEventRecord(P.ev_lists, s));  // classes, compact maps and DWQ boxes are ready
     launch_trim_cutprep(P, s);
     if (discover) {
         // node offsets are formed with the nodes; their total is needed to size the buffers first
@@ -231,9 +231,10 @@ static void form(Plan& P, const iga_coeff& c, double* vals, int flags, hipStream
     const bool full = (flags & IGA_FORM_FULL) != 0;
     hipStream_t a = P.aux;
     // aux stream: univariate tables and weights, c on the WQ grid and the band
-    // Gauss points, interior rows, rule points; the caller's stream: trimming,
-    // classes, lists, cut rules, c at the cut nodes, cut element matrices, the
-    // rows formed element-wise.
+    // Gauss points, the inside sums of the rows formed element-wise, interior
+    // rows, rule points; the caller's stream: trimming, classes, lists, cut
+    // rules, c at the cut nodes, cut element matrices and their entries in
+    // the rows formed element-wise.
     HIPX(hipEventRecord(P.ev_fork, s));
     HIPX(hipStreamWaitEvent(a, P.ev_fork, 0));
     if (full) setup_tables(P, a);
@@ -249,7 +250,11 @@ static void form(Plan& P, const iga_coeff& c, double* vals, int flags, hipStream
         HIPX(hipEventRecord(P.ev_lists, s));
     }
     HIPX(hipStreamWaitEvent(a, P.ev_lists, 0));
-    launch_coef(P, c, a, 3);
+    {
+        PhaseTimer t(P, a, IGA_PHASE_CUT);
+        launch_coef(P, c, a, 3);
+        launch_cut_rows_mode(P, c, vals, a, 1);  // rows formed element-wise: their inside sums
+    }
     HIPX(hipEventRecord(P.ev_band, a));
     {
         PhaseTimer t(P, a, IGA_PHASE_INTERIOR);
@@ -259,9 +264,10 @@ static void form(Plan& P, const iga_coeff& c, double* vals, int flags, hipStream
     HIPX(hipEventRecord(P.ev_interior, a));
     {
         PhaseTimer t(P, s, IGA_PHASE_CUT);
-        if (full) HIPX(hipStreamWaitEvent(s, P.ev_tables, 0));
         launch_coef(P, c, s, 4);
-        launch_cut_rows(P, c, vals, s, P.ev_band);
+        launch_cut_elems(P, c, s);
+        HIPX(hipStreamWaitEvent(s, P.ev_band, 0));
+        launch_cut_rows_mode(P, c, vals, s, 2);  // plus the cut element matrices' entries
         launch_dwq_rows(P, c, vals, s);
     }
     HIPX(hipStreamWaitEvent(s, P.ev_interior, 0));

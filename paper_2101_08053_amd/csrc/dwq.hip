@@ -389,13 +389,13 @@ __global__ void __launch_bounds__(256) k_dwq_rows(DwqRowArgs A) {
         sT[b][q1] = acc;
     }
     __syncthreads();
-    if (tid < W * W) {
-        const int a = tid / W, b = tid % W;
+    for (int t = tid; t < W * W; t += 256) {  // (2p+1)^2 slots: more than 256 at p = 8
+        const int a = t / W, b = t % W;
         const int j1 = i1 + a - P, j2 = i2 + b - P;
         if (j1 >= 0 && j1 < A.d1.n && j2 >= 0 && j2 < A.d2.n && A.act_of[j2 * A.d1.n + j1] >= 0) {
             double acc = 0.0;
             for (int q1 = 0; q1 < n1q; ++q1) acc += sWt[0][q1] * sB[0][q1][a] * sT[b][q1];
-            A.vals[(size_t)tid * A.n_act + row] += acc;
+            A.vals[(size_t)t * A.n_act + row] += acc;
         }
     }
 }

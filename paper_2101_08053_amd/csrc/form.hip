@@ -173,38 +173,46 @@ __global__ void __launch_bounds__(256) k_cut_elem(CutEArgs A) {
     cut_elem_body<P>(A, blockIdx.x, S);
 }
 
-template <int P>
+template <int P, int MODE>
 __global__ void __launch_bounds__((((2 * P + 1) * (2 * P + 1) + 63) / 64) * 64) k_cut_rows(CutRowArgs A) {
     __shared__ CutRSmem<P> S;
-    cut_row_body<P>(A, blockIdx.x, S);
+    cut_row_body_m<P, MODE>(A, blockIdx.x, S);
 }
 
-void launch_cut_rows(Plan& P, const iga_coeff& c, double* vals, hipStream_t s, hipEvent_t before_rows) {
-    if (P.method == IGA_NAIVE_WQ) return;
-    if (P.n_cut_el > 0) {
-        CutEArgs A = cute_args(P, c);
-        dim3 g((unsigned)P.n_cut_el), b(256);
-        switch (P.p) {
+void launch_cut_elems(Plan& P, const iga_coeff& c, hipStream_t s) {
+    if (P.method == IGA_NAIVE_WQ || P.n_cut_el == 0) return;
+    CutEArgs A = cute_args(P, c);
+    dim3 g((unsigned)P.n_cut_el), b(256);
+    switch (P.p) {
 #define CASE(PP) \
     case PP: hipLaunchKernelGGL(k_cut_elem<PP>, g, b, 0, s, A); break;
-            CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
+        CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
 #undef CASE
-            default: throw Error{IGA_E_UNSUPPORTED, "degree outside 1..8"};
-        }
+        default: throw Error{IGA_E_UNSUPPORTED, "degree outside 1..8"};
     }
-    if (before_rows) HIPX(hipStreamWaitEvent(s, before_rows, 0));
-    if (P.n_form_rows > 0) {
-        CutRowArgs A = cutr_args(P, c, vals);
-        int W = 2 * P.p + 1;
-        dim3 g((unsigned)P.n_form_rows), b(((W * W + 63) / 64) * 64);
-        switch (P.p) {
-#define CASE(PP) \
-    case PP: hipLaunchKernelGGL(k_cut_rows<PP>, g, b, 0, s, A); break;
-            CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
+}
+
+// mode: ROW_FUSED (after the cut element matrices), ROW_INSIDE (the inside sums, written; needs no cut
+// element matrix), ROW_CUT (adds the cut element matrices' entries to the inside sums)
+void launch_cut_rows_mode(Plan& P, const iga_coeff& c, double* vals, hipStream_t s, int mode) {
+    if (P.method == IGA_NAIVE_WQ || P.n_form_rows == 0) return;
+    CutRowArgs A = cutr_args(P, c, vals);
+    int W = 2 * P.p + 1;
+    dim3 g((unsigned)P.n_form_rows), b(((W * W + 63) / 64) * 64);
+    switch (P.p * 4 + mode) {
+#define CASE(PP)                                                                            \
+    case PP * 4 + ROW_FUSED: hipLaunchKernelGGL((k_cut_rows<PP, ROW_FUSED>), g, b, 0, s, A); break;   \
+    case PP * 4 + ROW_INSIDE: hipLaunchKernelGGL((k_cut_rows<PP, ROW_INSIDE>), g, b, 0, s, A); break; \
+    case PP * 4 + ROW_CUT: hipLaunchKernelGGL((k_cut_rows<PP, ROW_CUT>), g, b, 0, s, A); break;
+        CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
 #undef CASE
-            default: throw Error{IGA_E_UNSUPPORTED, "degree outside 1..8"};
-        }
+        default: throw Error{IGA_E_UNSUPPORTED, "degree outside 1..8"};
     }
+}
+
+void launch_cut_rows(Plan& P, const iga_coeff& c, double* vals, hipStream_t s) {
+    launch_cut_elems(P, c, s);
+    launch_cut_rows_mode(P, c, vals, s, ROW_FUSED);
 }
 
 }  // namespace iga

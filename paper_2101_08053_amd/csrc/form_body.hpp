@@ -184,10 +184,13 @@ __device__ __forceinline__ void interior_block(const IntArgs& A, int tx, int i2,
             live = A.all_active ? (cls != FN_EXTERIOR) : (cls == FN_INTERIOR);
             cid = id;
         }
-        double wb2 = 0.0;
-        if (tid < QM * W) {
-            const int q = tid / W;
-            if (q < q2) wb2 = D2.WB[((size_t)i2 * D2.qmax) * W + tid];
+        // the row's xi_2 factors: (4p+2)(2p+1) entries, more than 256 from p = 6 on
+        constexpr int NWB = (QM * W + 255) / 256;
+        double wb2[NWB];
+#pragma unroll
+        for (int u = 0; u < NWB; ++u) {
+            const int t = tid + 256 * u;
+            wb2[u] = (t < QM * W && t / W < q2) ? D2.WB[((size_t)i2 * D2.qmax) * W + t] : 0.0;
         }
         const int kk = min(tid, ks - 1);
         double cv[QM];
@@ -210,7 +213,11 @@ __device__ __forceinline__ void interior_block(const IntArgs& A, int tx, int i2,
                 for (int q = 0; q < QM; ++q) cv[q] = (q < q2) ? A.c.value : 0.0;
             }
         }
-        if (tid < QM * W) sWB2[tid / W][tid % W] = wb2;
+#pragma unroll
+        for (int u = 0; u < NWB; ++u) {
+            const int t = tid + 256 * u;
+            if (t < QM * W) sWB2[t / W][t % W] = wb2[u];
+        }
         if (!__syncthreads_or(live)) return;   // no row of the tile is formed here
 
         // ---- stage 1: contract xi_2 for every xi_1 point of the window
@@ -481,29 +488,32 @@ struct CutRowArgs {
 
 // One workgroup per row; the row's per-direction Gauss factors
 // F1[m1][g1][a] = w_g1 B_i1 B_{i1+a-p} (element e1 = i1-p+m1), F2 likewise,
-// the element classes and c at the Gauss points of its support elements are
-// staged in LDS. Inside elements are summed in two contractions: the
-// workgroup first forms U[m2][g2][a] (direction 1, summed over the element
-// columns m1), then thread (a, b) contracts U with F2 and adds its column's
-// entries of the cut element matrices.
+// the element classes, and per support element either c at its Gauss points
+// (inside) or the row's line of its local matrix (cut) are staged in LDS.
+// Inside elements are summed in two contractions: the workgroup first forms
+// U[m2][g2][a] (direction 1, summed over the element columns m1), then thread
+// (a, b) contracts U with F2 and adds its column's entries of the cut element
+// matrices. The row can also be formed in two launches with the same
+// arithmetic: the inside sum (written), then the cut entries (added).
+enum : int { ROW_FUSED = 0, ROW_INSIDE = 1, ROW_CUT = 2 };
+
 template <int P>
 struct CutRSmem {
     double sF1[P + 1][P + 1][2 * P + 1];
     double sF2[P + 1][P + 1][2 * P + 1];
-    double sX[P + 1][P + 1][(P + 1) * (P + 1)];  // inside element: c at its Gauss points (else 0)
-    double sE[P + 1][P + 1][(P + 1) * (P + 1)];  // cut element: row i of its local matrix (else 0)
-    double sU[P + 1][P + 1][2 * P + 1];          // direction-1 contraction, summed over m1
+    double sXE[P + 1][P + 1][(P + 1) * (P + 1)];  // inside: c at its Gauss points; cut: its local matrix line
+    double sU[P + 1][P + 1][2 * P + 1];           // direction-1 contraction, summed over m1
     int sCls[P + 1][P + 1];
     int sId[P + 1][P + 1];
 };
 
-template <int P>
-__device__ __forceinline__ void cut_row_body(const CutRowArgs& A, int r, CutRSmem<P>& S) {
+template <int P, int MODE>
+__device__ __forceinline__ void cut_row_body_m(const CutRowArgs& A, int r, CutRSmem<P>& S) {
     constexpr int W = 2 * P + 1, L = (P + 1) * (P + 1), NP = P + 1;
+    constexpr bool INS = (MODE != ROW_CUT), CUT = (MODE != ROW_INSIDE);
     auto& sF1 = S.sF1;
     auto& sF2 = S.sF2;
-    auto& sX = S.sX;
-    auto& sE = S.sE;
+    auto& sXE = S.sXE;
     auto& sCls = S.sCls;
     auto& sId = S.sId;
     if (r >= A.n_rows) return;
@@ -514,29 +524,31 @@ __device__ __forceinline__ void cut_row_body(const CutRowArgs& A, int r, CutRSme
     const int f = A.fn_of[row];
     const int i1 = f % D1.n, i2 = f / D1.n;
     int bx0 = 1, bx1 = 0, by0 = 1, by1 = 0;   // DWQ box (empty by default)
-    if (A.region && A.region[(size_t)r * 8] >= 0) {
+    if (INS && A.region && A.region[(size_t)r * 8] >= 0) {
         bx0 = A.region[(size_t)r * 8];
         bx1 = A.region[(size_t)r * 8 + 1];
         by0 = A.region[(size_t)r * 8 + 4];
         by1 = A.region[(size_t)r * 8 + 5];
     }
-    for (int t = tid; t < NP * NP * W; t += nt) {
-        int m = t / (NP * W), g = (t / W) % NP, a = t % W;
-        // direction 1
-        int e1 = i1 - P + m, j1 = i1 + a - P;
-        double v = 0.0;
-        if (e1 >= 0 && e1 < D1.N && j1 - e1 >= 0 && j1 - e1 <= P) {
-            int rr = (e1 * NP + g) * NP;
-            v = D1.wg[e1 * NP + g] * D1.Bg[rr + i1 - e1] * D1.Bg[rr + j1 - e1];
+    if (INS) {
+        for (int t = tid; t < NP * NP * W; t += nt) {
+            int m = t / (NP * W), g = (t / W) % NP, a = t % W;
+            // direction 1
+            int e1 = i1 - P + m, j1 = i1 + a - P;
+            double v = 0.0;
+            if (e1 >= 0 && e1 < D1.N && j1 - e1 >= 0 && j1 - e1 <= P) {
+                int rr = (e1 * NP + g) * NP;
+                v = D1.wg[e1 * NP + g] * D1.Bg[rr + i1 - e1] * D1.Bg[rr + j1 - e1];
+            }
+            sF1[m][g][a] = v;
+            int e2 = i2 - P + m, j2 = i2 + a - P;
+            v = 0.0;
+            if (e2 >= 0 && e2 < D2.N && j2 - e2 >= 0 && j2 - e2 <= P) {
+                int rr = (e2 * NP + g) * NP;
+                v = D2.wg[e2 * NP + g] * D2.Bg[rr + i2 - e2] * D2.Bg[rr + j2 - e2];
+            }
+            sF2[m][g][a] = v;
         }
-        sF1[m][g][a] = v;
-        int e2 = i2 - P + m, j2 = i2 + a - P;
-        v = 0.0;
-        if (e2 >= 0 && e2 < D2.N && j2 - e2 >= 0 && j2 - e2 <= P) {
-            int rr = (e2 * NP + g) * NP;
-            v = D2.wg[e2 * NP + g] * D2.Bg[rr + i2 - e2] * D2.Bg[rr + j2 - e2];
-        }
-        sF2[m][g][a] = v;
     }
     for (int t = tid; t < NP * NP; t += nt) {
         int m2 = t / NP, m1 = t % NP;
@@ -553,54 +565,69 @@ __device__ __forceinline__ void cut_row_body(const CutRowArgs& A, int r, CutRSme
         sId[m2][m1] = id;
     }
     __syncthreads();
-    // per support element: c at its Gauss points (inside) or row i of its local matrix (cut)
+    // per support element: c at its Gauss points (inside) or line i of its local matrix (cut)
     for (int t = tid; t < NP * NP * L; t += nt) {
         const int m2 = t / (NP * L), m1 = (t / L) % NP, g = t % L;
         const int cls = sCls[m2][m1];
-        double v = 0.0, w = 0.0;
-        if (cls == EL_INSIDE) v = A.c.is_const ? A.c.value : A.c.band[(size_t)sId[m2][m1] * L + g];
-        else if (cls == EL_CUT) w = A.E[((size_t)sId[m2][m1] * L + (P - m2) * NP + (P - m1)) * L + g];
-        sX[m2][m1][g] = v;
-        sE[m2][m1][g] = w;
+        double v = 0.0;
+        if (INS && cls == EL_INSIDE) v = A.c.is_const ? A.c.value : A.c.band[(size_t)sId[m2][m1] * L + g];
+        else if (CUT && cls == EL_CUT) v = A.E[((size_t)sId[m2][m1] * L + (P - m2) * NP + (P - m1)) * L + g];
+        sXE[m2][m1][g] = v;
     }
     __syncthreads();
-    // inside elements, sum-factorised: F2 does not depend on m1, so the direction-1 contraction
-    // is summed over the element columns first, U[m2][g2][a] = sum_m1 sum_g1 F1[m1][g1][a] X[m2][m1][g2][g1]
-    for (int t = tid; t < NP * NP * W; t += nt) {
-        const int m2 = t / (NP * W), g2 = (t / W) % NP, a = t % W;
-        double u = 0.0;
+    if (INS) {
+        // inside elements, sum-factorised: F2 does not depend on m1, so the direction-1 contraction is
+        // summed over the element columns first, U[m2][g2][a] = sum_m1 sum_g1 F1[m1][g1][a] X[m2][m1][g2][g1]
+        for (int t = tid; t < NP * NP * W; t += nt) {
+            const int m2 = t / (NP * W), g2 = (t / W) % NP, a = t % W;
+            double u = 0.0;
 #pragma unroll
-        for (int m1 = 0; m1 <= P; ++m1)
+            for (int m1 = 0; m1 <= P; ++m1) {
+                const bool in = sCls[m2][m1] == EL_INSIDE;
 #pragma unroll
-            for (int g1 = 0; g1 < NP; ++g1) u += sF1[m1][g1][a] * sX[m2][m1][g2 * NP + g1];
-        S.sU[m2][g2][a] = u;
+                for (int g1 = 0; g1 < NP; ++g1) u += in ? sF1[m1][g1][a] * sXE[m2][m1][g2 * NP + g1] : 0.0;
+            }
+            S.sU[m2][g2][a] = u;
+        }
+        __syncthreads();
     }
-    __syncthreads();
     const int s = tid;
     if (s >= W * W) return;
     const int a = s / W, b = s % W;          // column offsets a-p, b-p
     const int j1 = i1 + a - P, j2 = i2 + b - P;
+    double* out = A.vals + (size_t)s * A.n_act + row;
     double val = 0.0;
     if (j1 >= 0 && j1 < D1.n && j2 >= 0 && j2 < D2.n && A.act_of[j2 * D1.n + j1] >= 0) {
+        if (INS) {
 #pragma unroll
-        for (int m2 = 0; m2 <= P; ++m2)
+            for (int m2 = 0; m2 <= P; ++m2)
 #pragma unroll
-            for (int g2 = 0; g2 < NP; ++g2) val += sF2[m2][g2][b] * S.sU[m2][g2][a];
-        // cut elements: the column's entry of the staged row, zero where the element is not cut
-        // or does not overlap the column's support
+                for (int g2 = 0; g2 < NP; ++g2) val += sF2[m2][g2][b] * S.sU[m2][g2][a];
+        } else {
+            val = *out;   // the inside sum, written by the first launch
+        }
+        if (CUT) {
+            // cut elements: the column's entry of the staged line, zero where the element is not cut
+            // or does not overlap the column's support
 #pragma unroll
-        for (int m2 = 0; m2 <= P; ++m2) {
-            const int l2 = j2 - (i2 - P + m2);
+            for (int m2 = 0; m2 <= P; ++m2) {
+                const int l2 = j2 - (i2 - P + m2);
 #pragma unroll
-            for (int m1 = 0; m1 <= P; ++m1) {
-                const int l1 = j1 - (i1 - P + m1);
-                const bool ov = (l1 >= 0 && l1 <= P && l2 >= 0 && l2 <= P);
-                const double ev = sE[m2][m1][ov ? l2 * NP + l1 : 0];
-                val += ov ? ev : 0.0;
+                for (int m1 = 0; m1 <= P; ++m1) {
+                    const int l1 = j1 - (i1 - P + m1);
+                    const bool ov = (l1 >= 0 && l1 <= P && l2 >= 0 && l2 <= P) && sCls[m2][m1] == EL_CUT;
+                    const double ev = sXE[m2][m1][ov ? l2 * NP + l1 : 0];
+                    val += ov ? ev : 0.0;
+                }
             }
         }
     }
-    A.vals[(size_t)s * A.n_act + row] = val;
+    *out = val;
+}
+
+template <int P>
+__device__ __forceinline__ void cut_row_body(const CutRowArgs& A, int r, CutRSmem<P>& S) {
+    cut_row_body_m<P, ROW_FUSED>(A, r, S);
 }
 
 

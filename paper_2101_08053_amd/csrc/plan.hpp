@@ -289,8 +289,10 @@ CoefView coef_view(Plan& P, const iga_coeff& c);
 void launch_points(Plan& P, hipStream_t s, bool with_nodes = false);
 void launch_coef(Plan& P, const iga_coeff& c, hipStream_t s, int part = 0);
 void launch_interior_rows(Plan& P, const iga_coeff& c, double* vals, hipStream_t s);
-// before_rows: an event the rows wait for after the cut element matrices are launched (or null)
-void launch_cut_rows(Plan& P, const iga_coeff& c, double* vals, hipStream_t s, hipEvent_t before_rows = nullptr);
+void launch_cut_rows(Plan& P, const iga_coeff& c, double* vals, hipStream_t s);  // matrices, then rows
+void launch_cut_elems(Plan& P, const iga_coeff& c, hipStream_t s);
+// rows formed element-wise in one launch (mode 0), or their inside sums (1) and the cut entries (2)
+void launch_cut_rows_mode(Plan& P, const iga_coeff& c, double* vals, hipStream_t s, int mode);
 // dwq.hip
 void launch_dwq_sides(Plan& P, hipStream_t s);
 void launch_dwq_choose(Plan& P, hipStream_t s);
