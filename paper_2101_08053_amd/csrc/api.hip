@@ -233,8 +233,8 @@ static void form(Plan& P, const iga_coeff& c, double* vals, int flags, hipStream
     // aux stream: univariate tables and weights, c on the WQ grid and the band
     // Gauss points, the inside sums of the rows formed element-wise, interior
     // rows, rule points; the caller's stream: trimming, classes, lists, cut
-    // rules, c at the cut nodes, cut element matrices and their entries in
-    // the rows formed element-wise.
+    // rules, cut element matrices (with c at the cut nodes) and their entries
+    // in the rows formed element-wise.
     HIPX(hipEventRecord(P.ev_fork, s));
     HIPX(hipStreamWaitEvent(a, P.ev_fork, 0));
     if (full) setup_tables(P, a);
@@ -264,8 +264,7 @@ static void form(Plan& P, const iga_coeff& c, double* vals, int flags, hipStream
     HIPX(hipEventRecord(P.ev_interior, a));
     {
         PhaseTimer t(P, s, IGA_PHASE_CUT);
-        launch_coef(P, c, s, 4);
-        launch_cut_elems(P, c, s);
+        launch_cut_elems(P, c, s);  // with c at the cut nodes
         HIPX(hipStreamWaitEvent(s, P.ev_band, 0));
         launch_cut_rows_mode(P, c, vals, s, 2);  // plus the cut element matrices' entries
         launch_dwq_rows(P, c, vals, s);

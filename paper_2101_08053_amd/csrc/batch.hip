@@ -94,7 +94,7 @@ template <int P>
 __device__ __forceinline__ void run_item(const BatchPlan& Bp, const BatchItem& it, unsigned char* smem) {
     switch (it.kind) {
         case BK_COEF: {
-            const int64_t n = Bp.co.nq + Bp.co.nb + Bp.co.n_nodes;
+            const int64_t n = Bp.co.nq + Bp.co.nb;  // cut nodes: with the cut element items
             const int64_t t0 = (int64_t)it.unit * kCoefChunk;
             for (int64_t t = t0 + threadIdx.x; t < min(n, t0 + kCoefChunk); t += 256) coef_point<P>(Bp.co, t);
             break;
@@ -324,7 +324,7 @@ static iga_batch* batch_create(iga_plan* const* plans, int count, const iga_coef
         std::vector<int> node_off(P.n_cut_el + 1, 0);
         if (P.n_cut_el > 0)
             HIPX(hipMemcpy(node_off.data(), P.node_off, sizeof(int) * (P.n_cut_el + 1), hipMemcpyDeviceToHost));
-        const int64_t npts = bp.co.nq + bp.co.nb + bp.co.n_nodes;
+        const int64_t npts = bp.co.nq + bp.co.nb;
         const int n_coef = (c.kind == IGA_COEF_GEOM_DETJ) ? (int)((npts + kCoefChunk - 1) / kCoefChunk) : 0;
         const int n_int = (P.method == IGA_GAUSS_REF) ? 0 : bp.ia.ntx * P.n2;
         const int n_cute = (int)P.n_cut_el, n_cutr = (int)P.n_form_rows;

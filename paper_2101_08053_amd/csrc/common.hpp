@@ -103,6 +103,42 @@ __device__ __forceinline__ void basis_eval_rec(const double* __restrict__ knots,
     }
 }
 
+// Values and first derivatives from the span's reciprocal table (as
+// basis_eval_rec): dN_a = P (N^{P-1}_{a-1} / (t_{i+P} - t_i) - N^{P-1}_a /
+// (t_{i+P+1} - t_{i+1})), i = span - P + a, whose reciprocals are the
+// table's last level.
+template <int P>
+__device__ __forceinline__ void basis_eval_rec_d(const double* __restrict__ knots, int span,
+                                                 const double* __restrict__ rinv, double x, double* N, double* dN) {
+    double left[P + 1], right[P + 1], low[P + 1];
+    N[0] = 1.0;
+#pragma unroll
+    for (int j = 1; j <= P; ++j) {
+        if (j == P) {
+#pragma unroll
+            for (int r = 0; r < P; ++r) low[r] = N[r];
+        }
+        left[j] = x - knots[span + 1 - j];
+        right[j] = knots[span + j] - x;
+        double saved = 0.0;
+#pragma unroll
+        for (int r = 0; r < j; ++r) {
+            const double tmp = N[r] * rinv[j * (j - 1) / 2 + r];
+            N[r] = saved + right[r + 1] * tmp;
+            saved = left[j - r] * tmp;
+        }
+        N[j] = saved;
+    }
+    constexpr int b = P * (P - 1) / 2;
+#pragma unroll
+    for (int a = 0; a <= P; ++a) {
+        double v = 0.0;
+        if (a >= 1) v += P * (low[a - 1] * rinv[b + a - 1]);
+        if (a <= P - 1) v -= P * (low[a] * rinv[b + a]);
+        dN[a] = v;
+    }
+}
+
 // Values and first derivatives, compile-time degree.
 template <int P>
 __device__ __forceinline__ void basis_eval_d(const double* __restrict__ knots, int span, double x, double* N,

@@ -326,6 +326,11 @@ struct CutEArgs {
     const double *nx, *ny, *nw;
     double* E;
     int n_cut;
+    // c = |det J| of the geometry map: evaluated at the nodes here (and stored in c_cut)
+    int detj;
+    const double* geom_cp;
+    int n1;
+    double* c_cut;
 };
 
 template <int P>
@@ -344,6 +349,7 @@ struct CutESmem {
     double sPhi[CutECfg<P>::CH][CutECfg<P>::L];
     double sWc[CutECfg<P>::CH];
     double sRec[2][CutECfg<P>::NR + 1];
+    double sCp[(P + 1) * (P + 1)][2];  // the element's geometry control points (c = |det J|)
 };
 
 typedef double mfma_f64x4 __attribute__((ext_vector_type(4)));
@@ -360,6 +366,8 @@ __device__ __forceinline__ void tile_ij(int t, int T, int& I, int& J) {
 
 // Local matrix of cut element c (256 threads): E = sum_n w_n c_n phi_n phi_n^T
 // over the element's nodes, a Gram product contracted on the matrix cores.
+// With c = |det J| the node's thread evaluates c too, from the element's
+// control points staged in LDS, and stores it in the rule-point table.
 // Nodes are staged CH at a time with their basis products (one node per
 // thread, the element's reciprocal knot differences shared, so no divisions
 // per node). The L x L result is cut into 16 x 16 tiles of its upper
@@ -398,6 +406,11 @@ __device__ __forceinline__ void cut_elem_body(const CutEArgs& A, int c, CutESmem
     if (threadIdx.x < 2 * NR) {
         const int d = threadIdx.x / NR, idx = threadIdx.x % NR;
         S.sRec[d][idx] = basis_rec<P>(d ? A.d2.knots : A.d1.knots, P + (d ? e2 : e1), idx);
+    } else if (A.detj && threadIdx.x < 2 * NR + (P + 1) * (P + 1)) {
+        const int t = threadIdx.x - 2 * NR, a2 = t / (P + 1), a1 = t % (P + 1);
+        const double* q = A.geom_cp + 2 * ((size_t)(e2 + a2) * A.n1 + e1 + a1);
+        S.sCp[t][0] = q[0];
+        S.sCp[t][1] = q[1];
     }
     for (int base = nb; base < ne; base += CH) {
         __syncthreads();
@@ -405,10 +418,36 @@ __device__ __forceinline__ void cut_elem_body(const CutEArgs& A, int c, CutESmem
             const int n = base + threadIdx.x;
             if (n < ne) {
                 const double x = A.nx[n], y = A.ny[n], w = A.nw[n];
-                const double cv = A.c.is_const ? A.c.value : A.c.cut[n];
+                double cv;
                 double B1[P + 1], B2[P + 1];
-                basis_eval_rec<P>(A.d1.knots, P + e1, S.sRec[0], x, B1);
-                basis_eval_rec<P>(A.d2.knots, P + e2, S.sRec[1], y, B2);
+                if (A.detj) {  // |det J| from the staged control points (the sums of detj_local)
+                    double dB1[P + 1], dB2[P + 1];
+                    basis_eval_rec_d<P>(A.d1.knots, P + e1, S.sRec[0], x, B1, dB1);
+                    basis_eval_rec_d<P>(A.d2.knots, P + e2, S.sRec[1], y, B2, dB2);
+                    double x1 = 0.0, x2 = 0.0, y1 = 0.0, y2 = 0.0;
+#pragma unroll
+                    for (int a2 = 0; a2 <= P; ++a2) {
+                        double sx1 = 0.0, sx = 0.0, sy1 = 0.0, sy = 0.0;
+#pragma unroll
+                        for (int a1 = 0; a1 <= P; ++a1) {
+                            const double px = S.sCp[a2 * (P + 1) + a1][0], py = S.sCp[a2 * (P + 1) + a1][1];
+                            sx1 += dB1[a1] * px;
+                            sx += B1[a1] * px;
+                            sy1 += dB1[a1] * py;
+                            sy += B1[a1] * py;
+                        }
+                        x1 += B2[a2] * sx1;
+                        y1 += B2[a2] * sy1;
+                        x2 += dB2[a2] * sx;
+                        y2 += dB2[a2] * sy;
+                    }
+                    cv = fabs(x1 * y2 - x2 * y1);
+                    A.c_cut[n] = cv;
+                } else {
+                    cv = A.c.is_const ? A.c.value : A.c.cut[n];
+                    basis_eval_rec<P>(A.d1.knots, P + e1, S.sRec[0], x, B1);
+                    basis_eval_rec<P>(A.d2.knots, P + e2, S.sRec[1], y, B2);
+                }
 #pragma unroll
                 for (int a2 = 0; a2 <= P; ++a2)
 #pragma unroll
