@@ -268,7 +268,7 @@ int iga_trim_mass_form_batched(iga_plan* const* plans, int32_t count, const iga_
  * returns the accumulated milliseconds and counts per phase. */
 #define IGA_PHASE_SETUP     0  /* layout, weights, trimming, cut rules        */
 #define IGA_PHASE_COEF      1  /* coefficient at rule points                  */
-#define IGA_PHASE_INTERIOR  2  /* interior rows (WQ + sum factorisation)       */
+#define IGA_PHASE_INTERIOR  2  /* interior rows kernel, start to end of its run */
 #define IGA_PHASE_CUT       3  /* cut-element matrices and cut rows           */
 #define IGA_PHASE_COUNT     4
 int iga_plan_set_timing(iga_plan* plan, int32_t enable);

@@ -15,6 +15,8 @@
 //    rows; the reference: every row): element Gauss on inside elements of
 //    the support, the cut element matrices on cut elements. One workgroup per
 //    row, one thread per band slot.
+#include <hip/hip_ext.h>
+
 #include "form_body.hpp"
 
 namespace iga {
@@ -117,9 +119,10 @@ __global__ void __launch_bounds__(256) k_interior(IntArgs A) {
 }
 
 template <int P>
-static void launch_interior_p(Plan& Pl, IntArgs A, hipStream_t s) {
+static void launch_interior_p(Plan& Pl, IntArgs A, hipStream_t s, hipEvent_t t0, hipEvent_t t1) {
     const int nb = A.ntx * Pl.n2;
-    hipLaunchKernelGGL(k_interior<P>, dim3(nb), dim3(256), 0, s, A);
+    if (t0) hipExtLaunchKernelGGL(k_interior<P>, dim3(nb), dim3(256), 0, s, t0, t1, 0, A);  // events bracket the dispatch
+    else hipLaunchKernelGGL(k_interior<P>, dim3(nb), dim3(256), 0, s, A);
 }
 
 IntArgs int_args(Plan& P, const iga_coeff& c, double* vals) {
@@ -150,18 +153,18 @@ CutRowArgs cutr_args(Plan& P, const iga_coeff& c, double* vals) {
                       P.n_act};
 }
 
-void launch_interior_rows(Plan& P, const iga_coeff& c, double* vals, hipStream_t s) {
+void launch_interior_rows(Plan& P, const iga_coeff& c, double* vals, hipStream_t s, hipEvent_t t0, hipEvent_t t1) {
     if (P.method == IGA_GAUSS_REF) return;
     IntArgs A = int_args(P, c, vals);
     switch (P.p) {
-        case 1: launch_interior_p<1>(P, A, s); break;
-        case 2: launch_interior_p<2>(P, A, s); break;
-        case 3: launch_interior_p<3>(P, A, s); break;
-        case 4: launch_interior_p<4>(P, A, s); break;
-        case 5: launch_interior_p<5>(P, A, s); break;
-        case 6: launch_interior_p<6>(P, A, s); break;
-        case 7: launch_interior_p<7>(P, A, s); break;
-        case 8: launch_interior_p<8>(P, A, s); break;
+        case 1: launch_interior_p<1>(P, A, s, t0, t1); break;
+        case 2: launch_interior_p<2>(P, A, s, t0, t1); break;
+        case 3: launch_interior_p<3>(P, A, s, t0, t1); break;
+        case 4: launch_interior_p<4>(P, A, s, t0, t1); break;
+        case 5: launch_interior_p<5>(P, A, s, t0, t1); break;
+        case 6: launch_interior_p<6>(P, A, s, t0, t1); break;
+        case 7: launch_interior_p<7>(P, A, s, t0, t1); break;
+        case 8: launch_interior_p<8>(P, A, s, t0, t1); break;
         default: throw Error{IGA_E_UNSUPPORTED, "degree outside 1..8"};
     }
 }

@@ -288,7 +288,9 @@ CoefView coef_view(Plan& P, const iga_coeff& c);
 // rule-point coordinates: WQ grid and band Gauss points (and the cut nodes with with_nodes)
 void launch_points(Plan& P, hipStream_t s, bool with_nodes = false);
 void launch_coef(Plan& P, const iga_coeff& c, hipStream_t s, int part = 0);
-void launch_interior_rows(Plan& P, const iga_coeff& c, double* vals, hipStream_t s);
+// t0 / t1 (optional): events recorded at the start and end of the kernel's execution
+void launch_interior_rows(Plan& P, const iga_coeff& c, double* vals, hipStream_t s, hipEvent_t t0 = nullptr,
+                          hipEvent_t t1 = nullptr);
 void launch_cut_rows(Plan& P, const iga_coeff& c, double* vals, hipStream_t s);  // matrices, then rows
 void launch_cut_elems(Plan& P, const iga_coeff& c, hipStream_t s);
 // rows formed element-wise in one launch (mode 0), or their inside sums (1) and the cut entries (2)
