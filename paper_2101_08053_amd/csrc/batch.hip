@@ -172,7 +172,7 @@ __device__ __forceinline__ void batch_loop(const BatchDev& B, int g, unsigned ch
     }
 }
 
-__global__ void __launch_bounds__(256) k_batch(BatchDev B) {
+__global__ void __launch_bounds__(256, 2) k_batch(BatchDev B) {  // at most 256 VGPRs: two workgroups per CU
     __shared__ __align__(16) unsigned char smem[batch_smem_max<kBatchMaxP>()];
     __shared__ int s_sh[3];
     int g = 0;
@@ -201,6 +201,7 @@ struct Batch {
     int* d_counters = nullptr;  // status, heads[kBatchGroups], level counters[kBatchGroups][2]
     int n_items = 0;
     int n_cu = 256;
+    int max_wg_per_cu = 4;  // workgroups of k_batch that fit on one CU at once
     int wg_per_cu = 2;
     int order = 0;  // 0 cost-sorted, 1 patch by patch
     int chunk = 16; // queue items reserved per atomic
@@ -292,6 +293,11 @@ static iga_batch* batch_create(iga_plan* const* plans, int count, const iga_coef
     int dev = 0;
     HIPX(hipGetDevice(&dev));
     HIPX(hipDeviceGetAttribute(&B->n_cu, hipDeviceAttributeMultiprocessorCount, dev));
+    // a persistent grid larger than what fits at once only queues workgroups behind the resident ones
+    int fit = 0;
+    HIPX(hipOccupancyMaxActiveBlocksPerMultiprocessor(&fit, k_batch, 256, 0));
+    B->max_wg_per_cu = std::max(1, std::min(4, fit));
+    B->wg_per_cu = std::min(B->wg_per_cu, B->max_wg_per_cu);
     HIPX(hipStreamCreate(&B->cap_stream));
     std::vector<BatchPlan> hp(count);
     struct Cand {
@@ -397,7 +403,7 @@ static void batch_autotune(Batch& B, hipStream_t s, float* best_ms) {
         B.order = order;
         B.upload_items(s);
         for (int cidx = 0; cidx < 3; ++cidx)
-        for (int w = 1; w <= 4; ++w) {
+        for (int w = 1; w <= B.max_wg_per_cu; ++w) {
             B.chunk = (cidx == 0) ? 4 : (cidx == 1 ? 16 : 64);
             B.wg_per_cu = w;
             B.launch(s);  // warm-up

@@ -1,11 +1,11 @@
 // Formation of the trimmed mass matrix (Eqs. (6)-(7), Sects. 3.1-3.2).
 //
 //  * k_interior: rows of interior test functions by weighted quadrature and
-//    sum factorisation. A workgroup owns a tile of 64 consecutive i1 (one
-//    per lane) and tile2 consecutive i2. For each i2 it first contracts the
-//    xi_2 direction for every xi_1 point of the tile,
+//    sum factorisation. A workgroup owns one i2 and a tile of 128
+//    consecutive i1 (one per thread). It first contracts the xi_2 direction
+//    for every xi_1 point of the tile,
 //        T[b][k1] = sum_{k2 in Q_i2} w2_{k2,i2} B_{i2+b}(x_k2) c(x_k1, x_k2),
-//    into LDS, then each lane contracts xi_1 for its own row,
+//    into LDS, then each thread contracts xi_1 for its own row,
 //        M[a][b] = sum_{k1 in Q_i1} w1_{k1,i1} B_{i1+a}(x_k1) T[b][k1],
 //    and writes the (2p+1)^2 band of the row slot-major (coalesced across
 //    lanes, no atomics).
@@ -111,18 +111,19 @@ void launch_coef(Plan& P, const iga_coeff& c, hipStream_t s, int part) {
 
 // ------------------------------------------------------- interior rows
 template <int P>
-__global__ void __launch_bounds__(256) k_interior(IntArgs A) {
-    __shared__ __align__(16) IntSmem<P> S;
+__global__ void __launch_bounds__(128) k_interior(IntArgs A) {
+    __shared__ __align__(16) Int2Smem<P> S;
     const int blk = xcd_block(blockIdx.x, gridDim.x);
     const int i2 = blk / A.ntx;
-    interior_block<P>(A, blk - i2 * A.ntx, i2, S);
+    interior_rows_block<P>(A, blk - i2 * A.ntx, i2, S);
 }
 
 template <int P>
 static void launch_interior_p(Plan& Pl, IntArgs A, hipStream_t s, hipEvent_t t0, hipEvent_t t1) {
+    A.ntx = interior2_ntx(Pl.N1, P);
     const int nb = A.ntx * Pl.n2;
-    if (t0) hipExtLaunchKernelGGL(k_interior<P>, dim3(nb), dim3(256), 0, s, t0, t1, 0, A);  // events bracket the dispatch
-    else hipLaunchKernelGGL(k_interior<P>, dim3(nb), dim3(256), 0, s, A);
+    if (t0) hipExtLaunchKernelGGL(k_interior<P>, dim3(nb), dim3(128), 0, s, t0, t1, 0, A);  // events bracket the dispatch
+    else hipLaunchKernelGGL(k_interior<P>, dim3(nb), dim3(128), 0, s, A);
 }
 
 IntArgs int_args(Plan& P, const iga_coeff& c, double* vals) {

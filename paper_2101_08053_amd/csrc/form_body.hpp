@@ -107,13 +107,42 @@ __device__ __forceinline__ int xcd_block(int bid, int nb) {
     return x * q + min(x, r) + (bid >> 3);
 }
 
+// One column b of one interior row, shared by the one-launch and the batched
+// bodies so that both give the same bits. Tk points at T[b] for the row's
+// first support point. A row touching no end element: 2p+2 points, two per
+// element m, factors wbf(q, al) = (w1 B1) at point q for column m + al.
+template <int P, typename WBF>
+__device__ __forceinline__ void interior_col_reg(WBF wbf, const double* Tk, double* acc) {
+#pragma unroll
+    for (int a = 0; a < 2 * P + 1; ++a) acc[a] = 0.0;
+#pragma unroll
+    for (int m = 0; m <= P; ++m) {
+        const double t0 = Tk[2 * m], t1 = Tk[2 * m + 1];
+#pragma unroll
+        for (int al = 0; al <= P; ++al) acc[m + al] += wbf(2 * m, al) * t0 + wbf(2 * m + 1, al) * t1;
+    }
+}
+
+// A row touching the first or last element: its q1 support points, full
+// factor rows wb[q][a] = (w1 B1) at point q for column a.
+template <int P>
+__device__ __forceinline__ void interior_col_end(const double* wb, const double* Tk, int q1, double* acc) {
+    constexpr int W = 2 * P + 1;
+#pragma unroll
+    for (int a = 0; a < W; ++a) acc[a] = 0.0;
+#pragma unroll 1
+    for (int q = 0; q < q1; ++q) {
+        const double t = Tk[q];
+#pragma unroll
+        for (int a = 0; a < W; ++a) acc[a] += wb[q * W + a] * t;
+    }
+}
+
 template <int P>
 struct IntSmem {
     static constexpr int W = IntCfg<P>::W, QM = IntCfg<P>::QM, KS = IntCfg<P>::KS, KG = IntCfg<P>::KG;
     double sT[W][KS];                              // T[b][k - k1lo]
     double sWB2[QM][W];                            // w2 * B2 of the row
-    double sB1[IntCfg<P>::WBREG ? KG : KS][P + 1]; // B1 at the window's points
-    double sW1[64][QM + 1];                        // boundary tiles: w1 per lane
 };
 
 // One work item = one test-function row i2 and a tile tx of (up to) 64
@@ -130,8 +159,6 @@ __device__ __forceinline__ void interior_block(const IntArgs& A, int tx, int i2,
     constexpr int W = C::W, QM = C::QM, NR = C::NR, KG = C::KG;
     auto& sT = S.sT;
     auto& sWB2 = S.sWB2;
-    auto& sB1 = S.sB1;
-    auto& sW1 = S.sW1;
 
     const DirDev& D1 = A.d1;
     const DirDev& D2 = A.d2;
@@ -144,29 +171,7 @@ __device__ __forceinline__ void interior_block(const IntArgs& A, int tx, int i2,
     const int ks = wq_pt0(ehi + 1, D1.N, P) - k1lo;
     const int i1 = I1 + lane;
 
-    // ---- tile tables (independent of the row)
     __syncthreads();   // LDS of the previous work item is free
-    if (!generic && !C::WBREG) {
-        for (int t = tid; t < ks * (P + 1); t += 256) sB1[t / (P + 1)][t % (P + 1)] = D1.Bq[(size_t)k1lo * (P + 1) + t];
-    }
-    if (generic) {
-        constexpr int NGB = (KG * (P + 1) + 255) / 256;
-        double gb[NGB];
-#pragma unroll
-        for (int u = 0; u < NGB; ++u) {
-            const int t = tid + 256 * u;
-            gb[u] = (t < ks * (P + 1)) ? D1.Bq[(size_t)k1lo * (P + 1) + t] : 0.0;
-        }
-        for (int t = tid; t < 64 * QM; t += 256) {
-            const int l = t / QM, q = t % QM;
-            sW1[l][q] = (l < nlive && q < D1.qmax) ? D1.W[(size_t)(I1 + l) * D1.qmax + q] : 0.0;
-        }
-#pragma unroll
-        for (int u = 0; u < NGB; ++u) {
-            const int t = tid + 256 * u;
-            if (t < ks * (P + 1)) sB1[t / (P + 1)][t % (P + 1)] = gb[u];
-        }
-    }
 
     {
         if (i2 >= D2.n) return;
@@ -244,70 +249,247 @@ __device__ __forceinline__ void interior_block(const IntArgs& A, int tx, int i2,
                 }
             }
         }
-        // regular lanes: w1 * B1 (or w1) at the 2p+2 support points, loaded while stage 1 finishes
+        // regular lanes: w1 * B1 at the 2p+2 support points, loaded while stage 1 finishes
         double wb[C::WBREG ? NR : 1][C::WBREG ? P + 1 : 1];
-        double w1[C::WBREG ? 1 : NR];
-        if (!generic) {
-            const int i1c = min(i1, D1.n - 1);
-            if constexpr (C::WBREG) {
-                const double* row = D1.WB + (size_t)i1c * D1.qmax * W;
+        const int i1c = min(i1, D1.n - 1);
+        const double* wrow = D1.WB + (size_t)i1c * D1.qmax * W;
+        if (!generic && C::WBREG) {  // from the banded copy: consecutive lanes, consecutive addresses
 #pragma unroll
-                for (int q = 0; q < NR; ++q)
+            for (int q = 0; q < NR; ++q)
 #pragma unroll
-                    for (int al = 0; al <= P; ++al) wb[q][al] = row[q * W + (q >> 1) + al];
-            } else {
-#pragma unroll
-                for (int q = 0; q < NR; ++q) w1[q] = D1.W[(size_t)i1c * D1.qmax + q];
-            }
+                for (int al = 0; al <= P; ++al) wb[q][al] = D1.WBT[((size_t)q * (P + 1) + al) * D1.n + i1c];
         }
         __syncthreads();
 
         // ---- stage 2: contract xi_1, one row per lane, columns b shared by the wavefronts
+        if (!live) return;
         if (!generic) {
             // regular lane: support points 2*lane .. 2*lane + 2p+1 of the window, two per element
 #pragma unroll 1
             for (int b = wave; b < W; b += 4) {
                 double acc[W];
-#pragma unroll
-                for (int a = 0; a < W; ++a) acc[a] = 0.0;
-#pragma unroll
-                for (int m = 0; m <= P; ++m) {
-                    const int k = 2 * lane + 2 * m;
-                    const double2 t2 = *reinterpret_cast<const double2*>(&sT[b][k]);
-                    if constexpr (C::WBREG) {
-#pragma unroll
-                        for (int al = 0; al <= P; ++al) acc[m + al] += wb[2 * m][al] * t2.x + wb[2 * m + 1][al] * t2.y;
-                    } else {
-                        const double wa = w1[2 * m] * t2.x, wc = w1[2 * m + 1] * t2.y;
-#pragma unroll
-                        for (int al = 0; al <= P; ++al) acc[m + al] += wa * sB1[k][al] + wc * sB1[k + 1][al];
-                    }
-                }
-                if (live)
-#pragma unroll
-                    for (int a = 0; a < W; ++a) A.vals[(size_t)(a * W + b) * A.n_act + cid] = acc[a];
-            }
-        } else if (live) {
-            const int k0_1 = wq_pt0(max(0, i1 - P), D1.N, P) - k1lo;
-#pragma unroll 1
-            for (int b = wave; b < W; b += 4) {
-                double acc[W];
-#pragma unroll
-                for (int a = 0; a < W; ++a) acc[a] = 0.0;
-#pragma unroll
-                for (int m = 0; m <= P; ++m) {
-                    const int e = i1 - P + m;
-                    if (e < 0 || e >= D1.N) continue;
-                    const int kb = wq_pt0(e, D1.N, P) - k1lo, ke = wq_pt0(e + 1, D1.N, P) - k1lo;
-                    for (int k = kb; k < ke; ++k) {
-                        const double wt = sW1[lane][k - k0_1] * sT[b][k];
-#pragma unroll
-                        for (int al = 0; al <= P; ++al) acc[m + al] += wt * sB1[k][al];
-                    }
-                }
+                if constexpr (C::WBREG)
+                    interior_col_reg<P>([&](int q, int al) { return wb[q][al]; }, &sT[b][2 * lane], acc);
+                else
+                    interior_col_reg<P>([&](int q, int al) { return D1.WBT[((size_t)q * (P + 1) + al) * D1.n + i1c]; },
+                                        &sT[b][2 * lane], acc);
 #pragma unroll
                 for (int a = 0; a < W; ++a) A.vals[(size_t)(a * W + b) * A.n_act + cid] = acc[a];
             }
+        } else {
+            // a row touching the first or last element: its full factor rows
+            const int k0 = wq_pt0(max(0, i1 - P), D1.N, P);
+            const int q1 = wq_pt0(min(D1.N - 1, i1) + 1, D1.N, P) - k0;
+#pragma unroll 1
+            for (int b = wave; b < W; b += 4) {
+                double acc[W];
+                interior_col_end<P>(wrow, &sT[b][k0 - k1lo], q1, acc);
+#pragma unroll
+                for (int a = 0; a < W; ++a) A.vals[(size_t)(a * W + b) * A.n_act + cid] = acc[a];
+            }
+        }
+    }
+}
+
+// Interior rows, one-launch form. Per test row i2: tiles of up to R = 128
+// consecutive "regular" test rows i1 (p+1 <= i1 <= N1-2, two WQ points in
+// every support element), one per thread, and one workgroup for the 2(p+1)
+// end rows (supports touching the first or last element, p+1 points there),
+// one thread per (end row, column b). Stage 1 contracts xi_2 for every xi_1
+// point of the workgroup's window into T[b][k] (LDS); stage 2 contracts xi_1,
+// M[a][b] = sum_k (w1 B1)[i1][k][a] T[b][k], with the per-column sums of the
+// batched body. A regular row's banded w1 B1 factors are loaded into
+// registers (p <= 5) together with every other global load of the
+// workgroup, before stage 1; the end rows' full factor rows go to LDS.
+template <int P>
+struct Int2Cfg {
+    static constexpr int W = 2 * P + 1;                  // band width
+    static constexpr int QM = 4 * P + 2;                 // max WQ points in one support
+    static constexpr int NR = 2 * P + 2;                 // support points of a regular function
+    static constexpr int R = 128;                        // rows per tile (threads per workgroup)
+    static constexpr int KS = 2 * (R + P) + 2 * P + 2;   // max xi_1 points of a tile window
+    static constexpr int NJ = (KS + R - 1) / R;          // window points per thread
+    static constexpr int NG = P + 1;                     // end rows at each end
+    static constexpr bool PRE = (P <= 5);                // factors and coefficients preloaded in registers
+};
+
+template <int P>
+struct Int2Smem {
+    double sT[Int2Cfg<P>::W][Int2Cfg<P>::KS];
+    double sWB2[Int2Cfg<P>::QM][Int2Cfg<P>::W];
+    double sG[2 * Int2Cfg<P>::NG][Int2Cfg<P>::QM][Int2Cfg<P>::W];  // w1 B1 rows of the end rows
+};
+
+// Workgroups per test row i2: the regular tiles, then the end-row workgroup.
+__host__ __device__ inline int interior2_nreg(int N1, int p) {
+    return (N1 >= p + 3) ? ((N1 - 2) - (p + 1) + 1 + 127) / 128 : 0;
+}
+__host__ __device__ inline int interior2_ntx(int N1, int p) { return interior2_nreg(N1, p) + 1; }
+
+// End row g of a test row (first p+1 rows, then the rows from N1-1 on; -1 if none).
+template <int P>
+__device__ __forceinline__ int interior_end_row(int g, int N1, int n1) {
+    if (g < P + 1) return (g < n1) ? g : -1;
+    const int r = N1 - 1 + (g - (P + 1));
+    return (r < n1 && r > P) ? r : -1;
+}
+
+template <int P>
+__device__ __forceinline__ void interior_rows_block(const IntArgs& A, int tx, int i2, Int2Smem<P>& S) {
+    using C = Int2Cfg<P>;
+    constexpr int W = C::W, QM = C::QM, NR = C::NR, R = C::R, NJ = C::NJ, NG = C::NG;
+    const DirDev& D1 = A.d1;
+    const DirDev& D2 = A.d2;
+    const int tid = threadIdx.x;
+    if (i2 >= D2.n) return;
+    const int nreg = interior2_nreg(D1.N, P);
+    const bool endtile = tx >= nreg;
+    const int k2lo = wq_pt0(max(0, i2 - P), D2.N, P);
+    const int q2 = wq_pt0(min(D2.N - 1, i2) + 1, D2.N, P) - k2lo;
+    const bool reg_row = (i2 >= P + 1) && (i2 <= D2.N - 2);  // q2 == NR, two points per element
+
+    // ---- the workgroup's window of xi_1 points: one range, or (end rows) two
+    int I1 = 0, nlive = 0, wlo1 = 0, whi1 = 0, wlo2 = 0, whi2 = 0;
+    if (!endtile) {
+        I1 = (P + 1) + tx * R;
+        nlive = min(R, (D1.N - 2) - I1 + 1);
+        wlo1 = wq_pt0(I1 - P, D1.N, P);
+        whi1 = wq_pt0(I1 + nlive - 1 + 1, D1.N, P);
+    } else {
+        whi1 = wq_pt0(min(P + 1, D1.N), D1.N, P);
+        wlo2 = wq_pt0(max(0, D1.N - 1 - P), D1.N, P);
+        whi2 = D1.Q;
+        if (wlo2 <= whi1) {  // the two ranges meet: one window
+            whi1 = D1.Q;
+            wlo2 = whi2 = D1.Q;
+        }
+    }
+    const int ks = (whi1 - wlo1) + (whi2 - wlo2);
+    auto kglob = [&](int k) { return (k < whi1 - wlo1) ? wlo1 + k : wlo2 + (k - (whi1 - wlo1)); };
+    auto kloc = [&](int kg) { return (kg < whi1) ? kg - wlo1 : (whi1 - wlo1) + (kg - wlo2); };
+
+    // ---- loads: row identity, xi_2 factors, coefficient columns, the rows' w1 B1 factors
+    auto formed = [&](int8_t cls) { return A.all_active ? (cls != FN_EXTERIOR) : (cls == FN_INTERIOR); };
+    int i1 = -1;
+    bool live = false;
+    int64_t cid = 0;
+    if (!endtile) {
+        if (tid < nlive) {
+            i1 = I1 + tid;
+            const int f = i2 * D1.n + i1;
+            const int8_t cls = A.fcls[f];
+            cid = A.act_of[f];
+            live = formed(cls);
+        }
+    } else {  // any of this thread's (end row, column) pairs formed here
+        for (int t = tid; t < 2 * NG * W; t += R) {
+            const int ie = interior_end_row<P>(t / W, D1.N, D1.n);
+            if (ie >= 0 && formed(A.fcls[i2 * D1.n + ie])) live = true;
+        }
+    }
+    constexpr int NWB = (QM * W + R - 1) / R;
+    double wb2[NWB];
+#pragma unroll
+    for (int u = 0; u < NWB; ++u) {
+        const int t = tid + R * u;
+        wb2[u] = (t < QM * W && t / W < q2) ? D2.WB[((size_t)i2 * D2.qmax) * W + t] : 0.0;
+    }
+    double cv[C::PRE ? NJ : 1][NR];
+    if (C::PRE && reg_row) {
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) {
+            const int kg = kglob(min(tid + R * j, ks - 1));
+#pragma unroll
+            for (int q = 0; q < NR; ++q)
+                cv[C::PRE ? j : 0][q] = A.cwq ? A.cwq[(size_t)(k2lo + q) * D1.Q + kg] : A.c.value;
+        }
+    }
+    double wb[C::PRE ? NR : 1][P + 1];
+    if (C::PRE && !endtile && i1 >= 0) {  // from the banded copy: consecutive rows, consecutive addresses
+#pragma unroll
+        for (int q = 0; q < NR; ++q)
+#pragma unroll
+            for (int al = 0; al <= P; ++al) wb[C::PRE ? q : 0][al] = D1.WBT[((size_t)q * (P + 1) + al) * D1.n + i1];
+    }
+    if (endtile) {  // the end rows' full w1 B1 rows
+        for (int t = tid; t < 2 * NG * QM * W; t += R) {
+            const int g = t / (QM * W), q = (t / W) % QM, a = t % W;
+            const int ie = interior_end_row<P>(g, D1.N, D1.n);
+            S.sG[g][q][a] = (ie >= 0 && q < D1.qmax) ? D1.WB[((size_t)ie * D1.qmax + q) * W + a] : 0.0;
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < NWB; ++u) {
+        const int t = tid + R * u;
+        if (t < QM * W) S.sWB2[t / W][t % W] = wb2[u];
+    }
+    if (!__syncthreads_or(live)) return;  // no row of the workgroup is formed here
+
+    // ---- stage 1: contract xi_2 for every xi_1 point of the window
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+        const int k = tid + R * j;
+        if (k >= ks) break;
+        const int kg = kglob(k);
+        if (reg_row) {
+            double T[W];
+#pragma unroll
+            for (int b = 0; b < W; ++b) T[b] = 0.0;
+#pragma unroll
+            for (int q = 0; q < NR; ++q) {
+                const int m2 = q >> 1;
+                const double cq = C::PRE ? cv[C::PRE ? j : 0][q]
+                                         : (A.cwq ? A.cwq[(size_t)(k2lo + q) * D1.Q + kg] : A.c.value);
+#pragma unroll
+                for (int bl = 0; bl <= P; ++bl) T[m2 + bl] += S.sWB2[q][m2 + bl] * cq;
+            }
+#pragma unroll
+            for (int b = 0; b < W; ++b) S.sT[b][k] = T[b];
+        } else {
+            double c[QM];
+#pragma unroll
+            for (int q = 0; q < QM; ++q)
+                c[q] = (q < q2) ? (A.cwq ? A.cwq[(size_t)(k2lo + q) * D1.Q + kg] : A.c.value) : 0.0;
+#pragma unroll 1
+            for (int b = 0; b < W; ++b) {
+                double Tb = 0.0;
+#pragma unroll
+                for (int q = 0; q < QM; ++q) Tb += S.sWB2[q][b] * c[q];
+                S.sT[b][k] = Tb;
+            }
+        }
+    }
+    __syncthreads();
+    if (!live) return;
+
+    // ---- stage 2: contract xi_1
+    if (!endtile) {  // the whole row of this thread
+        const int k0 = kloc(wq_pt0(max(0, i1 - P), D1.N, P));  // the row's first support point
+#pragma unroll 1
+        for (int b = 0; b < W; ++b) {
+            double acc[W];
+            if constexpr (C::PRE)
+                interior_col_reg<P>([&](int q, int al) { return wb[q][al]; }, &S.sT[b][k0], acc);
+            else
+                interior_col_reg<P>([&](int q, int al) { return D1.WBT[((size_t)q * (P + 1) + al) * D1.n + i1]; },
+                                    &S.sT[b][k0], acc);
+#pragma unroll
+            for (int a = 0; a < W; ++a) A.vals[(size_t)(a * W + b) * A.n_act + cid] = acc[a];
+        }
+    } else {  // one column of an end row per pair
+        for (int t = tid; t < 2 * NG * W; t += R) {
+            const int g = t / W, bcol = t % W;
+            const int ie = interior_end_row<P>(g, D1.N, D1.n);
+            if (ie < 0) continue;
+            const int f = i2 * D1.n + ie;
+            if (!formed(A.fcls[f])) continue;
+            const int64_t cide = A.act_of[f];
+            const int kg0 = wq_pt0(max(0, ie - P), D1.N, P);
+            const int q1 = wq_pt0(min(D1.N - 1, ie) + 1, D1.N, P) - kg0;
+            double acc[W];
+            interior_col_end<P>(&S.sG[g][0][0], &S.sT[bcol][kloc(kg0)], q1, acc);
+#pragma unroll
+            for (int a = 0; a < W; ++a) A.vals[(size_t)(a * W + bcol) * A.n_act + cide] = acc[a];
         }
     }
 }
@@ -336,7 +518,7 @@ struct CutEArgs {
 template <int P>
 struct CutECfg {
     static constexpr int L = (P + 1) * (P + 1);
-    static constexpr int CH = (P <= 4) ? 256 : ((P <= 6) ? 128 : 64);  // nodes staged at a time
+    static constexpr int CH = (P == 1) ? 256 : ((P <= 6) ? 128 : 64);  // nodes staged at a time (LDS kept small)
     static constexpr int NR = P * (P + 1) / 2;                          // reciprocal denominators per direction
     static constexpr int T = (L + 15) / 16;                             // 16-wide blocks of the local basis
     static constexpr int NT = T * (T + 1) / 2;                          // 16 x 16 tiles of the upper triangle
@@ -620,7 +802,7 @@ __device__ __forceinline__ void cut_row_body_m(const CutRowArgs& A, int r, CutRS
         for (int t = tid; t < NP * NP * W; t += nt) {
             const int m2 = t / (NP * W), g2 = (t / W) % NP, a = t % W;
             double u = 0.0;
-#pragma unroll
+#pragma unroll 1
             for (int m1 = 0; m1 <= P; ++m1) {
                 const bool in = sCls[m2][m1] == EL_INSIDE;
 #pragma unroll
@@ -648,7 +830,7 @@ __device__ __forceinline__ void cut_row_body_m(const CutRowArgs& A, int r, CutRS
         if (CUT) {
             // cut elements: the column's entry of the staged line, zero where the element is not cut
             // or does not overlap the column's support
-#pragma unroll
+#pragma unroll 1
             for (int m2 = 0; m2 <= P; ++m2) {
                 const int l2 = j2 - (i2 - P + m2);
 #pragma unroll

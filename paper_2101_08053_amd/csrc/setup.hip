@@ -221,6 +221,8 @@ __global__ void __launch_bounds__(64) k_wq_weights(DirDev D1, DirDev D2, const d
                     if (c == j - jlo) v = y * a0[c];
             }
             wb[bb] = v;
+            const int al = bb - (lane >> 1);  // the banded copy, rows contiguous (points of a regular row)
+            if (lane < 2 * P + 2 && al >= 0 && al <= P) D.WBT[((size_t)lane * (P + 1) + al) * D.n + i] = v;
         }
     }
     if (lane == 0 && (singular || !(rmax <= 1e-12 * bmax))) atomicExch(status, IGA_E_SINGULAR_WEIGHTS);
@@ -240,6 +242,8 @@ __global__ void k_wb_table(DirDev D, int p) {
         if (loc >= 0 && loc <= p) v = D.W[(size_t)i * D.qmax + q] * D.Bq[(size_t)k * (p + 1) + loc];
     }
     D.WB[t] = v;
+    const int al = b - (q >> 1);  // the banded copy, rows contiguous (points of a regular row)
+    if (q < 2 * p + 2 && al >= 0 && al <= p) D.WBT[((size_t)q * (p + 1) + al) * D.n + i] = v;
 }
 
 void launch_wb_table(Plan& P, int d, hipStream_t s) {

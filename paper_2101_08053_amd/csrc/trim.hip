@@ -1143,6 +1143,7 @@ struct CutArgs {
     const double* gw;
     int* status;
     int* node_off;      // exclusive scan of node_cnt (written by k_cut_nodes)
+    int stage_pieces, stage_segs;  // k_cutprep: pieces / segments its LDS holds (0: read them from memory)
 };
 
 __device__ __forceinline__ int arc_nq(const CutArgs& A, const CurveDev& C) {
@@ -1223,9 +1224,10 @@ __global__ void __launch_bounds__(64) k_cutprep(CutArgs A) {
     __shared__ int sOverflow;
     __shared__ int sArc[kMaxArcsPerElem];
     __shared__ int sNa;
-    __shared__ PieceBox sP[kPrepPieces];
     __shared__ int sCoff[33];
-    __shared__ SegDev sSegAll[kPrepSegs];
+    extern __shared__ __align__(16) unsigned char sDyn[];  // pieces' boxes, then segments (sized at launch)
+    PieceBox* sP = reinterpret_cast<PieceBox*>(sDyn);
+    SegDev* sSegAll = reinterpret_cast<SegDev*>(sDyn + (size_t)A.stage_pieces * sizeof(PieceBox));
     __shared__ SegDev sArcSeg[kMaxArcsPerElem];
     __shared__ int sNq[kMaxArcsPerElem], sNqOff[kMaxArcsPerElem + 1];
     const int e = A.cut_list[c];
@@ -1234,7 +1236,7 @@ __global__ void __launch_bounds__(64) k_cutprep(CutArgs A) {
     CutElemDev& out = A.cut_el[c];
     // (0) the pieces for the hole tests, and the element's kept arcs in ascending order
     const int npc = *T.n_pieces;
-    const bool staged = npc <= kPrepPieces && T.n_curves <= 32;
+    const bool staged = npc <= A.stage_pieces && T.n_curves <= 32;
     if (staged) {
         for (int k = lane; k < npc; k += 64) {
             const PieceDev Pc = T.pieces[k];
@@ -1242,7 +1244,7 @@ __global__ void __launch_bounds__(64) k_cutprep(CutArgs A) {
         }
         for (int k = lane; k <= T.n_curves; k += 64) sCoff[k] = T.piece_curve_off[k];
     }
-    const bool segs_staged = staged && T.n_segs <= kPrepSegs;
+    const bool segs_staged = staged && T.n_segs <= A.stage_segs;
     if (segs_staged)
         for (int k = lane; k < T.n_segs; k += 64) sSegAll[k] = T.segs[k];
     if (lane == 0) {
@@ -1422,8 +1424,11 @@ void launch_trim_cutprep(Plan& P, hipStream_t s) {
     if (T.n_curves == 0 || nc == 0) return;
     GridDev G{P.dir[0].knots + P.p, P.dir[1].knots + P.p, P.N1, P.N2};  // breakpoints
     CutArgs A{T, G, nc, P.cut_list, P.ehead, P.arc_next, P.epoch, P.cut_el, P.node_cnt,
-              P.n_r, P.n_q_override, P.n_s, P.p, P.gauss_x, P.gauss_w, P.status, P.node_off};
-    hipLaunchKernelGGL(k_cutprep, dim3(nc), dim3(64), 0, s, A);
+              P.n_r, P.n_q_override, P.n_s, P.p, P.gauss_x, P.gauss_w, P.status, P.node_off, 0, 0};
+    A.stage_pieces = (T.cap_pieces <= kPrepPieces) ? T.cap_pieces : 0;
+    A.stage_segs = (A.stage_pieces > 0 && T.n_segs <= kPrepSegs) ? T.n_segs : 0;
+    const size_t lds = (size_t)A.stage_pieces * sizeof(PieceBox) + (size_t)A.stage_segs * sizeof(SegDev);
+    hipLaunchKernelGGL(k_cutprep, dim3(nc), dim3(64), lds, s, A);
 }
 
 // One wavefront per cut element writes its nodes (and their entries of the
@@ -1523,7 +1528,7 @@ void launch_trim_nodes(Plan& P, hipStream_t s) {
     if (T.n_curves == 0 || nc == 0) return;
     GridDev G{P.dir[0].knots + P.p, P.dir[1].knots + P.p, P.N1, P.N2};  // breakpoints
     CutArgs A{T, G, nc, P.cut_list, P.ehead, P.arc_next, P.epoch, P.cut_el, P.node_cnt,
-              P.n_r, P.n_q_override, P.n_s, P.p, P.gauss_x, P.gauss_w, P.status, P.node_off};
+              P.n_r, P.n_q_override, P.n_s, P.p, P.gauss_x, P.gauss_w, P.status, P.node_off, 0, 0};
     const size_t cut0 = (size_t)P.dir[0].Q * P.dir[1].Q + (size_t)P.n_band * (P.p + 1) * (P.p + 1);
     const int prefix_here = nc <= kNodePrefixMax;
     if (!prefix_here) exclusive_scan(P.node_cnt, P.node_off, nc, P.scan_tmp, s);
