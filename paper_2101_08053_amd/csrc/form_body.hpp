@@ -594,12 +594,24 @@ __device__ __forceinline__ void cut_elem_body(const CutEArgs& A, int c, CutESmem
         S.sCp[t][0] = q[0];
         S.sCp[t][1] = q[1];
     }
+    // this thread's node of the next chunk, loaded while the current chunk is contracted
+    double nxv = 0.0, nyv = 0.0, nwv = 0.0, ncv = 0.0;
+    auto prefetch = [&](int base) {
+        const int n = base + threadIdx.x;
+        if (threadIdx.x < CH && n < ne) {
+            nxv = A.nx[n];
+            nyv = A.ny[n];
+            nwv = A.nw[n];
+            if (!A.detj && !A.c.is_const) ncv = A.c.cut[n];
+        }
+    };
+    prefetch(nb);
     for (int base = nb; base < ne; base += CH) {
         __syncthreads();
         if (threadIdx.x < CH) {
             const int n = base + threadIdx.x;
             if (n < ne) {
-                const double x = A.nx[n], y = A.ny[n], w = A.nw[n];
+                const double x = nxv, y = nyv, w = nwv;
                 double cv;
                 double B1[P + 1], B2[P + 1];
                 if (A.detj) {  // |det J| from the staged control points (the sums of detj_local)
@@ -626,7 +638,7 @@ __device__ __forceinline__ void cut_elem_body(const CutEArgs& A, int c, CutESmem
                     cv = fabs(x1 * y2 - x2 * y1);
                     A.c_cut[n] = cv;
                 } else {
-                    cv = A.c.is_const ? A.c.value : A.c.cut[n];
+                    cv = A.c.is_const ? A.c.value : ncv;
                     basis_eval_rec<P>(A.d1.knots, P + e1, S.sRec[0], x, B1);
                     basis_eval_rec<P>(A.d2.knots, P + e2, S.sRec[1], y, B2);
                 }
@@ -642,6 +654,7 @@ __device__ __forceinline__ void cut_elem_body(const CutEArgs& A, int c, CutESmem
             }
         }
         __syncthreads();
+        prefetch(base + CH);
         if (KS == 1 && wave >= NT) continue;
         const int nsteps = (min(CH, ne - base) + 3) >> 2;
         for (int k = (KS == 1) ? 0 : wave; k < nsteps; k += KS) {
