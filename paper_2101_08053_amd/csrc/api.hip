@@ -86,17 +86,13 @@ static void setup_trim(Plan& P, hipStream_t s, bool discover, bool points) {
     TrimDev& T = P.trim;
     if (T.n_curves > 0) {
         launch_trim_curves(P, s);
-        if (discover) {
-            int np = d2h1(T.n_pieces, s);
-            std::vector<int> off(1);
-            int ncross = d2h1(T.cross_off + T.cap_pieces, s);
-            (void)np;
-            T.cap_cross = std::max(ncross, 1);
-            T.cap_arcs = ncross + np;
-            T.cross = P.alloc<CrossDev>(T.cap_cross);
-            T.merged = P.alloc<CrossDev>(T.cap_cross);
-            T.arcs = P.alloc<ArcDev>(std::max(T.cap_arcs, 1));
-            P.arc_next = P.alloc<int>(std::max(T.cap_arcs, 1));
+        if (discover) {  // one slot of arcs per piece, as many as the most crossings of a piece + 1
+            T.arc_slot = trim_max_crossings(P, s) + 1;
+            T.cap_arcs = std::max(T.cap_pieces, 1) * T.arc_slot;
+            T.cross = P.alloc<CrossDev>(T.cap_arcs);
+            T.merged = P.alloc<CrossDev>(T.cap_arcs);
+            T.arcs = P.alloc<ArcDev>(T.cap_arcs);
+            P.arc_next = P.alloc<int>(T.cap_arcs);
         }
         launch_trim_arcs(P, s);
     }
@@ -459,9 +455,6 @@ int iga_plan_create(const iga_patch_desc* desc, const iga_opts* opts, iga_plan**
         T.piece_curve_off = P->alloc<int>(T.n_curves + 1);
         T.isect_t = P->alloc<double>((size_t)T.cap_pieces0 * kMaxIsectPerPiece);
         T.isect_n = P->alloc<int>(T.cap_pieces0);
-        T.cross_cnt = P->alloc<int>(T.cap_pieces + 1);
-        T.nv = P->alloc<int>(T.cap_pieces + 1);
-        T.cross_off = P->alloc<int>(T.cap_pieces + 1);
         T.row_cnt = P->alloc<int>(P->N2);
         T.row_key = P->alloc<double>((size_t)P->N2 * kRowCross);
         T.row_curve = P->alloc<int>((size_t)P->N2 * kRowCross);

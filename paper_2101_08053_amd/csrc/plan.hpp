@@ -113,13 +113,11 @@ struct TrimDev {
     int* n_pieces0;
     double* isect_t;       // cap_pieces0 * kMaxIsectPerPiece
     int* isect_n;
-    int* cross_cnt;        // per piece: nv + nh
-    int* nv;               // per piece vertical crossings
-    int* cross_off;        // cap_pieces + 1 (exclusive scan)
-    CrossDev* cross;       // capacity cap_cross, ordered per piece (vertical then horizontal)
-    CrossDev* merged;      // sorted by t per piece
-    ArcDev* arcs;          // capacity cap_cross + cap_pieces
-    int cap_pieces0, cap_pieces, cap_cross, cap_arcs;
+    CrossDev* cross;       // crossings of long pieces (more than fit in LDS), arc_slot per piece
+    CrossDev* merged;      // the same sorted by t
+    ArcDev* arcs;          // arc_slot per piece: the arcs of piece k are k*arc_slot + j, j <= its crossings
+    int cap_pieces0, cap_pieces, cap_arcs;
+    int arc_slot;          // most crossings of one piece (found at plan creation) + 1
     // Per row of elements: crossings of spline pieces with the horizontal line
     // through the row's element centres (key = min(X, piece's largest x)).
     int* row_cnt;          // N2
@@ -278,6 +276,7 @@ void exclusive_scan(const int* in, int* out, int n, int* tmp, hipStream_t s);
 // trim.hip
 void launch_trim_curves(Plan& P, hipStream_t s);            // segments + monotone pieces (+ unions)
 void launch_trim_arcs(Plan& P, hipStream_t s);              // solve, merge, arcs
+int trim_max_crossings(Plan& P, hipStream_t s);             // plan creation: most grid-line crossings of one piece
 void launch_trim_classes(Plan& P, hipStream_t s);           // elements, functions, flags
 void launch_trim_lists(Plan& P, hipStream_t s);             // act_of, cut/band lists
 void launch_trim_cutprep(Plan& P, hipStream_t s);           // per cut element segments, variant, counts

@@ -515,27 +515,13 @@ __device__ __forceinline__ BpView stage_bp(const GridDev& G, double* sbp) {
     return {sbp, sbp + n1};  // the caller synchronises before use
 }
 
-// Crossings of a piece with the vertical (then horizontal) grid lines in its
-// box, counted half-open so that a crossing at a shared end belongs to one piece.
-__device__ __forceinline__ void piece_cross_count(const PieceDev& Pc, const BpView& bp, const GridDev& G, int& nv,
-                                                  int& nh) {
-    const double vx[2] = {fmin(Pc.x0, Pc.x1), fmax(Pc.x0, Pc.x1)};
-    const double vy[2] = {fmin(Pc.y0, Pc.y1), fmax(Pc.y0, Pc.y1)};
-    int rx[2], ry[2];
-    lower_bound_k<2>(bp.b1, G.N1 + 1, vx, rx);
-    lower_bound_k<2>(bp.b2, G.N2 + 1, vy, ry);
-    nv = rx[1] - rx[0];
-    nh = ry[1] - ry[0];
-}
-
 // Union of holes (one workgroup of 1024, after the curve-curve splits):
 // orientation of every curve (sign of its enclosed area by Gauss on each
 // segment; a hole traversed with the visible domain on its left is
-// clockwise), crossing counts of every piece and their offsets.
-__device__ void curves_orient_count(const TrimDev& T, CurveDev* __restrict__ curves, const GridDev& G,
-                                    const BpView& bp, const double* __restrict__ gx, const double* __restrict__ gw) {
+// clockwise).
+__device__ void curves_orient(const TrimDev& T, CurveDev* __restrict__ curves, const double* __restrict__ gx,
+                              const double* __restrict__ gw) {
     __shared__ double sh_area[1024 / 64];
-    __shared__ int sh[1024 / 64 + 1];
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     constexpr int ng = 8;
     for (int c = 0; c < T.n_curves; ++c) {
@@ -561,33 +547,14 @@ __device__ void curves_orient_count(const TrimDev& T, CurveDev* __restrict__ cur
         }
         __syncthreads();
     }
-    const int np = *T.n_pieces;
-    for (int k = tid; k < T.cap_pieces; k += 1024) {
-        int nv = 0, nh = 0;
-        if (k < np) piece_cross_count(T.pieces[k], bp, G, nv, nh);
-        T.nv[k] = nv;
-        T.cross_cnt[k] = nv + nh;
-    }
-    __syncthreads();
-    int carry = 0;
-    for (int base = 0; base < T.cap_pieces; base += 1024) {
-        const int k = base + tid;
-        const int v = (k < T.cap_pieces) ? T.cross_cnt[k] : 0;
-        int total;
-        const int ex = block_excl_scan(v, sh, total);
-        if (k < T.cap_pieces) T.cross_off[k] = ex + carry;
-        carry += total;
-    }
-    if (tid == 0) T.cross_off[T.cap_pieces] = carry;
 }
 
-// One curve, one workgroup: each thread forms its segment, splits it
-// into monotone pieces and counts their grid-line crossings, all in
-// registers; two block scans place the pieces and their crossings. The
+// One curve, one workgroup: each thread forms its segment and splits it into
+// monotone pieces, in registers; a block scan places the pieces. The
 // segment's 8-point Gauss share of the enclosed area gives the orientation.
 __device__ void front_one_curve(const TrimDev& T, const double* __restrict__ cp, const int* __restrict__ cp_off,
-                                CurveDev* __restrict__ curves, const GridDev& G, const BpView& bp,
-                                const double* __restrict__ gx, const double* __restrict__ gw) {
+                                CurveDev* __restrict__ curves, const double* __restrict__ gx,
+                                const double* __restrict__ gw) {
     __shared__ int sh[1024 / 64 + 1];
     __shared__ double sh_area[1024 / 64];
     constexpr int ng = 8;
@@ -599,7 +566,7 @@ __device__ void front_one_curve(const TrimDev& T, const double* __restrict__ cp,
         gxv[g] = gx[gauss_off(ng) + g];
         gwv[g] = gw[gauss_off(ng) + g];
     }
-    int carry_p = 0, carry_c = 0;
+    int carry_p = 0;
     double area = 0.0;
     for (int base = 0; base < T.n_segs; base += nt) {
         const int s = base + tid;
@@ -613,7 +580,7 @@ __device__ void front_one_curve(const TrimDev& T, const double* __restrict__ cp,
             double r[4];
             segment_splits(S, C.t_range, r);
             sp = segment_pieces(C.t_range, r);
-#pragma unroll
+#pragma unroll 1
             for (int g = 0; g < ng; ++g) {
                 const double tt = C.t_range * (gxv[g] + 1.0) * 0.5;
                 const double w = gwv[g] * C.t_range * 0.5;
@@ -622,52 +589,16 @@ __device__ void front_one_curve(const TrimDev& T, const double* __restrict__ cp,
                 area += 0.5 * w * (X * dY - Y * dX);
             }
         }
-        int tot_p, tot_c;
+        int tot_p;
         const int offp = block_scan_carry(sp.n, sh, tot_p) + carry_p;
-        // crossing counts of all five piece slots, the twenty searches in lockstep
-        PieceDev pcs[5];
-        double vx[10], vy[10];
-#pragma unroll
-        for (int k = 0; k < 5; ++k) {
-            pcs[k] = (valid && sp.use[k]) ? make_piece(S, s, sp.t0[k], sp.t1[k]) : PieceDev{};
-            vx[2 * k] = fmin(pcs[k].x0, pcs[k].x1);
-            vx[2 * k + 1] = fmax(pcs[k].x0, pcs[k].x1);
-            vy[2 * k] = fmin(pcs[k].y0, pcs[k].y1);
-            vy[2 * k + 1] = fmax(pcs[k].y0, pcs[k].y1);
-        }
-        int rx[10], ry[10];
-        lower_bound_k<10>(bp.b1, G.N1 + 1, vx, rx);
-        lower_bound_k<10>(bp.b2, G.N2 + 1, vy, ry);
-        int cnt[5], nvk[5], csum = 0;
-#pragma unroll
-        for (int k = 0; k < 5; ++k) {
-            const bool on = valid && sp.use[k];
-            nvk[k] = on ? rx[2 * k + 1] - rx[2 * k] : 0;
-            cnt[k] = on ? nvk[k] + (ry[2 * k + 1] - ry[2 * k]) : 0;
-            csum += cnt[k];
-        }
-        const int offc = block_scan_carry(csum, sh, tot_c) + carry_c;
         if (valid) {
-            int q = offp, run = offc;
+            int q = offp;
 #pragma unroll
-            for (int k = 0; k < 5; ++k) {
-                if (!sp.use[k]) continue;
-                T.pieces[q] = pcs[k];
-                T.nv[q] = nvk[k];
-                T.cross_cnt[q] = cnt[k];
-                T.cross_off[q] = run;
-                run += cnt[k];
-                ++q;
-            }
+            for (int k = 0; k < 5; ++k)
+                if (sp.use[k]) T.pieces[q++] = make_piece(S, s, sp.t0[k], sp.t1[k]);
             if (S.seg == 0) T.piece_curve_off[0] = offp;
         }
         carry_p += tot_p;
-        carry_c += tot_c;
-    }
-    for (int k = carry_p + tid; k < T.cap_pieces; k += nt) {
-        T.nv[k] = 0;
-        T.cross_cnt[k] = 0;
-        T.cross_off[k] = carry_c;
     }
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) area += __shfl_xor(area, o, 64);
@@ -676,27 +607,23 @@ __device__ void front_one_curve(const TrimDev& T, const double* __restrict__ cp,
     if (tid == 0) {
         *T.n_pieces = carry_p;
         T.piece_curve_off[1] = carry_p;
-        T.cross_off[T.cap_pieces] = carry_c;
         double a = 0.0;
         for (int w = 0; w < nt / 64; ++w) a += sh_area[w];
         curves[0].sigma = (a > 0.0) ? -1.0 : 1.0;
     }
 }
 
-// Front of the trimming set-up in one workgroup (256 threads). One curve: segments, pieces,
-// crossing counts and offsets, orientation (front_one_curve). A union of
-// holes: segments and the unsplit pieces only. Both clear the per-row
-// centre-line crossing counts that the arc kernel fills.
+// Front of the trimming set-up in one workgroup (256 threads). One curve:
+// segments, pieces, orientation (front_one_curve). A union of holes:
+// segments and the unsplit pieces only. Both clear the per-row centre-line
+// crossing counts that the arc kernel fills.
 __global__ void __launch_bounds__(256) k_trim_front(TrimDev T, const double* __restrict__ cp,
                                                      const int* __restrict__ cp_off, CurveDev* __restrict__ curves,
                                                      GridDev G, const double* __restrict__ gx,
                                                      const double* __restrict__ gw) {
-    __shared__ double sbp[kLdsBp];
     for (int r = threadIdx.x; r < G.N2; r += blockDim.x) T.row_cnt[r] = 0;
     if (T.n_curves == 1) {
-        const BpView bp = stage_bp(G, sbp);
-        __syncthreads();
-        front_one_curve(T, cp, cp_off, curves, G, bp, gx, gw);
+        front_one_curve(T, cp, cp_off, curves, gx, gw);
     } else {
         for (int s = threadIdx.x; s < T.n_segs; s += blockDim.x) segment_make(T, cp, cp_off, s);
         __syncthreads();
@@ -704,14 +631,12 @@ __global__ void __launch_bounds__(256) k_trim_front(TrimDev T, const double* __r
     }
 }
 
-// Union of holes: split the pieces where they meet another curve, then orientation and counts.
-__global__ void __launch_bounds__(1024) k_trim_split(TrimDev T, CurveDev* __restrict__ curves, GridDev G,
+// Union of holes: split the pieces where they meet another curve, then orientation.
+__global__ void __launch_bounds__(1024) k_trim_split(TrimDev T, CurveDev* __restrict__ curves,
                                                      const double* __restrict__ gx, const double* __restrict__ gw) {
-    __shared__ double sbp[kLdsBp];
-    const BpView bp = stage_bp(G, sbp);
     pieces_split(T);
     __syncthreads();
-    curves_orient_count(T, curves, G, bp, gx, gw);
+    curves_orient(T, curves, gx, gw);
 }
 
 void launch_trim_curves(Plan& P, hipStream_t s) {
@@ -722,7 +647,7 @@ void launch_trim_curves(Plan& P, hipStream_t s) {
                        P.gauss_w);
     if (T.n_curves > 1) {
         hipLaunchKernelGGL(k_piece_isect, dim3(T.cap_pieces0), dim3(64), 0, s, T, P.status);
-        hipLaunchKernelGGL(k_trim_split, dim3(1), dim3(1024), 0, s, T, P.d_curves, G, P.gauss_x, P.gauss_w);
+        hipLaunchKernelGGL(k_trim_split, dim3(1), dim3(1024), 0, s, T, P.d_curves, P.gauss_x, P.gauss_w);
     }
 }
 
@@ -737,30 +662,37 @@ void launch_trim_curves(Plan& P, hipStream_t s) {
 constexpr int kArcLds = 512;
 
 __global__ void __launch_bounds__(256) k_piece_arcs(TrimDev T, GridDev G, int* __restrict__ emark, int epoch,
-                                                    unsigned long long* __restrict__ ehead, int* __restrict__ arc_next) {
+                                                    unsigned long long* __restrict__ ehead, int* __restrict__ arc_next,
+                                                    int* __restrict__ status) {
     __shared__ double sbp[kLdsBp];
     __shared__ CrossDev sCross[kArcLds], sMerged[kArcLds];
     const int k = blockIdx.x;
     const int np = *T.n_pieces;
     const int tid = threadIdx.x;
-    if (k == 0) {  // arcs past the last piece's (capacity left from the plan's first set-up)
-        const int n_arcs = T.cross_off[np] + np;
-        for (int a = n_arcs + tid; a < T.cap_arcs; a += 256) T.arcs[a].keep = 0;
-    }
     if (k >= np) return;
     const BpView bp = stage_bp(G, sbp);
-    const int base = T.cross_off[k], n = T.cross_cnt[k], nv = T.nv[k];
     const PieceDev Pc = T.pieces[k];
     const SegDev S = T.segs[Pc.seg];
     const CurveDev C = T.curves[Pc.curve];
-    CrossDev* cross = (n <= kArcLds) ? sCross : T.cross + base;
-    CrossDev* merged = (n <= kArcLds) ? sMerged : T.merged + base;
     __syncthreads();
+    // crossings with the vertical (then horizontal) grid lines in the piece's box, counted
+    // half-open so that a crossing at a shared end belongs to one piece
     const double xmin = fmin(Pc.x0, Pc.x1), xmax = fmax(Pc.x0, Pc.x1);
     const double ymin = fmin(Pc.y0, Pc.y1), ymax = fmax(Pc.y0, Pc.y1);
-    int lv0, lh0;
-    lower_bound_k<1>(bp.b1, G.N1 + 1, &xmin, &lv0);
-    lower_bound_k<1>(bp.b2, G.N2 + 1, &ymin, &lh0);
+    int lv[2], lh[2];
+    {
+        const double vx[2] = {xmin, xmax}, vy[2] = {ymin, ymax};
+        lower_bound_k<2>(bp.b1, G.N1 + 1, vx, lv);
+        lower_bound_k<2>(bp.b2, G.N2 + 1, vy, lh);
+    }
+    const int lv0 = lv[0], lh0 = lh[0], nv = lv[1] - lv[0], n = nv + (lh[1] - lh[0]);
+    if (n + 1 > T.arc_slot) {  // more crossings than at plan creation: the geometry is not the plan's
+        if (tid == 0) atomicExch(status, IGA_E_TOPOLOGY);
+        return;
+    }
+    const int base = k * T.arc_slot;  // this piece's arcs are base + j, j = 0..n
+    CrossDev* cross = (n <= kArcLds) ? sCross : T.cross + base;
+    CrossDev* merged = (n <= kArcLds) ? sMerged : T.merged + base;
     // spline pieces: rows whose centre y lies in [ymin, ymax) (centres are non-decreasing in
     // the row): branch-free lower bounds of ymin and ymax over the row centres, in lockstep
     int r0 = 0, r1 = 0;
@@ -853,7 +785,7 @@ __global__ void __launch_bounds__(256) k_piece_arcs(TrimDev T, GridDev G, int* _
         upper_bound_k<1>(bp.b2, G.N2 + 1, &Y, &u2);
         A.e1 = min(max(u1 - 1, 0), G.N1 - 1);
         A.e2 = min(max(u2 - 1, 0), G.N2 - 1);
-        const int idx = base + k + j;
+        const int idx = base + j;
         T.arcs[idx] = A;
         if (keep) {  // push onto the element's list (order fixed later by arc index)
             const int e = A.e2 * G.N1 + A.e1;
@@ -865,12 +797,36 @@ __global__ void __launch_bounds__(256) k_piece_arcs(TrimDev T, GridDev G, int* _
     }
 }
 
+// Plan creation: the largest number of grid-line crossings of one piece.
+__global__ void k_piece_maxcross(TrimDev T, GridDev G, int* __restrict__ out) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= *T.n_pieces) return;
+    const PieceDev Pc = T.pieces[k];
+    const double vx[2] = {fmin(Pc.x0, Pc.x1), fmax(Pc.x0, Pc.x1)}, vy[2] = {fmin(Pc.y0, Pc.y1), fmax(Pc.y0, Pc.y1)};
+    int lv[2], lh[2];
+    lower_bound_k<2>(G.bp1, G.N1 + 1, vx, lv);
+    lower_bound_k<2>(G.bp2, G.N2 + 1, vy, lh);
+    atomicMax(out, (lv[1] - lv[0]) + (lh[1] - lh[0]));
+}
+
+int trim_max_crossings(Plan& P, hipStream_t s) {
+    TrimDev& T = P.trim;
+    GridDev G{P.dir[0].knots + P.p, P.dir[1].knots + P.p, P.N1, P.N2};  // breakpoints
+    HIPX(hipMemsetAsync(P.counts + 8, 0, sizeof(int), s));
+    hipLaunchKernelGGL(k_piece_maxcross, dim3((std::max(T.cap_pieces, 1) + 127) / 128), dim3(128), 0, s, T, G,
+                       P.counts + 8);
+    int m = 0;
+    HIPX(hipMemcpyAsync(&m, P.counts + 8, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPX(hipStreamSynchronize(s));
+    return m;
+}
+
 void launch_trim_arcs(Plan& P, hipStream_t s) {
     TrimDev& T = P.trim;
     if (T.n_curves == 0) return;
     GridDev G{P.dir[0].knots + P.p, P.dir[1].knots + P.p, P.N1, P.N2};  // breakpoints
     hipLaunchKernelGGL(k_piece_arcs, dim3(std::max(T.cap_pieces, 1)), dim3(256), 0, s, T, G, P.emark, P.epoch,
-                       P.ehead, P.arc_next);
+                       P.ehead, P.arc_next, P.status);
 }
 
 // -------------------------------------------------------------- classes
