@@ -191,6 +191,17 @@ int iga_plan_index_maps(const iga_plan* plan, const int32_t** act_of, const int3
  * IGA_E_UNSUPPORTED otherwise. */
 int iga_trim_mass_form(iga_plan* plan, const iga_coeff* c, double* vals, int32_t flags, void* stream);
 
+/* Graph replay of iga_trim_mass_form (off by default: on MI355X with ROCm
+ * 7 a replay costs the host about as much as the launches it replaces).
+ * enable != 0: the first call with a given (vals, coefficient, flags)
+ * records the formation's kernels and stream joins as a HIP graph on a
+ * private stream; later calls with the same three replay it on the caller's
+ * stream, reading the plan's inputs (curves, weights, nodes, coefficient
+ * values) as they stand then. Another vals, coefficient pointer or value, or
+ * flags records anew. Plans with per-phase timing enabled, or method
+ * IGA_NAIVE_WQ, always launch kernel by kernel. */
+int iga_plan_set_graph(iga_plan* plan, int32_t enable);
+
 /* Synchronises stream and returns the device status word of the plan
  * (IGA_OK or IGA_E_SINGULAR_WEIGHTS / IGA_E_CAPACITY), then clears it. */
 int iga_plan_status(iga_plan* plan, void* stream);
@@ -263,9 +274,11 @@ int iga_batch_status(iga_batch* batch, void* stream);
 int iga_trim_mass_form_batched(iga_plan* const* plans, int32_t count, const iga_coeff* cs,
                                double* const* vals, int32_t use_graph, void* stream);
 
-/* Per-phase device timing of the plan's calls (hipEvents on the call's
- * stream). enable != 0 starts recording; iga_plan_timings synchronises and
- * returns the accumulated milliseconds and counts per phase. */
+/* Per-phase device timing of the plan's calls (hipEvents on the streams the
+ * phases run on). enable != 0 starts recording; iga_plan_timings synchronises
+ * and returns the accumulated milliseconds and counts per phase. While timing
+ * is on, the interior rows kernel runs alone (the two streams join before
+ * and after it), so IGA_PHASE_INTERIOR is that kernel's own duration. */
 #define IGA_PHASE_SETUP     0  /* layout, weights, trimming, cut rules        */
 #define IGA_PHASE_COEF      1  /* coefficient at rule points                  */
 #define IGA_PHASE_INTERIOR  2  /* interior rows kernel, start to end of its run */

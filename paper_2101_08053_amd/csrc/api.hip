@@ -17,8 +17,11 @@ static thread_local std::string g_last_error;
 void set_error(const std::string& msg) { g_last_error = msg; }
 
 Plan::~Plan() {
+    if (fexec) hipGraphExecDestroy(fexec);
+    if (fgraph) hipGraphDestroy(fgraph);
+    if (cap_stream) hipStreamDestroy(cap_stream);
     if (sw.h_scal) hipHostFree(sw.h_scal);
-    for (hipEvent_t e : {ev_fork, ev_tables, ev_lists, ev_interior, ev_band})
+    for (hipEvent_t e : {ev_fork, ev_iso, ev_lists, ev_interior, ev_band})
         if (e) hipEventDestroy(e);
     if (aux) hipStreamDestroy(aux);
     for (auto& e : ev_pool) hipEventDestroy(e);
@@ -82,7 +85,6 @@ static void run_setup(Plan& P, hipStream_t s, bool discover) {
 }
 
 static void setup_trim(Plan& P, hipStream_t s, bool discover, bool points) {
-    ++P.epoch;
     TrimDev& T = P.trim;
     if (T.n_curves > 0) {
         launch_trim_curves(P, s);
@@ -238,7 +240,6 @@ static void form(Plan& P, const iga_coeff& c, double* vals, int flags, hipStream
         PhaseTimer t(P, a, IGA_PHASE_COEF);
         launch_coef(P, c, a, 1);
     }
-    HIPX(hipEventRecord(P.ev_tables, a));
     if (full) {
         PhaseTimer t(P, s, IGA_PHASE_SETUP);
         setup_trim(P, s, false, false);
@@ -252,7 +253,13 @@ static void form(Plan& P, const iga_coeff& c, double* vals, int flags, hipStream
         launch_cut_rows_mode(P, c, vals, a, 1);  // rows formed element-wise: their inside sums
     }
     HIPX(hipEventRecord(P.ev_band, a));
-    if (P.timing) {  // the interior kernel alone: events at its dispatch's start and end
+    if (P.timing) {
+        // The interior kernel alone, events at its dispatch's start and end:
+        // it waits for the work queued on s so far, and s waits for it before
+        // its next kernel, so the events time the kernel and not its share
+        // of a GPU busy with the cut elements.
+        HIPX(hipEventRecord(P.ev_iso, s));
+        HIPX(hipStreamWaitEvent(a, P.ev_iso, 0));
         hipEvent_t t0, t1;
         HIPX(hipEventCreate(&t0));
         HIPX(hipEventCreate(&t1));
@@ -263,6 +270,7 @@ static void form(Plan& P, const iga_coeff& c, double* vals, int flags, hipStream
     }
     if (full) launch_points(P, a);
     HIPX(hipEventRecord(P.ev_interior, a));
+    if (P.timing) HIPX(hipStreamWaitEvent(s, P.ev_interior, 0));
     {
         PhaseTimer t(P, s, IGA_PHASE_CUT);
         launch_cut_elems(P, c, s);  // with c at the cut nodes
@@ -271,6 +279,41 @@ static void form(Plan& P, const iga_coeff& c, double* vals, int flags, hipStream
         launch_dwq_rows(P, c, vals, s);
     }
     HIPX(hipStreamWaitEvent(s, P.ev_interior, 0));
+}
+
+// The formation recorded once as a HIP graph and replayed: one submission
+// instead of some forty kernel launches and stream joins. Kernel arguments
+// are the plan's buffers and sizes, which stay fixed for its life, plus the
+// output, the coefficient and the flags, which key the recording. The set-up
+// counter that tags marks and lists lives on the device, so replays need no
+// new argument.
+static bool same_coeff(const iga_coeff& a, const iga_coeff& b) {
+    return a.kind == b.kind && a.value == b.value && a.geom_cp == b.geom_cp && a.c_points == b.c_points;
+}
+
+static void form_graph(Plan& P, const iga_coeff& c, double* vals, int flags, hipStream_t s) {
+    if (!(P.fexec && P.fkey_vals == vals && P.fkey_flags == flags && same_coeff(P.fkey_c, c))) {
+        if (P.fexec) HIPX(hipGraphExecDestroy(P.fexec));
+        if (P.fgraph) HIPX(hipGraphDestroy(P.fgraph));
+        P.fexec = nullptr;
+        P.fgraph = nullptr;
+        if (!P.cap_stream) HIPX(hipStreamCreateWithFlags(&P.cap_stream, hipStreamNonBlocking));
+        HIPX(hipStreamBeginCapture(P.cap_stream, hipStreamCaptureModeRelaxed));
+        try {
+            form(P, c, vals, flags, P.cap_stream);
+        } catch (...) {
+            hipGraph_t g = nullptr;
+            hipStreamEndCapture(P.cap_stream, &g);
+            if (g) hipGraphDestroy(g);
+            throw;
+        }
+        HIPX(hipStreamEndCapture(P.cap_stream, &P.fgraph));
+        HIPX(hipGraphInstantiate(&P.fexec, P.fgraph, nullptr, nullptr, 0));
+        P.fkey_vals = vals;
+        P.fkey_flags = flags;
+        P.fkey_c = c;
+    }
+    HIPX(hipGraphLaunch(P.fexec, s));
 }
 
 static void validate_knots(const double* k, int n, int p, int d) {
@@ -331,7 +374,7 @@ int iga_plan_create(const iga_patch_desc* desc, const iga_opts* opts, iga_plan**
     std::unique_ptr<iga_plan> guard(P);
     HIPX(hipGetDevice(&P->device));
     HIPX(hipStreamCreateWithFlags(&P->aux, hipStreamNonBlocking));
-    for (hipEvent_t* e : {&P->ev_fork, &P->ev_tables, &P->ev_lists, &P->ev_interior, &P->ev_band})
+    for (hipEvent_t* e : {&P->ev_fork, &P->ev_iso, &P->ev_lists, &P->ev_interior, &P->ev_band})
         HIPX(hipEventCreateWithFlags(e, hipEventDisableTiming));
     P->p = p;
     P->method = desc->method;
@@ -463,6 +506,11 @@ int iga_plan_create(const iga_patch_desc* desc, const iga_opts* opts, iga_plan**
     P->ecls = P->alloc<int8_t>(ne);
     P->emark = P->alloc<int>(ne);
     HIPX(hipMemsetAsync(P->emark, 0, sizeof(int) * (size_t)ne, s));
+    P->d_epoch = P->alloc<int>(1);
+    const int epoch0 = 1;  // above every mark's initial 0
+    h2d(P->d_epoch, &epoch0, 1, s);
+    HIPX(hipStreamSynchronize(s));
+    T.epoch = P->d_epoch;
     P->ehead = P->alloc<unsigned long long>(ne);
     HIPX(hipMemsetAsync(P->ehead, 0, sizeof(unsigned long long) * (size_t)ne, s));
     P->cut_id = P->alloc<int>(ne);
@@ -541,8 +589,20 @@ int iga_trim_mass_form(iga_plan* P, const iga_coeff* c, double* vals, int32_t fl
     IGA_REQUIRE(c->kind != IGA_COEF_AT_POINTS || c->c_points, IGA_E_INVALID, "per-point coefficient missing");
     IGA_REQUIRE(!(P->method == IGA_DWQ && c->kind == IGA_COEF_AT_POINTS), IGA_E_UNSUPPORTED,
                 "discontinuous weighted quadrature needs c at nested points: constant or |det J| only");
-    form(*P, *c, vals, flags, (hipStream_t)stream);
+    hipStream_t s = (hipStream_t)stream;
+    if (P->timing || !P->use_graph || P->method == IGA_NAIVE_WQ) {
+        form(*P, *c, vals, flags, s);
+    } else {
+        form_graph(*P, *c, vals, flags, s);
+    }
     HIPX(hipGetLastError());
+    API_END
+}
+
+int iga_plan_set_graph(iga_plan* P, int32_t enable) {
+    API_BEGIN
+    IGA_REQUIRE(P, IGA_E_INVALID, "null plan");
+    P->use_graph = enable != 0;
     API_END
 }
 

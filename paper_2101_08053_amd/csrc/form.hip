@@ -111,7 +111,7 @@ void launch_coef(Plan& P, const iga_coeff& c, hipStream_t s, int part) {
 
 // ------------------------------------------------------- interior rows
 template <int P>
-__global__ void __launch_bounds__(128) k_interior(IntArgs A) {
+__global__ void __launch_bounds__(Int2Cfg<P>::NT) k_interior(IntArgs A) {
     __shared__ __align__(16) Int2Smem<P> S;
     const int blk = xcd_block(blockIdx.x, gridDim.x);
     const int i2 = blk / A.ntx;
@@ -122,8 +122,9 @@ template <int P>
 static void launch_interior_p(Plan& Pl, IntArgs A, hipStream_t s, hipEvent_t t0, hipEvent_t t1) {
     A.ntx = interior2_ntx(Pl.N1, P);
     const int nb = A.ntx * Pl.n2;
-    if (t0) hipExtLaunchKernelGGL(k_interior<P>, dim3(nb), dim3(128), 0, s, t0, t1, 0, A);  // events bracket the dispatch
-    else hipLaunchKernelGGL(k_interior<P>, dim3(nb), dim3(128), 0, s, A);
+    const dim3 blk(Int2Cfg<P>::NT);
+    if (t0) hipExtLaunchKernelGGL(k_interior<P>, dim3(nb), blk, 0, s, t0, t1, 0, A);  // events bracket the dispatch
+    else hipLaunchKernelGGL(k_interior<P>, dim3(nb), blk, 0, s, A);
 }
 
 IntArgs int_args(Plan& P, const iga_coeff& c, double* vals) {

@@ -291,38 +291,57 @@ __device__ __forceinline__ void interior_block(const IntArgs& A, int tx, int i2,
     }
 }
 
-// Interior rows, one-launch form. Per test row i2: tiles of up to R = 128
+// Interior rows, one-launch form. Per test row i2: tiles of up to R
 // consecutive "regular" test rows i1 (p+1 <= i1 <= N1-2, two WQ points in
-// every support element), one per thread, and one workgroup for the 2(p+1)
-// end rows (supports touching the first or last element, p+1 points there),
-// one thread per (end row, column b). Stage 1 contracts xi_2 for every xi_1
+// every support element), each row's 2p+1 columns b dealt round-robin to NB
+// threads (R * NB threads per workgroup: enough waves in flight to cover the
+// memory latency), and one workgroup for the 2(p+1) end rows (supports
+// touching the first or last element, p+1 points there), one thread per
+// (end row, column b). Stage 1 contracts xi_2 for every xi_1
 // point of the workgroup's window into T[b][k] (LDS); stage 2 contracts xi_1,
 // M[a][b] = sum_k (w1 B1)[i1][k][a] T[b][k], with the per-column sums of the
 // batched body. A regular row's banded w1 B1 factors are loaded into
 // registers (p <= 5) together with every other global load of the
 // workgroup, before stage 1; the end rows' full factor rows go to LDS.
+// Rows per tile and column groups per row, measured: whole rows per thread
+// are fastest for p <= 5; for p >= 6, whose factors do not fit in registers,
+// the columns of a row dealt to four threads.
+__host__ __device__ constexpr int interior2_rows(int p) { return p <= 5 ? 128 : 64; }
+__host__ __device__ constexpr int interior2_groups(int p) { return p <= 5 ? 1 : 4; }
 template <int P>
 struct Int2Cfg {
     static constexpr int W = 2 * P + 1;                  // band width
     static constexpr int QM = 4 * P + 2;                 // max WQ points in one support
     static constexpr int NR = 2 * P + 2;                 // support points of a regular function
-    static constexpr int R = 128;                        // rows per tile (threads per workgroup)
+    static constexpr int R = interior2_rows(P);          // rows per tile
+    static constexpr int NB = interior2_groups(P);       // column groups: the row's columns b = g, g+NB, ...
+    static constexpr int NT = R * NB;                    // threads per workgroup
     static constexpr int KS = 2 * (R + P) + 2 * P + 2;   // max xi_1 points of a tile window
-    static constexpr int NJ = (KS + R - 1) / R;          // window points per thread
+    static constexpr int NJ = (KS + NT - 1) / NT;        // window points per thread
     static constexpr int NG = P + 1;                     // end rows at each end
     static constexpr bool PRE = (P <= 5);                // factors and coefficients preloaded in registers
 };
 
+// A regular tile's window, or the end-row workgroup's two short windows
+// (at most 6p+2 points) with the end rows' factor rows: they share LDS.
 template <int P>
 struct Int2Smem {
-    double sT[Int2Cfg<P>::W][Int2Cfg<P>::KS];
-    double sWB2[Int2Cfg<P>::QM][Int2Cfg<P>::W];
-    double sG[2 * Int2Cfg<P>::NG][Int2Cfg<P>::QM][Int2Cfg<P>::W];  // w1 B1 rows of the end rows
+    using C = Int2Cfg<P>;
+    static constexpr int KSE = 6 * P + 2;
+    union {
+        double sT[C::W][C::KS];
+        struct {
+            double sT[C::W][KSE];
+            double sG[2 * C::NG][C::QM][C::W];  // w1 B1 rows of the end rows
+        } e;
+    };
+    double sWB2[C::QM][C::W];
 };
 
 // Workgroups per test row i2: the regular tiles, then the end-row workgroup.
 __host__ __device__ inline int interior2_nreg(int N1, int p) {
-    return (N1 >= p + 3) ? ((N1 - 2) - (p + 1) + 1 + 127) / 128 : 0;
+    const int R = interior2_rows(p);
+    return (N1 >= p + 3) ? ((N1 - 2) - (p + 1) + 1 + R - 1) / R : 0;
 }
 __host__ __device__ inline int interior2_ntx(int N1, int p) { return interior2_nreg(N1, p) + 1; }
 
@@ -337,10 +356,11 @@ __device__ __forceinline__ int interior_end_row(int g, int N1, int n1) {
 template <int P>
 __device__ __forceinline__ void interior_rows_block(const IntArgs& A, int tx, int i2, Int2Smem<P>& S) {
     using C = Int2Cfg<P>;
-    constexpr int W = C::W, QM = C::QM, NR = C::NR, R = C::R, NJ = C::NJ, NG = C::NG;
+    constexpr int W = C::W, QM = C::QM, NR = C::NR, R = C::R, NB = C::NB, NT = C::NT, NJ = C::NJ, NG = C::NG;
     const DirDev& D1 = A.d1;
     const DirDev& D2 = A.d2;
     const int tid = threadIdx.x;
+    const int rl = tid % R, grp = tid / R;  // the thread's row in the tile and column group
     if (i2 >= D2.n) return;
     const int nreg = interior2_nreg(D1.N, P);
     const bool endtile = tx >= nreg;
@@ -374,34 +394,43 @@ __device__ __forceinline__ void interior_rows_block(const IntArgs& A, int tx, in
     bool live = false;
     int64_t cid = 0;
     if (!endtile) {
-        if (tid < nlive) {
-            i1 = I1 + tid;
+        if (rl < nlive) {
+            i1 = I1 + rl;
             const int f = i2 * D1.n + i1;
             const int8_t cls = A.fcls[f];
             cid = A.act_of[f];
             live = formed(cls);
         }
     } else {  // any of this thread's (end row, column) pairs formed here
-        for (int t = tid; t < 2 * NG * W; t += R) {
+        for (int t = tid; t < 2 * NG * W; t += NT) {
             const int ie = interior_end_row<P>(t / W, D1.N, D1.n);
             if (ie >= 0 && formed(A.fcls[i2 * D1.n + ie])) live = true;
         }
     }
-    constexpr int NWB = (QM * W + R - 1) / R;
+    // (loads are unconditional, at clamped in-range addresses, and selected
+    // afterwards: one batch of independent loads instead of a branch each)
+    constexpr int NWB = (QM * W + NT - 1) / NT;
     double wb2[NWB];
 #pragma unroll
     for (int u = 0; u < NWB; ++u) {
-        const int t = tid + R * u;
-        wb2[u] = (t < QM * W && t / W < q2) ? D2.WB[((size_t)i2 * D2.qmax) * W + t] : 0.0;
+        const int t = tid + NT * u;
+        const double v = D2.WB[(size_t)i2 * D2.qmax * W + min(t, q2 * W - 1)];
+        wb2[u] = (t < q2 * W) ? v : 0.0;
     }
     double cv[C::PRE ? NJ : 1][NR];
     if (C::PRE && reg_row) {
+        if (A.cwq) {
 #pragma unroll
-        for (int j = 0; j < NJ; ++j) {
-            const int kg = kglob(min(tid + R * j, ks - 1));
+            for (int j = 0; j < NJ; ++j) {
+                const int kg = kglob(min(tid + NT * j, ks - 1));
 #pragma unroll
-            for (int q = 0; q < NR; ++q)
-                cv[C::PRE ? j : 0][q] = A.cwq ? A.cwq[(size_t)(k2lo + q) * D1.Q + kg] : A.c.value;
+                for (int q = 0; q < NR; ++q) cv[C::PRE ? j : 0][q] = A.cwq[(size_t)(k2lo + q) * D1.Q + kg];
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < NJ; ++j)
+#pragma unroll
+                for (int q = 0; q < NR; ++q) cv[C::PRE ? j : 0][q] = A.c.value;
         }
     }
     double wb[C::PRE ? NR : 1][P + 1];
@@ -411,51 +440,83 @@ __device__ __forceinline__ void interior_rows_block(const IntArgs& A, int tx, in
 #pragma unroll
             for (int al = 0; al <= P; ++al) wb[C::PRE ? q : 0][al] = D1.WBT[((size_t)q * (P + 1) + al) * D1.n + i1];
     }
-    if (endtile) {  // the end rows' full w1 B1 rows
-        for (int t = tid; t < 2 * NG * QM * W; t += R) {
-            const int g = t / (QM * W), q = (t / W) % QM, a = t % W;
-            const int ie = interior_end_row<P>(g, D1.N, D1.n);
-            S.sG[g][q][a] = (ie >= 0 && q < D1.qmax) ? D1.WB[((size_t)ie * D1.qmax + q) * W + a] : 0.0;
+    if (endtile) {  // the end rows' full w1 B1 rows, in batches of independent loads
+        constexpr int NGT = 2 * NG * QM * W, NBAT = 16;
+        double* sg = &S.e.sG[0][0][0];
+#pragma unroll 1
+        for (int t0 = 0; t0 < NGT; t0 += NT * NBAT) {
+            double gv[NBAT];
+#pragma unroll
+            for (int u = 0; u < NBAT; ++u) {
+                const int t = t0 + tid + NT * u;
+                const int g = t / (QM * W), q = (t / W) % QM, a = t % W;
+                const int ie = (t < NGT) ? interior_end_row<P>(g, D1.N, D1.n) : -1;
+                const double v = D1.WB[((size_t)max(ie, 0) * D1.qmax + min(q, D1.qmax - 1)) * W + a];
+                gv[u] = (ie >= 0 && q < D1.qmax) ? v : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < NBAT; ++u) {
+                const int t = t0 + tid + NT * u;
+                if (t < NGT) sg[t] = gv[u];
+            }
         }
     }
 #pragma unroll
     for (int u = 0; u < NWB; ++u) {
-        const int t = tid + R * u;
+        const int t = tid + NT * u;
         if (t < QM * W) S.sWB2[t / W][t % W] = wb2[u];
     }
     if (!__syncthreads_or(live)) return;  // no row of the workgroup is formed here
 
     // ---- stage 1: contract xi_2 for every xi_1 point of the window
+    double* sTb = endtile ? &S.e.sT[0][0] : &S.sT[0][0];
+    const int kst = endtile ? Int2Smem<P>::KSE : C::KS;
 #pragma unroll
     for (int j = 0; j < NJ; ++j) {
-        const int k = tid + R * j;
+        const int k = tid + NT * j;
         if (k >= ks) break;
         const int kg = kglob(k);
         if (reg_row) {
+            double cr[C::PRE ? 1 : NR];
+            if (!C::PRE) {
+                if (A.cwq) {
+#pragma unroll
+                    for (int q = 0; q < NR; ++q) cr[C::PRE ? 0 : q] = A.cwq[(size_t)(k2lo + q) * D1.Q + kg];
+                } else {
+#pragma unroll
+                    for (int q = 0; q < NR; ++q) cr[C::PRE ? 0 : q] = A.c.value;
+                }
+            }
             double T[W];
 #pragma unroll
             for (int b = 0; b < W; ++b) T[b] = 0.0;
 #pragma unroll
             for (int q = 0; q < NR; ++q) {
                 const int m2 = q >> 1;
-                const double cq = C::PRE ? cv[C::PRE ? j : 0][q]
-                                         : (A.cwq ? A.cwq[(size_t)(k2lo + q) * D1.Q + kg] : A.c.value);
+                const double cq = C::PRE ? cv[C::PRE ? j : 0][q] : cr[C::PRE ? 0 : q];
 #pragma unroll
                 for (int bl = 0; bl <= P; ++bl) T[m2 + bl] += S.sWB2[q][m2 + bl] * cq;
             }
 #pragma unroll
-            for (int b = 0; b < W; ++b) S.sT[b][k] = T[b];
+            for (int b = 0; b < W; ++b) sTb[b * kst + k] = T[b];
         } else {
             double c[QM];
+            if (A.cwq) {
 #pragma unroll
-            for (int q = 0; q < QM; ++q)
-                c[q] = (q < q2) ? (A.cwq ? A.cwq[(size_t)(k2lo + q) * D1.Q + kg] : A.c.value) : 0.0;
+                for (int q = 0; q < QM; ++q) {
+                    const double v = A.cwq[(size_t)(k2lo + min(q, q2 - 1)) * D1.Q + kg];
+                    c[q] = (q < q2) ? v : 0.0;
+                }
+            } else {
+#pragma unroll
+                for (int q = 0; q < QM; ++q) c[q] = (q < q2) ? A.c.value : 0.0;
+            }
 #pragma unroll 1
             for (int b = 0; b < W; ++b) {
                 double Tb = 0.0;
 #pragma unroll
                 for (int q = 0; q < QM; ++q) Tb += S.sWB2[q][b] * c[q];
-                S.sT[b][k] = Tb;
+                sTb[b * kst + k] = Tb;
             }
         }
     }
@@ -463,10 +524,10 @@ __device__ __forceinline__ void interior_rows_block(const IntArgs& A, int tx, in
     if (!live) return;
 
     // ---- stage 2: contract xi_1
-    if (!endtile) {  // the whole row of this thread
+    if (!endtile) {  // this thread's columns of its row
         const int k0 = kloc(wq_pt0(max(0, i1 - P), D1.N, P));  // the row's first support point
 #pragma unroll 1
-        for (int b = 0; b < W; ++b) {
+        for (int b = grp; b < W; b += NB) {
             double acc[W];
             if constexpr (C::PRE)
                 interior_col_reg<P>([&](int q, int al) { return wb[q][al]; }, &S.sT[b][k0], acc);
@@ -477,7 +538,7 @@ __device__ __forceinline__ void interior_rows_block(const IntArgs& A, int tx, in
             for (int a = 0; a < W; ++a) A.vals[(size_t)(a * W + b) * A.n_act + cid] = acc[a];
         }
     } else {  // one column of an end row per pair
-        for (int t = tid; t < 2 * NG * W; t += R) {
+        for (int t = tid; t < 2 * NG * W; t += NT) {
             const int g = t / W, bcol = t % W;
             const int ie = interior_end_row<P>(g, D1.N, D1.n);
             if (ie < 0) continue;
@@ -487,7 +548,7 @@ __device__ __forceinline__ void interior_rows_block(const IntArgs& A, int tx, in
             const int kg0 = wq_pt0(max(0, ie - P), D1.N, P);
             const int q1 = wq_pt0(min(D1.N - 1, ie) + 1, D1.N, P) - kg0;
             double acc[W];
-            interior_col_end<P>(&S.sG[g][0][0], &S.sT[bcol][kloc(kg0)], q1, acc);
+            interior_col_end<P>(&S.e.sG[g][0][0], &S.e.sT[bcol][kloc(kg0)], q1, acc);
 #pragma unroll
             for (int a = 0; a < W; ++a) A.vals[(size_t)(a * W + bcol) * A.n_act + cide] = acc[a];
         }

@@ -120,6 +120,7 @@ struct TrimDev {
     int arc_slot;          // most crossings of one piece (found at plan creation) + 1
     // Per row of elements: crossings of spline pieces with the horizontal line
     // through the row's element centres (key = min(X, piece's largest x)).
+    int* epoch;            // the set-up counter (device; k_trim_front advances it)
     int* row_cnt;          // N2
     double* row_key;       // N2 * kRowCross
     int* row_curve;        // N2 * kRowCross
@@ -173,7 +174,7 @@ struct Plan {
     // stale when the epoch differs; arc_next[a] is the next arc of a's element or -1
     unsigned long long* ehead = nullptr;
     int* arc_next = nullptr;
-    int epoch = 0;                 // set-up counter (marks need no clearing)
+    int* d_epoch = nullptr;        // set-up counter on the device, advanced by the trimming front (marks need no clearing)
     int* cut_list = nullptr;       // flat ids of cut elements
     int* band_list = nullptr;      // flat ids of band elements
     CutElemDev* cut_el = nullptr;
@@ -207,10 +208,19 @@ struct Plan {
     // second stream of the formation: univariate tables, weights, WQ-grid coefficient and interior
     // rows run there, beside the trimming chain (default priority; joined by events)
     hipStream_t aux = nullptr;
-    hipEvent_t ev_fork = nullptr, ev_tables = nullptr, ev_lists = nullptr, ev_interior = nullptr, ev_band = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_iso = nullptr, ev_lists = nullptr, ev_interior = nullptr, ev_band = nullptr;
 
     // timing
     bool timing = false;
+    // The formation as one HIP graph (captured on a private stream, replayed on the caller's):
+    // valid while the output, coefficient and flags match the captured call.
+    bool use_graph = false;
+    hipStream_t cap_stream = nullptr;
+    hipGraph_t fgraph = nullptr;
+    hipGraphExec_t fexec = nullptr;
+    double* fkey_vals = nullptr;
+    iga_coeff fkey_c{};
+    int fkey_flags = -1;
     std::vector<hipEvent_t> ev_pool;
     std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_records;
     double phase_ms[IGA_PHASE_COUNT] = {0, 0, 0, 0};

@@ -621,6 +621,7 @@ __global__ void __launch_bounds__(256) k_trim_front(TrimDev T, const double* __r
                                                      const int* __restrict__ cp_off, CurveDev* __restrict__ curves,
                                                      GridDev G, const double* __restrict__ gx,
                                                      const double* __restrict__ gw) {
+    if (threadIdx.x == 0) *T.epoch += 1;  // a new set-up: marks and lists of earlier ones become stale
     for (int r = threadIdx.x; r < G.N2; r += blockDim.x) T.row_cnt[r] = 0;
     if (T.n_curves == 1) {
         front_one_curve(T, cp, cp_off, curves, gx, gw);
@@ -661,7 +662,7 @@ void launch_trim_curves(Plan& P, hipStream_t s) {
 // the other elements. Breakpoints and (short pieces') crossings live in LDS.
 constexpr int kArcLds = 512;
 
-__global__ void __launch_bounds__(256) k_piece_arcs(TrimDev T, GridDev G, int* __restrict__ emark, int epoch,
+__global__ void __launch_bounds__(256) k_piece_arcs(TrimDev T, GridDev G, int* __restrict__ emark,
                                                     unsigned long long* __restrict__ ehead, int* __restrict__ arc_next,
                                                     int* __restrict__ status) {
     __shared__ double sbp[kLdsBp];
@@ -671,6 +672,7 @@ __global__ void __launch_bounds__(256) k_piece_arcs(TrimDev T, GridDev G, int* _
     const int tid = threadIdx.x;
     if (k >= np) return;
     const BpView bp = stage_bp(G, sbp);
+    const int epoch = *T.epoch;
     const PieceDev Pc = T.pieces[k];
     const SegDev S = T.segs[Pc.seg];
     const CurveDev C = T.curves[Pc.curve];
@@ -825,8 +827,8 @@ void launch_trim_arcs(Plan& P, hipStream_t s) {
     TrimDev& T = P.trim;
     if (T.n_curves == 0) return;
     GridDev G{P.dir[0].knots + P.p, P.dir[1].knots + P.p, P.N1, P.N2};  // breakpoints
-    hipLaunchKernelGGL(k_piece_arcs, dim3(std::max(T.cap_pieces, 1)), dim3(256), 0, s, T, G, P.emark, P.epoch,
-                       P.ehead, P.arc_next, P.status);
+    hipLaunchKernelGGL(k_piece_arcs, dim3(std::max(T.cap_pieces, 1)), dim3(256), 0, s, T, G, P.emark, P.ehead,
+                       P.arc_next, P.status);
 }
 
 // -------------------------------------------------------------- classes
@@ -837,11 +839,10 @@ void launch_trim_arcs(Plan& P, hipStream_t s) {
 // its piece's largest x lie right of the point, as in inside_curve); ellipses
 // use their implicit function. Rows with more crossings than recorded fall
 // back to the direct test.
-__global__ void k_elem_centre(TrimDev T, GridDev G, const int* __restrict__ emark, int epoch,
-                              int8_t* __restrict__ ecls) {
+__global__ void k_elem_centre(TrimDev T, GridDev G, const int* __restrict__ emark, int8_t* __restrict__ ecls) {
     int e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= G.N1 * G.N2) return;
-    if (emark[e] == epoch) {
+    if (emark[e] == *T.epoch) {
         ecls[e] = EL_CUT;
         return;
     }
@@ -945,7 +946,7 @@ void launch_trim_classes(Plan& P, hipStream_t s) {
     TrimDev& T = P.trim;
     GridDev G{P.dir[0].knots + P.p, P.dir[1].knots + P.p, P.N1, P.N2};  // breakpoints
     int ne = P.N1 * P.N2;
-    hipLaunchKernelGGL(k_elem_centre, dim3((ne + 127) / 128), dim3(128), 0, s, T, G, P.emark, P.epoch, P.ecls);
+    hipLaunchKernelGGL(k_elem_centre, dim3((ne + 127) / 128), dim3(128), 0, s, T, G, P.emark, P.ecls);
     int nf = P.n1 * P.n2;
     int* f_active = P.flags;
     int* f_cut = P.flags + (nf + 1);
@@ -1091,7 +1092,6 @@ struct CutArgs {
     const int* cut_list;
     const unsigned long long* ehead;  // element lists of kept arcs (k_piece_arcs)
     const int* arc_next;
-    int epoch;
     CutElemDev* cut_el;
     int* node_cnt;
     int n_r, n_q_override, n_s, p;
@@ -1205,7 +1205,7 @@ __global__ void __launch_bounds__(64) k_cutprep(CutArgs A) {
         for (int k = lane; k < T.n_segs; k += 64) sSegAll[k] = T.segs[k];
     if (lane == 0) {
         const unsigned long long h = A.ehead[e];
-        int a = ((int)(h >> 32) == A.epoch) ? (int)(h & 0xffffffffull) - 1 : -1;
+        int a = ((int)(h >> 32) == *T.epoch) ? (int)(h & 0xffffffffull) - 1 : -1;
         int n = 0;
         for (int it = 0; a >= 0 && it <= kMaxArcsPerElem; ++it) {
             if (n < kMaxArcsPerElem) sArc[n++] = a;
@@ -1379,7 +1379,7 @@ void launch_trim_cutprep(Plan& P, hipStream_t s) {
     int nc = (int)P.n_cut_el;
     if (T.n_curves == 0 || nc == 0) return;
     GridDev G{P.dir[0].knots + P.p, P.dir[1].knots + P.p, P.N1, P.N2};  // breakpoints
-    CutArgs A{T, G, nc, P.cut_list, P.ehead, P.arc_next, P.epoch, P.cut_el, P.node_cnt,
+    CutArgs A{T, G, nc, P.cut_list, P.ehead, P.arc_next, P.cut_el, P.node_cnt,
               P.n_r, P.n_q_override, P.n_s, P.p, P.gauss_x, P.gauss_w, P.status, P.node_off, 0, 0};
     A.stage_pieces = (T.cap_pieces <= kPrepPieces) ? T.cap_pieces : 0;
     A.stage_segs = (A.stage_pieces > 0 && T.n_segs <= kPrepSegs) ? T.n_segs : 0;
@@ -1483,7 +1483,7 @@ void launch_trim_nodes(Plan& P, hipStream_t s) {
     int nc = (int)P.n_cut_el;
     if (T.n_curves == 0 || nc == 0) return;
     GridDev G{P.dir[0].knots + P.p, P.dir[1].knots + P.p, P.N1, P.N2};  // breakpoints
-    CutArgs A{T, G, nc, P.cut_list, P.ehead, P.arc_next, P.epoch, P.cut_el, P.node_cnt,
+    CutArgs A{T, G, nc, P.cut_list, P.ehead, P.arc_next, P.cut_el, P.node_cnt,
               P.n_r, P.n_q_override, P.n_s, P.p, P.gauss_x, P.gauss_w, P.status, P.node_off, 0, 0};
     const size_t cut0 = (size_t)P.dir[0].Q * P.dir[1].Q + (size_t)P.n_band * (P.p + 1) * (P.p + 1);
     const int prefix_here = nc <= kNodePrefixMax;

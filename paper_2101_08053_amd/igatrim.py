@@ -112,6 +112,7 @@ def lib():
             "iga_batch_info": (C.c_int, [P, C.POINTER(iga_batch_stats)]),
             "iga_batch_status": (C.c_int, [P, V]),
             "iga_plan_set_timing": (C.c_int, [P, C.c_int32]),
+            "iga_plan_set_graph": (C.c_int, [P, C.c_int32]),
             "iga_plan_timings": (C.c_int, [P, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
             "iga_copy": (C.c_int, [V, V, C.c_int64, V]),
             "iga_plan_table": (C.c_int, [P, C.c_int32, C.c_int32, C.POINTER(C.c_void_p), C.POINTER(C.c_int64),
@@ -136,7 +137,7 @@ EXPORTED = ("iga_plan_create", "iga_plan_destroy", "iga_plan_sizes", "iga_plan_p
             "iga_trim_mass_form", "iga_plan_status", "iga_trim_l2_project", "iga_trim_rhs", "iga_mf_apply",
             "iga_mf_adjoint", "iga_trim_mass_form_batched", "iga_batch_create", "iga_batch_destroy",
             "iga_batch_form", "iga_batch_autotune", "iga_batch_info", "iga_batch_status",
-            "iga_plan_set_timing", "iga_plan_timings",
+            "iga_plan_set_timing", "iga_plan_timings", "iga_plan_set_graph",
             "iga_copy", "iga_plan_table", "iga_plan_int_table", "iga_plan_set_weights",
             "iga_plan_set_dwq_weights", "iga_plan_set_cut_nodes", "iga_status_string", "iga_last_error")
 
@@ -305,6 +306,9 @@ class Plan:
 
     def set_timing(self, on=True):
         _check(lib().iga_plan_set_timing(self.h, 1 if on else 0))
+
+    def set_graph(self, on=True):
+        _check(lib().iga_plan_set_graph(self.h, 1 if on else 0))
 
     def timings(self):
         ms = (C.c_double * 4)()

@@ -198,3 +198,44 @@ def test_untrimmed_kronecker():
             if 0 <= j1 < n1 and 0 <= j2 < n2:
                 ref[s, r] = M1[i1, j1] * M2[i2, j2]
     assert np.abs(vals - ref).max() <= 1e-13 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("method", ["HYBRID_GAUSS", "DWQ", "GAUSS_REF"])
+def test_graph_replay_equals_launches(method):
+    """Graph replays of the formation give the kernel-by-kernel result bit for bit.
+
+    Several replays with unrelated torch work and synchronisations between
+    them, a full and a fast call, a new coefficient value (a new recording),
+    and injected weights read by a replay.
+    """
+    require_gpu()
+    import torch
+    from paper_2101_08053_amd import igatrim
+    cfg, o = _oracle("ellipses3_p3_N40")
+    m = getattr(igatrim, method)
+    say(f"[graph] {method}")
+    g = igatrim.Plan(cfg, m)
+    g.set_graph(True)
+    e = igatrim.Plan(cfg, m)
+    shape = (g.sizes["band"], g.sizes["n_act"])
+    out_g = torch.empty(shape, dtype=torch.float64, device="cuda")
+    out_e = torch.empty(shape, dtype=torch.float64, device="cuda")
+    for value, full in ((1.0, True), (1.0, True), (1.0, False), (0.75, True), (0.75, False)):
+        ref = e.mass_form(e.coeff(igatrim.COEF_CONST, value), out=out_e, full=full).clone()
+        for rep in range(3):
+            out_g.fill_(float("nan"))
+            torch.cuda.synchronize()
+            g.mass_form(g.coeff(igatrim.COEF_CONST, value), out=out_g, full=full)
+            junk = torch.randn(4096, device="cuda").sum()  # eager work between replays
+            torch.cuda.synchronize()
+            assert torch.isfinite(junk)
+            assert torch.equal(out_g, ref), f"replay {rep} (c = {value}, full = {full}) differs"
+    g.status()
+    if method != "DWQ":
+        inject_oracle_rules(g, o)
+        inject_oracle_rules(e, o)
+        c = igatrim.COEF_CONST
+        ref = e.mass_form(e.coeff(c, 0.75), out=out_e, full=False)
+        got = g.mass_form(g.coeff(c, 0.75), out=out_g, full=False)
+        torch.cuda.synchronize()
+        assert torch.equal(got, ref)
