@@ -412,6 +412,7 @@ int iga_plan_create(const iga_patch_desc* desc, const iga_opts* opts, iga_plan**
         D.W = P->alloc<double>((size_t)D.n * D.qmax);
         D.WB = P->alloc<double>((size_t)D.n * D.qmax * (2 * p + 1));
         D.WBT = P->alloc<double>((size_t)D.n * (2 * p + 2) * (p + 1));
+        D.WT = P->alloc<double>((size_t)D.n * (2 * p + 2));
         D.xg = P->alloc<double>((size_t)D.N * (p + 1));
         D.wg = P->alloc<double>((size_t)D.N * (p + 1));
         D.Bg = P->alloc<double>((size_t)D.N * (p + 1) * (p + 1));

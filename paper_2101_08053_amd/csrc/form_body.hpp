@@ -329,7 +329,10 @@ struct Int2Smem {
     using C = Int2Cfg<P>;
     static constexpr int KSE = 6 * P + 2;
     union {
-        double sT[C::W][C::KS];
+        struct {
+            double sT[C::W][C::KS];
+            double sB[C::PRE ? C::KS * (P + 1) : 1];  // basis values B[k][al] at the window's points
+        } r;
         struct {
             double sT[C::W][KSE];
             double sG[2 * C::NG][C::QM][C::W];  // w1 B1 rows of the end rows
@@ -433,12 +436,20 @@ __device__ __forceinline__ void interior_rows_block(const IntArgs& A, int tx, in
                 for (int q = 0; q < NR; ++q) cv[C::PRE ? j : 0][q] = A.c.value;
         }
     }
-    double wb[C::PRE ? NR : 1][P + 1];
-    if (C::PRE && !endtile && i1 >= 0) {  // from the banded copy: consecutive rows, consecutive addresses
+    // A regular row's factors w1 B1 (the banded copy's values) are formed
+    // in registers from its weights (rows contiguous) and the window's basis
+    // values (staged once per workgroup): one product each, as in the table.
+    double wt[C::PRE ? NR : 1];
+    if (C::PRE && !endtile && i1 >= 0) {
 #pragma unroll
-        for (int q = 0; q < NR; ++q)
+        for (int q = 0; q < NR; ++q) wt[C::PRE ? q : 0] = D1.WT[(size_t)q * D1.n + i1];
+    }
+    constexpr int NBQ = C::PRE ? (C::KS * (P + 1) + NT - 1) / NT : 1;
+    double bq[NBQ];
+    const int nbq = ks * (P + 1);
+    if (C::PRE && !endtile) {
 #pragma unroll
-            for (int al = 0; al <= P; ++al) wb[C::PRE ? q : 0][al] = D1.WBT[((size_t)q * (P + 1) + al) * D1.n + i1];
+        for (int u = 0; u < NBQ; ++u) bq[u] = D1.Bq[(size_t)wlo1 * (P + 1) + min(tid + NT * u, nbq - 1)];
     }
     if (endtile) {  // the end rows' full w1 B1 rows, in batches of independent loads
         constexpr int NGT = 2 * NG * QM * W, NBAT = 16;
@@ -466,10 +477,15 @@ __device__ __forceinline__ void interior_rows_block(const IntArgs& A, int tx, in
         const int t = tid + NT * u;
         if (t < QM * W) S.sWB2[t / W][t % W] = wb2[u];
     }
+    if (C::PRE && !endtile) {
+#pragma unroll
+        for (int u = 0; u < NBQ; ++u)
+            if (tid + NT * u < nbq) S.r.sB[tid + NT * u] = bq[u];
+    }
     if (!__syncthreads_or(live)) return;  // no row of the workgroup is formed here
 
     // ---- stage 1: contract xi_2 for every xi_1 point of the window
-    double* sTb = endtile ? &S.e.sT[0][0] : &S.sT[0][0];
+    double* sTb = endtile ? &S.e.sT[0][0] : &S.r.sT[0][0];
     const int kst = endtile ? Int2Smem<P>::KSE : C::KS;
 #pragma unroll
     for (int j = 0; j < NJ; ++j) {
@@ -526,14 +542,22 @@ __device__ __forceinline__ void interior_rows_block(const IntArgs& A, int tx, in
     // ---- stage 2: contract xi_1
     if (!endtile) {  // this thread's columns of its row
         const int k0 = kloc(wq_pt0(max(0, i1 - P), D1.N, P));  // the row's first support point
+        double wb[C::PRE ? NR : 1][P + 1];
+        if (C::PRE) {
+#pragma unroll
+            for (int q = 0; q < NR; ++q)
+#pragma unroll
+                for (int al = 0; al <= P; ++al)
+                    wb[C::PRE ? q : 0][al] = wt[C::PRE ? q : 0] * S.r.sB[(k0 + q) * (P + 1) + al];
+        }
 #pragma unroll 1
         for (int b = grp; b < W; b += NB) {
             double acc[W];
             if constexpr (C::PRE)
-                interior_col_reg<P>([&](int q, int al) { return wb[q][al]; }, &S.sT[b][k0], acc);
+                interior_col_reg<P>([&](int q, int al) { return wb[q][al]; }, &S.r.sT[b][k0], acc);
             else
                 interior_col_reg<P>([&](int q, int al) { return D1.WBT[((size_t)q * (P + 1) + al) * D1.n + i1]; },
-                                    &S.sT[b][k0], acc);
+                                    &S.r.sT[b][k0], acc);
 #pragma unroll
             for (int a = 0; a < W; ++a) A.vals[(size_t)(a * W + b) * A.n_act + cid] = acc[a];
         }

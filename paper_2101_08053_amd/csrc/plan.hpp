@@ -37,6 +37,7 @@ struct DirDev {
     double* W;            // n*qmax weights, point k0(i)+q with k0(i) = pt0[max(0,i-p)]
     double* WB;           // n*qmax*(2p+1): W[i][q] * B_{i+b-p}(x_{k0(i)+q}) (0 off the element)
     double* WBT;          // (2p+2)*(p+1)*n: WB[i][q][(q>>1)+al] at [(q*(p+1)+al)*n + i] (the band, rows contiguous)
+    double* WT;           // (2p+2)*n: W[i][q] at [q*n + i] (rows contiguous; 0 past the row's points)
     double* xg;           // N*(p+1) Gauss points
     double* wg;           // N*(p+1) Gauss weights
     double* Bg;           // N*(p+1)*(p+1) [e][g][a]

@@ -209,6 +209,7 @@ __global__ void __launch_bounds__(64) k_wq_weights(DirDev D1, DirDev D2, const d
     }
     if (lane < D.qmax) {
         D.W[(size_t)i * D.qmax + lane] = y;
+        if (lane < 2 * P + 2) D.WT[(size_t)lane * D.n + i] = (lane < q) ? y : 0.0;
         // WB row q = lane: w_q B_{i+b-p}(x_q), zero where B_{i+b-p} vanishes on the point's element
         double* wb = D.WB + ((size_t)i * D.qmax + lane) * M;
 #pragma unroll
@@ -242,6 +243,7 @@ __global__ void k_wb_table(DirDev D, int p) {
         if (loc >= 0 && loc <= p) v = D.W[(size_t)i * D.qmax + q] * D.Bq[(size_t)k * (p + 1) + loc];
     }
     D.WB[t] = v;
+    if (b == 0 && q < 2 * p + 2) D.WT[(size_t)q * D.n + i] = (q < q_i) ? D.W[(size_t)i * D.qmax + q] : 0.0;
     const int al = b - (q >> 1);  // the banded copy, rows contiguous (points of a regular row)
     if (q < 2 * p + 2 && al >= 0 && al <= p) D.WBT[((size_t)q * (p + 1) + al) * D.n + i] = v;
 }
