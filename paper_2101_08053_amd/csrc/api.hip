@@ -227,6 +227,7 @@ static void form(Plan& P, const iga_coeff& c, double* vals, int flags, hipStream
         return;
     }
     const bool full = (flags & IGA_FORM_FULL) != 0;
+    const bool pts_by_coef = full && c.kind == IGA_COEF_GEOM_DETJ;  // the |det J| kernels write the rule points
     hipStream_t a = P.aux;
     // aux stream: univariate tables and weights, c on the WQ grid and the band
     // Gauss points, the inside sums of the rows formed element-wise, interior
@@ -238,7 +239,7 @@ static void form(Plan& P, const iga_coeff& c, double* vals, int flags, hipStream
     if (full) setup_tables(P, a);
     {
         PhaseTimer t(P, a, IGA_PHASE_COEF);
-        launch_coef(P, c, a, 1);
+        launch_coef(P, c, a, 1, pts_by_coef);
     }
     if (full) {
         PhaseTimer t(P, s, IGA_PHASE_SETUP);
@@ -249,7 +250,7 @@ static void form(Plan& P, const iga_coeff& c, double* vals, int flags, hipStream
     HIPX(hipStreamWaitEvent(a, P.ev_lists, 0));
     {
         PhaseTimer t(P, a, IGA_PHASE_CUT);
-        launch_coef(P, c, a, 3);
+        launch_coef(P, c, a, 3, pts_by_coef);
         launch_cut_rows_mode(P, c, vals, a, 1);  // rows formed element-wise: their inside sums
     }
     HIPX(hipEventRecord(P.ev_band, a));
@@ -268,7 +269,7 @@ static void form(Plan& P, const iga_coeff& c, double* vals, int flags, hipStream
     } else {
         launch_interior_rows(P, c, vals, a);
     }
-    if (full) launch_points(P, a);
+    if (full && !pts_by_coef) launch_points(P, a);
     HIPX(hipEventRecord(P.ev_interior, a));
     if (P.timing) HIPX(hipStreamWaitEvent(s, P.ev_interior, 0));
     {

@@ -89,12 +89,13 @@ CoefView coef_view(Plan& P, const iga_coeff& c) {
 CoefArgs coef_args(Plan& P, const iga_coeff& c) {
     return CoefArgs{P.dir[0], P.dir[1], c.geom_cp, P.n1, P.band_list, (int)P.n_band, P.cut_list, P.node_el,
                     P.node_x, P.node_y, (int)P.n_nodes, P.c_wq, P.c_band, P.c_cut,
-                    (int64_t)P.dir[0].Q * P.dir[1].Q, (int64_t)P.n_band * (P.p + 1) * (P.p + 1)};
+                    (int64_t)P.dir[0].Q * P.dir[1].Q, (int64_t)P.n_band * (P.p + 1) * (P.p + 1), nullptr};
 }
 
-void launch_coef(Plan& P, const iga_coeff& c, hipStream_t s, int part) {
+void launch_coef(Plan& P, const iga_coeff& c, hipStream_t s, int part, bool with_points) {
     if (c.kind != IGA_COEF_GEOM_DETJ) return;
     CoefArgs A = coef_args(P, c);
+    if (with_points) A.xy = P.pts_xy;
     // part 0: every rule point; 1: the WQ grid; 2: band Gauss points and cut nodes; 3: band; 4: cut nodes
     const int64_t t0 = (part == 2 || part == 3) ? A.nq : (part == 4 ? A.nq + A.nb : 0);
     const int64_t t1 = (part == 1) ? A.nq : (part == 3 ? A.nq + A.nb : A.nq + A.nb + A.n_nodes);

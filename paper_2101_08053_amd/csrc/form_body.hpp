@@ -20,6 +20,7 @@ struct CoefArgs {
     int n_nodes;
     double *c_wq, *c_band, *c_cut;
     int64_t nq, nb;           // WQ grid points, band Gauss points
+    double* xy;               // if set: the grid and band points' coordinates go to the rule-point table too
 };
 
 CoefArgs coef_args(Plan& P, const iga_coeff& c);
@@ -33,6 +34,10 @@ __device__ __forceinline__ void coef_point(const CoefArgs& A, int64_t t) {
         const int k1 = (int)(t % D1.Q), k2 = (int)(t / D1.Q);
         A.c_wq[t] = detj_local(A.cp, A.n1, P, D1.eq[k1], D2.eq[k2], D1.Bq + k1 * (P + 1), D1.dBq + k1 * (P + 1),
                                D2.Bq + k2 * (P + 1), D2.dBq + k2 * (P + 1));
+        if (A.xy) {
+            A.xy[2 * t] = D1.xq[k1];
+            A.xy[2 * t + 1] = D2.xq[k2];
+        }
     } else if (t < A.nq + A.nb) {
         constexpr int ng = (P + 1) * (P + 1);
         const int64_t u = t - A.nq;
@@ -40,6 +45,10 @@ __device__ __forceinline__ void coef_point(const CoefArgs& A, int64_t t) {
         const int e = A.band_list[b], e1 = e % D1.N, e2 = e / D1.N;
         const int r1 = (e1 * (P + 1) + g1) * (P + 1), r2 = (e2 * (P + 1) + g2) * (P + 1);
         A.c_band[u] = detj_local(A.cp, A.n1, P, e1, e2, D1.Bg + r1, D1.dBg + r1, D2.Bg + r2, D2.dBg + r2);
+        if (A.xy) {
+            A.xy[2 * t] = D1.xg[e1 * (P + 1) + g1];
+            A.xy[2 * t + 1] = D2.xg[e2 * (P + 1) + g2];
+        }
     } else if (t < A.nq + A.nb + A.n_nodes) {
         const int64_t u = t - A.nq - A.nb;
         const int e = A.cut_list[A.node_el[u]], e1 = e % D1.N, e2 = e / D1.N;

@@ -298,7 +298,9 @@ void launch_row_nnz(Plan& P, int* cnt, int* out, hipStream_t s);
 CoefView coef_view(Plan& P, const iga_coeff& c);
 // rule-point coordinates: WQ grid and band Gauss points (and the cut nodes with with_nodes)
 void launch_points(Plan& P, hipStream_t s, bool with_nodes = false);
-void launch_coef(Plan& P, const iga_coeff& c, hipStream_t s, int part = 0);
+// part 0: every rule point, 1: WQ grid, 2: band and cut nodes, 3: band, 4: cut nodes; with_points: the
+// grid and band points' coordinates are written to the rule-point table as well (|det J| only)
+void launch_coef(Plan& P, const iga_coeff& c, hipStream_t s, int part = 0, bool with_points = false);
 // t0 / t1 (optional): events recorded at the start and end of the kernel's execution
 void launch_interior_rows(Plan& P, const iga_coeff& c, double* vals, hipStream_t s, hipEvent_t t0 = nullptr,
                           hipEvent_t t1 = nullptr);

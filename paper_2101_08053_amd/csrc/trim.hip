@@ -839,14 +839,9 @@ void launch_trim_arcs(Plan& P, hipStream_t s) {
 // its piece's largest x lie right of the point, as in inside_curve); ellipses
 // use their implicit function. Rows with more crossings than recorded fall
 // back to the direct test.
-__global__ void k_elem_centre(TrimDev T, GridDev G, const int* __restrict__ emark, int8_t* __restrict__ ecls) {
-    int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= G.N1 * G.N2) return;
-    if (emark[e] == *T.epoch) {
-        ecls[e] = EL_CUT;
-        return;
-    }
-    int e1 = e % G.N1, e2 = e / G.N1;
+__device__ int8_t elem_class(const TrimDev& T, const GridDev& G, const int* __restrict__ emark, int epoch, int e1,
+                             int e2) {
+    if (emark[e2 * G.N1 + e1] == epoch) return EL_CUT;
     double x = 0.5 * (G.bp1[e1] + G.bp1[e1 + 1]), y = 0.5 * (G.bp2[e2] + G.bp2[e2 + 1]);
     bool out = false;
     if (T.n_curves > 0) {
@@ -864,12 +859,15 @@ __global__ void k_elem_centre(TrimDev T, GridDev G, const int* __restrict__ emar
             }
         }
     }
-    ecls[e] = out ? EL_OUTSIDE : EL_INSIDE;
+    return out ? EL_OUTSIDE : EL_INSIDE;
 }
 
 struct ClassArgs {
     int p, N1, N2, n1, n2, method;
-    const int8_t* ecls;
+    TrimDev T;
+    GridDev G;
+    const int* emark;
+    int8_t* ecls;
     int8_t* fcls;
     int* f_active;   // n1*n2 flags
     int* f_cut;      // n1*n2 flags
@@ -878,7 +876,8 @@ struct ClassArgs {
 };
 
 // Function classes and element flags on 16 x 16 tiles of elements. The
-// tile's element classes with a halo of p on each side are staged in LDS;
+// tile's element classes with a halo of p on each side are found in LDS
+// (each workgroup classifies its halo too, and writes its own elements');
 // from them the classes of the functions [x0, x0 + 16 + p) x [y0, ...)
 // (Sect. 2.2: exterior if every support element is outside, interior if
 // every one is inside, cut otherwise), and from those the tile's element
@@ -894,10 +893,16 @@ __global__ void __launch_bounds__(256) k_classes(ClassArgs A) {
     const int p = A.p, tid = threadIdx.x;
     const int x0 = blockIdx.x * kClsTile, y0 = blockIdx.y * kClsTile;
     const int we = kClsTile + 2 * p, wf = kClsTile + p;
+    const int epoch = *A.T.epoch;
     for (int t = tid; t < we * we; t += 256) {
         const int u = t % we, v = t / we;
         const int ex = x0 - p + u, ey = y0 - p + v;
-        sE[v][u] = (ex >= 0 && ex < A.N1 && ey >= 0 && ey < A.N2) ? A.ecls[ey * A.N1 + ex] : (int8_t)-1;
+        int8_t c = -1;
+        if (ex >= 0 && ex < A.N1 && ey >= 0 && ey < A.N2) {
+            c = elem_class(A.T, A.G, A.emark, epoch, ex, ey);
+            if (u >= p && u < p + kClsTile && v >= p && v < p + kClsTile) A.ecls[ey * A.N1 + ex] = c;
+        }
+        sE[v][u] = c;
     }
     __syncthreads();
     const bool lastx = blockIdx.x == gridDim.x - 1, lasty = blockIdx.y == gridDim.y - 1;
@@ -946,13 +951,12 @@ void launch_trim_classes(Plan& P, hipStream_t s) {
     TrimDev& T = P.trim;
     GridDev G{P.dir[0].knots + P.p, P.dir[1].knots + P.p, P.N1, P.N2};  // breakpoints
     int ne = P.N1 * P.N2;
-    hipLaunchKernelGGL(k_elem_centre, dim3((ne + 127) / 128), dim3(128), 0, s, T, G, P.emark, P.ecls);
     int nf = P.n1 * P.n2;
     int* f_active = P.flags;
     int* f_cut = P.flags + (nf + 1);
     int* e_cut = P.flags + 2 * (nf + 1);
     int* e_band = e_cut + (ne + 1);
-    ClassArgs A{P.p, P.N1, P.N2, P.n1, P.n2, P.method, P.ecls, P.fcls, f_active, f_cut, e_cut, e_band};
+    ClassArgs A{P.p, P.N1, P.N2, P.n1, P.n2, P.method, T, G, P.emark, P.ecls, P.fcls, f_active, f_cut, e_cut, e_band};
     dim3 g((P.N1 + kClsTile - 1) / kClsTile, (P.N2 + kClsTile - 1) / kClsTile);
     hipLaunchKernelGGL(k_classes, g, dim3(256), 0, s, A);
 }

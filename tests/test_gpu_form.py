@@ -239,3 +239,25 @@ def test_graph_replay_equals_launches(method):
         got = g.mass_form(g.coeff(c, 0.75), out=out_g, full=False)
         torch.cuda.synchronize()
         assert torch.equal(got, ref)
+
+
+def test_points_rewritten_by_full_formation():
+    """A full formation rewrites the rule-point table (by the |det J| kernels, or the point kernel
+    for other coefficients) with the values plan creation wrote."""
+    require_gpu()
+    import torch
+    from paper_2101_08053_amd import igatrim
+    cfg, _ = _oracle("cubic16_p4_N80")
+    plan = igatrim.Plan(cfg, igatrim.HYBRID_GAUSS)
+    p0 = plan.points().clone()
+    for coef in (plan.coeff(igatrim.COEF_GEOM_DETJ), plan.coeff(igatrim.COEF_CONST, 1.0)):
+        # clobber the table so that only the formation can restore it
+        n = p0.numel()
+        junk = torch.full((n,), float("nan"), dtype=torch.float64, device="cuda")
+        import ctypes as C
+        ptr, cnt = C.c_void_p(), C.c_int64()
+        igatrim._check(igatrim.lib().iga_plan_points(plan.h, C.byref(ptr), C.byref(cnt)))
+        igatrim._check(igatrim.lib().iga_copy(ptr, igatrim._dptr(junk), 8 * n, igatrim._stream()))
+        plan.mass_form(coef, full=True)
+        torch.cuda.synchronize()
+        assert torch.equal(plan.points(), p0)
