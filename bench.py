@@ -59,12 +59,21 @@ def _timed(fn, steps, warmup, sync):
     return 1e3 * (time.perf_counter() - t0) / steps
 
 
-def _source_digest(paths):
+def _source_digest(sections):
+    """Hash of the kernel's source: for each (file, title), the lines from the `// ---- title`
+    section rule to the next rule (the whole file if title is None)."""
     import hashlib
     h = hashlib.sha256()
-    for p in paths:
-        with open(os.path.join(ROOT, p), "rb") as fh:
-            h.update(fh.read())
+    for p, title in sections:
+        with open(os.path.join(ROOT, p)) as fh:
+            lines = fh.read().splitlines(True)
+        if title is not None:
+            start = [i for i, ln in enumerate(lines) if ln.startswith("// ---") and ln.rstrip().endswith(title)]
+            if len(start) != 1:
+                return None
+            end = next((j for j in range(start[0] + 1, len(lines)) if lines[j].startswith("// ---")), len(lines))
+            lines = lines[start[0]:end]
+        h.update("".join(lines).encode())
     return h.hexdigest()[:16]
 
 
@@ -137,7 +146,9 @@ def _cpu_baseline(Oracle, np, cfg, nnz_total, n_act, sample_rows):
                       f"+ {k_cut} cut rows of the same workload ({nnz_sample} nnz in {t_rows:.1f} s)"}
 
 
-INTERIOR_SOURCES = ["paper_2101_08053_amd/csrc/form_body.hpp", "paper_2101_08053_amd/csrc/form.hip"]
+INTERIOR_SOURCES = [("paper_2101_08053_amd/csrc/form_body.hpp", "interior rows"),
+                    ("paper_2101_08053_amd/csrc/form.hip", "interior rows"),
+                    ("paper_2101_08053_amd/csrc/common.hpp", None)]
 
 
 def main():
@@ -280,6 +291,7 @@ def bench_batched(igatrim, wl, args, sync):
             "plain_ms": ms_plain, "plain_value": nnz / (ms_plain * 1e-3), "speedup_vs_plain": ms_plain / ms_graph,
             "patches": len(plans), "nnz": nnz, "items": info["n_items"], "grid": info["grid"],
             "wg_per_cu": info["wg_per_cu"], "chunk": info["chunk"],
+            "registers": "256 (two workgroups per CU)" if info["capped"] else "up to 512 (one workgroup per CU)",
             "order": ["cost-sorted", "patch by patch"][info["order"]],
             "autotune_best_ms": tune_ms, "plan_setup_s": round(t_plan, 2),
             "note": "formation over resident tables, one persistent launch per call (graph replay) vs one "

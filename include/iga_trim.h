@@ -254,17 +254,20 @@ typedef struct iga_batch_stats {
     int32_t order;        /* 0: cost-sorted queue, 1: patch by patch    */
     int32_t graph_ready;  /* a recorded graph is cached                 */
     int32_t chunk;        /* queue items reserved per atomic (autotuned) */
-    int32_t reserved;
+    int32_t capped;       /* 1: kernel built for 256 registers (two workgroups per CU), 0: for one
+                             workgroup per CU (autotuned) */
 } iga_batch_stats;
 int iga_batch_create(iga_plan* const* plans, int32_t count, const iga_coeff* cs, double* const* vals,
                      iga_batch** out);
 void iga_batch_destroy(iga_batch* batch);
 /* Enqueues the batched formation on stream (graph replay with use_graph). */
 int iga_batch_form(iga_batch* batch, int32_t use_graph, void* stream);
-/* Autotuner: times the persistent grid (1..4 workgroups per compute unit),
- * the queue chunk (4, 16, 64 items per atomic) and the two queue orders on the device (3 timed runs each, stream
- * synchronised), keeps the fastest and drops a cached graph; *best_ms
- * (may be NULL) receives its time. */
+/* Autotuner: times the persistent grid (1, 2, 4, 8, 12 or 16 workgroups per
+ * compute unit, more than fit at once allowed), the kernel's register budget (two
+ * builds), the queue chunk (4, 16, 64 items per atomic) and the two queue
+ * orders on the device (3 timed runs each, stream synchronised), keeps the
+ * fastest and drops a cached graph; *best_ms (may be NULL) receives its
+ * time. */
 int iga_batch_autotune(iga_batch* batch, void* stream, float* best_ms);
 int iga_batch_info(const iga_batch* batch, iga_batch_stats* st);
 /* Synchronises stream; IGA_E_INVALID if a dependency wait hit its bound

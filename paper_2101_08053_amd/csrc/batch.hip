@@ -172,7 +172,11 @@ __device__ __forceinline__ void batch_loop(const BatchDev& B, int g, unsigned ch
     }
 }
 
-__global__ void __launch_bounds__(256, 2) k_batch(BatchDev B) {  // at most 256 VGPRs: two workgroups per CU
+// Two register budgets, chosen by the autotuner: MINW = 1 lets the largest
+// body keep everything in registers (one workgroup per CU), MINW = 2 caps
+// them at 256 so that two workgroups share a CU (a few values spill).
+template <int MINW>
+__global__ void __launch_bounds__(256, MINW) k_batch(BatchDev B) {
     __shared__ __align__(16) unsigned char smem[batch_smem_max<kBatchMaxP>()];
     __shared__ int s_sh[3];
     int g = 0;
@@ -201,8 +205,9 @@ struct Batch {
     int* d_counters = nullptr;  // status, heads[kBatchGroups], level counters[kBatchGroups][2]
     int n_items = 0;
     int n_cu = 256;
-    int max_wg_per_cu = 4;  // workgroups of k_batch that fit on one CU at once
+    int max_wg_per_cu = 16;  // largest grid the autotuner tries, in workgroups per CU
     int wg_per_cu = 2;
+    int capped = 1;  // k_batch<2> (256 registers) rather than k_batch<1>
     int order = 0;  // 0 cost-sorted, 1 patch by patch
     int chunk = 16; // queue items reserved per atomic
     hipGraph_t graph = nullptr;
@@ -267,7 +272,10 @@ struct Batch {
             B.n_level[g][0] = g_lvl[g][0];
             B.n_level[g][1] = g_lvl[g][1];
         }
-        if (total > 0) hipLaunchKernelGGL(k_batch, dim3(total), dim3(256), 0, s, B);
+        if (total > 0) {
+            if (capped) hipLaunchKernelGGL(k_batch<2>, dim3(total), dim3(256), 0, s, B);
+            else hipLaunchKernelGGL(k_batch<1>, dim3(total), dim3(256), 0, s, B);
+        }
     }
 };
 
@@ -293,11 +301,10 @@ static iga_batch* batch_create(iga_plan* const* plans, int count, const iga_coef
     int dev = 0;
     HIPX(hipGetDevice(&dev));
     HIPX(hipDeviceGetAttribute(&B->n_cu, hipDeviceAttributeMultiprocessorCount, dev));
-    // a persistent grid larger than what fits at once only queues workgroups behind the resident ones
-    int fit = 0;
-    HIPX(hipOccupancyMaxActiveBlocksPerMultiprocessor(&fit, k_batch, 256, 0));
-    B->max_wg_per_cu = std::max(1, std::min(4, fit));
-    B->wg_per_cu = std::min(B->wg_per_cu, B->max_wg_per_cu);
+    // A grid larger than what fits at once is allowed: workgroups past the
+    // resident ones start as those finish, and each degree's share of the
+    // grid then keeps more of its items in flight (measured faster). Only
+    // resident workgroups ever hold items, so the dependency waits still end.
     HIPX(hipStreamCreate(&B->cap_stream));
     std::vector<BatchPlan> hp(count);
     struct Cand {
@@ -391,19 +398,23 @@ static void batch_form(Batch& B, int use_graph, hipStream_t s) {
     HIPX(hipGraphLaunch(B.exec, s));
 }
 
-// Times every (workgroups per CU, queue chunk, item order) choice on the device, keeps the fastest.
+// Times every (register budget, workgroups per CU, queue chunk, item order) choice on the device,
+// keeps the fastest.
 static void batch_autotune(Batch& B, hipStream_t s, float* best_ms) {
     hipEvent_t a, b;
     HIPX(hipEventCreate(&a));
     HIPX(hipEventCreate(&b));
     float best = 1e30f;
     int bw = B.wg_per_cu, bo = B.order;
-    int bc = B.chunk;
+    int bc = B.chunk, bcap = B.capped;
     for (int order = 0; order < 2; ++order) {
         B.order = order;
         B.upload_items(s);
+        for (int cap = 0; cap < 2; ++cap)
         for (int cidx = 0; cidx < 3; ++cidx)
-        for (int w = 1; w <= B.max_wg_per_cu; ++w) {
+        for (int w : {1, 2, 4, 8, 12, 16}) {
+            if (w > B.max_wg_per_cu) break;
+            B.capped = cap;
             B.chunk = (cidx == 0) ? 4 : (cidx == 1 ? 16 : 64);
             B.wg_per_cu = w;
             B.launch(s);  // warm-up
@@ -422,6 +433,7 @@ static void batch_autotune(Batch& B, hipStream_t s, float* best_ms) {
                 bw = w;
                 bo = order;
                 bc = B.chunk;
+                bcap = cap;
             }
         }
     }
@@ -430,6 +442,7 @@ static void batch_autotune(Batch& B, hipStream_t s, float* best_ms) {
     B.wg_per_cu = bw;
     B.order = bo;
     B.chunk = bc;
+    B.capped = bcap;
     B.upload_items(s);
     B.drop_graph();
     if (best_ms) *best_ms = best;
@@ -492,6 +505,7 @@ int iga_batch_info(const iga_batch* b, iga_batch_stats* st) {
     st->grid = b->grid();
     st->wg_per_cu = b->wg_per_cu;
     st->order = b->order;
+    st->capped = b->capped;
     st->chunk = b->chunk;
     st->graph_ready = b->exec != nullptr;
     API_CATCH

@@ -134,16 +134,29 @@ __device__ __forceinline__ void interior_col_reg(WBF wbf, const double* Tk, doub
 
 // A row touching the first or last element: its q1 support points, full
 // factor rows wb[q][a] = (w1 B1) at point q for column a.
+// The factors are read a few points at a time before they are used (they
+// may come from global memory); the sums run over q in order either way.
 template <int P>
 __device__ __forceinline__ void interior_col_end(const double* wb, const double* Tk, int q1, double* acc) {
-    constexpr int W = 2 * P + 1;
+    constexpr int W = 2 * P + 1, QB = 2;
 #pragma unroll
     for (int a = 0; a < W; ++a) acc[a] = 0.0;
 #pragma unroll 1
-    for (int q = 0; q < q1; ++q) {
-        const double t = Tk[q];
+    for (int q0 = 0; q0 < q1; q0 += QB) {
+        double f[QB][W], t[QB];
 #pragma unroll
-        for (int a = 0; a < W; ++a) acc[a] += wb[q * W + a] * t;
+        for (int u = 0; u < QB; ++u) {
+            const int q = min(q0 + u, q1 - 1);
+            t[u] = Tk[q];
+#pragma unroll
+            for (int a = 0; a < W; ++a) f[u][a] = wb[q * W + a];
+        }
+#pragma unroll
+        for (int u = 0; u < QB; ++u) {
+            if (q0 + u >= q1) break;
+#pragma unroll
+            for (int a = 0; a < W; ++a) acc[a] += f[u][a] * t[u];
+        }
     }
 }
 

@@ -69,7 +69,7 @@ class iga_target(C.Structure):
 class iga_batch_stats(C.Structure):
     _fields_ = [("n_plans", C.c_int64), ("n_items", C.c_int64), ("nnz", C.c_int64), ("grid", C.c_int32),
                 ("wg_per_cu", C.c_int32), ("order", C.c_int32), ("graph_ready", C.c_int32),
-                ("chunk", C.c_int32), ("reserved", C.c_int32)]
+                ("chunk", C.c_int32), ("capped", C.c_int32)]
 
 
 class iga_solve_info(C.Structure):
