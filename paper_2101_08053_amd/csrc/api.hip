@@ -76,7 +76,8 @@ static void setup_tables(Plan& P, hipStream_t s) {
 // Trimming, classes, lists, cut rules and (with `points`) the grid and band
 // entries of the rule-point table. The trimming reads the knots directly;
 // only the rule points read the univariate tables.
-static void setup_trim(Plan& P, hipStream_t s, bool discover, bool points);
+// part 0: all of it; 1: up to the lists (and DWQ boxes), then ev_lists; 2: the cut rules and points.
+static void setup_trim(Plan& P, hipStream_t s, bool discover, bool points, int part = 0);
 
 static void run_setup(Plan& P, hipStream_t s, bool discover) {
     if (discover) launch_gauss_table(P, s);  // a constant table: once per plan
@@ -84,38 +85,41 @@ static void run_setup(Plan& P, hipStream_t s, bool discover) {
     setup_trim(P, s, discover, true);
 }
 
-static void setup_trim(Plan& P, hipStream_t s, bool discover, bool points) {
+static void setup_trim(Plan& P, hipStream_t s, bool discover, bool points, int part) {
     TrimDev& T = P.trim;
-    if (T.n_curves > 0) {
-        launch_trim_curves(P, s);
-        if (discover) {  // one slot of arcs per piece, as many as the most crossings of a piece + 1
-            T.arc_slot = trim_max_crossings(P, s) + 1;
-            T.cap_arcs = std::max(T.cap_pieces, 1) * T.arc_slot;
-            T.cross = P.alloc<CrossDev>(T.cap_arcs);
-            T.merged = P.alloc<CrossDev>(T.cap_arcs);
-            T.arcs = P.alloc<ArcDev>(T.cap_arcs);
-            P.arc_next = P.alloc<int>(T.cap_arcs);
+    if (part != 2) {
+        if (T.n_curves > 0) {
+            launch_trim_curves(P, s);
+            if (discover) {  // one slot of arcs per piece, as many as the most crossings of a piece + 1
+                T.arc_slot = trim_max_crossings(P, s) + 1;
+                T.cap_arcs = std::max(T.cap_pieces, 1) * T.arc_slot;
+                T.cross = P.alloc<CrossDev>(T.cap_arcs);
+                T.merged = P.alloc<CrossDev>(T.cap_arcs);
+                T.arcs = P.alloc<ArcDev>(T.cap_arcs);
+                P.arc_next = P.alloc<int>(T.cap_arcs);
+            }
+            launch_trim_arcs(P, s);
         }
-        launch_trim_arcs(P, s);
+        launch_trim_classes(P, s);
+        launch_trim_lists(P, s);
+        if (discover) {
+            int c[4];
+            HIPX(hipMemcpyAsync(c, P.counts, 4 * sizeof(int), hipMemcpyDeviceToHost, s));
+            HIPX(hipStreamSynchronize(s));
+            P.n_act = c[0];
+            P.n_form_rows = c[1];
+            P.n_cut_el = c[2];
+            P.n_band = c[3];
+            int nc = (int)P.n_cut_el;
+            P.cut_el = P.alloc<CutElemDev>(std::max(nc, 1));
+            P.node_cnt = P.alloc<int>(nc + 1);
+            P.node_off = P.alloc<int>(nc + 1);
+            if (P.method == IGA_DWQ) P.dwq_region = P.alloc<int>(8 * (size_t)std::max<int64_t>(P.n_form_rows, 1));
+        }
+        launch_dwq_choose(P, s);
+        HIPX(hipEventRecord(P.ev_lists, s));  // classes, compact maps and DWQ boxes are ready
     }
-    launch_trim_classes(P, s);
-    launch_trim_lists(P, s);
-    if (discover) {
-        int c[4];
-        HIPX(hipMemcpyAsync(c, P.counts, 4 * sizeof(int), hipMemcpyDeviceToHost, s));
-        HIPX(hipStreamSynchronize(s));
-        P.n_act = c[0];
-        P.n_form_rows = c[1];
-        P.n_cut_el = c[2];
-        P.n_band = c[3];
-        int nc = (int)P.n_cut_el;
-        P.cut_el = P.alloc<CutElemDev>(std::max(nc, 1));
-        P.node_cnt = P.alloc<int>(nc + 1);
-        P.node_off = P.alloc<int>(nc + 1);
-        if (P.method == IGA_DWQ) P.dwq_region = P.alloc<int>(8 * (size_t)std::max<int64_t>(P.n_form_rows, 1));
-    }
-    launch_dwq_choose(P, s);
-    HIPX(hipEventRecord(P.ev_lists, s));  // classes, compact maps and DWQ boxes are ready
+    if (part == 1) return;
     launch_trim_cutprep(P, s);
     if (discover) {
         // node offsets are formed with the nodes; their total is needed to size the buffers first
@@ -234,7 +238,17 @@ static void form(Plan& P, const iga_coeff& c, double* vals, int flags, hipStream
     // rows, rule points; the caller's stream: trimming, classes, lists, cut
     // rules, cut element matrices (with c at the cut nodes) and their entries
     // in the rows formed element-wise.
+    // Enqueued in the order the critical caller's stream needs them: the host
+    // spends about as long enqueuing a formation as the device takes to run
+    // it, so the trimming chain goes first, the cut rules right after the
+    // auxiliary stream's first kernels.
     HIPX(hipEventRecord(P.ev_fork, s));
+    if (full) {
+        PhaseTimer t(P, s, IGA_PHASE_SETUP);
+        setup_trim(P, s, false, false, 1);
+    } else {
+        HIPX(hipEventRecord(P.ev_lists, s));
+    }
     HIPX(hipStreamWaitEvent(a, P.ev_fork, 0));
     if (full) setup_tables(P, a);
     {
@@ -243,9 +257,7 @@ static void form(Plan& P, const iga_coeff& c, double* vals, int flags, hipStream
     }
     if (full) {
         PhaseTimer t(P, s, IGA_PHASE_SETUP);
-        setup_trim(P, s, false, false);
-    } else {
-        HIPX(hipEventRecord(P.ev_lists, s));
+        setup_trim(P, s, false, false, 2);
     }
     HIPX(hipStreamWaitEvent(a, P.ev_lists, 0));
     {
