@@ -536,6 +536,7 @@ int iga_plan_create(const iga_patch_desc* desc, const iga_opts* opts, iga_plan**
     P->fn_of = P->alloc<int>(nf);
     P->form_rows = P->alloc<int>(nf);
     P->flags = P->alloc<int>(2 * (size_t)(nf + 1) + 2 * (size_t)(ne + 1));
+    P->list_rcnt = P->alloc<int>(4 * (size_t)P->n2 * ((P->N1 + 15) / 16));
     int big = std::max(std::max(nf, ne), T.cap_pieces) + 2;
     P->scan_pos_off = ((big + 1023) / 1024 + 64 + 63) / 64 * 64;  // block sums first, then positions
     P->scan_tmp = P->alloc<int>((size_t)P->scan_pos_off + (size_t)big);

@@ -189,6 +189,7 @@ struct Plan {
 
     // scratch for scans and counts
     int* flags = nullptr;          // max(n1*n2, N1*N2) + 1
+    int* list_rcnt = nullptr;      // [4][n2][tiles along xi_1] flags set per row segment of a class tile
     int* scan_tmp = nullptr;       // block sums of a scan, then compaction positions
     int scan_pos_off = 0;
     int* counts = nullptr;         // small device counter block

@@ -839,34 +839,12 @@ void launch_trim_arcs(Plan& P, hipStream_t s) {
 // its piece's largest x lie right of the point, as in inside_curve); ellipses
 // use their implicit function. Rows with more crossings than recorded fall
 // back to the direct test.
-__device__ int8_t elem_class(const TrimDev& T, const GridDev& G, const int* __restrict__ emark, int epoch, int e1,
-                             int e2) {
-    if (emark[e2 * G.N1 + e1] == epoch) return EL_CUT;
-    double x = 0.5 * (G.bp1[e1] + G.bp1[e1 + 1]), y = 0.5 * (G.bp2[e2] + G.bp2[e2 + 1]);
-    bool out = false;
-    if (T.n_curves > 0) {
-        const int nc = T.row_cnt[e2];
-        if (nc > kRowCross || T.n_curves > 32) {
-            out = in_any_hole(T, x, y);
-        } else {
-            unsigned par = 0u;
-            for (int j = 0; j < nc; ++j)
-                if (T.row_key[(size_t)e2 * kRowCross + j] > x) par ^= 1u << T.row_curve[(size_t)e2 * kRowCross + j];
-            out = par != 0u;
-            for (int c = 0; c < T.n_curves && !out; ++c) {
-                const CurveDev C = T.curves[c];
-                if (C.kind == IGA_CURVE_ELLIPSE) out = ellipse_implicit(C, x, y) < 0.0;
-            }
-        }
-    }
-    return out ? EL_OUTSIDE : EL_INSIDE;
-}
-
 struct ClassArgs {
     int p, N1, N2, n1, n2, method;
     TrimDev T;
     GridDev G;
     const int* emark;
+    int* rcnt;  // [4][n2][tiles along x]: flags set per row segment of a tile (f_active, f_cut, e_cut, e_band)
     int8_t* ecls;
     int8_t* fcls;
     int* f_active;   // n1*n2 flags
@@ -893,13 +871,67 @@ __global__ void __launch_bounds__(256) k_classes(ClassArgs A) {
     const int p = A.p, tid = threadIdx.x;
     const int x0 = blockIdx.x * kClsTile, y0 = blockIdx.y * kClsTile;
     const int we = kClsTile + 2 * p, wf = kClsTile + p;
-    const int epoch = *A.T.epoch;
-    for (int t = tid; t < we * we; t += 256) {
+    // the window's element centres and its rows' centre-line crossings, staged once
+    __shared__ double sX[WE], sY[WE], sKey[WE][kRowCross];
+    __shared__ int sCnt[WE];
+    __shared__ int8_t sCur[WE][kRowCross];
+    const TrimDev& T = A.T;
+    const int epoch = *T.epoch;
+    __shared__ int sRC[4][WF];  // flags set per row of this tile (functions: rows v; elements: rows ty)
+    for (int t = tid; t < 4 * WF; t += 256) sRC[t / WF][t % WF] = 0;
+    if (tid < we) {
+        const int ex = min(max(x0 - p + tid, 0), A.N1 - 1), ey = min(max(y0 - p + tid, 0), A.N2 - 1);
+        sX[tid] = 0.5 * (A.G.bp1[ex] + A.G.bp1[ex + 1]);
+        sY[tid] = 0.5 * (A.G.bp2[ey] + A.G.bp2[ey + 1]);
+        sCnt[tid] = (T.n_curves > 0) ? T.row_cnt[ey] : 0;
+    }
+    if (T.n_curves > 0) {
+        for (int t = tid; t < we * kRowCross; t += 256) {
+            const int r = t / kRowCross, j = t % kRowCross;
+            const size_t o = (size_t)min(max(y0 - p + r, 0), A.N2 - 1) * kRowCross + j;
+            sKey[r][j] = T.row_key[o];
+            sCur[r][j] = (int8_t)T.row_curve[o];
+        }
+    }
+    constexpr int NIT = (WE * WE + 255) / 256;
+    int mk[NIT];
+#pragma unroll
+    for (int it = 0; it < NIT; ++it) {  // cut marks of this thread's elements, loaded together
+        const int t = tid + 256 * it, u = t % we, v = t / we;
+        const int ex = min(max(x0 - p + u, 0), A.N1 - 1), ey = min(max(y0 - p + v, 0), A.N2 - 1);
+        mk[it] = A.emark[ey * A.N1 + ex];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < NIT; ++it) {
+        const int t = tid + 256 * it;
+        if (t >= we * we) break;
         const int u = t % we, v = t / we;
         const int ex = x0 - p + u, ey = y0 - p + v;
         int8_t c = -1;
         if (ex >= 0 && ex < A.N1 && ey >= 0 && ey < A.N2) {
-            c = elem_class(A.T, A.G, A.emark, epoch, ex, ey);
+            if (mk[it] == epoch) {
+                c = EL_CUT;
+            } else {  // even-odd test at the centre, from the staged crossings
+                const double x = sX[u], y = sY[v];
+                bool out = false;
+                if (T.n_curves > 0) {
+                    const int nc = sCnt[v];
+                    if (nc > kRowCross || T.n_curves > 32) {
+                        out = in_any_hole(T, x, y);
+                    } else {
+                        unsigned par = 0u;
+                        for (int j = 0; j < nc; ++j)
+                            if (sKey[v][j] > x) par ^= 1u << sCur[v][j];
+                        out = par != 0u;
+                        for (int cc = 0; cc < T.n_curves && !out; ++cc) {
+                            const CurveDev C = T.curves[cc];
+                            if (C.kind == IGA_CURVE_ELLIPSE) out = ellipse_implicit(C, x, y) < 0.0;
+                        }
+                    }
+                }
+                c = out ? EL_OUTSIDE : EL_INSIDE;
+            }
             if (u >= p && u < p + kClsTile && v >= p && v < p + kClsTile) A.ecls[ey * A.N1 + ex] = c;
         }
         sE[v][u] = c;
@@ -923,9 +955,13 @@ __global__ void __launch_bounds__(256) k_classes(ClassArgs A) {
             const bool own = (u < kClsTile || lastx) && (v < kClsTile || lasty);
             if (own) {
                 const int f = j2 * A.n1 + j1;
+                const int act = cls != FN_EXTERIOR;
+                const int cut = (A.method == IGA_GAUSS_REF) ? (cls != FN_EXTERIOR) : (cls == FN_CUT);
                 A.fcls[f] = cls;
-                A.f_active[f] = cls != FN_EXTERIOR;
-                A.f_cut[f] = (A.method == IGA_GAUSS_REF) ? (cls != FN_EXTERIOR) : (cls == FN_CUT);
+                A.f_active[f] = act;
+                A.f_cut[f] = cut;
+                if (act) atomicAdd(&sRC[0][v], 1);
+                if (cut) atomicAdd(&sRC[1][v], 1);
             }
         }
         sF[v][u] = cls;
@@ -933,18 +969,37 @@ __global__ void __launch_bounds__(256) k_classes(ClassArgs A) {
     __syncthreads();
     const int tx = tid % kClsTile, ty = tid / kClsTile;
     const int e1 = x0 + tx, e2 = y0 + ty;
-    if (e1 >= A.N1 || e2 >= A.N2) return;
-    const int8_t c = sE[ty + p][tx + p];
-    int band = 0;
-    if (c == EL_INSIDE && A.method != IGA_NAIVE_WQ) {
-        if (A.method == IGA_GAUSS_REF) band = 1;
-        else
-            for (int d2 = 0; d2 <= p; ++d2)
-                for (int d1 = 0; d1 <= p; ++d1) band |= (sF[ty + d2][tx + d1] == FN_CUT);
+    if (e1 < A.N1 && e2 < A.N2) {
+        const int8_t c = sE[ty + p][tx + p];
+        int band = 0;
+        if (c == EL_INSIDE && A.method != IGA_NAIVE_WQ) {
+            if (A.method == IGA_GAUSS_REF) band = 1;
+            else
+                for (int d2 = 0; d2 <= p; ++d2)
+                    for (int d1 = 0; d1 <= p; ++d1) band |= (sF[ty + d2][tx + d1] == FN_CUT);
+        }
+        const int e = e2 * A.N1 + e1;
+        A.e_cut[e] = (c == EL_CUT);
+        A.e_band[e] = band;
+        if (c == EL_CUT) atomicAdd(&sRC[2][ty], 1);
+        if (band) atomicAdd(&sRC[3][ty], 1);
     }
-    const int e = e2 * A.N1 + e1;
-    A.e_cut[e] = (c == EL_CUT);
-    A.e_band[e] = band;
+    __syncthreads();
+    // the tile's row-segment counts, for the row-wise list writer's offsets
+    const int ntx = gridDim.x, bx = blockIdx.x;
+    if (tid < wf) {  // function rows this tile owns
+        const int j2 = y0 + tid;
+        if ((tid < kClsTile || lasty) && j2 < A.n2) {
+            A.rcnt[(size_t)(0 * A.n2 + j2) * ntx + bx] = sRC[0][tid];
+            A.rcnt[(size_t)(1 * A.n2 + j2) * ntx + bx] = sRC[1][tid];
+        }
+    } else if (tid >= 64 && tid < 64 + kClsTile) {  // element rows
+        const int r = tid - 64, er = y0 + r;
+        if (er < A.N2) {
+            A.rcnt[(size_t)(2 * A.n2 + er) * ntx + bx] = sRC[2][r];
+            A.rcnt[(size_t)(3 * A.n2 + er) * ntx + bx] = sRC[3][r];
+        }
+    }
 }
 
 void launch_trim_classes(Plan& P, hipStream_t s) {
@@ -956,7 +1011,8 @@ void launch_trim_classes(Plan& P, hipStream_t s) {
     int* f_cut = P.flags + (nf + 1);
     int* e_cut = P.flags + 2 * (nf + 1);
     int* e_band = e_cut + (ne + 1);
-    ClassArgs A{P.p, P.N1, P.N2, P.n1, P.n2, P.method, T, G, P.emark, P.ecls, P.fcls, f_active, f_cut, e_cut, e_band};
+    ClassArgs A{P.p,     P.N1,    P.N2,  P.n1,     P.n2,  P.method, T,     G,
+                P.emark, P.list_rcnt, P.ecls, P.fcls, f_active, f_cut, e_cut, e_band};
     dim3 g((P.N1 + kClsTile - 1) / kClsTile, (P.N2 + kClsTile - 1) / kClsTile);
     hipLaunchKernelGGL(k_classes, g, dim3(256), 0, s, A);
 }
@@ -964,20 +1020,21 @@ void launch_trim_classes(Plan& P, hipStream_t s) {
 // --------------------------------------------------------------- lists
 // The four compactions of the classes -- active functions (act_of, fn_of),
 // rows formed element-wise (their compact ids), cut elements and band
-// elements (id map and list) -- in one pass of three launches: per-tile
-// counts of all four flag arrays, one scan of the tile counts, and per-tile
-// positions with the writes. Lists come out in increasing flat order.
-constexpr int kListTile = 1024;  // 256 threads x 4 items
-
+// elements (id map and list) -- in one launch of one workgroup per row of
+// functions (and of elements): the class kernel left, per row and tile
+// column, how many flags of each kind it set; a row's offset is the sum of
+// those counts over the rows before it (summed by the row's workgroup, or
+// scanned by a separate launch for very large patches). Lists come out in
+// increasing flat order.
 struct ListArgs {
     const int* flag[4];  // f_active, f_cut (functions), e_cut, e_band (elements)
-    int n[4];
+    int rows[4], len[4]; // rows and row length of each flag array (n2 x n1 or N2 x N1)
     int* map[4];         // act_of, -, cut_id, band_id
     int* list[4];        // fn_of, form_rows (compact ids), cut_list, band_list
-    int* bsum;           // [4][ntiles] tile counts, then tile offsets
-    int ntiles;
+    int* bsum;           // [4][n2][ntx] row-segment counts (scanned in place when not prefix_here)
+    int n2, ntx;
     int* counts;         // [4] totals
-    int prefix_here;     // 1: each writing workgroup sums the tile counts before it; 0: bsum holds offsets
+    int prefix_here;     // 1: each workgroup sums the counts of the rows before it
 };
 
 __device__ __forceinline__ int block_sum256(int v, int* sh) {
@@ -991,79 +1048,81 @@ __device__ __forceinline__ int block_sum256(int v, int* sh) {
     return tot;
 }
 
-// Tile counts of the four flag arrays.
-__global__ void __launch_bounds__(256) k_list_count(ListArgs A) {
-    __shared__ int sh[4];
-    const int b = blockIdx.x, base = b * kListTile + threadIdx.x * 4;
-    int c[4];
-#pragma unroll
-    for (int a = 0; a < 4; ++a) {
-        c[a] = 0;
-#pragma unroll
-        for (int j = 0; j < 4; ++j) c[a] += (base + j < A.n[a]) ? (A.flag[a][base + j] != 0) : 0;
-    }
-#pragma unroll
-    for (int a = 0; a < 4; ++a) {
-        const int tot = block_sum256(c[a], sh);
-        if (threadIdx.x == 0) A.bsum[a * A.ntiles + b] = tot;
-    }
-}
-
-// Many tiles: exclusive scan of the tile counts (one workgroup).
+// Very large patches: exclusive scan of the row-segment counts (one workgroup).
 __global__ void __launch_bounds__(1024) k_list_scan(ListArgs A) {
     __shared__ int sh[1024 / 64 + 1];
+    const int nt = A.n2 * A.ntx;
     for (int a = 0; a < 4; ++a) {
         int carry = 0;
-        for (int t0 = 0; t0 < A.ntiles; t0 += 1024) {
+        for (int t0 = 0; t0 < nt; t0 += 1024) {
             const int idx = t0 + threadIdx.x;
-            const int v = (idx < A.ntiles) ? A.bsum[a * A.ntiles + idx] : 0;
+            const bool in = idx < A.rows[a] * A.ntx;  // element rows past N2 hold nothing
+            const int v = in ? A.bsum[a * nt + idx] : 0;
             int total;
             const int ex = block_excl_scan(v, sh, total);
-            if (idx < A.ntiles) A.bsum[a * A.ntiles + idx] = ex + carry;
+            if (in) A.bsum[a * nt + idx] = ex + carry;
             carry += total;
         }
-        if (threadIdx.x == 0) A.counts[a] = carry;
     }
 }
 
-__global__ void __launch_bounds__(256) k_list_write(ListArgs A) {
+// One workgroup per row r: function row r of arrays 0 and 1, element row r of 2 and 3.
+__global__ void __launch_bounds__(256) k_list_rows(ListArgs A) {
     __shared__ int sh[256 / 64 + 1];
     __shared__ int s_off[4];
-    const int b = blockIdx.x, base = b * kListTile + threadIdx.x * 4;
-    if (A.prefix_here) {  // this tile's offsets: the counts of the tiles before it
+    const int r = blockIdx.x, nt = A.n2 * A.ntx;
+    if (A.prefix_here) {
         int v[4] = {0, 0, 0, 0};
-        for (int t = threadIdx.x; t < b; t += 256)
+        for (int t = threadIdx.x; t < r * A.ntx; t += 256)
 #pragma unroll
-            for (int a = 0; a < 4; ++a) v[a] += A.bsum[a * A.ntiles + t];
+            for (int a = 0; a < 4; ++a) v[a] += (r <= A.rows[a]) ? A.bsum[a * nt + t] : 0;
 #pragma unroll
         for (int a = 0; a < 4; ++a) {
             const int tot = block_sum256(v[a], sh);
             if (threadIdx.x == 0) s_off[a] = tot;
         }
     } else if (threadIdx.x < 4) {
-        s_off[threadIdx.x] = A.bsum[threadIdx.x * A.ntiles + b];
+        const int a = threadIdx.x;
+        s_off[a] = (r < A.rows[a]) ? A.bsum[a * nt + r * A.ntx] : 0;
     }
     __syncthreads();
-    int fl[4][4];
+#pragma unroll 1
+    for (int pair = 0; pair < 2; ++pair) {  // (active functions, element-formed rows), (cut, band elements)
+        const int a0 = 2 * pair;
+        if (r >= A.rows[a0]) continue;
+        const int len = A.len[a0];
+        const int base = r * len;
+        int pos0[2] = {s_off[a0], s_off[a0 + 1]};
+#pragma unroll 1
+        for (int c0 = 0; c0 < len; c0 += 1024) {
+            const int i0 = c0 + threadIdx.x * 4;
+            int fl[2][4];
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+            for (int k = 0; k < 2; ++k)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) fl[a][j] = (base + j < A.n[a]) ? (A.flag[a][base + j] != 0) : 0;
-    int actpos[4] = {0, 0, 0, 0};
+                for (int j = 0; j < 4; ++j) fl[k][j] = (i0 + j < len) ? (A.flag[a0 + k][base + i0 + j] != 0) : 0;
+            int actpos[4] = {0, 0, 0, 0};
 #pragma unroll
-    for (int a = 0; a < 4; ++a) {
-        const int v = fl[a][0] + fl[a][1] + fl[a][2] + fl[a][3];
-        int total;
-        int pos = block_excl_scan(v, sh, total) + s_off[a];
-        if (A.prefix_here && b == A.ntiles - 1 && threadIdx.x == 0) A.counts[a] = s_off[a] + total;
+            for (int k = 0; k < 2; ++k) {
+                const int a = a0 + k;
+                const int v = fl[k][0] + fl[k][1] + fl[k][2] + fl[k][3];
+                int total;
+                int pos = block_excl_scan(v, sh, total) + pos0[k];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int i = base + j;
-            if (i >= A.n[a]) continue;
-            if (a == 0) actpos[j] = pos;
-            if (A.map[a]) A.map[a][i] = fl[a][j] ? pos : -1;
-            if (fl[a][j]) A.list[a][pos] = (a == 1) ? actpos[j] : i;
-            pos += fl[a][j];
+                for (int j = 0; j < 4; ++j) {
+                    if (i0 + j >= len) continue;
+                    const int i = base + i0 + j;
+                    if (a == 0) actpos[j] = pos;
+                    if (A.map[a]) A.map[a][i] = fl[k][j] ? pos : -1;
+                    if (fl[k][j]) A.list[a][pos] = (a == 1) ? actpos[j] : i;
+                    pos += fl[k][j];
+                }
+                pos0[k] += total;
+            }
+        }
+        if (r == A.rows[a0] - 1 && threadIdx.x == 0) {
+            A.counts[a0] = pos0[0];
+            A.counts[a0 + 1] = pos0[1];
         }
     }
 }
@@ -1076,16 +1135,17 @@ void launch_trim_lists(Plan& P, hipStream_t s) {
     int* e_band = e_cut + (ne + 1);
     ListArgs A;
     A.flag[0] = f_active; A.flag[1] = f_cut; A.flag[2] = e_cut; A.flag[3] = e_band;
-    A.n[0] = nf; A.n[1] = nf; A.n[2] = ne; A.n[3] = ne;
+    A.rows[0] = A.rows[1] = P.n2; A.rows[2] = A.rows[3] = P.N2;
+    A.len[0] = A.len[1] = P.n1; A.len[2] = A.len[3] = P.N1;
     A.map[0] = P.act_of; A.map[1] = nullptr; A.map[2] = P.cut_id; A.map[3] = P.band_id;
     A.list[0] = P.fn_of; A.list[1] = P.form_rows; A.list[2] = P.cut_list; A.list[3] = P.band_list;
-    A.ntiles = (std::max(nf, ne) + kListTile - 1) / kListTile;
-    A.bsum = P.scan_tmp + P.scan_pos_off;  // 4 * ntiles <= the position region
+    A.n2 = P.n2;
+    A.ntx = (P.N1 + kClsTile - 1) / kClsTile;
+    A.bsum = P.list_rcnt;
     A.counts = P.counts;
-    A.prefix_here = A.ntiles <= 1024;
-    hipLaunchKernelGGL(k_list_count, dim3(A.ntiles), dim3(256), 0, s, A);
+    A.prefix_here = (int64_t)P.n2 * A.ntx <= 8192;
     if (!A.prefix_here) hipLaunchKernelGGL(k_list_scan, dim3(1), dim3(1024), 0, s, A);
-    hipLaunchKernelGGL(k_list_write, dim3(A.ntiles), dim3(256), 0, s, A);
+    hipLaunchKernelGGL(k_list_rows, dim3(P.n2), dim3(256), 0, s, A);
 }
 
 // ------------------------------------------------------ cut-element rules

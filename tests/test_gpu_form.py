@@ -261,3 +261,25 @@ def test_points_rewritten_by_full_formation():
         plan.mass_form(coef, full=True)
         torch.cuda.synchronize()
         assert torch.equal(plan.points(), p0)
+
+
+@pytest.mark.parametrize("N", [100, 400])
+def test_lists_are_compactions_of_the_classes(N):
+    """Compact maps and lists equal the flat-order compaction of the device's own classes, on a
+    patch small enough for each row's workgroup to sum its offset (N = 100) and one large enough
+    for the separate offset scan (N = 400)."""
+    require_gpu()
+    from paper_2101_08053_amd import igatrim
+    cfg = wl.config1(N=N)
+    say(f"[lists] N={N}")
+    plan = igatrim.Plan(cfg, igatrim.HYBRID_GAUSS)
+    s = plan.sizes
+    act_of, fn_of, fcls = (t.cpu().numpy() for t in plan.index_maps())
+    active = fcls != EXTERIOR_FN
+    ref_act = np.where(active, np.cumsum(active) - 1, -1)
+    np.testing.assert_array_equal(act_of, ref_act)
+    np.testing.assert_array_equal(fn_of[: s["n_act"]], np.nonzero(active)[0])
+    assert s["n_act"] == int(active.sum())
+    assert s["n_cut_fn"] == int((fcls == CUT_FN).sum())
+    rows = plan.int_table(igatrim.ITABLE_FORM_ROWS).cpu().numpy().reshape(-1)
+    np.testing.assert_array_equal(rows[: s["n_cut_fn"]], ref_act[fcls == CUT_FN])
