@@ -1072,13 +1072,27 @@ __global__ void __launch_bounds__(256) k_list_rows(ListArgs A) {
     __shared__ int s_off[4];
     const int r = blockIdx.x, nt = A.n2 * A.ntx;
     if (A.prefix_here) {
+        // the counts of the rows before r, four per thread and array per pass, loaded together
+        const int m = r * A.ntx;
         int v[4] = {0, 0, 0, 0};
-        for (int t = threadIdx.x; t < r * A.ntx; t += 256)
+#pragma unroll 1
+        for (int t0 = 0; t0 < m; t0 += 1024) {
+            int x[4][4];
 #pragma unroll
-            for (int a = 0; a < 4; ++a) v[a] += (r <= A.rows[a]) ? A.bsum[a * nt + t] : 0;
+            for (int k = 0; k < 4; ++k) {
+                const int t = min(t0 + (int)threadIdx.x + 256 * k, m - 1);
+#pragma unroll
+                for (int a = 0; a < 4; ++a) x[a][k] = A.bsum[a * nt + t];
+            }
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                if (t0 + (int)threadIdx.x + 256 * k < m)
+#pragma unroll
+                    for (int a = 0; a < 4; ++a) v[a] += x[a][k];
+        }
 #pragma unroll
         for (int a = 0; a < 4; ++a) {
-            const int tot = block_sum256(v[a], sh);
+            const int tot = block_sum256(r <= A.rows[a] ? v[a] : 0, sh);
             if (threadIdx.x == 0) s_off[a] = tot;
         }
     } else if (threadIdx.x < 4) {
@@ -1100,7 +1114,10 @@ __global__ void __launch_bounds__(256) k_list_rows(ListArgs A) {
 #pragma unroll
             for (int k = 0; k < 2; ++k)
 #pragma unroll
-                for (int j = 0; j < 4; ++j) fl[k][j] = (i0 + j < len) ? (A.flag[a0 + k][base + i0 + j] != 0) : 0;
+                for (int j = 0; j < 4; ++j) {
+                    const int f = A.flag[a0 + k][base + min(i0 + j, len - 1)];
+                    fl[k][j] = (i0 + j < len) ? (f != 0) : 0;
+                }
             int actpos[4] = {0, 0, 0, 0};
 #pragma unroll
             for (int k = 0; k < 2; ++k) {
