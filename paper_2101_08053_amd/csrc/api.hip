@@ -260,17 +260,15 @@ static void form(Plan& P, const iga_coeff& c, double* vals, int flags, hipStream
         setup_trim(P, s, false, false, 2);
     }
     HIPX(hipStreamWaitEvent(a, P.ev_lists, 0));
-    {
-        PhaseTimer t(P, a, IGA_PHASE_CUT);
-        launch_coef(P, c, a, 3, pts_by_coef);
-        launch_cut_rows_mode(P, c, vals, a, 1);  // rows formed element-wise: their inside sums
-    }
-    HIPX(hipEventRecord(P.ev_band, a));
+    // The interior rows first (beside the cut rules, which leave most of the
+    // GPU idle), then the inside sums of the element-formed rows (beside the
+    // cut element matrices); the caller's stream joins once, before the cut
+    // entries, which need those sums.
     if (P.timing) {
         // The interior kernel alone, events at its dispatch's start and end:
         // it waits for the work queued on s so far, and s waits for it before
         // its next kernel, so the events time the kernel and not its share
-        // of a GPU busy with the cut elements.
+        // of a GPU busy with the cut rules.
         HIPX(hipEventRecord(P.ev_iso, s));
         HIPX(hipStreamWaitEvent(a, P.ev_iso, 0));
         hipEvent_t t0, t1;
@@ -278,12 +276,18 @@ static void form(Plan& P, const iga_coeff& c, double* vals, int flags, hipStream
         HIPX(hipEventCreate(&t1));
         launch_interior_rows(P, c, vals, a, t0, t1);
         P.ev_records.push_back({IGA_PHASE_INTERIOR, {t0, t1}});
+        HIPX(hipEventRecord(P.ev_interior, a));
+        HIPX(hipStreamWaitEvent(s, P.ev_interior, 0));
     } else {
         launch_interior_rows(P, c, vals, a);
     }
     if (full && !pts_by_coef) launch_points(P, a);
-    HIPX(hipEventRecord(P.ev_interior, a));
-    if (P.timing) HIPX(hipStreamWaitEvent(s, P.ev_interior, 0));
+    {
+        PhaseTimer t(P, a, IGA_PHASE_CUT);
+        launch_coef(P, c, a, 3, pts_by_coef);
+        launch_cut_rows_mode(P, c, vals, a, 1);  // rows formed element-wise: their inside sums
+    }
+    HIPX(hipEventRecord(P.ev_band, a));  // everything on the auxiliary stream is done
     {
         PhaseTimer t(P, s, IGA_PHASE_CUT);
         launch_cut_elems(P, c, s);  // with c at the cut nodes
@@ -291,7 +295,6 @@ static void form(Plan& P, const iga_coeff& c, double* vals, int flags, hipStream
         launch_cut_rows_mode(P, c, vals, s, 2);  // plus the cut element matrices' entries
         launch_dwq_rows(P, c, vals, s);
     }
-    HIPX(hipStreamWaitEvent(s, P.ev_interior, 0));
 }
 
 // The formation recorded once as a HIP graph and replayed: one submission

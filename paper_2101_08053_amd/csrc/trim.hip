@@ -863,6 +863,7 @@ struct ClassArgs {
 // function, whose Gauss points some row formed element-wise uses. The last
 // tile of each direction also owns the p functions past the last element.
 constexpr int kClsTile = 16;
+constexpr int8_t kElPending = -2;  // element class still to be found by the direct test
 
 __global__ void __launch_bounds__(256) k_classes(ClassArgs A) {
     constexpr int WE = kClsTile + 2 * IGA_MAXP, WF = kClsTile + IGA_MAXP;
@@ -915,10 +916,11 @@ __global__ void __launch_bounds__(256) k_classes(ClassArgs A) {
             } else {  // even-odd test at the centre, from the staged crossings
                 const double x = sX[u], y = sY[v];
                 bool out = false;
+                c = EL_INSIDE;
                 if (T.n_curves > 0) {
                     const int nc = sCnt[v];
                     if (nc > kRowCross || T.n_curves > 32) {
-                        out = in_any_hole(T, x, y);
+                        c = kElPending;  // the direct test, below
                     } else {
                         unsigned par = 0u;
                         for (int j = 0; j < nc; ++j)
@@ -930,10 +932,22 @@ __global__ void __launch_bounds__(256) k_classes(ClassArgs A) {
                         }
                     }
                 }
-                c = out ? EL_OUTSIDE : EL_INSIDE;
+                if (c != kElPending) c = out ? EL_OUTSIDE : EL_INSIDE;
             }
-            if (u >= p && u < p + kClsTile && v >= p && v < p + kClsTile) A.ecls[ey * A.N1 + ex] = c;
+            if (c != kElPending && u >= p && u < p + kClsTile && v >= p && v < p + kClsTile)
+                A.ecls[ey * A.N1 + ex] = c;
         }
+        sE[v][u] = c;
+    }
+    __syncthreads();
+    // rows with more crossings than recorded: the direct test (one copy of its code, not unrolled)
+#pragma unroll 1
+    for (int t = tid; t < we * we; t += 256) {
+        const int u = t % we, v = t / we;
+        if (sE[v][u] != kElPending) continue;
+        const int ex = x0 - p + u, ey = y0 - p + v;
+        const int8_t c = in_any_hole(T, sX[u], sY[v]) ? EL_OUTSIDE : EL_INSIDE;
+        if (u >= p && u < p + kClsTile && v >= p && v < p + kClsTile) A.ecls[ey * A.N1 + ex] = c;
         sE[v][u] = c;
     }
     __syncthreads();
