@@ -32,74 +32,154 @@ struct MfArgs {
     int nq, nb;        // point offsets: band points start at nq, cut nodes at nq + nb
 };
 
-__device__ __forceinline__ double u_at(const MfArgs& A, const double* __restrict__ u, int j1, int j2) {
-    int c = A.act_of[j2 * A.n1 + j1];
-    return c >= 0 ? u[c] : 0.0;
-}
-
-// U_k on the whole WQ grid; out = c_k U_k (forward) or U_k (adjoint).
-__global__ void k_mf_grid(MfArgs A, const double* __restrict__ u, double* __restrict__ out, int times_c) {
-    int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= A.nq) return;
-    int p = A.p;
-    int k1 = k % A.d1.Q, k2 = k / A.d1.Q;
-    int e1 = A.d1.eq[k1], e2 = A.d2.eq[k2];
-    double U = 0.0;
-    for (int a2 = 0; a2 <= p; ++a2) {
-        double s = 0.0;
-        for (int a1 = 0; a1 <= p; ++a1) s += A.d1.Bq[k1 * (p + 1) + a1] * u_at(A, u, e1 + a1, e2 + a2);
-        U += A.d2.Bq[k2 * (p + 1) + a2] * s;
-    }
-    out[k] = times_c ? A.c[k] * U : U;
-}
-
 __device__ __forceinline__ bool wq_row(const MfArgs& A, int8_t cls) {
     return A.method != IGA_GAUSS_REF && cls == FN_INTERIOR;
 }
 
-// y for rows formed by weighted quadrature.
-__global__ void k_mf_wq_rows(MfArgs A, const double* __restrict__ G, double* __restrict__ y) {
-    int r = blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= A.n_act) return;
-    int f = A.fn_of[r];
-    if (!wq_row(A, A.fcls[f])) return;
-    int p = A.p;
-    int i1 = f % A.n1, i2 = f / A.n1;
-    int k1 = A.d1.pt0[max(0, i1 - p)], q1 = A.d1.pt0[min(A.N1 - 1, i1) + 1] - k1;
-    int k2 = A.d2.pt0[max(0, i2 - p)], q2 = A.d2.pt0[min(A.N2 - 1, i2) + 1] - k2;
+// The weighted-quadrature part as four banded one-dimensional contractions
+// (sum factorisation), each a streaming kernel with the fast index along xi_1:
+//   V[j2][k1] = sum_a B1[k1][a] u(e1(k1) + a, j2)              (u on the xi_1 points)
+//   G[k2][k1] = c_k sum_a B2[k2][a] V[e2(k2) + a][k1]          (c U on the grid; U alone for the adjoint)
+//   H[k2][i1] = sum_q w1[i1][q] G[k2][k0(i1) + q]              (test rows along xi_1)
+//   y(i1, i2) = sum_q w2[i2][q] H[k0(i2) + q][i1]              (interior rows)
+// and, transposed, for the adjoint
+//   H[k2][i1] = sum_{i2 : k2 in supp} w2[i2][k2 - k0(i2)] r(i1, i2)
+//   R[k2][k1] = sum_{i1 : k1 in supp} w1[i1][k1 - k0(i1)] H[k2][i1],  dc = U R, CR = c R
+//   D[k2][j1] = sum_{k1 in supp j1} B1[k1][j1 - e1(k1)] CR[k2][k1]
+//   du(j1, j2) += sum_{k2 in supp j2} B2[k2][j2 - e2(k2)] D[k2][j1]   (in the gather kernel)
+template <int P>
+__global__ void __launch_bounds__(256) k_mf_v(MfArgs A, const double* __restrict__ u, double* __restrict__ V) {
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int Q1 = A.d1.Q;
+    if (t >= (int64_t)A.n2 * Q1) return;
+    const int k1 = (int)(t % Q1), j2 = (int)(t / Q1);
+    const int e1 = A.d1.eq[k1];
+    const int* act = A.act_of + (size_t)j2 * A.n1 + e1;
+    int cid[P + 1];
+#pragma unroll
+    for (int a = 0; a <= P; ++a) cid[a] = act[a];
     double s = 0.0;
-    for (int b = 0; b < q2; ++b) {
-        double in = 0.0;
-        for (int a = 0; a < q1; ++a) in += A.d1.W[(size_t)i1 * A.d1.qmax + a] * G[(size_t)(k2 + b) * A.d1.Q + k1 + a];
-        s += A.d2.W[(size_t)i2 * A.d2.qmax + b] * in;
+#pragma unroll
+    for (int a = 0; a <= P; ++a) {
+        const double uv = u[max(cid[a], 0)];
+        s += A.d1.Bq[(size_t)k1 * (P + 1) + a] * (cid[a] >= 0 ? uv : 0.0);
     }
-    y[r] = s;
+    V[t] = s;
 }
 
-// Adjoint on the WQ grid: R_k from the rows that use point k, dc_k = U_k R_k,
-// and CR_k = c_k R_k for the du gather.
-__global__ void k_mf_grid_adj(MfArgs A, const double* __restrict__ U, const double* __restrict__ r,
-                              double* __restrict__ dc, double* __restrict__ CR) {
-    int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= A.nq) return;
-    int p = A.p;
-    int k1 = k % A.d1.Q, k2 = k / A.d1.Q;
-    int e1 = A.d1.eq[k1], e2 = A.d2.eq[k2];
-    double R = 0.0;
-    for (int i2 = e2; i2 <= e2 + p; ++i2) {
-        int q2 = k2 - A.d2.pt0[max(0, i2 - p)];
-        double w2 = A.d2.W[(size_t)i2 * A.d2.qmax + q2];
-        double s = 0.0;
-        for (int i1 = e1; i1 <= e1 + p; ++i1) {
-            int f = i2 * A.n1 + i1;
-            if (!wq_row(A, A.fcls[f])) continue;
-            int q1 = k1 - A.d1.pt0[max(0, i1 - p)];
-            s += A.d1.W[(size_t)i1 * A.d1.qmax + q1] * r[A.act_of[f]];
-        }
-        R += w2 * s;
+template <int P>
+__global__ void __launch_bounds__(256) k_mf_g(MfArgs A, const double* __restrict__ V, double* __restrict__ G,
+                                              int times_c) {
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int Q1 = A.d1.Q;
+    if (t >= (int64_t)A.nq) return;
+    const int k1 = (int)(t % Q1), k2 = (int)(t / Q1);
+    const int e2 = A.d2.eq[k2];
+    double v[P + 1];
+#pragma unroll
+    for (int a = 0; a <= P; ++a) v[a] = V[(size_t)(e2 + a) * Q1 + k1];
+    double s = 0.0;
+#pragma unroll
+    for (int a = 0; a <= P; ++a) s += A.d2.Bq[(size_t)k2 * (P + 1) + a] * v[a];
+    G[t] = times_c ? A.c[t] * s : s;
+}
+
+template <int P>
+__global__ void __launch_bounds__(256) k_mf_h(MfArgs A, const double* __restrict__ G, double* __restrict__ H) {
+    constexpr int QM = 4 * P + 2;
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int n1 = A.n1, Q1 = A.d1.Q;
+    if (t >= (int64_t)A.d2.Q * n1) return;
+    const int i1 = (int)(t % n1), k2 = (int)(t / n1);
+    const int k0 = A.d1.pt0[max(0, i1 - P)], q1 = A.d1.pt0[min(A.N1 - 1, i1) + 1] - k0;
+    const double* g = G + (size_t)k2 * Q1 + k0;
+    const double* w = A.d1.W + (size_t)i1 * A.d1.qmax;
+    double s = 0.0;
+#pragma unroll
+    for (int q = 0; q < QM; ++q) {
+        if (q >= q1) break;
+        s += w[q] * g[q];
     }
-    dc[k] = U[k] * R;
-    CR[k] = A.c[k] * R;
+    H[t] = s;
+}
+
+template <int P>
+__global__ void __launch_bounds__(256) k_mf_y(MfArgs A, const double* __restrict__ H, double* __restrict__ y) {
+    constexpr int QM = 4 * P + 2;
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int n1 = A.n1;
+    if (t >= (int64_t)n1 * A.n2) return;
+    if (!wq_row(A, A.fcls[t])) return;
+    const int i1 = (int)(t % n1), i2 = (int)(t / n1);
+    const int k0 = A.d2.pt0[max(0, i2 - P)], q2 = A.d2.pt0[min(A.N2 - 1, i2) + 1] - k0;
+    const double* w = A.d2.W + (size_t)i2 * A.d2.qmax;
+    double s = 0.0;
+#pragma unroll
+    for (int q = 0; q < QM; ++q) {
+        if (q >= q2) break;
+        s += w[q] * H[(size_t)(k0 + q) * n1 + i1];
+    }
+    y[A.act_of[t]] = s;
+}
+
+template <int P>
+__global__ void __launch_bounds__(256) k_mf_hadj(MfArgs A, const double* __restrict__ r, double* __restrict__ H) {
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int n1 = A.n1;
+    if (t >= (int64_t)A.d2.Q * n1) return;
+    const int i1 = (int)(t % n1), k2 = (int)(t / n1);
+    const int e2 = A.d2.eq[k2];
+    double s = 0.0;
+#pragma unroll
+    for (int b = 0; b <= P; ++b) {
+        const int i2 = e2 + b;
+        if (i2 >= A.n2) break;
+        const int f = i2 * n1 + i1;
+        const int cid = A.act_of[f];
+        const bool use = cid >= 0 && wq_row(A, A.fcls[f]);
+        const double rv = r[max(cid, 0)];
+        const double w2 = A.d2.W[(size_t)i2 * A.d2.qmax + (k2 - A.d2.pt0[max(0, i2 - P)])];
+        s += use ? w2 * rv : 0.0;
+    }
+    H[t] = s;
+}
+
+template <int P>
+__global__ void __launch_bounds__(256) k_mf_radj(MfArgs A, const double* __restrict__ H, const double* __restrict__ U,
+                                                 double* __restrict__ dc, double* __restrict__ CR) {
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int Q1 = A.d1.Q, n1 = A.n1;
+    if (t >= (int64_t)A.nq) return;
+    const int k1 = (int)(t % Q1), k2 = (int)(t / Q1);
+    const int e1 = A.d1.eq[k1];
+    double s = 0.0;
+#pragma unroll
+    for (int a = 0; a <= P; ++a) {
+        const int i1 = e1 + a;
+        if (i1 >= n1) break;
+        const double w1 = A.d1.W[(size_t)i1 * A.d1.qmax + (k1 - A.d1.pt0[max(0, i1 - P)])];
+        s += w1 * H[(size_t)k2 * n1 + i1];
+    }
+    dc[t] = U[t] * s;
+    CR[t] = A.c[t] * s;
+}
+
+template <int P>
+__global__ void __launch_bounds__(256) k_mf_dadj(MfArgs A, const double* __restrict__ CR, double* __restrict__ D) {
+    constexpr int QM = 4 * P + 2;
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int n1 = A.n1, Q1 = A.d1.Q;
+    if (t >= (int64_t)A.d2.Q * n1) return;
+    const int j1 = (int)(t % n1), k2 = (int)(t / n1);
+    const int k0 = A.d1.pt0[max(0, j1 - P)], q1 = A.d1.pt0[min(A.N1 - 1, j1) + 1] - k0;
+    double s = 0.0;
+#pragma unroll
+    for (int q = 0; q < QM; ++q) {
+        if (q >= q1) break;
+        const int k1 = k0 + q;
+        s += A.d1.Bq[(size_t)k1 * (P + 1) + (j1 - A.d1.eq[k1])] * CR[(size_t)k2 * Q1 + k1];
+    }
+    D[t] = s;
 }
 
 // Element part: per band / cut element, forward Y_e[l] = sum_g w_g c_g U_g B_l(x_g),
@@ -194,7 +274,7 @@ __global__ void __launch_bounds__(64) k_mf_elem(MfArgs A, const double* __restri
 
 // Sum of the element vectors over the band / cut elements of supp B_j,
 // for the rows formed element-wise (forward) or every active function (adjoint),
-// plus (adjoint) the WQ-grid part sum_k B_j(x_k) CR_k.
+// plus (adjoint) the WQ-grid part sum_k B_j(x_k) CR_k from its xi_1 sums D.
 __global__ void k_mf_gather(MfArgs A, const double* __restrict__ Ye, const double* __restrict__ CR,
                             double* __restrict__ out, int adjoint) {
     int r = blockIdx.x * blockDim.x + threadIdx.x;
@@ -215,19 +295,12 @@ __global__ void k_mf_gather(MfArgs A, const double* __restrict__ Ye, const doubl
             if (re < 0) continue;  // inside element used by no element-formed row
             s += Ye[(size_t)re * L + (i2 - e2) * (p + 1) + (i1 - e1)];
         }
-    if (adjoint && A.method != IGA_GAUSS_REF) {
-        int k1 = A.d1.pt0[max(0, i1 - p)], q1 = A.d1.pt0[min(A.N1 - 1, i1) + 1] - k1;
+    if (adjoint && A.method != IGA_GAUSS_REF) {  // the grid part, sum_k2 B2 D[k2][i1]
         int k2 = A.d2.pt0[max(0, i2 - p)], q2 = A.d2.pt0[min(A.N2 - 1, i2) + 1] - k2;
         double g = 0.0;
         for (int b = 0; b < q2; ++b) {
             int kk2 = k2 + b, m2 = A.d2.eq[kk2];
-            double b2 = A.d2.Bq[kk2 * (p + 1) + (i2 - m2)];
-            double in = 0.0;
-            for (int a = 0; a < q1; ++a) {
-                int kk1 = k1 + a, m1 = A.d1.eq[kk1];
-                in += A.d1.Bq[kk1 * (p + 1) + (i1 - m1)] * CR[(size_t)kk2 * A.d1.Q + kk1];
-            }
-            g += b2 * in;
+            g += A.d2.Bq[kk2 * (p + 1) + (i2 - m2)] * CR[(size_t)kk2 * A.n1 + i1];
         }
         s += g;
     }
@@ -268,8 +341,39 @@ static MfArgs mf_args(Plan& P, const double* c) {
 static void mf_buffers(Plan& P) {
     size_t nq = (size_t)P.dir[0].Q * P.dir[1].Q;
     size_t L = (size_t)(P.p + 1) * (P.p + 1);
-    if (!P.sw.G) P.sw.G = P.alloc<double>(2 * nq);
+    if (!P.sw.G) P.sw.G = P.alloc<double>(nq);
+    if (!P.sw.CR) P.sw.CR = P.alloc<double>(nq);
+    if (!P.sw.V) P.sw.V = P.alloc<double>((size_t)P.n2 * P.dir[0].Q);
+    if (!P.sw.H) P.sw.H = P.alloc<double>((size_t)P.dir[1].Q * P.n1);
     if (!P.sw.Ue) P.sw.Ue = P.alloc<double>(std::max<int64_t>(1, P.n_band + P.n_cut_el) * L);
+}
+
+static dim3 grid256(int64_t n) { return dim3((unsigned)((n + 255) / 256)); }
+
+// U on the WQ grid (times c if times_c) into G.
+template <int P>
+static void launch_u_grid(Plan& Pl, const MfArgs& A, const double* u, int times_c, hipStream_t s) {
+    hipLaunchKernelGGL(k_mf_v<P>, grid256((int64_t)Pl.n2 * A.d1.Q), dim3(256), 0, s, A, u, Pl.sw.V);
+    hipLaunchKernelGGL(k_mf_g<P>, grid256(A.nq), dim3(256), 0, s, A, (const double*)Pl.sw.V, Pl.sw.G, times_c);
+}
+
+template <int P>
+static void launch_wq_forward(Plan& Pl, const MfArgs& A, const double* u, double* y, hipStream_t s) {
+    launch_u_grid<P>(Pl, A, u, 1, s);
+    hipLaunchKernelGGL(k_mf_h<P>, grid256((int64_t)A.d2.Q * Pl.n1), dim3(256), 0, s, A, (const double*)Pl.sw.G,
+                       Pl.sw.H);
+    hipLaunchKernelGGL(k_mf_y<P>, grid256((int64_t)Pl.n1 * Pl.n2), dim3(256), 0, s, A, (const double*)Pl.sw.H, y);
+}
+
+template <int P>
+static void launch_wq_adjoint(Plan& Pl, const MfArgs& A, const double* u, const double* r, double* dc,
+                              hipStream_t s) {
+    launch_u_grid<P>(Pl, A, u, 0, s);  // U
+    const int64_t nh = (int64_t)A.d2.Q * Pl.n1;
+    hipLaunchKernelGGL(k_mf_hadj<P>, grid256(nh), dim3(256), 0, s, A, r, Pl.sw.H);
+    hipLaunchKernelGGL(k_mf_radj<P>, grid256(A.nq), dim3(256), 0, s, A, (const double*)Pl.sw.H,
+                       (const double*)Pl.sw.G, dc, Pl.sw.CR);
+    hipLaunchKernelGGL(k_mf_dadj<P>, grid256(nh), dim3(256), 0, s, A, (const double*)Pl.sw.CR, Pl.sw.H);  // D
 }
 
 static void launch_elem(Plan& P, const MfArgs& A, const double* u, const double* r, double* Ye, double* dc,
@@ -289,8 +393,12 @@ void mf_apply(Plan& P, const double* c, const double* u, double* y, hipStream_t 
     MfArgs A = mf_args(P, c);
     int n = (int)P.n_act;
     if (P.method != IGA_GAUSS_REF) {
-        hipLaunchKernelGGL(k_mf_grid, dim3((A.nq + 255) / 256), dim3(256), 0, s, A, u, P.sw.G, 1);
-        hipLaunchKernelGGL(k_mf_wq_rows, dim3((n + 255) / 256), dim3(256), 0, s, A, (const double*)P.sw.G, y);
+        switch (P.p) {
+#define CASE(PP) \
+    case PP: launch_wq_forward<PP>(P, A, u, y, s); break;
+            CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
+#undef CASE
+        }
     }
     launch_elem(P, A, u, nullptr, P.sw.Ue, nullptr, s);
     hipLaunchKernelGGL(k_mf_gather, dim3((n + 255) / 256), dim3(256), 0, s, A, (const double*)P.sw.Ue,
@@ -302,17 +410,20 @@ void mf_adjoint(Plan& P, const double* c, const double* u, const double* r, doub
     MfArgs A = mf_args(P, c);
     int n = (int)P.n_act;
     size_t nq = (size_t)A.nq;
-    double* U = P.sw.G;
-    double* CR = P.sw.G + nq;
     if (P.method != IGA_GAUSS_REF) {
-        hipLaunchKernelGGL(k_mf_grid, dim3((A.nq + 255) / 256), dim3(256), 0, s, A, u, U, 0);
-        hipLaunchKernelGGL(k_mf_grid_adj, dim3((A.nq + 255) / 256), dim3(256), 0, s, A, (const double*)U, r, dc, CR);
+        switch (P.p) {
+#define CASE(PP) \
+    case PP: launch_wq_adjoint<PP>(P, A, u, r, dc, s); break;
+            CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
+#undef CASE
+        }
     } else {
         HIPX(hipMemsetAsync(dc, 0, sizeof(double) * nq, s));
     }
     launch_elem(P, A, u, r, P.sw.Ue, dc, s);
+    // the grid part of du reads D (held in H) through the CR argument
     hipLaunchKernelGGL(k_mf_gather, dim3((n + 255) / 256), dim3(256), 0, s, A, (const double*)P.sw.Ue,
-                       (const double*)CR, du, 1);
+                       (const double*)P.sw.H, du, 1);
 }
 
 }  // namespace iga
