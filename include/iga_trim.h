@@ -220,7 +220,9 @@ int iga_trim_rhs(iga_plan* plan, const iga_coeff* c, const iga_target* g, double
 
 /* Matrix-free product y = M(c) u (device vectors of length n_act) with c
  * given at every rule point (c_points, n_points values), the rows formed by
- * the plan's interior and hybrid rules, basis values recomputed on the fly. */
+ * the plan's interior and hybrid rules, basis values recomputed on the fly.
+ * The weighted-quadrature part runs sum-factorised with one row of the WQ
+ * grid in LDS: IGA_E_UNSUPPORTED past about 2700 elements along xi_1. */
 int iga_mf_apply(iga_plan* plan, const double* c_points, const double* u, double* y, void* stream);
 
 /* Adjoint of iga_mf_apply: for a cotangent gy (n_act), du = M(c)^T gy

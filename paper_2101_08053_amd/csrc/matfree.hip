@@ -36,17 +36,18 @@ __device__ __forceinline__ bool wq_row(const MfArgs& A, int8_t cls) {
     return A.method != IGA_GAUSS_REF && cls == FN_INTERIOR;
 }
 
-// The weighted-quadrature part as four banded one-dimensional contractions
-// (sum factorisation), each a streaming kernel with the fast index along xi_1:
-//   V[j2][k1] = sum_a B1[k1][a] u(e1(k1) + a, j2)              (u on the xi_1 points)
-//   G[k2][k1] = c_k sum_a B2[k2][a] V[e2(k2) + a][k1]          (c U on the grid; U alone for the adjoint)
-//   H[k2][i1] = sum_q w1[i1][q] G[k2][k0(i1) + q]              (test rows along xi_1)
-//   y(i1, i2) = sum_q w2[i2][q] H[k0(i2) + q][i1]              (interior rows)
+// The weighted-quadrature part as banded one-dimensional contractions (sum
+// factorisation), fast index along xi_1:
+//   V[j2][k1] = sum_a B1[k1][a] u(e1(k1) + a, j2)              (u on the xi_1 points; k_mf_v)
+//   G[k2][k1] = c_k sum_a B2[k2][a] V[e2(k2) + a][k1]          (c U along grid row k2, in LDS; k_mf_gh)
+//   H[k2][i1] = sum_q w1[i1][q] G[k2][k0(i1) + q]              (test rows along xi_1; k_mf_gh)
+//   y(i1, i2) = sum_q w2[i2][q] H[k0(i2) + q][i1]              (interior rows; k_mf_y)
 // and, transposed, for the adjoint
-//   H[k2][i1] = sum_{i2 : k2 in supp} w2[i2][k2 - k0(i2)] r(i1, i2)
-//   R[k2][k1] = sum_{i1 : k1 in supp} w1[i1][k1 - k0(i1)] H[k2][i1],  dc = U R, CR = c R
-//   D[k2][j1] = sum_{k1 in supp j1} B1[k1][j1 - e1(k1)] CR[k2][k1]
-//   du(j1, j2) += sum_{k2 in supp j2} B2[k2][j2 - e2(k2)] D[k2][j1]   (in the gather kernel)
+//   H[k2][i1] = sum_{i2 : k2 in supp} w2[i2][k2 - k0(i2)] r(i1, i2)                    (k_mf_hadj)
+//   R[k2][k1] = sum_{i1 : k1 in supp} w1[i1][k1 - k0(i1)] H[k2][i1],  dc = U R, c R      (k_mf_rd, per row)
+//   D[k2][j1] = sum_{k1 in supp j1} B1[k1][j1 - e1(k1)] c R[k2][k1]                    (k_mf_rd)
+//   du(j1, j2) += sum_{k2 in supp j2} B2[k2][j2 - e2(k2)] D[k2][j1]                    (k_mf_gather)
+// G, U, R and c R never leave their workgroup.
 template <int P>
 __global__ void __launch_bounds__(256) k_mf_v(MfArgs A, const double* __restrict__ u, double* __restrict__ V) {
     const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -65,42 +66,6 @@ __global__ void __launch_bounds__(256) k_mf_v(MfArgs A, const double* __restrict
         s += A.d1.Bq[(size_t)k1 * (P + 1) + a] * (cid[a] >= 0 ? uv : 0.0);
     }
     V[t] = s;
-}
-
-template <int P>
-__global__ void __launch_bounds__(256) k_mf_g(MfArgs A, const double* __restrict__ V, double* __restrict__ G,
-                                              int times_c) {
-    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    const int Q1 = A.d1.Q;
-    if (t >= (int64_t)A.nq) return;
-    const int k1 = (int)(t % Q1), k2 = (int)(t / Q1);
-    const int e2 = A.d2.eq[k2];
-    double v[P + 1];
-#pragma unroll
-    for (int a = 0; a <= P; ++a) v[a] = V[(size_t)(e2 + a) * Q1 + k1];
-    double s = 0.0;
-#pragma unroll
-    for (int a = 0; a <= P; ++a) s += A.d2.Bq[(size_t)k2 * (P + 1) + a] * v[a];
-    G[t] = times_c ? A.c[t] * s : s;
-}
-
-template <int P>
-__global__ void __launch_bounds__(256) k_mf_h(MfArgs A, const double* __restrict__ G, double* __restrict__ H) {
-    constexpr int QM = 4 * P + 2;
-    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    const int n1 = A.n1, Q1 = A.d1.Q;
-    if (t >= (int64_t)A.d2.Q * n1) return;
-    const int i1 = (int)(t % n1), k2 = (int)(t / n1);
-    const int k0 = A.d1.pt0[max(0, i1 - P)], q1 = A.d1.pt0[min(A.N1 - 1, i1) + 1] - k0;
-    const double* g = G + (size_t)k2 * Q1 + k0;
-    const double* w = A.d1.W + (size_t)i1 * A.d1.qmax;
-    double s = 0.0;
-#pragma unroll
-    for (int q = 0; q < QM; ++q) {
-        if (q >= q1) break;
-        s += w[q] * g[q];
-    }
-    H[t] = s;
 }
 
 template <int P>
@@ -144,42 +109,93 @@ __global__ void __launch_bounds__(256) k_mf_hadj(MfArgs A, const double* __restr
     H[t] = s;
 }
 
+// Weight w1[i1][q] of a test row, from the rows-contiguous copy where it holds it.
 template <int P>
-__global__ void __launch_bounds__(256) k_mf_radj(MfArgs A, const double* __restrict__ H, const double* __restrict__ U,
-                                                 double* __restrict__ dc, double* __restrict__ CR) {
-    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    const int Q1 = A.d1.Q, n1 = A.n1;
-    if (t >= (int64_t)A.nq) return;
-    const int k1 = (int)(t % Q1), k2 = (int)(t / Q1);
-    const int e1 = A.d1.eq[k1];
-    double s = 0.0;
-#pragma unroll
-    for (int a = 0; a <= P; ++a) {
-        const int i1 = e1 + a;
-        if (i1 >= n1) break;
-        const double w1 = A.d1.W[(size_t)i1 * A.d1.qmax + (k1 - A.d1.pt0[max(0, i1 - P)])];
-        s += w1 * H[(size_t)k2 * n1 + i1];
-    }
-    dc[t] = U[t] * s;
-    CR[t] = A.c[t] * s;
+__device__ __forceinline__ double w1_at(const MfArgs& A, int i1, int q) {
+    return (q < 2 * P + 2) ? A.d1.WT[(size_t)q * A.n1 + i1] : A.d1.W[(size_t)i1 * A.d1.qmax + q];
 }
 
+// Forward, one workgroup per grid row k2: G = c U along the row in LDS, then
+// the row's xi_1 test sums H[k2][i1] (G never leaves the workgroup).
 template <int P>
-__global__ void __launch_bounds__(256) k_mf_dadj(MfArgs A, const double* __restrict__ CR, double* __restrict__ D) {
+__global__ void __launch_bounds__(256) k_mf_gh(MfArgs A, const double* __restrict__ V, double* __restrict__ H) {
+    extern __shared__ double sG[];  // Q1
     constexpr int QM = 4 * P + 2;
-    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    const int n1 = A.n1, Q1 = A.d1.Q;
-    if (t >= (int64_t)A.d2.Q * n1) return;
-    const int j1 = (int)(t % n1), k2 = (int)(t / n1);
-    const int k0 = A.d1.pt0[max(0, j1 - P)], q1 = A.d1.pt0[min(A.N1 - 1, j1) + 1] - k0;
-    double s = 0.0;
+    const int k2 = blockIdx.x, Q1 = A.d1.Q, n1 = A.n1;
+    const int e2 = A.d2.eq[k2];
+    double b2[P + 1];
 #pragma unroll
-    for (int q = 0; q < QM; ++q) {
-        if (q >= q1) break;
-        const int k1 = k0 + q;
-        s += A.d1.Bq[(size_t)k1 * (P + 1) + (j1 - A.d1.eq[k1])] * CR[(size_t)k2 * Q1 + k1];
+    for (int a = 0; a <= P; ++a) b2[a] = A.d2.Bq[(size_t)k2 * (P + 1) + a];
+    for (int k1 = threadIdx.x; k1 < Q1; k1 += 256) {
+        double v[P + 1];
+#pragma unroll
+        for (int a = 0; a <= P; ++a) v[a] = V[(size_t)(e2 + a) * Q1 + k1];
+        double s = 0.0;
+#pragma unroll
+        for (int a = 0; a <= P; ++a) s += b2[a] * v[a];
+        sG[k1] = A.c[(size_t)k2 * Q1 + k1] * s;
     }
-    D[t] = s;
+    __syncthreads();
+    for (int i1 = threadIdx.x; i1 < n1; i1 += 256) {
+        const int k0 = A.d1.pt0[max(0, i1 - P)], q1 = A.d1.pt0[min(A.N1 - 1, i1) + 1] - k0;
+        double s = 0.0;
+#pragma unroll
+        for (int q = 0; q < QM; ++q) {
+            if (q >= q1) break;
+            s += w1_at<P>(A, i1, q) * sG[k0 + q];
+        }
+        H[(size_t)k2 * n1 + i1] = s;
+    }
+}
+
+// Adjoint, one workgroup per grid row k2: the row's w2-weighted residual sums
+// (H, staged in LDS), R along the row, dc = U R with U from V, c R in LDS,
+// then the row's xi_1 basis sums D[k2][j1], written over H's row.
+template <int P>
+__global__ void __launch_bounds__(256) k_mf_rd(MfArgs A, const double* __restrict__ V, double* __restrict__ HD,
+                                               double* __restrict__ dc) {
+    extern __shared__ double sm[];  // n1 (H row), then Q1 (c R)
+    constexpr int QM = 4 * P + 2;
+    const int k2 = blockIdx.x, Q1 = A.d1.Q, n1 = A.n1;
+    double* sH = sm;
+    double* sCR = sm + n1;
+    for (int i1 = threadIdx.x; i1 < n1; i1 += 256) sH[i1] = HD[(size_t)k2 * n1 + i1];
+    const int e2 = A.d2.eq[k2];
+    double b2[P + 1];
+#pragma unroll
+    for (int a = 0; a <= P; ++a) b2[a] = A.d2.Bq[(size_t)k2 * (P + 1) + a];
+    __syncthreads();
+    for (int k1 = threadIdx.x; k1 < Q1; k1 += 256) {
+        const int e1 = A.d1.eq[k1];
+        double v[P + 1];
+#pragma unroll
+        for (int a = 0; a <= P; ++a) v[a] = V[(size_t)(e2 + a) * Q1 + k1];
+        double U = 0.0;
+#pragma unroll
+        for (int a = 0; a <= P; ++a) U += b2[a] * v[a];
+        double R = 0.0;
+#pragma unroll
+        for (int a = 0; a <= P; ++a) {
+            const int i1 = e1 + a;
+            if (i1 >= n1) break;
+            R += w1_at<P>(A, i1, k1 - A.d1.pt0[max(0, i1 - P)]) * sH[i1];
+        }
+        const size_t k = (size_t)k2 * Q1 + k1;
+        dc[k] = U * R;
+        sCR[k1] = A.c[k] * R;
+    }
+    __syncthreads();
+    for (int j1 = threadIdx.x; j1 < n1; j1 += 256) {
+        const int k0 = A.d1.pt0[max(0, j1 - P)], q1 = A.d1.pt0[min(A.N1 - 1, j1) + 1] - k0;
+        double s = 0.0;
+#pragma unroll
+        for (int q = 0; q < QM; ++q) {
+            if (q >= q1) break;
+            const int k1 = k0 + q;
+            s += A.d1.Bq[(size_t)k1 * (P + 1) + (j1 - A.d1.eq[k1])] * sCR[k1];
+        }
+        HD[(size_t)k2 * n1 + j1] = s;
+    }
 }
 
 // Element part: per band / cut element, forward Y_e[l] = sum_g w_g c_g U_g B_l(x_g),
@@ -339,42 +355,16 @@ static MfArgs mf_args(Plan& P, const double* c) {
 }
 
 static void mf_buffers(Plan& P) {
-    size_t nq = (size_t)P.dir[0].Q * P.dir[1].Q;
     size_t L = (size_t)(P.p + 1) * (P.p + 1);
-    if (!P.sw.G) P.sw.G = P.alloc<double>(nq);
-    if (!P.sw.CR) P.sw.CR = P.alloc<double>(nq);
+    // one grid row of xi_1 points and one row of functions in LDS
+    IGA_REQUIRE(sizeof(double) * ((size_t)P.dir[0].Q + P.n1) <= 65536, IGA_E_UNSUPPORTED,
+                "matrix-free product: more than 2700 elements along xi_1");
     if (!P.sw.V) P.sw.V = P.alloc<double>((size_t)P.n2 * P.dir[0].Q);
     if (!P.sw.H) P.sw.H = P.alloc<double>((size_t)P.dir[1].Q * P.n1);
     if (!P.sw.Ue) P.sw.Ue = P.alloc<double>(std::max<int64_t>(1, P.n_band + P.n_cut_el) * L);
 }
 
 static dim3 grid256(int64_t n) { return dim3((unsigned)((n + 255) / 256)); }
-
-// U on the WQ grid (times c if times_c) into G.
-template <int P>
-static void launch_u_grid(Plan& Pl, const MfArgs& A, const double* u, int times_c, hipStream_t s) {
-    hipLaunchKernelGGL(k_mf_v<P>, grid256((int64_t)Pl.n2 * A.d1.Q), dim3(256), 0, s, A, u, Pl.sw.V);
-    hipLaunchKernelGGL(k_mf_g<P>, grid256(A.nq), dim3(256), 0, s, A, (const double*)Pl.sw.V, Pl.sw.G, times_c);
-}
-
-template <int P>
-static void launch_wq_forward(Plan& Pl, const MfArgs& A, const double* u, double* y, hipStream_t s) {
-    launch_u_grid<P>(Pl, A, u, 1, s);
-    hipLaunchKernelGGL(k_mf_h<P>, grid256((int64_t)A.d2.Q * Pl.n1), dim3(256), 0, s, A, (const double*)Pl.sw.G,
-                       Pl.sw.H);
-    hipLaunchKernelGGL(k_mf_y<P>, grid256((int64_t)Pl.n1 * Pl.n2), dim3(256), 0, s, A, (const double*)Pl.sw.H, y);
-}
-
-template <int P>
-static void launch_wq_adjoint(Plan& Pl, const MfArgs& A, const double* u, const double* r, double* dc,
-                              hipStream_t s) {
-    launch_u_grid<P>(Pl, A, u, 0, s);  // U
-    const int64_t nh = (int64_t)A.d2.Q * Pl.n1;
-    hipLaunchKernelGGL(k_mf_hadj<P>, grid256(nh), dim3(256), 0, s, A, r, Pl.sw.H);
-    hipLaunchKernelGGL(k_mf_radj<P>, grid256(A.nq), dim3(256), 0, s, A, (const double*)Pl.sw.H,
-                       (const double*)Pl.sw.G, dc, Pl.sw.CR);
-    hipLaunchKernelGGL(k_mf_dadj<P>, grid256(nh), dim3(256), 0, s, A, (const double*)Pl.sw.CR, Pl.sw.H);  // D
-}
 
 static void launch_elem(Plan& P, const MfArgs& A, const double* u, const double* r, double* Ye, double* dc,
                         hipStream_t s) {
@@ -386,6 +376,23 @@ static void launch_elem(Plan& P, const MfArgs& A, const double* u, const double*
         CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
 #undef CASE
     }
+}
+
+template <int P>
+static void launch_wq_forward(Plan& Pl, const MfArgs& A, const double* u, double* y, hipStream_t s) {
+    hipLaunchKernelGGL(k_mf_v<P>, grid256((int64_t)Pl.n2 * A.d1.Q), dim3(256), 0, s, A, u, Pl.sw.V);
+    hipLaunchKernelGGL(k_mf_gh<P>, dim3(A.d2.Q), dim3(256), sizeof(double) * A.d1.Q, s, A, (const double*)Pl.sw.V,
+                       Pl.sw.H);
+    hipLaunchKernelGGL(k_mf_y<P>, grid256((int64_t)Pl.n1 * Pl.n2), dim3(256), 0, s, A, (const double*)Pl.sw.H, y);
+}
+
+template <int P>
+static void launch_wq_adjoint(Plan& Pl, const MfArgs& A, const double* u, const double* r, double* dc,
+                              hipStream_t s) {
+    hipLaunchKernelGGL(k_mf_v<P>, grid256((int64_t)Pl.n2 * A.d1.Q), dim3(256), 0, s, A, u, Pl.sw.V);
+    hipLaunchKernelGGL(k_mf_hadj<P>, grid256((int64_t)A.d2.Q * Pl.n1), dim3(256), 0, s, A, r, Pl.sw.H);
+    hipLaunchKernelGGL(k_mf_rd<P>, dim3(A.d2.Q), dim3(256), sizeof(double) * (A.d1.Q + Pl.n1), s, A,
+                       (const double*)Pl.sw.V, Pl.sw.H, dc);  // D over H
 }
 
 void mf_apply(Plan& P, const double* c, const double* u, double* y, hipStream_t s) {
@@ -409,7 +416,6 @@ void mf_adjoint(Plan& P, const double* c, const double* u, const double* r, doub
     mf_buffers(P);
     MfArgs A = mf_args(P, c);
     int n = (int)P.n_act;
-    size_t nq = (size_t)A.nq;
     if (P.method != IGA_GAUSS_REF) {
         switch (P.p) {
 #define CASE(PP) \
@@ -418,7 +424,7 @@ void mf_adjoint(Plan& P, const double* c, const double* u, const double* r, doub
 #undef CASE
         }
     } else {
-        HIPX(hipMemsetAsync(dc, 0, sizeof(double) * nq, s));
+        HIPX(hipMemsetAsync(dc, 0, sizeof(double) * (size_t)A.nq, s));
     }
     launch_elem(P, A, u, r, P.sw.Ue, dc, s);
     // the grid part of du reads D (held in H) through the CR argument

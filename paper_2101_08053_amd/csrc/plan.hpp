@@ -134,10 +134,8 @@ struct SolveWork {
     double* A = nullptr;      // (M + M^T)/2
     double *r = nullptr, *z = nullptr, *pv = nullptr, *q = nullptr, *part = nullptr, *scal = nullptr, *b = nullptr;
     double* h_scal = nullptr; // pinned host copy of the scalars
-    double* G = nullptr;      // matrix-free: c U (forward) or U (adjoint) on the WQ grid [Q2][Q1]
     double* V = nullptr;      // matrix-free: u contracted along xi_1 [n2][Q1]
     double* H = nullptr;      // matrix-free: xi_1 row sums [Q2][n1] (forward), w2 r, then B1 c R (adjoint)
-    double* CR = nullptr;     // matrix-free adjoint: c R on the WQ grid [Q2][Q1]
     double* Ue = nullptr;     // matrix-free: element vectors
 };
 
