@@ -30,6 +30,8 @@ struct MfArgs {
     int n_band, n_cut, n_act;
     const double* c;   // n_points, plan point order
     int nq, nb;        // point offsets: band points start at nq, cut nodes at nq + nb
+    const double* WA;  // [Q1][p+1]: w1[e1(k1) + a][k1 - k0(e1(k1) + a)], 0 past the last function
+    const double* BR;  // [4p+2][n1]: B_j1(x_{k0(j1) + q}), 0 past the row's points
 };
 
 __device__ __forceinline__ bool wq_row(const MfArgs& A, int8_t cls) {
@@ -109,40 +111,66 @@ __global__ void __launch_bounds__(256) k_mf_hadj(MfArgs A, const double* __restr
     H[t] = s;
 }
 
-// Weight w1[i1][q] of a test row, from the rows-contiguous copy where it holds it.
+// Per-point and per-function views of the xi_1 tables that the grid-row
+// kernels read at every row: the test weights that meet at a point (WA) and
+// a function's basis values at its support points (BR, functions contiguous).
 template <int P>
-__device__ __forceinline__ double w1_at(const MfArgs& A, int i1, int q) {
-    return (q < 2 * P + 2) ? A.d1.WT[(size_t)q * A.n1 + i1] : A.d1.W[(size_t)i1 * A.d1.qmax + q];
+__global__ void __launch_bounds__(256) k_mf_tables(DirDev D, int n1, double* __restrict__ WA, double* __restrict__ BR) {
+    constexpr int QM = 4 * P + 2;
+    const int t = blockIdx.x * 256 + threadIdx.x;
+    if (t < D.Q * (P + 1)) {
+        const int k1 = t / (P + 1), a = t % (P + 1), i1 = D.eq[k1] + a;
+        WA[t] = (i1 < n1) ? D.W[(size_t)i1 * D.qmax + (k1 - D.pt0[max(0, i1 - P)])] : 0.0;
+    }
+    if (t < QM * n1) {
+        const int q = t / n1, j1 = t % n1;
+        const int k0 = D.pt0[max(0, j1 - P)], q1 = D.pt0[min(D.N - 1, j1) + 1] - k0;
+        BR[t] = (q < q1) ? D.Bq[(size_t)(k0 + q) * (P + 1) + (j1 - D.eq[k0 + q])] : 0.0;
+    }
 }
 
 // Forward, one workgroup per grid row k2: G = c U along the row in LDS, then
-// the row's xi_1 test sums H[k2][i1] (G never leaves the workgroup).
+// the row's xi_1 test sums H[k2][i1] (G never leaves the workgroup). Each
+// thread takes four points (or functions) at a time, loads first.
 template <int P>
 __global__ void __launch_bounds__(256) k_mf_gh(MfArgs A, const double* __restrict__ V, double* __restrict__ H) {
     extern __shared__ double sG[];  // Q1
-    constexpr int QM = 4 * P + 2;
+    constexpr int QM = 4 * P + 2, NB = 4;
     const int k2 = blockIdx.x, Q1 = A.d1.Q, n1 = A.n1;
     const int e2 = A.d2.eq[k2];
     double b2[P + 1];
 #pragma unroll
     for (int a = 0; a <= P; ++a) b2[a] = A.d2.Bq[(size_t)k2 * (P + 1) + a];
-    for (int k1 = threadIdx.x; k1 < Q1; k1 += 256) {
-        double v[P + 1];
+    const double* Vr = V + (size_t)e2 * Q1;
+    const double* cr = A.c + (size_t)k2 * Q1;
+#pragma unroll 1
+    for (int kb = threadIdx.x; kb < Q1; kb += 256 * NB) {
+        double v[NB][P + 1], cv[NB];
 #pragma unroll
-        for (int a = 0; a <= P; ++a) v[a] = V[(size_t)(e2 + a) * Q1 + k1];
-        double s = 0.0;
+        for (int j = 0; j < NB; ++j) {
+            const int k1 = min(kb + 256 * j, Q1 - 1);
 #pragma unroll
-        for (int a = 0; a <= P; ++a) s += b2[a] * v[a];
-        sG[k1] = A.c[(size_t)k2 * Q1 + k1] * s;
+            for (int a = 0; a <= P; ++a) v[j][a] = Vr[(size_t)a * Q1 + k1];
+            cv[j] = cr[k1];
+        }
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+            double s = 0.0;
+#pragma unroll
+            for (int a = 0; a <= P; ++a) s += b2[a] * v[j][a];
+            if (kb + 256 * j < Q1) sG[kb + 256 * j] = cv[j] * s;
+        }
     }
     __syncthreads();
+#pragma unroll 1
     for (int i1 = threadIdx.x; i1 < n1; i1 += 256) {
         const int k0 = A.d1.pt0[max(0, i1 - P)], q1 = A.d1.pt0[min(A.N1 - 1, i1) + 1] - k0;
         double s = 0.0;
 #pragma unroll
         for (int q = 0; q < QM; ++q) {
             if (q >= q1) break;
-            s += w1_at<P>(A, i1, q) * sG[k0 + q];
+            const double w = (q < 2 * P + 2) ? A.d1.WT[(size_t)q * n1 + i1] : A.d1.W[(size_t)i1 * A.d1.qmax + q];
+            s += w * sG[k0 + q];
         }
         H[(size_t)k2 * n1 + i1] = s;
     }
@@ -155,7 +183,7 @@ template <int P>
 __global__ void __launch_bounds__(256) k_mf_rd(MfArgs A, const double* __restrict__ V, double* __restrict__ HD,
                                                double* __restrict__ dc) {
     extern __shared__ double sm[];  // n1 (H row), then Q1 (c R)
-    constexpr int QM = 4 * P + 2;
+    constexpr int QM = 4 * P + 2, NB = 4;
     const int k2 = blockIdx.x, Q1 = A.d1.Q, n1 = A.n1;
     double* sH = sm;
     double* sCR = sm + n1;
@@ -164,36 +192,49 @@ __global__ void __launch_bounds__(256) k_mf_rd(MfArgs A, const double* __restric
     double b2[P + 1];
 #pragma unroll
     for (int a = 0; a <= P; ++a) b2[a] = A.d2.Bq[(size_t)k2 * (P + 1) + a];
+    const double* Vr = V + (size_t)e2 * Q1;
+    const double* cr = A.c + (size_t)k2 * Q1;
     __syncthreads();
-    for (int k1 = threadIdx.x; k1 < Q1; k1 += 256) {
-        const int e1 = A.d1.eq[k1];
-        double v[P + 1];
+#pragma unroll 1
+    for (int kb = threadIdx.x; kb < Q1; kb += 256 * NB) {
+        double v[NB][P + 1], wa[NB][P + 1], cv[NB];
+        int e1[NB];
 #pragma unroll
-        for (int a = 0; a <= P; ++a) v[a] = V[(size_t)(e2 + a) * Q1 + k1];
-        double U = 0.0;
+        for (int j = 0; j < NB; ++j) {
+            const int k1 = min(kb + 256 * j, Q1 - 1);
+            e1[j] = A.d1.eq[k1];
 #pragma unroll
-        for (int a = 0; a <= P; ++a) U += b2[a] * v[a];
-        double R = 0.0;
-#pragma unroll
-        for (int a = 0; a <= P; ++a) {
-            const int i1 = e1 + a;
-            if (i1 >= n1) break;
-            R += w1_at<P>(A, i1, k1 - A.d1.pt0[max(0, i1 - P)]) * sH[i1];
+            for (int a = 0; a <= P; ++a) {
+                v[j][a] = Vr[(size_t)a * Q1 + k1];
+                wa[j][a] = A.WA[(size_t)k1 * (P + 1) + a];
+            }
+            cv[j] = cr[k1];
         }
-        const size_t k = (size_t)k2 * Q1 + k1;
-        dc[k] = U * R;
-        sCR[k1] = A.c[k] * R;
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+            double U = 0.0, R = 0.0;
+#pragma unroll
+            for (int a = 0; a <= P; ++a) {
+                U += b2[a] * v[j][a];
+                R += wa[j][a] * sH[min(e1[j] + a, n1 - 1)];  // 0 weight past the last function
+            }
+            const int k1 = kb + 256 * j;
+            if (k1 < Q1) {
+                dc[(size_t)k2 * Q1 + k1] = U * R;
+                sCR[k1] = cv[j] * R;
+            }
+        }
     }
     __syncthreads();
+#pragma unroll 1
     for (int j1 = threadIdx.x; j1 < n1; j1 += 256) {
-        const int k0 = A.d1.pt0[max(0, j1 - P)], q1 = A.d1.pt0[min(A.N1 - 1, j1) + 1] - k0;
+        const int k0 = A.d1.pt0[max(0, j1 - P)];
+        double br[QM];
+#pragma unroll
+        for (int q = 0; q < QM; ++q) br[q] = A.BR[(size_t)q * n1 + j1];
         double s = 0.0;
 #pragma unroll
-        for (int q = 0; q < QM; ++q) {
-            if (q >= q1) break;
-            const int k1 = k0 + q;
-            s += A.d1.Bq[(size_t)k1 * (P + 1) + (j1 - A.d1.eq[k1])] * sCR[k1];
-        }
+        for (int q = 0; q < QM; ++q) s += br[q] * sCR[min(k0 + q, Q1 - 1)];  // 0 past the row's points
         HD[(size_t)k2 * n1 + j1] = s;
     }
 }
@@ -351,6 +392,8 @@ static MfArgs mf_args(Plan& P, const double* c) {
     A.c = c;
     A.nq = P.dir[0].Q * P.dir[1].Q;
     A.nb = (int)P.n_band * (P.p + 1) * (P.p + 1);
+    A.WA = P.sw.WA;
+    A.BR = P.sw.BR;
     return A;
 }
 
@@ -362,6 +405,8 @@ static void mf_buffers(Plan& P) {
     if (!P.sw.V) P.sw.V = P.alloc<double>((size_t)P.n2 * P.dir[0].Q);
     if (!P.sw.H) P.sw.H = P.alloc<double>((size_t)P.dir[1].Q * P.n1);
     if (!P.sw.Ue) P.sw.Ue = P.alloc<double>(std::max<int64_t>(1, P.n_band + P.n_cut_el) * L);
+    if (!P.sw.WA) P.sw.WA = P.alloc<double>((size_t)P.dir[0].Q * (P.p + 1));
+    if (!P.sw.BR) P.sw.BR = P.alloc<double>((size_t)(4 * P.p + 2) * P.n1);
 }
 
 static dim3 grid256(int64_t n) { return dim3((unsigned)((n + 255) / 256)); }
@@ -389,6 +434,8 @@ static void launch_wq_forward(Plan& Pl, const MfArgs& A, const double* u, double
 template <int P>
 static void launch_wq_adjoint(Plan& Pl, const MfArgs& A, const double* u, const double* r, double* dc,
                               hipStream_t s) {
+    const int nt = std::max(A.d1.Q * (P + 1), (4 * P + 2) * Pl.n1);  // the weights may have been injected
+    hipLaunchKernelGGL(k_mf_tables<P>, grid256(nt), dim3(256), 0, s, A.d1, Pl.n1, Pl.sw.WA, Pl.sw.BR);
     hipLaunchKernelGGL(k_mf_v<P>, grid256((int64_t)Pl.n2 * A.d1.Q), dim3(256), 0, s, A, u, Pl.sw.V);
     hipLaunchKernelGGL(k_mf_hadj<P>, grid256((int64_t)A.d2.Q * Pl.n1), dim3(256), 0, s, A, r, Pl.sw.H);
     hipLaunchKernelGGL(k_mf_rd<P>, dim3(A.d2.Q), dim3(256), sizeof(double) * (A.d1.Q + Pl.n1), s, A,

@@ -137,6 +137,8 @@ struct SolveWork {
     double* V = nullptr;      // matrix-free: u contracted along xi_1 [n2][Q1]
     double* H = nullptr;      // matrix-free: xi_1 row sums [Q2][n1] (forward), w2 r, then B1 c R (adjoint)
     double* Ue = nullptr;     // matrix-free: element vectors
+    double* WA = nullptr;     // matrix-free adjoint: test weights meeting at each xi_1 point [Q1][p+1]
+    double* BR = nullptr;     // matrix-free adjoint: basis values at each function's xi_1 points [4p+2][n1]
 };
 
 struct Plan {
