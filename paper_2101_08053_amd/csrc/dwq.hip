@@ -27,7 +27,7 @@ struct DwqCfg {
 };
 
 template <int P>
-__global__ void __launch_bounds__(64 * (P + 1)) k_dwq_sides(DirDev D1, DirDev D2, const double* __restrict__ gx,
+__global__ void __launch_bounds__(128) k_dwq_sides(DirDev D1, DirDev D2, const double* __restrict__ gx,
                                                             const double* __restrict__ gw, int* __restrict__ status) {
     using C = DwqCfg<P>;
     constexpr int KQ = C::KQ, NK = C::NK, M = C::M;
@@ -143,56 +143,60 @@ __global__ void __launch_bounds__(64 * (P + 1)) k_dwq_sides(DirDev D1, DirDev D2
     __syncthreads();
 
     const int np = sInfo[0], n_fun = sInfo[1], nEl = sInfo[2];
-    const int r = wave;  // refined function of this wavefront
-    if (r < n_fun) {
-        const int kr = min(r, nEl - 1);               // last local element of supp B~_r
-        const int q = sCnt[kr + 1];                   // its points
-        const int m = min(r + P, n_fun - 1) + 1;      // trial functions 0..m-1
-        double a[M], a0[M];
+    // two wavefronts take the p+1 refined functions in turn (two-wavefront
+    // workgroups: four fit on a CU beside each other at this register count)
+#pragma unroll 1
+    for (int r = wave; r <= P; r += 2) {
+        if (r < n_fun) {
+            const int kr = min(r, nEl - 1);               // last local element of supp B~_r
+            const int q = sCnt[kr + 1];                   // its points
+            const int m = min(r + P, n_fun - 1) + 1;      // trial functions 0..m-1
+            double a[M], a0[M];
 #pragma unroll
-        for (int c = 0; c < M; ++c) a[c] = 0.0;
-        if (lane < q) {
-            const int k = sEl[lane];
-            double Nv[P + 1];
-            basis_eval<P>(sRK, P + k, sU[lane], Nv);
+            for (int c = 0; c < M; ++c) a[c] = 0.0;
+            if (lane < q) {
+                const int k = sEl[lane];
+                double Nv[P + 1];
+                basis_eval<P>(sRK, P + k, sU[lane], Nv);
 #pragma unroll
-            for (int c = 0; c < M; ++c)
-                if (c < m && c >= k && c <= k + P) a[c] = Nv[c - k];
+                for (int c = 0; c < M; ++c)
+                    if (c < m && c >= k && c <= k + P) a[c] = Nv[c - k];
+            }
+#pragma unroll
+            for (int c = 0; c < M; ++c) a0[c] = a[c];
+            // moments int B~_c B~_r over the elements of supp B~_r, (p+1)-point Gauss
+            double mom[M];
+#pragma unroll
+            for (int c = 0; c < M; ++c) mom[c] = 0.0;
+            for (int pg = lane; pg < (kr + 1) * (P + 1); pg += 64) {
+                const int k = pg / (P + 1), g = pg % (P + 1);
+                const double ua = sRK[P + k], ub = sRK[P + k + 1];
+                const double xg = ua + (ub - ua) * (gx[gauss_off(P + 1) + g] + 1.0) * 0.5;
+                const double wgt = gw[gauss_off(P + 1) + g] * (ub - ua) * 0.5;
+                double Nv[P + 1];
+                basis_eval<P>(sRK, P + k, xg, Nv);
+                const double br = (r >= k && r <= k + P) ? Nv[r - k] : 0.0;
+#pragma unroll
+                for (int c = 0; c < M; ++c)
+                    if (c >= k && c <= k + P) mom[c] += wgt * Nv[c - k] * br;
+            }
+#pragma unroll
+            for (int c = 0; c < M; ++c) mom[c] = wave_sum(mom[c]);
+            bool singular = false;
+            const double y = wave_min_norm<M>(a, q, m, [&](int c) { return mom[c]; }, singular);
+            double rmax = 0.0, bmax = 0.0;
+#pragma unroll
+            for (int c = 0; c < M; ++c) {
+                if (c >= m) break;
+                const double rc = wave_sum(a0[c] * y);
+                rmax = fmax(rmax, fabs(rc - mom[c]));
+                bmax = fmax(bmax, fabs(mom[c]));
+            }
+            if (lane < KQ) sWt[r][lane] = y;
+            if (lane == 0 && (singular || !(rmax <= 1e-12 * bmax))) atomicExch(status, IGA_E_SINGULAR_WEIGHTS);
+        } else if (lane < KQ) {
+            sWt[r][lane] = 0.0;
         }
-#pragma unroll
-        for (int c = 0; c < M; ++c) a0[c] = a[c];
-        // moments int B~_c B~_r over the elements of supp B~_r, (p+1)-point Gauss
-        double mom[M];
-#pragma unroll
-        for (int c = 0; c < M; ++c) mom[c] = 0.0;
-        for (int pg = lane; pg < (kr + 1) * (P + 1); pg += 64) {
-            const int k = pg / (P + 1), g = pg % (P + 1);
-            const double ua = sRK[P + k], ub = sRK[P + k + 1];
-            const double xg = ua + (ub - ua) * (gx[gauss_off(P + 1) + g] + 1.0) * 0.5;
-            const double wgt = gw[gauss_off(P + 1) + g] * (ub - ua) * 0.5;
-            double Nv[P + 1];
-            basis_eval<P>(sRK, P + k, xg, Nv);
-            const double br = (r >= k && r <= k + P) ? Nv[r - k] : 0.0;
-#pragma unroll
-            for (int c = 0; c < M; ++c)
-                if (c >= k && c <= k + P) mom[c] += wgt * Nv[c - k] * br;
-        }
-#pragma unroll
-        for (int c = 0; c < M; ++c) mom[c] = wave_sum(mom[c]);
-        bool singular = false;
-        const double y = wave_min_norm<M>(a, q, m, [&](int c) { return mom[c]; }, singular);
-        double rmax = 0.0, bmax = 0.0;
-#pragma unroll
-        for (int c = 0; c < M; ++c) {
-            if (c >= m) break;
-            const double rc = wave_sum(a0[c] * y);
-            rmax = fmax(rmax, fabs(rc - mom[c]));
-            bmax = fmax(bmax, fabs(mom[c]));
-        }
-        if (lane < KQ) sWt[r][lane] = y;
-        if (lane == 0 && (singular || !(rmax <= 1e-12 * bmax))) atomicExch(status, IGA_E_SINGULAR_WEIGHTS);
-    } else if (lane < KQ) {
-        sWt[r][lane] = 0.0;
     }
     __syncthreads();
 
@@ -405,7 +409,7 @@ void launch_dwq_sides(Plan& P, hipStream_t s) {
     if (P.method != IGA_DWQ) return;
     const int nb = 2 * (P.dir[0].N - 1) + 2 * (P.dir[1].N - 1);
     if (nb <= 0) return;
-    dim3 g(nb), b(64 * (P.p + 1));
+    dim3 g(nb), b(128);
     switch (P.p) {
 #define CASE(PP) \
     case PP: hipLaunchKernelGGL(k_dwq_sides<PP>, g, b, 0, s, P.dir[0], P.dir[1], P.gauss_x, P.gauss_w, P.status); break;
