@@ -241,47 +241,67 @@ __device__ __forceinline__ void dwq_option(int k, int lo, int hi, int& a, int& b
     }
 }
 
+// One wavefront per row: lanes test the (I1, I2) options in parallel; the
+// choice -- largest box, then fewer discontinuities, then first option in
+// the enumeration order -- is a maximum of one 64-bit key over the lanes.
 template <int P>
-__global__ void k_dwq_choose(int N1, int N2, int n1, const int* __restrict__ rows, int n_rows,
-                             const int* __restrict__ fn_of, const int8_t* __restrict__ ecls, int* __restrict__ region) {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ void __launch_bounds__(64) k_dwq_choose(int N1, int N2, int n1, const int* __restrict__ rows, int n_rows,
+                                                   const int* __restrict__ fn_of, const int8_t* __restrict__ ecls,
+                                                   int* __restrict__ region) {
+    __shared__ unsigned s_rowm[P + 1];
+    const int t = blockIdx.x, lane = threadIdx.x;
     if (t >= n_rows) return;
     const int f = fn_of[rows[t]];
     const int i1 = f % n1, i2 = f / n1;
     const int lo1 = max(0, i1 - P), hi1 = min(N1 - 1, i1), lo2 = max(0, i2 - P), hi2 = min(N2 - 1, i2);
-    unsigned rowm[P + 1];
-#pragma unroll
-    for (int m2 = 0; m2 <= P; ++m2) {
+    if (lane <= P) {  // inside elements of support row lo2 + lane, one bit per column
         unsigned v = 0;
-        if (lo2 + m2 <= hi2)
-            for (int m1 = 0; m1 <= hi1 - lo1; ++m1)
-                if (ecls[(size_t)(lo2 + m2) * N1 + lo1 + m1] == EL_INSIDE) v |= 1u << m1;
-        rowm[m2] = v;
-    }
-    int best_n = 0, best_d = 3;
-    int R[8] = {-1, -1, -1, -1, -1, -1, -1, -1};
-    const int no1 = 1 + 2 * (hi1 - lo1), no2 = 1 + 2 * (hi2 - lo2);
-    for (int k1 = 0; k1 < no1; ++k1) {
-        int a1, b1, s1, d1;
-        dwq_option(k1, lo1, hi1, a1, b1, s1, d1);
-        const unsigned cm = ((1u << (b1 - a1 + 1)) - 1u) << (a1 - lo1);
-        for (int k2 = 0; k2 < no2; ++k2) {
-            int a2, b2, s2, d2;
-            dwq_option(k2, lo2, hi2, a2, b2, s2, d2);
-            const int nel = (b1 - a1 + 1) * (b2 - a2 + 1);
-            const int nd = (s1 >= 0) + (s2 >= 0);
-            if (!(nel > best_n || (nel == best_n && best_n > 0 && nd < best_d))) continue;
-            bool ok = true;
-            for (int e2 = a2; e2 <= b2 && ok; ++e2) ok = (rowm[e2 - lo2] & cm) == cm;
-            if (!ok) continue;
-            best_n = nel;
-            best_d = nd;
-            R[0] = a1; R[1] = b1; R[2] = s1; R[3] = d1;
-            R[4] = a2; R[5] = b2; R[6] = s2; R[7] = d2;
+        if (lo2 + lane <= hi2) {
+            int8_t c[P + 1];
+#pragma unroll
+            for (int m1 = 0; m1 <= P; ++m1) c[m1] = ecls[(size_t)(lo2 + lane) * N1 + min(lo1 + m1, hi1)];
+#pragma unroll
+            for (int m1 = 0; m1 <= P; ++m1)
+                if (m1 <= hi1 - lo1 && c[m1] == EL_INSIDE) v |= 1u << m1;
         }
+        s_rowm[lane] = v;
+    }
+    __syncthreads();
+    const int no1 = 1 + 2 * (hi1 - lo1), no2 = 1 + 2 * (hi2 - lo2);
+    unsigned long long best = 0ull;  // (box size, 3 - discontinuities, 65535 - option), 0: none
+    for (int o = lane; o < no1 * no2; o += 64) {
+        const int k1 = o / no2, k2 = o % no2;
+        int a1, b1, s1, d1, a2, b2, s2, d2;
+        dwq_option(k1, lo1, hi1, a1, b1, s1, d1);
+        dwq_option(k2, lo2, hi2, a2, b2, s2, d2);
+        const unsigned cm = ((1u << (b1 - a1 + 1)) - 1u) << (a1 - lo1);
+        bool ok = true;
+        for (int e2 = a2; e2 <= b2; ++e2) ok = ok && (s_rowm[e2 - lo2] & cm) == cm;
+        if (!ok) continue;
+        const unsigned long long nel = (unsigned long long)((b1 - a1 + 1) * (b2 - a2 + 1));
+        const int nd = (s1 >= 0) + (s2 >= 0);
+        const unsigned long long key = (nel << 32) | ((unsigned long long)(3 - nd) << 16) | (unsigned)(65535 - o);
+        best = key > best ? key : best;
     }
 #pragma unroll
-    for (int k = 0; k < 8; ++k) region[(size_t)t * 8 + k] = R[k];
+    for (int off = 32; off >= 1; off >>= 1) {
+        const unsigned long long other = __shfl_xor(best, off, 64);
+        best = other > best ? other : best;
+    }
+    if (lane < 8) {
+        int R = -1;
+        if (best != 0ull) {
+            const int o = 65535 - (int)(best & 0xffffu);
+            int a1, b1, s1, d1, a2, b2, s2, d2;
+            dwq_option(o / no2, lo1, hi1, a1, b1, s1, d1);
+            dwq_option(o % no2, lo2, hi2, a2, b2, s2, d2);
+            const int v[8] = {a1, b1, s1, d1, a2, b2, s2, d2};
+#pragma unroll
+            for (int k = 0; k < 8; ++k)
+                if (k == lane) R = v[k];
+        }
+        region[(size_t)t * 8 + lane] = R;
+    }
 }
 
 // ------------------------------------------------------------ box rows
@@ -421,7 +441,7 @@ void launch_dwq_sides(Plan& P, hipStream_t s) {
 
 void launch_dwq_choose(Plan& P, hipStream_t s) {
     if (P.method != IGA_DWQ || P.n_form_rows == 0) return;
-    dim3 g((unsigned)((P.n_form_rows + 127) / 128)), b(128);
+    dim3 g((unsigned)P.n_form_rows), b(64);
     switch (P.p) {
 #define CASE(PP)                                                                                                 \
     case PP:                                                                                                     \
