@@ -191,15 +191,14 @@ int iga_plan_index_maps(const iga_plan* plan, const int32_t** act_of, const int3
  * IGA_E_UNSUPPORTED otherwise. */
 int iga_trim_mass_form(iga_plan* plan, const iga_coeff* c, double* vals, int32_t flags, void* stream);
 
-/* Graph replay of iga_trim_mass_form (off by default: on MI355X with ROCm
- * 7 a replay costs the host about as much as the launches it replaces).
- * enable != 0: the first call with a given (vals, coefficient, flags)
- * records the formation's kernels and stream joins as a HIP graph on a
- * private stream; later calls with the same three replay it on the caller's
- * stream, reading the plan's inputs (curves, weights, nodes, coefficient
- * values) as they stand then. Another vals, coefficient pointer or value, or
- * flags records anew. Plans with per-phase timing enabled, or method
- * IGA_NAIVE_WQ, always launch kernel by kernel. */
+/* Graph replay of iga_trim_mass_form (on by default). A call with the same
+ * (vals, coefficient, flags) as the previous one records the formation's
+ * kernels and stream joins as a HIP graph on a private stream; later calls
+ * with the same three replay it on the caller's stream (one submission),
+ * reading the plan's inputs (curves, weights, nodes, coefficient values) as
+ * they stand then. A call unlike the previous one runs kernel by kernel.
+ * Plans with per-phase timing enabled, or method IGA_NAIVE_WQ, always launch
+ * kernel by kernel. enable = 0 turns replay off for the plan. */
 int iga_plan_set_graph(iga_plan* plan, int32_t enable);
 
 /* Synchronises stream and returns the device status word of the plan

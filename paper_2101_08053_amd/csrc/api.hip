@@ -308,7 +308,16 @@ static bool same_coeff(const iga_coeff& a, const iga_coeff& b) {
 }
 
 static void form_graph(Plan& P, const iga_coeff& c, double* vals, int flags, hipStream_t s) {
-    if (!(P.fexec && P.fkey_vals == vals && P.fkey_flags == flags && same_coeff(P.fkey_c, c))) {
+    const bool recorded = P.fexec && P.fkey_vals == vals && P.fkey_flags == flags && same_coeff(P.fkey_c, c);
+    if (!recorded && !(P.pkey_vals == vals && P.pkey_flags == flags && same_coeff(P.pkey_c, c))) {
+        // a call unlike the last one runs kernel by kernel; a repeated one is recorded
+        P.pkey_vals = vals;
+        P.pkey_flags = flags;
+        P.pkey_c = c;
+        form(P, c, vals, flags, s);
+        return;
+    }
+    if (!recorded) {
         if (P.fexec) HIPX(hipGraphExecDestroy(P.fexec));
         if (P.fgraph) HIPX(hipGraphDestroy(P.fgraph));
         P.fexec = nullptr;

@@ -219,13 +219,16 @@ struct Plan {
     bool timing = false;
     // The formation as one HIP graph (captured on a private stream, replayed on the caller's):
     // valid while the output, coefficient and flags match the captured call.
-    bool use_graph = false;
+    bool use_graph = true;
     hipStream_t cap_stream = nullptr;
     hipGraph_t fgraph = nullptr;
     hipGraphExec_t fexec = nullptr;
     double* fkey_vals = nullptr;
     iga_coeff fkey_c{};
     int fkey_flags = -1;
+    double* pkey_vals = nullptr;   // the previous call run kernel by kernel
+    iga_coeff pkey_c{};
+    int pkey_flags = -1;
     std::vector<hipEvent_t> ev_pool;
     std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_records;
     double phase_ms[IGA_PHASE_COUNT] = {0, 0, 0, 0};

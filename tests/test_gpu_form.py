@@ -204,9 +204,10 @@ def test_untrimmed_kronecker():
 def test_graph_replay_equals_launches(method):
     """Graph replays of the formation give the kernel-by-kernel result bit for bit.
 
-    Several replays with unrelated torch work and synchronisations between
-    them, a full and a fast call, a new coefficient value (a new recording),
-    and injected weights read by a replay.
+    Three calls per setting (run kernel by kernel, recorded, replayed) with
+    unrelated torch work and synchronisations between them, full and fast
+    calls, a new coefficient value (a new recording), and injected weights
+    read by a replay.
     """
     require_gpu()
     import torch
@@ -217,6 +218,7 @@ def test_graph_replay_equals_launches(method):
     g = igatrim.Plan(cfg, m)
     g.set_graph(True)
     e = igatrim.Plan(cfg, m)
+    e.set_graph(False)
     shape = (g.sizes["band"], g.sizes["n_act"])
     out_g = torch.empty(shape, dtype=torch.float64, device="cuda")
     out_e = torch.empty(shape, dtype=torch.float64, device="cuda")
