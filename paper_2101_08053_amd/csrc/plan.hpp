@@ -134,6 +134,7 @@ struct SolveWork {
     double* A = nullptr;      // (M + M^T)/2
     double *r = nullptr, *z = nullptr, *pv = nullptr, *q = nullptr, *part = nullptr, *scal = nullptr, *b = nullptr;
     double* h_scal = nullptr; // pinned host copy of the scalars
+    int* cols = nullptr;      // compact column of each band slot (PCG)
     double* V = nullptr;      // matrix-free: u contracted along xi_1 [n2][Q1]
     double* H = nullptr;      // matrix-free: xi_1 row sums [Q2][n1] (forward), w2 r, then B1 c R (adjoint)
     double* Ue = nullptr;     // matrix-free: element vectors

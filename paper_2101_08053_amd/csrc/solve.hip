@@ -263,7 +263,46 @@ struct SpArgs {
     const int* fn_of;
     const int* act_of;
     const double* A;
+    const int* cols;  // [(2p+1)^2][n_act] compact column of each slot, -1 if none (PCG iterations)
 };
+
+// Compact column of every slot of the band (once per solve).
+__global__ void k_cols(SpArgs S, int* __restrict__ cols) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int W = 2 * S.p + 1;
+    if (t >= (int64_t)W * W * S.n_act) return;
+    const int sl = (int)(t / S.n_act), r = (int)(t % S.n_act);
+    const int f = S.fn_of[r], j1 = f % S.n1 + sl / W - S.p, j2 = f / S.n1 + sl % W - S.p;
+    cols[t] = (j1 >= 0 && j1 < S.n1 && j2 >= 0 && j2 < S.n2) ? S.act_of[j2 * S.n1 + j1] : -1;
+}
+
+// Row r of A x from the column table, slots in the order (b outer, a inner),
+// every load of the row issued before the sums.
+template <int P>
+__device__ __forceinline__ double spmv_row_cols(const SpArgs& S, const double* __restrict__ x, int r) {
+    constexpr int W = 2 * P + 1;
+    double s = 0.0;
+#pragma unroll
+    for (int b = 0; b < W; ++b) {
+        int c[W];
+        double v[W], xv[W];
+#pragma unroll
+        for (int a = 0; a < W; ++a) {
+            const size_t o = (size_t)(a * W + b) * S.n_act + r;
+            c[a] = S.cols[o];
+            v[a] = S.A[o];
+        }
+#pragma unroll
+        for (int a = 0; a < W; ++a) xv[a] = x[max(c[a], 0)];
+#pragma unroll
+        for (int a = 0; a < W; ++a)
+            if (c[a] >= 0) s += v[a] * xv[a];
+    }
+    return s;
+}
+
+// Sum of a kernel's block partials, the same in every block (thread 0 holds it).
+__device__ __forceinline__ double sum_partials(const double* __restrict__ part, int nblk, int nv, int v, double* sh);
 
 __device__ __forceinline__ double spmv_row(const SpArgs& S, const double* __restrict__ x, int r) {
     int W = 2 * S.p + 1;
@@ -283,7 +322,7 @@ __device__ __forceinline__ double spmv_row(const SpArgs& S, const double* __rest
     return s;
 }
 
-// scal layout: 0 rz, 1 pq, 2 rr, 3 bb, 4 alpha, 5 beta
+// scal layout: 0 rz (initial), 2 rr, 3 bb, 6 / 7 rz of even / odd iterations
 // r = b - A x, z = r/d, p = z; partials of (r.z), (r.r), (b.b)
 __global__ void __launch_bounds__(kRedThreads) k_cg_init(SpArgs S, const double* __restrict__ bvec,
                                                          const double* __restrict__ x, double* __restrict__ rv,
@@ -312,39 +351,42 @@ __global__ void __launch_bounds__(kRedThreads) k_cg_init(SpArgs S, const double*
     }
 }
 
+// The initial (r.z), (r.r), (b.b) from the block partials (one workgroup).
 __global__ void __launch_bounds__(kRedThreads) k_reduce(const double* __restrict__ part, int nblk, int nv,
-                                                        double* __restrict__ scal, int mode) {
+                                                        double* __restrict__ scal) {
     __shared__ double sh[kRedThreads / 64];
     for (int v = 0; v < nv; ++v) {
         double s = 0.0;
         for (int k = threadIdx.x; k < nblk; k += blockDim.x) s += part[nv * k + v];
         double tot = block_sum(s, sh);
         if (threadIdx.x == 0) {
-            if (mode == 0) {          // init: rz, rr, bb
-                scal[v == 0 ? 0 : (v == 1 ? 2 : 3)] = tot;
-            } else if (mode == 1) {   // after spmv: pq -> alpha
-                scal[1] = tot;
-                scal[4] = scal[0] / tot;
-            } else {                  // after update: rz_new, rr -> beta
-                if (v == 0) {
-                    scal[5] = tot / scal[0];
-                    scal[0] = tot;
-                } else {
-                    scal[2] = tot;
-                }
-            }
+            scal[v == 0 ? 0 : (v == 1 ? 2 : 3)] = tot;
+            if (v == 0) scal[6] = tot;  // (r.z) of the first iteration
         }
         __syncthreads();
     }
 }
 
-__global__ void __launch_bounds__(kRedThreads) k_cg_spmv(SpArgs S, const double* __restrict__ pv,
-                                                         double* __restrict__ qv, double* __restrict__ part) {
+__device__ __forceinline__ double sum_partials(const double* __restrict__ part, int nblk, int nv, int v, double* sh) {
+    double s = 0.0;
+    for (int k = threadIdx.x; k < nblk; k += blockDim.x) s += part[nv * k + v];
+    return block_sum(s, sh);
+}
+
+// The iteration in three launches: every block of the update and direction
+// kernels sums the previous kernel's block partials itself (same order in
+// every block, so the same scalars), instead of a one-block reduction launch
+// in between. (r.z) alternates between scal[par] and scal[1 - par], so the
+// direction kernel's block 0 can store the new value while other blocks
+// still read the old one.
+template <int P>
+__global__ void __launch_bounds__(kRedThreads) k_cg_spmv_c(SpArgs S, const double* __restrict__ pv,
+                                                           double* __restrict__ qv, double* __restrict__ part) {
     __shared__ double sh[kRedThreads / 64];
     int r = blockIdx.x * blockDim.x + threadIdx.x;
     double pq = 0.0;
     if (r < S.n_act) {
-        double q = spmv_row(S, pv, r);
+        double q = spmv_row_cols<P>(S, pv, r);
         qv[r] = q;
         pq = pv[r] * q;
     }
@@ -352,15 +394,20 @@ __global__ void __launch_bounds__(kRedThreads) k_cg_spmv(SpArgs S, const double*
     if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
-__global__ void __launch_bounds__(kRedThreads) k_cg_update(SpArgs S, const double* __restrict__ scal,
-                                                           double* __restrict__ x, double* __restrict__ rv,
-                                                           double* __restrict__ zv, const double* __restrict__ pv,
-                                                           const double* __restrict__ qv, double* __restrict__ part) {
+__global__ void __launch_bounds__(kRedThreads) k_cg_update_c(SpArgs S, double* __restrict__ scal, int par, int nblk,
+                                                             const double* __restrict__ part_pq, double* __restrict__ x,
+                                                             double* __restrict__ rv, double* __restrict__ zv,
+                                                             const double* __restrict__ pv,
+                                                             const double* __restrict__ qv, double* __restrict__ part) {
     __shared__ double sh[kRedThreads / 64];
+    __shared__ double s_alpha;
+    const double pq = sum_partials(part_pq, nblk, 1, 0, sh);
+    if (threadIdx.x == 0) s_alpha = scal[6 + par] / pq;
+    __syncthreads();
     int r = blockIdx.x * blockDim.x + threadIdx.x;
     double rz = 0, rr = 0;
     if (r < S.n_act) {
-        double alpha = scal[4];
+        double alpha = s_alpha;
         int W = 2 * S.p + 1;
         double d = S.A[(size_t)(S.p * W + S.p) * S.n_act + r];
         x[r] += alpha * pv[r];
@@ -378,9 +425,23 @@ __global__ void __launch_bounds__(kRedThreads) k_cg_update(SpArgs S, const doubl
     }
 }
 
-__global__ void k_cg_dir(int n, const double* __restrict__ scal, const double* __restrict__ zv, double* __restrict__ pv) {
+__global__ void __launch_bounds__(kRedThreads) k_cg_dir_c(int n, double* __restrict__ scal, int par, int nblk,
+                                                          const double* __restrict__ part,
+                                                          const double* __restrict__ zv, double* __restrict__ pv) {
+    __shared__ double sh[kRedThreads / 64];
+    __shared__ double s_beta;
+    const double rz = sum_partials(part, nblk, 2, 0, sh);
+    const double rr = sum_partials(part, nblk, 2, 1, sh);
+    if (threadIdx.x == 0) {
+        s_beta = rz / scal[6 + par];
+        if (blockIdx.x == 0) {
+            scal[6 + (1 - par)] = rz;
+            scal[2] = rr;
+        }
+    }
+    __syncthreads();
     int r = blockIdx.x * blockDim.x + threadIdx.x;
-    if (r < n) pv[r] = zv[r] + scal[5] * pv[r];
+    if (r < n) pv[r] = zv[r] + s_beta * pv[r];
 }
 
 }  // namespace iga
@@ -497,15 +558,18 @@ int iga_trim_l2_project(iga_plan* plan, const iga_coeff* c, const double* vals, 
         W.b = P->alloc<double>(n);
         W.part = P->alloc<double>(3 * (size_t)nblk);
         W.scal = P->alloc<double>(8);
+        W.cols = P->alloc<int>((size_t)W2 * n);
         HIPX(hipHostMalloc((void**)&W.h_scal, 8 * sizeof(double), hipHostMallocDefault));
     }
     rhs(*P, *c, *g, W.b, s);
     int64_t tot = (int64_t)W2 * n;
     hipLaunchKernelGGL(k_symmetrize, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, P->p, P->n1, P->fn_of,
                        P->act_of, P->n2, n, vals, W.A);
-    SpArgs S{P->p, P->n1, P->n2, n, P->fn_of, P->act_of, W.A};
+    SpArgs S{P->p, P->n1, P->n2, n, P->fn_of, P->act_of, W.A, nullptr};
+    hipLaunchKernelGGL(k_cols, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, S, W.cols);
+    S.cols = W.cols;
     hipLaunchKernelGGL(k_cg_init, dim3(nblk), dim3(kRedThreads), 0, s, S, W.b, u, W.r, W.z, W.pv, W.part);
-    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kRedThreads), 0, s, W.part, nblk, 3, W.scal, 0);
+    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kRedThreads), 0, s, W.part, nblk, 3, W.scal);
     auto read = [&]() {
         HIPX(hipMemcpyAsync(W.h_scal, W.scal, 8 * sizeof(double), hipMemcpyDeviceToHost, s));
         HIPX(hipStreamSynchronize(s));
@@ -519,12 +583,18 @@ int iga_trim_l2_project(iga_plan* plan, const iga_coeff* c, const double* vals, 
     while (!conv && it < maxit) {
         int m = std::min(chunk, maxit - it);
         for (int k = 0; k < m; ++k) {
-            hipLaunchKernelGGL(k_cg_spmv, dim3(nblk), dim3(kRedThreads), 0, s, S, W.pv, W.q, W.part);
-            hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kRedThreads), 0, s, W.part, nblk, 1, W.scal, 1);
-            hipLaunchKernelGGL(k_cg_update, dim3(nblk), dim3(kRedThreads), 0, s, S, W.scal, u, W.r, W.z, W.pv, W.q,
-                               W.part);
-            hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kRedThreads), 0, s, W.part, nblk, 2, W.scal, 2);
-            hipLaunchKernelGGL(k_cg_dir, dim3((n + 255) / 256), dim3(256), 0, s, n, W.scal, W.z, W.pv);
+            const int par = (it + k) & 1;
+            double* part2 = W.part + nblk;
+            switch (P->p) {
+#define CASE(PP) \
+    case PP: hipLaunchKernelGGL(k_cg_spmv_c<PP>, dim3(nblk), dim3(kRedThreads), 0, s, S, W.pv, W.q, W.part); break;
+                CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
+#undef CASE
+            }
+            hipLaunchKernelGGL(k_cg_update_c, dim3(nblk), dim3(kRedThreads), 0, s, S, W.scal, par, nblk,
+                               (const double*)W.part, u, W.r, W.z, (const double*)W.pv, (const double*)W.q, part2);
+            hipLaunchKernelGGL(k_cg_dir_c, dim3(nblk), dim3(kRedThreads), 0, s, n, W.scal, par, nblk,
+                               (const double*)part2, (const double*)W.z, W.pv);
         }
         it += m;
         read();
