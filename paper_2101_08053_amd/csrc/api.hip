@@ -120,7 +120,7 @@ static void setup_trim(Plan& P, hipStream_t s, bool discover, bool points, int p
         HIPX(hipEventRecord(P.ev_lists, s));  // classes, compact maps and DWQ boxes are ready
     }
     if (part == 1) return;
-    launch_trim_cutprep(P, s);
+    launch_trim_cutprep(P, s, !discover);  // after plan creation the cut rules' nodes are written with them
     if (discover) {
         // node offsets are formed with the nodes; their total is needed to size the buffers first
         P.n_nodes = 0;
@@ -150,7 +150,7 @@ static void setup_trim(Plan& P, hipStream_t s, bool discover, bool points, int p
         P.c_cut = P.alloc<double>(nn);
         if (P.method == IGA_NAIVE_WQ) P.c_wq_masked = P.alloc<double>(nq);
     }
-    launch_trim_nodes(P, s);
+    if (discover) launch_trim_nodes(P, s);
     if (points) launch_points(P, s);
     if (discover) {
         check_status(P, s);

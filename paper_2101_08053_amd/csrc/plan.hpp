@@ -298,7 +298,8 @@ void launch_trim_arcs(Plan& P, hipStream_t s);              // solve, merge, arc
 int trim_max_crossings(Plan& P, hipStream_t s);             // plan creation: most grid-line crossings of one piece
 void launch_trim_classes(Plan& P, hipStream_t s);           // elements, functions, flags
 void launch_trim_lists(Plan& P, hipStream_t s);             // act_of, cut/band lists
-void launch_trim_cutprep(Plan& P, hipStream_t s);           // per cut element segments, variant, counts
+// per cut element segments, variant, counts; with fuse_nodes also the nodes, at the offsets plan creation found
+void launch_trim_cutprep(Plan& P, hipStream_t s, bool fuse_nodes = false);
 void launch_trim_nodes(Plan& P, hipStream_t s);             // node coordinates and weights
 void launch_naive_mask(Plan& P, const double* src, double cval, hipStream_t s);
 void launch_row_nnz(Plan& P, int* cnt, int* out, hipStream_t s);

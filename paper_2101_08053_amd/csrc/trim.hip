@@ -1195,7 +1195,15 @@ struct CutArgs {
     int* status;
     int* node_off;      // exclusive scan of node_cnt (written by k_cut_nodes)
     int stage_pieces, stage_segs;  // k_cutprep: pieces / segments its LDS holds (0: read them from memory)
+    // k_cutprep with fuse_nodes: also writes the element's nodes, at the offsets plan creation found
+    int fuse_nodes;
+    double *nx, *ny, *nw;
+    int* nel;
+    double* xy;         // the cut nodes' entries of the rule-point table
 };
+
+__device__ void write_cut_nodes(const CutArgs& A, int c, int pos, double* __restrict__ nx, double* __restrict__ ny,
+                                double* __restrict__ nw, int* __restrict__ nel, double* __restrict__ xy);
 
 __device__ __forceinline__ int arc_nq(const CutArgs& A, const CurveDev& C) {
     if (A.n_q_override > 0) return A.n_q_override;
@@ -1467,15 +1475,35 @@ __global__ void __launch_bounds__(64) k_cutprep(CutArgs A) {
         A.node_cnt[c] = narc_nodes + out.nseg[opp] * A.n_s * A.n_r;
         if (sOverflow) atomicExch(A.status, IGA_E_TOPOLOGY);
     }
+    if (A.fuse_nodes) {
+        // the same inputs as at plan creation give the same node counts, so
+        // the offsets found then hold; a different count is reported, not written
+        __syncthreads();
+        const int off = A.node_off[c];
+        if (A.node_cnt[c] == A.node_off[c + 1] - off) {
+            write_cut_nodes(A, c, off, A.nx, A.ny, A.nw, A.nel, A.xy);
+        } else if (lane == 0) {
+            atomicExch(A.status, IGA_E_CAPACITY);
+        }
+    }
 }
 
-void launch_trim_cutprep(Plan& P, hipStream_t s) {
+void launch_trim_cutprep(Plan& P, hipStream_t s, bool fuse_nodes) {
     TrimDev& T = P.trim;
     int nc = (int)P.n_cut_el;
     if (T.n_curves == 0 || nc == 0) return;
     GridDev G{P.dir[0].knots + P.p, P.dir[1].knots + P.p, P.N1, P.N2};  // breakpoints
     CutArgs A{T, G, nc, P.cut_list, P.ehead, P.arc_next, P.cut_el, P.node_cnt,
               P.n_r, P.n_q_override, P.n_s, P.p, P.gauss_x, P.gauss_w, P.status, P.node_off, 0, 0};
+    if (fuse_nodes) {
+        const size_t cut0 = (size_t)P.dir[0].Q * P.dir[1].Q + (size_t)P.n_band * (P.p + 1) * (P.p + 1);
+        A.fuse_nodes = 1;
+        A.nx = P.node_x;
+        A.ny = P.node_y;
+        A.nw = P.node_w;
+        A.nel = P.node_el;
+        A.xy = P.pts_xy + 2 * cut0;
+    }
     A.stage_pieces = (T.cap_pieces <= kPrepPieces) ? T.cap_pieces : 0;
     A.stage_segs = (A.stage_pieces > 0 && T.n_segs <= kPrepSegs) ? T.n_segs : 0;
     const size_t lds = (size_t)A.stage_pieces * sizeof(PieceBox) + (size_t)A.stage_segs * sizeof(SegDev);
@@ -1486,11 +1514,10 @@ void launch_trim_cutprep(Plan& P, hipStream_t s) {
 // rule-point table), at the offset the counts before it add up to.
 constexpr int kNodePrefixMax = 8192;  // up to this many cut elements each workgroup sums the counts before it
 
-__global__ void __launch_bounds__(64) k_cut_nodes(CutArgs A, int prefix_here, double* __restrict__ nx,
-                                                  double* __restrict__ ny, double* __restrict__ nw,
-                                                  int* __restrict__ nel, double* __restrict__ xy) {
-    int c = blockIdx.x;
-    if (c >= A.n_cut) return;
+// The element's nodes and weights (arcs first, then the straight pieces of
+// the edge opposite the base), from offset pos on.
+__device__ void write_cut_nodes(const CutArgs& A, int c, int pos, double* __restrict__ nx, double* __restrict__ ny,
+                                double* __restrict__ nw, int* __restrict__ nel, double* __restrict__ xy) {
     const TrimDev& T = A.T;
     const CutElemDev& E = A.cut_el[c];
     double xa = A.G.bp1[E.e1], xb = A.G.bp1[E.e1 + 1], ya = A.G.bp2[E.e2], yb = A.G.bp2[E.e2 + 1];
@@ -1501,30 +1528,6 @@ __global__ void __launch_bounds__(64) k_cut_nodes(CutArgs A, int prefix_here, do
     int nr = A.n_r;
     const double* rx = A.gx + gauss_off(nr);
     const double* rw = A.gw + gauss_off(nr);
-    // this element's first node: the sum of the counts before it (or the scanned offsets)
-    int pos;
-    if (prefix_here) {
-        int sum = 0;
-        for (int i0 = 0; i0 < c; i0 += 64 * 8) {
-            int v[8];
-#pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                const int i = i0 + threadIdx.x + 64 * j;
-                v[j] = (i < c) ? A.node_cnt[i] : 0;
-            }
-#pragma unroll
-            for (int j = 0; j < 8; ++j) sum += v[j];
-        }
-#pragma unroll
-        for (int o = 32; o >= 1; o >>= 1) sum += __shfl_xor(sum, o, 64);
-        pos = sum;
-        if (threadIdx.x == 0) {
-            A.node_off[c] = pos;
-            if (c == A.n_cut - 1) A.node_off[A.n_cut] = pos + A.node_cnt[c];
-        }
-    } else {
-        pos = A.node_off[c];
-    }
     for (int q = 0; q < E.narc; ++q) {
         const ArcDev R = T.arcs[E.arc[q]];
         const SegDev S = T.segs[R.gseg];
@@ -1571,6 +1574,38 @@ __global__ void __launch_bounds__(64) k_cut_nodes(CutArgs A, int prefix_here, do
         }
         pos += ns * nr;
     }
+}
+
+__global__ void __launch_bounds__(64) k_cut_nodes(CutArgs A, int prefix_here, double* __restrict__ nx,
+                                                  double* __restrict__ ny, double* __restrict__ nw,
+                                                  int* __restrict__ nel, double* __restrict__ xy) {
+    int c = blockIdx.x;
+    if (c >= A.n_cut) return;
+    // this element's first node: the sum of the counts before it (or the scanned offsets)
+    int pos;
+    if (prefix_here) {
+        int sum = 0;
+        for (int i0 = 0; i0 < c; i0 += 64 * 8) {
+            int v[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int i = i0 + threadIdx.x + 64 * j;
+                v[j] = (i < c) ? A.node_cnt[i] : 0;
+            }
+#pragma unroll
+            for (int j = 0; j < 8; ++j) sum += v[j];
+        }
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) sum += __shfl_xor(sum, o, 64);
+        pos = sum;
+        if (threadIdx.x == 0) {
+            A.node_off[c] = pos;
+            if (c == A.n_cut - 1) A.node_off[A.n_cut] = pos + A.node_cnt[c];
+        }
+    } else {
+        pos = A.node_off[c];
+    }
+    write_cut_nodes(A, c, pos, nx, ny, nw, nel, xy);
 }
 
 void launch_trim_nodes(Plan& P, hipStream_t s) {
