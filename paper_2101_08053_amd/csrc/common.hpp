@@ -247,10 +247,32 @@ __device__ __forceinline__ int block_excl_scan(int v, int* sh, int& total) {
 // q); singular is set if a pivot of R vanishes; the result is checked by the
 // caller.
 // -------------------------------------------------------------------------
+// A double moved across lanes of a row of 16 by a DPP control (the two
+// 32-bit halves); no LDS round trip.
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+__device__ __forceinline__ double read_lane(double v, int lane) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), lane);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+// Sum over the 64 lanes, the same value in every lane (all lanes active):
+// pairs inside quads, quads inside half rows, half rows inside rows of 16
+// (DPP moves), then the four row sums read as scalars.
 __device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
+    v += dpp_move<0xB1>(v);   // quad_perm [1,0,3,2]: lane ^ 1
+    v += dpp_move<0x4E>(v);   // quad_perm [2,3,0,1]: lane ^ 2
+    v += dpp_move<0x141>(v);  // row_half_mirror: the other quad of the half row
+    v += dpp_move<0x140>(v);  // row_mirror: the other half of the row
+    return (read_lane(v, 0) + read_lane(v, 16)) + (read_lane(v, 32) + read_lane(v, 48));
 }
 
 template <int M, typename BCol>
@@ -268,7 +290,7 @@ __device__ __forceinline__ double wave_min_norm(double (&a)[M], int q, int m, BC
         if (c >= m) break;
         double x = (lane >= c && lane < q) ? a[c] : 0.0;
         double nrm2 = wave_sum(x * x);
-        double xc = __shfl(a[c], c, 64);
+        double xc = read_lane(a[c], c);
         double alpha = (xc >= 0.0) ? -sqrt(nrm2) : sqrt(nrm2);
         double vl = (lane == c) ? x - alpha : x;
         double vv = 2.0 * (nrm2 - alpha * xc);
@@ -284,7 +306,7 @@ __device__ __forceinline__ double wave_min_norm(double (&a)[M], int q, int m, BC
         }
         if (lane == c) a[c] = (vv > 0.0) ? alpha : xc;
         else if (lane > c) a[c] = 0.0;
-        double rcc = __shfl(a[c], c, 64);
+        double rcc = read_lane(a[c], c);
         if (!(fabs(rcc) > 0.0)) singular = true;
     }
     // forward substitution R^T z = b (R[k][c] sits in lane k, column c)
@@ -294,7 +316,7 @@ __device__ __forceinline__ double wave_min_norm(double (&a)[M], int q, int m, BC
         if (c >= m) break;
         double bc = bcol(c);
         double sacc = wave_sum((lane < c) ? a[c] * zl : 0.0);
-        double rcc = __shfl(a[c], c, 64);
+        double rcc = read_lane(a[c], c);
         double zc = (bc - sacc) / rcc;
         if (lane == c) zl = zc;
     }
