@@ -536,8 +536,7 @@ __device__ void curves_orient(const TrimDev& T, CurveDev* __restrict__ curves, c
             seg_eval(S, tt, X, Y, dX, dY);
             area += 0.5 * w * (X * dY - Y * dX);
         }
-#pragma unroll
-        for (int o = 32; o >= 1; o >>= 1) area += __shfl_xor(area, o, 64);
+        area = wave_sum(area);
         if (lane == 0) sh_area[wid] = area;
         __syncthreads();
         if (tid == 0) {
@@ -600,8 +599,7 @@ __device__ void front_one_curve(const TrimDev& T, const double* __restrict__ cp,
         }
         carry_p += tot_p;
     }
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) area += __shfl_xor(area, o, 64);
+    area = wave_sum(area);
     if (lane == 0) sh_area[wid] = area;
     __syncthreads();
     if (tid == 0) {
@@ -1053,8 +1051,7 @@ struct ListArgs {
 
 __device__ __forceinline__ int block_sum256(int v, int* sh) {
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    v = wave_sum_i(v);
     if (lane == 0) sh[wid] = v;
     __syncthreads();
     const int tot = sh[0] + sh[1] + sh[2] + sh[3];
@@ -1202,9 +1199,6 @@ struct CutArgs {
     double* xy;         // the cut nodes' entries of the rule-point table
 };
 
-__device__ void write_cut_nodes(const CutArgs& A, int c, int pos, double* __restrict__ nx, double* __restrict__ ny,
-                                double* __restrict__ nw, int* __restrict__ nel, double* __restrict__ xy);
-
 __device__ __forceinline__ int arc_nq(const CutArgs& A, const CurveDev& C) {
     if (A.n_q_override > 0) return A.n_q_override;
     int d = (C.kind == IGA_CURVE_ELLIPSE) ? 3 : C.degree;
@@ -1214,7 +1208,7 @@ __device__ __forceinline__ int arc_nq(const CutArgs& A, const CurveDev& C) {
 // Pieces as the even-odd test reads them, staged in LDS by k_cutprep.
 constexpr int kPrepPieces = 256;
 struct PieceBox {
-    double ymin, ymax, xmax, t0, t1;
+    double ymin, ymax, xmin, xmax, t0, t1;
     int seg, curve;
 };
 
@@ -1229,18 +1223,23 @@ __device__ bool in_any_hole_lds(const TrimDev& T, const PieceBox* sp, const int*
             if (ellipse_implicit(C, x, y) < 0.0) return true;
             continue;
         }
-        // eight boxes per step, so their LDS reads overlap; the (few) hits are solved after
+        // eight boxes per step, so their LDS reads overlap; the (few) hits are solved after.
+        // Pieces are monotone in x and y, so one whose box lies right of the point (by more
+        // than the rounding of its end points) crosses the ray right of it without a solve.
         bool in = false;
         const int k1 = scoff[c + 1];
         for (int kb = scoff[c]; kb < k1; kb += 8) {
-            unsigned hit = 0u;
+            unsigned hit = 0u, right = 0u;
 #pragma unroll
             for (int u = 0; u < 8; ++u) {
                 const int k = min(kb + u, k1 - 1);
                 const PieceBox& B = sp[k];
                 const bool h = (kb + u < k1) && (y >= B.ymin && y < B.ymax) && !(B.xmax <= x);
-                hit |= (h ? 1u : 0u) << u;
+                const bool r = B.xmin - x > 1e-13 * (1.0 + fabs(x));
+                hit |= ((h && !r) ? 1u : 0u) << u;
+                right |= ((h && r) ? 1u : 0u) << u;
             }
+            if (__builtin_popcount(right) & 1) in = !in;
             while (hit) {
                 const int u = __builtin_ctz(hit);
                 hit &= hit - 1u;
@@ -1255,6 +1254,66 @@ __device__ bool in_any_hole_lds(const TrimDev& T, const PieceBox* sp, const int*
         if (in) return true;
     }
     return false;
+}
+
+// The nodes write_cut_nodes writes, from what k_cutprep holds in LDS (the
+// element's arcs, their Gauss point offsets and the merged edge pieces), with
+// the same expressions, so the values are the same; (arc, Gauss point) and
+// (piece, node) pairs are spread over the lanes.
+__device__ __forceinline__ void write_cut_nodes_staged(const CutArgs& A, int c, int pos, int na, int npts, int var,
+                                                       double xa, double xb, double ya, double yb,
+                                                       const double (*sT)[2], const SegDev* sArcSeg, const int* sNq,
+                                                       const int* sNqOff, const double* sSig, const int* sNseg,
+                                                       const double (*sSeg)[kMaxEdgeSegs][2]) {
+    const int lane = threadIdx.x;
+    const bool vert = var < 2;
+    const double b0 = (var == 0) ? xa : (var == 1) ? xb : (var == 2) ? ya : yb;
+    const double b1 = (var == 0) ? xb : (var == 1) ? xa : (var == 2) ? yb : ya;
+    const int nr = A.n_r;
+    const double* rx = A.gx + gauss_off(nr);
+    const double* rw = A.gw + gauss_off(nr);
+    for (int u = lane; u < npts; u += 64) {
+        int q = 0;
+        while (q + 1 < na && sNqOff[q + 1] <= u) ++q;
+        const int nq = sNq[q], g = u - sNqOff[q];
+        const double t0 = sT[q][0], t1 = sT[q][1];
+        const double tq = t0 + (t1 - t0) * (A.gx[gauss_off(nq) + g] + 1.0) * 0.5;
+        const double wt = A.gw[gauss_off(nq) + g] * (t1 - t0) * 0.5;
+        const double sg = sSig[q];
+        double X, Y, dX, dY;
+        seg_eval(sArcSeg[q], tq, X, Y, dX, dY);
+        for (int r = 0; r < nr; ++r) {
+            const int o = pos + u * nr + r;
+            const double f = (rx[r] + 1.0) * 0.5;
+            const double x = vert ? b0 + (X - b0) * f : X, y = vert ? Y : b0 + (Y - b0) * f;
+            A.nx[o] = x;
+            A.ny[o] = y;
+            A.nw[o] = vert ? sg * wt * dY * rw[r] * (X - b0) * 0.5 : -sg * wt * dX * rw[r] * (Y - b0) * 0.5;
+            A.nel[o] = c;
+            A.xy[2 * o] = x;
+            A.xy[2 * o + 1] = y;
+        }
+    }
+    pos += npts * nr;
+    const int edge = var ^ 1;  // the edge opposite the base
+    const int ns = A.n_s, nsr = ns * nr;
+    const double* sx = A.gx + gauss_off(ns);
+    const double* sw = A.gw + gauss_off(ns);
+    for (int u = lane; u < sNseg[edge] * nsr; u += 64) {
+        const int k = u / nsr, t = u - k * nsr;
+        const double a = sSeg[edge][k][0], b = sSeg[edge][k][1];
+        const int si = t / nr, r = t % nr;
+        const double v = a + (b - a) * (sx[si] + 1.0) * 0.5;
+        const double wu = sw[si] * (b - a) * 0.5;
+        const double inner = b0 + (b1 - b0) * (rx[r] + 1.0) * 0.5;
+        const int o = pos + u;
+        A.nx[o] = vert ? inner : v;
+        A.ny[o] = vert ? v : inner;
+        A.nw[o] = wu * rw[r] * fabs(b1 - b0) * 0.5;
+        A.nel[o] = c;
+        A.xy[2 * o] = vert ? inner : v;
+        A.xy[2 * o + 1] = vert ? v : inner;
+    }
 }
 
 // One wavefront per cut element. (0) lane 0 walks the element's list of kept
@@ -1289,7 +1348,12 @@ __global__ void __launch_bounds__(64) k_cutprep(CutArgs A) {
     SegDev* sSegAll = reinterpret_cast<SegDev*>(sDyn + (size_t)A.stage_pieces * sizeof(PieceBox));
     __shared__ SegDev sArcSeg[kMaxArcsPerElem];
     __shared__ int sNq[kMaxArcsPerElem], sNqOff[kMaxArcsPerElem + 1];
+    __shared__ double sSig[kMaxArcsPerElem];            // the arcs' curve orientation signs
+    __shared__ double sSeg[4][kMaxEdgeSegs][2];          // merged visible pieces per edge
+    __shared__ int sNseg[4], sVar, sCnt;
     const int e = A.cut_list[c];
+    // node offsets for the fused node writes, loaded while the rule is found
+    const int off0 = A.fuse_nodes ? A.node_off[c] : 0, off1 = A.fuse_nodes ? A.node_off[c + 1] : 0;
     const int e1 = e % A.G.N1, e2 = e / A.G.N1;
     const double xa = A.G.bp1[e1], xb = A.G.bp1[e1 + 1], ya = A.G.bp2[e2], yb = A.G.bp2[e2 + 1];
     CutElemDev& out = A.cut_el[c];
@@ -1299,7 +1363,8 @@ __global__ void __launch_bounds__(64) k_cutprep(CutArgs A) {
     if (staged) {
         for (int k = lane; k < npc; k += 64) {
             const PieceDev Pc = T.pieces[k];
-            sP[k] = PieceBox{fmin(Pc.y0, Pc.y1), fmax(Pc.y0, Pc.y1), fmax(Pc.x0, Pc.x1), Pc.t0, Pc.t1, Pc.seg, Pc.curve};
+            sP[k] = PieceBox{fmin(Pc.y0, Pc.y1), fmax(Pc.y0, Pc.y1), fmin(Pc.x0, Pc.x1), fmax(Pc.x0, Pc.x1),
+                             Pc.t0, Pc.t1, Pc.seg, Pc.curve};
         }
         for (int k = lane; k <= T.n_curves; k += 64) sCoff[k] = T.piece_curve_off[k];
     }
@@ -1331,7 +1396,9 @@ __global__ void __launch_bounds__(64) k_cutprep(CutArgs A) {
         out.arc[q] = sArc[q];
         const ArcDev R = T.arcs[sArc[q]];
         sArcSeg[q] = T.segs[R.gseg];
-        sNq[q] = arc_nq(A, T.curves[R.curve]);
+        const CurveDev Cv = T.curves[R.curve];
+        sNq[q] = arc_nq(A, Cv);
+        sSig[q] = Cv.sigma;
         sEnd[q][0][0] = R.x0;
         sEnd[q][0][1] = R.y0;
         sEnd[q][1][0] = R.x1;
@@ -1421,9 +1488,12 @@ __global__ void __launch_bounds__(64) k_cutprep(CutArgs A) {
             const double a = sIv[edge][q][0], b = sIv[edge][q][1];
             if (ns > 0 && fabs(last_hi - a) <= tol) {
                 out.seg[edge][ns - 1][1] = b;
+                sSeg[edge][ns - 1][1] = b;
             } else if (ns < kMaxEdgeSegs) {
                 out.seg[edge][ns][0] = a;
                 out.seg[edge][ns][1] = b;
+                sSeg[edge][ns][0] = a;
+                sSeg[edge][ns][1] = b;
                 ++ns;
             } else {
                 overflow = true;
@@ -1433,6 +1503,7 @@ __global__ void __launch_bounds__(64) k_cutprep(CutArgs A) {
             len += b - a;
         }
         out.nseg[edge] = ns;
+        sNseg[edge] = ns;
         sLen[edge] = len;
         if (overflow) sOverflow = 1;
     }
@@ -1454,13 +1525,10 @@ __global__ void __launch_bounds__(64) k_cutprep(CutArgs A) {
         s2 += wt * fabs(dX) * fabs(Y - ya);
         s3 += wt * fabs(dX) * fabs(Y - yb);
     }
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) {
-        s0 += __shfl_xor(s0, o, 64);
-        s1 += __shfl_xor(s1, o, 64);
-        s2 += __shfl_xor(s2, o, 64);
-        s3 += __shfl_xor(s3, o, 64);
-    }
+    s0 = wave_sum(s0);
+    s1 = wave_sum(s1);
+    s2 = wave_sum(s2);
+    s3 = wave_sum(s3);
     __syncthreads();
     if (lane == 0) {
         double sums[4] = {s0 + sLen[1] * (xb - xa), s1 + sLen[0] * (xb - xa), s2 + sLen[3] * (yb - ya),
@@ -1472,16 +1540,19 @@ __global__ void __launch_bounds__(64) k_cutprep(CutArgs A) {
         out.e1 = e1;
         out.e2 = e2;
         out.variant = var;
-        A.node_cnt[c] = narc_nodes + out.nseg[opp] * A.n_s * A.n_r;
+        const int cnt = narc_nodes + sNseg[opp] * A.n_s * A.n_r;
+        A.node_cnt[c] = cnt;
+        sVar = var;
+        sCnt = cnt;
         if (sOverflow) atomicExch(A.status, IGA_E_TOPOLOGY);
     }
     if (A.fuse_nodes) {
         // the same inputs as at plan creation give the same node counts, so
         // the offsets found then hold; a different count is reported, not written
         __syncthreads();
-        const int off = A.node_off[c];
-        if (A.node_cnt[c] == A.node_off[c + 1] - off) {
-            write_cut_nodes(A, c, off, A.nx, A.ny, A.nw, A.nel, A.xy);
+        if (sCnt == off1 - off0) {
+            write_cut_nodes_staged(A, c, off0, na, npts, sVar, xa, xb, ya, yb, sT, sArcSeg, sNq, sNqOff, sSig,
+                                   sNseg, sSeg);
         } else if (lane == 0) {
             atomicExch(A.status, IGA_E_CAPACITY);
         }
