@@ -21,7 +21,7 @@ Plan::~Plan() {
     if (fgraph) hipGraphDestroy(fgraph);
     if (cap_stream) hipStreamDestroy(cap_stream);
     if (sw.h_scal) hipHostFree(sw.h_scal);
-    for (hipEvent_t e : {ev_fork, ev_iso, ev_lists, ev_interior, ev_band})
+    for (hipEvent_t e : {ev_fork, ev_iso, ev_lists, ev_interior, ev_band, ev_classes})
         if (e) hipEventDestroy(e);
     if (aux) hipStreamDestroy(aux);
     for (auto& e : ev_pool) hipEventDestroy(e);
@@ -76,8 +76,16 @@ static void setup_tables(Plan& P, hipStream_t s) {
 // Trimming, classes, lists, cut rules and (with `points`) the grid and band
 // entries of the rule-point table. The trimming reads the knots directly;
 // only the rule points read the univariate tables.
-// part 0: all of it; 1: up to the lists (and DWQ boxes), then ev_lists; 2: the cut rules and points.
+// part 0: all of it; 1: up to the lists (and DWQ boxes), then ev_lists; 2: the cut rules and points;
+// 3: up to the classes, then ev_classes (the lists then come from setup_lists on another stream).
 static void setup_trim(Plan& P, hipStream_t s, bool discover, bool points, int part = 0);
+
+// Compact maps, lists and DWQ boxes from the classes, then ev_lists.
+static void setup_lists(Plan& P, hipStream_t s) {
+    launch_trim_lists(P, s);
+    launch_dwq_choose(P, s);
+    HIPX(hipEventRecord(P.ev_lists, s));
+}
 
 static void run_setup(Plan& P, hipStream_t s, bool discover) {
     if (discover) launch_gauss_table(P, s);  // a constant table: once per plan
@@ -101,6 +109,10 @@ static void setup_trim(Plan& P, hipStream_t s, bool discover, bool points, int p
             launch_trim_arcs(P, s);
         }
         launch_trim_classes(P, s);
+        if (part == 3) {
+            HIPX(hipEventRecord(P.ev_classes, s));
+            return;
+        }
         launch_trim_lists(P, s);
         if (discover) {
             int c[4];
@@ -112,6 +124,7 @@ static void setup_trim(Plan& P, hipStream_t s, bool discover, bool points, int p
             P.n_band = c[3];
             int nc = (int)P.n_cut_el;
             P.cut_el = P.alloc<CutElemDev>(std::max(nc, 1));
+            P.cut_e = P.alloc<int>(std::max(nc, 1));
             P.node_cnt = P.alloc<int>(nc + 1);
             P.node_off = P.alloc<int>(nc + 1);
             if (P.method == IGA_DWQ) P.dwq_region = P.alloc<int>(8 * (size_t)std::max<int64_t>(P.n_form_rows, 1));
@@ -242,10 +255,14 @@ static void form(Plan& P, const iga_coeff& c, double* vals, int flags, hipStream
     // spends about as long enqueuing a formation as the device takes to run
     // it, so the trimming chain goes first, the cut rules right after the
     // auxiliary stream's first kernels.
+    // With row offsets the list kernel sums itself, the cut rules find their
+    // elements from the class kernel's counts, so the lists move to the
+    // auxiliary stream, off the caller's (critical) one.
+    const bool split = full && trim_lists_prefix_here(P);
     HIPX(hipEventRecord(P.ev_fork, s));
     if (full) {
         PhaseTimer t(P, s, IGA_PHASE_SETUP);
-        setup_trim(P, s, false, false, 1);
+        setup_trim(P, s, false, false, split ? 3 : 1);
     } else {
         HIPX(hipEventRecord(P.ev_lists, s));
     }
@@ -259,7 +276,12 @@ static void form(Plan& P, const iga_coeff& c, double* vals, int flags, hipStream
         PhaseTimer t(P, s, IGA_PHASE_SETUP);
         setup_trim(P, s, false, false, 2);
     }
-    HIPX(hipStreamWaitEvent(a, P.ev_lists, 0));
+    if (split) {
+        HIPX(hipStreamWaitEvent(a, P.ev_classes, 0));
+        setup_lists(P, a);
+    } else {
+        HIPX(hipStreamWaitEvent(a, P.ev_lists, 0));
+    }
     // The interior rows first (beside the cut rules, which leave most of the
     // GPU idle), then the inside sums of the element-formed rows (beside the
     // cut element matrices); the caller's stream joins once, before the cut
@@ -399,7 +421,7 @@ int iga_plan_create(const iga_patch_desc* desc, const iga_opts* opts, iga_plan**
     std::unique_ptr<iga_plan> guard(P);
     HIPX(hipGetDevice(&P->device));
     HIPX(hipStreamCreateWithFlags(&P->aux, hipStreamNonBlocking));
-    for (hipEvent_t* e : {&P->ev_fork, &P->ev_iso, &P->ev_lists, &P->ev_interior, &P->ev_band})
+    for (hipEvent_t* e : {&P->ev_fork, &P->ev_iso, &P->ev_lists, &P->ev_interior, &P->ev_band, &P->ev_classes})
         HIPX(hipEventCreateWithFlags(e, hipEventDisableTiming));
     P->p = p;
     P->method = desc->method;

@@ -146,7 +146,7 @@ IntArgs int_args(Plan& P, const iga_coeff& c, double* vals) {
 }
 
 CutEArgs cute_args(Plan& P, const iga_coeff& c) {
-    return CutEArgs{P.dir[0], P.dir[1], coef_view(P, c), P.cut_list, P.node_off, P.node_x, P.node_y, P.node_w,
+    return CutEArgs{P.dir[0], P.dir[1], coef_view(P, c), P.cut_e, P.node_off, P.node_x, P.node_y, P.node_w,
                     P.cutE, (int)P.n_cut_el, c.kind == IGA_COEF_GEOM_DETJ, c.geom_cp, P.n1, P.c_cut};
 }
 

@@ -610,7 +610,7 @@ __host__ __device__ inline int interior_ntx(int N1, int p) {
 struct CutEArgs {
     DirDev d1, d2;
     CoefView c;
-    const int* cut_list;
+    const int* cut_list;  // flat id of each cut element (as the cut-rule kernel found it)
     const int* node_off;
     const double *nx, *ny, *nw;
     double* E;

@@ -183,6 +183,7 @@ struct Plan {
     int* cut_list = nullptr;       // flat ids of cut elements
     int* band_list = nullptr;      // flat ids of band elements
     CutElemDev* cut_el = nullptr;
+    int* cut_e = nullptr;          // flat id of each cut element, written by the cut-rule kernel
     int* node_cnt = nullptr;
     int* node_off = nullptr;
     double* node_x = nullptr;      // n_cut_nodes
@@ -214,7 +215,8 @@ struct Plan {
     // second stream of the formation: univariate tables, weights, WQ-grid coefficient and interior
     // rows run there, beside the trimming chain (default priority; joined by events)
     hipStream_t aux = nullptr;
-    hipEvent_t ev_fork = nullptr, ev_iso = nullptr, ev_lists = nullptr, ev_interior = nullptr, ev_band = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_iso = nullptr, ev_lists = nullptr, ev_interior = nullptr, ev_band = nullptr,
+               ev_classes = nullptr;
 
     // timing
     bool timing = false;
@@ -300,6 +302,7 @@ void launch_trim_classes(Plan& P, hipStream_t s);           // elements, functio
 void launch_trim_lists(Plan& P, hipStream_t s);             // act_of, cut/band lists
 // per cut element segments, variant, counts; with fuse_nodes also the nodes, at the offsets plan creation found
 void launch_trim_cutprep(Plan& P, hipStream_t s, bool fuse_nodes = false);
+bool trim_lists_prefix_here(const Plan& P);                  // the list kernel sums its own row offsets
 void launch_trim_nodes(Plan& P, hipStream_t s);             // node coordinates and weights
 void launch_naive_mask(Plan& P, const double* src, double cval, hipStream_t s);
 void launch_row_nnz(Plan& P, int* cnt, int* out, hipStream_t s);

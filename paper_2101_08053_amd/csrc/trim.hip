@@ -1155,6 +1155,10 @@ __global__ void __launch_bounds__(256) k_list_rows(ListArgs A) {
     }
 }
 
+bool trim_lists_prefix_here(const Plan& P) {
+    return (int64_t)P.n2 * ((P.N1 + kClsTile - 1) / kClsTile) <= 8192;
+}
+
 void launch_trim_lists(Plan& P, hipStream_t s) {
     const int nf = P.n1 * P.n2, ne = P.N1 * P.N2;
     int* f_active = P.flags;
@@ -1171,7 +1175,7 @@ void launch_trim_lists(Plan& P, hipStream_t s) {
     A.ntx = (P.N1 + kClsTile - 1) / kClsTile;
     A.bsum = P.list_rcnt;
     A.counts = P.counts;
-    A.prefix_here = (int64_t)P.n2 * A.ntx <= 8192;
+    A.prefix_here = trim_lists_prefix_here(P);
     if (!A.prefix_here) hipLaunchKernelGGL(k_list_scan, dim3(1), dim3(1024), 0, s, A);
     hipLaunchKernelGGL(k_list_rows, dim3(P.n2), dim3(256), 0, s, A);
 }
@@ -1197,6 +1201,12 @@ struct CutArgs {
     double *nx, *ny, *nw;
     int* nel;
     double* xy;         // the cut nodes' entries of the rule-point table
+    // locate: each workgroup finds its element from the class kernel's counts of cut
+    // elements per element row and tile column (loc_m of them, row-major) and the flags
+    int locate, loc_m, ntx;
+    const int* loc_cnt;
+    const int* e_cut;
+    int* cut_e;         // the element's flat id, for the element-matrix kernel
 };
 
 __device__ __forceinline__ int arc_nq(const CutArgs& A, const CurveDev& C) {
@@ -1254,6 +1264,68 @@ __device__ bool in_any_hole_lds(const TrimDev& T, const PieceBox* sp, const int*
         if (in) return true;
     }
     return false;
+}
+
+// The flat id of the c-th cut element (flat order, as the list kernel
+// orders them), from the per-segment counts: the counts are summed in
+// groups of 256 (a wavefront sum each, 16 groups per batch of loads) until
+// the group holding element c; a scan over the lanes of that group finds the
+// segment (element row, tile column); the segment's flags give the column.
+// All 64 lanes; -1 if there are fewer cut elements than c + 1.
+__device__ int locate_cut_element(const CutArgs& A, int c) {
+    const int lane = threadIdx.x, m = A.loc_m;
+    constexpr int GB = 16;
+    int before = 0, kf = -1;
+    int vf[4] = {0, 0, 0, 0};
+#pragma unroll 1
+    for (int k0 = 0; k0 * 256 < m && kf < 0; k0 += GB) {
+        int v[GB][4];
+#pragma unroll
+        for (int g = 0; g < GB; ++g)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int t = (k0 + g) * 256 + 4 * lane + j;
+                const int x = A.loc_cnt[min(t, m - 1)];
+                v[g][j] = (t < m) ? x : 0;
+            }
+#pragma unroll
+        for (int g = 0; g < GB; ++g) {
+            const int tot = wave_sum_i(v[g][0] + v[g][1] + v[g][2] + v[g][3]);
+            if (kf < 0) {
+                if (before + tot > c) {
+                    kf = k0 + g;
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) vf[j] = v[g][j];
+                } else {
+                    before += tot;
+                }
+            }
+        }
+    }
+    if (kf < 0) return -1;
+    const int mine = vf[0] + vf[1] + vf[2] + vf[3];
+    int inc = mine;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int u = __shfl_up(inc, o, 64);
+        if (lane >= o) inc += u;
+    }
+    const int ex = before + inc - mine;
+    const unsigned long long hit = __ballot(ex <= c && c < ex + mine);
+    const int L = __ffsll((long long)hit) - 1;
+    int need = c - ex, j = 0;
+    while (j < 3 && need >= vf[j]) {
+        need -= vf[j];
+        ++j;
+    }
+    const int t = __builtin_amdgcn_readlane(kf * 256 + 4 * lane + j, L);
+    need = __builtin_amdgcn_readlane(need, L);
+    const int N1 = A.G.N1, row = t / A.ntx, col0 = (t % A.ntx) * 16, col = col0 + lane;
+    const bool f = lane < 16 && col < N1 && A.e_cut[(size_t)row * N1 + min(col, N1 - 1)] != 0;
+    unsigned long long fm = __ballot(f);
+    for (int k = 0; k < need; ++k) fm &= fm - 1ull;
+    if (fm == 0ull) return -1;
+    return row * N1 + col0 + __ffsll((long long)fm) - 1;
 }
 
 // The nodes write_cut_nodes writes, from what k_cutprep holds in LDS (the
@@ -1351,9 +1423,14 @@ __global__ void __launch_bounds__(64) k_cutprep(CutArgs A) {
     __shared__ double sSig[kMaxArcsPerElem];            // the arcs' curve orientation signs
     __shared__ double sSeg[4][kMaxEdgeSegs][2];          // merged visible pieces per edge
     __shared__ int sNseg[4], sVar, sCnt;
-    const int e = A.cut_list[c];
     // node offsets for the fused node writes, loaded while the rule is found
     const int off0 = A.fuse_nodes ? A.node_off[c] : 0, off1 = A.fuse_nodes ? A.node_off[c + 1] : 0;
+    const int e = A.locate ? locate_cut_element(A, c) : A.cut_list[c];
+    if (e < 0) {  // fewer cut elements than at plan creation
+        if (lane == 0) atomicExch(A.status, IGA_E_CAPACITY);
+        return;
+    }
+    if (lane == 0) A.cut_e[c] = e;
     const int e1 = e % A.G.N1, e2 = e / A.G.N1;
     const double xa = A.G.bp1[e1], xb = A.G.bp1[e1 + 1], ya = A.G.bp2[e2], yb = A.G.bp2[e2 + 1];
     CutElemDev& out = A.cut_el[c];
@@ -1574,6 +1651,15 @@ void launch_trim_cutprep(Plan& P, hipStream_t s, bool fuse_nodes) {
         A.nw = P.node_w;
         A.nel = P.node_el;
         A.xy = P.pts_xy + 2 * cut0;
+    }
+    A.cut_e = P.cut_e;
+    A.locate = trim_lists_prefix_here(P);
+    if (A.locate) {  // the element counts of the class kernel's tile-row segments
+        const int nf = P.n1 * P.n2;
+        A.ntx = (P.N1 + kClsTile - 1) / kClsTile;
+        A.loc_m = P.N2 * A.ntx;
+        A.loc_cnt = P.list_rcnt + (size_t)2 * P.n2 * A.ntx;
+        A.e_cut = P.flags + 2 * (nf + 1);
     }
     A.stage_pieces = (T.cap_pieces <= kPrepPieces) ? T.cap_pieces : 0;
     A.stage_segs = (A.stage_pieces > 0 && T.n_segs <= kPrepSegs) ? T.n_segs : 0;
