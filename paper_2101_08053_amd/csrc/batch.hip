@@ -3,14 +3,16 @@
 // The work of every patch is cut into items of four kinds: chunks of
 // coefficient points (|det J| of each patch's geometry), cut-element local
 // matrices, interior work items (one test-function row i2 x one tile of 64
-// rows i1) and element-formed rows. Items are queued kind by kind --
-// coefficients first, then cut elements, then interior and element-formed
-// rows together -- and by decreasing cost inside a kind, one queue per
-// degree. A fixed grid of workgroups, split over the degrees in proportion
+// rows i1) and element-formed rows. The first three are queued kind by kind
+// -- coefficients first, then cut elements, then interior rows -- and by
+// decreasing cost inside a kind, one queue per degree. The element-formed
+// rows follow in one launch per degree, one small workgroup per row: they are
+// latency-bound and need many rows in flight per CU, which the persistent
+// kernel's register budget (set by its largest body) does not allow. A fixed grid of workgroups, split over the degrees in proportion
 // to their work, takes items from its degree's queue head (one atomic add
 // each; the degree is fixed per workgroup, so each body is compiled for its
 // degree and the kernel's registers are those of the largest body).
-// Dependencies go by level (0: coefficients, 1: cut elements, 2: rows): a
+// Dependencies go by level (0: coefficients, 1: cut elements and interior rows): a
 // workgroup counts the items it finished at each level and publishes the
 // counts (one agent-scope release, i.e. one L2 write-back) only when it takes
 // its first item of a later level or runs out of items; before running an
@@ -65,12 +67,13 @@ struct BatchDev {
     int n_level[kBatchGroups][2];       // items of levels 0 and 1 per queue
 };
 
-__device__ __forceinline__ int item_level(int kind) { return kind == BK_COEF ? 0 : (kind == BK_CUTE ? 1 : 2); }
+// cut elements and interior rows need the coefficients only
+__device__ __forceinline__ int item_level(int kind) { return kind == BK_COEF ? 0 : 1; }
 
 template <int P>
 struct BatchSmemSize {
-    static constexpr size_t a = sizeof(IntSmem<P>), b = sizeof(CutESmem<P>), c = sizeof(CutRSmem<P>);
-    static constexpr size_t v = a > b ? (a > c ? a : c) : (b > c ? b : c);
+    static constexpr size_t a = sizeof(IntSmem<P>), b = sizeof(CutESmem<P>);
+    static constexpr size_t v = a > b ? a : b;
 };
 template <int P>
 constexpr size_t batch_smem_max() {
@@ -105,8 +108,7 @@ __device__ __forceinline__ void run_item(const BatchPlan& Bp, const BatchItem& i
         case BK_INT:
             interior_block<P>(Bp.ia, it.unit % Bp.ia.ntx, it.unit / Bp.ia.ntx, *reinterpret_cast<IntSmem<P>*>(smem));
             break;
-        default:
-            cut_row_body<P>(Bp.cr, it.unit, *reinterpret_cast<CutRSmem<P>*>(smem));
+        default:  // element-formed rows run in their own launch
             break;
     }
 }
@@ -192,6 +194,20 @@ __global__ void __launch_bounds__(256, MINW) k_batch(BatchDev B) {
     }
 }
 
+// Element-formed rows of the batch's patches of degree P, one workgroup per
+// row, after the persistent launch in stream order (so the coefficients and
+// cut element matrices it formed are complete): the fused body of the
+// one-patch formation, so the values are the same.
+constexpr int batch_cut_row_threads(int p) { return (((2 * p + 1) * (2 * p + 1) + 63) / 64) * 64; }
+
+template <int P>
+__global__ void __launch_bounds__(batch_cut_row_threads(P))
+    k_batch_cut_rows(const BatchPlan* __restrict__ plans, const BatchItem* __restrict__ items) {
+    __shared__ CutRSmem<P> S;
+    const BatchItem it = items[blockIdx.x];
+    cut_row_body<P>(plans[it.plan].cr, it.unit, S);
+}
+
 // ------------------------------------------------------------------ host
 struct Batch {
     std::vector<Plan*> plans;
@@ -202,6 +218,8 @@ struct Batch {
     double g_work[kBatchGroups] = {};
     BatchPlan* d_plans = nullptr;
     BatchItem* d_items = nullptr;
+    BatchItem* d_rows = nullptr;  // element-formed rows, by degree: rows_off[g] .. + rows_n[g]
+    int rows_off[kBatchGroups] = {}, rows_n[kBatchGroups] = {};
     int* d_counters = nullptr;  // status, heads[kBatchGroups], level counters[kBatchGroups][2]
     int n_items = 0;
     int n_cu = 256;
@@ -221,6 +239,7 @@ struct Batch {
         if (cap_stream) hipStreamDestroy(cap_stream);
         if (d_plans) hipFree(d_plans);
         if (d_items) hipFree(d_items);
+        if (d_rows) hipFree(d_rows);
         if (d_counters) hipFree(d_counters);
     }
     void drop_graph() {
@@ -276,6 +295,20 @@ struct Batch {
             if (capped) hipLaunchKernelGGL(k_batch<2>, dim3(total), dim3(256), 0, s, B);
             else hipLaunchKernelGGL(k_batch<1>, dim3(total), dim3(256), 0, s, B);
         }
+        for (int g = 0; g < kBatchGroups; ++g) {
+            if (rows_n[g] == 0) continue;
+            const BatchItem* it = d_rows + rows_off[g];
+            const dim3 grid((unsigned)rows_n[g]);
+            switch (g + 1) {
+#define CASE(PP)                                                                                              \
+    case PP:                                                                                                  \
+        hipLaunchKernelGGL(k_batch_cut_rows<PP>, grid, dim3(batch_cut_row_threads(PP)), 0, s, d_plans, it); \
+        break;
+                CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6)
+#undef CASE
+                default: break;
+            }
+        }
     }
 };
 
@@ -312,6 +345,7 @@ static iga_batch* batch_create(iga_plan* const* plans, int count, const iga_coef
         double cost;
     };
     std::vector<Cand> all;
+    std::vector<BatchItem> rows[kBatchGroups];
     for (int k = 0; k < count; ++k) {
         IGA_REQUIRE(plans[k], IGA_E_INVALID, "null plan in batch");
         Plan& P = *static_cast<Plan*>(plans[k]);
@@ -344,11 +378,15 @@ static iga_batch* batch_create(iga_plan* const* plans, int count, const iga_coef
         const int counts[BK_NKIND] = {n_coef, n_cute, n_int, n_cutr};
         for (int kind = 0; kind < BK_NKIND; ++kind) {
             bp.need[kind] = counts[kind];
+            if (kind == BK_CUTR) {  // their own launch, after the persistent one
+                for (int u = 0; u < counts[kind]; ++u) rows[P.p - 1].push_back(BatchItem{k, kind, u, 0});
+                continue;
+            }
             for (int u = 0; u < counts[kind]; ++u)
                 all.push_back({BatchItem{k, kind, u, 0}, item_cost(P, kind, u, node_off)});
         }
     }
-    // queues by degree; inside, kinds in dependency order (interior and element-formed rows share a
+    // queues by degree; inside, kinds in dependency order (coefficients, cut elements, interior rows),
     // stage), then by decreasing cost (or patch by patch)
     auto stage = [](int kind) { return kind == BK_COEF ? 0 : (kind == BK_CUTE ? 1 : 2); };
     auto deg = [&](const Cand& a) { return hp[a.it.plan].p; };
@@ -374,10 +412,19 @@ static iga_batch* batch_create(iga_plan* const* plans, int count, const iga_coef
     }
     for (auto& c : lpt) B->items_lpt.push_back(c.it);
     for (auto& c : pm) B->items_plan.push_back(c.it);
-    B->n_items = (int)all.size();
+    std::vector<BatchItem> rows_all;
+    for (int g = 0; g < kBatchGroups; ++g) {
+        B->rows_off[g] = (int)rows_all.size();
+        B->rows_n[g] = (int)rows[g].size();
+        rows_all.insert(rows_all.end(), rows[g].begin(), rows[g].end());
+    }
+    B->n_items = (int)(all.size() + rows_all.size());
     HIPX(hipMalloc(&B->d_plans, sizeof(BatchPlan) * count));
     HIPX(hipMemcpy(B->d_plans, hp.data(), sizeof(BatchPlan) * count, hipMemcpyHostToDevice));
-    HIPX(hipMalloc(&B->d_items, sizeof(BatchItem) * std::max(1, B->n_items)));
+    HIPX(hipMalloc(&B->d_items, sizeof(BatchItem) * std::max<size_t>(1, all.size())));
+    HIPX(hipMalloc(&B->d_rows, sizeof(BatchItem) * std::max<size_t>(1, rows_all.size())));
+    if (!rows_all.empty())
+        HIPX(hipMemcpy(B->d_rows, rows_all.data(), sizeof(BatchItem) * rows_all.size(), hipMemcpyHostToDevice));
     HIPX(hipMalloc(&B->d_counters, sizeof(int) * (1 + 3 * kBatchGroups)));
     HIPX(hipMemset(B->d_counters, 0, sizeof(int) * (1 + 3 * kBatchGroups)));
     B->upload_items(B->cap_stream);
