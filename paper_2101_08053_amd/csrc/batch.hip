@@ -2,17 +2,18 @@
 //
 // The work of every patch is cut into items of four kinds: chunks of
 // coefficient points (|det J| of each patch's geometry), cut-element local
-// matrices, interior work items (one test-function row i2 x one tile of 64
-// rows i1) and element-formed rows. The first three are queued kind by kind
-// -- coefficients first, then cut elements, then interior rows -- and by
-// decreasing cost inside a kind, one queue per degree. The element-formed
-// rows follow in one launch per degree, one small workgroup per row: they are
-// latency-bound and need many rows in flight per CU, which the persistent
-// kernel's register budget (set by its largest body) does not allow. A fixed grid of workgroups, split over the degrees in proportion
+// matrices, interior work items (one test-function row i2 x one tile of rows
+// i1) and element-formed rows. The uneven ones are queued kind by kind --
+// coefficients first, then cut elements -- and by decreasing cost inside a
+// kind, one queue per degree. The rows follow in launches of their own per
+// degree, interior tiles first, then one small workgroup per element-formed
+// row: regular or latency-bound work that needs many workgroups in flight per
+// CU, which the persistent kernel's register budget (set by its largest body)
+// does not allow. A fixed grid of workgroups, split over the degrees in proportion
 // to their work, takes items from its degree's queue head (one atomic add
 // each; the degree is fixed per workgroup, so each body is compiled for its
 // degree and the kernel's registers are those of the largest body).
-// Dependencies go by level (0: coefficients, 1: cut elements and interior rows): a
+// Dependencies go by level (0: coefficients, 1: cut elements): a
 // workgroup counts the items it finished at each level and publishes the
 // counts (one agent-scope release, i.e. one L2 write-back) only when it takes
 // its first item of a later level or runs out of items; before running an
@@ -67,13 +68,11 @@ struct BatchDev {
     int n_level[kBatchGroups][2];       // items of levels 0 and 1 per queue
 };
 
-// cut elements and interior rows need the coefficients only
 __device__ __forceinline__ int item_level(int kind) { return kind == BK_COEF ? 0 : 1; }
 
 template <int P>
 struct BatchSmemSize {
-    static constexpr size_t a = sizeof(IntSmem<P>), b = sizeof(CutESmem<P>);
-    static constexpr size_t v = a > b ? a : b;
+    static constexpr size_t v = sizeof(CutESmem<P>);
 };
 template <int P>
 constexpr size_t batch_smem_max() {
@@ -105,10 +104,7 @@ __device__ __forceinline__ void run_item(const BatchPlan& Bp, const BatchItem& i
         case BK_CUTE:
             cut_elem_body<P>(Bp.ce, it.unit, *reinterpret_cast<CutESmem<P>*>(smem));
             break;
-        case BK_INT:
-            interior_block<P>(Bp.ia, it.unit % Bp.ia.ntx, it.unit / Bp.ia.ntx, *reinterpret_cast<IntSmem<P>*>(smem));
-            break;
-        default:  // element-formed rows run in their own launch
+        default:  // rows run in launches of their own
             break;
     }
 }
@@ -194,6 +190,19 @@ __global__ void __launch_bounds__(256, MINW) k_batch(BatchDev B) {
     }
 }
 
+// Interior tiles of the batch's patches of degree P (the one-patch kernel's
+// tiles and body), after the persistent launch, which formed c on the grid.
+template <int P>
+__global__ void __launch_bounds__(Int2Cfg<P>::NT)
+    k_batch_interior(const BatchPlan* __restrict__ plans, const BatchItem* __restrict__ items) {
+    __shared__ __align__(16) Int2Smem<P> S;
+    const BatchItem it = items[xcd_block(blockIdx.x, gridDim.x)];
+    const BatchPlan& Bp = plans[it.plan];
+    const int ntx = interior2_ntx(Bp.ia.d1.N, P);
+    const int i2 = it.unit / ntx;
+    interior_rows_block<P>(Bp.ia, it.unit - i2 * ntx, i2, S);
+}
+
 // Element-formed rows of the batch's patches of degree P, one workgroup per
 // row, after the persistent launch in stream order (so the coefficients and
 // cut element matrices it formed are complete): the fused body of the
@@ -218,7 +227,8 @@ struct Batch {
     double g_work[kBatchGroups] = {};
     BatchPlan* d_plans = nullptr;
     BatchItem* d_items = nullptr;
-    BatchItem* d_rows = nullptr;  // element-formed rows, by degree: rows_off[g] .. + rows_n[g]
+    BatchItem* d_rows = nullptr;  // interior tiles, then element-formed rows, by degree
+    int int_off[kBatchGroups] = {}, int_n[kBatchGroups] = {};
     int rows_off[kBatchGroups] = {}, rows_n[kBatchGroups] = {};
     int* d_counters = nullptr;  // status, heads[kBatchGroups], level counters[kBatchGroups][2]
     int n_items = 0;
@@ -296,6 +306,20 @@ struct Batch {
             else hipLaunchKernelGGL(k_batch<1>, dim3(total), dim3(256), 0, s, B);
         }
         for (int g = 0; g < kBatchGroups; ++g) {
+            if (int_n[g] == 0) continue;
+            const BatchItem* it = d_rows + int_off[g];
+            const dim3 grid((unsigned)int_n[g]);
+            switch (g + 1) {
+#define CASE(PP)                                                                                        \
+    case PP:                                                                                            \
+        hipLaunchKernelGGL(k_batch_interior<PP>, grid, dim3(Int2Cfg<PP>::NT), 0, s, d_plans, it); \
+        break;
+                CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6)
+#undef CASE
+                default: break;
+            }
+        }
+        for (int g = 0; g < kBatchGroups; ++g) {
             if (rows_n[g] == 0) continue;
             const BatchItem* it = d_rows + rows_off[g];
             const dim3 grid((unsigned)rows_n[g]);
@@ -345,7 +369,7 @@ static iga_batch* batch_create(iga_plan* const* plans, int count, const iga_coef
         double cost;
     };
     std::vector<Cand> all;
-    std::vector<BatchItem> rows[kBatchGroups];
+    std::vector<BatchItem> tiles[kBatchGroups], rows[kBatchGroups];
     for (int k = 0; k < count; ++k) {
         IGA_REQUIRE(plans[k], IGA_E_INVALID, "null plan in batch");
         Plan& P = *static_cast<Plan*>(plans[k]);
@@ -373,21 +397,22 @@ static iga_batch* batch_create(iga_plan* const* plans, int count, const iga_coef
             HIPX(hipMemcpy(node_off.data(), P.node_off, sizeof(int) * (P.n_cut_el + 1), hipMemcpyDeviceToHost));
         const int64_t npts = bp.co.nq + bp.co.nb;
         const int n_coef = (c.kind == IGA_COEF_GEOM_DETJ) ? (int)((npts + kCoefChunk - 1) / kCoefChunk) : 0;
-        const int n_int = (P.method == IGA_GAUSS_REF) ? 0 : bp.ia.ntx * P.n2;
+        const int n_int = (P.method == IGA_GAUSS_REF) ? 0 : interior2_ntx(P.N1, P.p) * P.n2;
         const int n_cute = (int)P.n_cut_el, n_cutr = (int)P.n_form_rows;
         const int counts[BK_NKIND] = {n_coef, n_cute, n_int, n_cutr};
         for (int kind = 0; kind < BK_NKIND; ++kind) {
             bp.need[kind] = counts[kind];
-            if (kind == BK_CUTR) {  // their own launch, after the persistent one
-                for (int u = 0; u < counts[kind]; ++u) rows[P.p - 1].push_back(BatchItem{k, kind, u, 0});
+            if (kind == BK_INT || kind == BK_CUTR) {  // their own launches, after the persistent one
+                auto& dst = (kind == BK_INT) ? tiles[P.p - 1] : rows[P.p - 1];
+                for (int u = 0; u < counts[kind]; ++u) dst.push_back(BatchItem{k, kind, u, 0});
                 continue;
             }
             for (int u = 0; u < counts[kind]; ++u)
                 all.push_back({BatchItem{k, kind, u, 0}, item_cost(P, kind, u, node_off)});
         }
     }
-    // queues by degree; inside, kinds in dependency order (coefficients, cut elements, interior rows),
-    // stage), then by decreasing cost (or patch by patch)
+    // queues by degree; inside, kinds in dependency order (coefficients, then cut elements), then
+    // by decreasing cost (or patch by patch)
     auto stage = [](int kind) { return kind == BK_COEF ? 0 : (kind == BK_CUTE ? 1 : 2); };
     auto deg = [&](const Cand& a) { return hp[a.it.plan].p; };
     std::vector<Cand> lpt = all;
@@ -413,6 +438,11 @@ static iga_batch* batch_create(iga_plan* const* plans, int count, const iga_coef
     for (auto& c : lpt) B->items_lpt.push_back(c.it);
     for (auto& c : pm) B->items_plan.push_back(c.it);
     std::vector<BatchItem> rows_all;
+    for (int g = 0; g < kBatchGroups; ++g) {
+        B->int_off[g] = (int)rows_all.size();
+        B->int_n[g] = (int)tiles[g].size();
+        rows_all.insert(rows_all.end(), tiles[g].begin(), tiles[g].end());
+    }
     for (int g = 0; g < kBatchGroups; ++g) {
         B->rows_off[g] = (int)rows_all.size();
         B->rows_n[g] = (int)rows[g].size();
