@@ -141,7 +141,7 @@ IntArgs int_args(Plan& P, const iga_coeff& c, double* vals) {
     A.vals = vals;
     A.n_act = P.n_act;
     A.tile2 = P.tile2;
-    A.ntx = interior_ntx(P.N1, P.p);
+    A.ntx = interior2_ntx(P.N1, P.p);
     return A;
 }
 

@@ -70,43 +70,8 @@ struct IntArgs {
     double* vals;
     int64_t n_act;
     int tile2;
-    int ntx;                 // tiles along xi_1
+    int ntx;                 // tiles along xi_1 (interior2_ntx)
 };
-
-template <int P>
-struct IntCfg {
-    static constexpr int W = 2 * P + 1;                  // band width
-    static constexpr int QM = 4 * P + 2;                 // max WQ points in one support
-    static constexpr int NR = 2 * P + 2;                 // support points of a regular function
-    static constexpr int KS = 2 * (64 + P) + 2 * P + 2;  // max xi_1 points of a tile window
-    static constexpr int KG = 4 * P + 2;                 // max xi_1 points of a boundary tile
-    static constexpr bool WBREG = (P <= 5);              // w1 * B1 of each lane held in registers
-};
-
-// Tiles along xi_1: for N1 >= p+3, tile 0 holds the p+1 functions whose
-// support touches the first element, the last tile those touching the last
-// element (their elements carry p+1 points), and the tiles in between hold
-// 64 "regular" functions each (2 points in every support element). Smaller
-// patches use one generic tile.
-__device__ __forceinline__ void tile_of(int tx, int ntx, int N1, int n1, int p, int& I1, int& nlive, bool& generic) {
-    if (N1 < p + 3) {
-        I1 = 0;
-        nlive = n1;
-        generic = true;
-    } else if (tx == 0) {
-        I1 = 0;
-        nlive = p + 1;
-        generic = true;
-    } else if (tx == ntx - 1) {
-        I1 = N1 - 1;
-        nlive = p + 1;
-        generic = true;
-    } else {
-        I1 = p + 1 + 64 * (tx - 1);
-        nlive = min(64, (N1 - 2) - I1 + 1);
-        generic = false;
-    }
-}
 
 // Workgroups are handed to the XCDs round-robin; renumber them so that each
 // XCD works on a contiguous range of rows (neighbouring rows share most of
@@ -116,8 +81,7 @@ __device__ __forceinline__ int xcd_block(int bid, int nb) {
     return x * q + min(x, r) + (bid >> 3);
 }
 
-// One column b of one interior row, shared by the one-launch and the batched
-// bodies so that both give the same bits. Tk points at T[b] for the row's
+// One column b of one interior row. Tk points at T[b] for the row's
 // first support point. A row touching no end element: 2p+2 points, two per
 // element m, factors wbf(q, al) = (w1 B1) at point q for column m + al.
 template <int P, typename WBF>
@@ -160,160 +124,7 @@ __device__ __forceinline__ void interior_col_end(const double* wb, const double*
     }
 }
 
-template <int P>
-struct IntSmem {
-    static constexpr int W = IntCfg<P>::W, QM = IntCfg<P>::QM, KS = IntCfg<P>::KS, KG = IntCfg<P>::KG;
-    double sT[W][KS];                              // T[b][k - k1lo]
-    double sWB2[QM][W];                            // w2 * B2 of the row
-};
-
-// One work item = one test-function row i2 and a tile tx of (up to) 64
-// rows i1 (256 threads). Stage 1
-// contracts xi_2 for every xi_1 point k of the tile's window,
-//   T[b][k] = sum_q (w2 B2)[i2][q][b] c(k, k2lo + q),
-// one point per thread; stage 2 contracts xi_1, one row i1 per lane,
-//   M[a][b] = sum_k (w1 B1)[i1][k][a] T[b][k],
-// the four wavefronts sharing the 2p+1 columns b. Every global load of a
-// stage is issued before the first one is used.
-template <int P>
-__device__ __forceinline__ void interior_block(const IntArgs& A, int tx, int i2, IntSmem<P>& S) {
-    using C = IntCfg<P>;
-    constexpr int W = C::W, QM = C::QM, NR = C::NR, KG = C::KG;
-    auto& sT = S.sT;
-    auto& sWB2 = S.sWB2;
-
-    const DirDev& D1 = A.d1;
-    const DirDev& D2 = A.d2;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    int I1, nlive;
-    bool generic;
-    tile_of(tx, A.ntx, D1.N, D1.n, P, I1, nlive, generic);
-    const int elo = max(0, I1 - P), ehi = min(D1.N - 1, I1 + nlive - 1);
-    const int k1lo = wq_pt0(elo, D1.N, P);
-    const int ks = wq_pt0(ehi + 1, D1.N, P) - k1lo;
-    const int i1 = I1 + lane;
-
-    __syncthreads();   // LDS of the previous work item is free
-
-    {
-        if (i2 >= D2.n) return;
-        const int k2lo = wq_pt0(max(0, i2 - P), D2.N, P);
-        const int q2 = wq_pt0(min(D2.N - 1, i2) + 1, D2.N, P) - k2lo;
-        const bool reg_row = (i2 >= P + 1) && (i2 <= D2.N - 2);  // q2 == NR, two points per element
-
-        // ---- loads: row identity, xi_2 factors, coefficient column
-        bool live = false;
-        int64_t cid = 0;
-        if (lane < nlive) {
-            const int f = i2 * D1.n + i1;
-            const int8_t cls = A.fcls[f];
-            const int id = A.act_of[f];
-            live = A.all_active ? (cls != FN_EXTERIOR) : (cls == FN_INTERIOR);
-            cid = id;
-        }
-        // the row's xi_2 factors: (4p+2)(2p+1) entries, more than 256 from p = 6 on
-        constexpr int NWB = (QM * W + 255) / 256;
-        double wb2[NWB];
-#pragma unroll
-        for (int u = 0; u < NWB; ++u) {
-            const int t = tid + 256 * u;
-            wb2[u] = (t < QM * W && t / W < q2) ? D2.WB[((size_t)i2 * D2.qmax) * W + t] : 0.0;
-        }
-        const int kk = min(tid, ks - 1);
-        double cv[QM];
-        if (reg_row) {
-            if (A.cwq) {
-                const double* cc = A.cwq + (size_t)k2lo * D1.Q + k1lo + kk;
-#pragma unroll
-                for (int q = 0; q < NR; ++q) cv[q] = cc[(size_t)q * D1.Q];
-            } else {
-#pragma unroll
-                for (int q = 0; q < NR; ++q) cv[q] = A.c.value;
-            }
-        } else {
-            if (A.cwq) {
-                const double* cc = A.cwq + (size_t)k2lo * D1.Q + k1lo + kk;
-#pragma unroll
-                for (int q = 0; q < QM; ++q) cv[q] = (q < q2) ? cc[(size_t)q * D1.Q] : 0.0;
-            } else {
-#pragma unroll
-                for (int q = 0; q < QM; ++q) cv[q] = (q < q2) ? A.c.value : 0.0;
-            }
-        }
-#pragma unroll
-        for (int u = 0; u < NWB; ++u) {
-            const int t = tid + 256 * u;
-            if (t < QM * W) sWB2[t / W][t % W] = wb2[u];
-        }
-        if (!__syncthreads_or(live)) return;   // no row of the tile is formed here
-
-        // ---- stage 1: contract xi_2 for every xi_1 point of the window
-        if (tid < ks) {
-            if (reg_row) {
-                double T[W];
-#pragma unroll
-                for (int b = 0; b < W; ++b) T[b] = 0.0;
-#pragma unroll
-                for (int q = 0; q < NR; ++q) {
-                    const int m2 = q >> 1;
-#pragma unroll
-                    for (int bl = 0; bl <= P; ++bl) T[m2 + bl] += sWB2[q][m2 + bl] * cv[q];
-                }
-#pragma unroll
-                for (int b = 0; b < W; ++b) sT[b][tid] = T[b];
-            } else {
-#pragma unroll 1
-                for (int b = 0; b < W; ++b) {
-                    double Tb = 0.0;
-#pragma unroll
-                    for (int q = 0; q < QM; ++q) Tb += sWB2[q][b] * cv[q];
-                    sT[b][tid] = Tb;
-                }
-            }
-        }
-        // regular lanes: w1 * B1 at the 2p+2 support points, loaded while stage 1 finishes
-        double wb[C::WBREG ? NR : 1][C::WBREG ? P + 1 : 1];
-        const int i1c = min(i1, D1.n - 1);
-        const double* wrow = D1.WB + (size_t)i1c * D1.qmax * W;
-        if (!generic && C::WBREG) {  // from the banded copy: consecutive lanes, consecutive addresses
-#pragma unroll
-            for (int q = 0; q < NR; ++q)
-#pragma unroll
-                for (int al = 0; al <= P; ++al) wb[q][al] = D1.WBT[((size_t)q * (P + 1) + al) * D1.n + i1c];
-        }
-        __syncthreads();
-
-        // ---- stage 2: contract xi_1, one row per lane, columns b shared by the wavefronts
-        if (!live) return;
-        if (!generic) {
-            // regular lane: support points 2*lane .. 2*lane + 2p+1 of the window, two per element
-#pragma unroll 1
-            for (int b = wave; b < W; b += 4) {
-                double acc[W];
-                if constexpr (C::WBREG)
-                    interior_col_reg<P>([&](int q, int al) { return wb[q][al]; }, &sT[b][2 * lane], acc);
-                else
-                    interior_col_reg<P>([&](int q, int al) { return D1.WBT[((size_t)q * (P + 1) + al) * D1.n + i1c]; },
-                                        &sT[b][2 * lane], acc);
-#pragma unroll
-                for (int a = 0; a < W; ++a) A.vals[(size_t)(a * W + b) * A.n_act + cid] = acc[a];
-            }
-        } else {
-            // a row touching the first or last element: its full factor rows
-            const int k0 = wq_pt0(max(0, i1 - P), D1.N, P);
-            const int q1 = wq_pt0(min(D1.N - 1, i1) + 1, D1.N, P) - k0;
-#pragma unroll 1
-            for (int b = wave; b < W; b += 4) {
-                double acc[W];
-                interior_col_end<P>(wrow, &sT[b][k0 - k1lo], q1, acc);
-#pragma unroll
-                for (int a = 0; a < W; ++a) A.vals[(size_t)(a * W + b) * A.n_act + cid] = acc[a];
-            }
-        }
-    }
-}
-
-// Interior rows, one-launch form. Per test row i2: tiles of up to R
+// Interior rows (the one-patch kernel and the batched launches). Per test row i2: tiles of up to R
 // consecutive "regular" test rows i1 (p+1 <= i1 <= N1-2, two WQ points in
 // every support element), each row's 2p+1 columns b dealt round-robin to NB
 // threads (R * NB threads per workgroup: enough waves in flight to cover the
@@ -321,8 +132,8 @@ __device__ __forceinline__ void interior_block(const IntArgs& A, int tx, int i2,
 // touching the first or last element, p+1 points there), one thread per
 // (end row, column b). Stage 1 contracts xi_2 for every xi_1
 // point of the workgroup's window into T[b][k] (LDS); stage 2 contracts xi_1,
-// M[a][b] = sum_k (w1 B1)[i1][k][a] T[b][k], with the per-column sums of the
-// batched body. A regular row's banded w1 B1 factors are loaded into
+// M[a][b] = sum_k (w1 B1)[i1][k][a] T[b][k], per column. A regular row's
+// banded w1 B1 factors are loaded into
 // registers (p <= 5) together with every other global load of the
 // workgroup, before stage 1; the end rows' full factor rows go to LDS.
 // Rows per tile and column groups per row, measured: whole rows per thread
@@ -599,11 +410,6 @@ __device__ __forceinline__ void interior_rows_block(const IntArgs& A, int tx, in
             for (int a = 0; a < W; ++a) A.vals[(size_t)(a * W + bcol) * A.n_act + cide] = acc[a];
         }
     }
-}
-
-// Tiles along xi_1 of a patch with N1 elements.
-__host__ __device__ inline int interior_ntx(int N1, int p) {
-    return (N1 < p + 3) ? 1 : 2 + ((N1 - 2) - (p + 1) + 1 + 63) / 64;
 }
 
 // ------------------------------------------------------------ cut element matrices
