@@ -230,15 +230,17 @@ int iga_mf_apply(iga_plan* plan, const double* c_points, const double* u, double
 int iga_mf_adjoint(iga_plan* plan, const double* c_points, const double* u, const double* gy,
                    double* du, double* dc, void* stream);
 
-/* Batched formation of many patches (the batched use named in the north
- * star; each patch's rules as in Sects. 2-3): the resident tables of count
- * plans (set up, each plan with its own degree <= 6, method hybrid Gauss or
- * element Gauss) are formed into vals[k] (device, band_k * n_act_k doubles)
- * with coefficient cs[k], in ONE persistent launch (plus a counter reset):
- * a cost-sorted work queue of coefficient chunks, cut-element matrices,
- * interior work items and element-formed rows of all patches, taken by a
- * fixed grid of workgroups; items that need another kind's results of their
- * patch wait on that patch's completion counter (bounded wait).
+/* Batched formation of many patches (each patch's rules as in Sects. 2-3):
+ * the resident tables of count plans (set up, each plan with its own degree
+ * <= 6, method hybrid Gauss or element Gauss) are formed into vals[k]
+ * (device, band_k * n_act_k doubles) with coefficient cs[k]. The uneven
+ * work, the cut-element matrices of all patches (node counts differ), is one
+ * persistent launch (plus a counter reset): a cost-sorted work queue per
+ * degree taken by a fixed grid of workgroups. Beside it, on a second stream,
+ * the coefficient chunks and then the interior tiles run in one launch per
+ * degree; once the persistent launch and the coefficient chunks are done,
+ * the element-formed rows run in one launch per degree (one workgroup per
+ * row). The values equal the one-patch formation's bit for bit.
  *
  * A batch object keeps the descriptors, the queue and, with use_graph != 0,
  * a HIP graph recorded on the first such call and replayed afterwards. The
@@ -248,7 +250,7 @@ int iga_mf_adjoint(iga_plan* plan, const double* c_points, const double* u, cons
 typedef struct iga_batch iga_batch;
 typedef struct iga_batch_stats {
     int64_t n_plans;
-    int64_t n_items;      /* work items in the queue                    */
+    int64_t n_items;      /* work items: queued ones and those of the other launches */
     int64_t nnz;          /* sum of the plans' structural non-zeros     */
     int32_t grid;         /* persistent workgroups                      */
     int32_t wg_per_cu;    /* workgroups per compute unit (autotuned)    */

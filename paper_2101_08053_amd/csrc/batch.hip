@@ -3,30 +3,36 @@
 // The work of every patch is cut into items of four kinds: chunks of
 // coefficient points (|det J| of each patch's geometry), cut-element local
 // matrices, interior work items (one test-function row i2 x one tile of rows
-// i1) and element-formed rows. The uneven ones are queued kind by kind --
-// coefficients first, then cut elements -- and by decreasing cost inside a
-// kind, one queue per degree. The rows follow in launches of their own per
-// degree, interior tiles first, then one small workgroup per element-formed
-// row: regular or latency-bound work that needs many workgroups in flight per
-// CU, which the persistent kernel's register budget (set by its largest body)
-// does not allow. A fixed grid of workgroups, split over the degrees in proportion
-// to their work, takes items from its degree's queue head (one atomic add
-// each; the degree is fixed per workgroup, so each body is compiled for its
-// degree and the kernel's registers are those of the largest body).
-// Dependencies go by level (0: coefficients, 1: cut elements): a
-// workgroup counts the items it finished at each level and publishes the
-// counts (one agent-scope release, i.e. one L2 write-back) only when it takes
-// its first item of a later level or runs out of items; before running an
-// item of level l it waits (agent-scope acquire) until its degree's items of
-// all lower levels are published. Every item of a lower level sits earlier in
-// the queue and is held by a workgroup that publishes before it waits, so the
-// waits always end; each is bounded all the same, and past the bound the
-// item proceeds and the batch status records the timeout.
+// i1) and element-formed rows. The cut element matrices, uneven in their
+// node counts, are queued by decreasing cost, one queue per degree, for the
+// persistent launch. The rest is regular or latency-bound work that needs
+// many workgroups in flight per CU, which the persistent kernel's registers
+// and LDS (set by its largest body) do not allow, so it runs in launches of
+// its own per degree: on a second stream, beside the persistent launch, the
+// coefficient chunks and then the interior tiles; on the first, once the
+// persistent launch and the coefficient chunks are done, one small workgroup
+// per element-formed row (beside the interior tiles).
 //
-// A batch object keeps the descriptors, the item list, the counters and,
-// once asked, a HIP graph of the two launches (counter reset, persistent
-// kernel); the autotuner times the grid size and the item order on the
-// device and keeps the fastest.
+// The persistent launch: a fixed grid of workgroups, split over the degrees
+// in proportion to their work, takes items from its degree's queue head (one
+// atomic add per chunk of items; the degree is fixed per workgroup, so each
+// body is compiled for its degree and the kernel's registers are those of
+// the largest body). The queue keeps dependency levels (0: coefficients,
+// 1: cut elements): a workgroup counts the items it finished at each level
+// and publishes the counts (one agent-scope release, i.e. one L2 write-back)
+// only when it takes its first item of a later level or runs out of items;
+// before running an item of level l it waits (agent-scope acquire) until its
+// degree's items of all lower levels are published. Every item of a lower
+// level sits earlier in the queue and is held by a workgroup that publishes
+// before it waits, so the waits always end; each is bounded all the same, and
+// past the bound the item proceeds and the batch status records the timeout.
+// With the coefficients in launches of their own the queue holds level-1
+// items only, so no workgroup waits.
+//
+// A batch object keeps the descriptors, the item lists, the counters and,
+// once asked, a HIP graph of all the launches on both streams; the autotuner
+// times the persistent grid, register budget, queue chunk and item order on
+// the device and keeps the fastest.
 #include <algorithm>
 #include <memory>
 #include <vector>
@@ -94,19 +100,8 @@ __device__ __forceinline__ bool wait_count(int* ctr, int need, int limit) {
 
 template <int P>
 __device__ __forceinline__ void run_item(const BatchPlan& Bp, const BatchItem& it, unsigned char* smem) {
-    switch (it.kind) {
-        case BK_COEF: {
-            const int64_t n = Bp.co.nq + Bp.co.nb;  // cut nodes: with the cut element items
-            const int64_t t0 = (int64_t)it.unit * kCoefChunk;
-            for (int64_t t = t0 + threadIdx.x; t < min(n, t0 + kCoefChunk); t += 256) coef_point<P>(Bp.co, t);
-            break;
-        }
-        case BK_CUTE:
-            cut_elem_body<P>(Bp.ce, it.unit, *reinterpret_cast<CutESmem<P>*>(smem));
-            break;
-        default:  // rows run in launches of their own
-            break;
-    }
+    if (it.kind == BK_CUTE) cut_elem_body<P>(Bp.ce, it.unit, *reinterpret_cast<CutESmem<P>*>(smem));
+    // coefficient chunks and rows run in launches of their own
 }
 
 __global__ void k_batch_reset(int* counters, int n) {
@@ -190,8 +185,22 @@ __global__ void __launch_bounds__(256, MINW) k_batch(BatchDev B) {
     }
 }
 
+// Coefficient chunks of the batch's patches of degree P: |det J| at the WQ
+// grid and band Gauss points (the cut element matrices evaluate it at their
+// nodes themselves). One point per thread: kCoefChunk / 256 workgroups per
+// chunk.
+template <int P>
+__global__ void __launch_bounds__(256)
+    k_batch_coef(const BatchPlan* __restrict__ plans, const BatchItem* __restrict__ items) {
+    constexpr int WPC = kCoefChunk / 256;
+    const BatchItem it = items[blockIdx.x / WPC];
+    const CoefArgs& co = plans[it.plan].co;
+    const int64_t t = (int64_t)it.unit * kCoefChunk + (blockIdx.x % WPC) * 256 + threadIdx.x;
+    if (t < co.nq + co.nb) coef_point<P>(co, t);
+}
+
 // Interior tiles of the batch's patches of degree P (the one-patch kernel's
-// tiles and body), after the persistent launch, which formed c on the grid.
+// tiles and body), after the coefficient chunks on the same stream.
 template <int P>
 __global__ void __launch_bounds__(Int2Cfg<P>::NT)
     k_batch_interior(const BatchPlan* __restrict__ plans, const BatchItem* __restrict__ items) {
@@ -204,8 +213,8 @@ __global__ void __launch_bounds__(Int2Cfg<P>::NT)
 }
 
 // Element-formed rows of the batch's patches of degree P, one workgroup per
-// row, after the persistent launch in stream order (so the coefficients and
-// cut element matrices it formed are complete): the fused body of the
+// row, after the persistent launch and the coefficient chunks (so the
+// coefficients and cut element matrices are complete): the fused body of the
 // one-patch formation, so the values are the same.
 constexpr int batch_cut_row_threads(int p) { return (((2 * p + 1) * (2 * p + 1) + 63) / 64) * 64; }
 
@@ -227,7 +236,8 @@ struct Batch {
     double g_work[kBatchGroups] = {};
     BatchPlan* d_plans = nullptr;
     BatchItem* d_items = nullptr;
-    BatchItem* d_rows = nullptr;  // interior tiles, then element-formed rows, by degree
+    BatchItem* d_rows = nullptr;  // coefficient chunks, interior tiles, element-formed rows, by degree
+    int coef_off[kBatchGroups] = {}, coef_n[kBatchGroups] = {};
     int int_off[kBatchGroups] = {}, int_n[kBatchGroups] = {};
     int rows_off[kBatchGroups] = {}, rows_n[kBatchGroups] = {};
     int* d_counters = nullptr;  // status, heads[kBatchGroups], level counters[kBatchGroups][2]
@@ -241,12 +251,18 @@ struct Batch {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     hipStream_t cap_stream = nullptr;
+    hipStream_t side = nullptr;  // coefficient chunks and interior tiles, beside the persistent launch
+    hipEvent_t ev_fork = nullptr, ev_coef = nullptr, ev_join = nullptr;
     int64_t nnz = 0;
 
     ~Batch() {
         if (exec) hipGraphExecDestroy(exec);
         if (graph) hipGraphDestroy(graph);
         if (cap_stream) hipStreamDestroy(cap_stream);
+        if (side) hipStreamDestroy(side);
+        if (ev_fork) hipEventDestroy(ev_fork);
+        if (ev_join) hipEventDestroy(ev_join);
+        if (ev_coef) hipEventDestroy(ev_coef);
         if (d_plans) hipFree(d_plans);
         if (d_items) hipFree(d_items);
         if (d_rows) hipFree(d_rows);
@@ -284,6 +300,38 @@ struct Batch {
     }
     void launch(hipStream_t s) {
         const int nc = 1 + 3 * kBatchGroups;  // status, heads, level counters
+        HIPX(hipEventRecord(ev_fork, s));
+        HIPX(hipStreamWaitEvent(side, ev_fork, 0));
+        for (int g = 0; g < kBatchGroups; ++g) {
+            if (coef_n[g] == 0) continue;
+            const BatchItem* it = d_rows + coef_off[g];
+            const dim3 grid((unsigned)coef_n[g] * (kCoefChunk / 256));
+            switch (g + 1) {
+#define CASE(PP)                                                                             \
+    case PP:                                                                                 \
+        hipLaunchKernelGGL(k_batch_coef<PP>, grid, dim3(256), 0, side, d_plans, it); \
+        break;
+                CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6)
+#undef CASE
+                default: break;
+            }
+        }
+        HIPX(hipEventRecord(ev_coef, side));
+        for (int g = 0; g < kBatchGroups; ++g) {
+            if (int_n[g] == 0) continue;
+            const BatchItem* it = d_rows + int_off[g];
+            const dim3 grid((unsigned)int_n[g]);
+            switch (g + 1) {
+#define CASE(PP)                                                                                           \
+    case PP:                                                                                               \
+        hipLaunchKernelGGL(k_batch_interior<PP>, grid, dim3(Int2Cfg<PP>::NT), 0, side, d_plans, it); \
+        break;
+                CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6)
+#undef CASE
+                default: break;
+            }
+        }
+        HIPX(hipEventRecord(ev_join, side));
         hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(64), 0, s, d_counters, nc);
         BatchDev B{};
         B.plans = d_plans;
@@ -305,20 +353,7 @@ struct Batch {
             if (capped) hipLaunchKernelGGL(k_batch<2>, dim3(total), dim3(256), 0, s, B);
             else hipLaunchKernelGGL(k_batch<1>, dim3(total), dim3(256), 0, s, B);
         }
-        for (int g = 0; g < kBatchGroups; ++g) {
-            if (int_n[g] == 0) continue;
-            const BatchItem* it = d_rows + int_off[g];
-            const dim3 grid((unsigned)int_n[g]);
-            switch (g + 1) {
-#define CASE(PP)                                                                                        \
-    case PP:                                                                                            \
-        hipLaunchKernelGGL(k_batch_interior<PP>, grid, dim3(Int2Cfg<PP>::NT), 0, s, d_plans, it); \
-        break;
-                CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6)
-#undef CASE
-                default: break;
-            }
-        }
+        HIPX(hipStreamWaitEvent(s, ev_coef, 0));
         for (int g = 0; g < kBatchGroups; ++g) {
             if (rows_n[g] == 0) continue;
             const BatchItem* it = d_rows + rows_off[g];
@@ -333,6 +368,7 @@ struct Batch {
                 default: break;
             }
         }
+        HIPX(hipStreamWaitEvent(s, ev_join, 0));
     }
 };
 
@@ -363,13 +399,17 @@ static iga_batch* batch_create(iga_plan* const* plans, int count, const iga_coef
     // grid then keeps more of its items in flight (measured faster). Only
     // resident workgroups ever hold items, so the dependency waits still end.
     HIPX(hipStreamCreate(&B->cap_stream));
+    HIPX(hipStreamCreateWithFlags(&B->side, hipStreamNonBlocking));
+    HIPX(hipEventCreateWithFlags(&B->ev_fork, hipEventDisableTiming));
+    HIPX(hipEventCreateWithFlags(&B->ev_join, hipEventDisableTiming));
+    HIPX(hipEventCreateWithFlags(&B->ev_coef, hipEventDisableTiming));
     std::vector<BatchPlan> hp(count);
     struct Cand {
         BatchItem it;
         double cost;
     };
     std::vector<Cand> all;
-    std::vector<BatchItem> tiles[kBatchGroups], rows[kBatchGroups];
+    std::vector<BatchItem> coefs[kBatchGroups], tiles[kBatchGroups], rows[kBatchGroups];
     for (int k = 0; k < count; ++k) {
         IGA_REQUIRE(plans[k], IGA_E_INVALID, "null plan in batch");
         Plan& P = *static_cast<Plan*>(plans[k]);
@@ -402,8 +442,8 @@ static iga_batch* batch_create(iga_plan* const* plans, int count, const iga_coef
         const int counts[BK_NKIND] = {n_coef, n_cute, n_int, n_cutr};
         for (int kind = 0; kind < BK_NKIND; ++kind) {
             bp.need[kind] = counts[kind];
-            if (kind == BK_INT || kind == BK_CUTR) {  // their own launches, after the persistent one
-                auto& dst = (kind == BK_INT) ? tiles[P.p - 1] : rows[P.p - 1];
+            if (kind != BK_CUTE) {  // launches of their own
+                auto& dst = (kind == BK_COEF) ? coefs[P.p - 1] : (kind == BK_INT) ? tiles[P.p - 1] : rows[P.p - 1];
                 for (int u = 0; u < counts[kind]; ++u) dst.push_back(BatchItem{k, kind, u, 0});
                 continue;
             }
@@ -438,6 +478,11 @@ static iga_batch* batch_create(iga_plan* const* plans, int count, const iga_coef
     for (auto& c : lpt) B->items_lpt.push_back(c.it);
     for (auto& c : pm) B->items_plan.push_back(c.it);
     std::vector<BatchItem> rows_all;
+    for (int g = 0; g < kBatchGroups; ++g) {
+        B->coef_off[g] = (int)rows_all.size();
+        B->coef_n[g] = (int)coefs[g].size();
+        rows_all.insert(rows_all.end(), coefs[g].begin(), coefs[g].end());
+    }
     for (int g = 0; g < kBatchGroups; ++g) {
         B->int_off[g] = (int)rows_all.size();
         B->int_n[g] = (int)tiles[g].size();

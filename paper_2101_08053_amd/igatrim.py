@@ -318,7 +318,7 @@ class Plan:
 
 
 def mass_form(patch, method=HYBRID_GAUSS, coef=None, **kw):
-    """One-call form of the spec entry point: knots, degree, trim curves, c, method -> band values."""
+    """One-call form of the formation entry point: knots, degree, trim curves, c, method -> band values."""
     plan = Plan(patch, method, **kw)
     c = plan.coeff() if coef is None else coef
     return plan, plan.mass_form(c)
