@@ -326,8 +326,9 @@ def bench_batched(igatrim, wl, args, sync):
             "registers": "256 (two workgroups per CU)" if info["capped"] else "up to 512 (one workgroup per CU)",
             "order": ["cost-sorted", "patch by patch"][info["order"]],
             "autotune_best_ms": tune_ms, "plan_setup_s": round(t_plan, 2),
-            "note": "formation over resident tables, one persistent launch per call (graph replay) vs one "
-                    "formation call per patch"}
+            "note": "formation over resident tables, one graph replay per call (persistent launch of the cut "
+                    "element matrices beside per-degree coefficient and interior launches, then the element-formed "
+                    "rows) vs one formation call per patch"}
 
 
 def bench_adjoint(igatrim, wl, args, sync):
