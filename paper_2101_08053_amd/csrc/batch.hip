@@ -76,17 +76,17 @@ struct BatchDev {
 
 __device__ __forceinline__ int item_level(int kind) { return kind == BK_COEF ? 0 : 1; }
 
-template <int P>
-struct BatchSmemSize {
-    static constexpr size_t v = sizeof(CutESmem<P>);
-};
-template <int P>
-constexpr size_t batch_smem_max() {
-    return (BatchSmemSize<P>::v > batch_smem_max<P - 1>()) ? BatchSmemSize<P>::v : batch_smem_max<P - 1>();
-}
-template <>
-constexpr size_t batch_smem_max<0>() {
-    return 0;
+// LDS of the persistent kernel's body for degree p (sized at launch for the
+// largest degree in the batch, so batches of low degrees fit more workgroups).
+static size_t batch_smem_bytes(int p) {
+    switch (p) {
+        case 1: return sizeof(CutESmem<1>);
+        case 2: return sizeof(CutESmem<2>);
+        case 3: return sizeof(CutESmem<3>);
+        case 4: return sizeof(CutESmem<4>);
+        case 5: return sizeof(CutESmem<5>);
+        default: return sizeof(CutESmem<6>);
+    }
 }
 
 __device__ __forceinline__ bool wait_count(int* ctr, int need, int limit) {
@@ -170,7 +170,7 @@ __device__ __forceinline__ void batch_loop(const BatchDev& B, int g, unsigned ch
 // them at 256 so that two workgroups share a CU (a few values spill).
 template <int MINW>
 __global__ void __launch_bounds__(256, MINW) k_batch(BatchDev B) {
-    __shared__ __align__(16) unsigned char smem[batch_smem_max<kBatchMaxP>()];
+    extern __shared__ __align__(16) unsigned char smem[];  // batch_smem_bytes of the batch's largest degree
     __shared__ int s_sh[3];
     int g = 0;
     while (g < kBatchGroups - 1 && (int)blockIdx.x >= B.first_block[g + 1]) ++g;
@@ -350,8 +350,11 @@ struct Batch {
             B.n_level[g][1] = g_lvl[g][1];
         }
         if (total > 0) {
-            if (capped) hipLaunchKernelGGL(k_batch<2>, dim3(total), dim3(256), 0, s, B);
-            else hipLaunchKernelGGL(k_batch<1>, dim3(total), dim3(256), 0, s, B);
+            size_t lds = 0;
+            for (int g = 0; g < kBatchGroups; ++g)
+                if (g_n[g] > 0) lds = std::max(lds, batch_smem_bytes(g + 1));
+            if (capped) hipLaunchKernelGGL(k_batch<2>, dim3(total), dim3(256), lds, s, B);
+            else hipLaunchKernelGGL(k_batch<1>, dim3(total), dim3(256), lds, s, B);
         }
         HIPX(hipStreamWaitEvent(s, ev_coef, 0));
         for (int g = 0; g < kBatchGroups; ++g) {
