@@ -1,8 +1,9 @@
-"""Batched formation (one persistent launch over many patches, HIP graph, autotuner).
+"""Batched formation (a persistent launch of the cut element matrices, per-degree launches of the
+coefficients, interior tiles and element-formed rows on two streams, HIP graph, autotuner).
 
-The batched kernel runs the same per-item bodies as the one-patch kernels,
-with the same summation order per entry, so its output must equal the
-one-patch formation bit for bit; the one-patch formation itself is checked
+The batched launches run the same bodies as the one-patch kernels, with the
+same summation order per entry, so their output must equal the one-patch
+formation bit for bit; the one-patch formation itself is checked
 against the oracle in test_gpu_form. The patch set follows the batched
 workload's generator (degrees 2..5, element counts log-uniform per
 direction, one ellipse each) at sizes small enough for a test.
@@ -97,3 +98,26 @@ def test_batch_constant_coefficient_and_one_shot():
     for g, r, c in zip(outs, ref, cfgs):
         assert np.array_equal(g, r)
         assert abs(g.sum() - TrimmedSpace(c).visible_area()) < 1e-10
+
+
+def test_batch_degree_ends_and_element_gauss():
+    """Degrees 1 and 6 (the ends of what the batch takes, outside the workload's 2..5) and an
+    element-Gauss plan (every row formed element-wise, no interior tiles) in one batch, eager and
+    replayed: bit for bit the one-patch formations."""
+    torch = require_gpu()
+    from paper_2101_08053_amd import igatrim
+    cfgs = (wl.config4(n_patch=3, n_range=(8, 30), p_range=(1, 1), seed=wl.SEED_BASE + 43)
+            + wl.config4(n_patch=3, n_range=(12, 30), p_range=(6, 6), seed=wl.SEED_BASE + 44))
+    say("[batch ends] degrees", [c.p for c in cfgs], "sizes", [c.n_el for c in cfgs])
+    plans = [igatrim.Plan(c, igatrim.HYBRID_GAUSS) for c in cfgs]
+    plans.append(igatrim.Plan(cfgs[0], igatrim.GAUSS_REF))
+    coeffs = [p.coeff() for p in plans]
+    ref = _plain(plans, coeffs)
+    b = igatrim.Batch(plans, coeffs)
+    for use_graph in (False, True, True):
+        for o in b.outs:
+            o.fill_(np.nan)
+        outs = [o.cpu().numpy() for o in b.form(use_graph=use_graph)]
+        b.status()
+        for k, (g, r) in enumerate(zip(outs, ref)):
+            assert np.array_equal(g, r), f"patch {k} (p = {plans[k].sizes['p']}), graph {use_graph}"
