@@ -14,8 +14,10 @@
   the device's formed matrix at that size (itself checked against the oracle
   at the sizes above), entry by entry relative to the sum of absolute terms
   (1e-12), and <dc, c> = <r, y>, an identity of the adjoint.
-* 256 patches of the batched workload: the persistent launch equals the
+* 256 patches of the batched workload: the batched launches equal the
   one-patch formation bit for bit.
+* 300 x 300, p = 2, circular hole (c = 1): the cut rules find their elements
+  from more class counts than one batch of loads covers; sampled rows as above.
 """
 import numpy as np
 import pytest
@@ -127,6 +129,15 @@ def test_fullsize_high_degree_dwq():
     require_gpu()
     from paper_2101_08053_amd import igatrim
     _check_sampled(igatrim, wl.config3(), igatrim.DWQ, 100, 30, 13)
+
+
+def test_fullsize_cut_rules_locate_past_one_batch():
+    """300 x 300, p = 2, circular hole: 300 element rows of 19 tile columns, so each cut-rule
+    workgroup sums the class kernel's counts in two batches of loads before finding its element
+    (the headline's 256 x 16 counts take one); sampled rows against the oracle."""
+    require_gpu()
+    from paper_2101_08053_amd import igatrim
+    _check_sampled(igatrim, wl.config1(N=300, p=2), igatrim.HYBRID_GAUSS, 100, 150, 14)
 
 
 def test_fullsize_matrix_free():
