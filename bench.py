@@ -154,8 +154,8 @@ INTERIOR_SOURCES = [("paper_2101_08053_amd/csrc/form_body.hpp", "interior rows")
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
-              "the multi-GPU sharding is described in DESIGN.md but not launched.", file=sys.stderr)
+        print(f"bench.py: the formation path runs on one GPU only (asked for --gpus {args.gpus}); "
+              "sharding across GPUs is not implemented.", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch
