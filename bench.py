@@ -325,10 +325,11 @@ def bench_batched(igatrim, wl, args, sync):
             "wg_per_cu": info["wg_per_cu"], "chunk": info["chunk"],
             "registers": "256 (two workgroups per CU)" if info["capped"] else "up to 512 (one workgroup per CU)",
             "order": ["cost-sorted", "patch by patch"][info["order"]],
+            "cut_elements": "persistent queue" if info["grid"] > 0 else "one workgroup each (autotuner's choice)",
             "autotune_best_ms": tune_ms, "plan_setup_s": round(t_plan, 2),
-            "note": "formation over resident tables, one graph replay per call (persistent launch of the cut "
-                    "element matrices beside per-degree coefficient and interior launches, then the element-formed "
-                    "rows) vs one formation call per patch"}
+            "note": "formation over resident tables, one graph replay per call (cut element matrices beside "
+                    "per-degree coefficient and interior launches, then the element-formed rows) vs one formation "
+                    "call per patch"}
 
 
 def bench_adjoint(igatrim, wl, args, sync):

@@ -252,7 +252,8 @@ typedef struct iga_batch_stats {
     int64_t n_plans;
     int64_t n_items;      /* work items: queued ones and those of the other launches */
     int64_t nnz;          /* sum of the plans' structural non-zeros     */
-    int32_t grid;         /* persistent workgroups                      */
+    int32_t grid;         /* persistent workgroups; 0: the autotuner chose one workgroup per
+                             cut element (per-degree launches) over the persistent queue */
     int32_t wg_per_cu;    /* workgroups per compute unit (autotuned)    */
     int32_t order;        /* 0: cost-sorted queue, 1: patch by patch    */
     int32_t graph_ready;  /* a recorded graph is cached                 */
@@ -268,9 +269,10 @@ int iga_batch_form(iga_batch* batch, int32_t use_graph, void* stream);
 /* Autotuner: times the persistent grid (1, 2, 4, 8, 12 or 16 workgroups per
  * compute unit, more than fit at once allowed), the kernel's register budget (two
  * builds), the queue chunk (4, 16, 64 items per atomic) and the two queue
- * orders on the device (3 timed runs each, stream synchronised), keeps the
- * fastest and drops a cached graph; *best_ms (may be NULL) receives its
- * time. */
+ * orders on the device (3 timed runs each, stream synchronised), and against
+ * them the cut element matrices launched one workgroup each per degree
+ * instead of the persistent queue; keeps the fastest and drops a cached
+ * graph; *best_ms (may be NULL) receives its time. */
 int iga_batch_autotune(iga_batch* batch, void* stream, float* best_ms);
 int iga_batch_info(const iga_batch* batch, iga_batch_stats* st);
 /* Synchronises stream; IGA_E_INVALID if a dependency wait hit its bound

@@ -185,6 +185,16 @@ __global__ void __launch_bounds__(256, MINW) k_batch(BatchDev B) {
     }
 }
 
+// Cut element matrices of the batch's patches of degree P, one workgroup per
+// element: the autotuner's alternative to the persistent queue.
+template <int P>
+__global__ void __launch_bounds__(256)
+    k_batch_cut_elems(const BatchPlan* __restrict__ plans, const BatchItem* __restrict__ items) {
+    __shared__ CutESmem<P> S;
+    const BatchItem it = items[blockIdx.x];
+    cut_elem_body<P>(plans[it.plan].ce, it.unit, S);
+}
+
 // Coefficient chunks of the batch's patches of degree P: |det J| at the WQ
 // grid and band Gauss points (the cut element matrices evaluate it at their
 // nodes themselves). One point per thread: kCoefChunk / 256 workgroups per
@@ -238,6 +248,8 @@ struct Batch {
     BatchItem* d_items = nullptr;
     BatchItem* d_rows = nullptr;  // coefficient chunks, interior tiles, element-formed rows, by degree
     int coef_off[kBatchGroups] = {}, coef_n[kBatchGroups] = {};
+    int cute_off[kBatchGroups] = {}, cute_n[kBatchGroups] = {};
+    int persistent = 1;  // 1: cut element matrices from the persistent queue, 0: one workgroup each (autotuned)
     int int_off[kBatchGroups] = {}, int_n[kBatchGroups] = {};
     int rows_off[kBatchGroups] = {}, rows_n[kBatchGroups] = {};
     int* d_counters = nullptr;  // status, heads[kBatchGroups], level counters[kBatchGroups][2]
@@ -349,6 +361,23 @@ struct Batch {
             B.n_level[g][0] = g_lvl[g][0];
             B.n_level[g][1] = g_lvl[g][1];
         }
+        if (!persistent) {
+            total = 0;
+            for (int g = 0; g < kBatchGroups; ++g) {
+                if (cute_n[g] == 0) continue;
+                const BatchItem* it = d_rows + cute_off[g];
+                const dim3 grid((unsigned)cute_n[g]);
+                switch (g + 1) {
+#define CASE(PP)                                                                            \
+    case PP:                                                                                \
+        hipLaunchKernelGGL(k_batch_cut_elems<PP>, grid, dim3(256), 0, s, d_plans, it); \
+        break;
+                    CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6)
+#undef CASE
+                    default: break;
+                }
+            }
+        }
         if (total > 0) {
             size_t lds = 0;
             for (int g = 0; g < kBatchGroups; ++g)
@@ -412,7 +441,7 @@ static iga_batch* batch_create(iga_plan* const* plans, int count, const iga_coef
         double cost;
     };
     std::vector<Cand> all;
-    std::vector<BatchItem> coefs[kBatchGroups], tiles[kBatchGroups], rows[kBatchGroups];
+    std::vector<BatchItem> coefs[kBatchGroups], tiles[kBatchGroups], rows[kBatchGroups], cutes[kBatchGroups];
     for (int k = 0; k < count; ++k) {
         IGA_REQUIRE(plans[k], IGA_E_INVALID, "null plan in batch");
         Plan& P = *static_cast<Plan*>(plans[k]);
@@ -445,6 +474,8 @@ static iga_batch* batch_create(iga_plan* const* plans, int count, const iga_coef
         const int counts[BK_NKIND] = {n_coef, n_cute, n_int, n_cutr};
         for (int kind = 0; kind < BK_NKIND; ++kind) {
             bp.need[kind] = counts[kind];
+            if (kind == BK_CUTE)  // also listed per degree, for the one-workgroup-each alternative
+                for (int u = 0; u < counts[kind]; ++u) cutes[P.p - 1].push_back(BatchItem{k, kind, u, 0});
             if (kind != BK_CUTE) {  // launches of their own
                 auto& dst = (kind == BK_COEF) ? coefs[P.p - 1] : (kind == BK_INT) ? tiles[P.p - 1] : rows[P.p - 1];
                 for (int u = 0; u < counts[kind]; ++u) dst.push_back(BatchItem{k, kind, u, 0});
@@ -487,6 +518,11 @@ static iga_batch* batch_create(iga_plan* const* plans, int count, const iga_coef
         rows_all.insert(rows_all.end(), coefs[g].begin(), coefs[g].end());
     }
     for (int g = 0; g < kBatchGroups; ++g) {
+        B->cute_off[g] = (int)rows_all.size();
+        B->cute_n[g] = (int)cutes[g].size();
+        rows_all.insert(rows_all.end(), cutes[g].begin(), cutes[g].end());
+    }
+    for (int g = 0; g < kBatchGroups; ++g) {
         B->int_off[g] = (int)rows_all.size();
         B->int_n[g] = (int)tiles[g].size();
         rows_all.insert(rows_all.end(), tiles[g].begin(), tiles[g].end());
@@ -496,7 +532,9 @@ static iga_batch* batch_create(iga_plan* const* plans, int count, const iga_coef
         B->rows_n[g] = (int)rows[g].size();
         rows_all.insert(rows_all.end(), rows[g].begin(), rows[g].end());
     }
-    B->n_items = (int)(all.size() + rows_all.size());
+    // cut elements sit in the queue and in their per-degree list: count them once
+    B->n_items = (int)(rows_all.size() + all.size());
+    for (int g = 0; g < kBatchGroups; ++g) B->n_items -= B->cute_n[g];
     HIPX(hipMalloc(&B->d_plans, sizeof(BatchPlan) * count));
     HIPX(hipMemcpy(B->d_plans, hp.data(), sizeof(BatchPlan) * count, hipMemcpyHostToDevice));
     HIPX(hipMalloc(&B->d_items, sizeof(BatchItem) * std::max<size_t>(1, all.size())));
@@ -532,6 +570,7 @@ static void batch_autotune(Batch& B, hipStream_t s, float* best_ms) {
     float best = 1e30f;
     int bw = B.wg_per_cu, bo = B.order;
     int bc = B.chunk, bcap = B.capped;
+    B.persistent = 1;
     for (int order = 0; order < 2; ++order) {
         B.order = order;
         B.upload_items(s);
@@ -562,6 +601,21 @@ static void batch_autotune(Batch& B, hipStream_t s, float* best_ms) {
             }
         }
     }
+    // the alternative: every cut element its own workgroup, no queue
+    B.persistent = 0;
+    B.launch(s);  // warm-up
+    float tp = 1e30f;
+    for (int rep = 0; rep < 3; ++rep) {
+        HIPX(hipEventRecord(a, s));
+        B.launch(s);
+        HIPX(hipEventRecord(b, s));
+        HIPX(hipEventSynchronize(b));
+        float ms = 0.f;
+        HIPX(hipEventElapsedTime(&ms, a, b));
+        tp = std::min(tp, ms);
+    }
+    B.persistent = tp < best ? 0 : 1;
+    best = std::min(best, tp);
     hipEventDestroy(a);
     hipEventDestroy(b);
     B.wg_per_cu = bw;
@@ -627,7 +681,7 @@ int iga_batch_info(const iga_batch* b, iga_batch_stats* st) {
     st->n_plans = (int64_t)b->plans.size();
     st->n_items = b->n_items;
     st->nnz = b->nnz;
-    st->grid = b->grid();
+    st->grid = b->persistent ? b->grid() : 0;
     st->wg_per_cu = b->wg_per_cu;
     st->order = b->order;
     st->capped = b->capped;
