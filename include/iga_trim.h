@@ -236,7 +236,8 @@ int iga_mf_adjoint(iga_plan* plan, const double* c_points, const double* u, cons
  * (device, band_k * n_act_k doubles) with coefficient cs[k]. The uneven
  * work, the cut-element matrices of all patches (node counts differ), is one
  * persistent launch (plus a counter reset): a cost-sorted work queue per
- * degree taken by a fixed grid of workgroups. Beside it, on a second stream,
+ * degree taken by a fixed grid of workgroups -- or, when the autotuner
+ * measures it faster, one launch per degree of one workgroup per element. Beside it, on a second stream,
  * the coefficient chunks and then the interior tiles run in one launch per
  * degree; once the persistent launch and the coefficient chunks are done,
  * the element-formed rows run in one launch per degree (one workgroup per

@@ -5,7 +5,8 @@
 // matrices, interior work items (one test-function row i2 x one tile of rows
 // i1) and element-formed rows. The cut element matrices, uneven in their
 // node counts, are queued by decreasing cost, one queue per degree, for the
-// persistent launch. The rest is regular or latency-bound work that needs
+// persistent launch (or, where the autotuner measures it faster, launched one
+// workgroup each per degree). The rest is regular or latency-bound work that needs
 // many workgroups in flight per CU, which the persistent kernel's registers
 // and LDS (set by its largest body) do not allow, so it runs in launches of
 // its own per degree: on a second stream, beside the persistent launch, the
