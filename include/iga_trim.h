@@ -92,14 +92,12 @@ typedef struct iga_patch_desc {
     const iga_curve* curves;     /* host, n_curves entries                    */
 } iga_patch_desc;
 
-/* Optional rule and tile settings (NULL or 0 fields = defaults). */
+/* Optional cut-rule settings (NULL or 0 fields = defaults). */
 typedef struct iga_opts {
     int32_t n_r;        /* inner Gauss points of the cut rule (default p+1)          */
     int32_t n_q;        /* points per boundary arc (default d(2p+1), d = 3 ellipses) */
     int32_t n_s;        /* points along straight edge pieces (default p+1)           */
-    int32_t tile1;      /* interior-row tile along xi_1, <= 64 (0 = automatic)       */
-    int32_t tile2;      /* interior-row tile along xi_2 (0 = automatic)              */
-    int32_t reserved[3];
+    int32_t reserved[5]; /* must be zero                                             */
 } iga_opts;
 
 typedef struct iga_plan iga_plan;   /* opaque, library owned */
@@ -159,7 +157,7 @@ typedef struct iga_solve_info {
  * iga_plan_destroy. Errors: IGA_E_INVALID (knots not open/uniformly simple,
  * curve data), IGA_E_UNSUPPORTED (p, kinds), IGA_E_NOMEM, IGA_E_HIP,
  * IGA_E_SINGULAR_WEIGHTS, IGA_E_TOPOLOGY. */
-int iga_plan_create(const iga_patch_desc* desc, const iga_opts* opts, iga_plan** out);
+int iga_trim_plan_create(const iga_patch_desc* desc, const iga_opts* opts, iga_plan** out);
 
 /* Releases the plan and its device memory (NULL is accepted). */
 void iga_plan_destroy(iga_plan* plan);
@@ -185,7 +183,7 @@ int iga_plan_index_maps(const iga_plan* plan, const int32_t** act_of, const int3
  * flags & IGA_FORM_FULL re-runs every set-up kernel from the plan's inputs
  * before the formation (the whole job); without it the resident tables are
  * reused. Errors found on the device (a singular weight system) are reported
- * by iga_plan_status after the stream has run. With method IGA_DWQ the
+ * by iga_status_get after the stream has run. With method IGA_DWQ the
  * coefficient must be IGA_COEF_CONST or IGA_COEF_GEOM_DETJ (the rule has
  * points nested between the WQ points, where no per-point value is given):
  * IGA_E_UNSUPPORTED otherwise. */
@@ -202,8 +200,9 @@ int iga_trim_mass_form(iga_plan* plan, const iga_coeff* c, double* vals, int32_t
 int iga_plan_set_graph(iga_plan* plan, int32_t enable);
 
 /* Synchronises stream and returns the device status word of the plan
- * (IGA_OK or IGA_E_SINGULAR_WEIGHTS / IGA_E_CAPACITY), then clears it. */
-int iga_plan_status(iga_plan* plan, void* stream);
+ * (IGA_OK, IGA_E_SINGULAR_WEIGHTS, IGA_E_TOPOLOGY or IGA_E_CAPACITY), then
+ * clears it. */
+int iga_status_get(iga_plan* plan, void* stream);
 
 /* L2 projection (Sect. 4.2): b_i by row i's own rule applied to g c, then
  * Jacobi-preconditioned CG on A = (M + M^T)/2 (M from iga_trim_mass_form
@@ -217,14 +216,17 @@ int iga_trim_l2_project(iga_plan* plan, const iga_coeff* c, const double* vals, 
 /* Right-hand side alone: b (device, n_act) = row rules applied to g c. */
 int iga_trim_rhs(iga_plan* plan, const iga_coeff* c, const iga_target* g, double* b, void* stream);
 
-/* Matrix-free product y = M(c) u (device vectors of length n_act) with c
+/* Matrix-free product y = M(c) u of Eq. (7) -- the weighted-quadrature rows
+ * y_i = sum_k w_{k,i} c_k sum_j B_j(x_k) u_j, and the element rules of the cut
+ * rows (Sect. 3.2) -- for device vectors of length n_act, with c
  * given at every rule point (c_points, n_points values), the rows formed by
  * the plan's interior and hybrid rules, basis values recomputed on the fly.
  * The weighted-quadrature part runs sum-factorised with one row of the WQ
  * grid in LDS: IGA_E_UNSUPPORTED past about 2700 elements along xi_1. */
 int iga_mf_apply(iga_plan* plan, const double* c_points, const double* u, double* y, void* stream);
 
-/* Adjoint of iga_mf_apply: for a cotangent gy (n_act), du = M(c)^T gy
+/* Adjoint of iga_mf_apply (the transpose of Eq. (7)'s product and its
+ * derivative in c): for a cotangent gy (n_act), du = M(c)^T gy
  * (n_act) and dc[k] = (sum_j B_j(x_k) u_j) (sum_i w_hat_{k,i} gy_i)
  * (n_points), w_hat_{k,i} being row i's test-side weight at point k. */
 int iga_mf_adjoint(iga_plan* plan, const double* c_points, const double* u, const double* gy,

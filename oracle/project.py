@@ -22,8 +22,13 @@ def _g_at(o, g, x, y, e1=None, e2=None):
     return g(X, Y)
 
 
-def rhs(o, g, method="hybrid"):
-    """b over active rows; ``g`` takes physical coordinates."""
+def rhs(o, g, method="hybrid", absolute=False):
+    """b over active rows; ``g`` takes physical coordinates.
+
+    ``absolute`` sums |w c g B_i| term by term instead: the scale of each
+    entry's rounding error (B-splines are non-negative).
+    """
+    ab = np.abs if absolute else (lambda v: v)
     ts = o.ts
     b = np.zeros(ts.n_act)
     if method == "hybrid":
@@ -37,7 +42,7 @@ def rhs(o, g, method="hybrid"):
             i2, i1 = divmod(int(f), ts.n1)
             q1 = np.nonzero(o.W1[i1])[0]
             q2 = np.nonzero(o.W2[i2])[0]
-            b[ts.act_of[f]] = np.einsum("k,l,kl->", o.W1[i1, q1], o.W2[i2, q2], G[np.ix_(q1, q2)])
+            b[ts.act_of[f]] = np.einsum("k,l,kl->", ab(o.W1[i1, q1]), ab(o.W2[i2, q2]), ab(G[np.ix_(q1, q2)]))
         rows = o.cut_rows_flat()
         elements = o.cut_band_elements()
     else:
@@ -56,7 +61,7 @@ def rhs(o, g, method="hybrid"):
             for a1 in range(o.p + 1):
                 f = (e2 + a2) * ts.n1 + e1 + a1
                 if keep[f]:
-                    b[ts.act_of[f]] += np.sum(w * c * gv * B1[:, a1] * B2[:, a2])
+                    b[ts.act_of[f]] += np.sum(ab(w * c * gv) * B1[:, a1] * B2[:, a2])
     return b
 
 

@@ -392,7 +392,7 @@ using namespace iga;
 
 extern "C" {
 
-int iga_plan_create(const iga_patch_desc* desc, const iga_opts* opts, iga_plan** out) {
+int iga_trim_plan_create(const iga_patch_desc* desc, const iga_opts* opts, iga_plan** out) {
     API_BEGIN
     IGA_REQUIRE(desc && out, IGA_E_INVALID, "null argument");
     *out = nullptr;
@@ -425,6 +425,8 @@ int iga_plan_create(const iga_patch_desc* desc, const iga_opts* opts, iga_plan**
         HIPX(hipEventCreateWithFlags(e, hipEventDisableTiming));
     P->p = p;
     P->method = desc->method;
+    if (opts)
+        for (int k = 0; k < 5; ++k) IGA_REQUIRE(opts->reserved[k] == 0, IGA_E_INVALID, "reserved option fields must be 0");
     P->n_r = (opts && opts->n_r > 0) ? opts->n_r : p + 1;
     P->n_s = (opts && opts->n_s > 0) ? opts->n_s : p + 1;
     P->n_q_override = (opts && opts->n_q > 0) ? opts->n_q : 0;
@@ -483,13 +485,6 @@ int iga_plan_create(const iga_patch_desc* desc, const iga_opts* opts, iga_plan**
     P->N2 = P->dir[1].N;
     P->n1 = P->dir[0].n;
     P->n2 = P->dir[1].n;
-    if (opts && opts->tile2 > 0) P->tile2 = opts->tile2;
-    else {
-        // enough workgroups to fill 256 compute units several times over
-        int tiles1 = (P->n1 + 63) / 64;
-        int t2 = (int)std::max<int64_t>(1, std::min<int64_t>(8, (int64_t)tiles1 * P->n2 / 2048));
-        P->tile2 = t2;
-    }
     P->gauss_x = P->alloc<double>(gauss_off(IGA_MAX_GAUSS + 1));
     P->gauss_w = P->alloc<double>(gauss_off(IGA_MAX_GAUSS + 1));
     P->status = P->alloc<int>(1);
@@ -655,7 +650,7 @@ int iga_plan_set_graph(iga_plan* P, int32_t enable) {
     API_END
 }
 
-int iga_plan_status(iga_plan* P, void* stream) {
+int iga_status_get(iga_plan* P, void* stream) {
     API_BEGIN
     IGA_REQUIRE(P, IGA_E_INVALID, "null plan");
     check_status(*P, (hipStream_t)stream);

@@ -140,7 +140,6 @@ IntArgs int_args(Plan& P, const iga_coeff& c, double* vals) {
     A.all_active = (P.method == IGA_NAIVE_WQ);
     A.vals = vals;
     A.n_act = P.n_act;
-    A.tile2 = P.tile2;
     A.ntx = interior2_ntx(P.N1, P.p);
     return A;
 }

@@ -69,7 +69,6 @@ struct IntArgs {
     int all_active;          // 1: every active row (naive WQ), 0: interior rows only
     double* vals;
     int64_t n_act;
-    int tile2;
     int ntx;                 // tiles along xi_1 (interior2_ntx)
 };
 

@@ -147,7 +147,6 @@ struct Plan {
     int p = 0;
     int method = IGA_HYBRID_GAUSS;
     int n_r = 0, n_q_override = 0, n_s = 0;
-    int tile1 = 64, tile2 = 8;
     int N1 = 0, N2 = 0, n1 = 0, n2 = 0;
 
     // raw inputs (device)

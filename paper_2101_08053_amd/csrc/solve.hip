@@ -402,7 +402,9 @@ __global__ void __launch_bounds__(kRedThreads) k_cg_update_c(SpArgs S, double* _
     __shared__ double sh[kRedThreads / 64];
     __shared__ double s_alpha;
     const double pq = sum_partials(part_pq, nblk, 1, 0, sh);
-    if (threadIdx.x == 0) s_alpha = scal[6 + par] / pq;
+    // the host reads convergence every few iterations, so iterations may run on after
+    // the residual has vanished: then p.q = 0 and the step is zero, not 0/0
+    if (threadIdx.x == 0) s_alpha = (pq != 0.0) ? scal[6 + par] / pq : 0.0;
     __syncthreads();
     int r = blockIdx.x * blockDim.x + threadIdx.x;
     double rz = 0, rr = 0;
@@ -433,7 +435,7 @@ __global__ void __launch_bounds__(kRedThreads) k_cg_dir_c(int n, double* __restr
     const double rz = sum_partials(part, nblk, 2, 0, sh);
     const double rr = sum_partials(part, nblk, 2, 1, sh);
     if (threadIdx.x == 0) {
-        s_beta = rz / scal[6 + par];
+        s_beta = (scal[6 + par] != 0.0) ? rz / scal[6 + par] : 0.0;  // a vanished residual keeps p = z
         if (blockIdx.x == 0) {
             scal[6 + (1 - par)] = rz;
             scal[2] = rr;

@@ -45,8 +45,7 @@ class iga_patch_desc(C.Structure):
 
 
 class iga_opts(C.Structure):
-    _fields_ = [("n_r", C.c_int32), ("n_q", C.c_int32), ("n_s", C.c_int32), ("tile1", C.c_int32),
-                ("tile2", C.c_int32), ("reserved", C.c_int32 * 3)]
+    _fields_ = [("n_r", C.c_int32), ("n_q", C.c_int32), ("n_s", C.c_int32), ("reserved", C.c_int32 * 5)]
 
 
 _SIZE_FIELDS = ["p", "N1", "N2", "n1", "n2", "n_act", "n_interior", "n_cut_fn", "n_cut_el", "n_band_el", "band",
@@ -90,13 +89,13 @@ def lib():
         L = C.CDLL(LIB_PATH)
         P, V = C.c_void_p, C.c_void_p
         sig = {
-            "iga_plan_create": (C.c_int, [C.POINTER(iga_patch_desc), C.POINTER(iga_opts), C.POINTER(P)]),
+            "iga_trim_plan_create": (C.c_int, [C.POINTER(iga_patch_desc), C.POINTER(iga_opts), C.POINTER(P)]),
             "iga_plan_destroy": (None, [P]),
             "iga_plan_sizes": (C.c_int, [P, C.POINTER(iga_sizes)]),
             "iga_plan_points": (C.c_int, [P, C.POINTER(C.c_void_p), C.POINTER(C.c_int64)]),
             "iga_plan_index_maps": (C.c_int, [P, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), C.POINTER(C.c_void_p)]),
             "iga_trim_mass_form": (C.c_int, [P, C.POINTER(iga_coeff), V, C.c_int32, V]),
-            "iga_plan_status": (C.c_int, [P, V]),
+            "iga_status_get": (C.c_int, [P, V]),
             "iga_trim_l2_project": (C.c_int, [P, C.POINTER(iga_coeff), V, C.POINTER(iga_target), C.c_double,
                                               C.c_int32, V, C.POINTER(iga_solve_info), V]),
             "iga_trim_rhs": (C.c_int, [P, C.POINTER(iga_coeff), C.POINTER(iga_target), V, V]),
@@ -133,8 +132,8 @@ def lib():
     return _lib
 
 
-EXPORTED = ("iga_plan_create", "iga_plan_destroy", "iga_plan_sizes", "iga_plan_points", "iga_plan_index_maps",
-            "iga_trim_mass_form", "iga_plan_status", "iga_trim_l2_project", "iga_trim_rhs", "iga_mf_apply",
+EXPORTED = ("iga_trim_plan_create", "iga_plan_destroy", "iga_plan_sizes", "iga_plan_points", "iga_plan_index_maps",
+            "iga_trim_mass_form", "iga_status_get", "iga_trim_l2_project", "iga_trim_rhs", "iga_mf_apply",
             "iga_mf_adjoint", "iga_trim_mass_form_batched", "iga_batch_create", "iga_batch_destroy",
             "iga_batch_form", "iga_batch_autotune", "iga_batch_info", "iga_batch_status",
             "iga_plan_set_timing", "iga_plan_timings", "iga_plan_set_graph",
@@ -169,9 +168,9 @@ def _dptr(t):
 
 
 class Plan:
-    """A trimmed patch prepared on the device (iga_plan_create)."""
+    """A trimmed patch prepared on the device (iga_trim_plan_create)."""
 
-    def __init__(self, patch, method=HYBRID_GAUSS, n_r=0, n_q=0, n_s=0, tile2=0):
+    def __init__(self, patch, method=HYBRID_GAUSS, n_r=0, n_q=0, n_s=0):
         L = lib()
         self._keep = []
         desc = iga_patch_desc()
@@ -194,10 +193,10 @@ class Plan:
             curves[i].cx, curves[i].cy, curves[i].a, curves[i].b, curves[i].phi = cv.cx, cv.cy, cv.a, cv.b, cv.phi
         desc.n_curves = len(patch.curves)
         desc.curves = C.cast(curves, C.POINTER(iga_curve))
-        opts = iga_opts(n_r, n_q, n_s, 0, tile2)
+        opts = iga_opts(n_r, n_q, n_s)
         h = C.c_void_p()
         _torch()
-        _check(L.iga_plan_create(C.byref(desc), C.byref(opts), C.byref(h)))
+        _check(L.iga_trim_plan_create(C.byref(desc), C.byref(opts), C.byref(h)))
         self.h = h
         self.patch = patch
         self.method = method
@@ -302,7 +301,7 @@ class Plan:
         return out
 
     def status(self, stream=None):
-        _check(lib().iga_plan_status(self.h, _stream(stream)))
+        _check(lib().iga_status_get(self.h, _stream(stream)))
 
     def set_timing(self, on=True):
         _check(lib().iga_plan_set_timing(self.h, 1 if on else 0))

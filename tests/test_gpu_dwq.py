@@ -29,6 +29,8 @@ CASES = {
     "cubic16_p4_N48": lambda: wl.config2(N=48),
     "ellipses3_p6_N30": lambda: wl.config3(N=30),
     "ellipses3_p5_N30": lambda: wl.config3(N=30, p=5),
+    "line_p7_N10": lambda: wl.table1_line(7),
+    "line_p8_N10": lambda: wl.table1_line(8),
 }
 _oracles = {}
 
@@ -131,7 +133,7 @@ def test_dwq_parity(name):
     assert np.array_equal(v3, plan.mass_form(full=True).cpu().numpy())
 
 
-@pytest.mark.parametrize("p", [1, 2, 3, 4, 5, 6])
+@pytest.mark.parametrize("p", [1, 2, 3, 4, 5, 6, 7, 8])
 def test_table1_dwq(p):
     """c = 1 on the line trim: DWQ at round-off from element Gauss (Table 1, middle column)."""
     require_gpu()

@@ -1,7 +1,9 @@
 """GPU L2 projection (Sect. 4.2): right-hand side and PCG against the oracle.
 
 Right-hand side under identical rules (oracle weights and cut nodes
-injected): max |db| <= 1e-13 max |b|; with the device's own rules 1e-10.
+injected): every entry within 1e-13 of the sum of the absolute values of its
+terms |w c g B_i| (the scale of its own rounding); with the device's own
+rules 1e-10 of that scale.
 Solution: the oracle's residual of the device solution, ||b - A u|| / ||b||
 with the oracle's A and b, stays within 1e-10 (PCG stops at 1e-12 on the
 device's A and b).
@@ -18,6 +20,14 @@ from oracle.geometry import Coefficient
 from paper_2101_08053_amd import workloads as wl
 
 pytestmark = pytest.mark.gpu
+
+
+def _rhs_close(b, bo, S, tol):
+    """Per entry: |b_i - bo_i| <= tol * S_i, S_i the sum of the absolute values of b_i's terms."""
+    assert np.all(S > 0)
+    rel = np.abs(b - bo) / S
+    say(f"   rhs per entry: max |db| / S = {rel.max():.2e} (row {int(rel.argmax())})")
+    assert rel.max() <= tol
 
 
 def _sincos():
@@ -46,7 +56,7 @@ def test_projection_config1(N):
     say(f"[l2] circle N={N}: {info}")
     assert info["converged"] and info["rel_residual"] <= 1e-12
     bo = project.rhs(o, wl.config1_target)
-    assert np.abs(b - bo).max() <= 1e-13 * np.abs(bo).max()
+    _rhs_close(b, bo, project.rhs(o, wl.config1_target, absolute=True), 1e-13)
     M = o.hybrid()
     A = 0.5 * (M + M.T)
     res = np.linalg.norm(bo - A @ u) / np.linalg.norm(bo)
@@ -94,9 +104,10 @@ def test_projection_geometry_detj():
     say(f"[l2 detJ] {info}")
     assert info["converged"]
     bo = project.rhs(o, wl.config1_target)
-    assert np.abs(b - bo).max() <= 1e-10 * np.abs(bo).max()
+    Sb = project.rhs(o, wl.config1_target, absolute=True)
+    _rhs_close(b, bo, Sb, 1e-10)
     plan2, u2, b2, info2 = _project(cfg, oracle=o)
-    assert np.abs(b2 - bo).max() <= 1e-13 * np.abs(bo).max()
+    _rhs_close(b2, bo, Sb, 1e-13)
     M = o.hybrid()
     res = np.linalg.norm(bo - 0.5 * (M + M.T) @ u) / np.linalg.norm(bo)
     assert res <= 1e-9
@@ -110,4 +121,4 @@ def test_projection_reference_rules():
     plan, u, b, info = _project(cfg, method=igatrim.GAUSS_REF, oracle=o)
     assert info["converged"]
     bo = project.rhs(o, wl.config1_target, "reference")
-    assert np.abs(b - bo).max() <= 1e-13 * np.abs(bo).max()
+    _rhs_close(b, bo, project.rhs(o, wl.config1_target, "reference", absolute=True), 1e-13)

@@ -110,3 +110,87 @@ def test_matfree_gradient_finite_differences():
         e[k] = h
         fd = (matfree.gradient(What, Bmat, c, u + e, f)[0] - matfree.gradient(What, Bmat, c, u - e, f)[0]) / (2 * h)
         assert abs(fd - du[k]) <= 1e-7 * max(abs(fd), 1e-3)
+
+
+def _disk_moment(poly, xs, ys, cx, cy, r):
+    """Exact integral of a polynomial in (xs, ys) over the disk |(x, y) - (cx, cy)| <= r (polar coordinates)."""
+    import sympy as sym
+    rho, th = sym.symbols("rho theta", nonnegative=True)
+    f = sym.expand(poly.subs({xs: cx + rho * sym.cos(th), ys: cy + rho * sym.sin(th)}) * rho)
+    return sym.integrate(sym.integrate(f, (th, 0, 2 * sym.pi)), (rho, 0, r))
+
+
+def _visible_integral(poly, xs, ys, cx, cy, r):
+    """Exact integral over [0,1]^2 minus the disk (the disk lies inside the square)."""
+    import sympy as sym
+    sq = sym.integrate(sym.integrate(sym.expand(poly), (xs, 0, 1)), (ys, 0, 1))
+    return sq - _disk_moment(poly, xs, ys, cx, cy, r)
+
+
+def test_l2_error_closed_form_identity_map():
+    """l2_error's value against an exact integral (Sect. 4.2's relative L2 error).
+
+    Identity map, c = 1, circular hole r = 1/4: the spline with coefficients at
+    the Greville abscissae in xi_1 is u_h = x on the visible domain (exterior
+    functions vanish there), so with g = 1 + x y + y^2 the error is
+    sqrt(int (x - g)^2 / int g^2) over the square minus the disk, computed
+    exactly by SymPy. A dropped hole, a wrong rule or a missing square root
+    changes the value far beyond the tolerance.
+    """
+    import sympy as sym
+    cfg = wl.config1(N=12, p=2)
+    o = _const(cfg)
+    g1 = wl.greville(o.k1, o.p)
+    flat = np.asarray(o.ts.active)
+    u = g1[flat % o.ts.n1]
+
+    def g(x, y):
+        return 1.0 + x * y + y ** 2
+
+    xs, ys = sym.symbols("x y")
+    r, c0 = sym.Rational(1, 4), sym.Rational(1, 2)
+    G = 1 + xs * ys + ys ** 2
+    num = _visible_integral((xs - G) ** 2, xs, ys, c0, c0, r)
+    den = _visible_integral(G ** 2, xs, ys, c0, c0, r)
+    exact = float(sym.sqrt(num / den).evalf(30))
+    got = project.l2_error(o, u, g)
+    assert abs(got - exact) <= 1e-12 * exact, (got, exact)
+
+
+def test_l2_error_closed_form_mapped():
+    """l2_error with a non-affine geometry map: c = |det J| varies and g is taken at physical points.
+
+    F(xi) = (xi1 + xi1 xi2 / 5, xi2 + xi1 / 10) is represented exactly by the
+    patch's space (tensor products of the Greville abscissae are the
+    B-spline coefficients of xi1 xi2), det J = 1 + xi2/5 - xi1/50 > 0. With
+    u_h = 1 (all coefficients one) and g(X, Y) = X Y:
+    error^2 = int c (1 - X Y)^2 / int c (X Y)^2 over the parameter domain
+    minus the disk, exact by SymPy. A norm without c, or g at parameter
+    instead of physical points, fails.
+    """
+    import sympy as sym
+    p, N = 3, 10
+    base = wl.config1(N=N, p=p)
+    k1, k2 = base.knots
+    g1, g2 = wl.greville(k1, p), wl.greville(k2, p)
+    cp = np.empty((len(g2), len(g1), 2))
+    cp[..., 0] = g1[None, :] + 0.2 * g1[None, :] * g2[:, None]
+    cp[..., 1] = g2[:, None] + 0.1 * g1[None, :]
+    cfg = wl.Patch(p=p, n_el=(N, N), knots=(k1, k2), curves=base.curves, geom_cp=cp, coef=wl.COEF_GEOM_DETJ,
+                   name="mapped")
+    o = Oracle(cfg)
+    u = np.ones(o.ts.n_act)
+
+    def g(X, Y):
+        return X * Y
+
+    xs, ys = sym.symbols("x y")
+    X = xs + xs * ys / 5
+    Y = ys + xs / 10
+    detj = sym.diff(X, xs) * sym.diff(Y, ys) - sym.diff(X, ys) * sym.diff(Y, xs)
+    r, c0 = sym.Rational(1, 4), sym.Rational(1, 2)
+    num = _visible_integral(detj * (1 - X * Y) ** 2, xs, ys, c0, c0, r)
+    den = _visible_integral(detj * (X * Y) ** 2, xs, ys, c0, c0, r)
+    exact = float(sym.sqrt(num / den).evalf(30))
+    got = project.l2_error(o, u, g)
+    assert abs(got - exact) <= 1e-12 * exact, (got, exact)
