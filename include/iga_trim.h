@@ -281,6 +281,23 @@ int iga_batch_info(const iga_batch* batch, iga_batch_stats* st);
 /* Synchronises stream; IGA_E_INVALID if a dependency wait hit its bound
  * (the bound is sticky for the batch), else the first plan's device status. */
 int iga_batch_status(iga_batch* batch, void* stream);
+/* Batched L2 projection (Sect. 4.2) of the batch's patches, after
+ * iga_batch_form: for every patch k, the right-hand side by its rows' own
+ * rules applied to gs[k] c_k (c_k the batch's coefficient of the patch), then
+ * Jacobi-preconditioned CG on (M_k + M_k^T)/2 with M_k the batch's output
+ * vals[k] -- every patch in the same launches, each with its own step sizes
+ * and its own convergence test ||b_k - A_k u_k|| <= rtol ||b_k||, taken every
+ * 16 iterations and at maxit as in iga_trim_l2_project, so each patch's
+ * iterates and iteration count are those of the one-patch call. u[k]
+ * (device, n_act_k doubles, caller owned) is the start vector and receives
+ * the solution; infos (host, count entries, may be NULL) receives each
+ * patch's iterations, convergence flag and relative residual. Degrees up to
+ * 6, hybrid Gauss or element Gauss plans. The first call takes device memory
+ * for the batch's symmetrised bands and vectors (kept until the batch is
+ * destroyed). Synchronous. IGA_E_NOCONV if some patch did not converge
+ * within maxit (its u is the last iterate). */
+int iga_batch_project(iga_batch* batch, const iga_target* gs, double rtol, int32_t maxit, double* const* u,
+                      iga_solve_info* infos, void* stream);
 /* One-shot form: create a batch, form (graph if use_graph), synchronise, destroy. */
 int iga_trim_mass_form_batched(iga_plan* const* plans, int32_t count, const iga_coeff* cs,
                                double* const* vals, int32_t use_graph, void* stream);

@@ -238,6 +238,9 @@ __global__ void __launch_bounds__(batch_cut_row_threads(P))
 }
 
 // ------------------------------------------------------------------ host
+struct BatchSolve;                      // batched projection state (batch_solve.hip)
+void batch_solve_free(BatchSolve* bs);
+
 struct Batch {
     std::vector<Plan*> plans;
     std::vector<iga_coeff> coeffs;
@@ -267,8 +270,10 @@ struct Batch {
     hipStream_t side = nullptr;  // coefficient chunks and interior tiles, beside the persistent launch
     hipEvent_t ev_fork = nullptr, ev_coef = nullptr, ev_join = nullptr;
     int64_t nnz = 0;
+    BatchSolve* solve = nullptr;  // created by the first batched projection
 
     ~Batch() {
+        if (solve) batch_solve_free(solve);
         if (exec) hipGraphExecDestroy(exec);
         if (graph) hipGraphDestroy(graph);
         if (cap_stream) hipStreamDestroy(cap_stream);
@@ -420,6 +425,10 @@ static double item_cost(const Plan& P, int kind, int unit, const std::vector<int
 struct iga_batch : public iga::Batch {};
 
 namespace iga {
+
+BatchView batch_view(iga_batch* b) {
+    return BatchView{(int)b->plans.size(), b->plans.data(), b->coeffs.data(), b->outs.data(), &b->solve};
+}
 
 static iga_batch* batch_create(iga_plan* const* plans, int count, const iga_coeff* cs, double* const* outs) {
     IGA_REQUIRE(count > 0 && plans && cs && outs, IGA_E_INVALID, "empty batch");

@@ -324,7 +324,21 @@ void launch_dwq_sides(Plan& P, hipStream_t s);
 void launch_dwq_choose(Plan& P, hipStream_t s);
 void launch_dwq_rows(Plan& P, const iga_coeff& c, double* vals, hipStream_t s);
 
+// batch.hip: the plans, coefficients and outputs a batch borrows
+struct BatchSolve;
+struct BatchView {
+    int n;
+    Plan* const* plans;
+    const iga_coeff* coeffs;
+    double* const* outs;
+    BatchSolve** solve;
+};
+
 }  // namespace iga
 
 // The opaque handle of the C ABI is the plan itself.
 struct iga_plan : public iga::Plan {};
+
+namespace iga {
+BatchView batch_view(iga_batch* b);
+}

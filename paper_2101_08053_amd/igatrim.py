@@ -110,6 +110,8 @@ def lib():
             "iga_batch_autotune": (C.c_int, [P, V, C.POINTER(C.c_float)]),
             "iga_batch_info": (C.c_int, [P, C.POINTER(iga_batch_stats)]),
             "iga_batch_status": (C.c_int, [P, V]),
+            "iga_batch_project": (C.c_int, [P, C.POINTER(iga_target), C.c_double, C.c_int32, C.POINTER(C.c_void_p),
+                                            C.POINTER(iga_solve_info), V]),
             "iga_plan_set_timing": (C.c_int, [P, C.c_int32]),
             "iga_plan_set_graph": (C.c_int, [P, C.c_int32]),
             "iga_plan_timings": (C.c_int, [P, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
@@ -135,7 +137,7 @@ def lib():
 EXPORTED = ("iga_trim_plan_create", "iga_plan_destroy", "iga_plan_sizes", "iga_plan_points", "iga_plan_index_maps",
             "iga_trim_mass_form", "iga_status_get", "iga_trim_l2_project", "iga_trim_rhs", "iga_mf_apply",
             "iga_mf_adjoint", "iga_trim_mass_form_batched", "iga_batch_create", "iga_batch_destroy",
-            "iga_batch_form", "iga_batch_autotune", "iga_batch_info", "iga_batch_status",
+            "iga_batch_form", "iga_batch_autotune", "iga_batch_info", "iga_batch_status", "iga_batch_project",
             "iga_plan_set_timing", "iga_plan_timings", "iga_plan_set_graph",
             "iga_copy", "iga_plan_table", "iga_plan_int_table", "iga_plan_set_weights",
             "iga_plan_set_dwq_weights", "iga_plan_set_cut_nodes", "iga_status_string", "iga_last_error")
@@ -459,6 +461,23 @@ class Batch:
 
     def status(self, stream=None):
         _check(lib().iga_batch_status(self.h, _stream(stream)))
+
+    def project(self, targets, rtol=1e-12, maxit=None, u0=None, stream=None, raise_on_noconv=True):
+        """Batched L2 projection of every patch (after form); returns (list of u, list of info dicts)."""
+        torch = _torch()
+        n = len(self.plans)
+        us = [torch.zeros(p.sizes["n_act"], dtype=torch.float64, device="cuda") if u0 is None else u0[k].clone()
+              for k, p in enumerate(self.plans)]
+        gs = (iga_target * n)(*targets)
+        up = (C.c_void_p * n)(*[_dptr(u) for u in us])
+        infos = (iga_solve_info * n)()
+        maxit = maxit or 10 * max(p.sizes["n_act"] for p in self.plans)
+        code = lib().iga_batch_project(self.h, gs, rtol, maxit, up, infos, _stream(stream))
+        out = [{"iterations": i.iterations, "converged": bool(i.converged), "rel_residual": i.rel_residual}
+               for i in infos]
+        if code != 0 and not (code == -8 and not raise_on_noconv):
+            _check(code)
+        return us, out
 
     def close(self):
         if getattr(self, "h", None):
