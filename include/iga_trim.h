@@ -225,6 +225,21 @@ int iga_trim_rhs(iga_plan* plan, const iga_coeff* c, const iga_target* g, double
  * grid in LDS: IGA_E_UNSUPPORTED past about 2700 elements along xi_1. */
 int iga_mf_apply(iga_plan* plan, const double* c_points, const double* u, double* y, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving or solver loops, harnesses that forbid hipMalloc):
+ * iga_mf_apply with the product's intermediate arrays taken from a static
+ * device array the library holds for the life of the process (64 MiB per
+ * device, one copy per device; its address is looked up when the first plan
+ * is created on the device) instead of the plan's workspace. Allocates
+ * nothing. Same arguments, kernels and result as iga_mf_apply.
+ * IGA_E_CAPACITY (nothing enqueued) when the patch needs more than 64 MiB of
+ * intermediate arrays: 8 (n2 q1 + q2 n1 + (n_band_el + n_cut_el)(p+1)^2)
+ * bytes, each part rounded up to 256 bytes (about 1400^2 elements at p = 4).
+ * Every call on a device shares that device's array: calls that overlap on
+ * one device (several streams or threads) race and must be ordered by the
+ * caller. */
+int iga_mf_apply_noalloc(iga_plan* plan, const double* c_points, const double* u, double* y, void* stream);
+
 /* Adjoint of iga_mf_apply (the transpose of Eq. (7)'s product and its
  * derivative in c): for a cotangent gy (n_act), du = M(c)^T gy
  * (n_act) and dc[k] = (sum_j B_j(x_k) u_j) (sum_i w_hat_{k,i} gy_i)

@@ -52,6 +52,9 @@ static T d2h1(const T* src, hipStream_t s) {
     return v;
 }
 
+// matfree.hip: device address of the allocation-free product's scratch array (once per device)
+void mf_scratch_init(int device);
+
 static void check_status(Plan& P, hipStream_t s) {
     int st = d2h1(P.status, s);
     if (st != IGA_OK) {
@@ -420,6 +423,7 @@ int iga_trim_plan_create(const iga_patch_desc* desc, const iga_opts* opts, iga_p
     auto* P = new iga_plan();
     std::unique_ptr<iga_plan> guard(P);
     HIPX(hipGetDevice(&P->device));
+    mf_scratch_init(P->device);  // the allocation-free product's scratch address on this device
     HIPX(hipStreamCreateWithFlags(&P->aux, hipStreamNonBlocking));
     for (hipEvent_t* e : {&P->ev_fork, &P->ev_iso, &P->ev_lists, &P->ev_interior, &P->ev_band, &P->ev_classes})
         HIPX(hipEventCreateWithFlags(e, hipEventDisableTiming));

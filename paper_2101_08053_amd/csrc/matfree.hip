@@ -9,6 +9,9 @@
 //   du_j = sum_k B_j(x_k) c_k R_k,   dc_k = U_k R_k,   R_k = sum_i w_hat_{k,i} r_i.
 // Basis values come from the per-direction tables or are recomputed at cut
 // nodes; U and R are never stored per row.
+#include <mutex>
+#include <string>
+
 #include "plan.hpp"
 
 namespace iga {
@@ -397,11 +400,15 @@ static MfArgs mf_args(Plan& P, const double* c) {
     return A;
 }
 
-static void mf_buffers(Plan& P) {
-    size_t L = (size_t)(P.p + 1) * (P.p + 1);
-    // one grid row of xi_1 points and one row of functions in LDS
+// one grid row of xi_1 points and one row of functions in LDS
+static void mf_check(const Plan& P) {
     IGA_REQUIRE(sizeof(double) * ((size_t)P.dir[0].Q + P.n1) <= 65536, IGA_E_UNSUPPORTED,
                 "matrix-free product: more than 2700 elements along xi_1");
+}
+
+static void mf_buffers(Plan& P) {
+    size_t L = (size_t)(P.p + 1) * (P.p + 1);
+    mf_check(P);
     if (!P.sw.V) P.sw.V = P.alloc<double>((size_t)P.n2 * P.dir[0].Q);
     if (!P.sw.H) P.sw.H = P.alloc<double>((size_t)P.dir[1].Q * P.n1);
     if (!P.sw.Ue) P.sw.Ue = P.alloc<double>(std::max<int64_t>(1, P.n_band + P.n_cut_el) * L);
@@ -424,11 +431,11 @@ static void launch_elem(Plan& P, const MfArgs& A, const double* u, const double*
 }
 
 template <int P>
-static void launch_wq_forward(Plan& Pl, const MfArgs& A, const double* u, double* y, hipStream_t s) {
-    hipLaunchKernelGGL(k_mf_v<P>, grid256((int64_t)Pl.n2 * A.d1.Q), dim3(256), 0, s, A, u, Pl.sw.V);
-    hipLaunchKernelGGL(k_mf_gh<P>, dim3(A.d2.Q), dim3(256), sizeof(double) * A.d1.Q, s, A, (const double*)Pl.sw.V,
-                       Pl.sw.H);
-    hipLaunchKernelGGL(k_mf_y<P>, grid256((int64_t)Pl.n1 * Pl.n2), dim3(256), 0, s, A, (const double*)Pl.sw.H, y);
+static void launch_wq_forward(Plan& Pl, const MfArgs& A, const double* u, double* y, double* V, double* H,
+                              hipStream_t s) {
+    hipLaunchKernelGGL(k_mf_v<P>, grid256((int64_t)Pl.n2 * A.d1.Q), dim3(256), 0, s, A, u, V);
+    hipLaunchKernelGGL(k_mf_gh<P>, dim3(A.d2.Q), dim3(256), sizeof(double) * A.d1.Q, s, A, (const double*)V, H);
+    hipLaunchKernelGGL(k_mf_y<P>, grid256((int64_t)Pl.n1 * Pl.n2), dim3(256), 0, s, A, (const double*)H, y);
 }
 
 template <int P>
@@ -442,21 +449,84 @@ static void launch_wq_adjoint(Plan& Pl, const MfArgs& A, const double* u, const 
                        (const double*)Pl.sw.V, Pl.sw.H, dc);  // D over H
 }
 
-void mf_apply(Plan& P, const double* c, const double* u, double* y, hipStream_t s) {
-    mf_buffers(P);
+// The forward product with its three intermediate arrays given: V [n2][Q1],
+// H [Q2][n1], Ue [n_band + n_cut][(p+1)^2]. Every entry of them is written
+// before it is read, so they need no clearing.
+static void mf_apply_into(Plan& P, const double* c, const double* u, double* y, double* V, double* H, double* Ue,
+                          hipStream_t s) {
     MfArgs A = mf_args(P, c);
     int n = (int)P.n_act;
     if (P.method != IGA_GAUSS_REF) {
         switch (P.p) {
 #define CASE(PP) \
-    case PP: launch_wq_forward<PP>(P, A, u, y, s); break;
+    case PP: launch_wq_forward<PP>(P, A, u, y, V, H, s); break;
             CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
 #undef CASE
         }
     }
-    launch_elem(P, A, u, nullptr, P.sw.Ue, nullptr, s);
-    hipLaunchKernelGGL(k_mf_gather, dim3((n + 255) / 256), dim3(256), 0, s, A, (const double*)P.sw.Ue,
+    launch_elem(P, A, u, nullptr, Ue, nullptr, s);
+    hipLaunchKernelGGL(k_mf_gather, dim3((n + 255) / 256), dim3(256), 0, s, A, (const double*)Ue,
                        (const double*)nullptr, y, 0);
+}
+
+void mf_apply(Plan& P, const double* c, const double* u, double* y, hipStream_t s) {
+    mf_buffers(P);
+    mf_apply_into(P, c, u, y, P.sw.V, P.sw.H, P.sw.Ue, s);
+}
+
+// ------------------------------------------------- allocation-free product
+// The intermediate arrays of iga_mf_apply_noalloc live in one array of
+// device memory that the library holds for the life of the process (one copy
+// per device, at its own address). Every call on a device shares that
+// device's copy: calls that overlap on one device race.
+constexpr size_t kMfScratchDoubles = (size_t)8 << 20;  // 64 MiB
+static __device__ __align__(256) double scratch[kMfScratchDoubles];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static double* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of this device's scratch array (looked up once per device,
+// with the device current; the array's name is no device address in host code).
+void mf_scratch_init(int device) {
+    IGA_REQUIRE(device >= 0 && device < kMaxDevices, IGA_E_UNSUPPORTED, "device index beyond the scratch table");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_ptr[device]) return;
+    int cur = -1;
+    HIPX(hipGetDevice(&cur));
+    IGA_REQUIRE(cur == device, IGA_E_INVALID, "scratch set-up needs its device current");
+    void* ptr = nullptr;
+    HIPX(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    IGA_REQUIRE(ptr != nullptr, IGA_E_HIP, "no device address for the scratch array");
+    g_scratch_ptr[device] = static_cast<double*>(ptr);
+}
+
+static size_t round256(size_t n_doubles) { return (n_doubles + 31) & ~(size_t)31; }  // 32 doubles = 256 B
+
+static void mf_apply_noalloc(Plan& P, const double* c, const double* u, double* y, hipStream_t s) {
+    mf_check(P);
+    const size_t L = (size_t)(P.p + 1) * (P.p + 1);
+    const size_t nV = round256((size_t)P.n2 * P.dir[0].Q), nH = round256((size_t)P.dir[1].Q * P.n1);
+    const size_t nU = round256((size_t)std::max<int64_t>(1, P.n_band + P.n_cut_el) * L);
+    const size_t need = nV + nH + nU;
+    IGA_REQUIRE(need <= kMfScratchDoubles, IGA_E_CAPACITY,
+                "allocation-free matrix-free product: the patch needs " + std::to_string(need * sizeof(double)) +
+                    " bytes of intermediate arrays, more than the " +
+                    std::to_string(kMfScratchDoubles * sizeof(double)) + "-byte scratch array");
+    int dev = -1;
+    HIPX(hipGetDevice(&dev));
+    IGA_REQUIRE(dev == P.device, IGA_E_INVALID, "the plan's device must be current");
+    double* base = nullptr;
+    {
+        std::lock_guard<std::mutex> lock(g_scratch_mu);
+        base = g_scratch_ptr[dev];
+    }
+    if (!base) {  // plan creation looks it up; a first call on a device that skipped it does so here
+        mf_scratch_init(dev);
+        std::lock_guard<std::mutex> lock(g_scratch_mu);
+        base = g_scratch_ptr[dev];
+    }
+    mf_apply_into(P, c, u, y, base, base + nV, base + nV + nH, s);
 }
 
 void mf_adjoint(Plan& P, const double* c, const double* u, const double* r, double* du, double* dc, hipStream_t s) {
@@ -491,6 +561,20 @@ int iga_mf_apply(iga_plan* plan, const double* c_points, const double* u, double
         IGA_REQUIRE(plan->method == IGA_HYBRID_GAUSS || plan->method == IGA_GAUSS_REF, IGA_E_UNSUPPORTED,
                     "matrix-free product is built for hybrid Gauss and the reference rules");
         mf_apply(*plan, c_points, u, y, (hipStream_t)stream);
+        HIPX(hipGetLastError());
+    } catch (const Error& e) {
+        set_error(e.msg);
+        return e.code;
+    }
+    return IGA_OK;
+}
+
+int iga_mf_apply_noalloc(iga_plan* plan, const double* c_points, const double* u, double* y, void* stream) {
+    try {
+        IGA_REQUIRE(plan && c_points && u && y, IGA_E_INVALID, "null argument");
+        IGA_REQUIRE(plan->method == IGA_HYBRID_GAUSS || plan->method == IGA_GAUSS_REF, IGA_E_UNSUPPORTED,
+                    "matrix-free product is built for hybrid Gauss and the reference rules");
+        mf_apply_noalloc(*plan, c_points, u, y, (hipStream_t)stream);
         HIPX(hipGetLastError());
     } catch (const Error& e) {
         set_error(e.msg);

@@ -100,6 +100,7 @@ def lib():
                                               C.c_int32, V, C.POINTER(iga_solve_info), V]),
             "iga_trim_rhs": (C.c_int, [P, C.POINTER(iga_coeff), C.POINTER(iga_target), V, V]),
             "iga_mf_apply": (C.c_int, [P, V, V, V, V]),
+            "iga_mf_apply_noalloc": (C.c_int, [P, V, V, V, V]),
             "iga_mf_adjoint": (C.c_int, [P, V, V, V, V, V, V]),
             "iga_trim_mass_form_batched": (C.c_int, [C.POINTER(P), C.c_int32, C.POINTER(iga_coeff),
                                                      C.POINTER(C.c_void_p), C.c_int32, V]),
@@ -136,6 +137,7 @@ def lib():
 
 EXPORTED = ("iga_trim_plan_create", "iga_plan_destroy", "iga_plan_sizes", "iga_plan_points", "iga_plan_index_maps",
             "iga_trim_mass_form", "iga_status_get", "iga_trim_l2_project", "iga_trim_rhs", "iga_mf_apply",
+            "iga_mf_apply_noalloc",
             "iga_mf_adjoint", "iga_trim_mass_form_batched", "iga_batch_create", "iga_batch_destroy",
             "iga_batch_form", "iga_batch_autotune", "iga_batch_info", "iga_batch_status", "iga_batch_project",
             "iga_plan_set_timing", "iga_plan_timings", "iga_plan_set_graph",
@@ -374,6 +376,12 @@ def mf_apply(plan, c_points, u, stream=None):
     torch = _torch()
     y = torch.empty_like(u)
     _check(lib().iga_mf_apply(plan.h, _dptr(c_points), _dptr(u), _dptr(y), _stream(stream)))
+    return y
+
+
+def mf_apply_noalloc(plan, c_points, u, y, stream=None):
+    """y = M(c) u into the caller's y with the library's static scratch (no device allocation)."""
+    _check(lib().iga_mf_apply_noalloc(plan.h, _dptr(c_points), _dptr(u), _dptr(y), _stream(stream)))
     return y
 
 
