@@ -318,10 +318,11 @@ int iga_trim_mass_form_batched(iga_plan* const* plans, int32_t count, const iga_
                                double* const* vals, int32_t use_graph, void* stream);
 
 /* Per-phase device timing of the plan's calls (hipEvents on the streams the
- * phases run on). enable != 0 starts recording; iga_plan_timings synchronises
- * and returns the accumulated milliseconds and counts per phase. While timing
- * is on, the interior rows kernel runs alone (the two streams join before
- * and after it), so IGA_PHASE_INTERIOR is that kernel's own duration. */
+ * phases run on). enable = 1 starts recording (2: per-kernel timing instead,
+ * below; 0: off); iga_plan_timings synchronises and returns the accumulated
+ * milliseconds and counts per phase. While phase timing is on, the interior
+ * rows kernel runs alone (the two streams join before and after it), so
+ * IGA_PHASE_INTERIOR is that kernel's own duration. */
 #define IGA_PHASE_SETUP     0  /* layout, weights, trimming, cut rules        */
 #define IGA_PHASE_COEF      1  /* coefficient at rule points                  */
 #define IGA_PHASE_INTERIOR  2  /* interior rows kernel, start to end of its run */
@@ -329,6 +330,21 @@ int iga_trim_mass_form_batched(iga_plan* const* plans, int32_t count, const iga_
 #define IGA_PHASE_COUNT     4
 int iga_plan_set_timing(iga_plan* plan, int32_t enable);
 int iga_plan_timings(iga_plan* plan, double* ms, int64_t* counts);
+
+/* Per-kernel timing: after iga_plan_set_timing(plan, 2), every kernel of the
+ * plan's formations (launched kernel by kernel) is dispatched with events
+ * recorded at the start and end of its execution on the stream it runs on.
+ * iga_plan_kernel_times synchronises and returns, per kernel name, the summed
+ * milliseconds and dispatch count since the last call (up to cap entries in
+ * out, in order of first dispatch; *n receives the number of kernels), then
+ * clears them. Durations of kernels that share the GPU with the other
+ * stream's kernels include that contention. */
+typedef struct iga_kernel_time {
+    char name[48];
+    double ms;
+    int64_t count;
+} iga_kernel_time;
+int iga_plan_kernel_times(iga_plan* plan, iga_kernel_time* out, int32_t cap, int32_t* n);
 
 /* Read-only device views of the plan's tables (valid while the plan lives),
  * for inspection and parity checks:
@@ -409,6 +425,22 @@ int iga_plan_set_cut_nodes(iga_plan* plan, const double* x, const double* y, con
  * (hipMemcpyAsync with hipMemcpyDefault, then a stream synchronisation); used
  * by bindings to read the plan's device views. */
 int iga_copy(void* dst, const void* src, int64_t bytes, void* stream);
+
+/* Measured ceilings of the current device, the denominators beside the
+ * datasheet peaks in roofline fractions: a streaming copy of n doubles from
+ * src to dst (both device, n >= 256 x 8 x compute units; bytes read plus
+ * written over the time), a loop of independent FP64 fused multiply-adds
+ * (2 flops each) and a loop of FP64 matrix-core products (16x16x4 per
+ * wavefront step); each the best of reps timed runs after a warm-up (HIP
+ * events on stream, synchronised). dst is overwritten. */
+typedef struct iga_peaks {
+    double copy_gbs;        /* GB/s, read + write */
+    double fma_tflops;      /* FP64 vector FMA, TFLOP/s */
+    double mfma_f64_tflops; /* FP64 matrix core, TFLOP/s */
+    int32_t n_cu;
+    int32_t reserved;
+} iga_peaks;
+int iga_measure_peaks(const double* src, double* dst, int64_t n, int32_t reps, iga_peaks* out, void* stream);
 
 const char* iga_status_string(int code);
 const char* iga_last_error(void);

@@ -638,7 +638,7 @@ int iga_trim_mass_form(iga_plan* P, const iga_coeff* c, double* vals, int32_t fl
     IGA_REQUIRE(!(P->method == IGA_DWQ && c->kind == IGA_COEF_AT_POINTS), IGA_E_UNSUPPORTED,
                 "discontinuous weighted quadrature needs c at nested points: constant or |det J| only");
     hipStream_t s = (hipStream_t)stream;
-    if (P->timing || !P->use_graph || P->method == IGA_NAIVE_WQ) {
+    if (P->timing || P->ktiming || !P->use_graph || P->method == IGA_NAIVE_WQ) {
         form(*P, *c, vals, flags, s);
     } else {
         form_graph(*P, *c, vals, flags, s);
@@ -664,7 +664,42 @@ int iga_status_get(iga_plan* P, void* stream) {
 int iga_plan_set_timing(iga_plan* P, int32_t enable) {
     API_BEGIN
     IGA_REQUIRE(P, IGA_E_INVALID, "null plan");
-    P->timing = enable != 0;
+    IGA_REQUIRE(enable >= 0 && enable <= 2, IGA_E_INVALID, "timing mode must be 0, 1 or 2");
+    P->timing = enable == 1;
+    P->ktiming = enable == 2;
+    API_END
+}
+
+int iga_plan_kernel_times(iga_plan* P, iga_kernel_time* out, int32_t cap, int32_t* n_out) {
+    API_BEGIN
+    IGA_REQUIRE(P && n_out && (cap == 0 || out), IGA_E_INVALID, "null argument");
+    std::vector<std::string> names;
+    std::vector<double> ms;
+    std::vector<int64_t> cnt;
+    for (auto& r : P->k_records) {
+        HIPX(hipEventSynchronize(r.b));
+        float t = 0.f;
+        HIPX(hipEventElapsedTime(&t, r.a, r.b));
+        size_t k = 0;
+        while (k < names.size() && names[k] != r.name) ++k;
+        if (k == names.size()) {
+            names.emplace_back(r.name);
+            ms.push_back(0.0);
+            cnt.push_back(0);
+        }
+        ms[k] += t;
+        cnt[k] += 1;
+        P->k_pool.push_back(r.a);
+        P->k_pool.push_back(r.b);
+    }
+    P->k_records.clear();
+    const int n = (int)names.size();
+    for (int k = 0; k < n && k < cap; ++k) {
+        std::snprintf(out[k].name, sizeof(out[k].name), "%s", names[k].c_str());
+        out[k].ms = ms[k];
+        out[k].count = cnt[k];
+    }
+    *n_out = n;
     API_END
 }
 

@@ -432,7 +432,7 @@ void launch_dwq_sides(Plan& P, hipStream_t s) {
     dim3 g(nb), b(128);
     switch (P.p) {
 #define CASE(PP) \
-    case PP: hipLaunchKernelGGL(k_dwq_sides<PP>, g, b, 0, s, P.dir[0], P.dir[1], P.gauss_x, P.gauss_w, P.status); break;
+    case PP: klaunch(P, "k_dwq_sides<" #PP ">", k_dwq_sides<PP>, g, b, 0, s, P.dir[0], P.dir[1], P.gauss_x, P.gauss_w, P.status); break;
         CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
 #undef CASE
         default: throw Error{IGA_E_UNSUPPORTED, "degree outside 1..8"};
@@ -445,7 +445,8 @@ void launch_dwq_choose(Plan& P, hipStream_t s) {
     switch (P.p) {
 #define CASE(PP)                                                                                                 \
     case PP:                                                                                                     \
-        hipLaunchKernelGGL(k_dwq_choose<PP>, g, b, 0, s, P.N1, P.N2, P.n1, P.form_rows, (int)P.n_form_rows,   \
+        klaunch(P, "k_dwq_choose<" #PP ">", k_dwq_choose<PP>, g, b, 0, s, P.N1, P.N2, P.n1, P.form_rows,      \
+                (int)P.n_form_rows,                                                                              \
                            P.fn_of, P.ecls, P.dwq_region);                                                       \
         break;
         CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
@@ -461,7 +462,7 @@ void launch_dwq_rows(Plan& P, const iga_coeff& c, double* vals, hipStream_t s) {
     dim3 g((unsigned)P.n_form_rows), b(256);
     switch (P.p) {
 #define CASE(PP) \
-    case PP: hipLaunchKernelGGL(k_dwq_rows<PP>, g, b, 0, s, A); break;
+    case PP: klaunch(P, "k_dwq_rows<" #PP ">", k_dwq_rows<PP>, g, b, 0, s, A); break;
         CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
 #undef CASE
         default: throw Error{IGA_E_UNSUPPORTED, "degree outside 1..8"};

@@ -56,7 +56,7 @@ void launch_points(Plan& P, hipStream_t s, bool with_nodes) {
     const int nb = (int)P.n_band * (P.p + 1) * (P.p + 1);
     const int nn = with_nodes ? (int)P.n_nodes : 0;
     const int64_t n = nq + nb + nn;
-    hipLaunchKernelGGL(k_points, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, D1, D2, P.p, P.band_list, nb,
+    klaunch(P, "k_points", k_points, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, D1, D2, P.p, P.band_list, nb,
                        P.node_x, P.node_y, nn, P.pts_xy);
 }
 
@@ -103,7 +103,7 @@ void launch_coef(Plan& P, const iga_coeff& c, hipStream_t s, int part, bool with
     dim3 g((unsigned)((t1 - t0 + 255) / 256)), b(256);
     switch (P.p) {
 #define CASE(PP) \
-    case PP: hipLaunchKernelGGL(k_coef<PP>, g, b, 0, s, A, t0, t1); break;
+    case PP: klaunch(P, "k_coef<" #PP ">", k_coef<PP>, g, b, 0, s, A, t0, t1); break;
         CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
 #undef CASE
         default: throw Error{IGA_E_UNSUPPORTED, "degree outside 1..8"};
@@ -119,13 +119,17 @@ __global__ void __launch_bounds__(Int2Cfg<P>::NT) k_interior(IntArgs A) {
     interior_rows_block<P>(A, blk - i2 * A.ntx, i2, S);
 }
 
+static const char* const kInteriorNames[IGA_MAXP + 1] = {"", "k_interior<1>", "k_interior<2>", "k_interior<3>",
+                                                          "k_interior<4>", "k_interior<5>", "k_interior<6>",
+                                                          "k_interior<7>", "k_interior<8>"};
+
 template <int P>
 static void launch_interior_p(Plan& Pl, IntArgs A, hipStream_t s, hipEvent_t t0, hipEvent_t t1) {
     A.ntx = interior2_ntx(Pl.N1, P);
     const int nb = A.ntx * Pl.n2;
     const dim3 blk(Int2Cfg<P>::NT);
     if (t0) hipExtLaunchKernelGGL(k_interior<P>, dim3(nb), blk, 0, s, t0, t1, 0, A);  // events bracket the dispatch
-    else hipLaunchKernelGGL(k_interior<P>, dim3(nb), blk, 0, s, A);
+    else klaunch(Pl, kInteriorNames[P], k_interior<P>, dim3(nb), blk, 0, s, A);
 }
 
 IntArgs int_args(Plan& P, const iga_coeff& c, double* vals) {
@@ -190,7 +194,7 @@ void launch_cut_elems(Plan& P, const iga_coeff& c, hipStream_t s) {
     dim3 g((unsigned)P.n_cut_el), b(256);
     switch (P.p) {
 #define CASE(PP) \
-    case PP: hipLaunchKernelGGL(k_cut_elem<PP>, g, b, 0, s, A); break;
+    case PP: klaunch(P, "k_cut_elem<" #PP ">", k_cut_elem<PP>, g, b, 0, s, A); break;
         CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
 #undef CASE
         default: throw Error{IGA_E_UNSUPPORTED, "degree outside 1..8"};
@@ -206,9 +210,9 @@ void launch_cut_rows_mode(Plan& P, const iga_coeff& c, double* vals, hipStream_t
     dim3 g((unsigned)P.n_form_rows), b(((W * W + 63) / 64) * 64);
     switch (P.p * 4 + mode) {
 #define CASE(PP)                                                                            \
-    case PP * 4 + ROW_FUSED: hipLaunchKernelGGL((k_cut_rows<PP, ROW_FUSED>), g, b, 0, s, A); break;   \
-    case PP * 4 + ROW_INSIDE: hipLaunchKernelGGL((k_cut_rows<PP, ROW_INSIDE>), g, b, 0, s, A); break; \
-    case PP * 4 + ROW_CUT: hipLaunchKernelGGL((k_cut_rows<PP, ROW_CUT>), g, b, 0, s, A); break;
+    case PP * 4 + ROW_FUSED: klaunch(P, "k_cut_rows<" #PP ",fused>", k_cut_rows<PP, ROW_FUSED>, g, b, 0, s, A); break;    \
+    case PP * 4 + ROW_INSIDE: klaunch(P, "k_cut_rows<" #PP ",inside>", k_cut_rows<PP, ROW_INSIDE>, g, b, 0, s, A); break; \
+    case PP * 4 + ROW_CUT: klaunch(P, "k_cut_rows<" #PP ",cut>", k_cut_rows<PP, ROW_CUT>, g, b, 0, s, A); break;
         CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
 #undef CASE
         default: throw Error{IGA_E_UNSUPPORTED, "degree outside 1..8"};

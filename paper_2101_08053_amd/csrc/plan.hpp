@@ -1,6 +1,8 @@
 // Internal layout of a plan: device tables of one trimmed patch.
 #pragma once
 
+#include <hip/hip_ext.h>
+
 #include "common.hpp"
 
 #include <vector>
@@ -219,6 +221,24 @@ struct Plan {
 
     // timing
     bool timing = false;
+    // per-kernel timing: every dispatch of the formation path bracketed by events at its start and end
+    bool ktiming = false;
+    struct KRec {
+        const char* name;
+        hipEvent_t a, b;
+    };
+    std::vector<KRec> k_records;
+    std::vector<hipEvent_t> k_pool;  // events of read records, reused
+    hipEvent_t kevent() {
+        if (!k_pool.empty()) {
+            hipEvent_t e = k_pool.back();
+            k_pool.pop_back();
+            return e;
+        }
+        hipEvent_t e = nullptr;
+        HIPX(hipEventCreate(&e));
+        return e;
+    }
     // The formation as one HIP graph (captured on a private stream, replayed on the caller's):
     // valid while the output, coefficient and flags match the captured call.
     bool use_graph = true;
@@ -250,6 +270,20 @@ struct Plan {
     }
     ~Plan();
 };
+
+// Launch of a formation-path kernel; with per-kernel timing on, the
+// dispatch is bracketed by events recorded at its start and end.
+template <typename... Params, typename... Args>
+inline void klaunch(Plan& P, const char* name, void (*kernel)(Params...), dim3 grid, dim3 block, uint32_t smem,
+                    hipStream_t s, Args... args) {
+    if (P.ktiming) {
+        hipEvent_t a = P.kevent(), b = P.kevent();
+        hipExtLaunchKernelGGL(kernel, grid, block, smem, s, a, b, 0, static_cast<Params>(args)...);
+        P.k_records.push_back({name, a, b});
+    } else {
+        hipLaunchKernelGGL(kernel, grid, block, smem, s, args...);
+    }
+}
 
 // Coefficient values seen by the formation kernels.
 struct CoefView {

@@ -38,7 +38,7 @@ __global__ void k_gauss_table(double* __restrict__ gx, double* __restrict__ gw) 
 
 void launch_gauss_table(Plan& P, hipStream_t s) {
     int tot = gauss_off(IGA_MAX_GAUSS + 1);
-    hipLaunchKernelGGL(k_gauss_table, dim3((tot + 255) / 256), dim3(256), 0, s, P.gauss_x, P.gauss_w);
+    klaunch(P, "k_gauss_table", k_gauss_table, dim3((tot + 255) / 256), dim3(256), 0, s, P.gauss_x, P.gauss_w);
 }
 
 // ------------------------------------------------------- direction tables
@@ -111,7 +111,7 @@ void launch_dir_tables(Plan& P, hipStream_t s) {
     dim3 g((n + 255) / 256), b(256);
     switch (P.p) {
 #define CASE(PP) \
-    case PP: hipLaunchKernelGGL(k_dir_tables<PP>, g, b, 0, s, P.dir[0], P.dir[1], P.gauss_x, P.gauss_w); break;
+    case PP: klaunch(P, "k_dir_tables<" #PP ">", k_dir_tables<PP>, g, b, 0, s, P.dir[0], P.dir[1], P.gauss_x, P.gauss_w); break;
         CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
 #undef CASE
         default: throw Error{IGA_E_UNSUPPORTED, "degree outside 1..8"};
@@ -251,7 +251,7 @@ __global__ void k_wb_table(DirDev D, int p) {
 void launch_wb_table(Plan& P, int d, hipStream_t s) {
     DirDev& D = P.dir[d];
     int n = D.n * D.qmax * (2 * P.p + 1);
-    hipLaunchKernelGGL(k_wb_table, dim3((n + 255) / 256), dim3(256), 0, s, D, P.p);
+    klaunch(P, "k_wb_table", k_wb_table, dim3((n + 255) / 256), dim3(256), 0, s, D, P.p);
 }
 
 void launch_wq_weights(Plan& P, hipStream_t s) {
@@ -259,7 +259,8 @@ void launch_wq_weights(Plan& P, hipStream_t s) {
     switch (P.p) {
 #define CASE(PP)                                                                                                 \
     case PP:                                                                                                     \
-        hipLaunchKernelGGL(k_wq_weights<PP>, g, b, 0, s, P.dir[0], P.dir[1], P.gauss_x, P.gauss_w, P.status); \
+        klaunch(P, "k_wq_weights<" #PP ">", k_wq_weights<PP>, g, b, 0, s, P.dir[0], P.dir[1], P.gauss_x, P.gauss_w,  \
+                P.status);                                                                                        \
         break;
         CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
 #undef CASE

@@ -642,11 +642,11 @@ void launch_trim_curves(Plan& P, hipStream_t s) {
     TrimDev& T = P.trim;
     if (T.n_curves == 0) return;
     GridDev G{P.dir[0].knots + P.p, P.dir[1].knots + P.p, P.N1, P.N2};  // breakpoints
-    hipLaunchKernelGGL(k_trim_front, dim3(1), dim3(256), 0, s, T, P.d_cp, P.d_cp_off, P.d_curves, G, P.gauss_x,
+    klaunch(P, "k_trim_front", k_trim_front, dim3(1), dim3(256), 0, s, T, P.d_cp, P.d_cp_off, P.d_curves, G, P.gauss_x,
                        P.gauss_w);
     if (T.n_curves > 1) {
-        hipLaunchKernelGGL(k_piece_isect, dim3(T.cap_pieces0), dim3(64), 0, s, T, P.status);
-        hipLaunchKernelGGL(k_trim_split, dim3(1), dim3(1024), 0, s, T, P.d_curves, P.gauss_x, P.gauss_w);
+        klaunch(P, "k_piece_isect", k_piece_isect, dim3(T.cap_pieces0), dim3(64), 0, s, T, P.status);
+        klaunch(P, "k_trim_split", k_trim_split, dim3(1), dim3(1024), 0, s, T, P.d_curves, P.gauss_x, P.gauss_w);
     }
 }
 
@@ -825,7 +825,7 @@ void launch_trim_arcs(Plan& P, hipStream_t s) {
     TrimDev& T = P.trim;
     if (T.n_curves == 0) return;
     GridDev G{P.dir[0].knots + P.p, P.dir[1].knots + P.p, P.N1, P.N2};  // breakpoints
-    hipLaunchKernelGGL(k_piece_arcs, dim3(std::max(T.cap_pieces, 1)), dim3(256), 0, s, T, G, P.emark, P.ehead,
+    klaunch(P, "k_piece_arcs", k_piece_arcs, dim3(std::max(T.cap_pieces, 1)), dim3(256), 0, s, T, G, P.emark, P.ehead,
                        P.arc_next, P.status);
 }
 
@@ -1026,7 +1026,7 @@ void launch_trim_classes(Plan& P, hipStream_t s) {
     ClassArgs A{P.p,     P.N1,    P.N2,  P.n1,     P.n2,  P.method, T,     G,
                 P.emark, P.list_rcnt, P.ecls, P.fcls, f_active, f_cut, e_cut, e_band};
     dim3 g((P.N1 + kClsTile - 1) / kClsTile, (P.N2 + kClsTile - 1) / kClsTile);
-    hipLaunchKernelGGL(k_classes, g, dim3(256), 0, s, A);
+    klaunch(P, "k_classes", k_classes, g, dim3(256), 0, s, A);
 }
 
 // --------------------------------------------------------------- lists
@@ -1176,8 +1176,8 @@ void launch_trim_lists(Plan& P, hipStream_t s) {
     A.bsum = P.list_rcnt;
     A.counts = P.counts;
     A.prefix_here = trim_lists_prefix_here(P);
-    if (!A.prefix_here) hipLaunchKernelGGL(k_list_scan, dim3(1), dim3(1024), 0, s, A);
-    hipLaunchKernelGGL(k_list_rows, dim3(P.n2), dim3(256), 0, s, A);
+    if (!A.prefix_here) klaunch(P, "k_list_scan", k_list_scan, dim3(1), dim3(1024), 0, s, A);
+    klaunch(P, "k_list_rows", k_list_rows, dim3(P.n2), dim3(256), 0, s, A);
 }
 
 // ------------------------------------------------------ cut-element rules
@@ -1664,7 +1664,7 @@ void launch_trim_cutprep(Plan& P, hipStream_t s, bool fuse_nodes) {
     A.stage_pieces = (T.cap_pieces <= kPrepPieces) ? T.cap_pieces : 0;
     A.stage_segs = (A.stage_pieces > 0 && T.n_segs <= kPrepSegs) ? T.n_segs : 0;
     const size_t lds = (size_t)A.stage_pieces * sizeof(PieceBox) + (size_t)A.stage_segs * sizeof(SegDev);
-    hipLaunchKernelGGL(k_cutprep, dim3(nc), dim3(64), lds, s, A);
+    klaunch(P, "k_cutprep", k_cutprep, dim3(nc), dim3(64), (uint32_t)lds, s, A);
 }
 
 // One wavefront per cut element writes its nodes (and their entries of the
@@ -1775,7 +1775,7 @@ void launch_trim_nodes(Plan& P, hipStream_t s) {
     const size_t cut0 = (size_t)P.dir[0].Q * P.dir[1].Q + (size_t)P.n_band * (P.p + 1) * (P.p + 1);
     const int prefix_here = nc <= kNodePrefixMax;
     if (!prefix_here) exclusive_scan(P.node_cnt, P.node_off, nc, P.scan_tmp, s);
-    hipLaunchKernelGGL(k_cut_nodes, dim3(nc), dim3(64), 0, s, A, prefix_here, P.node_x, P.node_y, P.node_w,
+    klaunch(P, "k_cut_nodes", k_cut_nodes, dim3(nc), dim3(64), 0, s, A, prefix_here, P.node_x, P.node_y, P.node_w,
                        P.node_el, P.pts_xy + 2 * cut0);
 }
 
@@ -1795,7 +1795,7 @@ __global__ void k_naive_mask(TrimDev T, DirDev D1, DirDev D2, const double* __re
 
 void launch_naive_mask(Plan& P, const double* src, double cval, hipStream_t s) {
     int nq = P.dir[0].Q * P.dir[1].Q;
-    hipLaunchKernelGGL(k_naive_mask, dim3((nq + 255) / 256), dim3(256), 0, s, P.trim, P.dir[0], P.dir[1], src, cval,
+    klaunch(P, "k_naive_mask", k_naive_mask, dim3((nq + 255) / 256), dim3(256), 0, s, P.trim, P.dir[0], P.dir[1], src, cval,
                        P.c_wq_masked);
 }
 

@@ -71,6 +71,15 @@ class iga_batch_stats(C.Structure):
                 ("chunk", C.c_int32), ("capped", C.c_int32)]
 
 
+class iga_kernel_time(C.Structure):
+    _fields_ = [("name", C.c_char * 48), ("ms", C.c_double), ("count", C.c_int64)]
+
+
+class iga_peaks(C.Structure):
+    _fields_ = [("copy_gbs", C.c_double), ("fma_tflops", C.c_double), ("mfma_f64_tflops", C.c_double),
+                ("n_cu", C.c_int32), ("reserved", C.c_int32)]
+
+
 class iga_solve_info(C.Structure):
     _fields_ = [("iterations", C.c_int32), ("converged", C.c_int32), ("rel_residual", C.c_double)]
 
@@ -116,7 +125,9 @@ def lib():
             "iga_plan_set_timing": (C.c_int, [P, C.c_int32]),
             "iga_plan_set_graph": (C.c_int, [P, C.c_int32]),
             "iga_plan_timings": (C.c_int, [P, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
+            "iga_plan_kernel_times": (C.c_int, [P, C.POINTER(iga_kernel_time), C.c_int32, C.POINTER(C.c_int32)]),
             "iga_copy": (C.c_int, [V, V, C.c_int64, V]),
+            "iga_measure_peaks": (C.c_int, [V, V, C.c_int64, C.c_int32, C.POINTER(iga_peaks), V]),
             "iga_plan_table": (C.c_int, [P, C.c_int32, C.c_int32, C.POINTER(C.c_void_p), C.POINTER(C.c_int64),
                                          C.POINTER(C.c_int64)]),
             "iga_plan_int_table": (C.c_int, [P, C.c_int32, C.c_int32, C.POINTER(C.c_void_p), C.POINTER(C.c_int64),
@@ -140,8 +151,8 @@ EXPORTED = ("iga_trim_plan_create", "iga_plan_destroy", "iga_plan_sizes", "iga_p
             "iga_mf_apply_noalloc",
             "iga_mf_adjoint", "iga_trim_mass_form_batched", "iga_batch_create", "iga_batch_destroy",
             "iga_batch_form", "iga_batch_autotune", "iga_batch_info", "iga_batch_status", "iga_batch_project",
-            "iga_plan_set_timing", "iga_plan_timings", "iga_plan_set_graph",
-            "iga_copy", "iga_plan_table", "iga_plan_int_table", "iga_plan_set_weights",
+            "iga_plan_set_timing", "iga_plan_timings", "iga_plan_kernel_times", "iga_plan_set_graph",
+            "iga_copy", "iga_measure_peaks", "iga_plan_table", "iga_plan_int_table", "iga_plan_set_weights",
             "iga_plan_set_dwq_weights", "iga_plan_set_cut_nodes", "iga_status_string", "iga_last_error")
 
 (TABLE_WQ_POINTS, TABLE_WQ_WEIGHTS, TABLE_MASS_1D, TABLE_C_WQ, TABLE_C_BAND, TABLE_C_CUT, TABLE_CUT_W,
@@ -307,8 +318,17 @@ class Plan:
     def status(self, stream=None):
         _check(lib().iga_status_get(self.h, _stream(stream)))
 
-    def set_timing(self, on=True):
-        _check(lib().iga_plan_set_timing(self.h, 1 if on else 0))
+    def set_timing(self, on=True, per_kernel=False):
+        """Phase timing (on), per-kernel dispatch timing (per_kernel) or off."""
+        _check(lib().iga_plan_set_timing(self.h, (2 if per_kernel else 1) if on else 0))
+
+    def kernel_times(self):
+        """{kernel name: (summed ms, dispatches)} since the last call (per-kernel timing)."""
+        cap = 64
+        buf = (iga_kernel_time * cap)()
+        n = C.c_int32()
+        _check(lib().iga_plan_kernel_times(self.h, buf, cap, C.byref(n)))
+        return {buf[k].name.decode(): (buf[k].ms, int(buf[k].count)) for k in range(min(n.value, cap))}
 
     def set_graph(self, on=True):
         _check(lib().iga_plan_set_graph(self.h, 1 if on else 0))
@@ -392,6 +412,18 @@ def mf_adjoint(plan, c_points, u, gy, stream=None):
     _check(lib().iga_mf_adjoint(plan.h, _dptr(c_points), _dptr(u), _dptr(gy), _dptr(du), _dptr(dc),
                                 _stream(stream)))
     return du, dc
+
+
+def measure_peaks(mib=1024, reps=5, stream=None):
+    """Measured copy bandwidth (GB/s) and FP64 FMA / matrix-core rates (TFLOP/s) of the current device."""
+    torch = _torch()
+    n = mib * (1 << 20) // 8
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    pk = iga_peaks()
+    _check(lib().iga_measure_peaks(_dptr(src), _dptr(dst), n, reps, C.byref(pk), _stream(stream)))
+    return {"copy_GBs": pk.copy_gbs, "fma_f64_TFs": pk.fma_tflops, "mfma_f64_TFs": pk.mfma_f64_tflops,
+            "compute_units": pk.n_cu, "copy_bytes_each_way": n * 8}
 
 
 def _make_mass_apply():
