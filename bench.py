@@ -49,6 +49,8 @@ def parse():
     ap.add_argument("--cpu-procs", type=int, default=0, help="oracle processes for the all-core sample (0: host cores, "
                                                               "at most 16)")
     ap.add_argument("--no-extra", action="store_true", help="headline only (no other sections)")
+    ap.add_argument("--sections", default="dwq,config3_dwq,projection,batched,adjoint,table1",
+                    help="comma-separated sections after the headline")
     ap.add_argument("--batch", type=int, default=256, help="patches of the batched workload")
     ap.add_argument("--mf-N", type=int, default=1024, help="elements per direction of the matrix-free workload")
     ap.add_argument("--cfg3-N", type=int, default=512, help="elements per direction of the degree-6 DWQ workload")
@@ -425,8 +427,11 @@ def main():
     }
     del vals
     if not args.no_extra:
+        wanted = set(args.sections.split(","))
         for key, fn in (("dwq", bench_dwq), ("config3_dwq", bench_config3), ("projection", bench_projection),
-                        ("batched", bench_batched), ("adjoint", bench_adjoint)):
+                        ("batched", bench_batched), ("adjoint", bench_adjoint), ("table1", bench_table1)):
+            if key not in wanted:
+                continue
             out[key] = fn(igatrim, wl, cfg, args, sync, stream, peaks)
             print(f"# {key} done", file=sys.stderr, flush=True)
     out["cpu_baseline"] = cpu
@@ -610,6 +615,18 @@ def bench_adjoint(igatrim, wl, cfg_unused, args, sync, stream, peaks):
                                  "8 B per u, r, du value and per rule-point c, dc",
                                  "whole call timed on the host / calls")},
             "note": f"p=4, {args.mf_N}^2 elements, c at every rule point; y = M(c)u and (dL/du, dL/dc)"}
+
+
+def bench_table1(igatrim, wl, cfg_unused, args, sync, stream, peaks):
+    """Table 1 (Sect. 4.1) from the device: each method's deviation from element Gauss, line trim, c = 1."""
+    from paper_2101_08053_amd import experiments
+    res = experiments.table1(degrees=tuple(range(1, 9)))
+    return {"frobenius": {str(p): {c: r[c][0] for c in experiments.METHOD_COLUMNS} for p, r in res.items()},
+            "spectral": {str(p): {c: r[c][1] for c in experiments.METHOD_COLUMNS} for p, r in res.items()},
+            "paper": {str(p): dict(zip(experiments.METHOD_COLUMNS, v)) for p, v in experiments.PAPER_TABLE1.items()},
+            "markdown": experiments.table1_markdown(res),
+            "note": "line trim 10x10 elements, c = 1; ||M_method - M_gauss|| with every matrix formed on the device; "
+                    "the paper's line is only drawn, so a seeded line stands in (magnitudes comparable)"}
 
 
 if __name__ == "__main__":

@@ -230,6 +230,29 @@ def table1_line(p, N=10, y0=0.31, y1=0.67):
                   f"line_p{p}_N{N}")
 
 
+def nonuniform_knots(rng, n_el: int, p: int, jitter=0.3) -> np.ndarray:
+    """Open knot vector on [0, 1] with simple interior knots k/n_el + U[-jitter h, jitter h] (h = 1/n_el).
+
+    One draw of n_el - 1 uniforms; the knots stay increasing for jitter < 0.5.
+    """
+    h = 1.0 / n_el
+    inner = np.arange(1, n_el) * h + rng.uniform(-jitter, jitter, size=n_el - 1) * h
+    return np.concatenate([np.zeros(p + 1), inner, np.ones(p + 1)])
+
+
+def nonuniform_variant(cfg, seed=SEED_BASE + 7, jitter=0.3):
+    """The same patch (degree, element counts, curves, geometry, coefficient) on non-uniform knots.
+
+    Draw order: direction-1 knots, then direction-2 knots. The geometry's control points are kept
+    (one per function), so a perturbed geometry stays a valid map of the new space.
+    """
+    rng = np.random.default_rng(seed)
+    k1 = nonuniform_knots(rng, cfg.n_el[0], cfg.p, jitter)
+    k2 = nonuniform_knots(rng, cfg.n_el[1], cfg.p, jitter)
+    return Patch(p=cfg.p, n_el=cfg.n_el, knots=(k1, k2), curves=cfg.curves, geom_cp=cfg.geom_cp, coef=cfg.coef,
+                 coef_value=cfg.coef_value, name=cfg.name + "_nonuniform")
+
+
 def small_variant(cfg_fn, N, p=None, **kw):
     """Same generator at a smaller element count (for parity tests)."""
     if p is None:

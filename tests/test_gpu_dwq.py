@@ -31,6 +31,8 @@ CASES = {
     "ellipses3_p5_N30": lambda: wl.config3(N=30, p=5),
     "line_p7_N10": lambda: wl.table1_line(7),
     "line_p8_N10": lambda: wl.table1_line(8),
+    "circle_p3_N30_nonuniform": lambda: wl.nonuniform_variant(wl.config1(N=30, p=3)),
+    "ellipses3_p5_N24_nonuniform": lambda: wl.nonuniform_variant(wl.config3(N=24, p=5)),
 }
 _oracles = {}
 

@@ -41,6 +41,9 @@ CASES = {
     "circle_p2_N70": lambda: wl.config1(N=70),
     "circle_p7_N24": lambda: wl.config1(N=24, p=7),
     "cubic16_p8_N20": lambda: wl.config2(N=20, p=8),
+    # non-uniform simple knots (interior knots jittered by up to 0.3 h)
+    "circle_p3_N30_nonuniform": lambda: wl.nonuniform_variant(wl.config1(N=30, p=3)),
+    "cubic16_p4_N40_nonuniform": lambda: wl.nonuniform_variant(wl.config2(N=40, p=4)),
 }
 _oracles = {}
 

@@ -20,7 +20,8 @@ def _const(cfg):
     return Oracle(cfg, coef=Coefficient(cfg, kind=wl.COEF_CONST))
 
 
-CASES = [wl.config1(N=12), wl.config2(N=14, p=3), wl.config3(N=16, p=2), wl.table1_line(3)]
+CASES = [wl.config1(N=12), wl.config2(N=14, p=3), wl.config3(N=16, p=2), wl.table1_line(3),
+         wl.nonuniform_variant(wl.config1(N=12, p=3)), wl.nonuniform_variant(wl.config2(N=10, p=4))]
 
 
 @pytest.mark.parametrize("cfg", CASES, ids=lambda c: c.name)

@@ -158,7 +158,8 @@ def test_table1_dwq_column():
         assert e <= max(gold[str(p)][1], 1e-16) * 10
 
 
-@pytest.mark.parametrize("cfg", [wl.config1(N=16), wl.config2(N=12, p=4), wl.config3(N=12, p=3)],
+@pytest.mark.parametrize("cfg", [wl.config1(N=16), wl.config2(N=12, p=4), wl.config3(N=12, p=3),
+                                 wl.nonuniform_variant(wl.config1(N=16, p=3))],
                          ids=lambda c: c.name)
 def test_dwq_equals_gauss_at_c1(cfg):
     o = _const(cfg)
