@@ -135,9 +135,12 @@ __device__ __forceinline__ void interior_col_end(const double* wb, const double*
 // banded w1 B1 factors are loaded into
 // registers (p <= 5) together with every other global load of the
 // workgroup, before stage 1; the end rows' full factor rows go to LDS.
+// For p >= 6 the factors do not fit in registers: each is formed where it
+// is used, from the row's weights (registers) and the window's basis values
+// (LDS), the same product as the precomputed table.
 // Rows per tile and column groups per row, measured: whole rows per thread
-// are fastest for p <= 5; for p >= 6, whose factors do not fit in registers,
-// the columns of a row dealt to four threads.
+// are fastest for p <= 5; for p >= 6 the columns of a row dealt to four
+// threads.
 __host__ __device__ constexpr int interior2_rows(int p) { return p <= 5 ? 128 : 64; }
 __host__ __device__ constexpr int interior2_groups(int p) { return p <= 5 ? 1 : 4; }
 template <int P>
@@ -163,7 +166,7 @@ struct Int2Smem {
     union {
         struct {
             double sT[C::W][C::KS];
-            double sB[C::PRE ? C::KS * (P + 1) : 1];  // basis values B[k][al] at the window's points
+            double sB[C::KS * (P + 1)];  // basis values B[k][al] at the window's points
         } r;
         struct {
             double sT[C::W][KSE];
@@ -271,15 +274,15 @@ __device__ __forceinline__ void interior_rows_block(const IntArgs& A, int tx, in
     // A regular row's factors w1 B1 (the banded copy's values) are formed
     // in registers from its weights (rows contiguous) and the window's basis
     // values (staged once per workgroup): one product each, as in the table.
-    double wt[C::PRE ? NR : 1];
-    if (C::PRE && !endtile && i1 >= 0) {
+    double wt[NR];
+    if (!endtile && i1 >= 0) {
 #pragma unroll
-        for (int q = 0; q < NR; ++q) wt[C::PRE ? q : 0] = D1.WT[(size_t)q * D1.n + i1];
+        for (int q = 0; q < NR; ++q) wt[q] = D1.WT[(size_t)q * D1.n + i1];
     }
-    constexpr int NBQ = C::PRE ? (C::KS * (P + 1) + NT - 1) / NT : 1;
+    constexpr int NBQ = (C::KS * (P + 1) + NT - 1) / NT;
     double bq[NBQ];
     const int nbq = ks * (P + 1);
-    if (C::PRE && !endtile) {
+    if (!endtile) {
 #pragma unroll
         for (int u = 0; u < NBQ; ++u) bq[u] = D1.Bq[(size_t)wlo1 * (P + 1) + min(tid + NT * u, nbq - 1)];
     }
@@ -309,7 +312,7 @@ __device__ __forceinline__ void interior_rows_block(const IntArgs& A, int tx, in
         const int t = tid + NT * u;
         if (t < QM * W) S.sWB2[t / W][t % W] = wb2[u];
     }
-    if (C::PRE && !endtile) {
+    if (!endtile) {
 #pragma unroll
         for (int u = 0; u < NBQ; ++u)
             if (tid + NT * u < nbq) S.r.sB[tid + NT * u] = bq[u];
@@ -380,7 +383,7 @@ __device__ __forceinline__ void interior_rows_block(const IntArgs& A, int tx, in
             for (int q = 0; q < NR; ++q)
 #pragma unroll
                 for (int al = 0; al <= P; ++al)
-                    wb[C::PRE ? q : 0][al] = wt[C::PRE ? q : 0] * S.r.sB[(k0 + q) * (P + 1) + al];
+                    wb[C::PRE ? q : 0][al] = wt[q] * S.r.sB[(k0 + q) * (P + 1) + al];
         }
 #pragma unroll 1
         for (int b = grp; b < W; b += NB) {
@@ -388,7 +391,7 @@ __device__ __forceinline__ void interior_rows_block(const IntArgs& A, int tx, in
             if constexpr (C::PRE)
                 interior_col_reg<P>([&](int q, int al) { return wb[q][al]; }, &S.r.sT[b][k0], acc);
             else
-                interior_col_reg<P>([&](int q, int al) { return D1.WBT[((size_t)q * (P + 1) + al) * D1.n + i1]; },
+                interior_col_reg<P>([&](int q, int al) { return wt[q] * S.r.sB[(k0 + q) * (P + 1) + al]; },
                                     &S.r.sT[b][k0], acc);
 #pragma unroll
             for (int a = 0; a < W; ++a) A.vals[(size_t)(a * W + b) * A.n_act + cid] = acc[a];

@@ -436,13 +436,21 @@ __global__ void __launch_bounds__(64) k_piece_isect(TrimDev T, int* __restrict__
                 double ga = __shfl(g[q], src, 64);
                 double a = Pc.t0 + (Pc.t1 - Pc.t0) * (double)js / 256.0;
                 double b = Pc.t0 + (Pc.t1 - Pc.t0) * (double)(js + 1) / 256.0;
-                for (int it = 0; it < 200; ++it) {
-                    double mid = 0.5 * (a + b);
-                    if (mid == a || mid == b) break;
+                // 64-section: lane l tests a + (b - a)(l + 1)/64; the bracket becomes the first
+                // sub-interval whose right end has changed sign (about 9 rounds to adjacent doubles)
+                for (int it = 0; it < 24; ++it) {
+                    const double tl = (lane == 63) ? b : a + (b - a) * (double)(lane + 1) / 64.0;
                     double X, Y, dX, dY;
-                    seg_eval(S, mid, X, Y, dX, dY);
-                    double gm = ellipse_implicit(C, X, Y);
-                    if ((gm < 0.0) == (ga < 0.0)) a = mid; else b = mid;
+                    seg_eval(S, tl, X, Y, dX, dY);
+                    const bool flip = (ellipse_implicit(C, X, Y) < 0.0) != (ga < 0.0);
+                    const unsigned long long fm = __ballot(flip && tl > a);
+                    const int l = fm ? __ffsll((long long)fm) - 1 : 63;
+                    const double nb = __shfl(tl, l, 64);
+                    const double na = (l == 0) ? a : __shfl(tl, max(l - 1, 0), 64);
+                    const bool done = !(na > a || nb < b);  // no progress: a and b are adjacent
+                    a = na;
+                    b = nb;
+                    if (done) break;
                 }
                 if (nf < kMaxIsectPerPiece) found[nf] = 0.5 * (a + b);
                 ++nf;
@@ -515,19 +523,19 @@ __device__ __forceinline__ BpView stage_bp(const GridDev& G, double* sbp) {
     return {sbp, sbp + n1};  // the caller synchronises before use
 }
 
-// Union of holes (one workgroup of 1024, after the curve-curve splits):
+// Union of holes (one workgroup, after the curve-curve splits):
 // orientation of every curve (sign of its enclosed area by Gauss on each
 // segment; a hole traversed with the visible domain on its left is
 // clockwise).
 __device__ void curves_orient(const TrimDev& T, CurveDev* __restrict__ curves, const double* __restrict__ gx,
                               const double* __restrict__ gw) {
     __shared__ double sh_area[1024 / 64];
-    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6, nt = blockDim.x;
     constexpr int ng = 8;
     for (int c = 0; c < T.n_curves; ++c) {
         const CurveDev C = curves[c];
         double area = 0.0;
-        for (int u = tid; u < C.n_seg * ng; u += 1024) {
+        for (int u = tid; u < C.n_seg * ng; u += nt) {
             const SegDev S = T.segs[C.seg0 + u / ng];
             const int g = u % ng;
             const double tt = C.t_range * (gx[gauss_off(ng) + g] + 1.0) * 0.5;
@@ -541,7 +549,7 @@ __device__ void curves_orient(const TrimDev& T, CurveDev* __restrict__ curves, c
         __syncthreads();
         if (tid == 0) {
             double a = 0.0;
-            for (int w = 0; w < 1024 / 64; ++w) a += sh_area[w];
+            for (int w = 0; w < nt / 64; ++w) a += sh_area[w];
             curves[c].sigma = (a > 0.0) ? -1.0 : 1.0;
         }
         __syncthreads();
@@ -630,8 +638,10 @@ __global__ void __launch_bounds__(256) k_trim_front(TrimDev T, const double* __r
     }
 }
 
-// Union of holes: split the pieces where they meet another curve, then orientation.
-__global__ void __launch_bounds__(1024) k_trim_split(TrimDev T, CurveDev* __restrict__ curves,
+// Union of holes: split the pieces where they meet another curve, then
+// orientation. 256 threads: a workgroup that fits beside the other stream's
+// kernels (a 1024-thread one waited for a whole free CU).
+__global__ void __launch_bounds__(256) k_trim_split(TrimDev T, CurveDev* __restrict__ curves,
                                                      const double* __restrict__ gx, const double* __restrict__ gw) {
     pieces_split(T);
     __syncthreads();
@@ -646,7 +656,7 @@ void launch_trim_curves(Plan& P, hipStream_t s) {
                        P.gauss_w);
     if (T.n_curves > 1) {
         klaunch(P, "k_piece_isect", k_piece_isect, dim3(T.cap_pieces0), dim3(64), 0, s, T, P.status);
-        klaunch(P, "k_trim_split", k_trim_split, dim3(1), dim3(1024), 0, s, T, P.d_curves, P.gauss_x, P.gauss_w);
+        klaunch(P, "k_trim_split", k_trim_split, dim3(1), dim3(256), 0, s, T, P.d_curves, P.gauss_x, P.gauss_w);
     }
 }
 
@@ -1059,21 +1069,36 @@ __device__ __forceinline__ int block_sum256(int v, int* sh) {
     return tot;
 }
 
-// Very large patches: exclusive scan of the row-segment counts (one workgroup).
-__global__ void __launch_bounds__(1024) k_list_scan(ListArgs A) {
-    __shared__ int sh[1024 / 64 + 1];
-    const int nt = A.n2 * A.ntx;
-    for (int a = 0; a < 4; ++a) {
-        int carry = 0;
-        for (int t0 = 0; t0 < nt; t0 += 1024) {
-            const int idx = t0 + threadIdx.x;
-            const bool in = idx < A.rows[a] * A.ntx;  // element rows past N2 hold nothing
-            const int v = in ? A.bsum[a * nt + idx] : 0;
-            int total;
-            const int ex = block_excl_scan(v, sh, total);
-            if (in) A.bsum[a * nt + idx] = ex + carry;
-            carry += total;
+// Very large patches: exclusive scan of the row-segment counts, one
+// workgroup of 256 per list; each pass, every thread loads 16 consecutive
+// counts (all loads issued together), scans them in registers and offsets
+// them by a block scan of the thread totals.
+constexpr int kListScanPer = 16;
+__global__ void __launch_bounds__(256) k_list_scan(ListArgs A) {
+    __shared__ int sh[256 / 64 + 1];
+    const int a = blockIdx.x, nt = A.n2 * A.ntx;
+    const int m = A.rows[a] * A.ntx;  // element rows past N2 hold nothing
+    int* v = A.bsum + (size_t)a * nt;
+    int carry = 0;
+#pragma unroll 1
+    for (int t0 = 0; t0 < m; t0 += 256 * kListScanPer) {
+        const int i0 = t0 + (int)threadIdx.x * kListScanPer;
+        int x[kListScanPer];
+#pragma unroll
+        for (int k = 0; k < kListScanPer; ++k) x[k] = v[min(i0 + k, m - 1)];
+        int sum = 0;
+#pragma unroll
+        for (int k = 0; k < kListScanPer; ++k) {
+            const int xv = (i0 + k < m) ? x[k] : 0;
+            x[k] = sum;  // exclusive within the thread
+            sum += xv;
         }
+        int total;
+        const int ex = block_excl_scan(sum, sh, total) + carry;
+#pragma unroll
+        for (int k = 0; k < kListScanPer; ++k)
+            if (i0 + k < m) v[i0 + k] = ex + x[k];
+        carry += total;
     }
 }
 
@@ -1176,7 +1201,7 @@ void launch_trim_lists(Plan& P, hipStream_t s) {
     A.bsum = P.list_rcnt;
     A.counts = P.counts;
     A.prefix_here = trim_lists_prefix_here(P);
-    if (!A.prefix_here) klaunch(P, "k_list_scan", k_list_scan, dim3(1), dim3(1024), 0, s, A);
+    if (!A.prefix_here) klaunch(P, "k_list_scan", k_list_scan, dim3(4), dim3(256), 0, s, A);
     klaunch(P, "k_list_rows", k_list_rows, dim3(P.n2), dim3(256), 0, s, A);
 }
 
