@@ -560,6 +560,23 @@ def bench_batched(igatrim, wl, cfg_unused, args, sync, stream, peaks):
     ms_proj_plain = 1e3 * (time.perf_counter() - t0)
     roof = _roof("batched formation (graph replay)", "hbm", band_bytes, ms_graph, peaks,
                  "8 B per band value written (all patches)", "whole replay timed on the host / replays")
+    # the same patches with the degree-5 ones formed by DWQ (their side rules solved in the batch too)
+    plans5 = [igatrim.Plan(c, igatrim.DWQ) if c.p == 5 else p for c, p in zip(cfgs, plans)]
+    coeffs5 = [p.coeff() for p in plans5]
+    b5 = igatrim.Batch(plans5, coeffs5)
+    b5.autotune()
+    ms_dwq5 = _timed(lambda: b5.form(use_graph=True), steps, 2, sync)
+    b5.status()
+    outs5 = b5.outs
+
+    def plain5():
+        for p, c, o in zip(plans5, coeffs5, outs5):
+            p.mass_form(c, out=o)
+
+    ms_dwq5_plain = _timed(plain5, max(3, steps // 2), 2, sync)
+    n_dwq5 = sum(1 for c in cfgs if c.p == 5)
+    nnz5 = sum(p.sizes["nnz"] for p in plans5)
+    del b5, outs5
     return {"value": nnz / (ms_graph * 1e-3), "unit": "nnz/s", "ms": ms_graph, "eager_ms": ms_eager,
             "plain_ms": ms_plain, "plain_value": nnz / (ms_plain * 1e-3), "speedup_vs_plain": ms_plain / ms_graph,
             "patches": len(plans), "nnz": nnz, "band_MB": band_bytes / 1e6, "roofline": roof,
@@ -571,6 +588,11 @@ def bench_batched(igatrim, wl, cfg_unused, args, sync, stream, peaks):
             "projection_speedup_vs_plain": ms_proj_plain / ms_proj,
             "projection_iterations": {"max": max(iters), "median": statistics.median(iters), "sum": sum(iters)},
             "projection_converged": all(i["converged"] for i in infos),
+            "dwq_p5": {"ms": ms_dwq5, "value": nnz5 / (ms_dwq5 * 1e-3), "plain_ms": ms_dwq5_plain,
+                       "speedup_vs_plain": ms_dwq5_plain / ms_dwq5, "dwq_patches": n_dwq5,
+                       "note": "the same 256 patches with the degree-5 ones by DWQ: their side rules (refined "
+                               "minimum-norm solves) batched across patches in the replay, then their box rows; "
+                               "the one-by-one calls form over the plans' resident side rules (no solves)"},
             "note": "formation over resident tables, one graph replay per call (cut element matrices beside "
                     "per-degree coefficient and interior launches, then the element-formed rows) vs one formation "
                     "call per patch; projection: batched right-hand sides + PCG of all patches (synchronous) vs "

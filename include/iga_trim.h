@@ -249,7 +249,7 @@ int iga_mf_adjoint(iga_plan* plan, const double* c_points, const double* u, cons
 
 /* Batched formation of many patches (each patch's rules as in Sects. 2-3):
  * the resident tables of count plans (set up, each plan with its own degree
- * <= 6, method hybrid Gauss or element Gauss) are formed into vals[k]
+ * <= 6, method hybrid Gauss, element Gauss or DWQ) are formed into vals[k]
  * (device, band_k * n_act_k doubles) with coefficient cs[k]. The uneven
  * work, the cut-element matrices of all patches (node counts differ), is one
  * persistent launch (plus a counter reset): a cost-sorted work queue per
@@ -258,7 +258,12 @@ int iga_mf_adjoint(iga_plan* plan, const double* c_points, const double* u, cons
  * the coefficient chunks and then the interior tiles run in one launch per
  * degree; once the persistent launch and the coefficient chunks are done,
  * the element-formed rows run in one launch per degree (one workgroup per
- * row). The values equal the one-patch formation's bit for bit.
+ * row). DWQ plans (coefficient constant or |det J|) also have their side
+ * rules (Sect. 3.3: the refined minimum-norm solves of every interior knot
+ * and side) solved again, every DWQ patch of a degree in one launch before
+ * the cut elements, and their rows' box parts added after the
+ * element-formed rows. The values equal the one-patch formation's bit for
+ * bit.
  *
  * A batch object keeps the descriptors, the queue and, with use_graph != 0,
  * a HIP graph recorded on the first such call and replayed afterwards. The

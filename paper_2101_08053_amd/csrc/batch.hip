@@ -38,6 +38,7 @@
 #include <memory>
 #include <vector>
 
+#include "dwq_body.hpp"
 #include "form_body.hpp"
 
 namespace iga {
@@ -54,6 +55,11 @@ struct BatchPlan {
     CutEArgs ce;
     CutRowArgs cr;
     CoefArgs co;
+    // discontinuous weighted quadrature (method IGA_DWQ): the side rules of
+    // every (direction, interior knot, side) slot and the rows' box parts
+    DwqRowArgs dr;
+    const double *gx, *gw;  // packed Gauss-Legendre table
+    int* status;
 };
 
 struct BatchItem {
@@ -223,6 +229,26 @@ __global__ void __launch_bounds__(Int2Cfg<P>::NT)
     interior_rows_block<P>(Bp.ia, it.unit - i2 * ntx, i2, S);
 }
 
+// Side rules of the batch's DWQ patches of degree P, one workgroup per
+// (direction, interior knot, side) slot: the uneven refined minimum-norm
+// solves of every patch in one launch.
+template <int P>
+__global__ void __launch_bounds__(128)
+    k_batch_dwq_sides(const BatchPlan* __restrict__ plans, const BatchItem* __restrict__ items) {
+    const BatchItem it = items[blockIdx.x];
+    const BatchPlan& Bp = plans[__builtin_amdgcn_readfirstlane(it.plan)];
+    dwq_sides_body<P>(Bp.ia.d1, Bp.ia.d2, Bp.gx, Bp.gw, Bp.status, it.unit);
+}
+
+// Box parts of the DWQ patches' element-formed rows (degree P), one
+// workgroup per row with a box, after the element-formed rows.
+template <int P>
+__global__ void __launch_bounds__(256)
+    k_batch_dwq_rows(const BatchPlan* __restrict__ plans, const BatchItem* __restrict__ items) {
+    const BatchItem it = items[blockIdx.x];
+    dwq_rows_body<P>(plans[__builtin_amdgcn_readfirstlane(it.plan)].dr, it.unit);
+}
+
 // Element-formed rows of the batch's patches of degree P, one workgroup per
 // row, after the persistent launch and the coefficient chunks (so the
 // coefficients and cut element matrices are complete): the fused body of the
@@ -256,6 +282,8 @@ struct Batch {
     int persistent = 1;  // 1: cut element matrices from the persistent queue, 0: one workgroup each (autotuned)
     int int_off[kBatchGroups] = {}, int_n[kBatchGroups] = {};
     int rows_off[kBatchGroups] = {}, rows_n[kBatchGroups] = {};
+    int dwqs_off[kBatchGroups] = {}, dwqs_n[kBatchGroups] = {};  // DWQ side slots
+    int dwqr_off[kBatchGroups] = {}, dwqr_n[kBatchGroups] = {};  // DWQ rows with a box
     int* d_counters = nullptr;  // status, heads[kBatchGroups], level counters[kBatchGroups][2]
     int n_items = 0;
     int n_cu = 256;
@@ -350,6 +378,20 @@ struct Batch {
             }
         }
         HIPX(hipEventRecord(ev_join, side));
+        for (int g = 0; g < kBatchGroups; ++g) {  // DWQ side rules (read the knots only)
+            if (dwqs_n[g] == 0) continue;
+            const BatchItem* it = d_rows + dwqs_off[g];
+            const dim3 grid((unsigned)dwqs_n[g]);
+            switch (g + 1) {
+#define CASE(PP)                                                                                 \
+    case PP:                                                                                     \
+        hipLaunchKernelGGL(k_batch_dwq_sides<PP>, grid, dim3(128), 0, s, d_plans, it); \
+        break;
+                CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6)
+#undef CASE
+                default: break;
+            }
+        }
         hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(64), 0, s, d_counters, nc);
         BatchDev B{};
         B.plans = d_plans;
@@ -406,6 +448,20 @@ struct Batch {
                 default: break;
             }
         }
+        for (int g = 0; g < kBatchGroups; ++g) {  // DWQ box parts, added to the element-formed rows
+            if (dwqr_n[g] == 0) continue;
+            const BatchItem* it = d_rows + dwqr_off[g];
+            const dim3 grid((unsigned)dwqr_n[g]);
+            switch (g + 1) {
+#define CASE(PP)                                                                                \
+    case PP:                                                                                    \
+        hipLaunchKernelGGL(k_batch_dwq_rows<PP>, grid, dim3(256), 0, s, d_plans, it); \
+        break;
+                CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6)
+#undef CASE
+                default: break;
+            }
+        }
         HIPX(hipStreamWaitEvent(s, ev_join, 0));
     }
 };
@@ -452,14 +508,17 @@ static iga_batch* batch_create(iga_plan* const* plans, int count, const iga_coef
     };
     std::vector<Cand> all;
     std::vector<BatchItem> coefs[kBatchGroups], tiles[kBatchGroups], rows[kBatchGroups], cutes[kBatchGroups];
+    std::vector<BatchItem> dwqs[kBatchGroups], dwqr[kBatchGroups];
     for (int k = 0; k < count; ++k) {
         IGA_REQUIRE(plans[k], IGA_E_INVALID, "null plan in batch");
         Plan& P = *static_cast<Plan*>(plans[k]);
         const iga_coeff& c = cs[k];
         IGA_REQUIRE(outs[k], IGA_E_INVALID, "output buffer missing");
         IGA_REQUIRE(P.p <= kBatchMaxP, IGA_E_UNSUPPORTED, "batched formation handles degrees up to 6");
-        IGA_REQUIRE(P.method == IGA_HYBRID_GAUSS || P.method == IGA_GAUSS_REF, IGA_E_UNSUPPORTED,
-                    "batched formation handles hybrid Gauss and element Gauss plans");
+        IGA_REQUIRE(P.method == IGA_HYBRID_GAUSS || P.method == IGA_GAUSS_REF || P.method == IGA_DWQ,
+                    IGA_E_UNSUPPORTED, "batched formation handles hybrid Gauss, element Gauss and DWQ plans");
+        IGA_REQUIRE(!(P.method == IGA_DWQ && c.kind == IGA_COEF_AT_POINTS), IGA_E_UNSUPPORTED,
+                    "discontinuous weighted quadrature needs c at nested points: constant or |det J| only");
         IGA_REQUIRE(c.kind >= IGA_COEF_CONST && c.kind <= IGA_COEF_AT_POINTS, IGA_E_UNSUPPORTED, "coefficient kind");
         IGA_REQUIRE(c.kind != IGA_COEF_GEOM_DETJ || c.geom_cp, IGA_E_INVALID, "geometry control points missing");
         IGA_REQUIRE(c.kind != IGA_COEF_AT_POINTS || c.c_points, IGA_E_INVALID, "per-point coefficient missing");
@@ -474,6 +533,21 @@ static iga_batch* batch_create(iga_plan* const* plans, int count, const iga_coef
         bp.ce = cute_args(P, c);
         bp.cr = cutr_args(P, c, outs[k]);
         bp.co = coef_args(P, c);
+        bp.dr = DwqRowArgs{P.dir[0], P.dir[1], coef_view(P, c), c.geom_cp, P.form_rows, (int)P.n_form_rows,
+                           P.fn_of, P.act_of, P.dwq_region, outs[k], P.n_act};
+        bp.gx = P.gauss_x;
+        bp.gw = P.gauss_w;
+        bp.status = P.status;
+        if (P.method == IGA_DWQ) {
+            const int nslot = 2 * (P.N1 - 1) + 2 * (P.N2 - 1);
+            for (int u = 0; u < nslot; ++u) dwqs[P.p - 1].push_back(BatchItem{k, 0, u, 0});
+            if (P.n_form_rows > 0) {
+                std::vector<int> reg(8 * (size_t)P.n_form_rows);
+                HIPX(hipMemcpy(reg.data(), P.dwq_region, sizeof(int) * reg.size(), hipMemcpyDeviceToHost));
+                for (int r = 0; r < (int)P.n_form_rows; ++r)
+                    if (reg[8 * (size_t)r] >= 0) dwqr[P.p - 1].push_back(BatchItem{k, 0, r, 0});
+            }
+        }
         std::vector<int> node_off(P.n_cut_el + 1, 0);
         if (P.n_cut_el > 0)
             HIPX(hipMemcpy(node_off.data(), P.node_off, sizeof(int) * (P.n_cut_el + 1), hipMemcpyDeviceToHost));
@@ -541,6 +615,16 @@ static iga_batch* batch_create(iga_plan* const* plans, int count, const iga_coef
         B->rows_off[g] = (int)rows_all.size();
         B->rows_n[g] = (int)rows[g].size();
         rows_all.insert(rows_all.end(), rows[g].begin(), rows[g].end());
+    }
+    for (int g = 0; g < kBatchGroups; ++g) {
+        B->dwqs_off[g] = (int)rows_all.size();
+        B->dwqs_n[g] = (int)dwqs[g].size();
+        rows_all.insert(rows_all.end(), dwqs[g].begin(), dwqs[g].end());
+    }
+    for (int g = 0; g < kBatchGroups; ++g) {
+        B->dwqr_off[g] = (int)rows_all.size();
+        B->dwqr_n[g] = (int)dwqr[g].size();
+        rows_all.insert(rows_all.end(), dwqr[g].begin(), dwqr[g].end());
     }
     // cut elements sit in the queue and in their per-degree list: count them once
     B->n_items = (int)(rows_all.size() + all.size());

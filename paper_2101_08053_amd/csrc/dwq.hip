@@ -15,209 +15,14 @@
 //    above s ascending, below s descending; direction-1 options outer).
 //  * k_dwq_rows: adds the box's contribution to a row that k_cut_rows formed
 //    element-wise over the rest of the support.
-#include "plan.hpp"
+#include "dwq_body.hpp"
 
 namespace iga {
 
 template <int P>
-struct DwqCfg {
-    static constexpr int KQ = 4 * P + 2;  // points of one side list / of one support
-    static constexpr int NK = 3 * P + 2;  // local refined knots used
-    static constexpr int M = 2 * P + 1;   // trial functions of a refined system
-};
-
-template <int P>
 __global__ void __launch_bounds__(128) k_dwq_sides(DirDev D1, DirDev D2, const double* __restrict__ gx,
-                                                            const double* __restrict__ gw, int* __restrict__ status) {
-    using C = DwqCfg<P>;
-    constexpr int KQ = C::KQ, NK = C::NK, M = C::M;
-    __shared__ double sRK[NK];         // refined local knots: 0 (p+1 times), then the side's knots
-    __shared__ double sU[KQ];          // local coordinate of each point, local order
-    __shared__ int sEl[KQ];            // local element of each point
-    __shared__ double sX[KQ];          // coordinates, increasing x
-    __shared__ int sOel[KQ], sOk[KQ];  // element / WQ index (-1 nested), increasing x
-    __shared__ int sCnt[P + 2];        // points in local elements < k
-    __shared__ double sS[P + 1][P];    // B_c = sum_r S[r][c] B~_r on the side (local c)
-    __shared__ double sWt[P + 1][KQ];  // refined weights, local order
-    __shared__ int sInfo[3];
-
-    const int nslot1 = 2 * (D1.N - 1);
-    int slot = blockIdx.x, d = 0;
-    if (slot >= nslot1) {
-        slot -= nslot1;
-        d = 1;
-    }
-    const DirDev& D = d ? D2 : D1;
-    const int N = D.N;
-    if (slot >= 2 * (N - 1)) return;
-    const int s = slot / 2 + 1;
-    const bool high = (slot & 1) != 0;
-    const int nk = N + 2 * P + 1;
-    const double t = D.knots[P + s];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-
-    if (tid == 0) {
-        const int nE = high ? N - s : s;
-        const int nEl = min(nE, P + 1);
-        const int nRK = high ? nk - s : s + 2 * P + 1;
-        for (int m = 0; m < NK; ++m) {
-            double v = 0.0;
-            if (m > P) {
-                const int kk = min(m, nRK - 1) - P - 1;
-                v = high ? D.knots[s + P + 1 + kk] - t : t - D.knots[s + P - 1 - kk];
-            }
-            sRK[m] = v;
-        }
-        // points of the side's first nEl elements, increasing x
-        int np = 0;
-        const int e_lo = high ? s : s - nEl, e_hi = high ? s + nEl - 1 : s - 1, e_adj = high ? s : s - 1;
-        for (int e = e_lo; e <= e_hi; ++e) {
-            const int ne = (e == 0 || e == N - 1) ? P + 1 : 2;
-            const double a = D.knots[P + e], b = D.knots[P + e + 1];
-            const int k0 = wq_pt0(e, N, P);
-            const int nadd = (e == e_adj) ? max(0, P + 1 - ne) : 0;
-            if (nadd == 0) {
-                for (int j = 1; j <= ne; ++j) {
-                    sX[np] = a + (b - a) * j / (ne + 1);
-                    sOel[np] = e;
-                    sOk[np] = k0 + j - 1;
-                    ++np;
-                }
-            } else {
-                const double E[4] = {a, a + (b - a) * 1 / 3, a + (b - a) * 2 / 3, b};
-                for (int g = 0; g < 3; ++g) {
-                    const int mg = high ? (nadd + 2 - g) / 3 : (nadd + g) / 3;
-                    for (int j = 1; j <= mg; ++j) {
-                        sX[np] = E[g] + (E[g + 1] - E[g]) * j / (mg + 1);
-                        sOel[np] = e;
-                        sOk[np] = -1;
-                        ++np;
-                    }
-                    if (g < 2) {
-                        sX[np] = E[g + 1];
-                        sOel[np] = e;
-                        sOk[np] = k0 + g;
-                        ++np;
-                    }
-                }
-            }
-        }
-        for (int k = 0; k <= P + 1; ++k) sCnt[k] = 0;
-        for (int q = 0; q < np; ++q) {
-            const int qo = high ? q : np - 1 - q;
-            sU[q] = high ? sX[qo] - t : t - sX[qo];
-            sEl[q] = high ? sOel[qo] - s : s - 1 - sOel[qo];
-            sCnt[sEl[q] + 1]++;
-        }
-        for (int k = 1; k <= P + 1; ++k) sCnt[k] += sCnt[k - 1];
-        sInfo[0] = np;
-        sInfo[1] = nRK - P - 1;  // refined functions on the side
-        sInfo[2] = nEl;
-    }
-    if (tid >= 64 && tid < 64 + P) {
-        // Eq. (10) p times on the local coarse knots, for the unit vector of local function c
-        const int c = tid - 64;
-        double K[3 * P + 2], Pc[2 * P + 1], Qn[2 * P + 1];
-        int L = 2 * P + 2, nf = P + 1;
-        for (int m = 0; m < L; ++m) K[m] = high ? D.knots[s + m] - t : t - D.knots[s + 2 * P - m];
-        for (int j = 0; j < 2 * P + 1; ++j) Pc[j] = (j == c) ? 1.0 : 0.0;
-        for (int ins = 0; ins < P; ++ins) {
-            int k = 0;
-            while (k + 1 < L && K[k + 1] <= 0.0) ++k;  // span of the inserted knot
-            for (int j = 0; j <= nf; ++j) {
-                double al;
-                if (j <= k - P) al = 1.0;
-                else if (j <= k) al = (0.0 - K[j]) / (K[j + P] - K[j]);
-                else al = 0.0;
-                const double pj = (j < nf) ? Pc[j] : 0.0, pm = (j >= 1) ? Pc[j - 1] : 0.0;
-                Qn[j] = al * pj + (1.0 - al) * pm;
-            }
-            for (int j = 0; j <= nf; ++j) Pc[j] = Qn[j];
-            for (int m = L; m > k + 1; --m) K[m] = K[m - 1];
-            K[k + 1] = 0.0;
-            ++L;
-            ++nf;
-        }
-        for (int r = 0; r <= P; ++r) sS[r][c] = Pc[P + r];
-    }
-    __syncthreads();
-
-    const int np = sInfo[0], n_fun = sInfo[1], nEl = sInfo[2];
-    // two wavefronts take the p+1 refined functions in turn (two-wavefront
-    // workgroups: four fit on a CU beside each other at this register count)
-#pragma unroll 1
-    for (int r = wave; r <= P; r += 2) {
-        if (r < n_fun) {
-            const int kr = min(r, nEl - 1);               // last local element of supp B~_r
-            const int q = sCnt[kr + 1];                   // its points
-            const int m = min(r + P, n_fun - 1) + 1;      // trial functions 0..m-1
-            double a[M], a0[M];
-#pragma unroll
-            for (int c = 0; c < M; ++c) a[c] = 0.0;
-            if (lane < q) {
-                const int k = sEl[lane];
-                double Nv[P + 1];
-                basis_eval<P>(sRK, P + k, sU[lane], Nv);
-#pragma unroll
-                for (int c = 0; c < M; ++c)
-                    if (c < m && c >= k && c <= k + P) a[c] = Nv[c - k];
-            }
-#pragma unroll
-            for (int c = 0; c < M; ++c) a0[c] = a[c];
-            // moments int B~_c B~_r over the elements of supp B~_r, (p+1)-point Gauss
-            double mom[M];
-#pragma unroll
-            for (int c = 0; c < M; ++c) mom[c] = 0.0;
-            for (int pg = lane; pg < (kr + 1) * (P + 1); pg += 64) {
-                const int k = pg / (P + 1), g = pg % (P + 1);
-                const double ua = sRK[P + k], ub = sRK[P + k + 1];
-                const double xg = ua + (ub - ua) * (gx[gauss_off(P + 1) + g] + 1.0) * 0.5;
-                const double wgt = gw[gauss_off(P + 1) + g] * (ub - ua) * 0.5;
-                double Nv[P + 1];
-                basis_eval<P>(sRK, P + k, xg, Nv);
-                const double br = (r >= k && r <= k + P) ? Nv[r - k] : 0.0;
-#pragma unroll
-                for (int c = 0; c < M; ++c)
-                    if (c >= k && c <= k + P) mom[c] += wgt * Nv[c - k] * br;
-            }
-#pragma unroll
-            for (int c = 0; c < M; ++c) mom[c] = wave_sum(mom[c]);
-            bool singular = false;
-            const double y = wave_min_norm<M>(a, q, m, [&](int c) { return mom[c]; }, singular);
-            double rmax = 0.0, bmax = 0.0;
-#pragma unroll
-            for (int c = 0; c < M; ++c) {
-                if (c >= m) break;
-                const double rc = wave_sum(a0[c] * y);
-                rmax = fmax(rmax, fabs(rc - mom[c]));
-                bmax = fmax(bmax, fabs(mom[c]));
-            }
-            if (lane < KQ) sWt[r][lane] = y;
-            if (lane == 0 && (singular || !(rmax <= 1e-12 * bmax))) atomicExch(status, IGA_E_SINGULAR_WEIGHTS);
-        } else if (lane < KQ) {
-            sWt[r][lane] = 0.0;
-        }
-    }
-    __syncthreads();
-
-    const int gslot = slot;
-    const int nr = min(P + 1, n_fun);
-    for (int tt = tid; tt < P * KQ; tt += blockDim.x) {
-        const int ii = tt / KQ, qo = tt % KQ;  // function s + ii, point qo (increasing x)
-        double v = 0.0;
-        if (qo < np) {
-            const int ql = high ? qo : np - 1 - qo;
-            const int c = high ? ii : P - 1 - ii;
-            for (int rr = 0; rr < nr; ++rr) v += sS[rr][c] * sWt[rr][ql];
-        }
-        D.dq_w[((size_t)gslot * P + ii) * KQ + qo] = v;
-    }
-    for (int qo = tid; qo < KQ; qo += blockDim.x) {
-        D.dq_x[(size_t)gslot * KQ + qo] = (qo < np) ? sX[qo] : 0.0;
-        D.dq_el[(size_t)gslot * KQ + qo] = (qo < np) ? sOel[qo] : -1;
-        D.dq_k[(size_t)gslot * KQ + qo] = (qo < np) ? sOk[qo] : -1;
-    }
-    if (tid == 0) D.dq_n[gslot] = np;
+                                                   const double* __restrict__ gw, int* __restrict__ status) {
+    dwq_sides_body<P>(D1, D2, gx, gw, status, blockIdx.x);
 }
 
 // ------------------------------------------------------------ box choice
@@ -305,123 +110,9 @@ __global__ void __launch_bounds__(64) k_dwq_choose(int N1, int N2, int n1, const
 }
 
 // ------------------------------------------------------------ box rows
-struct DwqRowArgs {
-    DirDev d1, d2;
-    CoefView c;
-    const double* geom_cp;
-    const int* rows;
-    int n_rows;
-    const int* fn_of;
-    const int* act_of;
-    const int* region;
-    double* vals;
-    int64_t n_act;
-};
-
-// One workgroup per formed row with a box: the two 1-D rules restricted to
-// the box (coarse WQ rule on a whole range, the side list otherwise) are
-// staged in LDS with the band's basis values, c on the tensor points (the WQ
-// grid where both coordinates are WQ points, |det J| evaluated otherwise),
-// then T[b][q1] = sum_q2 w2 B2 c and M[a][b] = sum_q1 w1 B1 T[b][q1] is added
-// to the row.
 template <int P>
 __global__ void __launch_bounds__(256) k_dwq_rows(DwqRowArgs A) {
-    constexpr int W = 2 * P + 1, KQ = DwqCfg<P>::KQ;
-    __shared__ double sX[2][KQ], sWt[2][KQ];
-    __shared__ int sE[2][KQ], sK[2][KQ], sNq[2];
-    __shared__ double sB[2][KQ][W];
-    __shared__ double sC[KQ][KQ + 1];
-    __shared__ double sT[W][KQ];
-    const int r = blockIdx.x;
-    if (r >= A.n_rows) return;
-    const int* reg = A.region + (size_t)r * 8;
-    if (reg[0] < 0) return;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int row = A.rows[r];
-    const int f = A.fn_of[row];
-    const int i1 = f % A.d1.n, i2 = f / A.d1.n;
-    if (wave < 2) {
-        const int d = wave;
-        const DirDev& D = d ? A.d2 : A.d1;
-        const int i = d ? i2 : i1;
-        const int lo = reg[4 * d], hi = reg[4 * d + 1], s = reg[4 * d + 2], sd = reg[4 * d + 3];
-        bool ok = false;
-        double x = 0.0, w = 0.0;
-        int e = 0, k = -1;
-        if (s < 0) {
-            const int k0 = wq_pt0(max(0, i - P), D.N, P);
-            const int kb = wq_pt0(lo, D.N, P), ke = wq_pt0(hi + 1, D.N, P);
-            const int kk = kb + lane;
-            ok = kk < ke;
-            if (ok) {
-                x = D.xq[kk];
-                e = D.eq[kk];
-                k = kk;
-                w = D.W[(size_t)i * D.qmax + (kk - k0)];
-            }
-        } else {
-            const int slot = 2 * (s - 1) + sd;
-            const int np = D.dq_n[slot];
-            if (lane < np) {
-                e = D.dq_el[(size_t)slot * KQ + lane];
-                ok = (e >= lo && e <= hi);
-                x = D.dq_x[(size_t)slot * KQ + lane];
-                k = D.dq_k[(size_t)slot * KQ + lane];
-                w = D.dq_w[((size_t)slot * P + (i - s)) * KQ + lane];
-            }
-        }
-        const unsigned long long msk = __ballot(ok);
-        const int pos = __popcll(msk & ((1ull << lane) - 1ull));
-        if (ok) {
-            sX[d][pos] = x;
-            sE[d][pos] = e;
-            sK[d][pos] = k;
-            sWt[d][pos] = w;
-            double Nv[P + 1];
-            basis_eval<P>(D.knots, P + e, x, Nv);
-#pragma unroll
-            for (int b = 0; b < W; ++b) {
-                const int j = i + b - P;
-                sB[d][pos][b] = (j >= e && j <= e + P) ? Nv[j - e] : 0.0;
-            }
-        }
-        if (lane == 0) sNq[d] = __popcll(msk);
-    }
-    __syncthreads();
-    const int n1q = sNq[0], n2q = sNq[1];
-    for (int tt = tid; tt < n1q * n2q; tt += 256) {
-        const int q1 = tt % n1q, q2 = tt / n1q;
-        double cv;
-        if (A.c.is_const) {
-            cv = A.c.value;
-        } else if (sK[0][q1] >= 0 && sK[1][q2] >= 0) {
-            cv = A.c.wq[(size_t)sK[1][q2] * A.d1.Q + sK[0][q1]];
-        } else {  // a nested coordinate: |det J| of the geometry there
-            const int e1 = sE[0][q1], e2 = sE[1][q2];
-            double B1[P + 1], dB1[P + 1], B2[P + 1], dB2[P + 1];
-            basis_eval_d<P>(A.d1.knots, P + e1, sX[0][q1], B1, dB1);
-            basis_eval_d<P>(A.d2.knots, P + e2, sX[1][q2], B2, dB2);
-            cv = detj_local(A.geom_cp, A.d1.n, P, e1, e2, B1, dB1, B2, dB2);
-        }
-        sC[q1][q2] = cv;
-    }
-    __syncthreads();
-    for (int tt = tid; tt < W * n1q; tt += 256) {
-        const int b = tt / n1q, q1 = tt % n1q;
-        double acc = 0.0;
-        for (int q2 = 0; q2 < n2q; ++q2) acc += sWt[1][q2] * sB[1][q2][b] * sC[q1][q2];
-        sT[b][q1] = acc;
-    }
-    __syncthreads();
-    for (int t = tid; t < W * W; t += 256) {  // (2p+1)^2 slots: more than 256 at p = 8
-        const int a = t / W, b = t % W;
-        const int j1 = i1 + a - P, j2 = i2 + b - P;
-        if (j1 >= 0 && j1 < A.d1.n && j2 >= 0 && j2 < A.d2.n && A.act_of[j2 * A.d1.n + j1] >= 0) {
-            double acc = 0.0;
-            for (int q1 = 0; q1 < n1q; ++q1) acc += sWt[0][q1] * sB[0][q1][a] * sT[b][q1];
-            A.vals[(size_t)t * A.n_act + row] += acc;
-        }
-    }
+    dwq_rows_body<P>(A, blockIdx.x);
 }
 
 // ------------------------------------------------------------ launchers
@@ -446,8 +137,7 @@ void launch_dwq_choose(Plan& P, hipStream_t s) {
 #define CASE(PP)                                                                                                 \
     case PP:                                                                                                     \
         klaunch(P, "k_dwq_choose<" #PP ">", k_dwq_choose<PP>, g, b, 0, s, P.N1, P.N2, P.n1, P.form_rows,      \
-                (int)P.n_form_rows,                                                                              \
-                           P.fn_of, P.ecls, P.dwq_region);                                                       \
+                (int)P.n_form_rows, P.fn_of, P.ecls, P.dwq_region);                                              \
         break;
         CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
 #undef CASE

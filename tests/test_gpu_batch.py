@@ -121,3 +121,37 @@ def test_batch_degree_ends_and_element_gauss():
         b.status()
         for k, (g, r) in enumerate(zip(outs, ref)):
             assert np.array_equal(g, r), f"patch {k} (p = {plans[k].sizes['p']}), graph {use_graph}"
+
+
+def test_batch_with_dwq_plans():
+    """DWQ plans in a batch (Sect. 3.3): the side rules of every DWQ patch solved in one launch per
+    degree, the box parts added after the element-formed rows; eager and replayed, each patch equals
+    its one-patch formation bit for bit (degree 5 patches as DWQ as in the batched workload, plus
+    degrees 2 and 6 and a constant coefficient)."""
+    torch = require_gpu()
+    from paper_2101_08053_amd import igatrim
+    cfgs = wl.config4(n_patch=10, n_range=(8, 40), seed=wl.SEED_BASE + 45)
+    cfgs += wl.config4(n_patch=2, n_range=(10, 24), p_range=(6, 6), seed=wl.SEED_BASE + 46)
+    cfgs += wl.config4(n_patch=2, n_range=(10, 24), p_range=(2, 2), seed=wl.SEED_BASE + 47)
+    methods = [igatrim.DWQ if (c.p in (5, 6) or k >= len(cfgs) - 2) else igatrim.HYBRID_GAUSS
+               for k, c in enumerate(cfgs)]
+    plans = [igatrim.Plan(c, m) for c, m in zip(cfgs, methods)]
+    coeffs = [p.coeff() for p in plans]
+    coeffs[-1] = plans[-1].coeff(igatrim.COEF_CONST, 1.0)
+    say("[batch dwq] degrees", [c.p for c in cfgs], "methods", methods,
+        "dwq rows", [p.sizes["n_dwq_rows"] for p in plans])
+    assert any(p.sizes["n_dwq_rows"] > 0 for p in plans)
+    ref = _plain(plans, coeffs)
+    b = igatrim.Batch(plans, coeffs)
+    for use_graph in (False, True, True):
+        for o in b.outs:
+            o.fill_(np.nan)
+        outs = [o.cpu().numpy() for o in b.form(use_graph=use_graph)]
+        b.status()
+        for k, (g, r) in enumerate(zip(outs, ref)):
+            assert np.array_equal(g, r), f"patch {k} (p = {cfgs[k].p}, method {methods[k]}), graph {use_graph}"
+    ms = b.autotune()
+    outs = [o.cpu().numpy() for o in b.form(use_graph=True)]
+    b.status()
+    for g, r in zip(outs, ref):
+        assert np.array_equal(g, r)
