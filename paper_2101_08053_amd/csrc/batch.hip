@@ -229,11 +229,11 @@ __global__ void __launch_bounds__(Int2Cfg<P>::NT)
     interior_rows_block<P>(Bp.ia, it.unit - i2 * ntx, i2, S);
 }
 
-// Side rules of the batch's DWQ patches of degree P, one workgroup per
-// (direction, interior knot, side) slot: the uneven refined minimum-norm
-// solves of every patch in one launch.
+// Side rules of the batch's DWQ patches of degree P, one workgroup per group
+// of (direction, interior knot, side) slots, one quad of lanes per refined system:
+// the uneven refined minimum-norm solves of every patch in one launch.
 template <int P>
-__global__ void __launch_bounds__(128)
+__global__ void __launch_bounds__(kDwqSideThreads)
     k_batch_dwq_sides(const BatchPlan* __restrict__ plans, const BatchItem* __restrict__ items) {
     const BatchItem it = items[blockIdx.x];
     const BatchPlan& Bp = plans[__builtin_amdgcn_readfirstlane(it.plan)];
@@ -385,7 +385,7 @@ struct Batch {
             switch (g + 1) {
 #define CASE(PP)                                                                                 \
     case PP:                                                                                     \
-        hipLaunchKernelGGL(k_batch_dwq_sides<PP>, grid, dim3(128), 0, s, d_plans, it); \
+        hipLaunchKernelGGL(k_batch_dwq_sides<PP>, grid, dim3(kDwqSideThreads), 0, s, d_plans, it); \
         break;
                 CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6)
 #undef CASE
@@ -539,8 +539,8 @@ static iga_batch* batch_create(iga_plan* const* plans, int count, const iga_coef
         bp.gw = P.gauss_w;
         bp.status = P.status;
         if (P.method == IGA_DWQ) {
-            const int nslot = 2 * (P.N1 - 1) + 2 * (P.N2 - 1);
-            for (int u = 0; u < nslot; ++u) dwqs[P.p - 1].push_back(BatchItem{k, 0, u, 0});
+            const int nslot = 2 * (P.N1 - 1) + 2 * (P.N2 - 1), spw = dwq_side_spw(P.p);
+            for (int u = 0; u < (nslot + spw - 1) / spw; ++u) dwqs[P.p - 1].push_back(BatchItem{k, 0, u, 0});
             if (P.n_form_rows > 0) {
                 std::vector<int> reg(8 * (size_t)P.n_form_rows);
                 HIPX(hipMemcpy(reg.data(), P.dwq_region, sizeof(int) * reg.size(), hipMemcpyDeviceToHost));

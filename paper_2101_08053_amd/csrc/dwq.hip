@@ -6,7 +6,8 @@
 //    WQ points plus nested ones, placed round robin from t in the three
 //    equal gaps); t is inserted p times (Eq. (10)), the minimum-norm systems
 //    (5) of the p+1 refined functions touching that element are solved, one
-//    wavefront each, and w^_{.,i} = sum_r S[r][i] w~_{.,r}. Both sides are
+//    quad of lanes each (several slots per workgroup), and
+//    w^_{.,i} = sum_r S[r][i] w~_{.,r}. Both sides are
 //    built in the local coordinate u = |x - t|, so the low side is the
 //    mirror image of the high one.
 //  * k_dwq_choose: per cut row, the box R = I1 x I2 of inside elements of
@@ -20,8 +21,9 @@
 namespace iga {
 
 template <int P>
-__global__ void __launch_bounds__(128) k_dwq_sides(DirDev D1, DirDev D2, const double* __restrict__ gx,
-                                                   const double* __restrict__ gw, int* __restrict__ status) {
+__global__ void __launch_bounds__(kDwqSideThreads) k_dwq_sides(DirDev D1, DirDev D2, const double* __restrict__ gx,
+                                                               const double* __restrict__ gw,
+                                                               int* __restrict__ status) {
     dwq_sides_body<P>(D1, D2, gx, gw, status, blockIdx.x);
 }
 
@@ -118,9 +120,10 @@ __global__ void __launch_bounds__(256) k_dwq_rows(DwqRowArgs A) {
 // ------------------------------------------------------------ launchers
 void launch_dwq_sides(Plan& P, hipStream_t s) {
     if (P.method != IGA_DWQ) return;
-    const int nb = 2 * (P.dir[0].N - 1) + 2 * (P.dir[1].N - 1);
-    if (nb <= 0) return;
-    dim3 g(nb), b(128);
+    const int nslot = 2 * (P.dir[0].N - 1) + 2 * (P.dir[1].N - 1);
+    if (nslot <= 0) return;
+    const int spw = dwq_side_spw(P.p);
+    dim3 g((nslot + spw - 1) / spw), b(kDwqSideThreads);
     switch (P.p) {
 #define CASE(PP) \
     case PP: klaunch(P, "k_dwq_sides<" #PP ">", k_dwq_sides<PP>, g, b, 0, s, P.dir[0], P.dir[1], P.gauss_x, P.gauss_w, P.status); break;

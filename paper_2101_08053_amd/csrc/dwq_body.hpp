@@ -1,7 +1,7 @@
 // Device bodies of discontinuous weighted quadrature (Sect. 3.3, Eqs. (9)-(10)),
 // shared by the one-patch kernels (dwq.hip) and the batched launches
-// (batch.hip): the side rules of one (direction, interior knot, side) slot
-// and the box contribution of one element-formed row.
+// (batch.hip): the side rules of a group of (direction, interior knot, side)
+// slots and the box contribution of one element-formed row.
 #pragma once
 
 #include "plan.hpp"
@@ -17,37 +17,85 @@ struct DwqCfg {
 
 // One (direction, interior knot, side) slot per 128-thread workgroup: the
 // body of k_dwq_sides and of the batched side launches.
+// ------------------------------------------------ side rules, four lanes per system
+// For every (direction, interior knot t = bp[s], side) slot: the side's
+// first element gets p+1 points (the two WQ points plus nested ones, placed
+// round robin from t in the three equal gaps); t is inserted p times (Eq.
+// (10)) giving S with B_c = sum_r S[r][c] B~_r; the minimum-norm systems
+// (5) of the p+1 refined functions touching that element are solved, and
+// w^_{.,i} = sum_r S[r][i] w~_{.,r}. Both sides are built in the local
+// coordinate u = |x - t|, so the low side is the mirror image of the high
+// one.
+//
+// A workgroup of 256 threads takes SPW slots; each refined system (at most
+// 4p points x (2p+1) trial functions) is solved by a quad of lanes holding
+// its A^T row-distributed in registers (row k in lane k % 4), by Householder
+// QR with quad reductions (DPP moves inside the quad): the systems are far
+// too small to spread over a wavefront. The slot's points and refined knots
+// are found by one lane, S by p lanes, and the quads of a slot then combine
+// the refined solutions into the rules of its p local functions.
+template <int P>
+struct DwqQuadCfg {
+    static constexpr int KQ = 4 * P + 2;   // point capacity of a side list (output layout)
+    static constexpr int QS = 4 * P;       // points of one system at most
+    static constexpr int RPL = P;          // rows of A^T per lane (QS / 4)
+    static constexpr int NK = 3 * P + 2;   // local refined knots used
+    static constexpr int M = 2 * P + 1;    // trial functions of a refined system
+    static constexpr int SPW = 64 / (P + 1);  // slots per workgroup (64 quads)
+    static constexpr int NSYS = SPW * (P + 1);
+};
+__host__ __device__ constexpr int dwq_side_spw(int p) { return 64 / (p + 1); }
+constexpr int kDwqSideThreads = 256;
+
+// Sum over the quad (the same value in its four lanes).
+__device__ __forceinline__ double quad_sum(double v) {
+    v += dpp_move<0xB1>(v);  // lane ^ 1
+    v += dpp_move<0x4E>(v);  // lane ^ 2
+    return v;
+}
+// Lane j's value in every lane of the quad (j is a constant after unrolling: one DPP move).
+__device__ __forceinline__ double quad_bcast(double v, int j) {
+    switch (j & 3) {
+        case 0: return dpp_move<0x00>(v);
+        case 1: return dpp_move<0x55>(v);
+        case 2: return dpp_move<0xAA>(v);
+        default: return dpp_move<0xFF>(v);
+    }
+}
+
 template <int P>
 __device__ __forceinline__ void dwq_sides_body(const DirDev& D1, const DirDev& D2, const double* __restrict__ gx,
                                                const double* __restrict__ gw, int* __restrict__ status, int blk) {
-    using C = DwqCfg<P>;
-    constexpr int KQ = C::KQ, NK = C::NK, M = C::M;
-    __shared__ double sRK[NK];         // refined local knots: 0 (p+1 times), then the side's knots
-    __shared__ double sU[KQ];          // local coordinate of each point, local order
-    __shared__ int sEl[KQ];            // local element of each point
-    __shared__ double sX[KQ];          // coordinates, increasing x
-    __shared__ int sOel[KQ], sOk[KQ];  // element / WQ index (-1 nested), increasing x
-    __shared__ int sCnt[P + 2];        // points in local elements < k
-    __shared__ double sS[P + 1][P];    // B_c = sum_r S[r][c] B~_r on the side (local c)
-    __shared__ double sWt[P + 1][KQ];  // refined weights, local order
-    __shared__ int sInfo[3];
+    using C = DwqQuadCfg<P>;
+    constexpr int KQ = C::KQ, QS = C::QS, RPL = C::RPL, NK = C::NK, M = C::M, SPW = C::SPW, NSYS = C::NSYS;
+    __shared__ double sY[NSYS * QS];     // [system][k]: the minimum-norm solutions, local order
+    __shared__ double sRK[SPW][NK];      // refined local knots: 0 (p+1 times), then the side's knots
+    __shared__ double sU[SPW][QS];       // local coordinate of each point, local order
+    __shared__ int sEl[SPW][QS];         // local element of each point
+    __shared__ double sX[SPW][QS];       // coordinates, increasing x
+    __shared__ int sOel[SPW][QS], sOk[SPW][QS];
+    __shared__ int sCnt[SPW][P + 2];     // points in local elements < k
+    __shared__ double sS[SPW][P + 1][P]; // B_c = sum_r S[r][c] B~_r on the side (local c)
+    __shared__ int sInfo[SPW][3];
 
-    const int nslot1 = 2 * (D1.N - 1);
-    int slot = blk, d = 0;
+    const int tid = threadIdx.x, g = tid & 3, sys = tid >> 2;
+    const int sl = sys / (P + 1), r = sys - sl * (P + 1);
+    const int nslot1 = 2 * (D1.N - 1), nslot = nslot1 + 2 * (D2.N - 1);
+    const int gs = blk * SPW + sl;
+    const bool on = sys < NSYS && gs < nslot;
+    int slot = gs, d = 0;
     if (slot >= nslot1) {
         slot -= nslot1;
         d = 1;
     }
     const DirDev& D = d ? D2 : D1;
     const int N = D.N;
-    if (slot >= 2 * (N - 1)) return;
     const int s = slot / 2 + 1;
     const bool high = (slot & 1) != 0;
     const int nk = N + 2 * P + 1;
-    const double t = D.knots[P + s];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const double t = on ? D.knots[P + s] : 0.0;
 
-    if (tid == 0) {
+    if (on && r == 0 && g == 0) {  // the slot's points and refined knots
         const int nE = high ? N - s : s;
         const int nEl = min(nE, P + 1);
         const int nRK = high ? nk - s : s + 2 * P + 1;
@@ -57,9 +105,8 @@ __device__ __forceinline__ void dwq_sides_body(const DirDev& D1, const DirDev& D
                 const int kk = min(m, nRK - 1) - P - 1;
                 v = high ? D.knots[s + P + 1 + kk] - t : t - D.knots[s + P - 1 - kk];
             }
-            sRK[m] = v;
+            sRK[sl][m] = v;
         }
-        // points of the side's first nEl elements, increasing x
         int np = 0;
         const int e_lo = high ? s : s - nEl, e_hi = high ? s + nEl - 1 : s - 1, e_adj = high ? s : s - 1;
         for (int e = e_lo; e <= e_hi; ++e) {
@@ -69,45 +116,45 @@ __device__ __forceinline__ void dwq_sides_body(const DirDev& D1, const DirDev& D
             const int nadd = (e == e_adj) ? max(0, P + 1 - ne) : 0;
             if (nadd == 0) {
                 for (int j = 1; j <= ne; ++j) {
-                    sX[np] = a + (b - a) * j / (ne + 1);
-                    sOel[np] = e;
-                    sOk[np] = k0 + j - 1;
+                    sX[sl][np] = a + (b - a) * j / (ne + 1);
+                    sOel[sl][np] = e;
+                    sOk[sl][np] = k0 + j - 1;
                     ++np;
                 }
             } else {
                 const double E[4] = {a, a + (b - a) * 1 / 3, a + (b - a) * 2 / 3, b};
-                for (int g = 0; g < 3; ++g) {
-                    const int mg = high ? (nadd + 2 - g) / 3 : (nadd + g) / 3;
+                for (int gg = 0; gg < 3; ++gg) {
+                    const int mg = high ? (nadd + 2 - gg) / 3 : (nadd + gg) / 3;
                     for (int j = 1; j <= mg; ++j) {
-                        sX[np] = E[g] + (E[g + 1] - E[g]) * j / (mg + 1);
-                        sOel[np] = e;
-                        sOk[np] = -1;
+                        sX[sl][np] = E[gg] + (E[gg + 1] - E[gg]) * j / (mg + 1);
+                        sOel[sl][np] = e;
+                        sOk[sl][np] = -1;
                         ++np;
                     }
-                    if (g < 2) {
-                        sX[np] = E[g + 1];
-                        sOel[np] = e;
-                        sOk[np] = k0 + g;
+                    if (gg < 2) {
+                        sX[sl][np] = E[gg + 1];
+                        sOel[sl][np] = e;
+                        sOk[sl][np] = k0 + gg;
                         ++np;
                     }
                 }
             }
         }
-        for (int k = 0; k <= P + 1; ++k) sCnt[k] = 0;
+        for (int k = 0; k <= P + 1; ++k) sCnt[sl][k] = 0;
         for (int q = 0; q < np; ++q) {
             const int qo = high ? q : np - 1 - q;
-            sU[q] = high ? sX[qo] - t : t - sX[qo];
-            sEl[q] = high ? sOel[qo] - s : s - 1 - sOel[qo];
-            sCnt[sEl[q] + 1]++;
+            sU[sl][q] = high ? sX[sl][qo] - t : t - sX[sl][qo];
+            sEl[sl][q] = high ? sOel[sl][qo] - s : s - 1 - sOel[sl][qo];
+            sCnt[sl][sEl[sl][q] + 1]++;
         }
-        for (int k = 1; k <= P + 1; ++k) sCnt[k] += sCnt[k - 1];
-        sInfo[0] = np;
-        sInfo[1] = nRK - P - 1;  // refined functions on the side
-        sInfo[2] = nEl;
+        for (int k = 1; k <= P + 1; ++k) sCnt[sl][k] += sCnt[sl][k - 1];
+        sInfo[sl][0] = np;
+        sInfo[sl][1] = nRK - P - 1;  // refined functions on the side
+        sInfo[sl][2] = nEl;
     }
-    if (tid >= 64 && tid < 64 + P) {
-        // Eq. (10) p times on the local coarse knots, for the unit vector of local function c
-        const int c = tid - 64;
+    if (on && r < P && g == 1) {
+        // Eq. (10) p times on the local coarse knots, for the unit vector of local function c = r
+        const int c = r;
         double K[3 * P + 2], Pc[2 * P + 1], Qn[2 * P + 1];
         int L = 2 * P + 2, nf = P + 1;
         for (int m = 0; m < L; ++m) K[m] = high ? D.knots[s + m] - t : t - D.knots[s + 2 * P - m];
@@ -129,86 +176,199 @@ __device__ __forceinline__ void dwq_sides_body(const DirDev& D1, const DirDev& D
             ++L;
             ++nf;
         }
-        for (int r = 0; r <= P; ++r) sS[r][c] = Pc[P + r];
+        for (int rr = 0; rr <= P; ++rr) sS[sl][rr][c] = Pc[P + rr];
     }
     __syncthreads();
 
-    const int np = sInfo[0], n_fun = sInfo[1], nEl = sInfo[2];
-    // two wavefronts take the p+1 refined functions in turn (two-wavefront
-    // workgroups: four fit on a CU beside each other at this register count)
-#pragma unroll 1
-    for (int r = wave; r <= P; r += 2) {
-        if (r < n_fun) {
-            const int kr = min(r, nEl - 1);               // last local element of supp B~_r
-            const int q = sCnt[kr + 1];                   // its points
-            const int m = min(r + P, n_fun - 1) + 1;      // trial functions 0..m-1
-            double a[M], a0[M];
+    // ---- the quad's refined system: A[c][k] = B~_c(u_k), b[c] = int B~_c B~_r. Every lane
+    // runs it (the quad reductions need all lanes); quads without a system solve zeros.
+    const int np = on ? sInfo[sl][0] : 0, n_fun = on ? sInfo[sl][1] : 0, nEl = on ? sInfo[sl][2] : 1;
+    const bool solve = on && r < n_fun;
+    const int slc = on ? sl : 0;
+    const double* rk = sRK[slc];
+    const int kr = min(r, nEl - 1);                         // last local element of supp B~_r
+    const int q = solve ? sCnt[slc][kr + 1] : 0;            // its points
+    const int m = solve ? min(r + P, n_fun - 1) + 1 : 0;    // trial functions 0..m-1
+    // (register arrays take compile-time indices only, selected by comparison)
+    double A[RPL][M];
 #pragma unroll
-            for (int c = 0; c < M; ++c) a[c] = 0.0;
-            if (lane < q) {
-                const int k = sEl[lane];
-                double Nv[P + 1];
-                basis_eval<P>(sRK, P + k, sU[lane], Nv);
+    for (int i = 0; i < RPL; ++i) {
+        const int k = 4 * i + g;
+        double Nv[P + 1];
+        int el = 0;
+        if (k < q) {
+            el = sEl[slc][k];
+            basis_eval<P>(rk, P + el, sU[slc][k], Nv);
+        }
 #pragma unroll
-                for (int c = 0; c < M; ++c)
-                    if (c < m && c >= k && c <= k + P) a[c] = Nv[c - k];
-            }
+        for (int c = 0; c < M; ++c) {
+            double v = 0.0;
 #pragma unroll
-            for (int c = 0; c < M; ++c) a0[c] = a[c];
-            // moments int B~_c B~_r over the elements of supp B~_r, (p+1)-point Gauss
-            double mom[M];
-#pragma unroll
-            for (int c = 0; c < M; ++c) mom[c] = 0.0;
-            for (int pg = lane; pg < (kr + 1) * (P + 1); pg += 64) {
-                const int k = pg / (P + 1), g = pg % (P + 1);
-                const double ua = sRK[P + k], ub = sRK[P + k + 1];
-                const double xg = ua + (ub - ua) * (gx[gauss_off(P + 1) + g] + 1.0) * 0.5;
-                const double wgt = gw[gauss_off(P + 1) + g] * (ub - ua) * 0.5;
-                double Nv[P + 1];
-                basis_eval<P>(sRK, P + k, xg, Nv);
-                const double br = (r >= k && r <= k + P) ? Nv[r - k] : 0.0;
-#pragma unroll
-                for (int c = 0; c < M; ++c)
-                    if (c >= k && c <= k + P) mom[c] += wgt * Nv[c - k] * br;
-            }
-#pragma unroll
-            for (int c = 0; c < M; ++c) mom[c] = wave_sum(mom[c]);
-            bool singular = false;
-            const double y = wave_min_norm<M>(a, q, m, [&](int c) { return mom[c]; }, singular);
-            double rmax = 0.0, bmax = 0.0;
-#pragma unroll
-            for (int c = 0; c < M; ++c) {
-                if (c >= m) break;
-                const double rc = wave_sum(a0[c] * y);
-                rmax = fmax(rmax, fabs(rc - mom[c]));
-                bmax = fmax(bmax, fabs(mom[c]));
-            }
-            if (lane < KQ) sWt[r][lane] = y;
-            if (lane == 0 && (singular || !(rmax <= 1e-12 * bmax))) atomicExch(status, IGA_E_SINGULAR_WEIGHTS);
-        } else if (lane < KQ) {
-            sWt[r][lane] = 0.0;
+            for (int a = 0; a <= P; ++a) v = (k < q && c < m && c == el + a) ? Nv[a] : v;
+            A[i][c] = v;
         }
     }
+    // moments over the elements of supp B~_r, (p+1)-point Gauss, the points dealt to the quad's lanes
+    double mom[M];
+#pragma unroll
+    for (int c = 0; c < M; ++c) mom[c] = 0.0;
+    for (int pg = g; pg < (solve ? (kr + 1) * (P + 1) : 0); pg += 4) {
+        const int k = pg / (P + 1), gp = pg - k * (P + 1);
+        const double ua = rk[P + k], ub = rk[P + k + 1];
+        const double xg = ua + (ub - ua) * (gx[gauss_off(P + 1) + gp] + 1.0) * 0.5;
+        const double wgt = gw[gauss_off(P + 1) + gp] * (ub - ua) * 0.5;
+        double Nv[P + 1];
+        basis_eval<P>(rk, P + k, xg, Nv);
+        double br = 0.0;
+#pragma unroll
+        for (int a = 0; a <= P; ++a) br = (r == k + a) ? Nv[a] : br;
+#pragma unroll
+        for (int c = 0; c < M; ++c) {
+            double nc = 0.0;
+#pragma unroll
+            for (int a = 0; a <= P; ++a) nc = (c == k + a) ? Nv[a] : nc;
+            mom[c] += wgt * nc * br;
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < M; ++c) mom[c] = quad_sum(mom[c]);
+
+    // Householder QR of A^T (q x m): column c's reflector I - tau v v^T, v_c = 1 (implicit),
+    // v below the diagonal, R_cc on it; R^T z = b as the columns come
+    bool singular = false;
+    double tauv[M], z[M];
+#pragma unroll
+    for (int c = 0; c < M; ++c) {
+        tauv[c] = 0.0;
+        z[c] = 0.0;
+    }
+#pragma unroll
+    for (int c = 0; c < M; ++c) {
+        if (c < m) {
+            double part = 0.0;
+#pragma unroll
+            for (int i = 0; i < RPL; ++i) {
+                const int k = 4 * i + g;
+                part += (k >= c && k < q) ? A[i][c] * A[i][c] : 0.0;
+            }
+            const double nrm2 = quad_sum(part);
+            const double xc = quad_bcast(A[c >> 2][c], c);
+            double alpha = 0.0, tau = 0.0, inv = 0.0;
+            if (nrm2 > 0.0) {
+                alpha = (xc >= 0.0) ? -sqrt(nrm2) : sqrt(nrm2);
+                const double uc = xc - alpha;
+                tau = -uc / alpha;
+                inv = 1.0 / uc;
+            } else {
+                singular = true;
+            }
+            double vv[RPL];
+#pragma unroll
+            for (int i = 0; i < RPL; ++i) {
+                const int k = 4 * i + g;
+                vv[i] = (k == c) ? 1.0 : ((k > c && k < q) ? A[i][c] * inv : 0.0);
+                A[i][c] = (k == c) ? alpha : ((k > c && k < q) ? vv[i] : A[i][c]);
+            }
+            tauv[c] = tau;
+#pragma unroll
+            for (int c2 = c + 1; c2 < M; ++c2) {
+                if (c2 < m) {
+                    double dp = 0.0;
+#pragma unroll
+                    for (int i = 0; i < RPL; ++i) dp += vv[i] * A[i][c2];
+                    const double f = tau * quad_sum(dp);
+#pragma unroll
+                    for (int i = 0; i < RPL; ++i) A[i][c2] -= f * vv[i];
+                }
+            }
+            // z_c = (b_c - sum_{i<c} R_ic z_i) / R_cc
+            double acc = mom[c];
+#pragma unroll
+            for (int i = 0; i < c; ++i) acc -= quad_bcast(A[i >> 2][c], i) * z[i];
+            z[c] = (alpha != 0.0) ? acc / alpha : 0.0;
+        }
+    }
+    // y = Q [z; 0]: the reflectors applied last to first (row k = 4 i + g in this lane)
+    double y[RPL];
+#pragma unroll
+    for (int i = 0; i < RPL; ++i) {
+        double v = 0.0;
+#pragma unroll
+        for (int gg = 0; gg < 4; ++gg)
+            if (4 * i + gg < M) v = (g == gg) ? z[(4 * i + gg < M) ? 4 * i + gg : 0] : v;
+        y[i] = v;
+    }
+#pragma unroll
+    for (int j = M - 1; j >= 0; --j) {
+        if (j < m) {
+            double vv[RPL], dp = 0.0;
+#pragma unroll
+            for (int i = 0; i < RPL; ++i) {
+                const int k = 4 * i + g;
+                vv[i] = (k == j) ? 1.0 : ((k > j && k < q) ? A[i][j] : 0.0);
+                dp += vv[i] * y[i];
+            }
+            const double f = tauv[j] * quad_sum(dp);
+#pragma unroll
+            for (int i = 0; i < RPL; ++i) y[i] -= f * vv[i];
+        }
+    }
+    // residual of the moment equations, A rebuilt at the lane's points
+    double res[M];
+#pragma unroll
+    for (int c = 0; c < M; ++c) res[c] = 0.0;
+#pragma unroll
+    for (int i = 0; i < RPL; ++i) {
+        const int k = 4 * i + g;
+        if (k < q) {
+            const int el = sEl[slc][k];
+            double Nv[P + 1];
+            basis_eval<P>(rk, P + el, sU[slc][k], Nv);
+#pragma unroll
+            for (int c = 0; c < M; ++c) {
+                double nc = 0.0;
+#pragma unroll
+                for (int a = 0; a <= P; ++a) nc = (c == el + a) ? Nv[a] : nc;
+                res[c] += nc * y[i];
+            }
+        }
+    }
+    double rmax = 0.0, bmax = 0.0;
+#pragma unroll
+    for (int c = 0; c < M; ++c) {
+        const double rc = quad_sum(res[c]);
+        if (c < m) {
+            rmax = fmax(rmax, fabs(rc - mom[c]));
+            bmax = fmax(bmax, fabs(mom[c]));
+        }
+    }
+    if (solve && g == 0 && (singular || !(rmax <= 1e-12 * bmax))) atomicExch(status, IGA_E_SINGULAR_WEIGHTS);
+    if (sys < NSYS) {
+#pragma unroll
+        for (int i = 0; i < RPL; ++i) sY[sys * QS + 4 * i + g] = solve ? y[i] : 0.0;
+    }
     __syncthreads();
 
-    const int gslot = slot;
+    // ---- the slot's p rules on its points (lanes of the slot's quads), and its point list
+    if (!on) return;
+    const int sys0 = sl * (P + 1), lane_in = tid - 4 * sys0, nlane = 4 * (P + 1);
     const int nr = min(P + 1, n_fun);
-    for (int tt = tid; tt < P * KQ; tt += blockDim.x) {
-        const int ii = tt / KQ, qo = tt % KQ;  // function s + ii, point qo (increasing x)
+    for (int o = lane_in; o < P * KQ; o += nlane) {
+        const int ii = o / KQ, qo = o - ii * KQ;
+        const int c = high ? ii : P - 1 - ii;
         double v = 0.0;
         if (qo < np) {
             const int ql = high ? qo : np - 1 - qo;
-            const int c = high ? ii : P - 1 - ii;
-            for (int rr = 0; rr < nr; ++rr) v += sS[rr][c] * sWt[rr][ql];
+            for (int rr = 0; rr < nr; ++rr) v += sS[sl][rr][c] * sY[(sys0 + rr) * QS + ql];
         }
-        D.dq_w[((size_t)gslot * P + ii) * KQ + qo] = v;
+        D.dq_w[((size_t)slot * P + ii) * KQ + qo] = v;
     }
-    for (int qo = tid; qo < KQ; qo += blockDim.x) {
-        D.dq_x[(size_t)gslot * KQ + qo] = (qo < np) ? sX[qo] : 0.0;
-        D.dq_el[(size_t)gslot * KQ + qo] = (qo < np) ? sOel[qo] : -1;
-        D.dq_k[(size_t)gslot * KQ + qo] = (qo < np) ? sOk[qo] : -1;
+    for (int qo = lane_in; qo < KQ; qo += nlane) {
+        D.dq_x[(size_t)slot * KQ + qo] = (qo < np) ? sX[sl][qo] : 0.0;
+        D.dq_el[(size_t)slot * KQ + qo] = (qo < np) ? sOel[sl][qo] : -1;
+        D.dq_k[(size_t)slot * KQ + qo] = (qo < np) ? sOk[sl][qo] : -1;
     }
-    if (tid == 0) D.dq_n[gslot] = np;
+    if (lane_in == 0) D.dq_n[slot] = np;
 }
 
 // ------------------------------------------------------------ box rows
