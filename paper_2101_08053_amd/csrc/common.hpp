@@ -285,6 +285,112 @@ __device__ __forceinline__ int wave_sum_i(int v) {
            (__builtin_amdgcn_readlane(v, 32) + __builtin_amdgcn_readlane(v, 48));
 }
 
+// -------------------------------------------------------------------------
+// Minimum 2-norm solution of a small under-determined system A w = b on one
+// quad of lanes (four lanes per system, sixteen systems per wavefront): row
+// k of A^T (point k) sits in lane k % 4 of the quad as A[k / 4][0..m), the
+// quad's lanes hold b (for c < m) alike. Householder QR of A^T (q x m) with
+// reductions inside the quad (DPP moves), R^T z = b solved as the columns
+// come, y = Q [z; 0]. On return y[i] is the weight of point 4 i + (lane % 4)
+// (0 past q); A holds R and the reflectors; singular is set if a pivot
+// vanishes (the caller checks the residual). Every lane of the quad must run
+// it (quads may differ in q and m).
+__device__ __forceinline__ double quad_sum(double v) {
+    v += dpp_move<0xB1>(v);  // lane ^ 1
+    v += dpp_move<0x4E>(v);  // lane ^ 2
+    return v;
+}
+// Lane j's value in every lane of the quad (j is a constant after unrolling: one DPP move).
+__device__ __forceinline__ double quad_bcast(double v, int j) {
+    switch (j & 3) {
+        case 0: return dpp_move<0x00>(v);
+        case 1: return dpp_move<0x55>(v);
+        case 2: return dpp_move<0xAA>(v);
+        default: return dpp_move<0xFF>(v);
+    }
+}
+
+template <int M, int RPL>
+__device__ __forceinline__ void quad_min_norm(double (&A)[RPL][M], int q, int m, const double (&b)[M],
+                                              double (&y)[RPL], bool& singular) {
+    const int g = threadIdx.x & 3;
+    double tauv[M], z[M];
+#pragma unroll
+    for (int c = 0; c < M; ++c) {
+        tauv[c] = 0.0;
+        z[c] = 0.0;
+    }
+#pragma unroll
+    for (int c = 0; c < M; ++c) {
+        if (c < m) {
+            double part = 0.0;
+#pragma unroll
+            for (int i = 0; i < RPL; ++i) {
+                const int k = 4 * i + g;
+                part += (k >= c && k < q) ? A[i][c] * A[i][c] : 0.0;
+            }
+            const double nrm2 = quad_sum(part);
+            const double xc = quad_bcast(A[c >> 2][c], c);
+            double alpha = 0.0, tau = 0.0, inv = 0.0;
+            if (nrm2 > 0.0) {
+                alpha = (xc >= 0.0) ? -sqrt(nrm2) : sqrt(nrm2);
+                const double uc = xc - alpha;
+                tau = -uc / alpha;
+                inv = 1.0 / uc;
+            } else {
+                singular = true;
+            }
+            double vv[RPL];
+#pragma unroll
+            for (int i = 0; i < RPL; ++i) {
+                const int k = 4 * i + g;
+                vv[i] = (k == c) ? 1.0 : ((k > c && k < q) ? A[i][c] * inv : 0.0);
+                A[i][c] = (k == c) ? alpha : ((k > c && k < q) ? vv[i] : A[i][c]);
+            }
+            tauv[c] = tau;
+#pragma unroll
+            for (int c2 = c + 1; c2 < M; ++c2) {
+                if (c2 < m) {
+                    double dp = 0.0;
+#pragma unroll
+                    for (int i = 0; i < RPL; ++i) dp += vv[i] * A[i][c2];
+                    const double f = tau * quad_sum(dp);
+#pragma unroll
+                    for (int i = 0; i < RPL; ++i) A[i][c2] -= f * vv[i];
+                }
+            }
+            // z_c = (b_c - sum_{i<c} R_ic z_i) / R_cc
+            double acc = b[c];
+#pragma unroll
+            for (int i = 0; i < c; ++i) acc -= quad_bcast(A[i >> 2][c], i) * z[i];
+            z[c] = (alpha != 0.0) ? acc / alpha : 0.0;
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < RPL; ++i) {
+        double v = 0.0;
+#pragma unroll
+        for (int gg = 0; gg < 4; ++gg)
+            if (4 * i + gg < M) v = (g == gg) ? z[(4 * i + gg < M) ? 4 * i + gg : 0] : v;
+        y[i] = v;
+    }
+#pragma unroll
+    for (int j = M - 1; j >= 0; --j) {
+        if (j < m) {
+            double vv[RPL], dp = 0.0;
+#pragma unroll
+            for (int i = 0; i < RPL; ++i) {
+                const int k = 4 * i + g;
+                vv[i] = (k == j) ? 1.0 : ((k > j && k < q) ? A[i][j] : 0.0);
+                dp += vv[i] * y[i];
+            }
+            const double f = tauv[j] * quad_sum(dp);
+#pragma unroll
+            for (int i = 0; i < RPL; ++i) y[i] -= f * vv[i];
+        }
+    }
+}
+
 template <int M, typename BCol>
 __device__ __forceinline__ double wave_min_norm(double (&a)[M], int q, int m, BCol bcol, bool& singular) {
     const int lane = threadIdx.x & 63;

@@ -47,22 +47,6 @@ struct DwqQuadCfg {
 __host__ __device__ constexpr int dwq_side_spw(int p) { return 64 / (p + 1); }
 constexpr int kDwqSideThreads = 256;
 
-// Sum over the quad (the same value in its four lanes).
-__device__ __forceinline__ double quad_sum(double v) {
-    v += dpp_move<0xB1>(v);  // lane ^ 1
-    v += dpp_move<0x4E>(v);  // lane ^ 2
-    return v;
-}
-// Lane j's value in every lane of the quad (j is a constant after unrolling: one DPP move).
-__device__ __forceinline__ double quad_bcast(double v, int j) {
-    switch (j & 3) {
-        case 0: return dpp_move<0x00>(v);
-        case 1: return dpp_move<0x55>(v);
-        case 2: return dpp_move<0xAA>(v);
-        default: return dpp_move<0xFF>(v);
-    }
-}
-
 template <int P>
 __device__ __forceinline__ void dwq_sides_body(const DirDev& D1, const DirDev& D2, const double* __restrict__ gx,
                                                const double* __restrict__ gw, int* __restrict__ status, int blk) {
@@ -233,86 +217,9 @@ __device__ __forceinline__ void dwq_sides_body(const DirDev& D1, const DirDev& D
 #pragma unroll
     for (int c = 0; c < M; ++c) mom[c] = quad_sum(mom[c]);
 
-    // Householder QR of A^T (q x m): column c's reflector I - tau v v^T, v_c = 1 (implicit),
-    // v below the diagonal, R_cc on it; R^T z = b as the columns come
     bool singular = false;
-    double tauv[M], z[M];
-#pragma unroll
-    for (int c = 0; c < M; ++c) {
-        tauv[c] = 0.0;
-        z[c] = 0.0;
-    }
-#pragma unroll
-    for (int c = 0; c < M; ++c) {
-        if (c < m) {
-            double part = 0.0;
-#pragma unroll
-            for (int i = 0; i < RPL; ++i) {
-                const int k = 4 * i + g;
-                part += (k >= c && k < q) ? A[i][c] * A[i][c] : 0.0;
-            }
-            const double nrm2 = quad_sum(part);
-            const double xc = quad_bcast(A[c >> 2][c], c);
-            double alpha = 0.0, tau = 0.0, inv = 0.0;
-            if (nrm2 > 0.0) {
-                alpha = (xc >= 0.0) ? -sqrt(nrm2) : sqrt(nrm2);
-                const double uc = xc - alpha;
-                tau = -uc / alpha;
-                inv = 1.0 / uc;
-            } else {
-                singular = true;
-            }
-            double vv[RPL];
-#pragma unroll
-            for (int i = 0; i < RPL; ++i) {
-                const int k = 4 * i + g;
-                vv[i] = (k == c) ? 1.0 : ((k > c && k < q) ? A[i][c] * inv : 0.0);
-                A[i][c] = (k == c) ? alpha : ((k > c && k < q) ? vv[i] : A[i][c]);
-            }
-            tauv[c] = tau;
-#pragma unroll
-            for (int c2 = c + 1; c2 < M; ++c2) {
-                if (c2 < m) {
-                    double dp = 0.0;
-#pragma unroll
-                    for (int i = 0; i < RPL; ++i) dp += vv[i] * A[i][c2];
-                    const double f = tau * quad_sum(dp);
-#pragma unroll
-                    for (int i = 0; i < RPL; ++i) A[i][c2] -= f * vv[i];
-                }
-            }
-            // z_c = (b_c - sum_{i<c} R_ic z_i) / R_cc
-            double acc = mom[c];
-#pragma unroll
-            for (int i = 0; i < c; ++i) acc -= quad_bcast(A[i >> 2][c], i) * z[i];
-            z[c] = (alpha != 0.0) ? acc / alpha : 0.0;
-        }
-    }
-    // y = Q [z; 0]: the reflectors applied last to first (row k = 4 i + g in this lane)
     double y[RPL];
-#pragma unroll
-    for (int i = 0; i < RPL; ++i) {
-        double v = 0.0;
-#pragma unroll
-        for (int gg = 0; gg < 4; ++gg)
-            if (4 * i + gg < M) v = (g == gg) ? z[(4 * i + gg < M) ? 4 * i + gg : 0] : v;
-        y[i] = v;
-    }
-#pragma unroll
-    for (int j = M - 1; j >= 0; --j) {
-        if (j < m) {
-            double vv[RPL], dp = 0.0;
-#pragma unroll
-            for (int i = 0; i < RPL; ++i) {
-                const int k = 4 * i + g;
-                vv[i] = (k == j) ? 1.0 : ((k > j && k < q) ? A[i][j] : 0.0);
-                dp += vv[i] * y[i];
-            }
-            const double f = tauv[j] * quad_sum(dp);
-#pragma unroll
-            for (int i = 0; i < RPL; ++i) y[i] -= f * vv[i];
-        }
-    }
+    quad_min_norm<M, RPL>(A, q, m, mom, y, singular);
     // residual of the moment equations, A rebuilt at the lane's points
     double res[M];
 #pragma unroll
