@@ -452,10 +452,19 @@ static void launch_wq_adjoint(Plan& Pl, const MfArgs& A, const double* u, const 
 // The forward product with its three intermediate arrays given: V [n2][Q1],
 // H [Q2][n1], Ue [n_band + n_cut][(p+1)^2]. Every entry of them is written
 // before it is read, so they need no clearing.
+// The element part (element vectors, then the rows formed element-wise) runs
+// on the plan's second stream beside the weighted-quadrature part: the two
+// write disjoint rows of y.
 static void mf_apply_into(Plan& P, const double* c, const double* u, double* y, double* V, double* H, double* Ue,
                           hipStream_t s) {
     MfArgs A = mf_args(P, c);
     int n = (int)P.n_act;
+    HIPX(hipEventRecord(P.ev_mf_fork, s));
+    HIPX(hipStreamWaitEvent(P.aux, P.ev_mf_fork, 0));
+    launch_elem(P, A, u, nullptr, Ue, nullptr, P.aux);
+    hipLaunchKernelGGL(k_mf_gather, dim3((n + 255) / 256), dim3(256), 0, P.aux, A, (const double*)Ue,
+                       (const double*)nullptr, y, 0);
+    HIPX(hipEventRecord(P.ev_mf_join, P.aux));
     if (P.method != IGA_GAUSS_REF) {
         switch (P.p) {
 #define CASE(PP) \
@@ -464,9 +473,7 @@ static void mf_apply_into(Plan& P, const double* c, const double* u, double* y, 
 #undef CASE
         }
     }
-    launch_elem(P, A, u, nullptr, Ue, nullptr, s);
-    hipLaunchKernelGGL(k_mf_gather, dim3((n + 255) / 256), dim3(256), 0, s, A, (const double*)Ue,
-                       (const double*)nullptr, y, 0);
+    HIPX(hipStreamWaitEvent(s, P.ev_mf_join, 0));
 }
 
 void mf_apply(Plan& P, const double* c, const double* u, double* y, hipStream_t s) {
@@ -533,6 +540,12 @@ void mf_adjoint(Plan& P, const double* c, const double* u, const double* r, doub
     mf_buffers(P);
     MfArgs A = mf_args(P, c);
     int n = (int)P.n_act;
+    // the element vectors (and dc at band Gauss points and cut nodes) on the second stream,
+    // beside the grid part; the gather needs both
+    HIPX(hipEventRecord(P.ev_mf_fork, s));
+    HIPX(hipStreamWaitEvent(P.aux, P.ev_mf_fork, 0));
+    launch_elem(P, A, u, r, P.sw.Ue, dc, P.aux);
+    HIPX(hipEventRecord(P.ev_mf_join, P.aux));
     if (P.method != IGA_GAUSS_REF) {
         switch (P.p) {
 #define CASE(PP) \
@@ -543,7 +556,7 @@ void mf_adjoint(Plan& P, const double* c, const double* u, const double* r, doub
     } else {
         HIPX(hipMemsetAsync(dc, 0, sizeof(double) * (size_t)A.nq, s));
     }
-    launch_elem(P, A, u, r, P.sw.Ue, dc, s);
+    HIPX(hipStreamWaitEvent(s, P.ev_mf_join, 0));
     // the grid part of du reads D (held in H) through the CR argument
     hipLaunchKernelGGL(k_mf_gather, dim3((n + 255) / 256), dim3(256), 0, s, A, (const double*)P.sw.Ue,
                        (const double*)P.sw.H, du, 1);
