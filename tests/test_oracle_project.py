@@ -64,11 +64,46 @@ def test_reference_and_hybrid_rhs_agree_for_splines():
 
     bh = project.rhs(o, g, "hybrid")
     br = project.rhs(o, g, "reference")
+    bd = project.rhs(o, g, "dwq")
     # M over all functions (exterior included) applied to the coefficients
     ref = o.gauss_reference().toarray() @ coeffs[o.ts.active]
     # exterior functions vanish on the visible domain, so dropping them changes nothing
     np.testing.assert_allclose(br, ref, rtol=0, atol=1e-14)
     np.testing.assert_allclose(bh, ref, rtol=0, atol=1e-14)
+    # the refined weights integrate B_i B_j exactly on their box (Sect. 3.3), hence any spline g
+    np.testing.assert_allclose(bd, ref, rtol=0, atol=1e-13)
+
+
+@pytest.mark.parametrize("cfg", [wl.table1_line(3), wl.config1(N=12), wl.config3(N=14, p=4)],
+                         ids=lambda c: c.name)
+def test_dwq_rhs_boxes_and_polynomial_reproduction(cfg):
+    """DWQ matrix and right-hand side: g in Q_p is reproduced (identity map, c = 1, Sect. 4.2)."""
+    cfg.geom_cp = None
+    o = _const(cfg)
+    p = cfg.p
+    n_box = sum(o.dwq_region(int(f) % o.ts.n1, int(f) // o.ts.n1) is not None for f in o.cut_rows_flat())
+    assert n_box > 0   # some cut rows do take their box part from the refined weights
+
+    def g(x, y):
+        return x ** p * y ** (p - 1) - 0.5 * x * y ** p + 0.25
+
+    u = project.solve(o.dwq(), project.rhs(o, g, "dwq"))
+    assert project.l2_error(o, u, g) < 1e-10
+
+
+def test_dwq_rhs_of_one_is_the_row_sum():
+    """g = 1: b_i = sum_j M_ij of the DWQ matrix (the B_j sum to one on the visible domain), mapped
+    geometry with c = |det J| evaluated at the nested points."""
+    cfg = wl.config2(N=12, p=3)
+    o = Oracle(cfg)
+    b = project.rhs(o, lambda x, y: np.ones_like(x), "dwq")
+    Sb = project.rhs(o, lambda x, y: np.ones_like(x), "dwq", absolute=True)
+    rows = np.asarray(o.dwq().sum(axis=1)).ravel()
+    assert np.abs(b - rows).max() <= 1e-13 * Sb.max()
+    # the cut rows differ from the hybrid rule's (the boxes change their quadrature)
+    bh = project.rhs(o, lambda x, y: np.ones_like(x), "hybrid")
+    cut = o.ts.act_of[np.asarray(o.cut_rows_flat())]
+    assert np.abs(b[cut] - bh[cut]).max() > 1e-12 * Sb.max()
 
 
 @pytest.mark.parametrize("cfg", [wl.config1(N=10), wl.config5(N=12)], ids=lambda c: c.name)
