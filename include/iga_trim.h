@@ -207,13 +207,22 @@ int iga_status_get(iga_plan* plan, void* stream);
 /* L2 projection (Sect. 4.2): b_i by row i's own rule applied to g c, then
  * Jacobi-preconditioned CG on A = (M + M^T)/2 (M from iga_trim_mass_form
  * with the same c) until ||b - A u|| <= rtol ||b|| or maxit iterations.
- * u (device, n_act) is caller owned and used as the start vector.
- * Synchronous: returns after the solve. Returns IGA_E_NOCONV (with u the
- * last iterate and info filled) when the tolerance was not reached. */
+ * Row rules: weighted quadrature for interior rows; element Gauss and the
+ * cut rule for rows formed element-wise; with IGA_DWQ, a cut row with a box
+ * takes the box part from its discontinuous weights at the box's tensor
+ * points (Sect. 3.3) and the rest of its support element-wise, as its matrix
+ * row does. Methods IGA_HYBRID_GAUSS, IGA_DWQ and IGA_GAUSS_REF
+ * (IGA_E_UNSUPPORTED otherwise); IGA_DWQ also needs g and c away from the
+ * plan's rule points, so IGA_TARGET_AT_POINTS and IGA_COEF_AT_POINTS are
+ * IGA_E_UNSUPPORTED there. u (device, n_act) is caller owned and used as the
+ * start vector. Synchronous: returns after the solve. Returns IGA_E_NOCONV
+ * (with u the last iterate and info filled) when the tolerance was not
+ * reached. */
 int iga_trim_l2_project(iga_plan* plan, const iga_coeff* c, const double* vals, const iga_target* g,
                         double rtol, int32_t maxit, double* u, iga_solve_info* info, void* stream);
 
-/* Right-hand side alone: b (device, n_act) = row rules applied to g c. */
+/* Right-hand side alone: b (device, n_act) = row rules applied to g c (the
+ * rules and the errors of iga_trim_l2_project). Asynchronous on stream. */
 int iga_trim_rhs(iga_plan* plan, const iga_coeff* c, const iga_target* g, double* b, void* stream);
 
 /* Matrix-free product y = M(c) u of Eq. (7) -- the weighted-quadrature rows
@@ -312,7 +321,8 @@ int iga_batch_status(iga_batch* batch, void* stream);
  * (device, n_act_k doubles, caller owned) is the start vector and receives
  * the solution; infos (host, count entries, may be NULL) receives each
  * patch's iterations, convergence flag and relative residual. Degrees up to
- * 6, hybrid Gauss or element Gauss plans. The first call takes device memory
+ * 6; hybrid Gauss, DWQ or element Gauss plans, with the right-hand side rules
+ * and restrictions of iga_trim_l2_project. The first call takes device memory
  * for the batch's symmetrised bands and vectors (kept until the batch is
  * destroyed). Synchronous. IGA_E_NOCONV if some patch did not converge
  * within maxit (its u is the last iterate). */

@@ -40,6 +40,7 @@ struct BsPatch {
     GcArgs gc;             // g c of the patch; out = its slice of the concatenated values
     RhsElemArgs ea;        // element vectors; F = its slice
     RhsGatherArgs ga;      // element-formed rows; F, b = its slices
+    DwqRhsArgs dq;         // DWQ plans: box parts of the element-formed rows (set per call)
     CoefArgs co;           // |det J| at every rule point (GEOM_DETJ patches)
     int64_t n_pts;         // rule points
     int detj;              // 1: c = |det J| (recomputed at every rule point first)
@@ -59,6 +60,8 @@ struct BatchSolve {
     int elem_off[kBsMaxP] = {}, elem_n[kBsMaxP] = {};
     BsItem* d_coef = nullptr;   // |det J| point chunks (kRedThreads points), grouped by degree
     int coef_off[kBsMaxP] = {}, coef_n[kBsMaxP] = {};
+    BsItem* d_dwq = nullptr;    // element-formed rows of DWQ plans, grouped by degree
+    int dwq_off[kBsMaxP] = {}, dwq_n[kBsMaxP] = {};
     int rows = 0;               // concatenated (padded) rows
     double *b = nullptr, *r = nullptr, *z = nullptr, *pv = nullptr, *q = nullptr;
     double *part0 = nullptr, *part1 = nullptr, *part2 = nullptr;  // init (3/blk), p.q (1/blk), update (2/blk)
@@ -128,6 +131,13 @@ __global__ void __launch_bounds__(kRedThreads) k_bs_gather(const BsPatch* __rest
     const BsPatch& B = bs_patch(P, seg, k);
     const int t = (blockIdx.x - B.seg0[SEG_GATHER]) * kRedThreads + threadIdx.x;
     if (t < B.ga.n_rows) rhs_gather_row(B.ga, t);
+}
+
+template <int DEG>
+__global__ void __launch_bounds__(kDwqRhsThreads) k_bs_rhs_dwq(const BsPatch* __restrict__ P,
+                                                               const BsItem* __restrict__ items) {
+    const BsItem it = items[blockIdx.x];
+    dwq_rhs_body<DEG>(P[__builtin_amdgcn_readfirstlane(it.patch)].dq, it.unit);
 }
 
 // (M + M^T)/2 and the compact column of every band entry.
@@ -243,15 +253,15 @@ static BatchSolve* bs_create(const BatchView& V) {
         bs->n = V.n;
         bs->hp.resize(V.n);
         std::vector<int> segtab[SEG_N];
-        std::vector<BsItem> elems[kBsMaxP], coefs[kBsMaxP];
+        std::vector<BsItem> elems[kBsMaxP], coefs[kBsMaxP], dwqs[kBsMaxP];
         int64_t ent = 0, pts = 0, fel = 0;
         std::vector<int64_t> ent0(V.n), pts0(V.n), fel0(V.n);  // offsets into the concatenated buffers
         int rows = 0;
         for (int k = 0; k < V.n; ++k) {
             Plan& P = *V.plans[k];
             IGA_REQUIRE(P.p <= kBsMaxP, IGA_E_UNSUPPORTED, "batched projection handles degrees up to 6");
-            IGA_REQUIRE(P.method == IGA_HYBRID_GAUSS || P.method == IGA_GAUSS_REF, IGA_E_UNSUPPORTED,
-                        "batched projection handles hybrid Gauss and element Gauss plans");
+            IGA_REQUIRE(P.method == IGA_HYBRID_GAUSS || P.method == IGA_GAUSS_REF || P.method == IGA_DWQ,
+                        IGA_E_UNSUPPORTED, "batched projection handles hybrid Gauss, DWQ and element Gauss plans");
             BsPatch& B = bs->hp[k];
             const int W = 2 * P.p + 1, L = (P.p + 1) * (P.p + 1);
             B.S = SpArgs{P.p, P.n1, P.n2, (int)P.n_act, P.fn_of, P.act_of, nullptr, nullptr};
@@ -284,6 +294,8 @@ static BatchSolve* bs_create(const BatchView& V) {
             fel += (int64_t)std::max(1, nre) * L;
             if (B.detj)
                 for (int u = 0; u < cdiv(P.n_points, kRedThreads); ++u) coefs[P.p - 1].push_back(BsItem{k, u});
+            if (P.method == IGA_DWQ)
+                for (int u = 0; u < (int)P.n_form_rows; ++u) dwqs[P.p - 1].push_back(BsItem{k, u});
         }
         bs->rows = rows;
         const int nblk = rows / kRedThreads;
@@ -319,8 +331,11 @@ static BatchSolve* bs_create(const BatchView& V) {
                 HIPX(hipMemcpy(bs->d_seg[sgi], segtab[sgi].data(), sizeof(int) * segtab[sgi].size(),
                                hipMemcpyHostToDevice));
         }
-        std::vector<BsItem> e_all, c_all;
+        std::vector<BsItem> e_all, c_all, d_all;
         for (int g = 0; g < kBsMaxP; ++g) {
+            bs->dwq_off[g] = (int)d_all.size();
+            bs->dwq_n[g] = (int)dwqs[g].size();
+            d_all.insert(d_all.end(), dwqs[g].begin(), dwqs[g].end());
             bs->elem_off[g] = (int)e_all.size();
             bs->elem_n[g] = (int)elems[g].size();
             e_all.insert(e_all.end(), elems[g].begin(), elems[g].end());
@@ -330,6 +345,9 @@ static BatchSolve* bs_create(const BatchView& V) {
         }
         bs->d_elem = bs->alloc<BsItem>(e_all.size());
         bs->d_coef = bs->alloc<BsItem>(c_all.size());
+        bs->d_dwq = bs->alloc<BsItem>(d_all.size());
+        if (!d_all.empty())
+            HIPX(hipMemcpy(bs->d_dwq, d_all.data(), sizeof(BsItem) * d_all.size(), hipMemcpyHostToDevice));
         if (!e_all.empty())
             HIPX(hipMemcpy(bs->d_elem, e_all.data(), sizeof(BsItem) * e_all.size(), hipMemcpyHostToDevice));
         if (!c_all.empty())
@@ -349,6 +367,7 @@ static void bs_prepare(BatchSolve& bs, const BatchView& V, const iga_target* gs,
         BsPatch& B = bs.hp[k];
         double* out = B.gc.out;
         B.gc = gc_args(*V.plans[k], V.coeffs[k], gs[k], out);
+        if (V.plans[k]->method == IGA_DWQ) B.dq = dwq_rhs_args(*V.plans[k], V.coeffs[k], gs[k], out, B.ga.b);
         B.u = u[k];
     }
     HIPX(hipMemcpyAsync(bs.d_p, bs.hp.data(), sizeof(BsPatch) * V.n, hipMemcpyHostToDevice, s));
@@ -381,6 +400,18 @@ static void bs_prepare(BatchSolve& bs, const BatchView& V, const iga_target* gs,
     }
     if (bs.seg_n[SEG_GATHER])
         hipLaunchKernelGGL(k_bs_gather, dim3(bs.seg_n[SEG_GATHER]), blk, 0, s, bs.d_p, bs.d_seg[SEG_GATHER]);
+    for (int g = 0; g < kBsMaxP; ++g) {   // DWQ box parts, added after the gather
+        if (bs.dwq_n[g] == 0) continue;
+        const BsItem* it = bs.d_dwq + bs.dwq_off[g];
+        const dim3 grid((unsigned)bs.dwq_n[g]);
+        switch (g + 1) {
+#define CASE(PP) \
+    case PP: hipLaunchKernelGGL(k_bs_rhs_dwq<PP>, grid, dim3(kDwqRhsThreads), 0, s, bs.d_p, it); break;
+            CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6)
+#undef CASE
+            default: break;
+        }
+    }
     hipLaunchKernelGGL(k_bs_sym, dim3(bs.seg_n[SEG_ENT]), blk, 0, s, bs.d_p, bs.d_seg[SEG_ENT], bs.A, bs.cols);
     hipLaunchKernelGGL(k_bs_init, dim3(bs.seg_n[SEG_ROWS]), blk, 0, s, bs.d_p, bs.d_seg[SEG_ROWS], bs.b, bs.r, bs.z,
                        bs.pv, bs.part0);
@@ -404,9 +435,7 @@ static int bs_project(iga_batch* batch, const iga_target* gs, double rtol, int m
     BatchView V = batch_view(batch);
     for (int k = 0; k < V.n; ++k) {
         IGA_REQUIRE(u[k], IGA_E_INVALID, "solution buffer missing");
-        const iga_target& g = gs[k];
-        IGA_REQUIRE(g.kind >= IGA_TARGET_SINCOS && g.kind <= IGA_TARGET_AT_POINTS, IGA_E_UNSUPPORTED, "target kind");
-        IGA_REQUIRE(g.kind != IGA_TARGET_AT_POINTS || g.g_points, IGA_E_INVALID, "target values missing");
+        rhs_check(*V.plans[k], V.coeffs[k], gs[k]);
     }
     if (!*V.solve) *V.solve = bs_create(V);
     BatchSolve& bs = **V.solve;

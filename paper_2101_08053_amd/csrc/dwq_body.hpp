@@ -298,6 +298,40 @@ struct DwqRowArgs {
 // grid where both coordinates are WQ points, |det J| evaluated otherwise),
 // then T[b][q1] = sum_q2 w2 B2 c and M[a][b] = sum_q1 w1 B1 T[b][q1] is added
 // to the row.
+// Point `lane` of row i's 1-D rule in one direction restricted to the box
+// range reg = {lo, hi, s, side}: the coarse WQ rule on a whole range of
+// elements (s < 0; lanes count the WQ points of elements lo..hi), the side
+// list of interior knot s otherwise (lanes count its points; those outside
+// lo..hi are dropped). k is the point's WQ index, -1 for a nested point.
+template <int P>
+__device__ __forceinline__ bool dwq_rule_point(const DirDev& D, int i, const int* __restrict__ reg, int lane,
+                                               double& x, double& w, int& e, int& k) {
+    constexpr int KQ = DwqCfg<P>::KQ;
+    const int lo = reg[0], hi = reg[1], s = reg[2], sd = reg[3];
+    x = 0.0;
+    w = 0.0;
+    e = 0;
+    k = -1;
+    if (s < 0) {
+        const int k0 = wq_pt0(max(0, i - P), D.N, P);
+        const int kb = wq_pt0(lo, D.N, P), ke = wq_pt0(hi + 1, D.N, P);
+        const int kk = kb + lane;
+        if (kk >= ke) return false;
+        x = D.xq[kk];
+        e = D.eq[kk];
+        k = kk;
+        w = D.W[(size_t)i * D.qmax + (kk - k0)];
+        return true;
+    }
+    const int slot = 2 * (s - 1) + sd;
+    if (lane >= D.dq_n[slot]) return false;
+    e = D.dq_el[(size_t)slot * KQ + lane];
+    x = D.dq_x[(size_t)slot * KQ + lane];
+    k = D.dq_k[(size_t)slot * KQ + lane];
+    w = D.dq_w[((size_t)slot * P + (i - s)) * KQ + lane];
+    return e >= lo && e <= hi;
+}
+
 template <int P>
 __device__ __forceinline__ void dwq_rows_body(const DwqRowArgs& A, int r) {
     constexpr int W = 2 * P + 1, KQ = DwqCfg<P>::KQ;
@@ -317,32 +351,9 @@ __device__ __forceinline__ void dwq_rows_body(const DwqRowArgs& A, int r) {
         const int d = wave;
         const DirDev& D = d ? A.d2 : A.d1;
         const int i = d ? i2 : i1;
-        const int lo = reg[4 * d], hi = reg[4 * d + 1], s = reg[4 * d + 2], sd = reg[4 * d + 3];
-        bool ok = false;
-        double x = 0.0, w = 0.0;
-        int e = 0, k = -1;
-        if (s < 0) {
-            const int k0 = wq_pt0(max(0, i - P), D.N, P);
-            const int kb = wq_pt0(lo, D.N, P), ke = wq_pt0(hi + 1, D.N, P);
-            const int kk = kb + lane;
-            ok = kk < ke;
-            if (ok) {
-                x = D.xq[kk];
-                e = D.eq[kk];
-                k = kk;
-                w = D.W[(size_t)i * D.qmax + (kk - k0)];
-            }
-        } else {
-            const int slot = 2 * (s - 1) + sd;
-            const int np = D.dq_n[slot];
-            if (lane < np) {
-                e = D.dq_el[(size_t)slot * KQ + lane];
-                ok = (e >= lo && e <= hi);
-                x = D.dq_x[(size_t)slot * KQ + lane];
-                k = D.dq_k[(size_t)slot * KQ + lane];
-                w = D.dq_w[((size_t)slot * P + (i - s)) * KQ + lane];
-            }
-        }
+        double x, w;
+        int e, k;
+        const bool ok = dwq_rule_point<P>(D, i, reg + 4 * d, lane, x, w, e, k);
         const unsigned long long msk = __ballot(ok);
         const int pos = __popcll(msk & ((1ull << lane) - 1ull));
         if (ok) {

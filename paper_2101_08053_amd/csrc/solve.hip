@@ -2,7 +2,8 @@
 // to g c, then Jacobi-preconditioned CG on A = (M + M^T)/2 in the band layout.
 // The rule of each row is the one its mass-matrix row uses: weighted
 // quadrature for interior rows, element Gauss + cut rule for rows formed
-// element-wise. Reductions are block partials summed in a fixed order by one
+// element-wise, and for DWQ rows with a box the refined rules on the box
+// plus element rules on the rest of the support. Reductions are block partials summed in a fixed order by one
 // workgroup, so every run is bitwise reproducible.
 #include <cmath>
 #include <vector>
@@ -35,6 +36,12 @@ __global__ void __launch_bounds__(64) k_rhs_elem(RhsElemArgs A) {
 __global__ void k_rhs_gather(RhsGatherArgs A) {
     int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t < A.n_rows) rhs_gather_row(A, t);
+}
+
+// DWQ rows with a box: the box part, one workgroup per element-formed row.
+template <int P>
+__global__ void __launch_bounds__(kDwqRhsThreads) k_rhs_dwq(DwqRhsArgs A) {
+    dwq_rhs_body<P>(A, blockIdx.x);
 }
 
 // ------------------------------------------------------------------- PCG
@@ -138,7 +145,13 @@ RhsElemArgs rhs_elem_args(Plan& P, const double* gc, double* F) {
 
 RhsGatherArgs rhs_gather_args(Plan& P, const double* F, double* b) {
     return RhsGatherArgs{P.p, P.N1, P.N2, P.n1, P.form_rows, (int)P.n_form_rows, P.fn_of, P.ecls, P.band_id,
-                         P.cut_id, (int)P.n_band, F, b};
+                         P.cut_id, (int)P.n_band, F, b, P.method == IGA_DWQ ? P.dwq_region : nullptr};
+}
+
+DwqRhsArgs dwq_rhs_args(Plan& P, const iga_coeff& c, const iga_target& g, const double* gc, double* b) {
+    const CoefView cv = coef_view(P, c);
+    return DwqRhsArgs{P.dir[0], P.dir[1], g, (c.kind == IGA_COEF_GEOM_DETJ) ? c.geom_cp : nullptr, P.n1,
+                      cv.is_const, cv.value, gc, P.form_rows, (int)P.n_form_rows, P.fn_of, P.dwq_region, b};
 }
 
 void rhs(Plan& P, const iga_coeff& c, const iga_target& g, double* b, hipStream_t s) {
@@ -165,6 +178,27 @@ void rhs(Plan& P, const iga_coeff& c, const iga_target& g, double* b, hipStream_
     }
     int nr = (int)P.n_form_rows;
     hipLaunchKernelGGL(k_rhs_gather, dim3((nr + 255) / 256), dim3(256), 0, s, rhs_gather_args(P, W.F, b));
+    if (P.method == IGA_DWQ) {
+        const DwqRhsArgs A = dwq_rhs_args(P, c, g, W.gc, b);
+        switch (P.p) {
+#define CASE(PP) \
+    case PP: hipLaunchKernelGGL(k_rhs_dwq<PP>, dim3(nr), dim3(kDwqRhsThreads), 0, s, A); break;
+            CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
+#undef CASE
+        }
+    }
+}
+
+// The rules each method's right-hand side takes g c at: DWQ boxes also need
+// it at their nested points, so values given only at the plan's rule points
+// (and a coefficient given there) cannot serve DWQ plans.
+void rhs_check(const Plan& P, const iga_coeff& c, const iga_target& g) {
+    IGA_REQUIRE(g.kind >= IGA_TARGET_SINCOS && g.kind <= IGA_TARGET_AT_POINTS, IGA_E_UNSUPPORTED, "target kind");
+    IGA_REQUIRE(g.kind != IGA_TARGET_AT_POINTS || g.g_points, IGA_E_INVALID, "target values missing");
+    IGA_REQUIRE(P.method == IGA_HYBRID_GAUSS || P.method == IGA_GAUSS_REF || P.method == IGA_DWQ,
+                IGA_E_UNSUPPORTED, "right-hand side is built for hybrid Gauss, DWQ and the reference rules");
+    IGA_REQUIRE(P.method != IGA_DWQ || (g.kind != IGA_TARGET_AT_POINTS && c.kind != IGA_COEF_AT_POINTS),
+                IGA_E_UNSUPPORTED, "DWQ right-hand side needs g and c at its nested points: no AT_POINTS values");
 }
 }  // namespace iga
 
@@ -187,10 +221,7 @@ int iga_trim_rhs(iga_plan* plan, const iga_coeff* c, const iga_target* g, double
     API_BEGIN
     Plan* P = plan;
     IGA_REQUIRE(P && c && g && b, IGA_E_INVALID, "null argument");
-    IGA_REQUIRE(g->kind >= IGA_TARGET_SINCOS && g->kind <= IGA_TARGET_AT_POINTS, IGA_E_UNSUPPORTED, "target kind");
-    IGA_REQUIRE(g->kind != IGA_TARGET_AT_POINTS || g->g_points, IGA_E_INVALID, "target values missing");
-    IGA_REQUIRE(P->method == IGA_HYBRID_GAUSS || P->method == IGA_GAUSS_REF, IGA_E_UNSUPPORTED,
-                "right-hand side is built for hybrid Gauss and the reference rules");
+    rhs_check(*P, *c, *g);
     rhs(*P, *c, *g, b, (hipStream_t)stream);
     HIPX(hipGetLastError());
     API_END
@@ -202,8 +233,7 @@ int iga_trim_l2_project(iga_plan* plan, const iga_coeff* c, const double* vals, 
     Plan* P = plan;
     IGA_REQUIRE(P && c && vals && g && u, IGA_E_INVALID, "null argument");
     IGA_REQUIRE(rtol > 0 && maxit > 0, IGA_E_INVALID, "rtol and maxit must be positive");
-    IGA_REQUIRE(P->method == IGA_HYBRID_GAUSS || P->method == IGA_GAUSS_REF, IGA_E_UNSUPPORTED,
-                "right-hand side is built for hybrid Gauss and the reference rules");
+    rhs_check(*P, *c, *g);
     hipStream_t s = (hipStream_t)stream;
     SolveWork& W = P->sw;
     int n = (int)P->n_act;

@@ -12,6 +12,7 @@
 //    products summed in a fixed order.
 #pragma once
 
+#include "dwq_body.hpp"
 #include "plan.hpp"
 
 namespace iga {
@@ -231,28 +232,129 @@ struct RhsGatherArgs {
     int n_band;
     const double* F;
     double* b;
+    const int* region;    // DWQ: [n_rows][8] boxes; support elements inside a row's box are skipped (nullptr: none)
 };
 
 __device__ __forceinline__ void rhs_gather_row(const RhsGatherArgs& A, int t) {
     const int p = A.p;
     int r = A.rows[t], f = A.fn_of[r], i1 = f % A.n1, i2 = f / A.n1;
     int L = (p + 1) * (p + 1);
+    int bx0 = 1, bx1 = 0, by0 = 1, by1 = 0;   // box (empty by default)
+    if (A.region && A.region[(size_t)t * 8] >= 0) {
+        bx0 = A.region[(size_t)t * 8];
+        bx1 = A.region[(size_t)t * 8 + 1];
+        by0 = A.region[(size_t)t * 8 + 4];
+        by1 = A.region[(size_t)t * 8 + 5];
+    }
     double s = 0.0;
     for (int e2 = max(0, i2 - p); e2 <= min(A.N2 - 1, i2); ++e2)
         for (int e1 = max(0, i1 - p); e1 <= min(A.N1 - 1, i1); ++e1) {
             int e = e2 * A.N1 + e1;
             int8_t c = A.ecls[e];
-            if (c == EL_OUTSIDE) continue;
+            if (c == EL_OUTSIDE || (e1 >= bx0 && e1 <= bx1 && e2 >= by0 && e2 <= by1)) continue;
             int re = (c == EL_CUT) ? A.n_band + A.cut_id[e] : A.band_id[e];
             s += A.F[(size_t)re * L + (i2 - e2) * (p + 1) + (i1 - e1)];
         }
     A.b[r] = s;
 }
 
+// Sum over the workgroup in a fixed order (valid in thread 0).
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+    int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    if (lane == 0) sh[wid] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0)
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += sh[w];
+    __syncthreads();
+    return s;  // valid in thread 0
+}
+
+// Box part of the right-hand side of a DWQ row (Sect. 3.3 with B_j -> g):
+// the row's two 1-D rules restricted to its box (dwq_rule_point) and
+// sum_k sum_l w1_k w2_l (g c)(x1_k, x2_l), added to b of the row (the gather
+// has written the element part outside the box). g c comes from the WQ grid
+// values where both coordinates are WQ points, and is evaluated otherwise
+// (nested points): g at the mapped point, c = |det J| or the constant.
+struct DwqRhsArgs {
+    DirDev d1, d2;
+    iga_target g;
+    const double* geom;   // control points or nullptr (identity map); c = |det J| when set
+    int n1;
+    int c_const;
+    double c_value;
+    const double* gc_wq;  // g c on the WQ grid
+    const int* rows;
+    int n_rows;
+    const int* fn_of;
+    const int* region;
+    double* b;
+};
+
+constexpr int kDwqRhsThreads = 128;
+
+template <int P>
+__device__ __forceinline__ void dwq_rhs_body(const DwqRhsArgs& A, int r) {
+    constexpr int KQ = 64;
+    __shared__ double sX[2][KQ], sW[2][KQ];
+    __shared__ int sE[2][KQ], sK[2][KQ], sN[2];
+    __shared__ double sh[kDwqRhsThreads / 64];
+    if (r >= A.n_rows) return;
+    const int* reg = A.region + (size_t)r * 8;
+    if (reg[0] < 0) return;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int row = A.rows[r];
+    const int f = A.fn_of[row];
+    const int i1 = f % A.d1.n, i2 = f / A.d1.n;
+    if (wave < 2) {
+        const int d = wave;
+        double x, w;
+        int e, k;
+        const bool ok = dwq_rule_point<P>(d ? A.d2 : A.d1, d ? i2 : i1, reg + 4 * d, lane, x, w, e, k);
+        const unsigned long long msk = __ballot(ok);
+        const int pos = __popcll(msk & ((1ull << lane) - 1ull));
+        if (ok) {
+            sX[d][pos] = x;
+            sW[d][pos] = w;
+            sE[d][pos] = e;
+            sK[d][pos] = k;
+        }
+        if (lane == 0) sN[d] = __popcll(msk);
+    }
+    __syncthreads();
+    const int n1q = sN[0], n2q = sN[1];
+    double acc = 0.0;
+    for (int tt = tid; tt < n1q * n2q; tt += kDwqRhsThreads) {
+        const int q1 = tt % n1q, q2 = tt / n1q;
+        double gc;
+        if (sK[0][q1] >= 0 && sK[1][q2] >= 0) {
+            gc = A.gc_wq[(size_t)sK[1][q2] * A.d1.Q + sK[0][q1]];
+        } else {
+            const int e1 = sE[0][q1], e2 = sE[1][q2];
+            const double x = sX[0][q1], y = sX[1][q2];
+            double B1[P + 1], dB1[P + 1], B2[P + 1], dB2[P + 1];
+            basis_eval_d<P>(A.d1.knots, P + e1, x, B1, dB1);
+            basis_eval_d<P>(A.d2.knots, P + e2, y, B2, dB2);
+            double X = x, Y = y, c = A.c_value;
+            if (A.geom) map_local(A.geom, A.n1, P, e1, e2, B1, B2, X, Y);
+            if (!A.c_const) c = detj_local(A.geom, A.n1, P, e1, e2, B1, dB1, B2, dB2);
+            gc = target_eval(A.g, X, Y) * c;
+        }
+        acc += sW[0][q1] * sW[1][q2] * gc;
+    }
+    acc = block_sum(acc, sh);
+    if (tid == 0) A.b[row] += acc;
+}
+
 // Argument blocks of one plan (solve.hip).
 GcArgs gc_args(Plan& P, const iga_coeff& c, const iga_target& g, double* out);
 RhsElemArgs rhs_elem_args(Plan& P, const double* gc, double* F);
 RhsGatherArgs rhs_gather_args(Plan& P, const double* F, double* b);
+DwqRhsArgs dwq_rhs_args(Plan& P, const iga_coeff& c, const iga_target& g, const double* gc, double* b);
+// Throws unless the plan's method has a right-hand side for this target and coefficient.
+void rhs_check(const Plan& P, const iga_coeff& c, const iga_target& g);
 
 // ------------------------------------------------------------------- PCG
 // A = (M + M^T)/2: slot (a, b) of row r pairs with slot (-a, -b) of its
@@ -277,19 +379,6 @@ __device__ __forceinline__ void symmetrize_entry(int p, int n1, int n2, const in
 
 constexpr int kRedThreads = 256;
 constexpr int kCgCheck = 16;  // iterations between two convergence checks
-
-__device__ __forceinline__ double block_sum(double v, double* sh) {
-    int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
-    if (lane == 0) sh[wid] = v;
-    __syncthreads();
-    double s = 0.0;
-    if (threadIdx.x == 0)
-        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += sh[w];
-    __syncthreads();
-    return s;  // valid in thread 0
-}
 
 struct SpArgs {
     int p, n1, n2, n_act;

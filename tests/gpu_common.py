@@ -67,7 +67,8 @@ def parity_S(gpu, ref, S, ts=None, label="", floor=0.0, rowfloor=0.0):
     if not m.any():
         return 0.0
     den = np.maximum(np.maximum(S, floor * np.abs(ref).max()), rowfloor * S.max(axis=0, keepdims=True))
-    rel = np.where(m, np.abs(gpu - ref) / den, 0.0)
+    with np.errstate(invalid="ignore", divide="ignore"):
+        rel = np.where(m, np.abs(gpu - ref) / den, 0.0)
     if ts is not None:
         W = int(round(np.sqrt(ref.shape[0])))
         p = (W - 1) // 2
@@ -160,3 +161,13 @@ def oracle_dwq_tables(o, d, KQ):
                 Wt[sl, ii, :n] = D.dwq_weights(s + ii, s, side)[3][keep]
             cond[sl] = D.side_condition(s, side)
     return npts, X, E, K, Wt, cond
+
+
+def inject_oracle_dwq(plan, o):
+    """Give a DWQ plan the oracle's discontinuous weights of both directions (points are identical)."""
+    import torch
+    from paper_2101_08053_amd import igatrim
+    for d in range(2):
+        KQ = plan.table(igatrim.TABLE_DWQ_X, d).shape[1]
+        *_, Wt, _ = oracle_dwq_tables(o, d, KQ)
+        plan.set_dwq_weights(d, torch.as_tensor(np.ascontiguousarray(Wt.reshape(-1, KQ)), device="cuda"))

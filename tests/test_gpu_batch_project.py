@@ -130,3 +130,25 @@ def test_batch_project_degree_ends():
         u1, info1 = igatrim.l2_project(p, o, c, g, rtol=1e-12)
         assert infos[k]["iterations"] == info1["iterations"]
         assert np.array_equal(us[k].cpu().numpy(), u1.cpu().numpy()), f"patch {k}"
+
+
+def test_batch_project_with_dwq_plans():
+    """DWQ plans beside hybrid Gauss ones: box parts of the right-hand side in the same launches,
+    bit for bit the one-patch projections."""
+    require_gpu()
+    from paper_2101_08053_amd import igatrim
+    cfgs = wl.config4(n_patch=6, n_range=(8, 32), seed=wl.SEED_BASE + 56)
+    plans = [igatrim.Plan(c, igatrim.DWQ if k % 2 == 0 else igatrim.HYBRID_GAUSS) for k, c in enumerate(cfgs)]
+    coeffs = [p.coeff() for p in plans]
+    b = igatrim.Batch(plans, coeffs)
+    b.form(use_graph=True)
+    b.status()
+    g = _sincos(igatrim)
+    us, infos = b.project([g] * len(plans), rtol=1e-12)
+    for k, (p, c, o) in enumerate(zip(plans, coeffs, b.outs)):
+        u1, info1 = igatrim.l2_project(p, o, c, g, rtol=1e-12)
+        say(f"   patch {k}: method={p.method} p={p.sizes['p']} n_dwq_rows={p.sizes['n_dwq_rows']} "
+            f"batched {infos[k]} one-patch {info1}")
+        assert infos[k]["converged"]
+        assert infos[k]["iterations"] == info1["iterations"]
+        assert np.array_equal(us[k].cpu().numpy(), u1.cpu().numpy()), f"patch {k}"

@@ -15,8 +15,8 @@
 import numpy as np
 import pytest
 
-from gpu_common import (FLOOR_P3, ROWFLOOR_P3, inject_oracle_rules, oracle_dwq_tables, p3_bound, parity_S,
-                        require_gpu, say)
+from gpu_common import (FLOOR_P3, ROWFLOOR_P3, inject_oracle_dwq, inject_oracle_rules, oracle_dwq_tables, p3_bound,
+                        parity_S, require_gpu, say)
 from oracle.assemble import Oracle, to_ell
 from oracle.geometry import Coefficient
 from paper_2101_08053_amd import workloads as wl
@@ -47,15 +47,6 @@ def _oracle(name):
 def _plan(cfg):
     from paper_2101_08053_amd import igatrim
     return igatrim.Plan(cfg, igatrim.DWQ)
-
-
-def _inject_dwq(plan, o):
-    import torch
-    from paper_2101_08053_amd import igatrim
-    for d in range(2):
-        KQ = plan.table(igatrim.TABLE_DWQ_X, d).shape[1]
-        *_, Wt, _ = oracle_dwq_tables(o, d, KQ)
-        plan.set_dwq_weights(d, torch.as_tensor(np.ascontiguousarray(Wt.reshape(-1, KQ)), device="cuda"))
 
 
 @pytest.mark.parametrize("name", list(CASES))
@@ -121,7 +112,7 @@ def test_dwq_parity(name):
     ref = to_ell(o.dwq(), o.ts)
     S = to_ell(o.dwq(absolute=True), o.ts)
     inject_oracle_rules(plan, o)
-    _inject_dwq(plan, o)
+    inject_oracle_dwq(plan, o)
     v2 = plan.mass_form().cpu().numpy()
     plan.status()
     m2 = parity_S(v2, ref, S, o.ts, "P2")

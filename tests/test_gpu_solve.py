@@ -7,13 +7,15 @@ rules 1e-10 of that scale.
 Solution: the oracle's residual of the device solution, ||b - A u|| / ||b||
 with the oracle's A and b, stays within 1e-10 (PCG stops at 1e-12 on the
 device's A and b).
+DWQ plans (Sect. 3.3): the same bars, with the oracle's discontinuous weights
+injected as well for the identical-rule comparison.
 """
 import math
 
 import numpy as np
 import pytest
 
-from gpu_common import inject_oracle_rules, require_gpu, say
+from gpu_common import inject_oracle_dwq, inject_oracle_rules, require_gpu, say
 from oracle import project
 from oracle.assemble import Oracle
 from oracle.geometry import Coefficient
@@ -122,3 +124,87 @@ def test_projection_reference_rules():
     assert info["converged"]
     bo = project.rhs(o, wl.config1_target, "reference")
     _rhs_close(b, bo, project.rhs(o, wl.config1_target, "reference", absolute=True), 1e-13)
+
+
+DWQ_CASES = {
+    "line_p3_N10": lambda: wl.table1_line(3),
+    "circle_p2_N40": lambda: wl.config1(N=40),
+    "cubic16_p4_N36_detj": lambda: wl.config2(N=36),
+    "ellipses3_p5_N24_detj": lambda: wl.config3(N=24, p=5),
+}
+
+
+@pytest.mark.parametrize("name", list(DWQ_CASES))
+def test_dwq_rhs_matches_oracle(name):
+    """b of a DWQ plan: box parts from the refined weights, element rules elsewhere."""
+    require_gpu()
+    from paper_2101_08053_amd import igatrim
+    cfg = DWQ_CASES[name]()
+    o = Oracle(cfg)
+    bo = project.rhs(o, wl.config1_target, "dwq")
+    Sb = project.rhs(o, wl.config1_target, "dwq", absolute=True)
+    plan = igatrim.Plan(cfg, igatrim.DWQ)
+    c = plan.coeff()
+    plan.mass_form(c)
+    b_own = igatrim.rhs(plan, c, _sincos()).cpu().numpy()
+    say(f"[dwq rhs] {name} (device rules)")
+    _rhs_close(b_own, bo, Sb, 1e-10)
+    inject_oracle_rules(plan, o)
+    inject_oracle_dwq(plan, o)
+    plan.mass_form(c)
+    b = igatrim.rhs(plan, c, _sincos()).cpu().numpy()
+    say(f"[dwq rhs] {name} (oracle rules)")
+    _rhs_close(b, bo, Sb, 1e-13)
+    bh = project.rhs(o, wl.config1_target, "hybrid")
+    assert np.abs(bh - bo).max() > 1e-3 * np.abs(b - bo).max()   # the boxes are used
+
+
+def test_dwq_projection_against_oracle():
+    require_gpu()
+    from paper_2101_08053_amd import igatrim
+    cfg = wl.config1(N=40)
+    o = Oracle(cfg)
+    plan, u, b, info = _project(cfg, method=igatrim.DWQ)
+    say(f"[l2 dwq] circle N=40: {info}")
+    assert info["converged"] and info["rel_residual"] <= 1e-12
+    bo = project.rhs(o, wl.config1_target, "dwq")
+    M = o.dwq()
+    res = np.linalg.norm(bo - 0.5 * (M + M.T) @ u) / np.linalg.norm(bo)
+    say(f"   oracle residual of device u: {res:.2e}")
+    assert res <= 1e-9
+    e_dev = project.l2_error(o, u, wl.config1_target)
+    e_or = project.l2_error(o, project.solve(M, bo), wl.config1_target)
+    e_hyb = project.l2_error(o, project.solve(o.hybrid(), project.rhs(o, wl.config1_target)), wl.config1_target)
+    say(f"   L2 error device {e_dev:.3e} oracle {e_or:.3e} (hybrid Gauss {e_hyb:.3e})")
+    assert abs(e_dev - e_or) <= 1e-6 * e_or
+
+
+def test_dwq_projection_polynomial_reproduction():
+    """g in Q_p, c = 1: the DWQ projection reproduces g."""
+    require_gpu()
+    from paper_2101_08053_amd import igatrim
+    cfg = wl.config3(N=20, p=4)
+    plan = igatrim.Plan(cfg, igatrim.DWQ)
+    c = plan.coeff(igatrim.COEF_CONST, 1.0)
+    vals = plan.mass_form(c)
+    u, info = igatrim.l2_project(plan, vals, c, igatrim.target_monomial(4, 3), rtol=1e-13)
+    cfg.geom_cp = None   # a constant coefficient maps g by the identity
+    err = project.l2_error(Oracle(cfg, coef=Coefficient(cfg, kind=wl.COEF_CONST)), u.cpu().numpy(),
+                           lambda x, y: x ** 4 * y ** 3)
+    say(f"[dwq reproduction] {info} error {err:.2e}")
+    assert err < 1e-10
+
+
+def test_dwq_rhs_rejects_values_at_points():
+    """DWQ boxes need g c at nested points: values given only at the plan's rule points are refused."""
+    require_gpu()
+    import torch
+    from paper_2101_08053_amd import igatrim
+    cfg = wl.config1(N=16)
+    plan = igatrim.Plan(cfg, igatrim.DWQ)
+    c = plan.coeff()
+    plan.mass_form(c)
+    g = igatrim.target_points(torch.ones(plan.sizes["n_points"], dtype=torch.float64, device="cuda"))
+    with pytest.raises(igatrim.IgaError) as ei:
+        igatrim.rhs(plan, c, g)
+    assert "nested" in str(ei.value)
