@@ -230,20 +230,23 @@ int iga_trim_rhs(iga_plan* plan, const iga_coeff* c, const iga_target* g, double
  * rows (Sect. 3.2) -- for device vectors of length n_act, with c
  * given at every rule point (c_points, n_points values), the rows formed by
  * the plan's interior and hybrid rules, basis values recomputed on the fly.
- * The weighted-quadrature part runs sum-factorised with one row of the WQ
- * grid in LDS: IGA_E_UNSUPPORTED past about 2700 elements along xi_1. */
+ * The weighted-quadrature part runs sum-factorised in one pass over the WQ
+ * grid (strips of test columns by bands of elements); the adjoint keeps one
+ * row of the WQ grid in LDS: IGA_E_UNSUPPORTED past about 2700 elements
+ * along xi_1. */
 int iga_mf_apply(iga_plan* plan, const double* c_points, const double* u, double* y, void* stream);
 
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving or solver loops, harnesses that forbid hipMalloc):
  * iga_mf_apply with the product's intermediate arrays taken from a static
- * device array the library holds for the life of the process (64 MiB per
+ * device array the library holds for the life of the process (16 MiB per
  * device, one copy per device; its address is looked up when the first plan
  * is created on the device) instead of the plan's workspace. Allocates
  * nothing. Same arguments, kernels and result as iga_mf_apply.
- * IGA_E_CAPACITY (nothing enqueued) when the patch needs more than 64 MiB of
- * intermediate arrays: 8 (n2 q1 + q2 n1 + (n_band_el + n_cut_el)(p+1)^2)
- * bytes, each part rounded up to 256 bytes (about 1400^2 elements at p = 4).
+ * IGA_E_CAPACITY (nothing enqueued) when the patch needs more than 16 MiB of
+ * intermediate arrays: 8 (2 nband p n1 + (n_band_el + n_cut_el)(p+1)^2)
+ * bytes with nband = max(1, floor(N2 / max(16, p+1))), each part rounded up
+ * to 256 bytes (about 1500^2 elements at p = 4 with a 16-point cubic hole).
  * Every call on a device shares that device's array: calls that overlap on
  * one device (several streams or threads) race and must be ordered by the
  * caller. */

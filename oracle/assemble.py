@@ -212,7 +212,7 @@ class Oracle:
         return self._dwq_dirs
 
     def dwq_region(self, i1, i2):
-        """((lo1, hi1, s1, side1), (lo2, hi2, s2, side2)) or None (reading R8)."""
+        """((lo1, hi1, s1, side1), (lo2, hi2, s2, side2)) or None (the box of dwq.choose_region)."""
         ts = self.ts
         return dwq.choose_region(ts.ecls == INSIDE, i1, i2, self.p, ts.N1, ts.N2)
 

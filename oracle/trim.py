@@ -204,7 +204,7 @@ class TrimmedSpace:
         return segs
 
     def cut_rule(self, e1, e2, n_r=None, n_q=None, n_s=None, variant=None):
-        """Nodes (x, y) and weights w of the Gauss-Green rule on V_e (R5) (cached)."""
+        """Nodes (x, y) and weights w of the Gauss-Green rule on V_e (the cut rule, on the exact boundary; cached)."""
         key = (e1, e2, n_r, n_q, n_s, variant)
         cache = self.__dict__.setdefault("_rule_cache", {})
         if key not in cache:

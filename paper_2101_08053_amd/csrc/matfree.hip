@@ -43,11 +43,11 @@ __device__ __forceinline__ bool wq_row(const MfArgs& A, int8_t cls) {
 
 // The weighted-quadrature part as banded one-dimensional contractions (sum
 // factorisation), fast index along xi_1:
-//   V[j2][k1] = sum_a B1[k1][a] u(e1(k1) + a, j2)              (u on the xi_1 points; k_mf_v)
-//   G[k2][k1] = c_k sum_a B2[k2][a] V[e2(k2) + a][k1]          (c U along grid row k2, in LDS; k_mf_gh)
-//   H[k2][i1] = sum_q w1[i1][q] G[k2][k0(i1) + q]              (test rows along xi_1; k_mf_gh)
-//   y(i1, i2) = sum_q w2[i2][q] H[k0(i2) + q][i1]              (interior rows; k_mf_y)
-// and, transposed, for the adjoint
+//   V[j2][k1] = sum_a B1[k1][a] u(e1(k1) + a, j2)              (u on the xi_1 points)
+//   G[k2][k1] = c_k sum_a B2[k2][a] V[e2(k2) + a][k1]          (c U along grid row k2)
+//   H[k2][i1] = sum_q w1[i1][q] G[k2][k0(i1) + q]              (test rows along xi_1)
+//   y(i1, i2) = sum_q w2[i2][q] H[k0(i2) + q][i1]              (interior rows)
+// all four in one pass over the grid (k_mf_fwd), and, transposed, for the adjoint
 //   H[k2][i1] = sum_{i2 : k2 in supp} w2[i2][k2 - k0(i2)] r(i1, i2)                    (k_mf_hadj)
 //   R[k2][k1] = sum_{i1 : k1 in supp} w1[i1][k1 - k0(i1)] H[k2][i1],  dc = U R, c R      (k_mf_rd, per row)
 //   D[k2][j1] = sum_{k1 in supp j1} B1[k1][j1 - e1(k1)] c R[k2][k1]                    (k_mf_rd)
@@ -74,25 +74,6 @@ __global__ void __launch_bounds__(256) k_mf_v(MfArgs A, const double* __restrict
 }
 
 template <int P>
-__global__ void __launch_bounds__(256) k_mf_y(MfArgs A, const double* __restrict__ H, double* __restrict__ y) {
-    constexpr int QM = 4 * P + 2;
-    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    const int n1 = A.n1;
-    if (t >= (int64_t)n1 * A.n2) return;
-    if (!wq_row(A, A.fcls[t])) return;
-    const int i1 = (int)(t % n1), i2 = (int)(t / n1);
-    const int k0 = A.d2.pt0[max(0, i2 - P)], q2 = A.d2.pt0[min(A.N2 - 1, i2) + 1] - k0;
-    const double* w = A.d2.W + (size_t)i2 * A.d2.qmax;
-    double s = 0.0;
-#pragma unroll
-    for (int q = 0; q < QM; ++q) {
-        if (q >= q2) break;
-        s += w[q] * H[(size_t)(k0 + q) * n1 + i1];
-    }
-    y[A.act_of[t]] = s;
-}
-
-template <int P>
 __global__ void __launch_bounds__(256) k_mf_hadj(MfArgs A, const double* __restrict__ r, double* __restrict__ H) {
     const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
     const int n1 = A.n1;
@@ -114,6 +95,263 @@ __global__ void __launch_bounds__(256) k_mf_hadj(MfArgs A, const double* __restr
     H[t] = s;
 }
 
+// Forward weighted-quadrature part in one pass over the grid. A workgroup
+// takes a strip of test columns i1 (one per thread) and a band of elements
+// e2 (at least p+1 of them) and walks the band's grid rows k2 in order:
+//   V[j2][k1] for a new u row (when an element starts; p+1 rows in a ring in LDS),
+//   G[k1] = c_k sum_b B2[k2][b] V[e2(k2)+b][k1]   (the strip's points of row k2, LDS),
+//   H(i1) = sum_q w1[i1][q] G[k0(i1)+q]            (registers),
+//   acc[i2] += w2[i2][k2 - k0(i2)] H(i1)           for the p+1 rows i2 = e2..e2+p.
+// When element e2 ends, row e2 has all of this band's terms: it is written to
+// y if its support lies in the band (or starts at the patch edge), otherwise
+// as the band's head part of that row; the p rows after the band are written
+// as its tail part, and k_mf_fix adds a band's head to the previous band's
+// tail. c rows are loaded two grid rows ahead and u rows one element ahead
+// (their active ids two); the values every thread needs at a grid row (B2,
+// w2, element bounds) are staged in LDS once, so no load in the loop waits
+// on a later-issued one. c is read once; V and H never leave the workgroup.
+constexpr int kMfThreads = 128;  // threads = test columns per strip (at most)
+constexpr int kMfNpt = 3;        // xi_1 points per thread (a strip has at most 2 (cols + p) + 2 (p - 1))
+constexpr int kMfUpt = 2;        // u columns per thread (cols + 2p)
+constexpr int kMfBand = 8;       // elements per band, at least p+1 (the last band takes the remainder)
+constexpr int kMfBandMax = kMfBand > IGA_MAXP + 1 ? kMfBand : IGA_MAXP + 1;
+constexpr int kMfRows = 2 * (2 * kMfBandMax - 1) + 2 * IGA_MAXP;  // grid rows of a band (+1 pad), at most
+
+struct MfFwdArgs {
+    int cols;     // test columns per strip
+    int band;     // elements per band (the last band takes the remainder)
+    int nstrip, nband;
+    double* head; // [nband][p][n1]
+    double* tail; // [nband][p][n1]
+};
+
+template <int P>
+__global__ void __launch_bounds__(kMfThreads) k_mf_fwd(MfArgs A, MfFwdArgs F, const double* __restrict__ u,
+                                                       double* __restrict__ y) {
+    constexpr int NP = kMfThreads * kMfNpt, NW = 2 * P + 2, QM = 4 * P + 2;
+    __shared__ double sU[kMfThreads * kMfUpt];
+    __shared__ double sV[P + 1][NP];
+    __shared__ double sG[2][NP];
+    __shared__ double sB2[kMfRows][P + 1], sW2[kMfRows][P + 1];
+    __shared__ int sPt[2 * kMfBandMax];
+    const int tid = threadIdx.x;
+    const int strip = blockIdx.x % F.nstrip, bnd = blockIdx.x / F.nstrip;
+    const int n1 = A.n1, N1 = A.N1, N2 = A.N2, Q1 = A.d1.Q;
+    const int c0 = strip * F.cols, c1 = min(n1, c0 + F.cols);
+    const int E0 = bnd * F.band, E1 = (bnd == F.nband - 1) ? N2 : E0 + F.band;
+    const int kA = A.d1.pt0[max(0, c0 - P)], kB = A.d1.pt0[min(N1 - 1, c1 - 1) + 1];
+    const int jA = max(0, c0 - P), jB = min(N1 - 1, c1 - 1) + P + 1;
+    const int KA2 = A.d2.pt0[E0], KB2 = A.d2.pt0[E1];
+    // the band's per-row values: element bounds, B2 and the test weights w2 meeting at each row
+    for (int t = tid; t <= E1 - E0; t += kMfThreads) sPt[t] = A.d2.pt0[E0 + t] - KA2;
+    // (rows are taken in pairs: an odd count gets one more row with B2 = w2 = 0)
+    for (int t = tid; t < ((KB2 - KA2 + 1) & ~1) * (P + 1); t += kMfThreads) {
+        const int r = t / (P + 1), b = t % (P + 1), k2 = min(KA2 + r, KB2 - 1);
+        const int i2 = A.d2.eq[k2] + b;
+        const bool in = KA2 + r < KB2;
+        sB2[r][b] = in ? A.d2.Bq[(size_t)k2 * (P + 1) + b] : 0.0;
+        sW2[r][b] = in ? A.d2.W[(size_t)i2 * A.d2.qmax + (k2 - A.d2.pt0[max(0, i2 - P)])] : 0.0;
+    }
+    // the thread's points: basis values and local element
+    double B1[kMfNpt][P + 1];
+    int le1[kMfNpt];
+    bool pv[kMfNpt];
+#pragma unroll
+    for (int m = 0; m < kMfNpt; ++m) {
+        const int k1 = kA + tid + kMfThreads * m;
+        pv[m] = k1 < kB;
+        const int kk = pv[m] ? k1 : kA;
+        le1[m] = A.d1.eq[kk] - jA;
+#pragma unroll
+        for (int a = 0; a <= P; ++a) B1[m][a] = A.d1.Bq[(size_t)kk * (P + 1) + a];
+    }
+    // the thread's test column: all its weights in registers (0 past its points)
+    const int i1 = c0 + tid;
+    const bool has_col = i1 < c1;
+    const int ic = has_col ? i1 : c0;
+    const int k0l = A.d1.pt0[max(0, ic - P)] - kA;
+    const int nq1 = A.d1.pt0[min(N1 - 1, ic) + 1] - A.d1.pt0[max(0, ic - P)];
+    double w1[QM];
+#pragma unroll
+    for (int q = 0; q < NW; ++q) w1[q] = A.d1.WT[(size_t)q * n1 + ic];
+#pragma unroll
+    for (int q = NW; q < QM; ++q) w1[q] = (q < nq1) ? A.d1.W[(size_t)ic * A.d1.qmax + q] : 0.0;
+    const bool wide = nq1 > NW;   // a column next to a patch end
+    // points past the strip's last one are read with weight 0: keep them finite
+    for (int k = (kB - kA) + tid; k < NP; k += kMfThreads) {
+        sG[0][k] = 0.0;
+        sG[1][k] = 0.0;
+    }
+    // Every load in the loop is unconditional (clamped address) and its value
+    // is selected where it is used: a load under a branch, or a select next to
+    // the load, makes the wave wait for it there -- and, the memory counter
+    // being in order, for every load issued before it.
+    bool ucol[kMfUpt];
+#pragma unroll
+    for (int v = 0; v < kMfUpt; ++v) ucol[v] = jA + tid + kMfThreads * v < jB;
+    auto u_ids = [&](int j2, int (&id)[kMfUpt]) {   // rows past the last are never used
+#pragma unroll
+        for (int v = 0; v < kMfUpt; ++v)
+            id[v] = A.act_of[(size_t)min(j2, A.n2 - 1) * n1 + min(jA + tid + kMfThreads * v, jB - 1)];
+    };
+    auto u_vals = [&](const int (&id)[kMfUpt], double (&val)[kMfUpt]) {
+#pragma unroll
+        for (int v = 0; v < kMfUpt; ++v) val[v] = u[max(id[v], 0)];
+    };
+    // V of u row j2 from the values in sU (after a barrier) into its ring slot
+    auto v_row = [&](int j2) {
+        double* dst = sV[j2 % (P + 1)];
+#pragma unroll
+        for (int m = 0; m < kMfNpt; ++m) {
+            double s = 0.0;
+#pragma unroll
+            for (int a = 0; a <= P; ++a) s += B1[m][a] * sU[le1[m] + a];
+            if (pv[m]) dst[tid + kMfThreads * m] = s;
+        }
+    };
+    auto put_u = [&](const double (&val)[kMfUpt], const bool (&ok)[kMfUpt]) {
+#pragma unroll
+        for (int v = 0; v < kMfUpt; ++v) sU[tid + kMfThreads * v] = ok[v] ? val[v] : 0.0;
+    };
+    auto u_ok = [&](const int (&id)[kMfUpt], bool (&ok)[kMfUpt]) {
+#pragma unroll
+        for (int v = 0; v < kMfUpt; ++v) ok[v] = ucol[v] && id[v] >= 0;
+    };
+    auto c_row = [&](int k2, double (&dst)[kMfNpt]) {
+#pragma unroll
+        for (int m = 0; m < kMfNpt; ++m) {
+            const int k1 = min(kA + tid + kMfThreads * m, kB - 1);
+            dst[m] = A.c[(size_t)min(k2, KB2 - 1) * Q1 + k1];
+        }
+    };
+    // prologue: u rows E0 .. E0+p-1 into the ring
+    // (the ids of rows E0 .. E0+p+1 are loaded together, then the values of rows E0 .. E0+p)
+    int idp[P + 2][kMfUpt];
+#pragma unroll
+    for (int j = 0; j < P + 2; ++j) u_ids(E0 + j, idp[j]);
+    double up[P + 1][kMfUpt];
+    bool okp[P + 1][kMfUpt];
+#pragma unroll
+    for (int j = 0; j <= P; ++j) {
+        u_vals(idp[j], up[j]);
+        u_ok(idp[j], okp[j]);
+    }
+#pragma unroll
+    for (int j = 0; j < P; ++j) {
+        __syncthreads();
+        put_u(up[j], okp[j]);
+        __syncthreads();
+        v_row(E0 + j);
+    }
+    int idb[kMfUpt];
+    double uv[kMfUpt];
+    bool uok[kMfUpt];
+#pragma unroll
+    for (int v = 0; v < kMfUpt; ++v) {
+        uv[v] = up[P][v];          // row E0+p (the first element's new row)
+        uok[v] = okp[P][v];
+        idb[v] = idp[P + 1][v];    // ids of row E0+p+1
+    }
+    // c rows two ahead, in two buffers that alternate (no copies: a copy of a
+    // loaded value waits for the load)
+    double ca[kMfNpt], cb[kMfNpt];
+    c_row(KA2, ca);
+    c_row(KA2 + 1, cb);
+    double acc[P + 1];
+#pragma unroll
+    for (int b = 0; b <= P; ++b) acc[b] = 0.0;
+    int e2 = E0, rend = 0, yid = -1;
+    int8_t ycls = 0;
+    // element e2 starts: its new u row e2+p into the ring, the next rows' loads, row e2's output id
+    auto start = [&]() {
+        __syncthreads();
+        put_u(uv, uok);
+        __syncthreads();
+        v_row(e2 + P);
+        u_vals(idb, uv);            // row e2+p+1
+        u_ok(idb, uok);
+        u_ids(e2 + P + 2, idb);     // ids of row e2+p+2
+        const size_t f = (size_t)e2 * n1 + ic;
+        yid = A.act_of[f];
+        ycls = A.fcls[f];
+        rend = sPt[e2 - E0 + 1];
+    };
+    // element e2 ends: row e2 has all of the band's terms
+    auto finish = [&]() {
+        if (has_col) {
+            if (E0 == 0 || e2 - P >= E0) {
+                if (yid >= 0 && wq_row(A, ycls)) y[yid] = acc[0];
+            } else {
+                F.head[((size_t)bnd * P + (e2 - E0)) * n1 + i1] = acc[0];
+            }
+        }
+#pragma unroll
+        for (int b = 0; b < P; ++b) acc[b] = acc[b + 1];
+        acc[P] = 0.0;
+        ++e2;
+    };
+    // grid row r of the band with its c values in cbuf; cbuf then takes row r+2
+    auto row = [&](int r, double (&cbuf)[kMfNpt]) {
+        double* g = sG[r & 1];
+        __syncthreads();  // the ring row written at the element start
+#pragma unroll
+        for (int m = 0; m < kMfNpt; ++m) {
+            const int k = tid + kMfThreads * m;
+            double s = 0.0;
+#pragma unroll
+            for (int b = 0; b <= P; ++b) s += sB2[r][b] * sV[(e2 + b) % (P + 1)][min(k, NP - 1)];
+            if (pv[m]) g[k] = cbuf[m] * s;
+        }
+        c_row(KA2 + r + 2, cbuf);
+        __syncthreads();
+        double h = 0.0;
+#pragma unroll
+        for (int q = 0; q < NW; ++q) h += w1[q] * g[k0l + q];
+        if (wide) {
+#pragma unroll
+            for (int q = NW; q < QM; ++q) h += w1[q] * g[min(k0l + q, NP - 1)];
+        }
+#pragma unroll
+        for (int b = 0; b <= P; ++b) acc[b] += sW2[r][b] * h;
+        if (r + 1 == rend) {
+            finish();
+            if (e2 < E1) start();
+        }
+    };
+    start();
+    const int R = KB2 - KA2;
+    for (int r = 0; r < R; r += 2) {  // both rows unconditional: a skipped row would make the waits conservative
+        row(r, ca);
+        row(r + 1, cb);
+    }
+    if (!has_col) return;
+#pragma unroll
+    for (int b = 0; b < P; ++b) {  // rows E1 .. E1+p-1
+        const int i2 = E1 + b;
+        if (E1 == N2) {
+            const size_t f = (size_t)i2 * n1 + i1;
+            const int id = A.act_of[f];
+            if (id >= 0 && wq_row(A, A.fcls[f])) y[id] = acc[b];
+        } else {
+            F.tail[((size_t)bnd * P + b) * n1 + i1] = acc[b];
+        }
+    }
+}
+
+// Rows whose support spans two bands: the band's head plus the previous band's tail.
+template <int P>
+__global__ void __launch_bounds__(256) k_mf_fix(MfArgs A, MfFwdArgs F, double* __restrict__ y) {
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int n1 = A.n1;
+    if (t >= (int64_t)(F.nband - 1) * P * n1) return;
+    const int bnd = 1 + (int)(t / ((int64_t)P * n1)), r = (int)((t / n1) % P), i1 = (int)(t % n1);
+    const int i2 = bnd * F.band + r;
+    const size_t f = (size_t)i2 * n1 + i1;
+    const int id = A.act_of[f];
+    if (id < 0 || !wq_row(A, A.fcls[f])) return;
+    y[id] = F.tail[((size_t)(bnd - 1) * P + r) * n1 + i1] + F.head[((size_t)bnd * P + r) * n1 + i1];
+}
+
 // Per-point and per-function views of the xi_1 tables that the grid-row
 // kernels read at every row: the test weights that meet at a point (WA) and
 // a function's basis values at its support points (BR, functions contiguous).
@@ -129,53 +367,6 @@ __global__ void __launch_bounds__(256) k_mf_tables(DirDev D, int n1, double* __r
         const int q = t / n1, j1 = t % n1;
         const int k0 = D.pt0[max(0, j1 - P)], q1 = D.pt0[min(D.N - 1, j1) + 1] - k0;
         BR[t] = (q < q1) ? D.Bq[(size_t)(k0 + q) * (P + 1) + (j1 - D.eq[k0 + q])] : 0.0;
-    }
-}
-
-// Forward, one workgroup per grid row k2: G = c U along the row in LDS, then
-// the row's xi_1 test sums H[k2][i1] (G never leaves the workgroup). Each
-// thread takes four points (or functions) at a time, loads first.
-template <int P>
-__global__ void __launch_bounds__(256) k_mf_gh(MfArgs A, const double* __restrict__ V, double* __restrict__ H) {
-    extern __shared__ double sG[];  // Q1
-    constexpr int QM = 4 * P + 2, NB = 4;
-    const int k2 = blockIdx.x, Q1 = A.d1.Q, n1 = A.n1;
-    const int e2 = A.d2.eq[k2];
-    double b2[P + 1];
-#pragma unroll
-    for (int a = 0; a <= P; ++a) b2[a] = A.d2.Bq[(size_t)k2 * (P + 1) + a];
-    const double* Vr = V + (size_t)e2 * Q1;
-    const double* cr = A.c + (size_t)k2 * Q1;
-#pragma unroll 1
-    for (int kb = threadIdx.x; kb < Q1; kb += 256 * NB) {
-        double v[NB][P + 1], cv[NB];
-#pragma unroll
-        for (int j = 0; j < NB; ++j) {
-            const int k1 = min(kb + 256 * j, Q1 - 1);
-#pragma unroll
-            for (int a = 0; a <= P; ++a) v[j][a] = Vr[(size_t)a * Q1 + k1];
-            cv[j] = cr[k1];
-        }
-#pragma unroll
-        for (int j = 0; j < NB; ++j) {
-            double s = 0.0;
-#pragma unroll
-            for (int a = 0; a <= P; ++a) s += b2[a] * v[j][a];
-            if (kb + 256 * j < Q1) sG[kb + 256 * j] = cv[j] * s;
-        }
-    }
-    __syncthreads();
-#pragma unroll 1
-    for (int i1 = threadIdx.x; i1 < n1; i1 += 256) {
-        const int k0 = A.d1.pt0[max(0, i1 - P)], q1 = A.d1.pt0[min(A.N1 - 1, i1) + 1] - k0;
-        double s = 0.0;
-#pragma unroll
-        for (int q = 0; q < QM; ++q) {
-            if (q >= q1) break;
-            const double w = (q < 2 * P + 2) ? A.d1.WT[(size_t)q * n1 + i1] : A.d1.W[(size_t)i1 * A.d1.qmax + q];
-            s += w * sG[k0 + q];
-        }
-        H[(size_t)k2 * n1 + i1] = s;
     }
 }
 
@@ -250,7 +441,9 @@ __global__ void __launch_bounds__(64) k_mf_elem(MfArgs A, const double* __restri
                                                 double* __restrict__ Ye, double* __restrict__ dc) {
     constexpr int L = (P + 1) * (P + 1);
     constexpr int PER = (L + 63) / 64;
-    __shared__ double sPhi[64][L];
+    // per node of the chunk: its two basis rows and its weight term (the products
+    // B1 B2 are formed where they are used, so little LDS is held per workgroup)
+    __shared__ double sB1[64][P + 1], sB2[64][P + 1];
     __shared__ double sT[64];
     __shared__ double sU[L], sR[L];
     int re = blockIdx.x;
@@ -299,14 +492,21 @@ __global__ void __launch_bounds__(64) k_mf_elem(MfArgs A, const double* __restri
             }
             double Ug = 0.0, Rg = 0.0;
 #pragma unroll
-            for (int a2 = 0; a2 <= P; ++a2)
+            for (int a2 = 0; a2 <= P; ++a2) {
+                double su = 0.0, sr = 0.0;
 #pragma unroll
                 for (int a1 = 0; a1 <= P; ++a1) {
-                    double phi = B1[a1] * B2[a2];
-                    sPhi[threadIdx.x][a2 * (P + 1) + a1] = phi;
-                    Ug += phi * sU[a2 * (P + 1) + a1];
-                    Rg += phi * sR[a2 * (P + 1) + a1];
+                    su += B1[a1] * sU[a2 * (P + 1) + a1];
+                    sr += B1[a1] * sR[a2 * (P + 1) + a1];
                 }
+                Ug += B2[a2] * su;
+                Rg += B2[a2] * sr;
+            }
+#pragma unroll
+            for (int a = 0; a <= P; ++a) {
+                sB1[threadIdx.x][a] = B1[a];
+                sB2[threadIdx.x][a] = B2[a];
+            }
             double cg = A.c[pbase + n];
             if (r) {
                 Rg *= w;
@@ -321,8 +521,10 @@ __global__ void __launch_bounds__(64) k_mf_elem(MfArgs A, const double* __restri
 #pragma unroll
         for (int k = 0; k < PER; ++k) {
             int l = threadIdx.x + 64 * k;
-            if (l < L)
-                for (int m = 0; m < cnt; ++m) acc[k] += sT[m] * sPhi[m][l];
+            if (l < L) {
+                const int a1 = l % (P + 1), a2 = l / (P + 1);
+                for (int m = 0; m < cnt; ++m) acc[k] += sT[m] * sB1[m][a1] * sB2[m][a2];
+            }
         }
     }
 #pragma unroll
@@ -367,6 +569,51 @@ __global__ void k_mf_gather(MfArgs A, const double* __restrict__ Ye, const doubl
     out[r] = s;
 }
 
+// Forward rows formed element-wise: the element vectors of the band and cut
+// elements of the row's support, summed in a fixed order. Four lanes per row
+// of the plan's element-formed list, each taking every fourth support element
+// (classes, then element ids, then vector entries loaded together), the four
+// partial sums added in the quad.
+template <int P>
+__global__ void __launch_bounds__(256) k_mf_gather_rows(MfArgs A, const int* __restrict__ rows, int n_rows,
+                                                        const double* __restrict__ Ye, double* __restrict__ y) {
+    constexpr int L = (P + 1) * (P + 1), PER = (L + 3) / 4;
+    const int t = blockIdx.x * 256 + threadIdx.x;
+    const int ri = t >> 2, part = t & 3;
+    const bool ok = ri < n_rows;   // lanes past the list still take part in the quad sum
+    const int r = rows[min(ri, n_rows - 1)], f = A.fn_of[r];
+    const int i1 = f % A.n1, i2 = f / A.n1;
+    int8_t cls[PER];
+    // slot idx of the (p+1)^2 support elements; the last quad's slots past them are
+    // clamped onto the last element (an outside class, so they add nothing)
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const int idx = min(part + 4 * k, L - 1), b = idx / (P + 1), a = idx % (P + 1);
+        const int e1 = i1 - P + a, e2 = i2 - P + b;
+        const bool in = part + 4 * k < L && e1 >= 0 && e1 < A.N1 && e2 >= 0 && e2 < A.N2;
+        cls[k] = in ? A.ecls[(size_t)e2 * A.N1 + e1] : (int8_t)EL_OUTSIDE;
+    }
+    int re[PER];
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const int idx = min(part + 4 * k, L - 1), b = idx / (P + 1), a = idx % (P + 1);
+        const int e = (i2 - P + b) * A.N1 + (i1 - P + a);
+        const int8_t c = cls[k];
+        re[k] = (c == EL_CUT) ? A.n_band + A.cut_id[e] : (c == EL_OUTSIDE ? -1 : A.band_id[e]);
+    }
+    double s = 0.0;
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        // element (i1-p+a, i2-p+b): the row is its local function (p-a, p-b)
+        const int idx = min(part + 4 * k, L - 1), b = idx / (P + 1), a = idx % (P + 1);
+        const int kk = re[k];
+        const double v = Ye[(size_t)max(kk, 0) * L + (P - b) * (P + 1) + (P - a)];
+        s += (kk >= 0) ? v : 0.0;
+    }
+    s = quad_sum(s);
+    if (ok && part == 0 && !wq_row(A, A.fcls[f])) y[r] = s;
+}
+
 static MfArgs mf_args(Plan& P, const double* c) {
     MfArgs A;
     A.d1 = P.dir[0];
@@ -406,6 +653,26 @@ static void mf_check(const Plan& P) {
                 "matrix-free product: more than 2700 elements along xi_1");
 }
 
+// Strips of test columns and bands of elements of the one-pass forward.
+static MfFwdArgs mf_fwd_shape(const Plan& P) {
+    MfFwdArgs F{};
+    const int ns = (P.n1 + kMfThreads - 1) / kMfThreads;
+    F.cols = (P.n1 + ns - 1) / ns;
+    F.nstrip = (P.n1 + F.cols - 1) / F.cols;
+    F.band = std::max(kMfBand, P.p + 1);
+    IGA_REQUIRE(F.band <= kMfBandMax, IGA_E_UNSUPPORTED, "matrix-free product: band size");
+    F.nband = std::max(1, P.N2 / F.band);
+    for (int st = 0; st < F.nstrip; ++st) {  // points of every strip within the workgroup's share
+        const int c0 = st * F.cols, c1 = std::min(P.n1, c0 + F.cols);
+        const int np = wq_pt0(std::min(P.N1 - 1, c1 - 1) + 1, P.N1, P.p) - wq_pt0(std::max(0, c0 - P.p), P.N1, P.p);
+        // the column sums read up to 2p+1 points past a strip's last one (weight 0 there)
+        IGA_REQUIRE(np + 2 * P.p + 2 <= kMfThreads * kMfNpt, IGA_E_UNSUPPORTED, "matrix-free product: strip point count");
+    }
+    return F;
+}
+
+static size_t mf_part_doubles(const Plan& P, const MfFwdArgs& F) { return 2 * (size_t)F.nband * P.p * P.n1; }
+
 static void mf_buffers(Plan& P) {
     size_t L = (size_t)(P.p + 1) * (P.p + 1);
     mf_check(P);
@@ -414,6 +681,7 @@ static void mf_buffers(Plan& P) {
     if (!P.sw.Ue) P.sw.Ue = P.alloc<double>(std::max<int64_t>(1, P.n_band + P.n_cut_el) * L);
     if (!P.sw.WA) P.sw.WA = P.alloc<double>((size_t)P.dir[0].Q * (P.p + 1));
     if (!P.sw.BR) P.sw.BR = P.alloc<double>((size_t)(4 * P.p + 2) * P.n1);
+    if (!P.sw.mfpart) P.sw.mfpart = P.alloc<double>(mf_part_doubles(P, mf_fwd_shape(P)));
 }
 
 static dim3 grid256(int64_t n) { return dim3((unsigned)((n + 255) / 256)); }
@@ -431,11 +699,28 @@ static void launch_elem(Plan& P, const MfArgs& A, const double* u, const double*
 }
 
 template <int P>
-static void launch_wq_forward(Plan& Pl, const MfArgs& A, const double* u, double* y, double* V, double* H,
-                              hipStream_t s) {
-    hipLaunchKernelGGL(k_mf_v<P>, grid256((int64_t)Pl.n2 * A.d1.Q), dim3(256), 0, s, A, u, V);
-    hipLaunchKernelGGL(k_mf_gh<P>, dim3(A.d2.Q), dim3(256), sizeof(double) * A.d1.Q, s, A, (const double*)V, H);
-    hipLaunchKernelGGL(k_mf_y<P>, grid256((int64_t)Pl.n1 * Pl.n2), dim3(256), 0, s, A, (const double*)H, y);
+static void launch_wq_forward(Plan& Pl, const MfArgs& A, const double* u, double* y, double* part, hipStream_t s) {
+    MfFwdArgs F = mf_fwd_shape(Pl);
+    F.head = part;
+    F.tail = part + (size_t)F.nband * P * Pl.n1;
+    hipLaunchKernelGGL(k_mf_fwd<P>, dim3((unsigned)(F.nstrip * F.nband)), dim3(kMfThreads), 0, s, A, F, u, y);
+    if (F.nband > 1)
+        hipLaunchKernelGGL(k_mf_fix<P>, grid256((int64_t)(F.nband - 1) * P * Pl.n1), dim3(256), 0, s, A, F, y);
+}
+
+static void launch_gather_rows(Plan& P, const MfArgs& A, const double* Ye, double* y, hipStream_t s) {
+    const int nr = (int)P.n_form_rows;
+    if (nr == 0) return;
+    switch (P.p) {
+#define CASE(PP)                                                                                            \
+    case PP:                                                                                                \
+        hipLaunchKernelGGL(k_mf_gather_rows<PP>, grid256(4 * (int64_t)nr), dim3(256), 0, s, A,             \
+                           (const int*)P.form_rows, nr,                                                     \
+                           Ye, y);                                                                          \
+        break;
+        CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
+#undef CASE
+    }
 }
 
 template <int P>
@@ -449,26 +734,24 @@ static void launch_wq_adjoint(Plan& Pl, const MfArgs& A, const double* u, const 
                        (const double*)Pl.sw.V, Pl.sw.H, dc);  // D over H
 }
 
-// The forward product with its three intermediate arrays given: V [n2][Q1],
-// H [Q2][n1], Ue [n_band + n_cut][(p+1)^2]. Every entry of them is written
-// before it is read, so they need no clearing.
+// The forward product with its two intermediate arrays given: the bands'
+// head and tail rows [2][nband][p][n1] and Ue [n_band + n_cut][(p+1)^2].
+// Every entry of them is written before it is read, so they need no clearing.
 // The element part (element vectors, then the rows formed element-wise) runs
 // on the plan's second stream beside the weighted-quadrature part: the two
 // write disjoint rows of y.
-static void mf_apply_into(Plan& P, const double* c, const double* u, double* y, double* V, double* H, double* Ue,
+static void mf_apply_into(Plan& P, const double* c, const double* u, double* y, double* part, double* Ue,
                           hipStream_t s) {
     MfArgs A = mf_args(P, c);
-    int n = (int)P.n_act;
     HIPX(hipEventRecord(P.ev_mf_fork, s));
     HIPX(hipStreamWaitEvent(P.aux, P.ev_mf_fork, 0));
     launch_elem(P, A, u, nullptr, Ue, nullptr, P.aux);
-    hipLaunchKernelGGL(k_mf_gather, dim3((n + 255) / 256), dim3(256), 0, P.aux, A, (const double*)Ue,
-                       (const double*)nullptr, y, 0);
+    launch_gather_rows(P, A, Ue, y, P.aux);
     HIPX(hipEventRecord(P.ev_mf_join, P.aux));
     if (P.method != IGA_GAUSS_REF) {
         switch (P.p) {
 #define CASE(PP) \
-    case PP: launch_wq_forward<PP>(P, A, u, y, V, H, s); break;
+    case PP: launch_wq_forward<PP>(P, A, u, y, part, s); break;
             CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
 #undef CASE
         }
@@ -478,7 +761,7 @@ static void mf_apply_into(Plan& P, const double* c, const double* u, double* y, 
 
 void mf_apply(Plan& P, const double* c, const double* u, double* y, hipStream_t s) {
     mf_buffers(P);
-    mf_apply_into(P, c, u, y, P.sw.V, P.sw.H, P.sw.Ue, s);
+    mf_apply_into(P, c, u, y, P.sw.mfpart, P.sw.Ue, s);
 }
 
 // ------------------------------------------------- allocation-free product
@@ -486,7 +769,7 @@ void mf_apply(Plan& P, const double* c, const double* u, double* y, hipStream_t 
 // device memory that the library holds for the life of the process (one copy
 // per device, at its own address). Every call on a device shares that
 // device's copy: calls that overlap on one device race.
-constexpr size_t kMfScratchDoubles = (size_t)8 << 20;  // 64 MiB
+constexpr size_t kMfScratchDoubles = (size_t)2 << 20;  // 16 MiB
 static __device__ __align__(256) double scratch[kMfScratchDoubles];
 
 constexpr int kMaxDevices = 64;
@@ -513,9 +796,9 @@ static size_t round256(size_t n_doubles) { return (n_doubles + 31) & ~(size_t)31
 static void mf_apply_noalloc(Plan& P, const double* c, const double* u, double* y, hipStream_t s) {
     mf_check(P);
     const size_t L = (size_t)(P.p + 1) * (P.p + 1);
-    const size_t nV = round256((size_t)P.n2 * P.dir[0].Q), nH = round256((size_t)P.dir[1].Q * P.n1);
+    const size_t nP = round256(mf_part_doubles(P, mf_fwd_shape(P)));
     const size_t nU = round256((size_t)std::max<int64_t>(1, P.n_band + P.n_cut_el) * L);
-    const size_t need = nV + nH + nU;
+    const size_t need = nP + nU;
     IGA_REQUIRE(need <= kMfScratchDoubles, IGA_E_CAPACITY,
                 "allocation-free matrix-free product: the patch needs " + std::to_string(need * sizeof(double)) +
                     " bytes of intermediate arrays, more than the " +
@@ -533,7 +816,7 @@ static void mf_apply_noalloc(Plan& P, const double* c, const double* u, double* 
         std::lock_guard<std::mutex> lock(g_scratch_mu);
         base = g_scratch_ptr[dev];
     }
-    mf_apply_into(P, c, u, y, base, base + nV, base + nV + nH, s);
+    mf_apply_into(P, c, u, y, base, base + nP, s);
 }
 
 void mf_adjoint(Plan& P, const double* c, const double* u, const double* r, double* du, double* dc, hipStream_t s) {

@@ -142,6 +142,7 @@ struct SolveWork {
     double* Ue = nullptr;     // matrix-free: element vectors
     double* WA = nullptr;     // matrix-free adjoint: test weights meeting at each xi_1 point [Q1][p+1]
     double* BR = nullptr;     // matrix-free adjoint: basis values at each function's xi_1 points [4p+2][n1]
+    double* mfpart = nullptr; // matrix-free forward: rows split between two bands [2][nband][p][n1]
 };
 
 struct Plan {

@@ -5,7 +5,7 @@
   solved independently (Householder on the device, SVD least squares in the
   oracle), agree row-relatively to max(1e-13, 1e-15 cond), cond being the
   largest condition number of the slot's refined systems.
-* Boxes (reading R8): identical integers for every row formed element-wise.
+* Boxes (the choice of region R among the support's inside boxes): identical integers for every row formed element-wise.
 * P2 (identical rules: the oracle's WQ weights, discontinuous weights and cut
   nodes injected): <= 1e-12 in the metric of the hybrid tests.
 * P3 (the device's own rules): the hybrid bound and floors.

@@ -40,11 +40,14 @@ def _close(dev, ref, scale, tol, label):
     assert err <= tol
 
 
-@pytest.mark.parametrize("N,inject", [(16, True), (72, True), (72, False)])
-def test_apply_and_adjoint_match_oracle(N, inject):
-    torch, igatrim, cfg, plan, c, o = _setup(N, inject=inject)
+# one band of elements (N = 16), several bands (72, 40: rows whose support spans two
+# bands are summed from both), several strips of test columns (140), degrees 2, 4, 6
+@pytest.mark.parametrize("N,p,inject", [(16, 4, True), (72, 4, True), (72, 4, False), (140, 4, True),
+                                        (40, 2, True), (40, 6, True)])
+def test_apply_and_adjoint_match_oracle(N, p, inject):
+    torch, igatrim, cfg, plan, c, o = _setup(N, p=p, inject=inject)
     tol = 1e-12 if inject else 1e-9
-    say(f"[mf] p=4 N={N} n_act={plan.sizes['n_act']} n_points={plan.sizes['n_points']}")
+    say(f"[mf] p={p} N={N} n_act={plan.sizes['n_act']} n_points={plan.sizes['n_points']}")
     What, Bmat = matfree.operators(o)
     x, y, *_ = matfree.rule_points(o)
     pts = plan.points().cpu().numpy()

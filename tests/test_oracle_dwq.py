@@ -2,10 +2,10 @@
 
 * knot insertion: the subdivision matrix against SciPy's knot insertion and
   against direct evaluation of the refined basis;
-* nested points (reading R9) against their closed form;
+* nested points (largest resulting gap first) against their closed form;
 * the 1-D rule's defining property (separability at t): on each side of t
   it integrates B_j B_i exactly for every trial function j;
-* the box choice (reading R8) on hand-made class patterns;
+* the box choice (largest inside box, fewer discontinuities, enumeration order) on hand-made class patterns;
 * the 2-D DWQ matrix against element-wise Gauss at c = 1 (Table 1, middle
   column) and its area invariant.
 """

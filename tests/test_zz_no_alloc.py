@@ -56,10 +56,10 @@ def test_noalloc_equals_apply_twice():
 def test_noalloc_rejects_oversized_patch():
     torch = require_gpu()
     from paper_2101_08053_amd import igatrim
-    plan, c, u = _case(1500, 2)  # needs about 2 x 36 MB of intermediate arrays
+    plan, c, u = _case(2000, 2)  # needs about 16 MB of band rows and 10 MB of element vectors
     y = torch.zeros_like(u)
     code = _noalloc(plan, c, u, y)
     msg = igatrim.lib().iga_last_error().decode()
-    say(f"[noalloc] N=1500: code {code}: {msg}")
+    say(f"[noalloc] N=2000: code {code}: {msg}")
     assert code == -7 and "scratch" in msg
     assert not torch.any(y)
