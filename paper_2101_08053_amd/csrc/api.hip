@@ -21,7 +21,7 @@ Plan::~Plan() {
     if (fgraph) hipGraphDestroy(fgraph);
     if (cap_stream) hipStreamDestroy(cap_stream);
     if (sw.h_scal) hipHostFree(sw.h_scal);
-    for (hipEvent_t e : {ev_fork, ev_iso, ev_lists, ev_interior, ev_band, ev_classes, ev_mf_fork, ev_mf_join})
+    for (hipEvent_t e : {ev_fork, ev_iso, ev_lists, ev_interior, ev_band, ev_classes})
         if (e) hipEventDestroy(e);
     if (aux) hipStreamDestroy(aux);
     for (auto& e : ev_pool) hipEventDestroy(e);
@@ -425,8 +425,7 @@ int iga_trim_plan_create(const iga_patch_desc* desc, const iga_opts* opts, iga_p
     HIPX(hipGetDevice(&P->device));
     mf_scratch_init(P->device);  // the allocation-free product's scratch address on this device
     HIPX(hipStreamCreateWithFlags(&P->aux, hipStreamNonBlocking));
-    for (hipEvent_t* e : {&P->ev_fork, &P->ev_iso, &P->ev_lists, &P->ev_interior, &P->ev_band, &P->ev_classes,
-                          &P->ev_mf_fork, &P->ev_mf_join})
+    for (hipEvent_t* e : {&P->ev_fork, &P->ev_iso, &P->ev_lists, &P->ev_interior, &P->ev_band, &P->ev_classes})
         HIPX(hipEventCreateWithFlags(e, hipEventDisableTiming));
     P->p = p;
     P->method = desc->method;

@@ -102,20 +102,24 @@ __global__ void __launch_bounds__(256) k_mf_hadj(MfArgs A, const double* __restr
 //   G[k1] = c_k sum_b B2[k2][b] V[e2(k2)+b][k1]   (the strip's points of row k2, LDS),
 //   H(i1) = sum_q w1[i1][q] G[k0(i1)+q]            (registers),
 //   acc[i2] += w2[i2][k2 - k0(i2)] H(i1)           for the p+1 rows i2 = e2..e2+p.
-// When element e2 ends, row e2 has all of this band's terms: it is written to
-// y if its support lies in the band (or starts at the patch edge), otherwise
-// as the band's head part of that row; the p rows after the band are written
-// as its tail part, and k_mf_fix adds a band's head to the previous band's
-// tail. c rows are loaded two grid rows ahead and u rows one element ahead
-// (their active ids two); the values every thread needs at a grid row (B2,
-// w2, element bounds) are staged in LDS once, so no load in the loop waits
-// on a later-issued one. c is read once; V and H never leave the workgroup.
+// Rows go two at a time (one pair of barriers per two rows, their chains
+// interleaved): each element's rows are laid out in an even number of slots,
+// a padding slot having B2 = w2 = 0. When element e2 ends, row e2 has all of
+// this band's terms: it is written to y if its support lies in the band (or
+// starts at the patch edge), otherwise as the band's head part of that row;
+// the p rows after the band are written as its tail part, and k_mf_fix adds
+// a band's head to the previous band's tail. c rows are loaded two pairs
+// ahead and u rows one element ahead (their active ids two); the values every
+// thread needs at a slot (row, B2, w2, element bounds) are staged in LDS once,
+// so no load in the loop waits on a later-issued one. c is read once; V and H
+// never leave the workgroup.
 constexpr int kMfThreads = 128;  // threads = test columns per strip (at most)
-constexpr int kMfNpt = 3;        // xi_1 points per thread (a strip has at most 2 (cols + p) + 2 (p - 1))
+constexpr int kMfNpt = 2;        // xi_1 points per thread (a strip has at most 2 (cols + p) + 2 (p - 1))
 constexpr int kMfUpt = 2;        // u columns per thread (cols + 2p)
 constexpr int kMfBand = 8;       // elements per band, at least p+1 (the last band takes the remainder)
 constexpr int kMfBandMax = kMfBand > IGA_MAXP + 1 ? kMfBand : IGA_MAXP + 1;
-constexpr int kMfRows = 2 * (2 * kMfBandMax - 1) + 2 * IGA_MAXP;  // grid rows of a band (+1 pad), at most
+// slots of a band: its rows, one padding slot per end element of odd row count, padding to 4 slots
+constexpr int kMfSlots = 2 * (2 * kMfBandMax - 1) + 2 * IGA_MAXP + 2 + 4;
 
 struct MfFwdArgs {
     int cols;     // test columns per strip
@@ -128,30 +132,45 @@ struct MfFwdArgs {
 template <int P>
 __global__ void __launch_bounds__(kMfThreads) k_mf_fwd(MfArgs A, MfFwdArgs F, const double* __restrict__ u,
                                                        double* __restrict__ y) {
-    constexpr int NP = kMfThreads * kMfNpt, NW = 2 * P + 2, QM = 4 * P + 2;
-    __shared__ double sU[kMfThreads * kMfUpt];
+    constexpr int NP = kMfThreads * kMfNpt, NW = 2 * P + 2, QM = 4 * P + 2, NU = kMfThreads * kMfUpt;
+    constexpr int NG = NP + QM;   // the column sums read up to 4p+1 points past a strip's last one
+    __shared__ double sU[P][NU];
     __shared__ double sV[P + 1][NP];
-    __shared__ double sG[2][NP];
-    __shared__ double sB2[kMfRows][P + 1], sW2[kMfRows][P + 1];
-    __shared__ int sPt[2 * kMfBandMax];
+    __shared__ double sG[2][NG];
+    __shared__ double sB2[kMfSlots][P + 1], sW2[kMfSlots][P + 1];
+    __shared__ int sK2[kMfSlots];
+    __shared__ int sEs[2 * kMfBandMax + 1];   // first slot of each element of the band, then the end
     const int tid = threadIdx.x;
     const int strip = blockIdx.x % F.nstrip, bnd = blockIdx.x / F.nstrip;
     const int n1 = A.n1, N1 = A.N1, N2 = A.N2, Q1 = A.d1.Q;
     const int c0 = strip * F.cols, c1 = min(n1, c0 + F.cols);
-    const int E0 = bnd * F.band, E1 = (bnd == F.nband - 1) ? N2 : E0 + F.band;
-    const int kA = A.d1.pt0[max(0, c0 - P)], kB = A.d1.pt0[min(N1 - 1, c1 - 1) + 1];
+    const int E0 = bnd * F.band, E1 = (bnd == F.nband - 1) ? N2 : E0 + F.band, NE = E1 - E0;
     const int jA = max(0, c0 - P), jB = min(N1 - 1, c1 - 1) + P + 1;
-    const int KA2 = A.d2.pt0[E0], KB2 = A.d2.pt0[E1];
-    // the band's per-row values: element bounds, B2 and the test weights w2 meeting at each row
-    for (int t = tid; t <= E1 - E0; t += kMfThreads) sPt[t] = A.d2.pt0[E0 + t] - KA2;
-    // (rows are taken in pairs: an odd count gets one more row with B2 = w2 = 0)
-    for (int t = tid; t < ((KB2 - KA2 + 1) & ~1) * (P + 1); t += kMfThreads) {
-        const int r = t / (P + 1), b = t % (P + 1), k2 = min(KA2 + r, KB2 - 1);
-        const int i2 = A.d2.eq[k2] + b;
-        const bool in = KA2 + r < KB2;
-        sB2[r][b] = in ? A.d2.Bq[(size_t)k2 * (P + 1) + b] : 0.0;
-        sW2[r][b] = in ? A.d2.W[(size_t)i2 * A.d2.qmax + (k2 - A.d2.pt0[max(0, i2 - P)])] : 0.0;
-    }
+    // Every load in the loop is unconditional (clamped address) and its value
+    // is selected where it is used: a load under a branch, or a select next to
+    // the load, makes the wave wait for it there -- and, the memory counter
+    // being in order, for every load issued before it.
+    bool ucol[kMfUpt];
+#pragma unroll
+    for (int v = 0; v < kMfUpt; ++v) ucol[v] = jA + tid + kMfThreads * v < jB;
+    auto u_ids = [&](int j2, int (&id)[kMfUpt]) {   // rows past the last are never used
+#pragma unroll
+        for (int v = 0; v < kMfUpt; ++v)
+            id[v] = A.act_of[(size_t)min(j2, A.n2 - 1) * n1 + min(jA + tid + kMfThreads * v, jB - 1)];
+    };
+    auto u_vals = [&](const int (&id)[kMfUpt], double (&val)[kMfUpt]) {
+#pragma unroll
+        for (int v = 0; v < kMfUpt; ++v) val[v] = u[max(id[v], 0)];
+    };
+    auto u_ok = [&](const int (&id)[kMfUpt], bool (&ok)[kMfUpt]) {
+#pragma unroll
+        for (int v = 0; v < kMfUpt; ++v) ok[v] = ucol[v] && id[v] >= 0;
+    };
+    // the ids of u rows E0 .. E0+p+1 first (they need nothing else)
+    int idp[P + 2][kMfUpt];
+#pragma unroll
+    for (int j = 0; j < P + 2; ++j) u_ids(E0 + j, idp[j]);
+    const int kA = A.d1.pt0[max(0, c0 - P)], kB = A.d1.pt0[min(N1 - 1, c1 - 1) + 1];
     // the thread's points: basis values and local element
     double B1[kMfNpt][P + 1];
     int le1[kMfNpt];
@@ -177,58 +196,41 @@ __global__ void __launch_bounds__(kMfThreads) k_mf_fwd(MfArgs A, MfFwdArgs F, co
 #pragma unroll
     for (int q = NW; q < QM; ++q) w1[q] = (q < nq1) ? A.d1.W[(size_t)ic * A.d1.qmax + q] : 0.0;
     const bool wide = nq1 > NW;   // a column next to a patch end
+    // element slot table: element e of the band takes round-up-even(rows of e) slots
+    if (tid <= NE) sEs[tid] = (tid < NE) ? A.d2.pt0[E0 + tid + 1] - A.d2.pt0[E0 + tid] : 0;
+    __syncthreads();
+    if (tid == 0) {
+        int s = 0;
+        for (int e = 0; e < NE; ++e) {
+            const int n = sEs[e];
+            sEs[e] = s;
+            s += (n + 1) & ~1;
+        }
+        sEs[NE] = s;
+    }
+    __syncthreads();
+    const int S = sEs[NE], S4 = (S + 3) & ~3;
+    for (int t = tid; t < S4 * (P + 1); t += kMfThreads) {
+        const int s = t / (P + 1), b = t % (P + 1);
+        int e = 0;
+        for (int k = 1; k < NE; ++k) e += (sEs[k] <= s);
+        const int ke = A.d2.pt0[E0 + e];
+        const int n = A.d2.pt0[E0 + e + 1] - ke;
+        const bool in = s < S && s - sEs[e] < n;
+        const int k2 = in ? ke + (s - sEs[e]) : ke;
+        const int i2 = E0 + e + b;
+        const double bq = A.d2.Bq[(size_t)k2 * (P + 1) + b];
+        const double wq = A.d2.W[(size_t)i2 * A.d2.qmax + (k2 - A.d2.pt0[max(0, i2 - P)])];
+        sB2[s][b] = in ? bq : 0.0;
+        sW2[s][b] = in ? wq : 0.0;
+        if (b == 0) sK2[s] = k2;   // padding slots read a real row of c (weight 0)
+    }
     // points past the strip's last one are read with weight 0: keep them finite
-    for (int k = (kB - kA) + tid; k < NP; k += kMfThreads) {
+    for (int k = (kB - kA) + tid; k < NG; k += kMfThreads) {
         sG[0][k] = 0.0;
         sG[1][k] = 0.0;
     }
-    // Every load in the loop is unconditional (clamped address) and its value
-    // is selected where it is used: a load under a branch, or a select next to
-    // the load, makes the wave wait for it there -- and, the memory counter
-    // being in order, for every load issued before it.
-    bool ucol[kMfUpt];
-#pragma unroll
-    for (int v = 0; v < kMfUpt; ++v) ucol[v] = jA + tid + kMfThreads * v < jB;
-    auto u_ids = [&](int j2, int (&id)[kMfUpt]) {   // rows past the last are never used
-#pragma unroll
-        for (int v = 0; v < kMfUpt; ++v)
-            id[v] = A.act_of[(size_t)min(j2, A.n2 - 1) * n1 + min(jA + tid + kMfThreads * v, jB - 1)];
-    };
-    auto u_vals = [&](const int (&id)[kMfUpt], double (&val)[kMfUpt]) {
-#pragma unroll
-        for (int v = 0; v < kMfUpt; ++v) val[v] = u[max(id[v], 0)];
-    };
-    // V of u row j2 from the values in sU (after a barrier) into its ring slot
-    auto v_row = [&](int j2) {
-        double* dst = sV[j2 % (P + 1)];
-#pragma unroll
-        for (int m = 0; m < kMfNpt; ++m) {
-            double s = 0.0;
-#pragma unroll
-            for (int a = 0; a <= P; ++a) s += B1[m][a] * sU[le1[m] + a];
-            if (pv[m]) dst[tid + kMfThreads * m] = s;
-        }
-    };
-    auto put_u = [&](const double (&val)[kMfUpt], const bool (&ok)[kMfUpt]) {
-#pragma unroll
-        for (int v = 0; v < kMfUpt; ++v) sU[tid + kMfThreads * v] = ok[v] ? val[v] : 0.0;
-    };
-    auto u_ok = [&](const int (&id)[kMfUpt], bool (&ok)[kMfUpt]) {
-#pragma unroll
-        for (int v = 0; v < kMfUpt; ++v) ok[v] = ucol[v] && id[v] >= 0;
-    };
-    auto c_row = [&](int k2, double (&dst)[kMfNpt]) {
-#pragma unroll
-        for (int m = 0; m < kMfNpt; ++m) {
-            const int k1 = min(kA + tid + kMfThreads * m, kB - 1);
-            dst[m] = A.c[(size_t)min(k2, KB2 - 1) * Q1 + k1];
-        }
-    };
-    // prologue: u rows E0 .. E0+p-1 into the ring
-    // (the ids of rows E0 .. E0+p+1 are loaded together, then the values of rows E0 .. E0+p)
-    int idp[P + 2][kMfUpt];
-#pragma unroll
-    for (int j = 0; j < P + 2; ++j) u_ids(E0 + j, idp[j]);
+    // u values of rows E0 .. E0+p; rows E0 .. E0+p-1 into the V ring
     double up[P + 1][kMfUpt];
     bool okp[P + 1][kMfUpt];
 #pragma unroll
@@ -237,12 +239,23 @@ __global__ void __launch_bounds__(kMfThreads) k_mf_fwd(MfArgs A, MfFwdArgs F, co
         u_ok(idp[j], okp[j]);
     }
 #pragma unroll
-    for (int j = 0; j < P; ++j) {
-        __syncthreads();
-        put_u(up[j], okp[j]);
-        __syncthreads();
-        v_row(E0 + j);
-    }
+    for (int j = 0; j < P; ++j)
+#pragma unroll
+        for (int v = 0; v < kMfUpt; ++v) sU[j][tid + kMfThreads * v] = okp[j][v] ? up[j][v] : 0.0;
+    __syncthreads();
+    // V of u row j2 from the values in sU[slot] into its ring slot
+    auto v_row = [&](int j2, const double* su) {
+        double* dst = sV[j2 % (P + 1)];
+#pragma unroll
+        for (int m = 0; m < kMfNpt; ++m) {
+            double s = 0.0;
+#pragma unroll
+            for (int a = 0; a <= P; ++a) s += B1[m][a] * su[le1[m] + a];
+            if (pv[m]) dst[tid + kMfThreads * m] = s;
+        }
+    };
+#pragma unroll
+    for (int j = 0; j < P; ++j) v_row(E0 + j, sU[j]);
     int idb[kMfUpt];
     double uv[kMfUpt];
     bool uok[kMfUpt];
@@ -252,29 +265,37 @@ __global__ void __launch_bounds__(kMfThreads) k_mf_fwd(MfArgs A, MfFwdArgs F, co
         uok[v] = okp[P][v];
         idb[v] = idp[P + 1][v];    // ids of row E0+p+1
     }
-    // c rows two ahead, in two buffers that alternate (no copies: a copy of a
-    // loaded value waits for the load)
-    double ca[kMfNpt], cb[kMfNpt];
-    c_row(KA2, ca);
-    c_row(KA2 + 1, cb);
+    // c of a pair of slots, two pairs ahead, in two buffers (no copies: a copy of a loaded value waits for it)
+    auto c_pair = [&](int s, double (&dst)[2][kMfNpt]) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int k2 = sK2[min(s + h, S4 - 1)];
+#pragma unroll
+            for (int m = 0; m < kMfNpt; ++m) dst[h][m] = A.c[(size_t)k2 * Q1 + min(kA + tid + kMfThreads * m, kB - 1)];
+        }
+    };
+    double ca[2][kMfNpt], cb[2][kMfNpt];
+    c_pair(0, ca);
+    c_pair(2, cb);
     double acc[P + 1];
 #pragma unroll
     for (int b = 0; b <= P; ++b) acc[b] = 0.0;
-    int e2 = E0, rend = 0, yid = -1;
+    int e2 = E0, send = 0, yid = -1;
     int8_t ycls = 0;
     // element e2 starts: its new u row e2+p into the ring, the next rows' loads, row e2's output id
     auto start = [&]() {
         __syncthreads();
-        put_u(uv, uok);
+#pragma unroll
+        for (int v = 0; v < kMfUpt; ++v) sU[0][tid + kMfThreads * v] = uok[v] ? uv[v] : 0.0;
         __syncthreads();
-        v_row(e2 + P);
+        v_row(e2 + P, sU[0]);
         u_vals(idb, uv);            // row e2+p+1
         u_ok(idb, uok);
         u_ids(e2 + P + 2, idb);     // ids of row e2+p+2
         const size_t f = (size_t)e2 * n1 + ic;
         yid = A.act_of[f];
         ycls = A.fcls[f];
-        rend = sPt[e2 - E0 + 1];
+        send = sEs[e2 - E0 + 1];
     };
     // element e2 ends: row e2 has all of the band's terms
     auto finish = [&]() {
@@ -290,39 +311,53 @@ __global__ void __launch_bounds__(kMfThreads) k_mf_fwd(MfArgs A, MfFwdArgs F, co
         acc[P] = 0.0;
         ++e2;
     };
-    // grid row r of the band with its c values in cbuf; cbuf then takes row r+2
-    auto row = [&](int r, double (&cbuf)[kMfNpt]) {
-        double* g = sG[r & 1];
-        __syncthreads();  // the ring row written at the element start
+    // slots s, s+1 of element e2 with their c values in cbuf; cbuf then takes slots s+4, s+5
+    auto pair = [&](int s, double (&cbuf)[2][kMfNpt]) {
+        __syncthreads();  // the ring row written at the element start; sG read by the last pair
 #pragma unroll
         for (int m = 0; m < kMfNpt; ++m) {
             const int k = tid + kMfThreads * m;
-            double s = 0.0;
+            double s0 = 0.0, s1 = 0.0;
 #pragma unroll
-            for (int b = 0; b <= P; ++b) s += sB2[r][b] * sV[(e2 + b) % (P + 1)][min(k, NP - 1)];
-            if (pv[m]) g[k] = cbuf[m] * s;
+            for (int b = 0; b <= P; ++b) {
+                const double v = sV[(e2 + b) % (P + 1)][k];
+                s0 += sB2[s][b] * v;
+                s1 += sB2[s + 1][b] * v;
+            }
+            if (pv[m]) {
+                sG[0][k] = cbuf[0][m] * s0;
+                sG[1][k] = cbuf[1][m] * s1;
+            }
         }
-        c_row(KA2 + r + 2, cbuf);
+        c_pair(s + 4, cbuf);
         __syncthreads();
-        double h = 0.0;
+        double h0 = 0.0, h1 = 0.0;
 #pragma unroll
-        for (int q = 0; q < NW; ++q) h += w1[q] * g[k0l + q];
+        for (int q = 0; q < NW; ++q) {
+            h0 += w1[q] * sG[0][k0l + q];
+            h1 += w1[q] * sG[1][k0l + q];
+        }
         if (wide) {
 #pragma unroll
-            for (int q = NW; q < QM; ++q) h += w1[q] * g[min(k0l + q, NP - 1)];
+            for (int q = NW; q < QM; ++q) {
+                h0 += w1[q] * sG[0][k0l + q];
+                h1 += w1[q] * sG[1][k0l + q];
+            }
         }
 #pragma unroll
-        for (int b = 0; b <= P; ++b) acc[b] += sW2[r][b] * h;
-        if (r + 1 == rend) {
+        for (int b = 0; b <= P; ++b) {
+            acc[b] += sW2[s][b] * h0;
+            acc[b] += sW2[s + 1][b] * h1;
+        }
+        if (s + 2 == send) {
             finish();
             if (e2 < E1) start();
         }
     };
     start();
-    const int R = KB2 - KA2;
-    for (int r = 0; r < R; r += 2) {  // both rows unconditional: a skipped row would make the waits conservative
-        row(r, ca);
-        row(r + 1, cb);
+    for (int s = 0; s < S4; s += 4) {  // every pair unconditional: a skipped one would make the waits conservative
+        pair(s, ca);
+        pair(s + 2, cb);
     }
     if (!has_col) return;
 #pragma unroll
@@ -436,28 +471,116 @@ __global__ void __launch_bounds__(256) k_mf_rd(MfArgs A, const double* __restric
 // Element part: per band / cut element, forward Y_e[l] = sum_g w_g c_g U_g B_l(x_g),
 // adjoint D_e[l] = sum_g c_g R_g B_l(x_g) with R_g = w_g sum_l B_l r_l over the
 // element-formed rows, and dc_g = U_g R_g.
+// Band elements (inside elements of the rows formed element-wise; a tensor
+// Gauss rule of (p+1)^2 points): several elements per 256-thread workgroup,
+// thread (element, l) taking local function l for u, point l for U, and
+// output l, the element's basis tables shared in LDS:
+//   U_g = sum_a2 B2[g2][a2] sum_a1 B1[g1][a1] u_a,  Y_l = sum_g2 B2[g2][l2] sum_g1 B1[g1][l1] w_g c_g U_g
+// (adjoint: R_g from r alike, dc_g = U_g w_g R_g, D_l from c_g w_g R_g).
 template <int P>
-__global__ void __launch_bounds__(64) k_mf_elem(MfArgs A, const double* __restrict__ u, const double* __restrict__ r,
-                                                double* __restrict__ Ye, double* __restrict__ dc) {
-    constexpr int L = (P + 1) * (P + 1);
-    constexpr int PER = (L + 63) / 64;
-    // per node of the chunk: its two basis rows and its weight term (the products
-    // B1 B2 are formed where they are used, so little LDS is held per workgroup)
-    __shared__ double sB1[64][P + 1], sB2[64][P + 1];
+__global__ void __launch_bounds__(256) k_mf_band(MfArgs A, const double* __restrict__ u, const double* __restrict__ r,
+                                                 double* __restrict__ Ye, double* __restrict__ dc) {
+    constexpr int NP1 = P + 1, L = NP1 * NP1, EPW = 256 / L;
+    __shared__ double sU[EPW][L], sR[EPW][L], sT[EPW][L];
+    __shared__ double sB1[EPW][NP1][NP1], sB2[EPW][NP1][NP1];
+    const int el = threadIdx.x / L, l = threadIdx.x % L;
+    const int re = blockIdx.x * EPW + el;
+    const bool on = el < EPW && re < A.n_band;
+    const int e = A.band_list[on ? re : 0];
+    const int e1 = e % A.N1, e2 = e / A.N1;
+    const int l1 = l % NP1, l2 = l / NP1;   // local function, point (g1, g2) and output alike
+    double B1[NP1], B2[NP1];
+#pragma unroll
+    for (int a = 0; a <= P; ++a) {
+        B1[a] = A.d1.Bg[(e1 * NP1 + l1) * NP1 + a];
+        B2[a] = A.d2.Bg[(e2 * NP1 + l2) * NP1 + a];
+    }
+    const double w = A.d1.wg[e1 * NP1 + l1] * A.d2.wg[e2 * NP1 + l2];
+    const size_t pt = (size_t)A.nq + (size_t)(on ? re : 0) * L + l;
+    const double cg = A.c[pt];
+    const int f = (e2 + l2) * A.n1 + (e1 + l1);
+    const int cid = A.act_of[f];
+    if (on) {
+        sU[el][l] = (cid >= 0) ? u[cid] : 0.0;
+        // rows formed element-wise: cut rows (hybrid) or every row (reference)
+        const bool erow = cid >= 0 && !wq_row(A, A.fcls[f]);
+        sR[el][l] = (r && erow) ? r[cid] : 0.0;
+#pragma unroll
+        for (int a = 0; a <= P; ++a) {
+            if (l2 == 0) sB1[el][l1][a] = B1[a];
+            if (l1 == 0) sB2[el][l2][a] = B2[a];
+        }
+    }
+    __syncthreads();
+    if (on) {
+        double Ug = 0.0, Rg = 0.0;
+#pragma unroll
+        for (int a2 = 0; a2 <= P; ++a2) {
+            double su = 0.0, sr = 0.0;
+#pragma unroll
+            for (int a1 = 0; a1 <= P; ++a1) {
+                su += B1[a1] * sU[el][a2 * NP1 + a1];
+                sr += B1[a1] * sR[el][a2 * NP1 + a1];
+            }
+            Ug += B2[a2] * su;
+            Rg += B2[a2] * sr;
+        }
+        if (r) {
+            Rg *= w;
+            dc[pt] = Ug * Rg;
+            sT[el][l] = cg * Rg;
+        } else {
+            sT[el][l] = w * cg * Ug;
+        }
+    }
+    __syncthreads();
+    if (!on) return;
+    double y = 0.0;
+#pragma unroll
+    for (int g2 = 0; g2 <= P; ++g2) {
+        double s = 0.0;
+#pragma unroll
+        for (int g1 = 0; g1 <= P; ++g1) s += sB1[el][g1][l1] * sT[el][g2 * NP1 + g1];
+        y += sB2[el][g2][l2] * s;
+    }
+    Ye[(size_t)re * L + l] = y;
+}
+
+// Cut elements, one 64-thread workgroup each: per chunk of 64 nodes, node n's
+// basis rows (from the element's reciprocal table: no divisions), U_n and
+// the weight term T_n in LDS; then the (p+1)^2 outputs are split over
+// G = max(1, 64 / (p+1)^2) lane groups, group g summing the chunk's nodes
+// m = g (mod G), and the groups' sums are added in order at the end.
+template <int P>
+__global__ void __launch_bounds__(64) k_mf_elem(MfArgs A, int re0, const double* __restrict__ u,
+                                                const double* __restrict__ r, double* __restrict__ Ye,
+                                                double* __restrict__ dc) {
+    constexpr int NP1 = P + 1, L = NP1 * NP1;
+    constexpr int G = L >= 64 ? 1 : 64 / L;      // lane groups of the accumulation
+    constexpr int PER = (L + 63) / 64;           // outputs per lane when G = 1
+    constexpr int NR = P * (P + 1) / 2;          // reciprocals of one span
+    __shared__ double sB1[64][NP1], sB2[64][NP1];
     __shared__ double sT[64];
     __shared__ double sU[L], sR[L];
-    int re = blockIdx.x;
-    bool is_cut = re >= A.n_band;
-    int e = is_cut ? A.cut_list[re - A.n_band] : A.band_list[re];
-    int e1 = e % A.N1, e2 = e / A.N1;
-    for (int l = threadIdx.x; l < L; l += 64) {
-        int j1 = e1 + l % (P + 1), j2 = e2 + l / (P + 1);
+    __shared__ double sRec[2][NR + 1];
+    __shared__ double sAcc[G][L];
+    const int tid = threadIdx.x;
+    const int re = re0 + blockIdx.x;
+    const bool is_cut = re >= A.n_band;
+    const int e = is_cut ? A.cut_list[re - A.n_band] : A.band_list[re];
+    const int e1 = e % A.N1, e2 = e / A.N1;
+    for (int l = tid; l < L; l += 64) {
+        int j1 = e1 + l % NP1, j2 = e2 + l / NP1;
         int f = j2 * A.n1 + j1;
         int cid = A.act_of[f];
         sU[l] = (cid >= 0) ? u[cid] : 0.0;
         // rows formed element-wise: cut rows (hybrid) or every row (reference)
         bool erow = cid >= 0 && !wq_row(A, A.fcls[f]);
         sR[l] = (r && erow) ? r[cid] : 0.0;
+    }
+    if (tid < 2 * NR) {
+        const int d = tid / NR, idx = tid % NR;
+        sRec[d][idx] = basis_rec<P>(d ? A.d2.knots : A.d1.knots, P + (d ? e2 : e1), idx);
     }
     int nb, ne, pbase;
     if (is_cut) {
@@ -469,26 +592,29 @@ __global__ void __launch_bounds__(64) k_mf_elem(MfArgs A, const double* __restri
         ne = L;
         pbase = A.nq + re * L;
     }
+    // this lane's outputs: group grp, local functions l = li + 64 k (G = 1) or li (G > 1)
+    const int grp = (G > 1) ? tid / L : 0, li = (G > 1) ? tid % L : tid;
+    const bool acc_on = (G > 1) ? grp < G : true;
     double acc[PER];
 #pragma unroll
     for (int k = 0; k < PER; ++k) acc[k] = 0.0;
     for (int base = nb; base < ne; base += 64) {
         __syncthreads();
-        int n = base + threadIdx.x;
+        int n = base + tid;
         if (n < ne) {
-            double B1[P + 1], B2[P + 1], w;
+            double B1[NP1], B2[NP1], w;
             if (is_cut) {
-                basis_eval<P>(A.d1.knots, P + e1, A.nx[n], B1);
-                basis_eval<P>(A.d2.knots, P + e2, A.ny[n], B2);
+                basis_eval_rec<P>(A.d1.knots, P + e1, sRec[0], A.nx[n], B1);
+                basis_eval_rec<P>(A.d2.knots, P + e2, sRec[1], A.ny[n], B2);
                 w = A.nw[n];
             } else {
-                int g1 = n % (P + 1), g2 = n / (P + 1);
+                int g1 = n % NP1, g2 = n / NP1;
 #pragma unroll
                 for (int a = 0; a <= P; ++a) {
-                    B1[a] = A.d1.Bg[(e1 * (P + 1) + g1) * (P + 1) + a];
-                    B2[a] = A.d2.Bg[(e2 * (P + 1) + g2) * (P + 1) + a];
+                    B1[a] = A.d1.Bg[(e1 * NP1 + g1) * NP1 + a];
+                    B2[a] = A.d2.Bg[(e2 * NP1 + g2) * NP1 + a];
                 }
-                w = A.d1.wg[e1 * (P + 1) + g1] * A.d2.wg[e2 * (P + 1) + g2];
+                w = A.d1.wg[e1 * NP1 + g1] * A.d2.wg[e2 * NP1 + g2];
             }
             double Ug = 0.0, Rg = 0.0;
 #pragma unroll
@@ -496,41 +622,54 @@ __global__ void __launch_bounds__(64) k_mf_elem(MfArgs A, const double* __restri
                 double su = 0.0, sr = 0.0;
 #pragma unroll
                 for (int a1 = 0; a1 <= P; ++a1) {
-                    su += B1[a1] * sU[a2 * (P + 1) + a1];
-                    sr += B1[a1] * sR[a2 * (P + 1) + a1];
+                    su += B1[a1] * sU[a2 * NP1 + a1];
+                    sr += B1[a1] * sR[a2 * NP1 + a1];
                 }
                 Ug += B2[a2] * su;
                 Rg += B2[a2] * sr;
             }
 #pragma unroll
             for (int a = 0; a <= P; ++a) {
-                sB1[threadIdx.x][a] = B1[a];
-                sB2[threadIdx.x][a] = B2[a];
+                sB1[tid][a] = B1[a];
+                sB2[tid][a] = B2[a];
             }
             double cg = A.c[pbase + n];
             if (r) {
                 Rg *= w;
                 dc[pbase + n] = Ug * Rg;
-                sT[threadIdx.x] = cg * Rg;
+                sT[tid] = cg * Rg;
             } else {
-                sT[threadIdx.x] = w * cg * Ug;
+                sT[tid] = w * cg * Ug;
             }
         }
         __syncthreads();
-        int cnt = min(64, ne - base);
+        const int cnt = min(64, ne - base);
+        if (acc_on) {
 #pragma unroll
-        for (int k = 0; k < PER; ++k) {
-            int l = threadIdx.x + 64 * k;
-            if (l < L) {
-                const int a1 = l % (P + 1), a2 = l / (P + 1);
-                for (int m = 0; m < cnt; ++m) acc[k] += sT[m] * sB1[m][a1] * sB2[m][a2];
+            for (int k = 0; k < PER; ++k) {
+                const int l = li + 64 * k;
+                if (l < L) {
+                    const int a1 = l % NP1, a2 = l / NP1;
+                    for (int m = grp; m < cnt; m += G) acc[k] += sT[m] * sB1[m][a1] * sB2[m][a2];
+                }
             }
         }
     }
+    if (G > 1) {
+        if (acc_on) sAcc[grp][li] = acc[0];
+        __syncthreads();
+        if (tid < L) {
+            double s = 0.0;
 #pragma unroll
-    for (int k = 0; k < PER; ++k) {
-        int l = threadIdx.x + 64 * k;
-        if (l < L) Ye[(size_t)re * L + l] = acc[k];
+            for (int g = 0; g < G; ++g) s += sAcc[g][tid];
+            Ye[(size_t)re * L + tid] = s;
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            const int l = li + 64 * k;
+            if (l < L) Ye[(size_t)re * L + l] = acc[k];
+        }
     }
 }
 
@@ -656,7 +795,8 @@ static void mf_check(const Plan& P) {
 // Strips of test columns and bands of elements of the one-pass forward.
 static MfFwdArgs mf_fwd_shape(const Plan& P) {
     MfFwdArgs F{};
-    const int ns = (P.n1 + kMfThreads - 1) / kMfThreads;
+    const int cmax = std::min(kMfThreads, (kMfThreads * kMfNpt - 2 * (P.p - 1)) / 2 - P.p);  // 2 (cols + p) + 2 (p - 1) points
+    const int ns = (P.n1 + cmax - 1) / cmax;
     F.cols = (P.n1 + ns - 1) / ns;
     F.nstrip = (P.n1 + F.cols - 1) / F.cols;
     F.band = std::max(kMfBand, P.p + 1);
@@ -665,8 +805,7 @@ static MfFwdArgs mf_fwd_shape(const Plan& P) {
     for (int st = 0; st < F.nstrip; ++st) {  // points of every strip within the workgroup's share
         const int c0 = st * F.cols, c1 = std::min(P.n1, c0 + F.cols);
         const int np = wq_pt0(std::min(P.N1 - 1, c1 - 1) + 1, P.N1, P.p) - wq_pt0(std::max(0, c0 - P.p), P.N1, P.p);
-        // the column sums read up to 2p+1 points past a strip's last one (weight 0 there)
-        IGA_REQUIRE(np + 2 * P.p + 2 <= kMfThreads * kMfNpt, IGA_E_UNSUPPORTED, "matrix-free product: strip point count");
+        IGA_REQUIRE(np <= kMfThreads * kMfNpt, IGA_E_UNSUPPORTED, "matrix-free product: strip point count");
     }
     return F;
 }
@@ -686,13 +825,17 @@ static void mf_buffers(Plan& P) {
 
 static dim3 grid256(int64_t n) { return dim3((unsigned)((n + 255) / 256)); }
 
+// Element vectors: band elements several to a workgroup, cut elements one each.
 static void launch_elem(Plan& P, const MfArgs& A, const double* u, const double* r, double* Ye, double* dc,
                         hipStream_t s) {
-    int nre = (int)(P.n_band + P.n_cut_el);
-    if (nre == 0) return;
+    const int nb = (int)P.n_band, nc = (int)P.n_cut_el;
+    const int epw = 256 / ((P.p + 1) * (P.p + 1));
     switch (P.p) {
-#define CASE(PP) \
-    case PP: hipLaunchKernelGGL(k_mf_elem<PP>, dim3(nre), dim3(64), 0, s, A, u, r, Ye, dc); break;
+#define CASE(PP)                                                                                          \
+    case PP:                                                                                              \
+        if (nb > 0) hipLaunchKernelGGL(k_mf_band<PP>, dim3((nb + epw - 1) / epw), dim3(256), 0, s, A, u, r, Ye, dc); \
+        if (nc > 0) hipLaunchKernelGGL(k_mf_elem<PP>, dim3(nc), dim3(64), 0, s, A, nb, u, r, Ye, dc);    \
+        break;
         CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
 #undef CASE
     }
@@ -737,17 +880,15 @@ static void launch_wq_adjoint(Plan& Pl, const MfArgs& A, const double* u, const 
 // The forward product with its two intermediate arrays given: the bands'
 // head and tail rows [2][nband][p][n1] and Ue [n_band + n_cut][(p+1)^2].
 // Every entry of them is written before it is read, so they need no clearing.
-// The element part (element vectors, then the rows formed element-wise) runs
-// on the plan's second stream beside the weighted-quadrature part: the two
-// write disjoint rows of y.
+// All on the caller's stream: the element part (element vectors, then the
+// rows formed element-wise) and the weighted-quadrature part write disjoint
+// rows of y, but a second stream measured no overlap here (the other queue
+// started its kernels some 16 us after the fork's kernels had ended).
 static void mf_apply_into(Plan& P, const double* c, const double* u, double* y, double* part, double* Ue,
                           hipStream_t s) {
     MfArgs A = mf_args(P, c);
-    HIPX(hipEventRecord(P.ev_mf_fork, s));
-    HIPX(hipStreamWaitEvent(P.aux, P.ev_mf_fork, 0));
-    launch_elem(P, A, u, nullptr, Ue, nullptr, P.aux);
-    launch_gather_rows(P, A, Ue, y, P.aux);
-    HIPX(hipEventRecord(P.ev_mf_join, P.aux));
+    launch_elem(P, A, u, nullptr, Ue, nullptr, s);
+    launch_gather_rows(P, A, Ue, y, s);
     if (P.method != IGA_GAUSS_REF) {
         switch (P.p) {
 #define CASE(PP) \
@@ -756,7 +897,6 @@ static void mf_apply_into(Plan& P, const double* c, const double* u, double* y, 
 #undef CASE
         }
     }
-    HIPX(hipStreamWaitEvent(s, P.ev_mf_join, 0));
 }
 
 void mf_apply(Plan& P, const double* c, const double* u, double* y, hipStream_t s) {
@@ -823,12 +963,9 @@ void mf_adjoint(Plan& P, const double* c, const double* u, const double* r, doub
     mf_buffers(P);
     MfArgs A = mf_args(P, c);
     int n = (int)P.n_act;
-    // the element vectors (and dc at band Gauss points and cut nodes) on the second stream,
-    // beside the grid part; the gather needs both
-    HIPX(hipEventRecord(P.ev_mf_fork, s));
-    HIPX(hipStreamWaitEvent(P.aux, P.ev_mf_fork, 0));
-    launch_elem(P, A, u, r, P.sw.Ue, dc, P.aux);
-    HIPX(hipEventRecord(P.ev_mf_join, P.aux));
+    // the element vectors (and dc at band Gauss points and cut nodes), then the grid part;
+    // the gather needs both (one stream, as the forward product)
+    launch_elem(P, A, u, r, P.sw.Ue, dc, s);
     if (P.method != IGA_GAUSS_REF) {
         switch (P.p) {
 #define CASE(PP) \
@@ -839,7 +976,6 @@ void mf_adjoint(Plan& P, const double* c, const double* u, const double* r, doub
     } else {
         HIPX(hipMemsetAsync(dc, 0, sizeof(double) * (size_t)A.nq, s));
     }
-    HIPX(hipStreamWaitEvent(s, P.ev_mf_join, 0));
     // the grid part of du reads D (held in H) through the CR argument
     hipLaunchKernelGGL(k_mf_gather, dim3((n + 255) / 256), dim3(256), 0, s, A, (const double*)P.sw.Ue,
                        (const double*)P.sw.H, du, 1);

@@ -219,7 +219,6 @@ struct Plan {
     hipStream_t aux = nullptr;
     hipEvent_t ev_fork = nullptr, ev_iso = nullptr, ev_lists = nullptr, ev_interior = nullptr, ev_band = nullptr,
                ev_classes = nullptr;
-    hipEvent_t ev_mf_fork = nullptr, ev_mf_join = nullptr;  // matrix-free product: element part beside the grid part
 
     // timing
     bool timing = false;
