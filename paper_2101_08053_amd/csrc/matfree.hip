@@ -98,21 +98,23 @@ __global__ void __launch_bounds__(256) k_mf_hadj(MfArgs A, const double* __restr
 // Forward weighted-quadrature part in one pass over the grid. A workgroup
 // takes a strip of test columns i1 (one per thread) and a band of elements
 // e2 (at least p+1 of them) and walks the band's grid rows k2 in order:
-//   V[j2][k1] for a new u row (when an element starts; p+1 rows in a ring in LDS),
+//   V[j2][k1] for a new u row (once per element; p+1 rows in a ring in LDS),
 //   G[k1] = c_k sum_b B2[k2][b] V[e2(k2)+b][k1]   (the strip's points of row k2, LDS),
 //   H(i1) = sum_q w1[i1][q] G[k0(i1)+q]            (registers),
 //   acc[i2] += w2[i2][k2 - k0(i2)] H(i1)           for the p+1 rows i2 = e2..e2+p.
-// Rows go two at a time (one pair of barriers per two rows, their chains
-// interleaved): each element's rows are laid out in an even number of slots,
-// a padding slot having B2 = w2 = 0. When element e2 ends, row e2 has all of
-// this band's terms: it is written to y if its support lies in the band (or
-// starts at the patch edge), otherwise as the band's head part of that row;
-// the p rows after the band are written as its tail part, and k_mf_fix adds
-// a band's head to the previous band's tail. c rows are loaded two pairs
-// ahead and u rows one element ahead (their active ids two); the values every
-// thread needs at a slot (row, B2, w2, element bounds) are staged in LDS once,
-// so no load in the loop waits on a later-issued one. c is read once; V and H
-// never leave the workgroup.
+// Rows go two at a time with two barriers per pair: each element's rows
+// take an even number of slots (a padding slot has B2 = w2 = 0), and the
+// next element's V row is formed in the last pair of the current one, after
+// its second barrier (its ring slot held row e2, which that pair's G was the
+// last to read). When element e2 ends, row e2 has all of this band's terms:
+// it is written to y if its support lies in the band (or starts at the patch
+// edge), otherwise as the band's head part of that row; the p rows after the
+// band are written as its tail part, and k_mf_fix adds a band's head to the
+// previous band's tail. The point layout is the closed form of the WQ rule
+// (p+1 points in the first and last element, 2 elsewhere), so the slot table
+// needs no loads; c rows are loaded two pairs ahead and u rows one element
+// ahead (their active ids two), and no load in the loop waits on a later-
+// issued one. c is read once; V and H never leave the workgroup.
 constexpr int kMfThreads = 128;  // threads = test columns per strip (at most)
 constexpr int kMfNpt = 2;        // xi_1 points per thread (a strip has at most 2 (cols + p) + 2 (p - 1))
 constexpr int kMfUpt = 2;        // u columns per thread (cols + 2p)
@@ -134,12 +136,15 @@ __global__ void __launch_bounds__(kMfThreads) k_mf_fwd(MfArgs A, MfFwdArgs F, co
                                                        double* __restrict__ y) {
     constexpr int NP = kMfThreads * kMfNpt, NW = 2 * P + 2, QM = 4 * P + 2, NU = kMfThreads * kMfUpt;
     constexpr int NG = NP + QM;   // the column sums read up to 4p+1 points past a strip's last one
-    __shared__ double sU[P][NU];
+    // G of a row with even and odd points apart: the column sums read points k0(i1) + q, and k0
+    // steps by 2 from one column to the next, so each half is read with unit stride (no bank conflicts)
+    constexpr int NGH = (NG + 1) / 2;
+    auto gi = [](int k) { return (k & 1) * NGH + (k >> 1); };
+    __shared__ double sU[P + 1][NU];  // the first p+1 u rows; then rows alternate in sU[0], sU[1]
     __shared__ double sV[P + 1][NP];
-    __shared__ double sG[2][NG];
+    __shared__ double sG[2][2 * NGH];
     __shared__ double sB2[kMfSlots][P + 1], sW2[kMfSlots][P + 1];
     __shared__ int sK2[kMfSlots];
-    __shared__ int sEs[2 * kMfBandMax + 1];   // first slot of each element of the band, then the end
     const int tid = threadIdx.x;
     const int strip = blockIdx.x % F.nstrip, bnd = blockIdx.x / F.nstrip;
     const int n1 = A.n1, N1 = A.N1, N2 = A.N2, Q1 = A.d1.Q;
@@ -166,11 +171,36 @@ __global__ void __launch_bounds__(kMfThreads) k_mf_fwd(MfArgs A, MfFwdArgs F, co
 #pragma unroll
         for (int v = 0; v < kMfUpt; ++v) ok[v] = ucol[v] && id[v] >= 0;
     };
-    // the ids of u rows E0 .. E0+p+1 first (they need nothing else)
-    int idp[P + 2][kMfUpt];
+    // the ids of u rows E0 .. E0+p+2 first (they need nothing else)
+    int idp[P + 3][kMfUpt];
 #pragma unroll
-    for (int j = 0; j < P + 2; ++j) u_ids(E0 + j, idp[j]);
-    const int kA = A.d1.pt0[max(0, c0 - P)], kB = A.d1.pt0[min(N1 - 1, c1 - 1) + 1];
+    for (int j = 0; j < P + 3; ++j) u_ids(E0 + j, idp[j]);
+    // the band's slots: element e (from E0) starts at slot es(e), its rows at wq_pt0(E0 + e)
+    auto es = [&](int e) {   // sum over the band's elements before e of round-up-even(rows)
+        int s = wq_pt0(E0 + e, N2, P) - wq_pt0(E0, N2, P);
+        if ((P + 1) & 1) {   // p+1 rows (odd) in the patch's first and last element
+            if (E0 == 0 && e > 0) ++s;
+            if (N2 >= 2 && E0 + e >= N2) ++s;
+        }
+        return s;
+    };
+    const int S = es(NE), S4 = (S + 3) & ~3;
+    const int KA2 = wq_pt0(E0, N2, P);
+    for (int t = tid; t < S4 * (P + 1); t += kMfThreads) {
+        const int s = t / (P + 1), b = t % (P + 1);
+        int e = 0;
+        while (e + 1 < NE && es(e + 1) <= s) ++e;
+        const int ke = wq_pt0(E0 + e, N2, P), n = wq_pt0(E0 + e + 1, N2, P) - ke;
+        const bool in = s < S && s - es(e) < n;
+        const int k2 = in ? ke + (s - es(e)) : ke;
+        const int i2 = E0 + e + b;
+        const double bq = A.d2.Bq[(size_t)k2 * (P + 1) + b];
+        const double wq = A.d2.W[(size_t)i2 * A.d2.qmax + (k2 - wq_pt0(max(0, i2 - P), N2, P))];
+        sB2[s][b] = in ? bq : 0.0;
+        sW2[s][b] = in ? wq : 0.0;
+        if (b == 0) sK2[s] = k2;   // padding slots read a real row of c (weight 0)
+    }
+    const int kA = wq_pt0(max(0, c0 - P), N1, P), kB = wq_pt0(min(N1 - 1, c1 - 1) + 1, N1, P);
     // the thread's points: basis values and local element
     double B1[kMfNpt][P + 1];
     int le1[kMfNpt];
@@ -188,62 +218,33 @@ __global__ void __launch_bounds__(kMfThreads) k_mf_fwd(MfArgs A, MfFwdArgs F, co
     const int i1 = c0 + tid;
     const bool has_col = i1 < c1;
     const int ic = has_col ? i1 : c0;
-    const int k0l = A.d1.pt0[max(0, ic - P)] - kA;
-    const int nq1 = A.d1.pt0[min(N1 - 1, ic) + 1] - A.d1.pt0[max(0, ic - P)];
+    const int k0l = wq_pt0(max(0, ic - P), N1, P) - kA;
+    const int nq1 = wq_pt0(min(N1 - 1, ic) + 1, N1, P) - wq_pt0(max(0, ic - P), N1, P);
     double w1[QM];
 #pragma unroll
     for (int q = 0; q < NW; ++q) w1[q] = A.d1.WT[(size_t)q * n1 + ic];
 #pragma unroll
     for (int q = NW; q < QM; ++q) w1[q] = (q < nq1) ? A.d1.W[(size_t)ic * A.d1.qmax + q] : 0.0;
     const bool wide = nq1 > NW;   // a column next to a patch end
-    // element slot table: element e of the band takes round-up-even(rows of e) slots
-    if (tid <= NE) sEs[tid] = (tid < NE) ? A.d2.pt0[E0 + tid + 1] - A.d2.pt0[E0 + tid] : 0;
-    __syncthreads();
-    if (tid == 0) {
-        int s = 0;
-        for (int e = 0; e < NE; ++e) {
-            const int n = sEs[e];
-            sEs[e] = s;
-            s += (n + 1) & ~1;
-        }
-        sEs[NE] = s;
-    }
-    __syncthreads();
-    const int S = sEs[NE], S4 = (S + 3) & ~3;
-    for (int t = tid; t < S4 * (P + 1); t += kMfThreads) {
-        const int s = t / (P + 1), b = t % (P + 1);
-        int e = 0;
-        for (int k = 1; k < NE; ++k) e += (sEs[k] <= s);
-        const int ke = A.d2.pt0[E0 + e];
-        const int n = A.d2.pt0[E0 + e + 1] - ke;
-        const bool in = s < S && s - sEs[e] < n;
-        const int k2 = in ? ke + (s - sEs[e]) : ke;
-        const int i2 = E0 + e + b;
-        const double bq = A.d2.Bq[(size_t)k2 * (P + 1) + b];
-        const double wq = A.d2.W[(size_t)i2 * A.d2.qmax + (k2 - A.d2.pt0[max(0, i2 - P)])];
-        sB2[s][b] = in ? bq : 0.0;
-        sW2[s][b] = in ? wq : 0.0;
-        if (b == 0) sK2[s] = k2;   // padding slots read a real row of c (weight 0)
-    }
     // points past the strip's last one are read with weight 0: keep them finite
     for (int k = (kB - kA) + tid; k < NG; k += kMfThreads) {
-        sG[0][k] = 0.0;
-        sG[1][k] = 0.0;
+        sG[0][gi(k)] = 0.0;
+        sG[1][gi(k)] = 0.0;
     }
-    // u values of rows E0 .. E0+p; rows E0 .. E0+p-1 into the V ring
-    double up[P + 1][kMfUpt];
-    bool okp[P + 1][kMfUpt];
+    // u values of rows E0 .. E0+p+1; rows E0 .. E0+p into the V ring
+    double up[P + 2][kMfUpt];
+    bool okp[P + 2][kMfUpt];
 #pragma unroll
-    for (int j = 0; j <= P; ++j) {
+    for (int j = 0; j <= P + 1; ++j) {
         u_vals(idp[j], up[j]);
         u_ok(idp[j], okp[j]);
     }
 #pragma unroll
-    for (int j = 0; j < P; ++j)
+    for (int j = 0; j <= P; ++j)
 #pragma unroll
         for (int v = 0; v < kMfUpt; ++v) sU[j][tid + kMfThreads * v] = okp[j][v] ? up[j][v] : 0.0;
     __syncthreads();
-    // V of u row j2 from the values in sU[slot] into its ring slot
+    // V of u row j2 from the values in su into its ring slot
     auto v_row = [&](int j2, const double* su) {
         double* dst = sV[j2 % (P + 1)];
 #pragma unroll
@@ -255,15 +256,15 @@ __global__ void __launch_bounds__(kMfThreads) k_mf_fwd(MfArgs A, MfFwdArgs F, co
         }
     };
 #pragma unroll
-    for (int j = 0; j < P; ++j) v_row(E0 + j, sU[j]);
+    for (int j = 0; j <= P; ++j) v_row(E0 + j, sU[j]);
     int idb[kMfUpt];
     double uv[kMfUpt];
     bool uok[kMfUpt];
 #pragma unroll
     for (int v = 0; v < kMfUpt; ++v) {
-        uv[v] = up[P][v];          // row E0+p (the first element's new row)
-        uok[v] = okp[P][v];
-        idb[v] = idp[P + 1][v];    // ids of row E0+p+1
+        uv[v] = up[P + 1][v];      // row E0+p+1 (the second element's new row)
+        uok[v] = okp[P + 1][v];
+        idb[v] = idp[P + 2][v];    // ids of row E0+p+2
     }
     // c of a pair of slots, two pairs ahead, in two buffers (no copies: a copy of a loaded value waits for it)
     auto c_pair = [&](int s, double (&dst)[2][kMfNpt]) {
@@ -280,40 +281,13 @@ __global__ void __launch_bounds__(kMfThreads) k_mf_fwd(MfArgs A, MfFwdArgs F, co
     double acc[P + 1];
 #pragma unroll
     for (int b = 0; b <= P; ++b) acc[b] = 0.0;
-    int e2 = E0, send = 0, yid = -1;
-    int8_t ycls = 0;
-    // element e2 starts: its new u row e2+p into the ring, the next rows' loads, row e2's output id
-    auto start = [&]() {
-        __syncthreads();
-#pragma unroll
-        for (int v = 0; v < kMfUpt; ++v) sU[0][tid + kMfThreads * v] = uok[v] ? uv[v] : 0.0;
-        __syncthreads();
-        v_row(e2 + P, sU[0]);
-        u_vals(idb, uv);            // row e2+p+1
-        u_ok(idb, uok);
-        u_ids(e2 + P + 2, idb);     // ids of row e2+p+2
-        const size_t f = (size_t)e2 * n1 + ic;
-        yid = A.act_of[f];
-        ycls = A.fcls[f];
-        send = sEs[e2 - E0 + 1];
-    };
-    // element e2 ends: row e2 has all of the band's terms
-    auto finish = [&]() {
-        if (has_col) {
-            if (E0 == 0 || e2 - P >= E0) {
-                if (yid >= 0 && wq_row(A, ycls)) y[yid] = acc[0];
-            } else {
-                F.head[((size_t)bnd * P + (e2 - E0)) * n1 + i1] = acc[0];
-            }
-        }
-#pragma unroll
-        for (int b = 0; b < P; ++b) acc[b] = acc[b + 1];
-        acc[P] = 0.0;
-        ++e2;
-    };
+    int e2 = E0, send = es(1);
+    int yid = A.act_of[(size_t)E0 * n1 + ic];
+    int8_t ycls = A.fcls[(size_t)E0 * n1 + ic];
     // slots s, s+1 of element e2 with their c values in cbuf; cbuf then takes slots s+4, s+5
     auto pair = [&](int s, double (&cbuf)[2][kMfNpt]) {
-        __syncthreads();  // the ring row written at the element start; sG read by the last pair
+        const bool last = s + 2 == send, next = last && e2 + 1 < E1;
+        __syncthreads();  // the V row of the element; sG read by the last pair
 #pragma unroll
         for (int m = 0; m < kMfNpt; ++m) {
             const int k = tid + kMfThreads * m;
@@ -325,23 +299,28 @@ __global__ void __launch_bounds__(kMfThreads) k_mf_fwd(MfArgs A, MfFwdArgs F, co
                 s1 += sB2[s + 1][b] * v;
             }
             if (pv[m]) {
-                sG[0][k] = cbuf[0][m] * s0;
-                sG[1][k] = cbuf[1][m] * s1;
+                sG[0][gi(k)] = cbuf[0][m] * s0;
+                sG[1][gi(k)] = cbuf[1][m] * s1;
             }
         }
         c_pair(s + 4, cbuf);
+        double* su = sU[(e2 + 1 + P) & 1];
+        if (next) {   // u row e2+1+p for the next element's V row (after the barrier)
+#pragma unroll
+            for (int v = 0; v < kMfUpt; ++v) su[tid + kMfThreads * v] = uok[v] ? uv[v] : 0.0;
+        }
         __syncthreads();
         double h0 = 0.0, h1 = 0.0;
 #pragma unroll
         for (int q = 0; q < NW; ++q) {
-            h0 += w1[q] * sG[0][k0l + q];
-            h1 += w1[q] * sG[1][k0l + q];
+            h0 += w1[q] * sG[0][gi(k0l + q)];
+            h1 += w1[q] * sG[1][gi(k0l + q)];
         }
         if (wide) {
 #pragma unroll
             for (int q = NW; q < QM; ++q) {
-                h0 += w1[q] * sG[0][k0l + q];
-                h1 += w1[q] * sG[1][k0l + q];
+                h0 += w1[q] * sG[0][gi(k0l + q)];
+                h1 += w1[q] * sG[1][gi(k0l + q)];
             }
         }
 #pragma unroll
@@ -349,12 +328,32 @@ __global__ void __launch_bounds__(kMfThreads) k_mf_fwd(MfArgs A, MfFwdArgs F, co
             acc[b] += sW2[s][b] * h0;
             acc[b] += sW2[s + 1][b] * h1;
         }
-        if (s + 2 == send) {
-            finish();
-            if (e2 < E1) start();
+        if (last) {   // element e2 ends: row e2 has all of the band's terms
+            if (next) {
+                v_row(e2 + 1 + P, su);       // into row e2's ring slot, read by no later pair
+                u_vals(idb, uv);            // row e2+p+2
+                u_ok(idb, uok);
+                u_ids(e2 + P + 3, idb);     // ids of row e2+p+3
+            }
+            if (has_col) {
+                if (E0 == 0 || e2 - P >= E0) {
+                    if (yid >= 0 && wq_row(A, ycls)) y[yid] = acc[0];
+                } else {
+                    F.head[((size_t)bnd * P + (e2 - E0)) * n1 + i1] = acc[0];
+                }
+            }
+#pragma unroll
+            for (int b = 0; b < P; ++b) acc[b] = acc[b + 1];
+            acc[P] = 0.0;
+            ++e2;
+            if (e2 < E1) {
+                const size_t f = (size_t)e2 * n1 + ic;
+                yid = A.act_of[f];
+                ycls = A.fcls[f];
+                send = es(e2 - E0 + 1);
+            }
         }
     };
-    start();
     for (int s = 0; s < S4; s += 4) {  // every pair unconditional: a skipped one would make the waits conservative
         pair(s, ca);
         pair(s + 2, cb);
