@@ -231,9 +231,7 @@ int iga_trim_rhs(iga_plan* plan, const iga_coeff* c, const iga_target* g, double
  * given at every rule point (c_points, n_points values), the rows formed by
  * the plan's interior and hybrid rules, basis values recomputed on the fly.
  * The weighted-quadrature part runs sum-factorised in one pass over the WQ
- * grid (strips of test columns by bands of elements); the adjoint keeps one
- * row of the WQ grid in LDS: IGA_E_UNSUPPORTED past about 2700 elements
- * along xi_1. */
+ * grid (strips of test columns by bands of elements), as does its adjoint. */
 int iga_mf_apply(iga_plan* plan, const double* c_points, const double* u, double* y, void* stream);
 
 /* For callers that cannot allocate device memory (code under HIP graph
@@ -245,8 +243,8 @@ int iga_mf_apply(iga_plan* plan, const double* c_points, const double* u, double
  * nothing. Same arguments, kernels and result as iga_mf_apply.
  * IGA_E_CAPACITY (nothing enqueued) when the patch needs more than 16 MiB of
  * intermediate arrays: 8 (2 nband p n1 + (n_band_el + n_cut_el)(p+1)^2)
- * bytes with nband = max(1, floor(N2 / max(16, p+1))), each part rounded up
- * to 256 bytes (about 1500^2 elements at p = 4 with a 16-point cubic hole).
+ * bytes with nband = max(1, floor(N2 / max(8, p+1))), each part rounded up
+ * to 256 bytes (about 1150^2 elements at p = 4 with a 16-point cubic hole).
  * Every call on a device shares that device's array: calls that overlap on
  * one device (several streams or threads) race and must be ordered by the
  * caller. */
@@ -255,7 +253,9 @@ int iga_mf_apply_noalloc(iga_plan* plan, const double* c_points, const double* u
 /* Adjoint of iga_mf_apply (the transpose of Eq. (7)'s product and its
  * derivative in c): for a cotangent gy (n_act), du = M(c)^T gy
  * (n_act) and dc[k] = (sum_j B_j(x_k) u_j) (sum_i w_hat_{k,i} gy_i)
- * (n_points), w_hat_{k,i} being row i's test-side weight at point k. */
+ * (n_points), w_hat_{k,i} being row i's test-side weight at point k. The
+ * first call on a plan lists, on the host, the rows that receive element
+ * vectors (it synchronises the stream once and keeps the list). */
 int iga_mf_adjoint(iga_plan* plan, const double* c_points, const double* u, const double* gy,
                    double* du, double* dc, void* stream);
 

@@ -33,8 +33,6 @@ struct MfArgs {
     int n_band, n_cut, n_act;
     const double* c;   // n_points, plan point order
     int nq, nb;        // point offsets: band points start at nq, cut nodes at nq + nb
-    const double* WA;  // [Q1][p+1]: w1[e1(k1) + a][k1 - k0(e1(k1) + a)], 0 past the last function
-    const double* BR;  // [4p+2][n1]: B_j1(x_{k0(j1) + q}), 0 past the row's points
 };
 
 __device__ __forceinline__ bool wq_row(const MfArgs& A, int8_t cls) {
@@ -48,53 +46,11 @@ __device__ __forceinline__ bool wq_row(const MfArgs& A, int8_t cls) {
 //   H[k2][i1] = sum_q w1[i1][q] G[k2][k0(i1) + q]              (test rows along xi_1)
 //   y(i1, i2) = sum_q w2[i2][q] H[k0(i2) + q][i1]              (interior rows)
 // all four in one pass over the grid (k_mf_fwd), and, transposed, for the adjoint
-//   H[k2][i1] = sum_{i2 : k2 in supp} w2[i2][k2 - k0(i2)] r(i1, i2)                    (k_mf_hadj)
-//   R[k2][k1] = sum_{i1 : k1 in supp} w1[i1][k1 - k0(i1)] H[k2][i1],  dc = U R, c R      (k_mf_rd, per row)
-//   D[k2][j1] = sum_{k1 in supp j1} B1[k1][j1 - e1(k1)] c R[k2][k1]                    (k_mf_rd)
-//   du(j1, j2) += sum_{k2 in supp j2} B2[k2][j2 - e2(k2)] D[k2][j1]                    (k_mf_gather)
-// G, U, R and c R never leave their workgroup.
-template <int P>
-__global__ void __launch_bounds__(256) k_mf_v(MfArgs A, const double* __restrict__ u, double* __restrict__ V) {
-    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    const int Q1 = A.d1.Q;
-    if (t >= (int64_t)A.n2 * Q1) return;
-    const int k1 = (int)(t % Q1), j2 = (int)(t / Q1);
-    const int e1 = A.d1.eq[k1];
-    const int* act = A.act_of + (size_t)j2 * A.n1 + e1;
-    int cid[P + 1];
-#pragma unroll
-    for (int a = 0; a <= P; ++a) cid[a] = act[a];
-    double s = 0.0;
-#pragma unroll
-    for (int a = 0; a <= P; ++a) {
-        const double uv = u[max(cid[a], 0)];
-        s += A.d1.Bq[(size_t)k1 * (P + 1) + a] * (cid[a] >= 0 ? uv : 0.0);
-    }
-    V[t] = s;
-}
-
-template <int P>
-__global__ void __launch_bounds__(256) k_mf_hadj(MfArgs A, const double* __restrict__ r, double* __restrict__ H) {
-    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    const int n1 = A.n1;
-    if (t >= (int64_t)A.d2.Q * n1) return;
-    const int i1 = (int)(t % n1), k2 = (int)(t / n1);
-    const int e2 = A.d2.eq[k2];
-    double s = 0.0;
-#pragma unroll
-    for (int b = 0; b <= P; ++b) {
-        const int i2 = e2 + b;
-        if (i2 >= A.n2) break;
-        const int f = i2 * n1 + i1;
-        const int cid = A.act_of[f];
-        const bool use = cid >= 0 && wq_row(A, A.fcls[f]);
-        const double rv = r[max(cid, 0)];
-        const double w2 = A.d2.W[(size_t)i2 * A.d2.qmax + (k2 - A.d2.pt0[max(0, i2 - P)])];
-        s += use ? w2 * rv : 0.0;
-    }
-    H[t] = s;
-}
-
+//   Hr[k2][i1] = sum_{i2 : k2 in supp} w2[i2][k2 - k0(i2)] r(i1, i2)
+//   R[k2][k1] = sum_{i1 : k1 in supp} w1[i1][k1 - k0(i1)] Hr[k2][i1],  dc = U R, c R
+//   D[k2][j1] = sum_{k1 in supp j1} B1[k1][j1 - e1(k1)] c R[k2][k1]
+//   du(j1, j2) += sum_{k2 in supp j2} B2[k2][j2 - e2(k2)] D[k2][j1]
+// in one pass as well (k_mf_adj). None of V, G, H, U, R, c R or D leaves its workgroup.
 // Forward weighted-quadrature part in one pass over the grid. A workgroup
 // takes a strip of test columns i1 (one per thread) and a band of elements
 // e2 (at least p+1 of them) and walks the band's grid rows k2 in order:
@@ -372,9 +328,308 @@ __global__ void __launch_bounds__(kMfThreads) k_mf_fwd(MfArgs A, MfFwdArgs F, co
     }
 }
 
-// Rows whose support spans two bands: the band's head plus the previous band's tail.
+// Adjoint weighted-quadrature part in one pass over the grid, the forward
+// pass transposed. A workgroup takes a strip of output columns j1 (lane t)
+// and the test columns c0-p+t around them (lane t, their r rows in
+// registers), and a band of elements, and walks the band's grid rows:
+//   Hr(k2, i1) = sum_b w2[e2+b][k2 - k0(e2+b)] r(i1, e2+b)          (registers -> LDS)
+//   R(k2, k1) = sum_a w1[e1+a][k1 - k0(e1+a)] Hr(k2, e1(k1)+a)      (the strip's points)
+//   dc = U R with U from the V ring as in the forward pass,  CR = c R  (LDS)
+//   D(k2, j1) = sum_q B_j1(x_{k0(j1)+q}) CR(k2, k0(j1)+q)
+//   acc[j2] += B2[k2][j2 - e2] D(k2, j1)                             for j2 = e2..e2+p
+// r counts on rows formed by weighted quadrature only; du rows are
+// written for every active function (head, tail and k_mf_fix as forward),
+// the element part is added afterwards.
 template <int P>
-__global__ void __launch_bounds__(256) k_mf_fix(MfArgs A, MfFwdArgs F, double* __restrict__ y) {
+__global__ void __launch_bounds__(kMfThreads) k_mf_adj(MfArgs A, MfFwdArgs F, const double* __restrict__ u,
+                                                       const double* __restrict__ r, double* __restrict__ du,
+                                                       double* __restrict__ dc) {
+    constexpr int NP = kMfThreads * kMfNpt, NW = 2 * P + 2, QM = 4 * P + 2, NU = kMfThreads * kMfUpt;
+    constexpr int NG = NP + QM;
+    constexpr int NGH = (NG + 1) / 2;   // CR rows with even and odd points apart (unit-stride column sums)
+    auto gi = [](int k) { return (k & 1) * NGH + (k >> 1); };
+    __shared__ double sU[P + 1][NU];
+    __shared__ double sV[P + 1][NP];
+    __shared__ double sH[2][kMfThreads];
+    __shared__ double sC[2][2 * NGH];
+    __shared__ double sB2[kMfSlots][P + 1], sW2[kMfSlots][P + 1];
+    __shared__ int sK2[kMfSlots];
+    const int tid = threadIdx.x;
+    const int strip = blockIdx.x % F.nstrip, bnd = blockIdx.x / F.nstrip;
+    const int n1 = A.n1, N1 = A.N1, N2 = A.N2, Q1 = A.d1.Q;
+    const int c0 = strip * F.cols, c1 = min(n1, c0 + F.cols);
+    const int E0 = bnd * F.band, E1 = (bnd == F.nband - 1) ? N2 : E0 + F.band, NE = E1 - E0;
+    const int jA = max(0, c0 - P), jB = min(N1 - 1, c1 - 1) + P + 1;
+    bool ucol[kMfUpt];
+#pragma unroll
+    for (int v = 0; v < kMfUpt; ++v) ucol[v] = jA + tid + kMfThreads * v < jB;
+    auto u_ids = [&](int j2, int (&id)[kMfUpt]) {
+#pragma unroll
+        for (int v = 0; v < kMfUpt; ++v)
+            id[v] = A.act_of[(size_t)min(j2, A.n2 - 1) * n1 + min(jA + tid + kMfThreads * v, jB - 1)];
+    };
+    auto u_vals = [&](const int (&id)[kMfUpt], double (&val)[kMfUpt]) {
+#pragma unroll
+        for (int v = 0; v < kMfUpt; ++v) val[v] = u[max(id[v], 0)];
+    };
+    auto u_ok = [&](const int (&id)[kMfUpt], bool (&ok)[kMfUpt]) {
+#pragma unroll
+        for (int v = 0; v < kMfUpt; ++v) ok[v] = ucol[v] && id[v] >= 0;
+    };
+    // the lane's test column for Hr and its r rows (0 off the weighted-quadrature rows)
+    const int hc = c0 - P + tid;
+    const bool hcol = hc >= 0 && hc < n1 && hc < c1 + P;
+    const int hcc = min(max(hc, 0), n1 - 1);
+    auto r_id = [&](int i2) {   // active id of (hc, i2) if it is a weighted-quadrature row, else -1
+        const size_t f = (size_t)min(i2, A.n2 - 1) * n1 + hcc;
+        const int id = A.act_of[f];
+        const int8_t cls = A.fcls[f];
+        return (hcol && i2 < A.n2 && id >= 0 && wq_row(A, cls)) ? id : -1;
+    };
+    int ida[P + 3][kMfUpt];
+#pragma unroll
+    for (int j = 0; j < P + 3; ++j) u_ids(E0 + j, ida[j]);
+    int rid[P + 2];
+#pragma unroll
+    for (int j = 0; j < P + 2; ++j) rid[j] = r_id(E0 + j);
+    auto es = [&](int e) {
+        int s = wq_pt0(E0 + e, N2, P) - wq_pt0(E0, N2, P);
+        if ((P + 1) & 1) {
+            if (E0 == 0 && e > 0) ++s;
+            if (N2 >= 2 && E0 + e >= N2) ++s;
+        }
+        return s;
+    };
+    const int S = es(NE), S4 = (S + 3) & ~3;
+    for (int t = tid; t < S4 * (P + 1); t += kMfThreads) {
+        const int s = t / (P + 1), b = t % (P + 1);
+        int e = 0;
+        while (e + 1 < NE && es(e + 1) <= s) ++e;
+        const int ke = wq_pt0(E0 + e, N2, P), n = wq_pt0(E0 + e + 1, N2, P) - ke;
+        const bool in = s < S && s - es(e) < n;
+        const int k2 = in ? ke + (s - es(e)) : ke;
+        const int i2 = E0 + e + b;
+        const double bq = A.d2.Bq[(size_t)k2 * (P + 1) + b];
+        const double wq = A.d2.W[(size_t)i2 * A.d2.qmax + (k2 - wq_pt0(max(0, i2 - P), N2, P))];
+        sB2[s][b] = in ? bq : 0.0;
+        sW2[s][b] = in ? wq : 0.0;
+        if (b == 0) sK2[s] = in ? k2 : -1;
+    }
+    const int kA = wq_pt0(max(0, c0 - P), N1, P), kB = wq_pt0(min(N1 - 1, c1 - 1) + 1, N1, P);
+    // the lane's points: basis values, local element and the test weights meeting there
+    double B1[kMfNpt][P + 1], WA[kMfNpt][P + 1];
+    int le1[kMfNpt];
+    bool pv[kMfNpt];
+#pragma unroll
+    for (int m = 0; m < kMfNpt; ++m) {
+        const int k1 = kA + tid + kMfThreads * m;
+        pv[m] = k1 < kB;
+        const int kk = pv[m] ? k1 : kA;
+        const int e1 = A.d1.eq[kk];
+        le1[m] = e1 - jA;
+#pragma unroll
+        for (int a = 0; a <= P; ++a) {
+            B1[m][a] = A.d1.Bq[(size_t)kk * (P + 1) + a];
+            const int i1 = min(e1 + a, n1 - 1);
+            const double w = A.d1.W[(size_t)i1 * A.d1.qmax + (kk - wq_pt0(max(0, i1 - P), N1, P))];
+            WA[m][a] = (e1 + a < n1) ? w : 0.0;
+        }
+    }
+    // the lane's output column: its basis values at its support points (0 past them)
+    const int j1 = c0 + tid;
+    const bool has_col = j1 < c1;
+    const int jc = has_col ? j1 : c0;
+    const int k0l = wq_pt0(max(0, jc - P), N1, P) - kA;
+    const int nq1 = wq_pt0(min(N1 - 1, jc) + 1, N1, P) - wq_pt0(max(0, jc - P), N1, P);
+    double bj[QM];
+#pragma unroll
+    for (int q = 0; q < QM; ++q) {
+        const int k = min(kA + k0l + q, Q1 - 1);
+        const int a = jc - A.d1.eq[k];
+        const double v = A.d1.Bq[(size_t)k * (P + 1) + min(max(a, 0), P)];
+        bj[q] = (q < nq1 && a >= 0 && a <= P) ? v : 0.0;
+    }
+    const bool wide = nq1 > NW;
+    for (int k = (kB - kA) + tid; k < NG; k += kMfThreads) {
+        sC[0][gi(k)] = 0.0;
+        sC[1][gi(k)] = 0.0;
+    }
+    // u rows E0 .. E0+p into the V ring, r rows E0 .. E0+p into registers
+    double up[P + 2][kMfUpt];
+    bool okp[P + 2][kMfUpt];
+#pragma unroll
+    for (int j = 0; j <= P + 1; ++j) {
+        u_vals(ida[j], up[j]);
+        u_ok(ida[j], okp[j]);
+    }
+    double rr[P + 1], rnext;
+#pragma unroll
+    for (int j = 0; j <= P; ++j) {
+        const double t = r[max(rid[j], 0)];
+        rr[j] = rid[j] >= 0 ? t : 0.0;
+    }
+    rnext = r[max(rid[P + 1], 0)];    // row E0+p+1 (selected when it enters the ring)
+    int rnid = rid[P + 1];
+#pragma unroll
+    for (int j = 0; j <= P; ++j)
+#pragma unroll
+        for (int v = 0; v < kMfUpt; ++v) sU[j][tid + kMfThreads * v] = okp[j][v] ? up[j][v] : 0.0;
+    __syncthreads();
+    auto v_row = [&](int j2, const double* su) {
+        double* dst = sV[j2 % (P + 1)];
+#pragma unroll
+        for (int m = 0; m < kMfNpt; ++m) {
+            double s = 0.0;
+#pragma unroll
+            for (int a = 0; a <= P; ++a) s += B1[m][a] * su[le1[m] + a];
+            if (pv[m]) dst[tid + kMfThreads * m] = s;
+        }
+    };
+#pragma unroll
+    for (int j = 0; j <= P; ++j) v_row(E0 + j, sU[j]);
+    int idb[kMfUpt];
+    double uv[kMfUpt];
+    bool uok[kMfUpt];
+#pragma unroll
+    for (int v = 0; v < kMfUpt; ++v) {
+        uv[v] = up[P + 1][v];
+        uok[v] = okp[P + 1][v];
+        idb[v] = ida[P + 2][v];
+    }
+    int rnid2 = r_id(E0 + P + 2);   // the r row after next
+    auto c_pair = [&](int s, double (&dst)[2][kMfNpt]) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int k2 = max(sK2[min(s + h, S4 - 1)], 0);
+#pragma unroll
+            for (int m = 0; m < kMfNpt; ++m) dst[h][m] = A.c[(size_t)k2 * Q1 + min(kA + tid + kMfThreads * m, kB - 1)];
+        }
+    };
+    double ca[2][kMfNpt], cb[2][kMfNpt];
+    c_pair(0, ca);
+    c_pair(2, cb);
+    double acc[P + 1];
+#pragma unroll
+    for (int b = 0; b <= P; ++b) acc[b] = 0.0;
+    int e2 = E0, send = es(1);
+    int yid = A.act_of[(size_t)E0 * n1 + jc];
+    auto pair = [&](int s, double (&cbuf)[2][kMfNpt]) {
+        const bool last = s + 2 == send, next = last && e2 + 1 < E1;
+        // the lane's Hr of both rows
+        double h0 = 0.0, h1 = 0.0;
+#pragma unroll
+        for (int b = 0; b <= P; ++b) {
+            h0 += sW2[s][b] * rr[b];
+            h1 += sW2[s + 1][b] * rr[b];
+        }
+        __syncthreads();  // V row of the element; sH and sC read by the last pair
+        sH[0][tid] = h0;
+        sH[1][tid] = h1;
+        __syncthreads();
+        const int ka = sK2[s], kb = sK2[s + 1];
+#pragma unroll
+        for (int m = 0; m < kMfNpt; ++m) {
+            const int k = tid + kMfThreads * m;
+            double u0 = 0.0, u1 = 0.0, r0 = 0.0, r1 = 0.0;
+#pragma unroll
+            for (int b = 0; b <= P; ++b) {
+                const double v = sV[(e2 + b) % (P + 1)][k];
+                u0 += sB2[s][b] * v;
+                u1 += sB2[s + 1][b] * v;
+            }
+#pragma unroll
+            for (int a = 0; a <= P; ++a) {   // Hr columns e1+a: local index e1 + a - (c0 - p)
+                const int hi = min(le1[m] + a + (jA - (c0 - P)), kMfThreads - 1);
+                r0 += WA[m][a] * sH[0][hi];
+                r1 += WA[m][a] * sH[1][hi];
+            }
+            if (pv[m]) {
+                const int k1 = kA + k;
+                if (le1[m] + jA >= c0) {   // the point's element is the strip's (the previous strip writes the halo)
+                    if (ka >= 0) dc[(size_t)ka * Q1 + k1] = u0 * r0;
+                    if (kb >= 0) dc[(size_t)kb * Q1 + k1] = u1 * r1;
+                }
+                sC[0][gi(k)] = cbuf[0][m] * r0;
+                sC[1][gi(k)] = cbuf[1][m] * r1;
+            }
+        }
+        c_pair(s + 4, cbuf);
+        double* su = sU[(e2 + 1 + P) & 1];
+        if (next) {
+#pragma unroll
+            for (int v = 0; v < kMfUpt; ++v) su[tid + kMfThreads * v] = uok[v] ? uv[v] : 0.0;
+        }
+        __syncthreads();
+        double d0 = 0.0, d1 = 0.0;
+#pragma unroll
+        for (int q = 0; q < NW; ++q) {
+            d0 += bj[q] * sC[0][gi(k0l + q)];
+            d1 += bj[q] * sC[1][gi(k0l + q)];
+        }
+        if (wide) {
+#pragma unroll
+            for (int q = NW; q < QM; ++q) {
+                d0 += bj[q] * sC[0][gi(k0l + q)];
+                d1 += bj[q] * sC[1][gi(k0l + q)];
+            }
+        }
+#pragma unroll
+        for (int b = 0; b <= P; ++b) {
+            acc[b] += sB2[s][b] * d0;
+            acc[b] += sB2[s + 1][b] * d1;
+        }
+        if (last) {   // element e2 ends: du row e2 has all of the band's grid terms
+            if (next) {
+                v_row(e2 + 1 + P, su);
+                u_vals(idb, uv);
+                u_ok(idb, uok);
+                u_ids(e2 + P + 3, idb);
+            }
+            if (has_col) {
+                if (E0 == 0 || e2 - P >= E0) {
+                    if (yid >= 0) du[yid] = acc[0];
+                } else {
+                    F.head[((size_t)bnd * P + (e2 - E0)) * n1 + j1] = acc[0];
+                }
+            }
+#pragma unroll
+            for (int b = 0; b < P; ++b) {
+                acc[b] = acc[b + 1];
+                rr[b] = rr[b + 1];
+            }
+            acc[P] = 0.0;
+            rr[P] = rnid >= 0 ? rnext : 0.0;   // r row e2+1+p
+            rnext = r[max(rnid2, 0)];
+            rnid = rnid2;
+            rnid2 = r_id(e2 + P + 3);
+            ++e2;
+            if (e2 < E1) {
+                yid = A.act_of[(size_t)e2 * n1 + jc];
+                send = es(e2 - E0 + 1);
+            }
+        }
+    };
+    for (int s = 0; s < S4; s += 4) {
+        pair(s, ca);
+        pair(s + 2, cb);
+    }
+    if (!has_col) return;
+#pragma unroll
+    for (int b = 0; b < P; ++b) {  // rows E1 .. E1+p-1
+        const int i2 = E1 + b;
+        if (E1 == N2) {
+            const int id = A.act_of[(size_t)i2 * n1 + j1];
+            if (id >= 0) du[id] = acc[b];
+        } else {
+            F.tail[((size_t)bnd * P + b) * n1 + j1] = acc[b];
+        }
+    }
+}
+
+// Rows whose support spans two bands: the band's head plus the previous band's tail.
+// (all_rows: every active row, as the adjoint's du; else the weighted-quadrature rows)
+template <int P>
+__global__ void __launch_bounds__(256) k_mf_fix(MfArgs A, MfFwdArgs F, double* __restrict__ y, int all_rows) {
     const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
     const int n1 = A.n1;
     if (t >= (int64_t)(F.nband - 1) * P * n1) return;
@@ -382,94 +637,10 @@ __global__ void __launch_bounds__(256) k_mf_fix(MfArgs A, MfFwdArgs F, double* _
     const int i2 = bnd * F.band + r;
     const size_t f = (size_t)i2 * n1 + i1;
     const int id = A.act_of[f];
-    if (id < 0 || !wq_row(A, A.fcls[f])) return;
+    if (id < 0 || !(all_rows || wq_row(A, A.fcls[f]))) return;
     y[id] = F.tail[((size_t)(bnd - 1) * P + r) * n1 + i1] + F.head[((size_t)bnd * P + r) * n1 + i1];
 }
 
-// Per-point and per-function views of the xi_1 tables that the grid-row
-// kernels read at every row: the test weights that meet at a point (WA) and
-// a function's basis values at its support points (BR, functions contiguous).
-template <int P>
-__global__ void __launch_bounds__(256) k_mf_tables(DirDev D, int n1, double* __restrict__ WA, double* __restrict__ BR) {
-    constexpr int QM = 4 * P + 2;
-    const int t = blockIdx.x * 256 + threadIdx.x;
-    if (t < D.Q * (P + 1)) {
-        const int k1 = t / (P + 1), a = t % (P + 1), i1 = D.eq[k1] + a;
-        WA[t] = (i1 < n1) ? D.W[(size_t)i1 * D.qmax + (k1 - D.pt0[max(0, i1 - P)])] : 0.0;
-    }
-    if (t < QM * n1) {
-        const int q = t / n1, j1 = t % n1;
-        const int k0 = D.pt0[max(0, j1 - P)], q1 = D.pt0[min(D.N - 1, j1) + 1] - k0;
-        BR[t] = (q < q1) ? D.Bq[(size_t)(k0 + q) * (P + 1) + (j1 - D.eq[k0 + q])] : 0.0;
-    }
-}
-
-// Adjoint, one workgroup per grid row k2: the row's w2-weighted residual sums
-// (H, staged in LDS), R along the row, dc = U R with U from V, c R in LDS,
-// then the row's xi_1 basis sums D[k2][j1], written over H's row.
-template <int P>
-__global__ void __launch_bounds__(256) k_mf_rd(MfArgs A, const double* __restrict__ V, double* __restrict__ HD,
-                                               double* __restrict__ dc) {
-    extern __shared__ double sm[];  // n1 (H row), then Q1 (c R)
-    constexpr int QM = 4 * P + 2, NB = 4;
-    const int k2 = blockIdx.x, Q1 = A.d1.Q, n1 = A.n1;
-    double* sH = sm;
-    double* sCR = sm + n1;
-    for (int i1 = threadIdx.x; i1 < n1; i1 += 256) sH[i1] = HD[(size_t)k2 * n1 + i1];
-    const int e2 = A.d2.eq[k2];
-    double b2[P + 1];
-#pragma unroll
-    for (int a = 0; a <= P; ++a) b2[a] = A.d2.Bq[(size_t)k2 * (P + 1) + a];
-    const double* Vr = V + (size_t)e2 * Q1;
-    const double* cr = A.c + (size_t)k2 * Q1;
-    __syncthreads();
-#pragma unroll 1
-    for (int kb = threadIdx.x; kb < Q1; kb += 256 * NB) {
-        double v[NB][P + 1], wa[NB][P + 1], cv[NB];
-        int e1[NB];
-#pragma unroll
-        for (int j = 0; j < NB; ++j) {
-            const int k1 = min(kb + 256 * j, Q1 - 1);
-            e1[j] = A.d1.eq[k1];
-#pragma unroll
-            for (int a = 0; a <= P; ++a) {
-                v[j][a] = Vr[(size_t)a * Q1 + k1];
-                wa[j][a] = A.WA[(size_t)k1 * (P + 1) + a];
-            }
-            cv[j] = cr[k1];
-        }
-#pragma unroll
-        for (int j = 0; j < NB; ++j) {
-            double U = 0.0, R = 0.0;
-#pragma unroll
-            for (int a = 0; a <= P; ++a) {
-                U += b2[a] * v[j][a];
-                R += wa[j][a] * sH[min(e1[j] + a, n1 - 1)];  // 0 weight past the last function
-            }
-            const int k1 = kb + 256 * j;
-            if (k1 < Q1) {
-                dc[(size_t)k2 * Q1 + k1] = U * R;
-                sCR[k1] = cv[j] * R;
-            }
-        }
-    }
-    __syncthreads();
-#pragma unroll 1
-    for (int j1 = threadIdx.x; j1 < n1; j1 += 256) {
-        const int k0 = A.d1.pt0[max(0, j1 - P)];
-        double br[QM];
-#pragma unroll
-        for (int q = 0; q < QM; ++q) br[q] = A.BR[(size_t)q * n1 + j1];
-        double s = 0.0;
-#pragma unroll
-        for (int q = 0; q < QM; ++q) s += br[q] * sCR[min(k0 + q, Q1 - 1)];  // 0 past the row's points
-        HD[(size_t)k2 * n1 + j1] = s;
-    }
-}
-
-// Element part: per band / cut element, forward Y_e[l] = sum_g w_g c_g U_g B_l(x_g),
-// adjoint D_e[l] = sum_g c_g R_g B_l(x_g) with R_g = w_g sum_l B_l r_l over the
-// element-formed rows, and dc_g = U_g R_g.
 // Band elements (inside elements of the rows formed element-wise; a tensor
 // Gauss rule of (p+1)^2 points): several elements per 256-thread workgroup,
 // thread (element, l) taking local function l for u, point l for U, and
@@ -672,41 +843,6 @@ __global__ void __launch_bounds__(64) k_mf_elem(MfArgs A, int re0, const double*
     }
 }
 
-// Sum of the element vectors over the band / cut elements of supp B_j,
-// for the rows formed element-wise (forward) or every active function (adjoint),
-// plus (adjoint) the WQ-grid part sum_k B_j(x_k) CR_k from its xi_1 sums D.
-__global__ void k_mf_gather(MfArgs A, const double* __restrict__ Ye, const double* __restrict__ CR,
-                            double* __restrict__ out, int adjoint) {
-    int r = blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= A.n_act) return;
-    int f = A.fn_of[r];
-    int p = A.p;
-    int8_t cls = A.fcls[f];
-    if (!adjoint && wq_row(A, cls)) return;
-    int i1 = f % A.n1, i2 = f / A.n1;
-    int L = (p + 1) * (p + 1);
-    double s = 0.0;
-    for (int e2 = max(0, i2 - p); e2 <= min(A.N2 - 1, i2); ++e2)
-        for (int e1 = max(0, i1 - p); e1 <= min(A.N1 - 1, i1); ++e1) {
-            int e = e2 * A.N1 + e1;
-            int8_t c = A.ecls[e];
-            if (c == EL_OUTSIDE) continue;
-            int re = (c == EL_CUT) ? A.n_band + A.cut_id[e] : A.band_id[e];
-            if (re < 0) continue;  // inside element used by no element-formed row
-            s += Ye[(size_t)re * L + (i2 - e2) * (p + 1) + (i1 - e1)];
-        }
-    if (adjoint && A.method != IGA_GAUSS_REF) {  // the grid part, sum_k2 B2 D[k2][i1]
-        int k2 = A.d2.pt0[max(0, i2 - p)], q2 = A.d2.pt0[min(A.N2 - 1, i2) + 1] - k2;
-        double g = 0.0;
-        for (int b = 0; b < q2; ++b) {
-            int kk2 = k2 + b, m2 = A.d2.eq[kk2];
-            g += A.d2.Bq[kk2 * (p + 1) + (i2 - m2)] * CR[(size_t)kk2 * A.n1 + i1];
-        }
-        s += g;
-    }
-    out[r] = s;
-}
-
 // Forward rows formed element-wise: the element vectors of the band and cut
 // elements of the row's support, summed in a fixed order. Four lanes per row
 // of the plan's element-formed list, each taking every fourth support element
@@ -752,6 +888,46 @@ __global__ void __launch_bounds__(256) k_mf_gather_rows(MfArgs A, const int* __r
     if (ok && part == 0 && !wq_row(A, A.fcls[f])) y[r] = s;
 }
 
+// Adjoint: the element vectors of the band and cut elements of each listed
+// row's support added to du (after the grid part), four lanes per row as in
+// the forward gather.
+template <int P>
+__global__ void __launch_bounds__(256) k_mf_gather_add(MfArgs A, const int* __restrict__ rows, int n_rows,
+                                                       const double* __restrict__ Ye, double* __restrict__ du) {
+    constexpr int L = (P + 1) * (P + 1), PER = (L + 3) / 4;
+    const int t = blockIdx.x * 256 + threadIdx.x;
+    const int ri = t >> 2, part = t & 3;
+    const bool ok = ri < n_rows;
+    const int r = rows[min(ri, n_rows - 1)], f = A.fn_of[r];
+    const int i1 = f % A.n1, i2 = f / A.n1;
+    int8_t cls[PER];
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const int idx = min(part + 4 * k, L - 1), b = idx / (P + 1), a = idx % (P + 1);
+        const int e1 = i1 - P + a, e2 = i2 - P + b;
+        const bool in = part + 4 * k < L && e1 >= 0 && e1 < A.N1 && e2 >= 0 && e2 < A.N2;
+        cls[k] = in ? A.ecls[(size_t)e2 * A.N1 + e1] : (int8_t)EL_OUTSIDE;
+    }
+    int re[PER];
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const int idx = min(part + 4 * k, L - 1), b = idx / (P + 1), a = idx % (P + 1);
+        const int e = (i2 - P + b) * A.N1 + (i1 - P + a);
+        const int8_t c = cls[k];
+        re[k] = (c == EL_CUT) ? A.n_band + A.cut_id[e] : (c == EL_OUTSIDE ? -1 : A.band_id[e]);
+    }
+    double s = 0.0;
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const int idx = min(part + 4 * k, L - 1), b = idx / (P + 1), a = idx % (P + 1);
+        const int kk = re[k];
+        const double v = Ye[(size_t)max(kk, 0) * L + (P - b) * (P + 1) + (P - a)];
+        s += (kk >= 0) ? v : 0.0;
+    }
+    s = quad_sum(s);
+    if (ok && part == 0) du[r] += s;
+}
+
 static MfArgs mf_args(Plan& P, const double* c) {
     MfArgs A;
     A.d1 = P.dir[0];
@@ -780,21 +956,16 @@ static MfArgs mf_args(Plan& P, const double* c) {
     A.c = c;
     A.nq = P.dir[0].Q * P.dir[1].Q;
     A.nb = (int)P.n_band * (P.p + 1) * (P.p + 1);
-    A.WA = P.sw.WA;
-    A.BR = P.sw.BR;
     return A;
 }
 
-// one grid row of xi_1 points and one row of functions in LDS
-static void mf_check(const Plan& P) {
-    IGA_REQUIRE(sizeof(double) * ((size_t)P.dir[0].Q + P.n1) <= 65536, IGA_E_UNSUPPORTED,
-                "matrix-free product: more than 2700 elements along xi_1");
-}
 
 // Strips of test columns and bands of elements of the one-pass forward.
-static MfFwdArgs mf_fwd_shape(const Plan& P) {
+// adjoint: the lanes also hold the test columns p either side of the strip's
+static MfFwdArgs mf_fwd_shape(const Plan& P, bool adjoint = false) {
     MfFwdArgs F{};
-    const int cmax = std::min(kMfThreads, (kMfThreads * kMfNpt - 2 * (P.p - 1)) / 2 - P.p);  // 2 (cols + p) + 2 (p - 1) points
+    int cmax = std::min(kMfThreads, (kMfThreads * kMfNpt - 2 * (P.p - 1)) / 2 - P.p);  // 2 (cols + p) + 2 (p - 1) points
+    if (adjoint) cmax = std::min(cmax, kMfThreads - 2 * P.p);
     const int ns = (P.n1 + cmax - 1) / cmax;
     F.cols = (P.n1 + ns - 1) / ns;
     F.nstrip = (P.n1 + F.cols - 1) / F.cols;
@@ -813,13 +984,37 @@ static size_t mf_part_doubles(const Plan& P, const MfFwdArgs& F) { return 2 * (s
 
 static void mf_buffers(Plan& P) {
     size_t L = (size_t)(P.p + 1) * (P.p + 1);
-    mf_check(P);
-    if (!P.sw.V) P.sw.V = P.alloc<double>((size_t)P.n2 * P.dir[0].Q);
-    if (!P.sw.H) P.sw.H = P.alloc<double>((size_t)P.dir[1].Q * P.n1);
     if (!P.sw.Ue) P.sw.Ue = P.alloc<double>(std::max<int64_t>(1, P.n_band + P.n_cut_el) * L);
-    if (!P.sw.WA) P.sw.WA = P.alloc<double>((size_t)P.dir[0].Q * (P.p + 1));
-    if (!P.sw.BR) P.sw.BR = P.alloc<double>((size_t)(4 * P.p + 2) * P.n1);
     if (!P.sw.mfpart) P.sw.mfpart = P.alloc<double>(mf_part_doubles(P, mf_fwd_shape(P)));
+}
+
+// The rows that receive element vectors in the adjoint: every active row
+// with a band or cut element in its support (built on the host once per plan).
+static void mf_adj_rows(Plan& P, hipStream_t s) {
+    if (P.sw.adj_rows) return;
+    const int n = (int)P.n_act, ne = P.N1 * P.N2, p = P.p;
+    std::vector<int> fn(n), bid(ne), cid(ne), rows;
+    std::vector<int8_t> cls(ne);
+    HIPX(hipMemcpyAsync(fn.data(), P.fn_of, sizeof(int) * n, hipMemcpyDeviceToHost, s));
+    HIPX(hipMemcpyAsync(cls.data(), P.ecls, ne, hipMemcpyDeviceToHost, s));
+    HIPX(hipMemcpyAsync(bid.data(), P.band_id, sizeof(int) * ne, hipMemcpyDeviceToHost, s));
+    HIPX(hipMemcpyAsync(cid.data(), P.cut_id, sizeof(int) * ne, hipMemcpyDeviceToHost, s));
+    HIPX(hipStreamSynchronize(s));
+    for (int r = 0; r < n; ++r) {
+        const int i1 = fn[r] % P.n1, i2 = fn[r] / P.n1;
+        bool hit = false;
+        for (int e2 = std::max(0, i2 - p); e2 <= std::min(P.N2 - 1, i2) && !hit; ++e2)
+            for (int e1 = std::max(0, i1 - p); e1 <= std::min(P.N1 - 1, i1) && !hit; ++e1) {
+                const int e = e2 * P.N1 + e1;
+                hit = (cls[e] == EL_CUT && cid[e] >= 0) || (cls[e] == EL_INSIDE && bid[e] >= 0);
+            }
+        if (hit) rows.push_back(r);
+    }
+    P.sw.n_adj_rows = (int)rows.size();
+    P.sw.adj_rows = P.alloc<int>(std::max<size_t>(1, rows.size()));
+    if (!rows.empty())
+        HIPX(hipMemcpyAsync(P.sw.adj_rows, rows.data(), sizeof(int) * rows.size(), hipMemcpyHostToDevice, s));
+    HIPX(hipStreamSynchronize(s));
 }
 
 static dim3 grid256(int64_t n) { return dim3((unsigned)((n + 255) / 256)); }
@@ -847,7 +1042,7 @@ static void launch_wq_forward(Plan& Pl, const MfArgs& A, const double* u, double
     F.tail = part + (size_t)F.nband * P * Pl.n1;
     hipLaunchKernelGGL(k_mf_fwd<P>, dim3((unsigned)(F.nstrip * F.nband)), dim3(kMfThreads), 0, s, A, F, u, y);
     if (F.nband > 1)
-        hipLaunchKernelGGL(k_mf_fix<P>, grid256((int64_t)(F.nband - 1) * P * Pl.n1), dim3(256), 0, s, A, F, y);
+        hipLaunchKernelGGL(k_mf_fix<P>, grid256((int64_t)(F.nband - 1) * P * Pl.n1), dim3(256), 0, s, A, F, y, 0);
 }
 
 static void launch_gather_rows(Plan& P, const MfArgs& A, const double* Ye, double* y, hipStream_t s) {
@@ -866,14 +1061,14 @@ static void launch_gather_rows(Plan& P, const MfArgs& A, const double* Ye, doubl
 }
 
 template <int P>
-static void launch_wq_adjoint(Plan& Pl, const MfArgs& A, const double* u, const double* r, double* dc,
-                              hipStream_t s) {
-    const int nt = std::max(A.d1.Q * (P + 1), (4 * P + 2) * Pl.n1);  // the weights may have been injected
-    hipLaunchKernelGGL(k_mf_tables<P>, grid256(nt), dim3(256), 0, s, A.d1, Pl.n1, Pl.sw.WA, Pl.sw.BR);
-    hipLaunchKernelGGL(k_mf_v<P>, grid256((int64_t)Pl.n2 * A.d1.Q), dim3(256), 0, s, A, u, Pl.sw.V);
-    hipLaunchKernelGGL(k_mf_hadj<P>, grid256((int64_t)A.d2.Q * Pl.n1), dim3(256), 0, s, A, r, Pl.sw.H);
-    hipLaunchKernelGGL(k_mf_rd<P>, dim3(A.d2.Q), dim3(256), sizeof(double) * (A.d1.Q + Pl.n1), s, A,
-                       (const double*)Pl.sw.V, Pl.sw.H, dc);  // D over H
+static void launch_wq_adjoint(Plan& Pl, const MfArgs& A, const double* u, const double* r, double* du, double* dc,
+                              double* part, hipStream_t s) {
+    MfFwdArgs F = mf_fwd_shape(Pl, true);
+    F.head = part;
+    F.tail = part + (size_t)F.nband * P * Pl.n1;
+    hipLaunchKernelGGL(k_mf_adj<P>, dim3((unsigned)(F.nstrip * F.nband)), dim3(kMfThreads), 0, s, A, F, u, r, du, dc);
+    if (F.nband > 1)
+        hipLaunchKernelGGL(k_mf_fix<P>, grid256((int64_t)(F.nband - 1) * P * Pl.n1), dim3(256), 0, s, A, F, du, 1);
 }
 
 // The forward product with its two intermediate arrays given: the bands'
@@ -933,7 +1128,6 @@ void mf_scratch_init(int device) {
 static size_t round256(size_t n_doubles) { return (n_doubles + 31) & ~(size_t)31; }  // 32 doubles = 256 B
 
 static void mf_apply_noalloc(Plan& P, const double* c, const double* u, double* y, hipStream_t s) {
-    mf_check(P);
     const size_t L = (size_t)(P.p + 1) * (P.p + 1);
     const size_t nP = round256(mf_part_doubles(P, mf_fwd_shape(P)));
     const size_t nU = round256((size_t)std::max<int64_t>(1, P.n_band + P.n_cut_el) * L);
@@ -958,26 +1152,36 @@ static void mf_apply_noalloc(Plan& P, const double* c, const double* u, double* 
     mf_apply_into(P, c, u, y, base, base + nP, s);
 }
 
+// The adjoint: the element vectors (and dc at band Gauss points and cut
+// nodes), the grid part of du and dc in one pass (every active row of du
+// written), then the element vectors added to the rows they touch.
 void mf_adjoint(Plan& P, const double* c, const double* u, const double* r, double* du, double* dc, hipStream_t s) {
     mf_buffers(P);
+    mf_adj_rows(P, s);
     MfArgs A = mf_args(P, c);
-    int n = (int)P.n_act;
-    // the element vectors (and dc at band Gauss points and cut nodes), then the grid part;
-    // the gather needs both (one stream, as the forward product)
     launch_elem(P, A, u, r, P.sw.Ue, dc, s);
     if (P.method != IGA_GAUSS_REF) {
         switch (P.p) {
 #define CASE(PP) \
-    case PP: launch_wq_adjoint<PP>(P, A, u, r, dc, s); break;
+    case PP: launch_wq_adjoint<PP>(P, A, u, r, du, dc, P.sw.mfpart, s); break;
             CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
 #undef CASE
         }
     } else {
         HIPX(hipMemsetAsync(dc, 0, sizeof(double) * (size_t)A.nq, s));
+        HIPX(hipMemsetAsync(du, 0, sizeof(double) * (size_t)P.n_act, s));
     }
-    // the grid part of du reads D (held in H) through the CR argument
-    hipLaunchKernelGGL(k_mf_gather, dim3((n + 255) / 256), dim3(256), 0, s, A, (const double*)P.sw.Ue,
-                       (const double*)P.sw.H, du, 1);
+    const int nr = P.sw.n_adj_rows;
+    if (nr == 0) return;
+    switch (P.p) {
+#define CASE(PP)                                                                                            \
+    case PP:                                                                                                \
+        hipLaunchKernelGGL(k_mf_gather_add<PP>, grid256(4 * (int64_t)nr), dim3(256), 0, s, A,              \
+                           (const int*)P.sw.adj_rows, nr, (const double*)P.sw.Ue, du);                      \
+        break;
+        CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
+#undef CASE
+    }
 }
 
 }  // namespace iga

@@ -137,12 +137,10 @@ struct SolveWork {
     double *r = nullptr, *z = nullptr, *pv = nullptr, *q = nullptr, *part = nullptr, *scal = nullptr, *b = nullptr;
     double* h_scal = nullptr; // pinned host copy of the scalars
     int* cols = nullptr;      // compact column of each band slot (PCG)
-    double* V = nullptr;      // matrix-free: u contracted along xi_1 [n2][Q1]
-    double* H = nullptr;      // matrix-free: xi_1 row sums [Q2][n1] (forward), w2 r, then B1 c R (adjoint)
     double* Ue = nullptr;     // matrix-free: element vectors
-    double* WA = nullptr;     // matrix-free adjoint: test weights meeting at each xi_1 point [Q1][p+1]
-    double* BR = nullptr;     // matrix-free adjoint: basis values at each function's xi_1 points [4p+2][n1]
-    double* mfpart = nullptr; // matrix-free forward: rows split between two bands [2][nband][p][n1]
+    double* mfpart = nullptr; // matrix-free: rows split between two bands [2][nband][p][n1]
+    int* adj_rows = nullptr;  // matrix-free adjoint: rows with band or cut elements in their support
+    int n_adj_rows = 0;
 };
 
 struct Plan {
