@@ -623,19 +623,40 @@ def bench_adjoint(igatrim, wl, cfg_unused, args, sync, stream, peaks):
     # algorithmic bytes: forward reads u and c, writes y; adjoint reads u, c, r, writes du and dc
     fwd_bytes = 8 * (2 * n + npts)
     bwd_bytes = 8 * (3 * n + 2 * npts)
+    # the one-pass grid kernels alone (per-kernel HIP events): c on the WQ grid plus the vectors
+    plan.set_timing(True, per_kernel=True)
+    for _ in range(2):
+        igatrim.mf_apply(plan, c, u)
+        igatrim.mf_adjoint(plan, c, u, gy)
+    plan.kernel_times()
+    for _ in range(steps):
+        igatrim.mf_apply(plan, c, u)
+        igatrim.mf_adjoint(plan, c, u, gy)
+    kt = plan.kernel_times()
+    plan.set_timing(False)
+    p = sz["p"]
+    nq = sz["q1"] * sz["q2"]
+    kernels = {k: {"avg_launch_ms": ms / max(1, cnt), "calls": cnt} for k, (ms, cnt) in kt.items()}
+    grid_roofs = {}
+    for name, nbytes, per in ((f"k_mf_fwd<{p}>", 8 * (nq + 2 * n), "8 B per WQ-grid c and per u, y value"),
+                              (f"k_mf_adj<{p}>", 8 * (2 * nq + 3 * n), "8 B per WQ-grid c, dc and per u, r, du value")):
+        if name in kernels:
+            grid_roofs[name] = _roof(name, "hbm", nbytes, kernels[name]["avg_launch_ms"], peaks, per,
+                                     "HIP events at the dispatch's start and end")
     return {"forward_ms": ms_fwd, "backward_ms": ms_bwd, "forward_noalloc_ms": ms_fwd_na,
             "plain_formation_ms": ms_form,
             "forward_value": nnz / (ms_fwd * 1e-3), "backward_value": nnz / (ms_bwd * 1e-3),
             "plain_value": nnz / (ms_form * 1e-3), "unit": "nnz-equivalent/s", "nnz": nnz,
             "n_act": n, "n_points": npts,
             "rooflines": {
-                "forward": _roof("matrix-free forward (k_mf_v, k_mf_gh, k_mf_y, k_mf_elem, k_mf_gather)", "hbm",
-                                 fwd_bytes, ms_fwd, peaks, "8 B per u, y value and per rule-point c",
+                "forward": _roof("matrix-free forward (k_mf_band, k_mf_elem, k_mf_gather_rows, k_mf_fwd, k_mf_fix)",
+                                 "hbm", fwd_bytes, ms_fwd, peaks, "8 B per u, y value and per rule-point c",
                                  "whole call timed on the host / calls"),
-                "adjoint": _roof("matrix-free adjoint (k_mf_tables, k_mf_v, k_mf_hadj, k_mf_rd, k_mf_elem, "
-                                 "k_mf_gather)", "hbm", bwd_bytes, ms_bwd, peaks,
-                                 "8 B per u, r, du value and per rule-point c, dc",
-                                 "whole call timed on the host / calls")},
+                "adjoint": _roof("matrix-free adjoint (k_mf_band, k_mf_elem, k_mf_adj, k_mf_fix, k_mf_gather_add)",
+                                 "hbm", bwd_bytes, ms_bwd, peaks, "8 B per u, r, du value and per rule-point c, dc",
+                                 "whole call timed on the host / calls"),
+                **grid_roofs},
+            "kernels": kernels,
             "note": f"p=4, {args.mf_N}^2 elements, c at every rule point; y = M(c)u and (dL/du, dL/dc)"}
 
 

@@ -1027,22 +1027,32 @@ static void launch_elem(Plan& P, const MfArgs& A, const double* u, const double*
     switch (P.p) {
 #define CASE(PP)                                                                                          \
     case PP:                                                                                              \
-        if (nb > 0) hipLaunchKernelGGL(k_mf_band<PP>, dim3((nb + epw - 1) / epw), dim3(256), 0, s, A, u, r, Ye, dc); \
-        if (nc > 0) hipLaunchKernelGGL(k_mf_elem<PP>, dim3(nc), dim3(64), 0, s, A, nb, u, r, Ye, dc);    \
+        if (nb > 0)                                                                                       \
+            klaunch(P, "k_mf_band<" #PP ">", k_mf_band<PP>, dim3((nb + epw - 1) / epw), dim3(256), 0, s, A, u, r, Ye, \
+                    dc);                                                                                  \
+        if (nc > 0) klaunch(P, "k_mf_elem<" #PP ">", k_mf_elem<PP>, dim3(nc), dim3(64), 0, s, A, nb, u, r, Ye, dc); \
         break;
         CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
 #undef CASE
     }
 }
 
+static const char* const kMfFwdNames[] = {"", "k_mf_fwd<1>", "k_mf_fwd<2>", "k_mf_fwd<3>", "k_mf_fwd<4>",
+                                          "k_mf_fwd<5>", "k_mf_fwd<6>", "k_mf_fwd<7>", "k_mf_fwd<8>"};
+static const char* const kMfAdjNames[] = {"", "k_mf_adj<1>", "k_mf_adj<2>", "k_mf_adj<3>", "k_mf_adj<4>",
+                                          "k_mf_adj<5>", "k_mf_adj<6>", "k_mf_adj<7>", "k_mf_adj<8>"};
+static const char* const kMfFixNames[] = {"", "k_mf_fix<1>", "k_mf_fix<2>", "k_mf_fix<3>", "k_mf_fix<4>",
+                                          "k_mf_fix<5>", "k_mf_fix<6>", "k_mf_fix<7>", "k_mf_fix<8>"};
+
 template <int P>
 static void launch_wq_forward(Plan& Pl, const MfArgs& A, const double* u, double* y, double* part, hipStream_t s) {
     MfFwdArgs F = mf_fwd_shape(Pl);
     F.head = part;
     F.tail = part + (size_t)F.nband * P * Pl.n1;
-    hipLaunchKernelGGL(k_mf_fwd<P>, dim3((unsigned)(F.nstrip * F.nband)), dim3(kMfThreads), 0, s, A, F, u, y);
+    klaunch(Pl, kMfFwdNames[P], k_mf_fwd<P>, dim3((unsigned)(F.nstrip * F.nband)), dim3(kMfThreads), 0, s, A, F, u, y);
     if (F.nband > 1)
-        hipLaunchKernelGGL(k_mf_fix<P>, grid256((int64_t)(F.nband - 1) * P * Pl.n1), dim3(256), 0, s, A, F, y, 0);
+        klaunch(Pl, kMfFixNames[P], k_mf_fix<P>, grid256((int64_t)(F.nband - 1) * P * Pl.n1), dim3(256), 0, s, A, F, y,
+                0);
 }
 
 static void launch_gather_rows(Plan& P, const MfArgs& A, const double* Ye, double* y, hipStream_t s) {
@@ -1051,9 +1061,8 @@ static void launch_gather_rows(Plan& P, const MfArgs& A, const double* Ye, doubl
     switch (P.p) {
 #define CASE(PP)                                                                                            \
     case PP:                                                                                                \
-        hipLaunchKernelGGL(k_mf_gather_rows<PP>, grid256(4 * (int64_t)nr), dim3(256), 0, s, A,             \
-                           (const int*)P.form_rows, nr,                                                     \
-                           Ye, y);                                                                          \
+        klaunch(P, "k_mf_gather_rows<" #PP ">", k_mf_gather_rows<PP>, grid256(4 * (int64_t)nr), dim3(256), 0, s, A, \
+                (const int*)P.form_rows, nr, Ye, y);                                                        \
         break;
         CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
 #undef CASE
@@ -1066,9 +1075,11 @@ static void launch_wq_adjoint(Plan& Pl, const MfArgs& A, const double* u, const 
     MfFwdArgs F = mf_fwd_shape(Pl, true);
     F.head = part;
     F.tail = part + (size_t)F.nband * P * Pl.n1;
-    hipLaunchKernelGGL(k_mf_adj<P>, dim3((unsigned)(F.nstrip * F.nband)), dim3(kMfThreads), 0, s, A, F, u, r, du, dc);
+    klaunch(Pl, kMfAdjNames[P], k_mf_adj<P>, dim3((unsigned)(F.nstrip * F.nband)), dim3(kMfThreads), 0, s, A, F, u, r,
+            du, dc);
     if (F.nband > 1)
-        hipLaunchKernelGGL(k_mf_fix<P>, grid256((int64_t)(F.nband - 1) * P * Pl.n1), dim3(256), 0, s, A, F, du, 1);
+        klaunch(Pl, kMfFixNames[P], k_mf_fix<P>, grid256((int64_t)(F.nband - 1) * P * Pl.n1), dim3(256), 0, s, A, F, du,
+                1);
 }
 
 // The forward product with its two intermediate arrays given: the bands'
@@ -1176,8 +1187,8 @@ void mf_adjoint(Plan& P, const double* c, const double* u, const double* r, doub
     switch (P.p) {
 #define CASE(PP)                                                                                            \
     case PP:                                                                                                \
-        hipLaunchKernelGGL(k_mf_gather_add<PP>, grid256(4 * (int64_t)nr), dim3(256), 0, s, A,              \
-                           (const int*)P.sw.adj_rows, nr, (const double*)P.sw.Ue, du);                      \
+        klaunch(P, "k_mf_gather_add<" #PP ">", k_mf_gather_add<PP>, grid256(4 * (int64_t)nr), dim3(256), 0, s, A,   \
+                (const int*)P.sw.adj_rows, nr, (const double*)P.sw.Ue, du);                                 \
         break;
         CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
 #undef CASE
