@@ -152,8 +152,8 @@ def kernel_work(name, sz, plan_info):
     WQ grid once (8 B per point); a cut element's Gram product sum_n w c phi phi^T
     costs n_nodes L (L+1)/2 FMA (upper triangle, L = (p+1)^2, 2 flops each);
     c = |det J| at a point writes 8 B (and, in a full formation, the point's
-    coordinates, 16 B) and reads its element's (p+1)^2 control points (kept in
-    cache; counted once per patch: 16 n1 n2 B); a weight
+    coordinates, 16 B) and reads the control points (counted once per patch:
+    16 n1 n2 B); a weight
     system of Eq. (5) (m = 2p+1 rows, q = 2p+2 points) is a Householder QR of
     q x m: 2 q m^2 - (2/3) m^3 flops; the cut-element preparation writes each
     node's (x, y, w) (24 B); the element-formed rows' cut entries read each cut

@@ -45,7 +45,6 @@ namespace iga {
 
 enum : int { BK_COEF = 0, BK_CUTE = 1, BK_INT = 2, BK_CUTR = 3, BK_NKIND = 4 };
 constexpr int kBatchMaxP = 6;
-constexpr int kCoefChunk = 1024;  // coefficient points per item
 
 struct BatchPlan {
     int p;
@@ -202,17 +201,22 @@ __global__ void __launch_bounds__(256)
     cut_elem_body<P>(plans[it.plan].ce, it.unit, S);
 }
 
-// Coefficient chunks of the batch's patches of degree P: |det J| at the WQ
-// grid and band Gauss points (the cut element matrices evaluate it at their
-// nodes themselves). One point per thread: kCoefChunk / 256 workgroups per
-// chunk.
+// Coefficient items of the batch's patches of degree P, one wavefront each:
+// |det J| on a tile of the WQ grid (sum-factorised, the one-patch kernel's
+// body), then on kCgPts band Gauss points per item (the cut element matrices
+// evaluate it at their nodes themselves).
 template <int P>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(kCgPts)
     k_batch_coef(const BatchPlan* __restrict__ plans, const BatchItem* __restrict__ items) {
-    constexpr int WPC = kCoefChunk / 256;
-    const BatchItem it = items[blockIdx.x / WPC];
+    __shared__ CoefGridSmem<P> S;
+    const BatchItem it = items[blockIdx.x];
     const CoefArgs& co = plans[it.plan].co;
-    const int64_t t = (int64_t)it.unit * kCoefChunk + (blockIdx.x % WPC) * 256 + threadIdx.x;
+    const int ntile = coef_grid_tiles(co.d1.Q, co.d2.N);
+    if (it.unit < ntile) {
+        coef_grid_body<P>(co, it.unit, S);
+        return;
+    }
+    const int64_t t = co.nq + (int64_t)(it.unit - ntile) * kCgPts + threadIdx.x;
     if (t < co.nq + co.nb) coef_point<P>(co, t);
 }
 
@@ -351,11 +355,11 @@ struct Batch {
         for (int g = 0; g < kBatchGroups; ++g) {
             if (coef_n[g] == 0) continue;
             const BatchItem* it = d_rows + coef_off[g];
-            const dim3 grid((unsigned)coef_n[g] * (kCoefChunk / 256));
+            const dim3 grid((unsigned)coef_n[g]);
             switch (g + 1) {
 #define CASE(PP)                                                                             \
     case PP:                                                                                 \
-        hipLaunchKernelGGL(k_batch_coef<PP>, grid, dim3(256), 0, side, d_plans, it); \
+        hipLaunchKernelGGL(k_batch_coef<PP>, grid, dim3(kCgPts), 0, side, d_plans, it); \
         break;
                 CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6)
 #undef CASE
@@ -469,7 +473,7 @@ struct Batch {
 static double item_cost(const Plan& P, int kind, int unit, const std::vector<int>& node_off) {
     const double p1 = P.p + 1.0;
     switch (kind) {
-        case BK_COEF: return kCoefChunk * p1 * p1;
+        case BK_COEF: return kCgPts * p1 * 8.0;
         case BK_CUTE: return (node_off[unit + 1] - node_off[unit]) * p1 * p1 * p1 * p1 * 0.5;
         case BK_INT: return 64.0 * p1 * p1 * p1 * 4.0;
         default: return p1 * p1 * p1 * p1 * p1;
@@ -551,8 +555,9 @@ static iga_batch* batch_create(iga_plan* const* plans, int count, const iga_coef
         std::vector<int> node_off(P.n_cut_el + 1, 0);
         if (P.n_cut_el > 0)
             HIPX(hipMemcpy(node_off.data(), P.node_off, sizeof(int) * (P.n_cut_el + 1), hipMemcpyDeviceToHost));
-        const int64_t npts = bp.co.nq + bp.co.nb;
-        const int n_coef = (c.kind == IGA_COEF_GEOM_DETJ) ? (int)((npts + kCoefChunk - 1) / kCoefChunk) : 0;
+        const int n_coef = (c.kind == IGA_COEF_GEOM_DETJ)
+                               ? coef_grid_tiles(P.dir[0].Q, P.dir[1].N) + (int)((bp.co.nb + kCgPts - 1) / kCgPts)
+                               : 0;
         const int n_int = (P.method == IGA_GAUSS_REF) ? 0 : interior2_ntx(P.N1, P.p) * P.n2;
         const int n_cute = (int)P.n_cut_el, n_cutr = (int)P.n_form_rows;
         const int counts[BK_NKIND] = {n_coef, n_cute, n_int, n_cutr};

@@ -59,6 +59,111 @@ __device__ __forceinline__ void coef_point(const CoefArgs& A, int64_t t) {
     }
 }
 
+// |det J| on the WQ grid, sum-factorised. A tile is a strip of kCgPts
+// points along xi_1 (one per thread, one wavefront) by a band of kCgBand
+// elements along xi_2. The band's control rows (for the strip's columns) and
+// its grid rows' B2, dB2 are staged in LDS with all loads in flight at once;
+// each thread then contracts every control row once with its point's B1 and
+// dB1 (x, y and their xi_1 derivatives along the row), keeps the p+1 rows of
+// the current element in registers, and forms the four partial derivatives
+// at each grid row of the element with B2, dB2: 4(p+1) multiply-adds per
+// point instead of 4(p+1)^2, and the same sums in the same order as
+// detj_local.
+constexpr int kCgPts = 64;    // points (threads) per tile along xi_1
+constexpr int kCgBand = 8;    // elements per tile along xi_2
+constexpr int kCgCols = kCgPts / 2 + IGA_MAXP + 2;          // control columns of a strip, at most
+constexpr int kCgCrows = kCgBand + IGA_MAXP;                // control rows of a band, at most
+constexpr int kCgRows = 2 * kCgBand + 2 * IGA_MAXP;         // grid rows of a band, at most
+
+__host__ __device__ inline int coef_grid_tiles(int Q1, int N2) {
+    return ((Q1 + kCgPts - 1) / kCgPts) * ((N2 + kCgBand - 1) / kCgBand);
+}
+
+template <int P>
+struct CoefGridSmem {
+    double sP[kCgBand + P][2 * kCgCols];
+    double sB2[kCgRows][P + 1], sdB2[kCgRows][P + 1];
+};
+
+template <int P>
+__device__ __forceinline__ void coef_grid_body(const CoefArgs& A, int tile, CoefGridSmem<P>& S) {
+    const DirDev& D1 = A.d1;
+    const DirDev& D2 = A.d2;
+    const int nsx = (D1.Q + kCgPts - 1) / kCgPts;
+    const int sx = tile % nsx, bz = tile / nsx;
+    const int E0 = bz * kCgBand, E1 = min(D2.N, E0 + kCgBand);
+    const int t = threadIdx.x, nt = blockDim.x;
+    const int kfirst = sx * kCgPts, klast = min(D1.Q, kfirst + kCgPts) - 1;
+    const bool on = kfirst + t <= klast;
+    const int k1 = on ? kfirst + t : klast;
+    const int jA = D1.eq[kfirst], ncol = D1.eq[klast] + P + 1 - jA;
+    const int e1l = D1.eq[k1] - jA;
+    double B1[P + 1], dB1[P + 1];
+#pragma unroll
+    for (int a = 0; a <= P; ++a) {
+        B1[a] = D1.Bq[(size_t)k1 * (P + 1) + a];
+        dB1[a] = D1.dBq[(size_t)k1 * (P + 1) + a];
+    }
+    const int KA2 = D2.pt0[E0], KB2 = D2.pt0[E1];
+    for (int r = t; r < (KB2 - KA2) * (P + 1); r += nt) {
+        const int k2 = KA2 + r / (P + 1), b = r % (P + 1);
+        S.sB2[r / (P + 1)][b] = D2.Bq[(size_t)k2 * (P + 1) + b];
+        S.sdB2[r / (P + 1)][b] = D2.dBq[(size_t)k2 * (P + 1) + b];
+    }
+    // control rows E0 .. E1+p-1, columns jA .. jA+ncol-1 (x and y interleaved)
+    const int nrow = E1 - E0 + P;
+    for (int c = t; c < nrow * 2 * ncol; c += nt) {
+        const int j = c / (2 * ncol), q = c % (2 * ncol);
+        S.sP[j][q] = A.cp[2 * ((size_t)(E0 + j) * A.n1 + jA) + q];
+    }
+    __syncthreads();
+    // (sum_a1 B1 x, B1 y, dB1 x, dB1 y) of control row E0 + j
+    auto t_row = [&](int j, double (&o)[4]) {
+        double sx = 0.0, sy = 0.0, sx1 = 0.0, sy1 = 0.0;
+#pragma unroll
+        for (int a = 0; a <= P; ++a) {
+            const double px = S.sP[j][2 * (e1l + a)], py = S.sP[j][2 * (e1l + a) + 1];
+            sx1 += dB1[a] * px;
+            sx += B1[a] * px;
+            sy1 += dB1[a] * py;
+            sy += B1[a] * py;
+        }
+        o[0] = sx;
+        o[1] = sy;
+        o[2] = sx1;
+        o[3] = sy1;
+    };
+    double T[P + 1][4];   // control rows e2 .. e2+p of the current element
+#pragma unroll
+    for (int j = 0; j < P; ++j) t_row(j, T[j]);
+    for (int e2 = E0; e2 < E1; ++e2) {
+        t_row(e2 - E0 + P, T[P]);
+        for (int k2 = D2.pt0[e2]; k2 < D2.pt0[e2 + 1]; ++k2) {
+            const int r = k2 - KA2;
+            double x1 = 0.0, y1 = 0.0, x2 = 0.0, y2 = 0.0;
+#pragma unroll
+            for (int b = 0; b <= P; ++b) {
+                x1 += S.sB2[r][b] * T[b][2];
+                y1 += S.sB2[r][b] * T[b][3];
+                x2 += S.sdB2[r][b] * T[b][0];
+                y2 += S.sdB2[r][b] * T[b][1];
+            }
+            if (on) {
+                const size_t pt = (size_t)k2 * D1.Q + k1;
+                A.c_wq[pt] = fabs(x1 * y2 - x2 * y1);
+                if (A.xy) {
+                    A.xy[2 * pt] = D1.xq[k1];
+                    A.xy[2 * pt + 1] = D2.xq[k2];
+                }
+            }
+        }
+#pragma unroll
+        for (int b = 0; b < P; ++b)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) T[b][q] = T[b + 1][q];
+    }
+}
+
 // ------------------------------------------------------------ interior rows
 struct IntArgs {
     DirDev d1, d2;
