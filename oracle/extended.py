@@ -20,7 +20,9 @@ B-splines themselves):
   lambda_i(q); on monomials lambda_i(x^k) = sigma_k(t_{i+1}, ..., t_{i+p}) /
   binom(p, k), sigma_k the elementary symmetric polynomial of the knots
   inside B_i's support (Marsden's identity), so the weights solve
-      sum_m e_m lambda_{l+m}(x^k) = lambda_j(x^k),  k = 0..p;
+      sum_m e_m lambda_{l+m}(x^k) = lambda_j(x^k),  k = 0..p
+  (on uniform knots away from the ends: Lagrange extrapolation of the
+  coefficient sequence from the nodes l..l+p to j);
 * e_{i,j} = e^1_{i1 - l1}(j1) e^2_{i2 - l2}(j2), and the extended basis is
   B_i^e = B_i + sum_{outer j : i in I(j)} e_{i,j} B_j over the inner i.
   With E[i, j] = 1 (j = i inner) or e_{i,j} (j outer, i in I(j)) the
@@ -54,17 +56,25 @@ def inner_mask(ts):
     return out
 
 
-def dual_power(knots, p, i, k):
-    """lambda_i(x^k) = sigma_k(t_{i+1}, ..., t_{i+p}) / binom(p, k) (Marsden's identity)."""
-    t = knots[i + 1:i + p + 1]
+def dual_power(knots, p, i, k, x0=0.0, h=1.0):
+    """lambda_i(((x - x0)/h)^k) = sigma_k(s_{i+1}, ..., s_{i+p}) / binom(p, k), s = (t - x0)/h (Marsden's identity)."""
+    t = [(knots[m] - x0) / h for m in range(i + 1, i + p + 1)]
     s = sum(math.prod(c) for c in combinations(t, k)) if k > 0 else 1.0
     return s / math.comb(p, k)
 
 
 def weights_1d(knots, p, j, l):
-    """e_m, m = 0..p: the block l..l+p reproduces B_j's coefficient of every polynomial of degree p."""
-    V = np.array([[dual_power(knots, p, l + m, k) for m in range(p + 1)] for k in range(p + 1)])
-    v = np.array([dual_power(knots, p, j, k) for k in range(p + 1)])
+    """e_m, m = 0..p: the block l..l+p reproduces B_j's coefficient of every polynomial of degree p.
+
+    The conditions are taken on the monomials ((x - x0)/h)^k, x0 and h the centre and half
+    length of the knots t_a..t_b the functions involved read (a = min(j, l) + 1,
+    b = max(j, l + p) + p): the weights do not depend on the basis of the polynomials,
+    and about 0 the monomials' conditions grow ill-posed with the number of elements.
+    """
+    a, b = min(j, l) + 1, max(j, l + p) + p
+    x0, h = 0.5 * (knots[a] + knots[b]), 0.5 * (knots[b] - knots[a])
+    V = np.array([[dual_power(knots, p, l + m, k, x0, h) for m in range(p + 1)] for k in range(p + 1)])
+    v = np.array([dual_power(knots, p, j, k, x0, h) for k in range(p + 1)])
     return np.linalg.solve(V, v)
 
 

@@ -4,6 +4,10 @@
   polynomial in the full basis (fitted independently by least squares on
   SciPy's B-spline design matrix), E^T c_inner = c on every outer function,
   on uniform and non-uniform knots;
+* on uniform knots away from the repeated ends the 1-D weights are the
+  Lagrange extrapolation weights of the nodes l..l+p at j (the coefficients
+  of a polynomial are a polynomial of the same degree in the index there),
+  also on fine meshes where the raw monomial conditions are ill-posed;
 * the extended projection reproduces Q_p on trimmed patches;
 * on a sliver trim the extended matrix is far better conditioned than the
   plain one, and the projection error stays that of the plain projection.
@@ -52,6 +56,23 @@ def test_extension_reproduces_polynomials(cfg):
             ci = np.outer(c2, c1).reshape(-1)[inner_flat]
             err = np.abs(E.T @ ci - c).max()
             assert err <= 1e-11 * max(1.0, np.abs(c).max()), (a, b, err)
+
+
+@pytest.mark.parametrize("p", [1, 2, 3, 4, 6, 8])
+@pytest.mark.parametrize("N", [16, 1024])
+def test_weights_are_lagrange_extrapolation(p, N):
+    knots = np.r_[np.zeros(p), np.linspace(0.0, 1.0, N + 1), np.ones(p)]
+    n = N + p
+    worst, seen = 0.0, 0
+    for j, l in [(n // 2, n // 2 + 1), (n // 2, n // 2 - p - 3), (n // 2 + 2, n // 2 - p), (n // 2 - 4, n // 2),
+                 (p - 1, p), (2 * p, p - 1)]:
+        if min(j, l) + 1 < p or max(j, l + p) + p > p + N:
+            continue   # reads a repeated end knot
+        e = extended.weights_1d(knots, p, j, l)
+        lag = np.array([np.prod([(j - (l + k)) / (m - k) for k in range(p + 1) if k != m]) for m in range(p + 1)])
+        worst = max(worst, np.abs(e - lag).max() / max(1.0, np.abs(lag).max()))
+        seen += 1
+    assert seen >= 2 and worst <= 1e-9, (seen, worst)
 
 
 @pytest.mark.parametrize("cfg", [_sliver(3), wl.config1(N=12), wl.config3(N=12, p=4)], ids=lambda c: c.name)
