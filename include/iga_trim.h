@@ -225,6 +225,36 @@ int iga_trim_l2_project(iga_plan* plan, const iga_coeff* c, const double* vals, 
  * rules and the errors of iga_trim_l2_project). Asynchronous on stream. */
 int iga_trim_rhs(iga_plan* plan, const iga_coeff* c, const iga_target* g, double* b, void* stream);
 
+/* L2 projection in the extended B-spline basis (Sect. 2.2, closing remarks,
+ * and Sect. 4.2: the paper stabilises its projections this way, after the
+ * weighted extended B-splines of the works it cites). Inner functions are
+ * active with an inside element in their support; every other active
+ * (outer) function j is tied to the block {l1..l1+p} x {l2..l2+p} of inner
+ * functions whose centre l + p/2 is nearest to j (squared index distance;
+ * ties to the smaller l2, then l1), with weights e_{i,j} = e^1 e^2 that make
+ * the block reproduce j's B-spline coefficient of every polynomial of degree
+ * p in each direction. With E[i, j] = 1 (j = i inner) or e_{i,j}, the call
+ * solves (E A E^T) x = E b by Jacobi-preconditioned CG (exact diagonal of
+ * E A E^T) and writes u = E^T x. A = (M + M^T)/2 and b as in
+ * iga_trim_l2_project, with its methods, arguments and errors; the start is
+ * the inner coefficients of u; info reports ||E b - E A E^T x|| / ||E b||.
+ * The blocks and weights follow the plan's element classes as they stand.
+ * Errors also: IGA_E_TOPOLOGY (an outer function with no all-inner block:
+ * the visible domain is too small for the degree), IGA_E_CAPACITY (more
+ * outer functions than the plan's non-interior rows at creation).
+ * Synchronous. */
+int iga_trim_l2_project_ext(iga_plan* plan, const iga_coeff* c, const double* vals, const iga_target* g,
+                            double rtol, int32_t maxit, double* u, iga_solve_info* info, void* stream);
+
+/* The extension's columns (Sect. 2.2, as in iga_trim_l2_project_ext): for
+ * every compact row j, members[j*(p+1)^2 + m] (compact ids, row-major over
+ * the block, m = m2 (p+1) + m1) and weights[...] of the inner functions it
+ * is tied to, so that u_j = sum_m weights * x[members]; an inner row has
+ * itself with weight 1, then -1 and 0. members and weights are device
+ * buffers of n_act (p+1)^2 entries, caller owned. Synchronous; errors as
+ * iga_trim_l2_project_ext. */
+int iga_trim_extension(iga_plan* plan, int32_t* members, double* weights, void* stream);
+
 /* Matrix-free product y = M(c) u of Eq. (7) -- the weighted-quadrature rows
  * y_i = sum_k w_{k,i} c_k sum_j B_j(x_k) u_j, and the element rules of the cut
  * rows (Sect. 3.2) -- for device vectors of length n_act, with c

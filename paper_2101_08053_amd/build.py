@@ -14,7 +14,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libigatrim.so")
-SOURCES = ["api.hip", "setup.hip", "scan.hip", "trim.hip", "form.hip", "solve.hip", "matfree.hip", "dwq.hip", "batch.hip", "batch_solve.hip", "calib.hip"]
+SOURCES = ["api.hip", "setup.hip", "scan.hip", "trim.hip", "form.hip", "solve.hip", "matfree.hip", "dwq.hip", "batch.hip", "batch_solve.hip", "calib.hip", "extended.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",

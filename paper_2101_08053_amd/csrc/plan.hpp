@@ -141,6 +141,21 @@ struct SolveWork {
     double* mfpart = nullptr; // matrix-free: rows split between two bands [2][nband][p][n1]
     int* adj_rows = nullptr;  // matrix-free adjoint: rows with band or cut elements in their support
     int n_adj_rows = 0;
+    // extended B-splines (first extended projection): vectors of the extended system live in the
+    // compact row space, zero at outer rows
+    int8_t* x_inner = nullptr;  // [n2][n1] active with an inside element in the support
+    int8_t* x_ok = nullptr;     // [n2-p][n1-p] block {l..l+p}^2 of inner functions only
+    int* x_slot = nullptr;      // [n_act] outer slot of the row, -1 for inner rows
+    int* x_cnt = nullptr;       // [n_act] outer rows tied to the row (a fill cursor after the scan)
+    int* x_off = nullptr;       // [n_act + 1] start of the row's list of outer rows
+    int* x_misc = nullptr;      // [2] outer rows, error
+    int* x_row = nullptr;       // [x_cap] compact row of each outer slot
+    int* x_fid = nullptr;       // [x_cap][(p+1)^2] block members (compact)
+    double* x_fw = nullptr;     // [x_cap][(p+1)^2] their weights
+    int* x_tj = nullptr;        // per inner row, ascending: the outer rows tied to it
+    double* x_tw = nullptr;     // and their weights
+    double *x_dg = nullptr, *x_e = nullptr, *x_z = nullptr, *x_w = nullptr, *x_b = nullptr;
+    int x_cap = 0;
 };
 
 struct Plan {

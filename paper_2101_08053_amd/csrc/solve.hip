@@ -189,6 +189,36 @@ void rhs(Plan& P, const iga_coeff& c, const iga_target& g, double* b, hipStream_
     }
 }
 
+void solve_buffers(Plan& P) {
+    SolveWork& W = P.sw;
+    if (W.A) return;
+    const int n = (int)P.n_act;
+    const int W2 = (2 * P.p + 1) * (2 * P.p + 1);
+    const int nblk = (n + kRedThreads - 1) / kRedThreads;
+    W.A = P.alloc<double>((size_t)W2 * n);
+    W.r = P.alloc<double>(n);
+    W.z = P.alloc<double>(n);
+    W.pv = P.alloc<double>(n);
+    W.q = P.alloc<double>(n);
+    W.b = P.alloc<double>(n);
+    W.part = P.alloc<double>(3 * (size_t)nblk);
+    W.scal = P.alloc<double>(8);
+    W.cols = P.alloc<int>((size_t)W2 * n);
+    HIPX(hipHostMalloc((void**)&W.h_scal, 8 * sizeof(double), hipHostMallocDefault));
+}
+
+SpArgs solve_operator(Plan& P, const double* vals, hipStream_t s) {
+    SolveWork& W = P.sw;
+    const int n = (int)P.n_act;
+    const int64_t tot = (int64_t)(2 * P.p + 1) * (2 * P.p + 1) * n;
+    hipLaunchKernelGGL(k_symmetrize, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, P.p, P.n1, P.fn_of,
+                       P.act_of, P.n2, n, vals, W.A);
+    SpArgs S{P.p, P.n1, P.n2, n, P.fn_of, P.act_of, W.A, nullptr};
+    hipLaunchKernelGGL(k_cols, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, S, W.cols);
+    S.cols = W.cols;
+    return S;
+}
+
 // The rules each method's right-hand side takes g c at: DWQ boxes also need
 // it at their nested points, so values given only at the plan's rule points
 // (and a coefficient given there) cannot serve DWQ plans.
@@ -237,27 +267,10 @@ int iga_trim_l2_project(iga_plan* plan, const iga_coeff* c, const double* vals, 
     hipStream_t s = (hipStream_t)stream;
     SolveWork& W = P->sw;
     int n = (int)P->n_act;
-    int W2 = (2 * P->p + 1) * (2 * P->p + 1);
     int nblk = (n + kRedThreads - 1) / kRedThreads;
-    if (!W.A) {
-        W.A = P->alloc<double>((size_t)W2 * n);
-        W.r = P->alloc<double>(n);
-        W.z = P->alloc<double>(n);
-        W.pv = P->alloc<double>(n);
-        W.q = P->alloc<double>(n);
-        W.b = P->alloc<double>(n);
-        W.part = P->alloc<double>(3 * (size_t)nblk);
-        W.scal = P->alloc<double>(8);
-        W.cols = P->alloc<int>((size_t)W2 * n);
-        HIPX(hipHostMalloc((void**)&W.h_scal, 8 * sizeof(double), hipHostMallocDefault));
-    }
+    solve_buffers(*P);
     rhs(*P, *c, *g, W.b, s);
-    int64_t tot = (int64_t)W2 * n;
-    hipLaunchKernelGGL(k_symmetrize, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, P->p, P->n1, P->fn_of,
-                       P->act_of, P->n2, n, vals, W.A);
-    SpArgs S{P->p, P->n1, P->n2, n, P->fn_of, P->act_of, W.A, nullptr};
-    hipLaunchKernelGGL(k_cols, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, S, W.cols);
-    S.cols = W.cols;
+    const SpArgs S = solve_operator(*P, vals, s);
     hipLaunchKernelGGL(k_cg_init, dim3(nblk), dim3(kRedThreads), 0, s, S, W.b, u, W.r, W.z, W.pv, W.part);
     hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kRedThreads), 0, s, W.part, nblk, W.scal);
     auto read = [&]() {

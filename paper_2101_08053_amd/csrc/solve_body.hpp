@@ -355,6 +355,9 @@ RhsGatherArgs rhs_gather_args(Plan& P, const double* F, double* b);
 DwqRhsArgs dwq_rhs_args(Plan& P, const iga_coeff& c, const iga_target& g, const double* gc, double* b);
 // Throws unless the plan's method has a right-hand side for this target and coefficient.
 void rhs_check(const Plan& P, const iga_coeff& c, const iga_target& g);
+// b (device, n_act) = row rules applied to g c, on stream s
+void rhs(Plan& P, const iga_coeff& c, const iga_target& g, double* b, hipStream_t s);
+
 
 // ------------------------------------------------------------------- PCG
 // A = (M + M^T)/2: slot (a, b) of row r pairs with slot (-a, -b) of its
@@ -386,6 +389,7 @@ struct SpArgs {
     const int* act_of;
     const double* A;
     const int* cols;  // [(2p+1)^2][n_act] compact column of each slot, -1 if none (PCG iterations)
+    const double* dg = nullptr;  // preconditioner diagonal when given, else A's own
 };
 
 // Compact column of band entry t = s * n_act + r.
@@ -447,10 +451,10 @@ __device__ __forceinline__ double sum_partials(const double* __restrict__ part, 
     return block_sum(s, sh);
 }
 
-// Diagonal of A at row r (Jacobi preconditioner).
+// Diagonal of the Jacobi preconditioner at row r: A's own, or the one given.
 __device__ __forceinline__ double diag_of(const SpArgs& S, int r) {
     const int W = 2 * S.p + 1;
-    return S.A[(size_t)(S.p * W + S.p) * S.n_act + r];
+    return S.dg ? S.dg[r] : S.A[(size_t)(S.p * W + S.p) * S.n_act + r];
 }
 
 // ---- the steps of the iteration, for one workgroup of kRedThreads rows: lb
@@ -567,5 +571,10 @@ __device__ __forceinline__ double cg_dir_block(int n, int lb, double* __restrict
     if (r < n) pv[r] = zv[r] + *s_beta * pv[r];
     return rr;
 }
+
+// PCG buffers of the plan (first call allocates)
+void solve_buffers(Plan& P);
+// A = (M + M^T)/2 and the slot columns from vals; the operator's arguments
+SpArgs solve_operator(Plan& P, const double* vals, hipStream_t s);
 
 }  // namespace iga

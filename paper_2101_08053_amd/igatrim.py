@@ -108,6 +108,9 @@ def lib():
             "iga_trim_l2_project": (C.c_int, [P, C.POINTER(iga_coeff), V, C.POINTER(iga_target), C.c_double,
                                               C.c_int32, V, C.POINTER(iga_solve_info), V]),
             "iga_trim_rhs": (C.c_int, [P, C.POINTER(iga_coeff), C.POINTER(iga_target), V, V]),
+            "iga_trim_l2_project_ext": (C.c_int, [P, C.POINTER(iga_coeff), V, C.POINTER(iga_target), C.c_double,
+                                                  C.c_int32, V, C.POINTER(iga_solve_info), V]),
+            "iga_trim_extension": (C.c_int, [P, V, V, V]),
             "iga_mf_apply": (C.c_int, [P, V, V, V, V]),
             "iga_mf_apply_noalloc": (C.c_int, [P, V, V, V, V]),
             "iga_mf_adjoint": (C.c_int, [P, V, V, V, V, V, V]),
@@ -148,7 +151,7 @@ def lib():
 
 EXPORTED = ("iga_trim_plan_create", "iga_plan_destroy", "iga_plan_sizes", "iga_plan_points", "iga_plan_index_maps",
             "iga_trim_mass_form", "iga_status_get", "iga_trim_l2_project", "iga_trim_rhs", "iga_mf_apply",
-            "iga_mf_apply_noalloc",
+            "iga_trim_l2_project_ext", "iga_trim_extension", "iga_mf_apply_noalloc",
             "iga_mf_adjoint", "iga_trim_mass_form_batched", "iga_batch_create", "iga_batch_destroy",
             "iga_batch_form", "iga_batch_autotune", "iga_batch_info", "iga_batch_status", "iga_batch_project",
             "iga_plan_set_timing", "iga_plan_timings", "iga_plan_kernel_times", "iga_plan_set_graph",
@@ -390,6 +393,31 @@ def l2_project(plan, vals, coeff, target, rtol=1e-12, maxit=None, u0=None, strea
     if code != 0 and not (code == -8 and not raise_on_noconv):
         _check(code)
     return u, out
+
+
+def l2_project_ext(plan, vals, coeff, target, rtol=1e-12, maxit=None, u0=None, stream=None, raise_on_noconv=True):
+    """L2 projection in the extended B-spline basis (Sects. 2.2, 4.2); returns (u, info dict)."""
+    torch = _torch()
+    n = plan.sizes["n_act"]
+    u = torch.zeros(n, dtype=torch.float64, device="cuda") if u0 is None else u0.clone()
+    info = iga_solve_info()
+    maxit = maxit or 10 * n
+    code = lib().iga_trim_l2_project_ext(plan.h, C.byref(coeff), _dptr(vals), C.byref(target), rtol, maxit,
+                                         _dptr(u), C.byref(info), _stream(stream))
+    out = {"iterations": info.iterations, "converged": bool(info.converged), "rel_residual": info.rel_residual}
+    if code != 0 and not (code == -8 and not raise_on_noconv):
+        _check(code)
+    return u, out
+
+
+def extension(plan, stream=None):
+    """Columns of the extension: (members, weights), each [n_act, (p+1)^2] on the device."""
+    torch = _torch()
+    n, L = plan.sizes["n_act"], (plan.patch.p + 1) ** 2
+    members = torch.empty((n, L), dtype=torch.int32, device="cuda")
+    weights = torch.empty((n, L), dtype=torch.float64, device="cuda")
+    _check(lib().iga_trim_extension(plan.h, _dptr(members), _dptr(weights), _stream(stream)))
+    return members, weights
 
 
 def mf_apply(plan, c_points, u, stream=None):

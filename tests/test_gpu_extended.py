@@ -1,0 +1,153 @@
+"""GPU extended B-spline projection (Sects. 2.2 and 4.2) against the oracle.
+
+* the extension itself: the inner set, every outer function's block (compact
+  ids, exact) and its weights (within 1e-12 of the larger of 1 and the
+  weight) equal the oracle's, on a sliver cut, circles, an ellipse patch of
+  degree 4 and non-uniform knots;
+* the projection under identical rules (oracle weights and cut nodes
+  injected): the oracle's residual of the device's extended unknowns,
+  ||E b - E A E^T x|| / ||E b|| with the oracle's E, A and b, stays within
+  1e-10 (PCG stops at 1e-12 on the device's), the outer coefficients are E^T
+  of the inner ones, and the device u is within 1e-9 of the oracle's solve;
+* Q_p is reproduced (c = 1, g in Q_p), with hybrid Gauss and DWQ plans;
+* on a sliver cut the extended solve converges in no more iterations than
+  the plain one and its error stays that of the plain projection;
+* a visible domain with no block of inner functions is refused.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from gpu_common import inject_oracle_rules, require_gpu, say
+from oracle import extended, project
+from oracle.assemble import Oracle
+from oracle.geometry import Coefficient
+from paper_2101_08053_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+def _sliver(p, y=0.505, N=10):
+    return wl.table1_line(p, N=N, y0=y, y1=y)
+
+
+def _sincos():
+    from paper_2101_08053_amd import igatrim
+    return igatrim.target_sincos(math.pi, 0.0, math.pi, 0.0)
+
+
+def _oracle_columns(o):
+    """Per compact row: {compact inner id: weight} of the oracle's E."""
+    inner_flat, E = extended.extension(o)
+    act_of = o.ts.act_of
+    cols = [dict() for _ in range(o.ts.n_act)]
+    Ec = E.tocoo()
+    for i, j, v in zip(Ec.row, Ec.col, Ec.data):
+        cols[j][int(act_of[inner_flat[i]])] = float(v)
+    return inner_flat, E, cols
+
+
+@pytest.mark.parametrize("cfg", [_sliver(3), wl.config1(N=32), wl.config3(N=20, p=4),
+                                 wl.nonuniform_variant(wl.config1(N=14, p=3))], ids=lambda c: c.name)
+def test_extension_against_oracle(cfg):
+    require_gpu()
+    from paper_2101_08053_amd import igatrim
+    o = Oracle(cfg)
+    plan = igatrim.Plan(cfg)
+    _, fn_of, _ = (t.cpu().numpy() for t in plan.index_maps())
+    assert np.array_equal(fn_of, o.ts.active), "compact numbering differs"
+    members, weights = (t.cpu().numpy() for t in igatrim.extension(plan))
+    _, _, cols = _oracle_columns(o)
+    n_outer, worst = 0, 0.0
+    for j, col in enumerate(cols):
+        m = members[j]
+        ids = [int(v) for v in m if v >= 0]
+        assert sorted(ids) == sorted(col), (j, ids, sorted(col))
+        if len(ids) > 1 or ids[0] != j:
+            n_outer += 1
+        for k, v in zip(m, weights[j]):
+            if k >= 0:
+                worst = max(worst, abs(v - col[int(k)]) / max(1.0, abs(col[int(k)])))
+            else:
+                assert v == 0.0
+    say(f"[ext] {cfg.name}: {n_outer} outer of {len(cols)}, max weight difference {worst:.2e}")
+    assert n_outer > 0 and worst <= 1e-12
+
+
+def _project_both(cfg, method=None, rtol=1e-12):
+    from paper_2101_08053_amd import igatrim
+    o = Oracle(cfg)
+    plan = igatrim.Plan(cfg, igatrim.HYBRID_GAUSS if method is None else method)
+    inject_oracle_rules(plan, o)
+    c = plan.coeff()
+    vals = plan.mass_form(c)
+    u, info = igatrim.l2_project_ext(plan, vals, c, _sincos(), rtol=rtol)
+    u0, info0 = igatrim.l2_project(plan, vals, c, _sincos(), rtol=rtol)
+    return o, u.cpu().numpy(), info, u0.cpu().numpy(), info0
+
+
+@pytest.mark.parametrize("N", [32, 70])
+def test_extended_projection_against_oracle(N):
+    require_gpu()
+    cfg = wl.config1(N=N)
+    o, u, info, u0, info0 = _project_both(cfg)
+    say(f"[l2 ext] circle N={N}: {info} (plain {info0})")
+    assert info["converged"] and info["rel_residual"] <= 1e-12
+    inner_flat, E, _ = _oracle_columns(o)
+    x = u[o.ts.act_of[inner_flat]]                     # inner coefficients are the extended unknowns
+    assert np.abs(E.T @ x - u).max() <= 1e-13 * np.abs(u).max()
+    M = o.hybrid()
+    A = 0.5 * (M + M.T)
+    be = E @ project.rhs(o, wl.config1_target)
+    res = np.linalg.norm(be - E @ (A @ (E.T @ x))) / np.linalg.norm(be)
+    uo = extended.solve_extended(M, project.rhs(o, wl.config1_target), E)
+    du = np.abs(u - uo).max() / np.abs(uo).max()
+    say(f"   oracle residual of device x: {res:.2e}; |u - u_oracle| / |u| = {du:.2e}")
+    assert res <= 1e-10 and du <= 1e-9
+    e_ext = project.l2_error(o, u, wl.config1_target)
+    e_plain = project.l2_error(o, u0, wl.config1_target)
+    say(f"   L2 error extended {e_ext:.3e} plain {e_plain:.3e}")
+    assert e_ext <= 2.0 * e_plain
+
+
+@pytest.mark.parametrize("method", ["hybrid", "dwq"])
+def test_extended_projection_reproduces_qp(method):
+    require_gpu()
+    from paper_2101_08053_amd import igatrim
+    cfg = wl.config3(N=20, p=4)
+    plan = igatrim.Plan(cfg, igatrim.DWQ if method == "dwq" else igatrim.HYBRID_GAUSS)
+    c = plan.coeff(igatrim.COEF_CONST, 1.0)
+    vals = plan.mass_form(c)
+    u, info = igatrim.l2_project_ext(plan, vals, c, igatrim.target_monomial(4, 3), rtol=1e-13)
+    cfg.geom_cp = None   # a constant coefficient maps g by the identity
+    err = project.l2_error(Oracle(cfg, coef=Coefficient(cfg, kind=wl.COEF_CONST)), u.cpu().numpy(),
+                           lambda x, y: x ** 4 * y ** 3)
+    say(f"[ext reproduction] {method}: {info} error {err:.2e}")
+    assert info["converged"] and err < 1e-10
+
+
+@pytest.mark.parametrize("y", [0.505, 0.5001])
+def test_extended_projection_on_a_sliver(y):
+    require_gpu()
+    cfg = _sliver(3, y=y)
+    o, u, info, u0, info0 = _project_both(cfg)
+    e_ext = project.l2_error(o, u, wl.config1_target)
+    e_plain = project.l2_error(o, u0, wl.config1_target)
+    say(f"[ext sliver] y={y}: extended {info} error {e_ext:.3e}; plain {info0} error {e_plain:.3e}; "
+        f"max |u| {np.abs(u).max():.2e} vs {np.abs(u0).max():.2e}")
+    assert info["converged"] and info["iterations"] <= info0["iterations"]
+    assert e_ext <= 2.0 * e_plain + 1e-12
+
+
+def test_extension_needs_an_inner_block():
+    """A strip of height 0.05 in the first row of elements: no inside element, so no inner function."""
+    require_gpu()
+    from paper_2101_08053_amd import igatrim
+    plan = igatrim.Plan(_sliver(3, y=0.05))
+    with pytest.raises(RuntimeError, match="(?i)topology|block"):
+        igatrim.extension(plan)
+    c = plan.coeff()
+    vals = plan.mass_form(c)
+    with pytest.raises(RuntimeError, match="(?i)topology|block"):
+        igatrim.l2_project_ext(plan, vals, c, _sincos())
