@@ -22,7 +22,10 @@
 // the plain projection. E^T is a gather over each outer row's block, E a
 // gather over each inner row's list of the outer rows tied to it; the lists
 // are sorted, so every sum runs in a fixed order and a solve is bitwise
-// reproducible.
+// reproducible. An iteration is three launches, as in the plain solver: the
+// band product of z = E^T p with the partials of p.q = z.(A z); the update,
+// which forms q = E (A z) row by row; the direction, which also forms E^T of
+// the new direction (from E^T z and E^T of the old one).
 #include <cmath>
 
 #include "solve_body.hpp"
@@ -311,33 +314,51 @@ __global__ void k_ext_t(ExtArgs X, const double* __restrict__ x, double* __restr
     z[r] = v;
 }
 
+// w = A z; with part, the block partial of (z . w) at part[block] (z = E^T p: p.q of the extended system).
 template <int P>
 __global__ void __launch_bounds__(kRedThreads) k_ext_spmv(SpArgs S, const double* __restrict__ z,
-                                                          double* __restrict__ w) {
-    const int r = blockIdx.x * kRedThreads + threadIdx.x;
-    if (r < S.n_act) w[r] = spmv_row_cols<P>(S, z, r);
-}
-
-// q = E w, zero at outer rows; with pv, the block partial of (pv . q) at part[block].
-__global__ void __launch_bounds__(kRedThreads) k_ext_e(ExtArgs X, const double* __restrict__ w,
-                                                       double* __restrict__ q, const double* __restrict__ pv,
-                                                       double* __restrict__ part) {
+                                                          double* __restrict__ w, double* __restrict__ part) {
     __shared__ double sh[kRedThreads / 64];
     const int r = blockIdx.x * kRedThreads + threadIdx.x;
-    double pq = 0.0;
-    if (r < X.n_act) {
-        double v = 0.0;
-        if (X.slot[r] < 0) {
-            v = w[r];
-            for (int k = X.off[r]; k < X.off[r + 1]; ++k) v += X.tw[k] * w[X.tj[k]];
-        }
-        q[r] = v;
-        if (pv) pq = pv[r] * v;
+    double zw = 0.0;
+    if (r < S.n_act) {
+        const double v = spmv_row_cols<P>(S, z, r);
+        w[r] = v;
+        zw = z[r] * v;
     }
     if (part) {
-        const double s = block_sum(pq, sh);
+        const double s = block_sum(zw, sh);
         if (threadIdx.x == 0) part[blockIdx.x] = s;
     }
+}
+
+// Row r of E w (zero at outer rows). The list is read eight entries at a
+// time, every load of a chunk issued before its sums (padding adds zeros).
+__device__ __forceinline__ double ext_e_row(const ExtArgs& X, const double* __restrict__ w, int r) {
+    if (X.slot[r] >= 0) return 0.0;
+    double v = w[r];
+    const int b = X.off[r], e = X.off[r + 1];
+    for (int k0 = b; k0 < e; k0 += 8) {
+        int j[8];
+        double t[8], wv[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int k = min(k0 + u, e - 1);
+            j[u] = X.tj[k];
+            t[u] = (k0 + u < e) ? X.tw[k] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) wv[u] = w[j[u]];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v += t[u] * wv[u];
+    }
+    return v;
+}
+
+// q = E w.
+__global__ void k_ext_e(ExtArgs X, const double* __restrict__ w, double* __restrict__ q) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r < X.n_act) q[r] = ext_e_row(X, w, r);
 }
 
 // r = b - q (q = E A E^T x), z = r/d, p = z; partials of (r.z), (r.r), (b.b).
@@ -372,22 +393,109 @@ __global__ void __launch_bounds__(kRedThreads) k_ext_reduce(const double* __rest
     cg_reduce0(part, nblk, scal, sh);
 }
 
-__global__ void __launch_bounds__(kRedThreads) k_ext_update(SpArgs S, double* __restrict__ scal, int par, int nblk,
-                                                            const double* __restrict__ part_pq, double* __restrict__ x,
+// alpha = (r.z) / (p.q) from the product's partials (summed by every block in
+// the same order); q = E w, x += alpha p, r -= alpha q, z = r/d; partials of
+// (r.z), (r.r) at part[2 block ..]. The row's loads, E w among them, do not
+// depend on alpha and are issued before the partials are summed.
+__global__ void __launch_bounds__(kRedThreads) k_ext_update(ExtArgs X, SpArgs S, const double* __restrict__ scal,
+                                                            int par, int nblk, const double* __restrict__ part_pq,
+                                                            const double* __restrict__ w, double* __restrict__ x,
                                                             double* __restrict__ rv, double* __restrict__ zv,
-                                                            const double* __restrict__ pv,
-                                                            const double* __restrict__ qv, double* __restrict__ part) {
+                                                            const double* __restrict__ pv, double* __restrict__ part) {
     __shared__ double sh[kRedThreads / 64];
     __shared__ double s_alpha;
-    cg_update_block(S, blockIdx.x, scal, par, nblk, part_pq, x, rv, zv, pv, qv, part, sh, &s_alpha);
+    const int r = blockIdx.x * kRedThreads + threadIdx.x;
+    const bool act = r < X.n_act;
+    double pp = 0.0;  // this thread's share of the partials, loaded first
+    for (int k = threadIdx.x; k < nblk; k += blockDim.x) pp += part_pq[k];
+    double q = 0.0, pr = 0.0, rr0 = 0.0, xr = 0.0, d = 1.0;
+    if (act) {
+        q = ext_e_row(X, w, r);
+        pr = pv[r];
+        rr0 = rv[r];
+        xr = x[r];
+        d = diag_of(S, r);
+    }
+    const double pq = block_sum(pp, sh);
+    if (threadIdx.x == 0) s_alpha = (pq != 0.0) ? scal[6 + par] / pq : 0.0;
+    __syncthreads();
+    double rz = 0, rr = 0;
+    if (act) {
+        const double alpha = s_alpha;
+        x[r] = xr + alpha * pr;
+        const double res = rr0 - alpha * q;
+        const double z = res / d;
+        rv[r] = res;
+        zv[r] = z;
+        rz = res * z;
+        rr = res * res;
+    }
+    const double s0 = block_sum(rz, sh), s1 = block_sum(rr, sh);
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = s0;
+        part[2 * blockIdx.x + 1] = s1;
+    }
 }
 
-__global__ void __launch_bounds__(kRedThreads) k_ext_dir(int n, double* __restrict__ scal, int par, int nblk,
+// beta = (r.z)_new / (r.z)_old; p_new = z + beta p_old (into the other buffer)
+// and zp = E^T p_new, at an outer row as (E^T z) + beta (E^T p_old): both sums
+// are read before beta is known, with the row's own loads, while the partials
+// are summed. Block 0 stores the new (r.z) and (r.r).
+template <int P>
+__global__ void __launch_bounds__(kRedThreads) k_ext_dir(ExtArgs X, double* __restrict__ scal, int par, int nblk,
                                                          const double* __restrict__ part,
-                                                         const double* __restrict__ zv, double* __restrict__ pv) {
+                                                         const double* __restrict__ zv,
+                                                         const double* __restrict__ p_old, double* __restrict__ p_new,
+                                                         double* __restrict__ zp) {
     __shared__ double sh[kRedThreads / 64];
     __shared__ double s_beta;
-    cg_dir_block(n, blockIdx.x, scal, par, nblk, part, zv, pv, sh, &s_beta);
+    constexpr int L = (P + 1) * (P + 1);
+    const int r = blockIdx.x * kRedThreads + threadIdx.x;
+    const bool act = r < X.n_act;
+    double prz = 0.0, prr = 0.0;  // this thread's share of the partials, loaded first
+    for (int k = threadIdx.x; k < nblk; k += blockDim.x) {
+        prz += part[2 * k];
+        prr += part[2 * k + 1];
+    }
+    int s = -1;
+    double zr = 0.0, pr = 0.0, ez = 0.0, ep = 0.0;
+    if (act) {
+        zr = zv[r];
+        pr = p_old[r];
+        s = X.slot[r];
+        if (s >= 0) {
+#pragma unroll
+            for (int m0 = 0; m0 < L; m0 += P + 1) {
+                int id[P + 1];
+                double wv[P + 1];
+#pragma unroll
+                for (int m = 0; m <= P; ++m) {
+                    id[m] = X.fid[(size_t)s * L + m0 + m];
+                    wv[m] = X.fw[(size_t)s * L + m0 + m];
+                }
+#pragma unroll
+                for (int m = 0; m <= P; ++m) {
+                    ez += wv[m] * zv[id[m]];
+                    ep += wv[m] * p_old[id[m]];
+                }
+            }
+        }
+    }
+    const double rz = block_sum(prz, sh);
+    const double rr = block_sum(prr, sh);
+    if (threadIdx.x == 0) {
+        s_beta = (scal[6 + par] != 0.0) ? rz / scal[6 + par] : 0.0;
+        if (blockIdx.x == 0) {
+            scal[6 + (1 - par)] = rz;
+            scal[2] = rr;
+        }
+    }
+    __syncthreads();
+    if (!act) return;
+    const double beta = s_beta;
+    const double pn = zr + beta * pr;
+    p_new[r] = pn;
+    zp[r] = (s < 0) ? pn : ez + beta * ep;
 }
 
 inline dim3 grid_of(int64_t n, int threads) { return dim3((unsigned)std::max<int64_t>(1, (n + threads - 1) / threads)); }
@@ -413,6 +521,7 @@ void ext_buffers(Plan& P) {
     W.x_z = P.alloc<double>(n);
     W.x_w = P.alloc<double>(n);
     W.x_b = P.alloc<double>(n);
+    W.x_p = P.alloc<double>(n);
 }
 
 ExtArgs ext_args(Plan& P) {
@@ -440,6 +549,15 @@ void ext_build(Plan& P, const ExtArgs& X, bool lists, hipStream_t s) {
     hipLaunchKernelGGL(k_ext_sort, grid_of(n, 256), dim3(256), 0, s, X);
 }
 
+void ext_spmv(Plan& P, const SpArgs& S, const double* z, double* w, double* part, hipStream_t s) {
+    switch (P.p) {
+#define CASE(PP) \
+    case PP: hipLaunchKernelGGL(k_ext_spmv<PP>, grid_of(S.n_act, kRedThreads), dim3(kRedThreads), 0, s, S, z, w, part); break;
+        CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
+#undef CASE
+    }
+}
+
 void ext_check(int err) {
     if (err == kExtNoBlock)
         throw Error{IGA_E_TOPOLOGY, "an outer function has no block of (p+1)^2 inner functions"};
@@ -447,20 +565,13 @@ void ext_check(int err) {
     if (err == kExtCapacity) throw Error{IGA_E_CAPACITY, "more outer functions than the plan reserved"};
 }
 
-// out = E A E^T in (extended vectors); with pv, block partials of (pv . out) at part.
-void ext_apply(Plan& P, const ExtArgs& X, const SpArgs& S, const double* in, double* out, const double* pv,
-               double* part, hipStream_t s) {
+// out = E A E^T in (extended vectors).
+void ext_apply(Plan& P, const ExtArgs& X, const SpArgs& S, const double* in, double* out, hipStream_t s) {
     SolveWork& W = P.sw;
     const int n = (int)P.n_act;
     hipLaunchKernelGGL(k_ext_t, grid_of(n, 256), dim3(256), 0, s, X, in, W.x_z);
-    switch (P.p) {
-#define CASE(PP) \
-    case PP: hipLaunchKernelGGL(k_ext_spmv<PP>, grid_of(n, kRedThreads), dim3(kRedThreads), 0, s, S, (const double*)W.x_z, W.x_w); break;
-        CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
-#undef CASE
-    }
-    hipLaunchKernelGGL(k_ext_e, grid_of(n, kRedThreads), dim3(kRedThreads), 0, s, X, (const double*)W.x_w, out, pv,
-                       part);
+    ext_spmv(P, S, W.x_z, W.x_w, nullptr, s);
+    hipLaunchKernelGGL(k_ext_e, grid_of(n, 256), dim3(256), 0, s, X, (const double*)W.x_w, out);
 }
 
 }  // namespace
@@ -520,12 +631,12 @@ int iga_trim_l2_project_ext(iga_plan* plan, const iga_coeff* c, const double* va
     hipLaunchKernelGGL(k_ext_diag, grid_of(n, 256), dim3(256), 0, s, X, S, W.x_dg);
     S.dg = W.x_dg;
     hipLaunchKernelGGL(k_ext_start, grid_of(n, 256), dim3(256), 0, s, X, (const double*)u, W.x_e);
-    ext_apply(*P, X, S, W.x_e, W.q, nullptr, nullptr, s);
-    hipLaunchKernelGGL(k_ext_e, grid_of(n, kRedThreads), dim3(kRedThreads), 0, s, X, (const double*)W.b, W.x_b,
-                       (const double*)nullptr, (double*)nullptr);
+    ext_apply(*P, X, S, W.x_e, W.q, s);
+    hipLaunchKernelGGL(k_ext_e, grid_of(n, 256), dim3(256), 0, s, X, (const double*)W.b, W.x_b);
     hipLaunchKernelGGL(k_ext_init, grid_of(n, kRedThreads), dim3(kRedThreads), 0, s, S, (const double*)W.x_b,
                        (const double*)W.q, W.r, W.z, W.pv, W.part);
     hipLaunchKernelGGL(k_ext_reduce, dim3(1), dim3(kRedThreads), 0, s, (const double*)W.part, nblk, W.scal);
+    hipLaunchKernelGGL(k_ext_t, grid_of(n, 256), dim3(256), 0, s, X, (const double*)W.pv, W.x_z);
     int err = 0;
     auto read = [&]() {
         HIPX(hipMemcpyAsync(W.h_scal, W.scal, 8 * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -538,17 +649,27 @@ int iga_trim_l2_project_ext(iga_plan* plan, const iga_coeff* c, const double* va
     double rel = (bnorm > 0) ? std::sqrt(W.h_scal[2]) / bnorm : 0.0;
     int it = 0;
     bool conv = rel <= rtol;
+    // directions alternate between two buffers: iteration k reads pbuf[k & 1], writes pbuf[1 - (k & 1)]
+    double* pbuf[2] = {W.pv, W.x_p};
     while (!conv && it < maxit) {
         const int m = std::min(kCgCheck, maxit - it);
         for (int k = 0; k < m; ++k) {
             const int par = (it + k) & 1;
             double* part2 = W.part + nblk;
-            ext_apply(*P, X, S, W.pv, W.q, W.pv, W.part, s);
-            hipLaunchKernelGGL(k_ext_update, dim3(nblk), dim3(kRedThreads), 0, s, S, W.scal, par, nblk,
-                               (const double*)W.part, W.x_e, W.r, W.z, (const double*)W.pv, (const double*)W.q,
-                               part2);
-            hipLaunchKernelGGL(k_ext_dir, dim3(nblk), dim3(kRedThreads), 0, s, n, W.scal, par, nblk,
-                               (const double*)part2, (const double*)W.z, W.pv);
+            ext_spmv(*P, S, W.x_z, W.x_w, W.part, s);
+            hipLaunchKernelGGL(k_ext_update, dim3(nblk), dim3(kRedThreads), 0, s, X, S, (const double*)W.scal, par,
+                               nblk, (const double*)W.part, (const double*)W.x_w, W.x_e, W.r, W.z,
+                               (const double*)pbuf[par], part2);
+            switch (P->p) {
+#define CASE(PP)                                                                                                \
+    case PP:                                                                                                    \
+        hipLaunchKernelGGL(k_ext_dir<PP>, dim3(nblk), dim3(kRedThreads), 0, s, X, W.scal, par, nblk,           \
+                           (const double*)part2, (const double*)W.z, (const double*)pbuf[par], pbuf[1 - par], \
+                           W.x_z);                                                                              \
+        break;
+                CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
+#undef CASE
+            }
         }
         it += m;
         read();

@@ -154,7 +154,7 @@ struct SolveWork {
     double* x_fw = nullptr;     // [x_cap][(p+1)^2] their weights
     int* x_tj = nullptr;        // per inner row, ascending: the outer rows tied to it
     double* x_tw = nullptr;     // and their weights
-    double *x_dg = nullptr, *x_e = nullptr, *x_z = nullptr, *x_w = nullptr, *x_b = nullptr;
+    double *x_dg = nullptr, *x_e = nullptr, *x_z = nullptr, *x_w = nullptr, *x_b = nullptr, *x_p = nullptr;
     int x_cap = 0;
 };
 
