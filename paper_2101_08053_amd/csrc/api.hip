@@ -70,10 +70,10 @@ static void check_status(Plan& P, hipStream_t s) {
 // back after each stage to size the next buffers (plan creation only).
 // Univariate tables, weighted-quadrature weights (and DWQ side rules): they
 // depend on the knots only.
-static void setup_tables(Plan& P, hipStream_t s) {
+static void setup_tables(Plan& P, hipStream_t s, bool sides = true) {
     launch_dir_tables(P, s);
     launch_wq_weights(P, s);
-    launch_dwq_sides(P, s);
+    if (sides) launch_dwq_sides(P, s);
 }
 
 // Trimming, classes, lists, cut rules and (with `points`) the grid and band
@@ -238,9 +238,11 @@ static void form_serial(Plan& P, const iga_coeff& c, double* vals, int flags, hi
 // Two streams: the caller's stream s carries the trimming chain, the cut
 // rules, the band/cut coefficients and the cut rows; the plan's second
 // stream carries the univariate tables and weights, the WQ-grid coefficient
-// and the interior rows (after the compact maps exist). Both start after the
-// work already queued on s and are joined back into s. Phase timers: SETUP
-// and CUT on s, COEF (WQ grid) and INTERIOR on the second stream (they overlap).
+// and the interior rows (after the compact maps exist); a DWQ plan's side
+// rules run on s after the cut element matrices.
+// Both start after the work already queued on s and are joined back into s.
+// Phase timers: SETUP and CUT on s, COEF (WQ grid) and INTERIOR on the second
+// stream (they overlap).
 static void form(Plan& P, const iga_coeff& c, double* vals, int flags, hipStream_t s) {
     if (P.method == IGA_NAIVE_WQ) {
         form_serial(P, c, vals, flags, s);
@@ -270,7 +272,10 @@ static void form(Plan& P, const iga_coeff& c, double* vals, int flags, hipStream
         HIPX(hipEventRecord(P.ev_lists, s));
     }
     HIPX(hipStreamWaitEvent(a, P.ev_fork, 0));
-    if (full) setup_tables(P, a);
+    // A full DWQ formation runs the side rules (which read the knots only) on
+    // the caller's stream after the cut element matrices, where that stream
+    // waits for the second one anyway.
+    if (full) setup_tables(P, a, false);
     {
         PhaseTimer t(P, a, IGA_PHASE_COEF);
         launch_coef(P, c, a, 1, pts_by_coef);
@@ -316,6 +321,7 @@ static void form(Plan& P, const iga_coeff& c, double* vals, int flags, hipStream
     {
         PhaseTimer t(P, s, IGA_PHASE_CUT);
         launch_cut_elems(P, c, s);  // with c at the cut nodes
+        if (full) launch_dwq_sides(P, s);  // DWQ plans: from the knots alone
         HIPX(hipStreamWaitEvent(s, P.ev_band, 0));
         launch_cut_rows_mode(P, c, vals, s, 2);  // plus the cut element matrices' entries
         launch_dwq_rows(P, c, vals, s);
@@ -429,6 +435,7 @@ int iga_trim_plan_create(const iga_patch_desc* desc, const iga_opts* opts, iga_p
         HIPX(hipEventCreateWithFlags(e, hipEventDisableTiming));
     P->p = p;
     P->method = desc->method;
+
     if (opts)
         for (int k = 0; k < 5; ++k) IGA_REQUIRE(opts->reserved[k] == 0, IGA_E_INVALID, "reserved option fields must be 0");
     P->n_r = (opts && opts->n_r > 0) ? opts->n_r : p + 1;
