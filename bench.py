@@ -637,7 +637,7 @@ def bench_adjoint(igatrim, wl, cfg_unused, args, sync, stream, peaks):
     # algorithmic bytes: forward reads u and c, writes y; adjoint reads u, c, r, writes du and dc
     fwd_bytes = 8 * (2 * n + npts)
     bwd_bytes = 8 * (3 * n + 2 * npts)
-    # the one-pass grid kernels alone (per-kernel HIP events): c on the WQ grid plus the vectors
+    # the one-launch kernels alone (per-kernel HIP events)
     plan.set_timing(True, per_kernel=True)
     for _ in range(2):
         igatrim.mf_apply(plan, c, u)
@@ -652,8 +652,13 @@ def bench_adjoint(igatrim, wl, cfg_unused, args, sync, stream, peaks):
     nq = sz["q1"] * sz["q2"]
     kernels = {k: {"avg_launch_ms": ms / max(1, cnt), "calls": cnt} for k, (ms, cnt) in kt.items()}
     grid_roofs = {}
-    for name, nbytes, per in ((f"k_mf_fwd<{p}>", 8 * (nq + 2 * n), "8 B per WQ-grid c and per u, y value"),
-                              (f"k_mf_adj<{p}>", 8 * (2 * nq + 3 * n), "8 B per WQ-grid c, dc and per u, r, du value")):
+    # the one-launch kernels: the grid part and the element vectors (Ue, (p+1)^2 entries per band or cut
+    # element) beside it
+    ue = (p + 1) ** 2 * (sz["n_band_el"] + sz["n_cut_el"])
+    for name, nbytes, per in ((f"k_mf_fwd<{p}>", 8 * (npts + 2 * n + ue),
+                               "8 B per rule-point c, per u, y value and per element-vector entry written"),
+                              (f"k_mf_adj<{p}>", 8 * (2 * npts + 3 * n + ue),
+                               "8 B per rule-point c, dc, per u, r, du value and per element-vector entry written")):
         if name in kernels:
             grid_roofs[name] = _roof(name, "hbm", nbytes, kernels[name]["avg_launch_ms"], peaks, per,
                                      "HIP events at the dispatch's start and end")
@@ -663,10 +668,10 @@ def bench_adjoint(igatrim, wl, cfg_unused, args, sync, stream, peaks):
             "plain_value": nnz / (ms_form * 1e-3), "unit": "nnz-equivalent/s", "nnz": nnz,
             "n_act": n, "n_points": npts,
             "rooflines": {
-                "forward": _roof("matrix-free forward (k_mf_band, k_mf_elem, k_mf_gather_rows, k_mf_fwd, k_mf_fix)",
+                "forward": _roof("matrix-free forward (k_mf_fwd, k_mf_rows)",
                                  "hbm", fwd_bytes, ms_fwd, peaks, "8 B per u, y value and per rule-point c",
                                  "whole call timed on the host / calls"),
-                "adjoint": _roof("matrix-free adjoint (k_mf_band, k_mf_elem, k_mf_adj, k_mf_fix, k_mf_gather_add)",
+                "adjoint": _roof("matrix-free adjoint (k_mf_adj, k_mf_fix, k_mf_gather_add)",
                                  "hbm", bwd_bytes, ms_bwd, peaks, "8 B per u, r, du value and per rule-point c, dc",
                                  "whole call timed on the host / calls"),
                 **grid_roofs},

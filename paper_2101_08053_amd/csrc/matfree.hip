@@ -87,22 +87,36 @@ struct MfFwdArgs {
     double* tail; // [nband][p][n1]
 };
 
+// LDS of one forward workgroup of the grid part.
 template <int P>
-__global__ void __launch_bounds__(kMfThreads) k_mf_fwd(MfArgs A, MfFwdArgs F, const double* __restrict__ u,
-                                                       double* __restrict__ y) {
-    constexpr int NP = kMfThreads * kMfNpt, NW = 2 * P + 2, QM = 4 * P + 2, NU = kMfThreads * kMfUpt;
-    constexpr int NG = NP + QM;   // the column sums read up to 4p+1 points past a strip's last one
+struct MfFwdSmem {
+    static constexpr int NP = kMfThreads * kMfNpt, QM = 4 * P + 2, NU = kMfThreads * kMfUpt;
+    static constexpr int NG = NP + QM;   // the column sums read up to 4p+1 points past a strip's last one
     // G of a row with even and odd points apart: the column sums read points k0(i1) + q, and k0
     // steps by 2 from one column to the next, so each half is read with unit stride (no bank conflicts)
-    constexpr int NGH = (NG + 1) / 2;
+    static constexpr int NGH = (NG + 1) / 2;
+    double sU[P + 1][NU];  // the first p+1 u rows; then rows alternate in sU[0], sU[1]
+    double sV[P + 1][NP];
+    double sG[2][2 * NGH];
+    double sB2[kMfSlots][P + 1], sW2[kMfSlots][P + 1];
+    int sK2[kMfSlots];
+};
+
+// Workgroup blk (strip blk % nstrip, band blk / nstrip) of the forward grid part.
+template <int P>
+__device__ __forceinline__ void mf_fwd_body(const MfArgs& A, const MfFwdArgs& F, int blk,
+                                            const double* __restrict__ u, double* __restrict__ y, MfFwdSmem<P>& SM) {
+    constexpr int NP = MfFwdSmem<P>::NP, NW = 2 * P + 2, QM = MfFwdSmem<P>::QM, NU = MfFwdSmem<P>::NU;
+    constexpr int NG = MfFwdSmem<P>::NG, NGH = MfFwdSmem<P>::NGH;
     auto gi = [](int k) { return (k & 1) * NGH + (k >> 1); };
-    __shared__ double sU[P + 1][NU];  // the first p+1 u rows; then rows alternate in sU[0], sU[1]
-    __shared__ double sV[P + 1][NP];
-    __shared__ double sG[2][2 * NGH];
-    __shared__ double sB2[kMfSlots][P + 1], sW2[kMfSlots][P + 1];
-    __shared__ int sK2[kMfSlots];
+    auto& sU = SM.sU;
+    auto& sV = SM.sV;
+    auto& sG = SM.sG;
+    auto& sB2 = SM.sB2;
+    auto& sW2 = SM.sW2;
+    auto& sK2 = SM.sK2;
     const int tid = threadIdx.x;
-    const int strip = blockIdx.x % F.nstrip, bnd = blockIdx.x / F.nstrip;
+    const int strip = blk % F.nstrip, bnd = blk / F.nstrip;
     const int n1 = A.n1, N1 = A.N1, N2 = A.N2, Q1 = A.d1.Q;
     const int c0 = strip * F.cols, c1 = min(n1, c0 + F.cols);
     const int E0 = bnd * F.band, E1 = (bnd == F.nband - 1) ? N2 : E0 + F.band, NE = E1 - E0;
@@ -340,22 +354,37 @@ __global__ void __launch_bounds__(kMfThreads) k_mf_fwd(MfArgs A, MfFwdArgs F, co
 // r counts on rows formed by weighted quadrature only; du rows are
 // written for every active function (head, tail and k_mf_fix as forward),
 // the element part is added afterwards.
+// LDS of one adjoint workgroup of the grid part.
 template <int P>
-__global__ void __launch_bounds__(kMfThreads) k_mf_adj(MfArgs A, MfFwdArgs F, const double* __restrict__ u,
-                                                       const double* __restrict__ r, double* __restrict__ du,
-                                                       double* __restrict__ dc) {
-    constexpr int NP = kMfThreads * kMfNpt, NW = 2 * P + 2, QM = 4 * P + 2, NU = kMfThreads * kMfUpt;
-    constexpr int NG = NP + QM;
-    constexpr int NGH = (NG + 1) / 2;   // CR rows with even and odd points apart (unit-stride column sums)
+struct MfAdjSmem {
+    static constexpr int NP = kMfThreads * kMfNpt, QM = 4 * P + 2, NU = kMfThreads * kMfUpt;
+    static constexpr int NG = NP + QM;
+    static constexpr int NGH = (NG + 1) / 2;   // CR rows with even and odd points apart (unit-stride column sums)
+    double sU[P + 1][NU];
+    double sV[P + 1][NP];
+    double sH[2][kMfThreads];
+    double sC[2][2 * NGH];
+    double sB2[kMfSlots][P + 1], sW2[kMfSlots][P + 1];
+    int sK2[kMfSlots];
+};
+
+// Workgroup blk of the adjoint grid part.
+template <int P>
+__device__ __forceinline__ void mf_adj_body(const MfArgs& A, const MfFwdArgs& F, int blk,
+                                            const double* __restrict__ u, const double* __restrict__ r,
+                                            double* __restrict__ du, double* __restrict__ dc, MfAdjSmem<P>& SM) {
+    constexpr int NP = MfAdjSmem<P>::NP, NW = 2 * P + 2, QM = MfAdjSmem<P>::QM, NU = MfAdjSmem<P>::NU;
+    constexpr int NG = MfAdjSmem<P>::NG, NGH = MfAdjSmem<P>::NGH;
     auto gi = [](int k) { return (k & 1) * NGH + (k >> 1); };
-    __shared__ double sU[P + 1][NU];
-    __shared__ double sV[P + 1][NP];
-    __shared__ double sH[2][kMfThreads];
-    __shared__ double sC[2][2 * NGH];
-    __shared__ double sB2[kMfSlots][P + 1], sW2[kMfSlots][P + 1];
-    __shared__ int sK2[kMfSlots];
+    auto& sU = SM.sU;
+    auto& sV = SM.sV;
+    auto& sH = SM.sH;
+    auto& sC = SM.sC;
+    auto& sB2 = SM.sB2;
+    auto& sW2 = SM.sW2;
+    auto& sK2 = SM.sK2;
     const int tid = threadIdx.x;
-    const int strip = blockIdx.x % F.nstrip, bnd = blockIdx.x / F.nstrip;
+    const int strip = blk % F.nstrip, bnd = blk / F.nstrip;
     const int n1 = A.n1, N1 = A.N1, N2 = A.N2, Q1 = A.d1.Q;
     const int c0 = strip * F.cols, c1 = min(n1, c0 + F.cols);
     const int E0 = bnd * F.band, E1 = (bnd == F.nband - 1) ? N2 : E0 + F.band, NE = E1 - E0;
@@ -629,8 +658,8 @@ __global__ void __launch_bounds__(kMfThreads) k_mf_adj(MfArgs A, MfFwdArgs F, co
 // Rows whose support spans two bands: the band's head plus the previous band's tail.
 // (all_rows: every active row, as the adjoint's du; else the weighted-quadrature rows)
 template <int P>
-__global__ void __launch_bounds__(256) k_mf_fix(MfArgs A, MfFwdArgs F, double* __restrict__ y, int all_rows) {
-    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+__device__ __forceinline__ void mf_fix_at(const MfArgs& A, const MfFwdArgs& F, double* __restrict__ y, int all_rows,
+                                          int64_t t) {
     const int n1 = A.n1;
     if (t >= (int64_t)(F.nband - 1) * P * n1) return;
     const int bnd = 1 + (int)(t / ((int64_t)P * n1)), r = (int)((t / n1) % P), i1 = (int)(t % n1);
@@ -641,20 +670,37 @@ __global__ void __launch_bounds__(256) k_mf_fix(MfArgs A, MfFwdArgs F, double* _
     y[id] = F.tail[((size_t)(bnd - 1) * P + r) * n1 + i1] + F.head[((size_t)bnd * P + r) * n1 + i1];
 }
 
+template <int P>
+__global__ void __launch_bounds__(256) k_mf_fix(MfArgs A, MfFwdArgs F, double* __restrict__ y, int all_rows) {
+    mf_fix_at<P>(A, F, y, all_rows, (int64_t)blockIdx.x * 256 + threadIdx.x);
+}
+
 // Band elements (inside elements of the rows formed element-wise; a tensor
-// Gauss rule of (p+1)^2 points): several elements per 256-thread workgroup,
+// Gauss rule of (p+1)^2 points): several elements per workgroup of NT threads,
 // thread (element, l) taking local function l for u, point l for U, and
 // output l, the element's basis tables shared in LDS:
 //   U_g = sum_a2 B2[g2][a2] sum_a1 B1[g1][a1] u_a,  Y_l = sum_g2 B2[g2][l2] sum_g1 B1[g1][l1] w_g c_g U_g
 // (adjoint: R_g from r alike, dc_g = U_g w_g R_g, D_l from c_g w_g R_g).
-template <int P>
-__global__ void __launch_bounds__(256) k_mf_band(MfArgs A, const double* __restrict__ u, const double* __restrict__ r,
-                                                 double* __restrict__ Ye, double* __restrict__ dc) {
-    constexpr int NP1 = P + 1, L = NP1 * NP1, EPW = 256 / L;
-    __shared__ double sU[EPW][L], sR[EPW][L], sT[EPW][L];
-    __shared__ double sB1[EPW][NP1][NP1], sB2[EPW][NP1][NP1];
+template <int P, int NT>
+struct MfBandSmem {
+    static constexpr int NP1 = P + 1, L = NP1 * NP1, EPW = NT / L;
+    double sU[EPW][L], sR[EPW][L], sT[EPW][L];
+    double sB1[EPW][NP1][NP1], sB2[EPW][NP1][NP1];
+};
+
+template <int P, int NT>
+__device__ __forceinline__ void mf_band_body(const MfArgs& A, int blk, const double* __restrict__ u,
+                                             const double* __restrict__ r, double* __restrict__ Ye,
+                                             double* __restrict__ dc, MfBandSmem<P, NT>& S) {
+    constexpr int NP1 = P + 1, L = NP1 * NP1, EPW = NT / L;
+    static_assert(EPW >= 1, "an element's functions must fit the workgroup");
+    auto& sU = S.sU;
+    auto& sR = S.sR;
+    auto& sT = S.sT;
+    auto& sB1 = S.sB1;
+    auto& sB2 = S.sB2;
     const int el = threadIdx.x / L, l = threadIdx.x % L;
-    const int re = blockIdx.x * EPW + el;
+    const int re = blk * EPW + el;
     const bool on = el < EPW && re < A.n_band;
     const int e = A.band_list[on ? re : 0];
     const int e1 = e % A.N1, e2 = e / A.N1;
@@ -716,30 +762,43 @@ __global__ void __launch_bounds__(256) k_mf_band(MfArgs A, const double* __restr
     Ye[(size_t)re * L + l] = y;
 }
 
-// Cut elements, one 64-thread workgroup each: per chunk of 64 nodes, node n's
-// basis rows (from the element's reciprocal table: no divisions), U_n and
+// Cut elements, one workgroup of NT threads each: per chunk of NT nodes, node
+// n's basis rows (from the element's reciprocal table: no divisions), U_n and
 // the weight term T_n in LDS; then the (p+1)^2 outputs are split over
-// G = max(1, 64 / (p+1)^2) lane groups, group g summing the chunk's nodes
+// G = max(1, NT / (p+1)^2) lane groups, group g summing the chunk's nodes
 // m = g (mod G), and the groups' sums are added in order at the end.
-template <int P>
-__global__ void __launch_bounds__(64) k_mf_elem(MfArgs A, int re0, const double* __restrict__ u,
-                                                const double* __restrict__ r, double* __restrict__ Ye,
-                                                double* __restrict__ dc) {
+template <int P, int NT>
+struct MfElemSmem {
+    static constexpr int NP1 = P + 1, L = NP1 * NP1;
+    static constexpr int G = L >= NT ? 1 : NT / L;  // lane groups of the accumulation
+    static constexpr int NR = P * (P + 1) / 2;       // reciprocals of one span
+    double sB1[NT][NP1], sB2[NT][NP1];
+    double sT[NT];
+    double sU[L], sR[L];
+    double sRec[2][NR + 1];
+    double sAcc[G][L];
+};
+
+template <int P, int NT>
+__device__ __forceinline__ void mf_elem_body(const MfArgs& A, int re, const double* __restrict__ u,
+                                             const double* __restrict__ r, double* __restrict__ Ye,
+                                             double* __restrict__ dc, MfElemSmem<P, NT>& S) {
     constexpr int NP1 = P + 1, L = NP1 * NP1;
-    constexpr int G = L >= 64 ? 1 : 64 / L;      // lane groups of the accumulation
-    constexpr int PER = (L + 63) / 64;           // outputs per lane when G = 1
-    constexpr int NR = P * (P + 1) / 2;          // reciprocals of one span
-    __shared__ double sB1[64][NP1], sB2[64][NP1];
-    __shared__ double sT[64];
-    __shared__ double sU[L], sR[L];
-    __shared__ double sRec[2][NR + 1];
-    __shared__ double sAcc[G][L];
+    constexpr int G = MfElemSmem<P, NT>::G;      // lane groups of the accumulation
+    constexpr int PER = (L + NT - 1) / NT;       // outputs per lane when G = 1
+    constexpr int NR = MfElemSmem<P, NT>::NR;    // reciprocals of one span
+    auto& sB1 = S.sB1;
+    auto& sB2 = S.sB2;
+    auto& sT = S.sT;
+    auto& sU = S.sU;
+    auto& sR = S.sR;
+    auto& sRec = S.sRec;
+    auto& sAcc = S.sAcc;
     const int tid = threadIdx.x;
-    const int re = re0 + blockIdx.x;
     const bool is_cut = re >= A.n_band;
     const int e = is_cut ? A.cut_list[re - A.n_band] : A.band_list[re];
     const int e1 = e % A.N1, e2 = e / A.N1;
-    for (int l = tid; l < L; l += 64) {
+    for (int l = tid; l < L; l += NT) {
         int j1 = e1 + l % NP1, j2 = e2 + l / NP1;
         int f = j2 * A.n1 + j1;
         int cid = A.act_of[f];
@@ -748,8 +807,8 @@ __global__ void __launch_bounds__(64) k_mf_elem(MfArgs A, int re0, const double*
         bool erow = cid >= 0 && !wq_row(A, A.fcls[f]);
         sR[l] = (r && erow) ? r[cid] : 0.0;
     }
-    if (tid < 2 * NR) {
-        const int d = tid / NR, idx = tid % NR;
+    for (int t = tid; t < 2 * NR; t += NT) {
+        const int d = t / NR, idx = t % NR;
         sRec[d][idx] = basis_rec<P>(d ? A.d2.knots : A.d1.knots, P + (d ? e2 : e1), idx);
     }
     int nb, ne, pbase;
@@ -762,13 +821,13 @@ __global__ void __launch_bounds__(64) k_mf_elem(MfArgs A, int re0, const double*
         ne = L;
         pbase = A.nq + re * L;
     }
-    // this lane's outputs: group grp, local functions l = li + 64 k (G = 1) or li (G > 1)
+    // this lane's outputs: group grp, local functions l = li + NT k (G = 1) or li (G > 1)
     const int grp = (G > 1) ? tid / L : 0, li = (G > 1) ? tid % L : tid;
     const bool acc_on = (G > 1) ? grp < G : true;
     double acc[PER];
 #pragma unroll
     for (int k = 0; k < PER; ++k) acc[k] = 0.0;
-    for (int base = nb; base < ne; base += 64) {
+    for (int base = nb; base < ne; base += NT) {
         __syncthreads();
         int n = base + tid;
         if (n < ne) {
@@ -813,11 +872,11 @@ __global__ void __launch_bounds__(64) k_mf_elem(MfArgs A, int re0, const double*
             }
         }
         __syncthreads();
-        const int cnt = min(64, ne - base);
+        const int cnt = min(NT, ne - base);
         if (acc_on) {
 #pragma unroll
             for (int k = 0; k < PER; ++k) {
-                const int l = li + 64 * k;
+                const int l = li + NT * k;
                 if (l < L) {
                     const int a1 = l % NP1, a2 = l / NP1;
                     for (int m = grp; m < cnt; m += G) acc[k] += sT[m] * sB1[m][a1] * sB2[m][a2];
@@ -837,7 +896,7 @@ __global__ void __launch_bounds__(64) k_mf_elem(MfArgs A, int re0, const double*
     } else {
 #pragma unroll
         for (int k = 0; k < PER; ++k) {
-            const int l = li + 64 * k;
+            const int l = li + NT * k;
             if (l < L) Ye[(size_t)re * L + l] = acc[k];
         }
     }
@@ -849,10 +908,9 @@ __global__ void __launch_bounds__(64) k_mf_elem(MfArgs A, int re0, const double*
 // (classes, then element ids, then vector entries loaded together), the four
 // partial sums added in the quad.
 template <int P>
-__global__ void __launch_bounds__(256) k_mf_gather_rows(MfArgs A, const int* __restrict__ rows, int n_rows,
-                                                        const double* __restrict__ Ye, double* __restrict__ y) {
+__device__ __forceinline__ void mf_gather_at(const MfArgs& A, const int* __restrict__ rows, int n_rows,
+                                             const double* __restrict__ Ye, double* __restrict__ y, int t) {
     constexpr int L = (P + 1) * (P + 1), PER = (L + 3) / 4;
-    const int t = blockIdx.x * 256 + threadIdx.x;
     const int ri = t >> 2, part = t & 3;
     const bool ok = ri < n_rows;   // lanes past the list still take part in the quad sum
     const int r = rows[min(ri, n_rows - 1)], f = A.fn_of[r];
@@ -886,6 +944,65 @@ __global__ void __launch_bounds__(256) k_mf_gather_rows(MfArgs A, const int* __r
     }
     s = quad_sum(s);
     if (ok && part == 0 && !wq_row(A, A.fcls[f])) y[r] = s;
+}
+
+// The forward's row fix-ups in one launch: blocks below nfix add band heads
+// to tails (k_mf_fix's rows), the others gather the element vectors of the
+// rows formed element-wise (disjoint rows of y).
+template <int P>
+__global__ void __launch_bounds__(256) k_mf_rows(MfArgs A, MfFwdArgs F, int nfix, const int* __restrict__ rows,
+                                                 int n_rows, const double* __restrict__ Ye, double* __restrict__ y) {
+    if ((int)blockIdx.x < nfix)
+        mf_fix_at<P>(A, F, y, 0, (int64_t)blockIdx.x * 256 + threadIdx.x);
+    else
+        mf_gather_at<P>(A, rows, n_rows, Ye, y, ((int)blockIdx.x - nfix) * 256 + threadIdx.x);
+}
+
+// The forward in one launch: the first workgroups take the weighted-
+// quadrature grid part, the next ncut the cut elements and the last
+// nband_blk the band elements (their element vectors). The grid part's
+// workgroups come first: the element workgroups, latency-bound, then fill
+// the CUs as the grid part frees them (0.048 against 0.053 ms the other way
+// round at 1024^2). All roles share one LDS allocation.
+template <int P>
+__global__ void __launch_bounds__(kMfThreads) k_mf_fwd(MfArgs A, MfFwdArgs F, int ncut, int nband_blk,
+                                                       const double* __restrict__ u, double* __restrict__ y,
+                                                       double* __restrict__ Ye) {
+    __shared__ union {
+        MfFwdSmem<P> f;
+        MfElemSmem<P, kMfThreads> e;
+        MfBandSmem<P, kMfThreads> b;
+    } S;
+    const int ngrid = (int)gridDim.x - ncut - nband_blk;
+    const int blk = blockIdx.x;
+    if (blk < ngrid)
+        mf_fwd_body<P>(A, F, blk, u, y, S.f);
+    else if (blk - ngrid < ncut)
+        mf_elem_body<P, kMfThreads>(A, A.n_band + blk - ngrid, u, nullptr, Ye, nullptr, S.e);
+    else
+        mf_band_body<P, kMfThreads>(A, blk - ngrid - ncut, u, nullptr, Ye, nullptr, S.b);
+}
+
+// The adjoint's grid part and its element vectors (and dc at band Gauss
+// points and cut nodes) in one launch, laid out as the forward's.
+template <int P>
+__global__ void __launch_bounds__(kMfThreads) k_mf_adj(MfArgs A, MfFwdArgs F, int ncut, int nband_blk,
+                                                       const double* __restrict__ u, const double* __restrict__ r,
+                                                       double* __restrict__ du, double* __restrict__ dc,
+                                                       double* __restrict__ Ye) {
+    __shared__ union {
+        MfAdjSmem<P> a;
+        MfElemSmem<P, kMfThreads> e;
+        MfBandSmem<P, kMfThreads> b;
+    } S;
+    const int ngrid = (int)gridDim.x - ncut - nband_blk;
+    const int blk = blockIdx.x;
+    if (blk < ngrid)
+        mf_adj_body<P>(A, F, blk, u, r, du, dc, S.a);
+    else if (blk - ngrid < ncut)
+        mf_elem_body<P, kMfThreads>(A, A.n_band + blk - ngrid, u, r, Ye, dc, S.e);
+    else
+        mf_band_body<P, kMfThreads>(A, blk - ngrid - ncut, u, r, Ye, dc, S.b);
 }
 
 // Adjoint: the element vectors of the band and cut elements of each listed
@@ -1019,22 +1136,12 @@ static void mf_adj_rows(Plan& P, hipStream_t s) {
 
 static dim3 grid256(int64_t n) { return dim3((unsigned)((n + 255) / 256)); }
 
-// Element vectors: band elements several to a workgroup, cut elements one each.
-static void launch_elem(Plan& P, const MfArgs& A, const double* u, const double* r, double* Ye, double* dc,
-                        hipStream_t s) {
-    const int nb = (int)P.n_band, nc = (int)P.n_cut_el;
-    const int epw = 256 / ((P.p + 1) * (P.p + 1));
-    switch (P.p) {
-#define CASE(PP)                                                                                          \
-    case PP:                                                                                              \
-        if (nb > 0)                                                                                       \
-            klaunch(P, "k_mf_band<" #PP ">", k_mf_band<PP>, dim3((nb + epw - 1) / epw), dim3(256), 0, s, A, u, r, Ye, \
-                    dc);                                                                                  \
-        if (nc > 0) klaunch(P, "k_mf_elem<" #PP ">", k_mf_elem<PP>, dim3(nc), dim3(64), 0, s, A, nb, u, r, Ye, dc); \
-        break;
-        CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
-#undef CASE
-    }
+// Element workgroups of the one-launch forward and adjoint: the cut elements
+// one each, the band elements kMfThreads / (p+1)^2 to a workgroup.
+static void elem_blocks(const Plan& P, int& ncut, int& nband_blk) {
+    const int epw = kMfThreads / ((P.p + 1) * (P.p + 1));
+    ncut = (int)P.n_cut_el;
+    nband_blk = (int)((P.n_band + epw - 1) / epw);
 }
 
 static const char* const kMfFwdNames[] = {"", "k_mf_fwd<1>", "k_mf_fwd<2>", "k_mf_fwd<3>", "k_mf_fwd<4>",
@@ -1043,41 +1150,55 @@ static const char* const kMfAdjNames[] = {"", "k_mf_adj<1>", "k_mf_adj<2>", "k_m
                                           "k_mf_adj<5>", "k_mf_adj<6>", "k_mf_adj<7>", "k_mf_adj<8>"};
 static const char* const kMfFixNames[] = {"", "k_mf_fix<1>", "k_mf_fix<2>", "k_mf_fix<3>", "k_mf_fix<4>",
                                           "k_mf_fix<5>", "k_mf_fix<6>", "k_mf_fix<7>", "k_mf_fix<8>"};
+static const char* const kMfRowsNames[] = {"", "k_mf_rows<1>", "k_mf_rows<2>", "k_mf_rows<3>", "k_mf_rows<4>",
+                                           "k_mf_rows<5>", "k_mf_rows<6>", "k_mf_rows<7>", "k_mf_rows<8>"};
 
+// Forward: element vectors and the grid part in one launch, then the row
+// fix-ups (band heads added to tails, element vectors gathered) in another.
+// The reference rules have no grid part: every row is formed element-wise.
 template <int P>
-static void launch_wq_forward(Plan& Pl, const MfArgs& A, const double* u, double* y, double* part, hipStream_t s) {
-    MfFwdArgs F = mf_fwd_shape(Pl);
-    F.head = part;
-    F.tail = part + (size_t)F.nband * P * Pl.n1;
-    klaunch(Pl, kMfFwdNames[P], k_mf_fwd<P>, dim3((unsigned)(F.nstrip * F.nband)), dim3(kMfThreads), 0, s, A, F, u, y);
-    if (F.nband > 1)
-        klaunch(Pl, kMfFixNames[P], k_mf_fix<P>, grid256((int64_t)(F.nband - 1) * P * Pl.n1), dim3(256), 0, s, A, F, y,
-                0);
-}
-
-static void launch_gather_rows(Plan& P, const MfArgs& A, const double* Ye, double* y, hipStream_t s) {
-    const int nr = (int)P.n_form_rows;
-    if (nr == 0) return;
-    switch (P.p) {
-#define CASE(PP)                                                                                            \
-    case PP:                                                                                                \
-        klaunch(P, "k_mf_gather_rows<" #PP ">", k_mf_gather_rows<PP>, grid256(4 * (int64_t)nr), dim3(256), 0, s, A, \
-                (const int*)P.form_rows, nr, Ye, y);                                                        \
-        break;
-        CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
-#undef CASE
+static void launch_forward(Plan& Pl, const MfArgs& A, const double* u, double* y, double* part, double* Ue,
+                           hipStream_t s) {
+    const bool wq = Pl.method != IGA_GAUSS_REF;
+    MfFwdArgs F{};
+    if (wq) {
+        F = mf_fwd_shape(Pl);
+        F.head = part;
+        F.tail = part + (size_t)F.nband * P * Pl.n1;
     }
+    int ncut = 0, nbb = 0;
+    elem_blocks(Pl, ncut, nbb);
+    const int64_t nblk = (int64_t)ncut + nbb + (wq ? (int64_t)F.nstrip * F.nband : 0);
+    if (nblk > 0)
+        klaunch(Pl, kMfFwdNames[P], k_mf_fwd<P>, dim3((unsigned)nblk), dim3(kMfThreads), 0, s, A, F, ncut, nbb, u, y,
+                Ue);
+    const int nfix = (wq && F.nband > 1) ? (int)grid256((int64_t)(F.nband - 1) * P * Pl.n1).x : 0;
+    const int nr = (int)Pl.n_form_rows;
+    const int ngat = nr > 0 ? (int)grid256(4 * (int64_t)nr).x : 0;
+    if (nfix + ngat > 0)
+        klaunch(Pl, kMfRowsNames[P], k_mf_rows<P>, dim3(nfix + ngat), dim3(256), 0, s, A, F, nfix,
+                (const int*)Pl.form_rows, nr, (const double*)Ue, y);
 }
 
+// Adjoint: element vectors (with dc at their points) and the grid part (every
+// active row of du) in one launch, then the band heads added to tails.
 template <int P>
-static void launch_wq_adjoint(Plan& Pl, const MfArgs& A, const double* u, const double* r, double* du, double* dc,
-                              double* part, hipStream_t s) {
-    MfFwdArgs F = mf_fwd_shape(Pl, true);
-    F.head = part;
-    F.tail = part + (size_t)F.nband * P * Pl.n1;
-    klaunch(Pl, kMfAdjNames[P], k_mf_adj<P>, dim3((unsigned)(F.nstrip * F.nband)), dim3(kMfThreads), 0, s, A, F, u, r,
-            du, dc);
-    if (F.nband > 1)
+static void launch_adjoint(Plan& Pl, const MfArgs& A, const double* u, const double* r, double* du, double* dc,
+                           double* part, double* Ue, hipStream_t s) {
+    const bool wq = Pl.method != IGA_GAUSS_REF;
+    MfFwdArgs F{};
+    if (wq) {
+        F = mf_fwd_shape(Pl, true);
+        F.head = part;
+        F.tail = part + (size_t)F.nband * P * Pl.n1;
+    }
+    int ncut = 0, nbb = 0;
+    elem_blocks(Pl, ncut, nbb);
+    const int64_t nblk = (int64_t)ncut + nbb + (wq ? (int64_t)F.nstrip * F.nband : 0);
+    if (nblk > 0)
+        klaunch(Pl, kMfAdjNames[P], k_mf_adj<P>, dim3((unsigned)nblk), dim3(kMfThreads), 0, s, A, F, ncut, nbb, u, r,
+                du, dc, Ue);
+    if (wq && F.nband > 1)
         klaunch(Pl, kMfFixNames[P], k_mf_fix<P>, grid256((int64_t)(F.nband - 1) * P * Pl.n1), dim3(256), 0, s, A, F, du,
                 1);
 }
@@ -1085,22 +1206,18 @@ static void launch_wq_adjoint(Plan& Pl, const MfArgs& A, const double* u, const 
 // The forward product with its two intermediate arrays given: the bands'
 // head and tail rows [2][nband][p][n1] and Ue [n_band + n_cut][(p+1)^2].
 // Every entry of them is written before it is read, so they need no clearing.
-// All on the caller's stream: the element part (element vectors, then the
-// rows formed element-wise) and the weighted-quadrature part write disjoint
-// rows of y, but a second stream measured no overlap here (the other queue
-// started its kernels some 16 us after the fork's kernels had ended).
+// Two launches on the caller's stream: the element vectors beside the
+// weighted-quadrature grid part (workgroups of one launch, so they overlap;
+// a second stream measured no overlap here, its queue starting some 16 us
+// after the fork's kernels had ended), then the rows' fix-ups.
 static void mf_apply_into(Plan& P, const double* c, const double* u, double* y, double* part, double* Ue,
                           hipStream_t s) {
     MfArgs A = mf_args(P, c);
-    launch_elem(P, A, u, nullptr, Ue, nullptr, s);
-    launch_gather_rows(P, A, Ue, y, s);
-    if (P.method != IGA_GAUSS_REF) {
-        switch (P.p) {
+    switch (P.p) {
 #define CASE(PP) \
-    case PP: launch_wq_forward<PP>(P, A, u, y, part, s); break;
-            CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
+    case PP: launch_forward<PP>(P, A, u, y, part, Ue, s); break;
+        CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
 #undef CASE
-        }
     }
 }
 
@@ -1164,21 +1281,19 @@ static void mf_apply_noalloc(Plan& P, const double* c, const double* u, double* 
 }
 
 // The adjoint: the element vectors (and dc at band Gauss points and cut
-// nodes), the grid part of du and dc in one pass (every active row of du
-// written), then the element vectors added to the rows they touch.
+// nodes) beside the grid part of du and dc (every active row of du written),
+// in one launch, then the element vectors added to the rows they touch.
 void mf_adjoint(Plan& P, const double* c, const double* u, const double* r, double* du, double* dc, hipStream_t s) {
     mf_buffers(P);
     mf_adj_rows(P, s);
     MfArgs A = mf_args(P, c);
-    launch_elem(P, A, u, r, P.sw.Ue, dc, s);
-    if (P.method != IGA_GAUSS_REF) {
-        switch (P.p) {
+    switch (P.p) {
 #define CASE(PP) \
-    case PP: launch_wq_adjoint<PP>(P, A, u, r, du, dc, P.sw.mfpart, s); break;
-            CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
+    case PP: launch_adjoint<PP>(P, A, u, r, du, dc, P.sw.mfpart, P.sw.Ue, s); break;
+        CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
 #undef CASE
-        }
-    } else {
+    }
+    if (P.method == IGA_GAUSS_REF) {
         HIPX(hipMemsetAsync(dc, 0, sizeof(double) * (size_t)A.nq, s));
         HIPX(hipMemsetAsync(du, 0, sizeof(double) * (size_t)P.n_act, s));
     }
