@@ -41,9 +41,11 @@ def _close(dev, ref, scale, tol, label):
 
 
 # one band of elements (N = 16), several bands (72, 40: rows whose support spans two
-# bands are summed from both), several strips of test columns (140), degrees 2, 4, 6
+# bands are summed from both), several strips of test columns (140), degrees 1, 2, 4, 6
+# and 8 (32 band elements to a workgroup at degree 1; at degree 8 one, and more reciprocals
+# per span than a wavefront has lanes)
 @pytest.mark.parametrize("N,p,inject", [(16, 4, True), (72, 4, True), (72, 4, False), (140, 4, True),
-                                        (40, 2, True), (40, 6, True)])
+                                        (40, 2, True), (40, 6, True), (24, 1, True), (24, 8, True)])
 def test_apply_and_adjoint_match_oracle(N, p, inject):
     torch, igatrim, cfg, plan, c, o = _setup(N, p=p, inject=inject)
     tol = 1e-12 if inject else 1e-9
