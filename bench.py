@@ -89,7 +89,8 @@ def _source_digest(sections):
     return h.hexdigest()[:16]
 
 
-TRAFFIC_FILE = "formation_p4_N256_hbm_traffic.md"
+# committed counter summaries per (p, N) workload
+TRAFFIC_FILES = {(4, 256): "formation_p4_N256_hbm_traffic.md", (4, 1024): "matfree_p4_N1024_hbm_traffic.md"}
 # the source sections each counted kernel is built from (counter values are used while they hash the same)
 KERNEL_SOURCES = {
     "k_interior": [("paper_2101_08053_amd/csrc/form_body.hpp", "interior rows"),
@@ -102,15 +103,23 @@ KERNEL_SOURCES = {
                   ("paper_2101_08053_amd/csrc/trim.hip", "evaluation"),
                   ("paper_2101_08053_amd/csrc/plan.hpp", None),
                   ("paper_2101_08053_amd/csrc/common.hpp", None)],
+    "k_mf_fwd": [("paper_2101_08053_amd/csrc/matfree.hip", None),
+                 ("paper_2101_08053_amd/csrc/plan.hpp", None),
+                 ("paper_2101_08053_amd/csrc/common.hpp", None)],
+    "k_mf_adj": [("paper_2101_08053_amd/csrc/matfree.hip", None),
+                 ("paper_2101_08053_amd/csrc/plan.hpp", None),
+                 ("paper_2101_08053_amd/csrc/common.hpp", None)],
 }
 
 
 def _traffic(kernel, p=4, N=256):
-    """HBM bytes per launch of `kernel` from the committed counter summary of the headline workload,
-    or None if it holds none for this kernel or the kernel's sources changed since."""
+    """HBM bytes per launch of `kernel` from the committed counter summary of its workload (p, N x N),
+    or None if there is none for this kernel or the kernel's sources changed since."""
     base = kernel.split("<")[0]
-    path = os.path.join(ROOT, "profiles", TRAFFIC_FILE)
-    if (p, N) != (4, 256) or base not in KERNEL_SOURCES or not os.path.exists(path):
+    if (p, N) not in TRAFFIC_FILES or base not in KERNEL_SOURCES:
+        return None
+    path = os.path.join(ROOT, "profiles", TRAFFIC_FILES[(p, N)])
+    if not os.path.exists(path):
         return None
     vals = {}
     for line in open(path):
@@ -661,7 +670,8 @@ def bench_adjoint(igatrim, wl, cfg_unused, args, sync, stream, peaks):
                                "8 B per rule-point c, dc, per u, r, du value and per element-vector entry written")):
         if name in kernels:
             grid_roofs[name] = _roof(name, "hbm", nbytes, kernels[name]["avg_launch_ms"], peaks, per,
-                                     "HIP events at the dispatch's start and end")
+                                     "HIP events at the dispatch's start and end",
+                                     traffic=_traffic(name, p, args.mf_N))
     return {"forward_ms": ms_fwd, "backward_ms": ms_bwd, "forward_noalloc_ms": ms_fwd_na,
             "plain_formation_ms": ms_form,
             "forward_value": nnz / (ms_fwd * 1e-3), "backward_value": nnz / (ms_bwd * 1e-3),
