@@ -275,8 +275,13 @@ static void form(Plan& P, const iga_coeff& c, double* vals, int flags, hipStream
     // A full DWQ formation runs the side rules (which read the knots only) on
     // the caller's stream after the cut element matrices, where that stream
     // waits for the second one anyway.
-    if (full) setup_tables(P, a, false);
-    {
+    if (full && c.kind == IGA_COEF_GEOM_DETJ) {
+        // the weights and c on the WQ grid in one launch (the COEF phase times both)
+        launch_dir_tables(P, a);
+        PhaseTimer t(P, a, IGA_PHASE_COEF);
+        launch_weights_coef(P, c, a, pts_by_coef);
+    } else {
+        if (full) setup_tables(P, a, false);
         PhaseTimer t(P, a, IGA_PHASE_COEF);
         launch_coef(P, c, a, 1, pts_by_coef);
     }

@@ -338,6 +338,8 @@ __device__ __forceinline__ double detj_local(const double* __restrict__ cp, int 
 void launch_gauss_table(Plan& P, hipStream_t s);
 void launch_dir_tables(Plan& P, hipStream_t s);
 void launch_wq_weights(Plan& P, hipStream_t s);
+// the weights and c = |det J| on the WQ grid (with_points: the grid points' coordinates too) in one launch
+void launch_weights_coef(Plan& P, const iga_coeff& c, hipStream_t s, bool with_points);
 void launch_wb_table(Plan& P, int d, hipStream_t s);
 // scan.hip
 void exclusive_scan(const int* in, int* out, int n, int* tmp, hipStream_t s);

@@ -1,7 +1,7 @@
 // Univariate tables (Sect. 2.1): Gauss-Legendre rules, the weighted-quadrature
 // point layout, basis values at every rule point, the univariate mass matrix
 // and the weighted-quadrature weights of Eq. (5), one system per test function.
-#include "plan.hpp"
+#include "form_body.hpp"
 
 namespace iga {
 
@@ -128,10 +128,10 @@ void launch_dir_tables(Plan& P, hipStream_t s) {
 // by its residual, then written with the row's test-side factors
 // WB[i][q][b] = w_q B_{i+b-p}(x_q).
 template <int P>
-__global__ void __launch_bounds__(64) k_wq_weights(DirDev D1, DirDev D2, const double* __restrict__ gx,
-                                                   const double* __restrict__ gw, int* __restrict__ status) {
+__device__ __forceinline__ void wq_weights_body(const DirDev& D1, const DirDev& D2, const double* __restrict__ gx,
+                                                const double* __restrict__ gw, int* __restrict__ status, int blk) {
     constexpr int M = 2 * P + 1;
-    int i = blockIdx.x;
+    int i = blk;
     const bool second = i >= D1.n;
     const DirDev& D = second ? D2 : D1;
     if (second) i -= D1.n;
@@ -229,6 +229,29 @@ __global__ void __launch_bounds__(64) k_wq_weights(DirDev D1, DirDev D2, const d
     if (lane == 0 && (singular || !(rmax <= 1e-12 * bmax))) atomicExch(status, IGA_E_SINGULAR_WEIGHTS);
 }
 
+template <int P>
+__global__ void __launch_bounds__(64) k_wq_weights(DirDev D1, DirDev D2, const double* __restrict__ gx,
+                                                   const double* __restrict__ gw, int* __restrict__ status) {
+    wq_weights_body<P>(D1, D2, gx, gw, status, blockIdx.x);
+}
+
+// The weights of both directions and c = |det J| on the WQ grid in one launch:
+// workgroups below nw solve one weight system each, the others take 64 grid
+// points each. Both read only the univariate tables, and the weight systems
+// (one wavefront each, two per CU) leave the GPU mostly idle, so the grid's
+// coefficient runs in their shadow instead of after them.
+template <int P>
+__global__ void __launch_bounds__(64) k_weights_coef(DirDev D1, DirDev D2, const double* __restrict__ gx,
+                                                     const double* __restrict__ gw, int* __restrict__ status, int nw,
+                                                     CoefArgs C, int64_t t1) {
+    if ((int)blockIdx.x < nw) {
+        wq_weights_body<P>(D1, D2, gx, gw, status, blockIdx.x);
+        return;
+    }
+    const int64_t t = (int64_t)(blockIdx.x - nw) * 64 + threadIdx.x;
+    if (t < t1) coef_point<P>(C, t);
+}
+
 // Test-side factors of the weighted-quadrature rows, WB[i][q][b] =
 // w_{k0(i)+q, i} B_{i+b-p}(x_{k0(i)+q}), zero where B_{i+b-p} vanishes.
 __global__ void k_wb_table(DirDev D, int p) {
@@ -252,6 +275,24 @@ void launch_wb_table(Plan& P, int d, hipStream_t s) {
     DirDev& D = P.dir[d];
     int n = D.n * D.qmax * (2 * P.p + 1);
     klaunch(P, "k_wb_table", k_wb_table, dim3((n + 255) / 256), dim3(256), 0, s, D, P.p);
+}
+
+void launch_weights_coef(Plan& P, const iga_coeff& c, hipStream_t s, bool with_points) {
+    CoefArgs C = coef_args(P, c);
+    if (with_points) C.xy = P.pts_xy;
+    const int nw = P.dir[0].n + P.dir[1].n;
+    const int64_t t1 = C.nq;
+    dim3 g((unsigned)(nw + (t1 + 63) / 64)), b(64);
+    switch (P.p) {
+#define CASE(PP)                                                                                                 \
+    case PP:                                                                                                     \
+        klaunch(P, "k_weights_coef<" #PP ">", k_weights_coef<PP>, g, b, 0, s, P.dir[0], P.dir[1], P.gauss_x,      \
+                P.gauss_w, P.status, nw, C, t1);                                                                  \
+        break;
+        CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
+#undef CASE
+        default: throw Error{IGA_E_UNSUPPORTED, "degree outside 1..8"};
+    }
 }
 
 void launch_wq_weights(Plan& P, hipStream_t s) {
