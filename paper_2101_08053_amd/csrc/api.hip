@@ -157,6 +157,7 @@ static void setup_trim(Plan& P, hipStream_t s, bool discover, bool points, int p
         P.node_el = P.alloc<int>(nn);
         size_t L = (size_t)(P.p + 1) * (P.p + 1);
         P.cutE = P.alloc<double>(std::max<int64_t>(P.n_cut_el, 1) * L * L);
+        P.cut_part = P.alloc<double>((size_t)std::max<int64_t>(P.n_form_rows, 1) * (2 * P.p + 1) * (2 * P.p + 1));
         size_t nq = (size_t)P.dir[0].Q * P.dir[1].Q;
         size_t nb = (size_t)P.n_band * L;
         P.n_points = (int64_t)(nq + nb + P.n_nodes);

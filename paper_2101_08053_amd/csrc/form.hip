@@ -161,7 +161,7 @@ CutEArgs cute_args(Plan& P, const iga_coeff& c) {
 CutRowArgs cutr_args(Plan& P, const iga_coeff& c, double* vals) {
     return CutRowArgs{P.dir[0], P.dir[1], coef_view(P, c), P.form_rows, (int)P.n_form_rows, P.fn_of, P.act_of,
                       P.ecls, P.cut_id, P.band_id, P.cutE, P.method == IGA_DWQ ? P.dwq_region : nullptr, vals,
-                      P.n_act};
+                      P.n_act, P.cut_part};
 }
 
 void launch_interior_rows(Plan& P, const iga_coeff& c, double* vals, hipStream_t s, hipEvent_t t0, hipEvent_t t1) {
@@ -206,8 +206,9 @@ void launch_cut_elems(Plan& P, const iga_coeff& c, hipStream_t s) {
     }
 }
 
-// mode: ROW_FUSED (after the cut element matrices), ROW_INSIDE (the inside sums, written; needs no cut
-// element matrix), ROW_CUT (adds the cut element matrices' entries to the inside sums)
+// mode: ROW_FUSED (after the cut element matrices), ROW_INSIDE (the inside sums, to the plan's
+// scratch array; needs no cut element matrix), ROW_CUT (adds the cut element matrices' entries to the
+// inside sums and writes the rows)
 void launch_cut_rows_mode(Plan& P, const iga_coeff& c, double* vals, hipStream_t s, int mode) {
     if (P.method == IGA_NAIVE_WQ || P.n_form_rows == 0) return;
     CutRowArgs A = cutr_args(P, c, vals);

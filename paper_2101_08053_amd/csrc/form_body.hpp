@@ -738,6 +738,7 @@ struct CutRowArgs {
     const int* region;      // DWQ: box of inside elements left to k_dwq_rows (nullptr: none)
     double* vals;
     int64_t n_act;
+    double* part;           // two-launch form: [n_rows][(2p+1)^2] inside sums, row r's slots contiguous
 };
 
 // One workgroup per row; the row's per-direction Gauss factors
@@ -748,7 +749,10 @@ struct CutRowArgs {
 // U[m2][g2][a] (direction 1, summed over the element columns m1), then thread
 // (a, b) contracts U with F2 and adds its column's entries of the cut element
 // matrices. The row can also be formed in two launches with the same
-// arithmetic: the inside sum (written), then the cut entries (added).
+// arithmetic: the inside sum (to a scratch array, the row's slots side by
+// side), then the cut entries (added, and the row written to the band
+// layout). A row's slots lie n_act apart in the band layout, so the scratch
+// array spares the second launch a read of one cache line per slot.
 enum : int { ROW_FUSED = 0, ROW_INSIDE = 1, ROW_CUT = 2 };
 
 template <int P>
@@ -858,7 +862,7 @@ __device__ __forceinline__ void cut_row_body_m(const CutRowArgs& A, int r, CutRS
 #pragma unroll
                 for (int g2 = 0; g2 < NP; ++g2) val += sF2[m2][g2][b] * S.sU[m2][g2][a];
         } else {
-            val = *out;   // the inside sum, written by the first launch
+            val = A.part[(size_t)r * (W * W) + s];   // the inside sum, written by the first launch
         }
         if (CUT) {
             // cut elements: the column's entry of the staged line, zero where the element is not cut
@@ -876,7 +880,10 @@ __device__ __forceinline__ void cut_row_body_m(const CutRowArgs& A, int r, CutRS
             }
         }
     }
-    *out = val;
+    if (MODE == ROW_INSIDE)
+        A.part[(size_t)r * (W * W) + s] = val;
+    else
+        *out = val;
 }
 
 template <int P>

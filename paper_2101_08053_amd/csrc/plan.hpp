@@ -206,6 +206,7 @@ struct Plan {
     double* node_w = nullptr;
     int* node_el = nullptr;        // cut element id of each node
     double* cutE = nullptr;        // n_cut_el * (p+1)^4 local matrices
+    double* cut_part = nullptr;    // n_form_rows * (2p+1)^2 inside sums of the two-launch row formation
 
     // scratch for scans and counts
     int* flags = nullptr;          // max(n1*n2, N1*N2) + 1
