@@ -314,13 +314,17 @@ static void form(Plan& P, const iga_coeff& c, double* vals, int flags, hipStream
         P.ev_records.push_back({IGA_PHASE_INTERIOR, {t0, t1}});
         HIPX(hipEventRecord(P.ev_interior, a));
         HIPX(hipStreamWaitEvent(s, P.ev_interior, 0));
+    } else if (c.kind == IGA_COEF_GEOM_DETJ && P.method != IGA_GAUSS_REF && P.n_band > 0) {
+        // the interior rows and c at the band Gauss points in one launch
+        launch_interior_coef(P, c, vals, a, pts_by_coef);
     } else {
         launch_interior_rows(P, c, vals, a);
     }
+    const bool band_coef_done = !P.timing && c.kind == IGA_COEF_GEOM_DETJ && P.method != IGA_GAUSS_REF && P.n_band > 0;
     if (full && !pts_by_coef) launch_points(P, a);
     {
         PhaseTimer t(P, a, IGA_PHASE_CUT);
-        launch_coef(P, c, a, 3, pts_by_coef);
+        if (!band_coef_done) launch_coef(P, c, a, 3, pts_by_coef);
         launch_cut_rows_mode(P, c, vals, a, 1);  // rows formed element-wise: their inside sums
     }
     HIPX(hipEventRecord(P.ev_band, a));  // everything on the auxiliary stream is done

@@ -124,6 +124,25 @@ __global__ void __launch_bounds__(Int2Cfg<P>::NT) k_interior(IntArgs A) {
     interior_rows_block<P>(A, blk - i2 * A.ntx, i2, S);
 }
 
+// The interior rows and c = |det J| at the band Gauss points in one launch
+// (the inside sums of the rows formed element-wise read those next): the
+// first ncb workgroups take NT points each, the others the interior tiles.
+// ncb is a multiple of 8, so the tiles' XCD renumbering sees the same
+// round-robin as in the launch of their own.
+template <int P>
+__global__ void __launch_bounds__(Int2Cfg<P>::NT) k_interior_coef(IntArgs A, CoefArgs C, int ncb, int64_t t0,
+                                                                  int64_t t1) {
+    __shared__ __align__(16) Int2Smem<P> S;
+    if ((int)blockIdx.x < ncb) {
+        const int64_t t = t0 + (int64_t)blockIdx.x * Int2Cfg<P>::NT + threadIdx.x;
+        if (t < t1) coef_point<P>(C, t);
+        return;
+    }
+    const int blk = xcd_block((int)blockIdx.x - ncb, (int)gridDim.x - ncb);
+    const int i2 = blk / A.ntx;
+    interior_rows_block<P>(A, blk - i2 * A.ntx, i2, S);
+}
+
 static const char* const kInteriorNames[IGA_MAXP + 1] = {"", "k_interior<1>", "k_interior<2>", "k_interior<3>",
                                                           "k_interior<4>", "k_interior<5>", "k_interior<6>",
                                                           "k_interior<7>", "k_interior<8>"};
@@ -135,6 +154,15 @@ static void launch_interior_p(Plan& Pl, IntArgs A, hipStream_t s, hipEvent_t t0,
     const dim3 blk(Int2Cfg<P>::NT);
     if (t0) hipExtLaunchKernelGGL(k_interior<P>, dim3(nb), blk, 0, s, t0, t1, 0, A);  // events bracket the dispatch
     else klaunch(Pl, kInteriorNames[P], k_interior<P>, dim3(nb), blk, 0, s, A);
+}
+
+template <int P>
+static void launch_interior_coef_p(Plan& Pl, IntArgs A, CoefArgs C, hipStream_t s) {
+    A.ntx = interior2_ntx(Pl.N1, P);
+    const int nb = A.ntx * Pl.n2;
+    const int64_t t0 = C.nq, t1 = C.nq + C.nb;
+    const int ncb = (int)(((t1 - t0 + Int2Cfg<P>::NT - 1) / Int2Cfg<P>::NT + 7) / 8 * 8);
+    klaunch(Pl, kInteriorNames[P], k_interior_coef<P>, dim3(nb + ncb), dim3(Int2Cfg<P>::NT), 0, s, A, C, ncb, t0, t1);
 }
 
 IntArgs int_args(Plan& P, const iga_coeff& c, double* vals) {
@@ -162,6 +190,21 @@ CutRowArgs cutr_args(Plan& P, const iga_coeff& c, double* vals) {
     return CutRowArgs{P.dir[0], P.dir[1], coef_view(P, c), P.form_rows, (int)P.n_form_rows, P.fn_of, P.act_of,
                       P.ecls, P.cut_id, P.band_id, P.cutE, P.method == IGA_DWQ ? P.dwq_region : nullptr, vals,
                       P.n_act, P.cut_part};
+}
+
+void launch_interior_coef(Plan& P, const iga_coeff& c, double* vals, hipStream_t s, bool with_points) {
+    IGA_REQUIRE(P.method != IGA_GAUSS_REF && c.kind == IGA_COEF_GEOM_DETJ, IGA_E_INVALID,
+                "interior rows with the band coefficient: |det J| and a method with interior rows");
+    IntArgs A = int_args(P, c, vals);
+    CoefArgs C = coef_args(P, c);
+    if (with_points) C.xy = P.pts_xy;
+    switch (P.p) {
+#define CASE(PP) \
+    case PP: launch_interior_coef_p<PP>(P, A, C, s); break;
+        CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
+#undef CASE
+        default: throw Error{IGA_E_UNSUPPORTED, "degree outside 1..8"};
+    }
 }
 
 void launch_interior_rows(Plan& P, const iga_coeff& c, double* vals, hipStream_t s, hipEvent_t t0, hipEvent_t t1) {

@@ -366,6 +366,8 @@ void launch_coef(Plan& P, const iga_coeff& c, hipStream_t s, int part = 0, bool 
 // t0 / t1 (optional): events recorded at the start and end of the kernel's execution
 void launch_interior_rows(Plan& P, const iga_coeff& c, double* vals, hipStream_t s, hipEvent_t t0 = nullptr,
                           hipEvent_t t1 = nullptr);
+// the interior rows and c = |det J| at the band Gauss points (with_points: their coordinates too) in one launch
+void launch_interior_coef(Plan& P, const iga_coeff& c, double* vals, hipStream_t s, bool with_points);
 void launch_cut_rows(Plan& P, const iga_coeff& c, double* vals, hipStream_t s);  // matrices, then rows
 void launch_cut_elems(Plan& P, const iga_coeff& c, hipStream_t s);
 // rows formed element-wise in one launch (mode 0), or their inside sums (1) and the cut entries (2)
