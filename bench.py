@@ -163,7 +163,7 @@ def kernel_work(name, sz, plan_info):
     c = |det J| at a point writes 8 B (and, in a full formation, the point's
     coordinates, 16 B) and reads the control points (counted once per launch:
     16 n1 n2 B; a full formation computes the WQ grid's values beside the weight
-    systems, k_weights_coef, and the band Gauss points' in k_coef); a weight
+    systems, k_weights_coef, and the band Gauss points' in the interior launch); a weight
     system of Eq. (5) (m = 2p+1 rows, q = 2p+2 points) is a Householder QR of
     q x m: 2 q m^2 - (2/3) m^3 flops; the cut-element preparation writes each
     node's (x, y, w) (24 B); the element-formed rows' cut entries read each cut
@@ -174,15 +174,19 @@ def kernel_work(name, sz, plan_info):
     W2 = (2 * p + 1) ** 2
     base = name.split("<")[0]
     if base == "k_interior":
-        return ("hbm", 8 * W2 * sz["n_interior"] + 8 * sz["q1"] * sz["q2"],
-                f"8 (2p+1)^2 = {8 * W2} B per interior row + 8 B per WQ point")
+        work = 8 * W2 * sz["n_interior"] + 8 * sz["q1"] * sz["q2"]
+        per = f"8 (2p+1)^2 = {8 * W2} B per interior row + 8 B per WQ point"
+        if "coef_points" in plan_info:  # c = |det J|: the band Gauss points' c rides in the same launch
+            work += 24 * (plan_info["coef_points"] - sz["q1"] * sz["q2"])
+            per += " + 24 B per band Gauss point (its c and coordinates)"
+        return ("hbm", work, per)
     if base == "k_cut_elem":
         return ("mfma", 2 * sz["n_cut_nodes"] * L * (L + 1) // 2,
                 f"n_nodes L(L+1)/2 FMA = 2 x {L * (L + 1) // 2} flops per node")
-    if base == "k_coef":  # a full formation's one launch: the band Gauss points
-        npts = plan_info.get("coef_points", sz["q1"] * sz["q2"]) - sz["q1"] * sz["q2"]
-        return ("hbm", 24 * npts + 16 * sz["n1"] * sz["n2"],
-                "24 B per band Gauss point (c and its coordinates) + control points once")
+    if base == "k_coef":  # a launch of its own (formations over resident tables): the WQ grid or the band points
+        npts = plan_info.get("coef_points", sz["q1"] * sz["q2"])
+        return ("hbm", (24 * npts + 16 * sz["n1"] * sz["n2"]) // 2,
+                "24 B per point (c and its coordinates) + control points once, over the two launches")
     if base == "k_weights_coef":  # the weights and c = |det J| on the WQ grid in one launch
         return ("hbm", 24 * sz["q1"] * sz["q2"] + 16 * sz["n1"] * sz["n2"],
                 "24 B per WQ-grid point (c and its coordinates) + control points once; the weight systems "
