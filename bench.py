@@ -95,6 +95,14 @@ TRAFFIC_FILES = {(4, 256): "formation_p4_N256_hbm_traffic.md", (4, 1024): "matfr
 KERNEL_SOURCES = {
     "k_interior": [("paper_2101_08053_amd/csrc/form_body.hpp", "interior rows"),
                    ("paper_2101_08053_amd/csrc/form.hip", "interior rows"),
+                   ("paper_2101_08053_amd/csrc/form_body.hpp", "coefficient"),
+                   ("paper_2101_08053_amd/csrc/common.hpp", None)],
+    "k_weights_coef": [("paper_2101_08053_amd/csrc/setup.hip", "WQ weights (5)"),
+                       ("paper_2101_08053_amd/csrc/form_body.hpp", "coefficient"),
+                       ("paper_2101_08053_amd/csrc/plan.hpp", None),
+                       ("paper_2101_08053_amd/csrc/common.hpp", None)],
+    "k_cut_rows": [("paper_2101_08053_amd/csrc/form_body.hpp", "cut rows"),
+                   ("paper_2101_08053_amd/csrc/form.hip", "cut element matrices / rows"),
                    ("paper_2101_08053_amd/csrc/common.hpp", None)],
     "k_cut_elem": [("paper_2101_08053_amd/csrc/form_body.hpp", "cut element matrices"),
                    ("paper_2101_08053_amd/csrc/form.hip", "cut element matrices / rows"),
