@@ -54,6 +54,8 @@ static T d2h1(const T* src, hipStream_t s) {
 
 // matfree.hip: device address of the allocation-free product's scratch array (once per device)
 void mf_scratch_init(int device);
+// dwq.hip: a DWQ plan's side rules as workgroups of the cut element matrices' launch
+void launch_cut_elems_sides(Plan& P, const iga_coeff& c, hipStream_t s);
 
 static void check_status(Plan& P, hipStream_t s) {
     int st = d2h1(P.status, s);
@@ -240,7 +242,7 @@ static void form_serial(Plan& P, const iga_coeff& c, double* vals, int flags, hi
 // rules, the band/cut coefficients and the cut rows; the plan's second
 // stream carries the univariate tables and weights, the WQ-grid coefficient
 // and the interior rows (after the compact maps exist); a DWQ plan's side
-// rules run on s after the cut element matrices.
+// rules run on s in the cut element matrices' launch.
 // Both start after the work already queued on s and are joined back into s.
 // Phase timers: SETUP and CUT on s, COEF (WQ grid) and INTERIOR on the second
 // stream (they overlap).
@@ -274,8 +276,7 @@ static void form(Plan& P, const iga_coeff& c, double* vals, int flags, hipStream
     }
     HIPX(hipStreamWaitEvent(a, P.ev_fork, 0));
     // A full DWQ formation runs the side rules (which read the knots only) on
-    // the caller's stream after the cut element matrices, where that stream
-    // waits for the second one anyway.
+    // the caller's stream, as workgroups of the cut element matrices' launch.
     if (full && c.kind == IGA_COEF_GEOM_DETJ) {
         // the weights and c on the WQ grid in one launch (the COEF phase times both)
         launch_dir_tables(P, a);
@@ -330,8 +331,10 @@ static void form(Plan& P, const iga_coeff& c, double* vals, int flags, hipStream
     HIPX(hipEventRecord(P.ev_band, a));  // everything on the auxiliary stream is done
     {
         PhaseTimer t(P, s, IGA_PHASE_CUT);
-        launch_cut_elems(P, c, s);  // with c at the cut nodes
-        if (full) launch_dwq_sides(P, s);  // DWQ plans: from the knots alone
+        if (full && P.method == IGA_DWQ)
+            launch_cut_elems_sides(P, c, s);  // the side rules (from the knots alone) beside them
+        else
+            launch_cut_elems(P, c, s);  // with c at the cut nodes
         HIPX(hipStreamWaitEvent(s, P.ev_band, 0));
         launch_cut_rows_mode(P, c, vals, s, 2);  // plus the cut element matrices' entries
         launch_dwq_rows(P, c, vals, s);

@@ -17,6 +17,7 @@
 //  * k_dwq_rows: adds the box's contribution to a row that k_cut_rows formed
 //    element-wise over the rest of the support.
 #include "dwq_body.hpp"
+#include "form_body.hpp"
 
 namespace iga {
 
@@ -25,6 +26,23 @@ __global__ void __launch_bounds__(kDwqSideThreads) k_dwq_sides(DirDev D1, DirDev
                                                                const double* __restrict__ gw,
                                                                int* __restrict__ status) {
     dwq_sides_body<P>(D1, D2, gx, gw, status, blockIdx.x);
+}
+
+// A full formation of a DWQ plan: the side rules (they read the knots only)
+// and the cut element matrices in one launch, the side rules' workgroups
+// first (they take the longest), instead of the side rules after the cut
+// element matrices on the caller's stream.
+template <int P>
+__global__ void __launch_bounds__(kDwqSideThreads) k_cut_elem_sides(CutEArgs A, DirDev D1, DirDev D2,
+                                                                    const double* __restrict__ gx,
+                                                                    const double* __restrict__ gw,
+                                                                    int* __restrict__ status, int nside) {
+    __shared__ CutESmem<P> S;
+    if ((int)blockIdx.x < nside) {
+        dwq_sides_body<P>(D1, D2, gx, gw, status, blockIdx.x);
+        return;
+    }
+    cut_elem_body<P>(A, (int)blockIdx.x - nside, S);
 }
 
 // ------------------------------------------------------------ box choice
@@ -127,6 +145,28 @@ void launch_dwq_sides(Plan& P, hipStream_t s) {
     switch (P.p) {
 #define CASE(PP) \
     case PP: klaunch(P, "k_dwq_sides<" #PP ">", k_dwq_sides<PP>, g, b, 0, s, P.dir[0], P.dir[1], P.gauss_x, P.gauss_w, P.status); break;
+        CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
+#undef CASE
+        default: throw Error{IGA_E_UNSUPPORTED, "degree outside 1..8"};
+    }
+}
+
+void launch_cut_elems_sides(Plan& P, const iga_coeff& c, hipStream_t s) {
+    IGA_REQUIRE(P.method == IGA_DWQ, IGA_E_INVALID, "side rules belong to DWQ plans");
+    const int nslot = 2 * (P.dir[0].N - 1) + 2 * (P.dir[1].N - 1);
+    const int spw = dwq_side_spw(P.p);
+    const int nside = nslot > 0 ? (nslot + spw - 1) / spw : 0;
+    const int ncut = (int)P.n_cut_el;
+    if (nside + ncut == 0) return;
+    const CutEArgs A = cute_args(P, c);
+    dim3 g((unsigned)(nside + ncut)), b(kDwqSideThreads);
+    static_assert(kDwqSideThreads == 256, "the cut element matrices' workgroups have 256 threads");
+    switch (P.p) {
+#define CASE(PP)                                                                                                   \
+    case PP:                                                                                                       \
+        klaunch(P, "k_cut_elem_sides<" #PP ">", k_cut_elem_sides<PP>, g, b, 0, s, A, P.dir[0], P.dir[1], P.gauss_x, \
+                P.gauss_w, P.status, nside);                                                                        \
+        break;
         CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
 #undef CASE
         default: throw Error{IGA_E_UNSUPPORTED, "degree outside 1..8"};

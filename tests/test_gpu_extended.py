@@ -9,6 +9,7 @@
   ||E b - E A E^T x|| / ||E b|| with the oracle's E, A and b, stays within
   1e-10 (PCG stops at 1e-12 on the device's), the outer coefficients are E^T
   of the inner ones, and the device u is within 1e-9 of the oracle's solve;
+* on a mapped patch (c = |det J|) the same residual bar;
 * Q_p is reproduced (c = 1, g in Q_p), with hybrid Gauss and DWQ plans;
 * on a sliver cut the extended solve converges in no more iterations than
   the plain one and its error stays that of the plain projection;
@@ -113,6 +114,25 @@ def test_extended_projection_against_oracle(N):
     e_plain = project.l2_error(o, u0, wl.config1_target)
     say(f"   L2 error extended {e_ext:.3e} plain {e_plain:.3e}")
     assert e_ext <= 2.0 * e_plain
+
+
+def test_extended_projection_mapped_patch():
+    """Perturbed geometry, c = |det J|, g at physical points (a non-constant, non-symmetric mass
+    matrix), oracle rules injected: the oracle's extended residual of the device's unknowns."""
+    require_gpu()
+    cfg = wl.config2(N=40, p=3)
+    o, u, info, u0, info0 = _project_both(cfg)
+    say(f"[l2 ext detJ] {info} (plain {info0})")
+    assert info["converged"]
+    inner_flat, E, _ = _oracle_columns(o)
+    x = u[o.ts.act_of[inner_flat]]
+    assert np.abs(E.T @ x - u).max() <= 1e-13 * np.abs(u).max()
+    M = o.hybrid()
+    A = 0.5 * (M + M.T)
+    be = E @ project.rhs(o, wl.config1_target)
+    res = np.linalg.norm(be - E @ (A @ (E.T @ x))) / np.linalg.norm(be)
+    say(f"   oracle residual of device x: {res:.2e}")
+    assert res <= 1e-9
 
 
 @pytest.mark.parametrize("method", ["hybrid", "dwq"])
