@@ -21,7 +21,7 @@ Plan::~Plan() {
     if (fgraph) hipGraphDestroy(fgraph);
     if (cap_stream) hipStreamDestroy(cap_stream);
     if (sw.h_scal) hipHostFree(sw.h_scal);
-    for (hipEvent_t e : {ev_fork, ev_iso, ev_lists, ev_interior, ev_band, ev_classes})
+    for (hipEvent_t e : {ev_fork, ev_iso, ev_lists, ev_interior, ev_band, ev_classes, ev_aux_lists})
         if (e) hipEventDestroy(e);
     if (aux) hipStreamDestroy(aux);
     for (auto& e : ev_pool) hipEventDestroy(e);
@@ -56,6 +56,8 @@ static T d2h1(const T* src, hipStream_t s) {
 void mf_scratch_init(int device);
 // dwq.hip: a DWQ plan's side rules as workgroups of the cut element matrices' launch
 void launch_cut_elems_sides(Plan& P, const iga_coeff& c, hipStream_t s);
+// dwq.hip: a DWQ plan's box parts into the plan's second row scratch array (added by the cut-entry launch)
+void launch_dwq_box_parts(Plan& P, const iga_coeff& c, hipStream_t s);
 
 static void check_status(Plan& P, hipStream_t s) {
     int st = d2h1(P.status, s);
@@ -159,7 +161,9 @@ static void setup_trim(Plan& P, hipStream_t s, bool discover, bool points, int p
         P.node_el = P.alloc<int>(nn);
         size_t L = (size_t)(P.p + 1) * (P.p + 1);
         P.cutE = P.alloc<double>(std::max<int64_t>(P.n_cut_el, 1) * L * L);
-        P.cut_part = P.alloc<double>((size_t)std::max<int64_t>(P.n_form_rows, 1) * (2 * P.p + 1) * (2 * P.p + 1));
+        // inside sums of the rows formed in two launches (and, for DWQ, their box parts after them)
+        P.cut_part = P.alloc<double>((P.method == IGA_DWQ ? 2 : 1) * (size_t)std::max<int64_t>(P.n_form_rows, 1) *
+                                     (2 * P.p + 1) * (2 * P.p + 1));
         size_t nq = (size_t)P.dir[0].Q * P.dir[1].Q;
         size_t nb = (size_t)P.n_band * L;
         P.n_points = (int64_t)(nq + nb + P.n_nodes);
@@ -297,6 +301,8 @@ static void form(Plan& P, const iga_coeff& c, double* vals, int flags, hipStream
     } else {
         HIPX(hipStreamWaitEvent(a, P.ev_lists, 0));
     }
+    const bool box_early = P.method == IGA_DWQ && P.n_form_rows > 0;
+    if (box_early) HIPX(hipEventRecord(P.ev_aux_lists, a));  // the box parts read c on the WQ grid and the boxes
     // The interior rows first (beside the cut rules, which leave most of the
     // GPU idle), then the inside sums of the element-formed rows (beside the
     // cut element matrices); the caller's stream joins once, before the cut
@@ -335,9 +341,12 @@ static void form(Plan& P, const iga_coeff& c, double* vals, int flags, hipStream
             launch_cut_elems_sides(P, c, s);  // the side rules (from the knots alone) beside them
         else
             launch_cut_elems(P, c, s);  // with c at the cut nodes
+        if (box_early) {  // DWQ: the rows' box parts, while the second stream finishes
+            HIPX(hipStreamWaitEvent(s, P.ev_aux_lists, 0));
+            launch_dwq_box_parts(P, c, s);
+        }
         HIPX(hipStreamWaitEvent(s, P.ev_band, 0));
-        launch_cut_rows_mode(P, c, vals, s, 2);  // plus the cut element matrices' entries
-        launch_dwq_rows(P, c, vals, s);
+        launch_cut_rows_mode(P, c, vals, s, 2);  // plus the cut element matrices' entries (and box parts)
     }
 }
 
@@ -444,7 +453,8 @@ int iga_trim_plan_create(const iga_patch_desc* desc, const iga_opts* opts, iga_p
     HIPX(hipGetDevice(&P->device));
     mf_scratch_init(P->device);  // the allocation-free product's scratch address on this device
     HIPX(hipStreamCreateWithFlags(&P->aux, hipStreamNonBlocking));
-    for (hipEvent_t* e : {&P->ev_fork, &P->ev_iso, &P->ev_lists, &P->ev_interior, &P->ev_band, &P->ev_classes})
+    for (hipEvent_t* e :
+         {&P->ev_fork, &P->ev_iso, &P->ev_lists, &P->ev_interior, &P->ev_band, &P->ev_classes, &P->ev_aux_lists})
         HIPX(hipEventCreateWithFlags(e, hipEventDisableTiming));
     P->p = p;
     P->method = desc->method;

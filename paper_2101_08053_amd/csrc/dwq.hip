@@ -188,6 +188,24 @@ void launch_dwq_choose(Plan& P, hipStream_t s) {
     }
 }
 
+// The box parts of a DWQ plan's rows into the plan's second row scratch
+// array (the cut-entry launch adds them), so they can be formed before the
+// rows themselves.
+void launch_dwq_box_parts(Plan& P, const iga_coeff& c, hipStream_t s) {
+    if (P.method != IGA_DWQ || P.n_form_rows == 0) return;
+    const int W = 2 * P.p + 1;
+    DwqRowArgs A{P.dir[0], P.dir[1], coef_view(P, c), c.geom_cp, P.form_rows, (int)P.n_form_rows, P.fn_of,
+                 P.act_of, P.dwq_region, nullptr, P.n_act, P.cut_part + (size_t)P.n_form_rows * W * W};
+    dim3 g((unsigned)P.n_form_rows), b(256);
+    switch (P.p) {
+#define CASE(PP) \
+    case PP: klaunch(P, "k_dwq_rows<" #PP ">", k_dwq_rows<PP>, g, b, 0, s, A); break;
+        CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
+#undef CASE
+        default: throw Error{IGA_E_UNSUPPORTED, "degree outside 1..8"};
+    }
+}
+
 void launch_dwq_rows(Plan& P, const iga_coeff& c, double* vals, hipStream_t s) {
     if (P.method != IGA_DWQ || P.n_form_rows == 0) return;
     DwqRowArgs A{P.dir[0], P.dir[1], coef_view(P, c), c.geom_cp, P.form_rows, (int)P.n_form_rows, P.fn_of,

@@ -290,6 +290,7 @@ struct DwqRowArgs {
     const int* region;
     double* vals;
     int64_t n_act;
+    double* boxp = nullptr;  // if set: box parts to boxp[r][(2p+1)^2] (a later launch adds them) instead of vals
 };
 
 // One workgroup per formed row with a box: the two 1-D rules restricted to
@@ -403,7 +404,10 @@ __device__ __forceinline__ void dwq_rows_body(const DwqRowArgs& A, int r) {
         if (j1 >= 0 && j1 < A.d1.n && j2 >= 0 && j2 < A.d2.n && A.act_of[j2 * A.d1.n + j1] >= 0) {
             double acc = 0.0;
             for (int q1 = 0; q1 < n1q; ++q1) acc += sWt[0][q1] * sB[0][q1][a] * sT[b][q1];
-            A.vals[(size_t)t * A.n_act + row] += acc;
+            if (A.boxp)
+                A.boxp[(size_t)r * (W * W) + t] = acc;
+            else
+                A.vals[(size_t)t * A.n_act + row] += acc;
         }
     }
 }

@@ -256,6 +256,7 @@ void launch_cut_rows_mode(Plan& P, const iga_coeff& c, double* vals, hipStream_t
     if (P.method == IGA_NAIVE_WQ || P.n_form_rows == 0) return;
     CutRowArgs A = cutr_args(P, c, vals);
     int W = 2 * P.p + 1;
+    if (mode == ROW_CUT && P.method == IGA_DWQ) A.boxp = P.cut_part + (size_t)P.n_form_rows * W * W;
     dim3 g((unsigned)P.n_form_rows), b(((W * W + 63) / 64) * 64);
     switch (P.p * 4 + mode) {
 #define CASE(PP)                                                                            \

@@ -739,6 +739,7 @@ struct CutRowArgs {
     double* vals;
     int64_t n_act;
     double* part;           // two-launch form: [n_rows][(2p+1)^2] inside sums, row r's slots contiguous
+    const double* boxp = nullptr;  // cut-entry launch of a DWQ plan: [n_rows][(2p+1)^2] box parts, added last
 };
 
 // One workgroup per row; the row's per-direction Gauss factors
@@ -752,7 +753,9 @@ struct CutRowArgs {
 // arithmetic: the inside sum (to a scratch array, the row's slots side by
 // side), then the cut entries (added, and the row written to the band
 // layout). A row's slots lie n_act apart in the band layout, so the scratch
-// array spares the second launch a read of one cache line per slot.
+// array spares the second launch a read of one cache line per slot. A DWQ
+// row's box part, formed into a second scratch array beforehand, is added
+// last there, as the box launch would add it to the written row.
 enum : int { ROW_FUSED = 0, ROW_INSIDE = 1, ROW_CUT = 2 };
 
 template <int P>
@@ -879,6 +882,7 @@ __device__ __forceinline__ void cut_row_body_m(const CutRowArgs& A, int r, CutRS
                 }
             }
         }
+        if (MODE == ROW_CUT && A.boxp && A.region[(size_t)r * 8] >= 0) val += A.boxp[(size_t)r * (W * W) + s];
     }
     if (MODE == ROW_INSIDE)
         A.part[(size_t)r * (W * W) + s] = val;

@@ -233,6 +233,7 @@ struct Plan {
     hipStream_t aux = nullptr;
     hipEvent_t ev_fork = nullptr, ev_iso = nullptr, ev_lists = nullptr, ev_interior = nullptr, ev_band = nullptr,
                ev_classes = nullptr;
+    hipEvent_t ev_aux_lists = nullptr;  // second stream: WQ-grid c and (split formation) the lists are done
 
     // timing
     bool timing = false;
