@@ -477,11 +477,12 @@ def bench_dwq(igatrim, wl, cfg, args, sync, stream, peaks):
     steps = max(5, args.steps // 5)
     kernels, kroofs = kernel_breakdown(plan, lambda: plan.mass_form(coef, out=vals, full=True, stream=stream), steps,
                                        sz, peaks, {"coef_points": sz["n_points"] - sz["n_cut_nodes"]})
-    sides = [r for r in kernels if r["kernel"].startswith("k_dwq_sides")]
+    sides = [r for r in kernels if r["kernel"].startswith(("k_dwq_sides", "k_cut_elem_sides"))]
     return {"value": sz["nnz"] / (ms_full * 1e-3), "unit": "nnz/s", "ms_per_step": ms_full,
             "formation_only_ms": ms_form, "formation_only_value": sz["nnz"] / (ms_form * 1e-3),
             "n_dwq_rows": sz["n_dwq_rows"], "n_cut_fn": sz["n_cut_fn"],
             "side_rules_ms_per_step": sides[0]["ms_per_step"] if sides else None,
+            "side_rules_kernel": sides[0]["kernel"] if sides else None,
             "kernels": [{k: (round(v, 5) if isinstance(v, float) else v) for k, v in r.items()} for r in kernels[:8]],
             "note": "same workload and step as the headline, cut rows by DWQ boxes + element rules"}
 
@@ -503,13 +504,14 @@ def bench_config3(igatrim, wl, cfg, args, sync, stream, peaks):
     kernels, kroofs = kernel_breakdown(plan, lambda: plan.mass_form(coef, out=vals, full=True, stream=stream), steps,
                                        sz, peaks, {"coef_points": sz["n_points"] - sz["n_cut_nodes"]})
     band_bytes = 8 * sz["band"] * sz["n_act"]
-    sides = [r for r in kernels if r["kernel"].startswith("k_dwq_sides")]
+    sides = [r for r in kernels if r["kernel"].startswith(("k_dwq_sides", "k_cut_elem_sides"))]
     return {"value": sz["nnz"] / (ms_full * 1e-3), "unit": "nnz/s", "ms_per_step": ms_full,
             "formation_only_ms": ms_form, "formation_only_value": sz["nnz"] / (ms_form * 1e-3),
             "band_MB": band_bytes / 1e6, "formation_only_GBs_written": band_bytes / (ms_form * 1e-3) / 1e9,
             "nnz": sz["nnz"], "n_act": sz["n_act"], "n_cut_fn": sz["n_cut_fn"], "n_cut_el": sz["n_cut_el"],
             "n_dwq_rows": sz["n_dwq_rows"], "plan_setup_s": round(t_plan, 2),
             "side_rules_ms_per_step": sides[0]["ms_per_step"] if sides else None,
+            "side_rules_kernel": sides[0]["kernel"] if sides else None,
             "kernels": [{k: (round(v, 5) if isinstance(v, float) else v) for k, v in r.items()} for r in kernels[:10]],
             "rooflines": {k: v for k, v in kroofs.items() if k.startswith(("k_interior", "k_cut_elem"))},
             "note": f"p=6, {args.cfg3_N}^2 elements, perturbed geometry c=|det J|, hole = union of 3 seeded "

@@ -337,10 +337,15 @@ static void form(Plan& P, const iga_coeff& c, double* vals, int flags, hipStream
     HIPX(hipEventRecord(P.ev_band, a));  // everything on the auxiliary stream is done
     {
         PhaseTimer t(P, s, IGA_PHASE_CUT);
-        if (full && P.method == IGA_DWQ)
-            launch_cut_elems_sides(P, c, s);  // the side rules (from the knots alone) beside them
-        else
+        // DWQ up to degree 4: the side rules (from the knots alone) as workgroups of the cut element
+        // matrices' launch; at degree 6 that launch's registers and LDS (the larger of the two bodies,
+        // and both bodies' LDS) slow the cut element matrices more than the overlap saves
+        if (full && P.method == IGA_DWQ && P.p <= 4) {
+            launch_cut_elems_sides(P, c, s);
+        } else {
             launch_cut_elems(P, c, s);  // with c at the cut nodes
+            if (full) launch_dwq_sides(P, s);
+        }
         if (box_early) {  // DWQ: the rows' box parts, while the second stream finishes
             HIPX(hipStreamWaitEvent(s, P.ev_aux_lists, 0));
             launch_dwq_box_parts(P, c, s);
