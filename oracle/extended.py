@@ -22,7 +22,8 @@ B-splines themselves):
   inside B_i's support (Marsden's identity), so the weights solve
       sum_m e_m lambda_{l+m}(x^k) = lambda_j(x^k),  k = 0..p
   (on uniform knots away from the ends: Lagrange extrapolation of the
-  coefficient sequence from the nodes l..l+p to j);
+  coefficient sequence from the nodes l..l+p to j), here in exact rational
+  arithmetic;
 * e_{i,j} = e^1_{i1 - l1}(j1) e^2_{i2 - l2}(j2), and the extended basis is
   B_i^e = B_i + sum_{outer j : i in I(j)} e_{i,j} B_j over the inner i.
   With E[i, j] = 1 (j = i inner) or e_{i,j} (j outer, i in I(j)) the
@@ -36,6 +37,7 @@ smaller l1.
 from __future__ import annotations
 
 import math
+from fractions import Fraction
 from itertools import combinations
 
 import numpy as np
@@ -66,16 +68,27 @@ def dual_power(knots, p, i, k, x0=0.0, h=1.0):
 def weights_1d(knots, p, j, l):
     """e_m, m = 0..p: the block l..l+p reproduces B_j's coefficient of every polynomial of degree p.
 
-    The conditions are taken on the monomials ((x - x0)/h)^k, x0 and h the centre and half
-    length of the knots t_a..t_b the functions involved read (a = min(j, l) + 1,
-    b = max(j, l + p) + p): the weights do not depend on the basis of the polynomials,
-    and about 0 the monomials' conditions grow ill-posed with the number of elements.
+    The conditions sum_m e_m lambda_{l+m}(x^k) = lambda_j(x^k), k = 0..p, are solved in exact
+    rational arithmetic from the (exactly representable) floating-point knots: in floating point
+    their condition number grows with the distance from j to the block and with p (about 1e7 at
+    p = 8 even on centred, scaled monomials), the exact solution has none of that error.
     """
-    a, b = min(j, l) + 1, max(j, l + p) + p
-    x0, h = 0.5 * (knots[a] + knots[b]), 0.5 * (knots[b] - knots[a])
-    V = np.array([[dual_power(knots, p, l + m, k, x0, h) for m in range(p + 1)] for k in range(p + 1)])
-    v = np.array([dual_power(knots, p, j, k, x0, h) for k in range(p + 1)])
-    return np.linalg.solve(V, v)
+    t = [Fraction(float(x)) for x in knots]
+
+    def lam(i, k):
+        s = sum((math.prod(c) for c in combinations(t[i + 1:i + p + 1], k)), Fraction(0)) if k > 0 else Fraction(1)
+        return s / math.comb(p, k)
+
+    n = p + 1
+    A = [[lam(l + m, k) for m in range(n)] + [lam(j, k)] for k in range(n)]
+    for c in range(n):   # Gauss-Jordan elimination, exact
+        r = next(r for r in range(c, n) if A[r][c] != 0)
+        A[c], A[r] = A[r], A[c]
+        for r in range(n):
+            if r != c and A[r][c] != 0:
+                f = A[r][c] / A[c][c]
+                A[r] = [a - f * b for a, b in zip(A[r], A[c])]
+    return np.array([float(A[r][n] / A[r][r]) for r in range(n)])
 
 
 def all_inner_blocks(inner, p):
