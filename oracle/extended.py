@@ -58,13 +58,6 @@ def inner_mask(ts):
     return out
 
 
-def dual_power(knots, p, i, k, x0=0.0, h=1.0):
-    """lambda_i(((x - x0)/h)^k) = sigma_k(s_{i+1}, ..., s_{i+p}) / binom(p, k), s = (t - x0)/h (Marsden's identity)."""
-    t = [(knots[m] - x0) / h for m in range(i + 1, i + p + 1)]
-    s = sum(math.prod(c) for c in combinations(t, k)) if k > 0 else 1.0
-    return s / math.comb(p, k)
-
-
 def weights_1d(knots, p, j, l):
     """e_m, m = 0..p: the block l..l+p reproduces B_j's coefficient of every polynomial of degree p.
 
