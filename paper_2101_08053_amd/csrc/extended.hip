@@ -8,11 +8,10 @@
 //    inner functions whose centre l + p/2 is nearest to j (squared index
 //    distance, ties to the smaller l2, then the smaller l1);
 //  * per direction the block's weights reproduce j's B-spline coefficient of
-//    every polynomial of degree p: the coefficient is the dual functional,
-//    which on monomials is an elementary symmetric polynomial of the knots in
-//    the support over a binomial (Marsden's identity), so the weights solve a
-//    (p+1) x (p+1) system, set up on monomials centred and scaled to the
-//    knots involved (the weights do not depend on the polynomial basis);
+//    every polynomial of degree p; the coefficient is the polynomial's blossom
+//    at j's knot window, so the weights are the blossoms of the block
+//    functions' polynomial pieces on their common element (de Boor's
+//    algorithm with the window as arguments);
 //  * E[i, j] = 1 (j = i inner) or e_{i,j} = e^1 e^2 (j outer, i in its block);
 //    the projection solves (E A E^T) x = E b, A = (M + M^T)/2, by
 //    Jacobi-preconditioned CG and returns u = E^T x.
@@ -125,55 +124,35 @@ __device__ bool nearest_block(const int8_t* __restrict__ ok, int nb1, int nb2, i
 }
 
 // Weights e_0..e_P of the functions l..l+P that reproduce B_j's coefficient of
-// every polynomial of degree P: sum_m e_m lambda_{l+m}(q_k) = lambda_j(q_k)
-// for q_k = ((x - x0)/h)^k, x0 and h the centre and half length of the knots
-// t_a..t_b the functions read. lambda_i(q_k) = sigma_k(s_{i+1..i+P}) /
-// binom(P, k) with s = (t - x0)/h. Gaussian elimination with partial pivoting.
+// every polynomial of degree P. The B-spline coefficient of a polynomial is its
+// blossom at the function's knot window (t_{j+1}, ..., t_{j+P}); the functions
+// l..l+P are all nonzero on the element [t_{l+P}, t_{l+P+1}], where their
+// polynomial pieces q_0..q_P have de Boor points e_0..e_P (unit vectors), and
+// each q_n has coefficient 1 on B_{l+n} and 0 on the block's other functions,
+// so e_n = lambda_j(q_n) = blossom of q_n at j's window: de Boor's algorithm on
+// the unit vectors with argument t_{j+r} at level r. The same weights as the
+// reproduction conditions solved exactly, without their conditioning (which
+// reaches 1e7 at P = 8 even on scaled monomials): the steps are affine
+// combinations, extrapolating only as far as j lies from the element.
 template <int P>
 __device__ bool ext_weights(const double* __restrict__ t, int j, int l, double* e) {
-    const int a = min(j, l) + 1, b = max(j, l + P) + P;
-    const double x0 = 0.5 * (t[a] + t[b]), h = 0.5 * (t[b] - t[a]);
-    double V[P + 1][P + 2];
-    for (int m = 0; m <= P + 1; ++m) {
-        const int i = (m <= P) ? l + m : j;
-        double sg[P + 1];
-        sg[0] = 1.0;
-        for (int k = 1; k <= P; ++k) sg[k] = 0.0;
-        for (int q = 1; q <= P; ++q) {
-            const double y = (t[i + q] - x0) / h;
-            for (int k = q; k >= 1; --k) sg[k] += y * sg[k - 1];
-        }
-        double binom = 1.0;
-        for (int k = 0; k <= P; ++k) {
-            V[k][m] = sg[k] / binom;
-            binom = binom * (double)(P - k) / (double)(k + 1);
+    double d[P + 1][P + 1];
+#pragma unroll
+    for (int i = 0; i <= P; ++i)
+#pragma unroll
+        for (int n = 0; n <= P; ++n) d[i][n] = (i == n) ? 1.0 : 0.0;
+    for (int r = 1; r <= P; ++r) {
+        const double u = t[j + r];
+        for (int i = P; i >= r; --i) {   // descending: d[i - 1] still holds level r - 1
+            const double lo = t[l + i], hi = t[l + i + P + 1 - r];
+            if (!(hi > lo)) return false;
+            const double a = (u - lo) / (hi - lo);
+#pragma unroll
+            for (int n = 0; n <= P; ++n) d[i][n] = (1.0 - a) * d[i - 1][n] + a * d[i][n];
         }
     }
-    for (int c = 0; c <= P; ++c) {
-        int pr = c;
-        double mx = fabs(V[c][c]);
-        for (int r = c + 1; r <= P; ++r)
-            if (fabs(V[r][c]) > mx) {
-                mx = fabs(V[r][c]);
-                pr = r;
-            }
-        if (!(mx > 0.0)) return false;
-        if (pr != c)
-            for (int k = c; k <= P + 1; ++k) {
-                const double tmp = V[c][k];
-                V[c][k] = V[pr][k];
-                V[pr][k] = tmp;
-            }
-        for (int r = c + 1; r <= P; ++r) {
-            const double f = V[r][c] / V[c][c];
-            for (int k = c; k <= P + 1; ++k) V[r][k] -= f * V[c][k];
-        }
-    }
-    for (int c = P; c >= 0; --c) {
-        double s = V[c][P + 1];
-        for (int k = c + 1; k <= P; ++k) s -= V[c][k] * e[k];
-        e[c] = s / V[c][c];
-    }
+#pragma unroll
+    for (int n = 0; n <= P; ++n) e[n] = d[P][n];
     return true;
 }
 

@@ -2,8 +2,10 @@
 
 * the extension itself: the inner set, every outer function's block (compact
   ids, exact) and its weights (within 1e-12 of the larger of 1 and the
-  weight) equal the oracle's, on a sliver cut, circles, an ellipse patch of
-  degree 4 and non-uniform knots;
+  weight; the oracle solves the reproduction conditions exactly, the device
+  blossoms the block's polynomial pieces) equal the oracle's, on a sliver
+  cut, circles, an ellipse patch of degree 4, non-uniform knots and line
+  trims of degrees 1, 6 and 8;
 * the projection under identical rules (oracle weights and cut nodes
   injected): the oracle's residual of the device's extended unknowns,
   ||E b - E A E^T x|| / ||E b|| with the oracle's E, A and b, stays within
@@ -54,7 +56,9 @@ def _oracle_columns(o):
 
 
 @pytest.mark.parametrize("cfg", [_sliver(3), wl.config1(N=32), wl.config3(N=20, p=4),
-                                 wl.nonuniform_variant(wl.config1(N=14, p=3))], ids=lambda c: c.name)
+                                 wl.nonuniform_variant(wl.config1(N=14, p=3)),
+                                 wl.table1_line(1, N=12), wl.table1_line(6, N=12), wl.table1_line(8, N=12)],
+                         ids=lambda c: c.name)
 def test_extension_against_oracle(cfg):
     require_gpu()
     from paper_2101_08053_amd import igatrim
