@@ -11,7 +11,8 @@
   ||E b - E A E^T x|| / ||E b|| with the oracle's E, A and b, stays within
   1e-10 (PCG stops at 1e-12 on the device's), the outer coefficients are E^T
   of the inner ones, and the device u is within 1e-9 of the oracle's solve;
-* on a mapped patch (c = |det J|) the same residual bar;
+* on a mapped patch (c = |det J|), with DWQ rows and with the element-Gauss
+  reference rules, the same residual bar;
 * Q_p is reproduced (c = 1, g in Q_p), with hybrid Gauss and DWQ plans;
 * on a sliver cut the extended solve converges in no more iterations than
   the plain one and its error stays that of the plain projection;
@@ -26,7 +27,7 @@ import math
 import numpy as np
 import pytest
 
-from gpu_common import inject_oracle_rules, require_gpu, say
+from gpu_common import inject_oracle_dwq, inject_oracle_rules, require_gpu, say
 from oracle import extended, project
 from oracle.assemble import Oracle
 from oracle.geometry import Coefficient
@@ -134,6 +135,34 @@ def test_extended_projection_mapped_patch():
     M = o.hybrid()
     A = 0.5 * (M + M.T)
     be = E @ project.rhs(o, wl.config1_target)
+    res = np.linalg.norm(be - E @ (A @ (E.T @ x))) / np.linalg.norm(be)
+    say(f"   oracle residual of device x: {res:.2e}")
+    assert res <= 1e-9
+
+
+@pytest.mark.parametrize("method", ["dwq", "reference"])
+def test_extended_projection_other_rules(method):
+    """DWQ rows (discontinuous weights injected too) and the element-Gauss reference rules: the
+    oracle's extended residual of the device's unknowns with that method's matrix and right-hand side."""
+    require_gpu()
+    from paper_2101_08053_amd import igatrim
+    cfg = wl.config1(N=24)
+    o = Oracle(cfg)
+    plan = igatrim.Plan(cfg, igatrim.DWQ if method == "dwq" else igatrim.GAUSS_REF)
+    inject_oracle_rules(plan, o)
+    if method == "dwq":
+        inject_oracle_dwq(plan, o)
+    c = plan.coeff()
+    vals = plan.mass_form(c)
+    u, info = igatrim.l2_project_ext(plan, vals, c, _sincos(), rtol=1e-12)
+    u = u.cpu().numpy()
+    say(f"[l2 ext {method}] {info}")
+    assert info["converged"]
+    M = o.dwq() if method == "dwq" else o.gauss_reference()
+    inner_flat, E, _ = _oracle_columns(o)
+    x = u[o.ts.act_of[inner_flat]]
+    A = 0.5 * (M + M.T)
+    be = E @ project.rhs(o, wl.config1_target, method)
     res = np.linalg.norm(be - E @ (A @ (E.T @ x))) / np.linalg.norm(be)
     say(f"   oracle residual of device x: {res:.2e}")
     assert res <= 1e-9
