@@ -311,7 +311,11 @@ int iga_mf_adjoint(iga_plan* plan, const double* c_points, const double* u, cons
  * a HIP graph recorded on the first such call and replayed afterwards. The
  * plans, coefficient data and output buffers are borrowed: they must stay
  * valid and keep their addresses while the batch lives. Calls on one batch
- * must not overlap (they share its counters). */
+ * must not overlap (they share its counters). iga_batch_create checks every
+ * plan and buffer pointer, degree and method before it touches the device:
+ * IGA_E_INVALID (count <= 0, a null array, plan or buffer),
+ * IGA_E_UNSUPPORTED (degree above 6, naive WQ), IGA_E_NOMEM, IGA_E_HIP;
+ * *out is NULL after a failure. */
 typedef struct iga_batch iga_batch;
 typedef struct iga_batch_stats {
     int64_t n_plans;

@@ -492,6 +492,14 @@ BatchView batch_view(iga_batch* b) {
 
 static iga_batch* batch_create(iga_plan* const* plans, int count, const iga_coeff* cs, double* const* outs) {
     IGA_REQUIRE(count > 0 && plans && cs && outs, IGA_E_INVALID, "empty batch");
+    for (int k = 0; k < count; ++k) {  // every argument before any device work
+        IGA_REQUIRE(plans[k], IGA_E_INVALID, "null plan in batch");
+        IGA_REQUIRE(outs[k], IGA_E_INVALID, "output buffer missing");
+        const Plan& P = *static_cast<const Plan*>(plans[k]);
+        IGA_REQUIRE(P.p <= kBatchMaxP, IGA_E_UNSUPPORTED, "batched formation handles degrees up to 6");
+        IGA_REQUIRE(P.method == IGA_HYBRID_GAUSS || P.method == IGA_GAUSS_REF || P.method == IGA_DWQ,
+                    IGA_E_UNSUPPORTED, "batched formation handles hybrid Gauss, element Gauss and DWQ plans");
+    }
     auto B = std::make_unique<iga_batch>();
     int dev = 0;
     HIPX(hipGetDevice(&dev));
@@ -514,13 +522,8 @@ static iga_batch* batch_create(iga_plan* const* plans, int count, const iga_coef
     std::vector<BatchItem> coefs[kBatchGroups], tiles[kBatchGroups], rows[kBatchGroups], cutes[kBatchGroups];
     std::vector<BatchItem> dwqs[kBatchGroups], dwqr[kBatchGroups];
     for (int k = 0; k < count; ++k) {
-        IGA_REQUIRE(plans[k], IGA_E_INVALID, "null plan in batch");
         Plan& P = *static_cast<Plan*>(plans[k]);
         const iga_coeff& c = cs[k];
-        IGA_REQUIRE(outs[k], IGA_E_INVALID, "output buffer missing");
-        IGA_REQUIRE(P.p <= kBatchMaxP, IGA_E_UNSUPPORTED, "batched formation handles degrees up to 6");
-        IGA_REQUIRE(P.method == IGA_HYBRID_GAUSS || P.method == IGA_GAUSS_REF || P.method == IGA_DWQ,
-                    IGA_E_UNSUPPORTED, "batched formation handles hybrid Gauss, element Gauss and DWQ plans");
         IGA_REQUIRE(!(P.method == IGA_DWQ && c.kind == IGA_COEF_AT_POINTS), IGA_E_UNSUPPORTED,
                     "discontinuous weighted quadrature needs c at nested points: constant or |det J| only");
         IGA_REQUIRE(c.kind >= IGA_COEF_CONST && c.kind <= IGA_COEF_AT_POINTS, IGA_E_UNSUPPORTED, "coefficient kind");
@@ -749,6 +752,7 @@ int iga_batch_create(iga_plan* const* plans, int32_t count, const iga_coeff* cs,
                      iga_batch** out) {
     API_TRY
     IGA_REQUIRE(out, IGA_E_INVALID, "null argument");
+    *out = nullptr;
     *out = batch_create(plans, count, cs, vals);
     API_CATCH
 }
