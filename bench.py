@@ -175,7 +175,8 @@ def kernel_work(name, sz, plan_info):
     system of Eq. (5) (m = 2p+1 rows, q = 2p+2 points) is a Householder QR of
     q x m: 2 q m^2 - (2/3) m^3 flops; the cut-element preparation writes each
     node's (x, y, w) (24 B); the element-formed rows' cut entries read each cut
-    element matrix once (8 L^2 B) and write their rows (8 (2p+1)^2 B).
+    element matrix once (8 L^2 B) and write their rows (8 (2p+1)^2 B); a DWQ
+    row's box part is one value per slot (8 (2p+1)^2 B).
     """
     p = sz["p"]
     L = (p + 1) ** 2
@@ -191,6 +192,13 @@ def kernel_work(name, sz, plan_info):
     if base == "k_cut_elem":
         return ("mfma", 2 * sz["n_cut_nodes"] * L * (L + 1) // 2,
                 f"n_nodes L(L+1)/2 FMA = 2 x {L * (L + 1) // 2} flops per node")
+    if base == "k_cut_elem_sides":  # DWQ: the side rules' systems run beside the cut element matrices
+        return ("mfma", 2 * sz["n_cut_nodes"] * L * (L + 1) // 2,
+                f"n_nodes L(L+1)/2 FMA = 2 x {L * (L + 1) // 2} flops per node (the cut element matrices); "
+                "the DWQ side rules' refined systems run beside them in the same launch, uncounted")
+    if base == "k_dwq_rows":
+        return ("hbm", 8 * W2 * sz["n_dwq_rows"],
+                f"8 (2p+1)^2 = {8 * W2} B per DWQ row: its box part, one value per slot")
     if base == "k_coef":  # a launch of its own (formations over resident tables): the WQ grid or the band points
         npts = plan_info.get("coef_points", sz["q1"] * sz["q2"])
         return ("hbm", (24 * npts + 16 * sz["n1"] * sz["n2"]) // 2,
@@ -478,11 +486,16 @@ def bench_dwq(igatrim, wl, cfg, args, sync, stream, peaks):
     kernels, kroofs = kernel_breakdown(plan, lambda: plan.mass_form(coef, out=vals, full=True, stream=stream), steps,
                                        sz, peaks, {"coef_points": sz["n_points"] - sz["n_cut_nodes"]})
     sides = [r for r in kernels if r["kernel"].startswith(("k_dwq_sides", "k_cut_elem_sides"))]
+    # the section's roofline: the kernel with the largest time per step among those with a work count
+    top = next((r["kernel"] for r in kernels if r["kernel"] in kroofs), None)
     return {"value": sz["nnz"] / (ms_full * 1e-3), "unit": "nnz/s", "ms_per_step": ms_full,
             "formation_only_ms": ms_form, "formation_only_value": sz["nnz"] / (ms_form * 1e-3),
             "n_dwq_rows": sz["n_dwq_rows"], "n_cut_fn": sz["n_cut_fn"],
             "side_rules_ms_per_step": sides[0]["ms_per_step"] if sides else None,
             "side_rules_kernel": sides[0]["kernel"] if sides else None,
+            "roofline": dict(kroofs[top], chosen="largest time per step among the step's counted kernels")
+            if top else None,
+            "rooflines": kroofs,
             "kernels": [{k: (round(v, 5) if isinstance(v, float) else v) for k, v in r.items()} for r in kernels[:8]],
             "note": "same workload and step as the headline, cut rows by DWQ boxes + element rules"}
 
