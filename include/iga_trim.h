@@ -494,6 +494,15 @@ typedef struct iga_peaks {
 } iga_peaks;
 int iga_measure_peaks(const double* src, double* dst, int64_t n, int32_t reps, iga_peaks* out, void* stream);
 
+/* For test builds of the library (compiled with -DIGA_DEBUG_BOUNDS), not a
+ * paper operation: every store into the band layout vals[slot * n_act + row]
+ * and into the per-row scratch arrays checks its slot and row; an offset out
+ * of range is counted and redirected to the array's first element, so no
+ * store leaves the array. *hits (host) receives the count over all modules
+ * since the last reset (the device is synchronised first); reset != 0 clears
+ * it. A release build has no checks: IGA_E_UNSUPPORTED, *hits = 0. */
+int iga_debug_bounds_hits(int64_t* hits, int32_t reset);
+
 const char* iga_status_string(int code);
 const char* iga_last_error(void);
 

@@ -28,6 +28,17 @@ Plan::~Plan() {
     for (void* ptr : allocations) hipFree(ptr);
 }
 
+// Readers of the index-check counts of the modules built with -DIGA_DEBUG_BOUNDS
+// (each registers one at load time); none in a release build.
+static std::vector<unsigned long long (*)(bool)>& bounds_readers() {
+    static std::vector<unsigned long long (*)(bool)> v;
+    return v;
+}
+int bounds_register(unsigned long long (*read)(bool reset)) {
+    bounds_readers().push_back(read);
+    return (int)bounds_readers().size();
+}
+
 static int qmax_of(int N, int p) {
     // most WQ points in the support of one function: elements i-p..i
     int best = 0;
@@ -860,6 +871,26 @@ int iga_copy(void* dst, const void* src, int64_t bytes, void* stream) {
         HIPX(hipMemcpyAsync(dst, src, (size_t)bytes, hipMemcpyDefault, (hipStream_t)stream));
         HIPX(hipStreamSynchronize((hipStream_t)stream));
     }
+    API_END
+}
+
+int iga_debug_bounds_hits(int64_t* hits, int32_t reset) {
+    API_BEGIN
+    IGA_REQUIRE(hits, IGA_E_INVALID, "null argument");
+    *hits = 0;
+#ifdef IGA_DEBUG_BOUNDS
+    HIPX(hipDeviceSynchronize());
+    unsigned long long total = 0;
+    for (auto read : bounds_readers()) {
+        const unsigned long long v = read(reset != 0);
+        IGA_REQUIRE(v != ~0ull, IGA_E_HIP, "reading an index-check count failed");
+        total += v;
+    }
+    *hits = (int64_t)total;
+#else
+    (void)reset;
+    throw Error{IGA_E_UNSUPPORTED, "index checks are compiled in with -DIGA_DEBUG_BOUNDS only"};
+#endif
     API_END
 }
 

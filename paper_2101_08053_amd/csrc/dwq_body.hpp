@@ -4,6 +4,7 @@
 // slots and the box contribution of one element-formed row.
 #pragma once
 
+#include "bounds.hpp"
 #include "plan.hpp"
 
 namespace iga {
@@ -405,9 +406,9 @@ __device__ __forceinline__ void dwq_rows_body(const DwqRowArgs& A, int r) {
             double acc = 0.0;
             for (int q1 = 0; q1 < n1q; ++q1) acc += sWt[0][q1] * sB[0][q1][a] * sT[b][q1];
             if (A.boxp)
-                A.boxp[(size_t)r * (W * W) + t] = acc;
+                A.boxp[band_index(r, A.n_rows, t, W * W)] = acc;
             else
-                A.vals[(size_t)t * A.n_act + row] += acc;
+                A.vals[band_index(t, W * W, row, A.n_act)] += acc;
         }
     }
 }

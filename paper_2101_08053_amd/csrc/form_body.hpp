@@ -3,6 +3,7 @@
 // one work item with 256 threads on LDS the caller provides.
 #pragma once
 
+#include "bounds.hpp"
 #include "plan.hpp"
 
 namespace iga {
@@ -499,7 +500,7 @@ __device__ __forceinline__ void interior_rows_block(const IntArgs& A, int tx, in
                 interior_col_reg<P>([&](int q, int al) { return wt[q] * S.r.sB[(k0 + q) * (P + 1) + al]; },
                                     &S.r.sT[b][k0], acc);
 #pragma unroll
-            for (int a = 0; a < W; ++a) A.vals[(size_t)(a * W + b) * A.n_act + cid] = acc[a];
+            for (int a = 0; a < W; ++a) A.vals[band_index(a * W + b, W * W, cid, A.n_act)] = acc[a];
         }
     } else {  // one column of an end row per pair
         for (int t = tid; t < 2 * NG * W; t += NT) {
@@ -514,7 +515,7 @@ __device__ __forceinline__ void interior_rows_block(const IntArgs& A, int tx, in
             double acc[W];
             interior_col_end<P>(&S.e.sG[g][0][0], &S.e.sT[bcol][kloc(kg0)], q1, acc);
 #pragma unroll
-            for (int a = 0; a < W; ++a) A.vals[(size_t)(a * W + bcol) * A.n_act + cide] = acc[a];
+            for (int a = 0; a < W; ++a) A.vals[band_index(a * W + bcol, W * W, cide, A.n_act)] = acc[a];
         }
     }
 }
@@ -856,7 +857,7 @@ __device__ __forceinline__ void cut_row_body_m(const CutRowArgs& A, int r, CutRS
     if (s >= W * W) return;
     const int a = s / W, b = s % W;          // column offsets a-p, b-p
     const int j1 = i1 + a - P, j2 = i2 + b - P;
-    double* out = A.vals + (size_t)s * A.n_act + row;
+    double* out = A.vals + band_index(s, W * W, row, A.n_act);
     double val = 0.0;
     if (j1 >= 0 && j1 < D1.n && j2 >= 0 && j2 < D2.n && A.act_of[j2 * D1.n + j1] >= 0) {
         if (INS) {
@@ -865,7 +866,7 @@ __device__ __forceinline__ void cut_row_body_m(const CutRowArgs& A, int r, CutRS
 #pragma unroll
                 for (int g2 = 0; g2 < NP; ++g2) val += sF2[m2][g2][b] * S.sU[m2][g2][a];
         } else {
-            val = A.part[(size_t)r * (W * W) + s];   // the inside sum, written by the first launch
+            val = A.part[band_index(r, A.n_rows, s, W * W)];   // the inside sum, written by the first launch
         }
         if (CUT) {
             // cut elements: the column's entry of the staged line, zero where the element is not cut
@@ -885,7 +886,7 @@ __device__ __forceinline__ void cut_row_body_m(const CutRowArgs& A, int r, CutRS
         if (MODE == ROW_CUT && A.boxp && A.region[(size_t)r * 8] >= 0) val += A.boxp[(size_t)r * (W * W) + s];
     }
     if (MODE == ROW_INSIDE)
-        A.part[(size_t)r * (W * W) + s] = val;
+        A.part[band_index(r, A.n_rows, s, W * W)] = val;
     else
         *out = val;
 }

@@ -14,7 +14,8 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libigatrim.so")
+# IGA_TRIM_LIB names another build of the library (the index-checking test build)
+LIB_PATH = os.environ.get("IGA_TRIM_LIB") or os.path.join(HERE, "libigatrim.so")
 
 GAUSS_REF, HYBRID_GAUSS, DWQ, NAIVE_WQ = 0, 1, 2, 3
 COEF_CONST, COEF_GEOM_DETJ, COEF_AT_POINTS = 0, 1, 2
@@ -138,6 +139,7 @@ def lib():
             "iga_plan_set_weights": (C.c_int, [P, C.c_int32, V, V]),
             "iga_plan_set_dwq_weights": (C.c_int, [P, C.c_int32, V, V]),
             "iga_plan_set_cut_nodes": (C.c_int, [P, V, V, V, C.c_int64, V]),
+            "iga_debug_bounds_hits": (C.c_int, [C.POINTER(C.c_int64), C.c_int32]),
             "iga_status_string": (C.c_char_p, [C.c_int]),
             "iga_last_error": (C.c_char_p, []),
         }
@@ -156,11 +158,19 @@ EXPORTED = ("iga_trim_plan_create", "iga_plan_destroy", "iga_plan_sizes", "iga_p
             "iga_batch_form", "iga_batch_autotune", "iga_batch_info", "iga_batch_status", "iga_batch_project",
             "iga_plan_set_timing", "iga_plan_timings", "iga_plan_kernel_times", "iga_plan_set_graph",
             "iga_copy", "iga_measure_peaks", "iga_plan_table", "iga_plan_int_table", "iga_plan_set_weights",
-            "iga_plan_set_dwq_weights", "iga_plan_set_cut_nodes", "iga_status_string", "iga_last_error")
+            "iga_plan_set_dwq_weights", "iga_plan_set_cut_nodes", "iga_debug_bounds_hits", "iga_status_string",
+            "iga_last_error")
 
 (TABLE_WQ_POINTS, TABLE_WQ_WEIGHTS, TABLE_MASS_1D, TABLE_C_WQ, TABLE_C_BAND, TABLE_C_CUT, TABLE_CUT_W,
  TABLE_DWQ_X, TABLE_DWQ_W) = range(9)
 ITABLE_DWQ_NPTS, ITABLE_DWQ_ELEM, ITABLE_DWQ_WQIDX, ITABLE_DWQ_BOX, ITABLE_FORM_ROWS = range(5)
+
+
+def debug_bounds_hits(reset=False):
+    """Out-of-range band stores counted by an index-checking build (IGA_TRIM_LIB); raises on a release build."""
+    n = C.c_int64(0)
+    _check(lib().iga_debug_bounds_hits(C.byref(n), 1 if reset else 0))
+    return int(n.value)
 
 
 def _check(code):

@@ -31,3 +31,18 @@ def test_status_strings():
     L.iga_status_string.restype = ctypes.c_char_p
     assert L.iga_status_string(0) == b"ok"
     assert L.iga_status_string(-5) == b"singular weight system"
+
+
+def test_index_check_count_is_a_test_build_call():
+    """A release build answers IGA_E_UNSUPPORTED; the index-checking build exports the same symbols."""
+    _ensure_built()
+    L = ctypes.CDLL(igatrim.LIB_PATH)
+    n = ctypes.c_int64(-1)
+    assert L.iga_debug_bounds_hits(ctypes.byref(n), 0) == -2 and n.value == 0
+    dbg = os.path.join(os.path.dirname(igatrim.LIB_PATH), "libigatrim_debug.so")
+    if os.path.exists(dbg):
+        hdr = open(os.path.join(ROOT, "include", "iga_trim.h")).read()
+        declared = set(re.findall(r"^\s*(?:int|void|const char\*)\s+(iga_\w+)\s*\(", hdr, re.M))
+        D = ctypes.CDLL(dbg)
+        for name in declared:
+            assert hasattr(D, name), name
