@@ -15,12 +15,14 @@ which every dispatch is bracketed by HIP events on its own stream; beside it
 objects. The line also carries: the measured copy / FP64 FMA / FP64 MFMA
 ceilings; the step with a 1 GiB write between replays (the step's 32 MB
 would otherwise stay in the 256 MB last-level cache); the same workload with
-discontinuous weighted quadrature; the degree-6, 512 x 512, three-ellipse
-DWQ workload; the L2 projection; 256 patches formed by the batched launches
-(HIP graph, autotuned) and L2-projected by the batched PCG, against the same
-patches one by one; the matrix-free product and its adjoint on 1024 x 1024
-elements against plain formation there; and the oracle's rate on a bounded
-sample, on one core and on all host cores.
+discontinuous weighted quadrature (with its own rooflines); the degree-6,
+512 x 512, three-ellipse DWQ workload; the L2 projection, in the trimmed
+basis and in the extended B-spline basis; 256 patches formed by the batched
+launches (HIP graph, autotuned) and L2-projected by the batched PCG, against
+the same patches one by one; the matrix-free product and its adjoint on
+1024 x 1024 elements against plain formation there; Table 1 (the methods
+against element Gauss, p = 1..8) from the device; and the oracle's rate on a
+bounded sample, on one core and on all host cores.
 """
 import argparse
 import json
