@@ -201,3 +201,103 @@ def test_ell_roundtrip():
     o = _const(wl.config1(N=10))
     H = o.hybrid()
     assert abs(from_ell(to_ell(H, o.ts), o.ts) - H).max() == 0.0
+
+
+def _separable_patch(p=3, N=10):
+    """Line-trimmed patch with a separable map F(x, y) = (f(x), g(y)): c = |det J| = f'(x) g'(y)."""
+    cfg = wl.table1_line(p, N=N)
+    g1 = wl.greville(cfg.knots[0], p)
+    g2 = wl.greville(cfg.knots[1], p)
+    a = g1 + 0.2 * g1 ** 2            # increasing: f' > 0
+    b = g2 - 0.15 * g2 ** 2           # increasing: g' > 0
+    cp = np.empty((len(g2), len(g1), 2))
+    cp[..., 0] = a[None, :]
+    cp[..., 1] = b[:, None]
+    cfg.geom_cp = cp
+    cfg.coef = wl.COEF_GEOM_DETJ
+    return cfg, a, b
+
+
+def _factor_1d(knots, p, coefs, x, w):
+    """sum_k w_k f'(x_k) B_j(x_k) for every j, f = sum_i coefs_i B_i (SciPy evaluation)."""
+    from scipy.interpolate import BSpline
+    fp = BSpline(knots, coefs, p).derivative()(x)
+    B = BSpline.design_matrix(x, knots, p).toarray()
+    return (w * fp) @ B
+
+
+def test_wq_rows_separable_coefficient():
+    """WQ interior rows with a non-constant c pinned by separability (Eqs. (5)-(7)).
+
+    For c(x, y) = c1(x) c2(y) the double sum of Eq. (7) factorises: the entry
+    (i, j) is (sum_k w1_{k,i1} c1 B_j1)(sum_l w2_{l,i2} c2 B_j2). Here c is
+    |det J| of a separable map, whose factors f', g' and the basis values are
+    evaluated by SciPy; the oracle's rows come from its two-dimensional grid of
+    c and its tensor sums. c is not symmetric in (i, j), so an exchanged test
+    and trial index fails as well as a wrong direction or a wrong c.
+    """
+    cfg, a, b = _separable_patch()
+    o = Oracle(cfg, coef=Coefficient(cfg, kind=wl.COEF_GEOM_DETJ))
+    p, n1 = cfg.p, o.ts.n1
+    k1, k2 = o.k1, o.k2
+    rows = o.interior_rows_flat()
+    assert len(rows) > 20
+    worst = 0.0
+    for f in rows:
+        i2, i1 = divmod(int(f), n1)
+        F1 = _factor_1d(k1, p, a, o.xs1, o.W1[i1])
+        F2 = _factor_1d(k2, p, b, o.xs2, o.W2[i2])
+        row = o.wq_row(i1, i2)
+        scale = max(abs(v) for v in row.values())
+        for col, v in row.items():
+            j2, j1 = divmod(col, n1)
+            worst = max(worst, abs(v - F1[j1] * F2[j2]) / scale)
+    assert worst < 1e-13, worst
+    # the coefficient is far from constant, so the pin is not the c = 1 case
+    c = o.wq_grid_coef()
+    assert c.max() / c.min() > 1.3
+
+
+def test_dwq_box_separable_coefficient():
+    """DWQ rows (Sect. 3.3) with a non-constant c: the box part factorises like a WQ row.
+
+    Each DWQ row is its box's tensor rule plus element rules on the rest of
+    its support. With c = f'(x) g'(y) the box part is the product of the two
+    1-D refined sums (SciPy values of f', g' and the basis), so the row minus
+    its element-rule part must equal that product.
+    """
+    cfg, a, b = _separable_patch()
+    o = Oracle(cfg, coef=Coefficient(cfg, kind=wl.COEF_GEOM_DETJ))
+    p, ts = cfg.p, o.ts
+    n1 = ts.n1
+    from oracle.trim import CUT, INSIDE
+    checked = 0
+    worst = 0.0
+    for f in o.cut_rows_flat():
+        i2, i1 = divmod(int(f), n1)
+        reg = o.dwq_region(i1, i2)
+        if reg is None:
+            continue
+        o1, o2 = reg
+        x1, _, _, w1 = o.dwq_rule(0, i1, o1)
+        x2, _, _, w2 = o.dwq_rule(1, i2, o2)
+        F1 = _factor_1d(o.k1, p, a, x1, w1)
+        F2 = _factor_1d(o.k2, p, b, x2, w2)
+        row = dict(o.dwq_row(i1, i2))
+        for e2 in range(max(0, i2 - p), min(ts.N2 - 1, i2) + 1):   # take away the element-rule part
+            for e1 in range(max(0, i1 - p), min(ts.N1 - 1, i1) + 1):
+                if (o1[0] <= e1 <= o1[1] and o2[0] <= e2 <= o2[1]) or ts.ecls[e2, e1] not in (INSIDE, CUT):
+                    continue
+                E = o.local_matrix(e1, e2)
+                li = (i2 - e2) * (p + 1) + (i1 - e1)
+                for a2 in range(p + 1):
+                    for a1 in range(p + 1):
+                        col = (e2 + a2) * n1 + (e1 + a1)
+                        row[col] -= E[li, a2 * (p + 1) + a1]
+        scale = max(abs(v) for v in row.values())
+        for col, v in row.items():
+            j2, j1 = divmod(col, n1)
+            worst = max(worst, abs(v - F1[j1] * F2[j2]) / scale)
+        checked += 1
+    assert checked >= 5
+    assert worst < 1e-12, worst
