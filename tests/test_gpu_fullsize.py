@@ -18,6 +18,9 @@
   one-patch formation bit for bit.
 * 300 x 300, p = 2, circular hole (c = 1): the cut rules find their elements
   from more class counts than one batch of loads covers; sampled rows as above.
+* 256 x 256, p = 4, cubic hole, with a separable map (c = f'(x) g'(y)): sampled
+  interior rows equal products of 1-D weighted sums evaluated by SciPy, a
+  property that holds at any size and needs no oracle set-up.
 """
 import numpy as np
 import pytest
@@ -205,3 +208,66 @@ def test_fullsize_batched():
     bad = [k for k, (g, r) in enumerate(zip(outs, ref)) if not np.array_equal(g, r)]
     say(f"   {len(cfgs) - len(bad)} of {len(cfgs)} patches bit-identical; info {b.info()}")
     assert not bad
+
+
+def test_fullsize_separable_map_rows_factorise():
+    """256 x 256, p = 4, cubic hole, graph replay: interior rows with a non-constant c against a property.
+
+    With a separable map F(x, y) = (f(x), g(y)), c = |det J| = f'(x) g'(y), and
+    an interior row's entry for column (j1, j2) is the product of the 1-D sums
+    sum_k w1_{k,i1} f'(x_k) B_j1(x_k) and sum_l w2_{l,i2} g'(y_l) B_j2(y_l)
+    (Eq. (7) with a separable c). The device's own weights and points, SciPy's
+    f', g' and basis values give the products; 400 sampled interior rows of
+    the device's full formation must match them to 1e-12 of the row's largest
+    entry (the device sums the same terms in another order).
+    """
+    torch = require_gpu()
+    from scipy.interpolate import BSpline
+    from paper_2101_08053_amd import igatrim
+    p, N = 4, 256
+    cfg = wl.config2(N=N, p=p)
+    g1, g2 = wl.greville(cfg.knots[0], p), wl.greville(cfg.knots[1], p)
+    a, b = g1 + 0.2 * g1 ** 2, g2 - 0.15 * g2 ** 2   # increasing: f', g' > 0
+    cp = np.empty((len(g2), len(g1), 2))
+    cp[..., 0] = a[None, :]
+    cp[..., 1] = b[:, None]
+    cfg.geom_cp = cp
+    plan = igatrim.Plan(cfg, igatrim.HYBRID_GAUSS)
+    vals = _device_full(plan, igatrim)
+    act_of, _, fcls = (t.cpu().numpy() for t in plan.index_maps())
+    n1, W = plan.sizes["n1"], 2 * p + 1
+
+    def pt0(e, Ne):  # first WQ point of element e: p+1 points in the end elements, 2 in the others
+        return 0 if e <= 0 else (p + 1) + 2 * (e - 1)
+
+    factors = []
+    for d, coefs in ((0, a), (1, b)):
+        xq = plan.table(igatrim.TABLE_WQ_POINTS, d).cpu().numpy().ravel()
+        Wt = plan.table(igatrim.TABLE_WQ_WEIGHTS, d).cpu().numpy()
+        knots = cfg.knots[d]
+        fp = BSpline(knots, coefs, p).derivative()(xq)
+        B = BSpline.design_matrix(xq, knots, p).toarray()
+        Wfull = np.zeros((Wt.shape[0], len(xq)))
+        for i in range(Wt.shape[0]):
+            k0 = pt0(max(0, i - p), N)
+            q = min(Wt.shape[1], len(xq) - k0)
+            Wfull[i, k0:k0 + q] = Wt[i, :q]
+        factors.append((Wfull * fp[None, :]) @ B)   # [i, j]
+    F1, F2 = factors
+    interior = np.nonzero(fcls == 1)[0]   # function class 1: interior
+    rows = np.sort(np.random.default_rng(wl.SEED_BASE + 77).choice(interior, 400, replace=False))
+    worst = 0.0
+    for f in rows:
+        i2, i1 = divmod(int(f), n1)
+        r = act_of[f]
+        got = np.zeros((W, W))
+        exp = np.zeros((W, W))
+        for ai in range(W):
+            for bi in range(W):
+                j1, j2 = i1 + ai - p, i2 + bi - p
+                if 0 <= j1 < n1 and 0 <= j2 < plan.sizes["n2"] and act_of[j2 * n1 + j1] >= 0:
+                    got[ai, bi] = vals[ai * W + bi, r]
+                    exp[ai, bi] = F1[i1, j1] * F2[i2, j2]
+        worst = max(worst, np.abs(got - exp).max() / np.abs(exp).max())
+    say(f"[separable map 256^2 p4] {len(rows)} interior rows: max |device - product| / row max = {worst:.2e}")
+    assert worst <= 1e-12
